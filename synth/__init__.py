@@ -1,0 +1,179 @@
+"""Seeded synthetic inputs for the staggered periodic Navier-Stokes path.
+
+This module is shared by the CPU oracle, the tests and the benchmark. It only
+*samples* input fields; it contains none of the method's operators (no
+divergence, gradient, diffusion, convection, Poisson solve, projection or time
+stepping). Random numbers are drawn here and handed to both sides as plain
+arrays.
+
+Layout (same for every consumer): a velocity field on a d-dimensional grid with
+cell counts ``n = (N_x, N_y[, N_z])`` is a float64 array of shape
+``(d, N_z, N_y, N_x)`` (3D) or ``(d, N_y, N_x)`` (2D); component ``a`` is the
+velocity normal to the ``a``-faces and entry ``[a][I]`` sits on the face to the
+right of cell centre ``I`` in direction ``a`` (paper Sec. 2.1 and App. A.1:
+one pressure and one of each velocity component per volume, velocity to the
+right of the centre). Cell ``i`` spans ``[lo + i h, lo + (i+1) h]``.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+__all__ = [
+    "spacing",
+    "face_coords",
+    "taylor_green_2d",
+    "taylor_green_3d_extruded",
+    "shear_wave",
+    "random_field",
+    "random_scalar",
+    "turbulence_ic",
+    "energy_spectrum_shape",
+]
+
+TWO_PI = 2.0 * math.pi
+
+
+def spacing(n, lo=None, hi=None):
+    """Uniform spacings h_a = (hi_a - lo_a) / N_a for a 2pi-periodic box by default."""
+    d = len(n)
+    lo = [0.0] * d if lo is None else list(lo)
+    hi = [TWO_PI] * d if hi is None else list(hi)
+    return tuple((hi[a] - lo[a]) / n[a] for a in range(d))
+
+
+def face_coords(n, alpha, lo=None, hi=None):
+    """Coordinates of the alpha-velocity points as broadcastable arrays.
+
+    Returns a list ``[x_0, x_1, ...]`` (x_0 = x-coordinate) of arrays shaped to
+    broadcast against ``(N_z, N_y, N_x)``: along ``alpha`` the point is the
+    right face ``lo + (i+1) h``, along the other directions the cell centre
+    ``lo + (i+1/2) h``.
+    """
+    d = len(n)
+    lo = [0.0] * d if lo is None else list(lo)
+    h = spacing(n, lo, hi)
+    out = []
+    for b in range(d):
+        off = 1.0 if b == alpha else 0.5
+        c = lo[b] + (np.arange(n[b], dtype=np.float64) + off) * h[b]
+        shape = [1] * d
+        shape[d - 1 - b] = n[b]
+        out.append(c.reshape(shape))
+    return out
+
+
+def taylor_green_2d(n, amplitude=1.0):
+    """2D Taylor-Green vortex u = sin(x)cos(y), v = -cos(x)sin(y) on [0,2pi]^2.
+
+    Sampled at the staggered velocity points. ``n`` is an int or (N_x, N_y).
+    """
+    if np.isscalar(n):
+        n = (int(n), int(n))
+    nx, ny = n
+    u = np.empty((2, ny, nx), dtype=np.float64)
+    x, y = face_coords(n, 0)
+    u[0] = np.sin(x) * np.cos(y)
+    x, y = face_coords(n, 1)
+    u[1] = -np.cos(x) * np.sin(y)
+    return amplitude * u
+
+
+def taylor_green_3d_extruded(n, amplitude=1.0):
+    """The 2D Taylor-Green field repeated along z, with zero z-velocity."""
+    if np.isscalar(n):
+        n = (int(n),) * 3
+    nx, ny, nz = n
+    u = np.zeros((3, nz, ny, nx), dtype=np.float64)
+    u2 = taylor_green_2d((nx, ny), amplitude)
+    u[0] = u2[0][None]
+    u[1] = u2[1][None]
+    return u
+
+
+def shear_wave(n, m=1, amplitude=1.0):
+    """u_x = A sin(m y) (a parallel shear flow), other components zero."""
+    d = len(n)
+    shape = (d,) + tuple(reversed(n))
+    u = np.zeros(shape, dtype=np.float64)
+    coords = face_coords(n, 0)
+    u[0] = amplitude * np.sin(m * coords[1]) * np.ones(tuple(reversed(n)))
+    return u
+
+
+def random_field(n, seed, components=None):
+    """Seeded standard-normal vector field of shape (d, *reversed(n))."""
+    d = len(n)
+    c = d if components is None else components
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((c,) + tuple(reversed(n)))
+
+
+def random_scalar(n, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(tuple(reversed(n)))
+
+
+def energy_spectrum_shape(k, k0):
+    """Target shape E(k) ~ k^4 exp(-2 (k/k0)^2) of the decaying-turbulence initial field."""
+    k = np.asarray(k, dtype=np.float64)
+    return k ** 4 * np.exp(-2.0 * (k / k0) ** 2)
+
+
+def _int_wavenumbers(n):
+    d = len(n)
+    ks = []
+    for b in range(d):
+        k = np.fft.fftfreq(n[b], 1.0 / n[b])
+        shape = [1] * d
+        shape[d - 1 - b] = n[b]
+        ks.append(k.reshape(shape))
+    return ks
+
+
+def _filtered_noise(n, rng, amp):
+    w = rng.standard_normal(tuple(reversed(n)))
+    return np.real(np.fft.ifftn(np.fft.fftn(w) * amp))
+
+
+def turbulence_ic(n, seed, k0=4.0, energy=1.0):
+    """Random solenoidal velocity with E(k) ~ k^4 exp(-2(k/k0)^2), mean KE = ``energy``.
+
+    The field is the staggered-grid curl of a random potential (a stream
+    function on cell corners in 2D, a vector potential on cell edges in 3D)
+    whose Fourier amplitudes follow sqrt(E(|k|) / S_d(|k|)) / |k| with
+    S_2 = 2 pi k and S_3 = 4 pi k^2, applied to seeded white noise. The discrete
+    divergence of a discrete curl vanishes identically, so the result is
+    solenoidal up to rounding without using the solver's projection. It is
+    then scaled so that (1/2) mean_I sum_a u_a[I]^2 = energy.
+    """
+    n = tuple(int(v) for v in n)
+    d = len(n)
+    if d not in (2, 3):
+        raise ValueError("dim must be 2 or 3")
+    rng = np.random.default_rng(seed)
+    h = spacing(n)
+    ks = _int_wavenumbers(n)
+    kk = np.sqrt(sum(k * k for k in ks))
+    shell = 2.0 * math.pi * kk if d == 2 else 4.0 * math.pi * kk ** 2
+    with np.errstate(divide="ignore", invalid="ignore"):
+        amp = np.sqrt(energy_spectrum_shape(kk, k0) / shell) / kk
+    amp[(0,) * d] = 0.0
+
+    def back(f, b):  # f[I - e_b]
+        return np.roll(f, 1, axis=d - 1 - b)
+
+    u = np.empty((d,) + tuple(reversed(n)), dtype=np.float64)
+    if d == 2:
+        psi = _filtered_noise(n, rng, amp)
+        u[0] = (psi - back(psi, 1)) / h[1]
+        u[1] = -(psi - back(psi, 0)) / h[0]
+    else:
+        ax_, ay_, az_ = (_filtered_noise(n, rng, amp) for _ in range(3))
+        u[0] = (az_ - back(az_, 1)) / h[1] - (ay_ - back(ay_, 2)) / h[2]
+        u[1] = (ax_ - back(ax_, 2)) / h[2] - (az_ - back(az_, 0)) / h[0]
+        u[2] = (ay_ - back(ay_, 0)) / h[0] - (ax_ - back(ax_, 1)) / h[1]
+    ke = 0.5 * np.mean(np.sum(u * u, axis=0))
+    u *= math.sqrt(energy / ke)
+    return u
