@@ -1,0 +1,280 @@
+"""Throughput of the RK4 step of the staggered periodic Navier-Stokes solver on one MI355X.
+
+Workload: 3D periodic decaying turbulence on [0, 2 pi]^3, 256^3 staggered grid,
+nu = 1/1600, dt = 1e-3, seeded solenoidal initial field with
+E(k) ~ k^4 exp(-2 (k/4)^2) and unit kinetic energy.
+
+`value` is the float64 forward step rate in Mcell-updates/s (one cell update =
+one full RK4 step of one cell; inputs resident in HBM). The same line reports
+the float64 forward+adjoint rate and the FP32-stencil mode (float32 fields,
+float64 divergence/Poisson/projection), the HBM-roofline fraction of each
+step and of the dominant kernel (per-kernel durations from HIP events recorded
+on the library's stream), and the float64 CPU oracle timed on a bounded
+sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 256] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+METRIC = "Mcell-updates/s per RK4 step (fwd, fwd+adjoint), FP32 vs FP64, % HBM peak"
+
+
+def kernel_bytes(name, n, elem, batch=1):
+    """Algorithmic HBM bytes of one launch: each input read once, each output written once.
+
+    n = (nx, ny, nz); elem = bytes of a velocity value (8 or 4). Pressure-point
+    fields are float64 (8 B); the half spectrum holds (nx/2+1) ny nz complex
+    float64 values (16 B).
+    """
+    nx, ny, nz = n
+    N = nx * ny * nz * batch
+    Ns = (nx // 2 + 1) * ny * nz * batch
+    E, S, C = elem, 8, 16
+    v = 3 * E  # one velocity field per cell
+    table = {
+        "stage_first": 3 * v * N,                 # read u0; write y, w
+        "stage_first_rec": 2 * v * N,             # read u0; write w
+        "stage": (5 * v + S) * N,                 # read w, p, u0, y; write y, w
+        "stage_last": (3 * v + S) * N,            # read w, p, y; write y
+        "stage_rec": (3 * v + S) * N,             # read w, p, u0; write w
+        "fft_x_fwd_div": v * N + C * Ns,          # read w; write spectrum
+        "fft_x_fwd": S * N + C * Ns,
+        "fft_y_fwd": 2 * C * Ns,
+        "fft_y_inv": 2 * C * Ns,
+        "fft_z_solve": 2 * C * Ns,
+        "fft_y_solve": 2 * C * Ns,
+        "fft_x_inv": C * Ns + S * N,              # read spectrum; write p
+        "apply_projection": (2 * v + S) * N,      # read w, p; write u
+        "stage_vjp_first": (4 * v + S) * N,       # read w, p, ybar; write u0bar, ubar
+        "stage_vjp": (6 * v + 2 * S) * N,         # read w, p, ybar, ubar', q, u0bar; write u0bar, ubar
+        "stage_vjp_last": (5 * v + S) * N,        # read u0, ybar, ubar', q, u0bar; write u0bar
+        "rhs": 2 * v * N,
+        "rhs_vjp": 3 * v * N,
+    }
+    return table.get(name)
+
+
+def _source_hash(names):
+    h = hashlib.sha256()
+    for f in names:
+        with open(os.path.join(ROOT, "paper_2604_18536_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic_record(kernel):
+    """HBM bytes per launch measured with rocprofv3 counters, if still valid for the current source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh).get(kernel)
+    if not rec:
+        return None
+    if rec.get("source_hash") != _source_hash(rec.get("sources", [])):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def time_steps(fn, steps, warmup, solver=None):
+    import torch
+
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    if solver is not None:
+        solver.profile_reset()
+        solver.profile(True)
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    prof = None
+    if solver is not None:
+        prof = solver.profile_read()
+        solver.profile(False)
+    return a.elapsed_time(b) / steps, prof
+
+
+def run_mode(n, nu, dt, precision, steps, warmup, u0_np, adjoint):
+    import torch
+
+    from paper_2604_18536_amd import Solver
+
+    s = Solver(n, nu=nu, precision=precision)
+    u0 = torch.tensor(u0_np, dtype=s.dtype, device="cuda")
+    s.project(u0, out=u0)
+    u1 = torch.empty_like(u0)
+    ubar = torch.empty_like(u0)
+    gbar = torch.empty_like(u0)
+    if adjoint:
+        torch.manual_seed(0)
+        ubar.copy_(torch.randn_like(u0))
+
+        def fn():
+            s.step(u0, dt, out=u1)
+            s.step_vjp(u0, ubar, dt, out=gbar)
+    else:
+
+        def fn():
+            s.step(u0, dt, out=u1)
+    ms, _ = time_steps(fn, steps, warmup)
+    ms_p, prof = time_steps(fn, steps, 1, solver=s)
+    ok = s.stats(u1)[3]
+    ws = s.workspace_bytes()
+    s.close()
+    return ms, ms_p, prof, ok, ws
+
+
+def cpu_baseline(n, nu, dt, u0_np, budget_s=30.0):
+    """The float64 numpy oracle, as written, on the host: RK4 steps of the same field."""
+    import oracle as O
+    import synth as S
+
+    h = S.spacing(n)
+    ncell = n[0] * n[1] * n[2]
+    t0 = time.perf_counter()
+    u = O.step_rk4(u0_np, h, nu, dt)
+    t1 = time.perf_counter()
+    steps = 1
+    if (t1 - t0) * 2 < budget_s:
+        u = O.step_rk4(u, h, nu, dt)
+        steps = 2
+    t = time.perf_counter() - t0
+    return {
+        "value": round(ncell * steps / t / 1e6, 4),
+        "unit": "Mcell/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{steps} float64 RK4 step(s) of the {n[0]}x{n[1]}x{n[2]} field (numpy, single-threaded "
+                  f"elementwise and FFT), {t:.1f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--modes", default="fp64,fp64_adj,fp32,fp32_adj")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); multi-GPU runs are not part "
+              "of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth as S
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    n = (args.n,) * 3
+    nu, dt = 1.0 / 1600.0, 1e-3
+    ncell = n[0] * n[1] * n[2]
+    u0 = S.turbulence_ic(n, seed=0, k0=4.0)
+    print(f"[bench] initial field ready {n}", file=sys.stderr, flush=True)
+
+    modes = {}
+    kernels = {}
+    for mode in args.modes.split(","):
+        precision = "fp64" if mode.startswith("fp64") else "fp32"
+        adjoint = mode.endswith("_adj")
+        ms, ms_p, prof, ok, ws = run_mode(n, nu, dt, precision, args.steps, args.warmup, u0, adjoint)
+        elem = 8 if precision == "fp64" else 4
+        alg = 0
+        for name, (cnt, tot) in prof.items():
+            b = kernel_bytes(name, n, elem)
+            if b is not None:
+                alg += b * cnt
+        alg_per_step = alg / args.steps
+        modes[mode] = {
+            "mcell_per_s": round(ncell / (ms * 1e-3) / 1e6, 2),
+            "ms_per_step": round(ms, 4),
+            "ms_per_step_with_kernel_events": round(ms_p, 4),
+            "alg_bytes_per_cell": round(alg_per_step / ncell, 1),
+            "hbm_frac": round(alg_per_step / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+            "finite": bool(ok),
+            "workspace_gb": round(ws / 1e9, 3),
+        }
+        kernels[mode] = {
+            name: {
+                "launches_per_step": cnt / args.steps,
+                "avg_ms": round(tot / cnt, 5),
+                "gbs": (round(kernel_bytes(name, n, elem) / (tot / cnt * 1e-3) / 1e9, 1)
+                        if kernel_bytes(name, n, elem) else None),
+            }
+            for name, (cnt, tot) in prof.items()
+        }
+        print(f"[bench] {mode}: {modes[mode]}", file=sys.stderr, flush=True)
+
+    main_mode = "fp64" if "fp64" in modes else next(iter(modes))
+    kprof = kernels[main_mode]
+    dom = max(kprof, key=lambda k: kprof[k]["avg_ms"] * kprof[k]["launches_per_step"])
+    elem = 8 if main_mode.startswith("fp64") else 4
+    dom_bytes = kernel_bytes(dom, n, elem)
+    achieved = dom_bytes / (kprof[dom]["avg_ms"] * 1e-3) / 1e9
+    roofline = {
+        "bound": "hbm",
+        "kernel": dom,
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": _traffic_record(dom),
+        "alg_bytes_per_launch": dom_bytes,
+        "avg_ms": kprof[dom]["avg_ms"],
+    }
+    cpu = None if args.no_cpu else cpu_baseline(n, nu, dt, u0)
+    ms = modes[main_mode]["ms_per_step"]
+    line = {
+        "metric": METRIC,
+        "value": modes[main_mode]["mcell_per_s"],
+        "unit": "Mcell/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"3D periodic decaying turbulence {n[0]}^3 staggered grid, nu=1/1600, dt=1e-3, "
+                        "E(k)~k^4 exp(-2(k/4)^2), unit KE; float64 RK4 step",
+            "grid": list(n),
+            "nu": nu,
+            "dt": dt,
+        },
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "modes": modes,
+        "kernels": kernels,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,211 @@
+/*
+ * ins.h - C ABI of the MI355X (gfx950) staggered-grid incompressible
+ * Navier-Stokes hot path: matrix-free operators, spectral pressure solve,
+ * projection, classical RK4 step, and the pullback (vector-Jacobian product)
+ * of each, plus the learned convolutional closure and LES data helpers.
+ *
+ * Method: Agdestein & Sanderse, "A differentiable software suite for
+ * accelerated simulation of turbulent flows" (arXiv 2604.18536):
+ *   Sec. 2.1   staggered Harlow-Welch grid, code-index convention (Sec. 3.1)
+ *   Sec. 2.2   discrete operators; App. B explicit kernels and pullbacks
+ *   Sec. 2.5.1 pressure Poisson equation, spectral (DFT) solver
+ *   Sec. 2.5.2 explicit Runge-Kutta with a projection at every stage
+ *   Sec. 3.3   memory: array reuse, low-storage stepping, lazy fluxes
+ *   Sec. 3.4   pullback rule and hand-written adjoint kernels
+ *   Sec. 4     neural closure inside the solver, a-posteriori training
+ *
+ * ----------------------------------------------------------------------------
+ * Conventions shared by every entry point
+ * ----------------------------------------------------------------------------
+ * Grid. Uniform, periodic in every direction, dim 2 or 3, cell counts n[0]
+ * (x), n[1] (y), n[2] (z; ignored in 2D), box [lo, hi] per direction, and
+ * `batch` independent fields processed by every call.
+ *
+ * Layout. All field arguments are device pointers to dense arrays, x fastest:
+ *   velocity-point field (u, f, ubar, ...):  [batch][dim][n_z][n_y][n_x]
+ *   pressure-point field (r, p, ...):        [batch][n_z][n_y][n_x]
+ * (2D: drop n_z.) Component a of a velocity field at index I is the
+ * a-velocity on the face to the right of cell I in direction a (Sec. 2.1 /
+ * Sec. 3.1). There are no ghost cells: neighbours wrap periodically.
+ *
+ * Precision (ins_dtype).
+ *   INS_FP64: every field and all arithmetic in float64.
+ *   INS_FP32: velocity-point fields are float32 and the stencils and RK
+ *             stage arithmetic run in float32; the divergence, the Poisson
+ *             solve and the projection u - G p are computed in float64 and
+ *             pressure-point fields (r, p) are float64. (The paper supports a
+ *             choice of format but no mixed strategy, Sec. 6.2; this mode is
+ *             the mixed strategy its outlook proposes.)
+ *
+ * Ownership. The caller owns every field buffer; buffers must be 256-byte
+ * aligned (torch allocations are) and lie on the context's device. The
+ * context owns its FFT plans, twiddle tables, spectrum, pressure and RK
+ * stage registers. Forward workspace is allocated in ins_create; the
+ * reverse-pass stage storage on the first *_vjp call that needs it; the
+ * closure workspace in ins_closure_set. ins_workspace_bytes reports the total.
+ *
+ * Streams. Every call enqueues its kernels on the context's stream
+ * (default: the null stream) and returns without a host synchronisation,
+ * except where a host scalar is returned (ins_stats, ins_profile_*).
+ *
+ * Aliasing. Outputs must not alias inputs, except where an entry point says
+ * so. Outputs are overwritten, never accumulated into.
+ *
+ * Errors. Every entry point returns an ins_status and never throws or
+ * aborts. INS_ERR_INVALID: null pointer, bad size or parameter.
+ * INS_ERR_UNSUPPORTED: a grid the FFT cannot take (see ins_create).
+ * INS_ERR_OOM: device allocation failed. INS_ERR_HIP: a HIP call or kernel
+ * launch failed. ins_last_error() returns a thread-local message for the
+ * last non-OK status of the calling thread. Faults inside a kernel surface
+ * asynchronously at the caller's next synchronisation.
+ *
+ * Threading. A context is not thread-safe; use one context per stream.
+ */
+#ifndef INS_H_
+#define INS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ins_ctx_s* ins_ctx;
+
+typedef enum {
+    INS_OK = 0,
+    INS_ERR_INVALID = -1,
+    INS_ERR_UNSUPPORTED = -2,
+    INS_ERR_OOM = -3,
+    INS_ERR_HIP = -4
+} ins_status;
+
+typedef enum { INS_FP64 = 0, INS_FP32 = 1 } ins_dtype;
+
+typedef enum { INS_BC_PERIODIC = 0 } ins_bc;
+
+typedef struct {
+    int32_t dim;     /* 2 or 3 */
+    int64_t n[3];    /* cells per direction x, y, z (n[2] ignored in 2D) */
+    double lo[3];    /* box lower corner */
+    double hi[3];    /* box upper corner; h_a = (hi[a]-lo[a]) / n[a] */
+    int64_t batch;   /* number of independent fields per call, >= 1 */
+} ins_grid;
+
+/* ---------------------------------------------------------------------------
+ * Context
+ * ------------------------------------------------------------------------- */
+
+/* Create a context on the current HIP device.
+ * Requirements (else INS_ERR_UNSUPPORTED): n_x even; n_x/2, n_y and n_z each
+ * a product of the primes 2, 3, 5, 7 and at most 4096; n_y, n_z >= 2, n_x >= 4.
+ * (The real-to-complex FFT along x works on n_x/2 complex points; the spectral
+ * solver of Sec. 2.5.1 needs a uniform periodic grid.) nu >= 0 is the
+ * kinematic viscosity of the diffusion term. Allocates the forward
+ * workspace: stage registers (3 velocity fields), pressure and half spectrum. */
+ins_status ins_create(const ins_grid* grid, ins_bc bc, double nu, ins_dtype dtype, ins_ctx* out);
+ins_status ins_destroy(ins_ctx ctx);
+/* stream: a hipStream_t (NULL = null stream). */
+ins_status ins_set_stream(ins_ctx ctx, void* stream);
+/* Device bytes currently held by the context. */
+ins_status ins_workspace_bytes(ins_ctx ctx, size_t* bytes);
+const char* ins_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Forward operators (App. B kernels; Sec. 2.5)
+ * ------------------------------------------------------------------------- */
+
+/* f = C(u) + nu * Lap(u) (+ m_theta(u) when a closure is set): the
+ * convection of eq. conv-kernel (uniform weights 1/2, skew-symmetric form)
+ * and the diffusion of eq. diff-kernel. u, f: velocity fields. */
+ins_status ins_rhs(ins_ctx ctx, const void* u, void* f);
+
+/* r = D u, eq. div-kernel: r[I] = sum_a (u_a[I] - u_a[I - e_a]) / h_a.
+ * r is a pressure-point field, float64 in both precision modes. */
+ins_status ins_divergence(ins_ctx ctx, const void* u, double* r);
+
+/* g = G p, eq. presgrad-kernel: g_a[I] = (p[I + e_a] - p[I]) / h_a.
+ * p float64 pressure-point field; g velocity field in the context dtype. */
+ins_status ins_gradient(ins_ctx ctx, const double* p, void* g);
+
+/* Solve D G p = r by the spectral solver of Sec. 2.5.1: p = DFT^-1 L^-1 DFT r
+ * with the exact discrete transfer function
+ * L(k) = -sum_a 4 sin^2(pi k_a / n_a) / h_a^2 and L(0) := 1 (so the mean of
+ * p equals the mean of r). r, p: float64 pressure-point fields; r may equal p. */
+ins_status ins_poisson_solve(ins_ctx ctx, const double* r, double* p);
+
+/* u_out = P u = u - G p with p = (D G)^-1 D u (the projection applied at every
+ * RK stage, Sec. 2.5.2). The divergence, Poisson solve and u - G p run in
+ * float64. p_out (float64, may be NULL) receives p. u == u_out is allowed. */
+ins_status ins_project(ins_ctx ctx, const void* u, void* u_out, double* p_out);
+
+/* One classical RK4 step with the velocity projected after every stage
+ * (Sec. 2.5.2): u_{i+1} = P(u0 + dt a_{i+1} F(u_i)), a = (1/2, 1/2, 1);
+ * u1 = P(u0 + dt (F1 + 2F2 + 2F3 + F4) / 6), F = ins_rhs. u0 is used as
+ * given (callers pass a solenoidal field). Low-storage schedule: stage
+ * register, accumulator and one pressure solve per stage, with the
+ * projection of each stage fused into the next stage's stencil.
+ * u0 == u1 is allowed (in-place step). dt > 0. */
+ins_status ins_step_rk4(ins_ctx ctx, const void* u0, void* u1, double dt);
+
+/* ---------------------------------------------------------------------------
+ * Pullbacks (Sec. 3.4 eq. pullback; App. B)
+ * ------------------------------------------------------------------------- */
+
+/* ubar = J_F(u)^T fbar: the convection pullback derived from the forward
+ * kernel (gather form, no atomics) plus the diffusion pullback (the
+ * diffusion itself on a uniform grid). With a closure set, also adds the
+ * closure's input gradient and accumulates its parameter gradient (see
+ * ins_closure_grad). */
+ins_status ins_rhs_vjp(ins_ctx ctx, const void* u, const void* fbar, void* ubar);
+
+/* ubar = D^T rbar = -G rbar: ubar_a[J] = (rbar[J] - rbar[J + e_a]) / h_a.
+ * rbar float64 pressure-point field. */
+ins_status ins_divergence_vjp(ins_ctx ctx, const double* rbar, void* ubar);
+
+/* pbar = G^T gbar = -D gbar. gbar velocity field, pbar float64. */
+ins_status ins_gradient_vjp(ins_ctx ctx, const void* gbar, double* pbar);
+
+/* rbar = L^-T pbar = L^-1 pbar: the Poisson solve is self-adjoint (Sec. 2.5.1). */
+ins_status ins_poisson_solve_vjp(ins_ctx ctx, const double* pbar, double* rbar);
+
+/* ubar = P^T ubar_out = P ubar_out (P is symmetric on the uniform periodic
+ * grid). ubar == ubar_out is allowed. */
+ins_status ins_project_vjp(ins_ctx ctx, const void* ubar_out, void* ubar);
+
+/* u0bar = (d u1 / d u0)^T u1bar for u1 = ins_step_rk4(u0, dt): recomputes the
+ * stage states from u0, then runs the stages backwards (pullbacks of the
+ * projection and of the right-hand side). Allocates the reverse-pass stage
+ * storage on first use. u0bar must not alias u0 or u1bar. */
+ins_status ins_step_rk4_vjp(ins_ctx ctx, const void* u0, const void* u1bar, void* u0bar, double dt);
+
+/* ---------------------------------------------------------------------------
+ * Utilities (diagnostics, benchmarking)
+ * ------------------------------------------------------------------------- */
+
+/* Host-returned statistics of a velocity field, summed over the batch:
+ * out[0] = kinetic energy (1/2) mean_I sum_a u_a^2 (mean over batch),
+ * out[1] = max |u_a[I]|, out[2] = max |(D u)[I]|, out[3] = 1 if every entry
+ * is finite else 0. Synchronises the stream. */
+ins_status ins_stats(ins_ctx ctx, const void* u, double out[4]);
+
+/* Plain device copy of nbytes (multiple of 16) from src to dst with the
+ * library's streaming-copy kernel; used to calibrate bandwidth counters. */
+ins_status ins_stream_copy(ins_ctx ctx, const void* src, void* dst, size_t nbytes);
+
+/* Kernel timing: when enabled, every kernel launch of this context is
+ * bracketed by HIP events on the context stream. ins_profile_read
+ * synchronises, then reports for entry i < count: the kernel name, the
+ * number of launches and their summed duration in milliseconds, and clears
+ * nothing; ins_profile_reset clears the records. */
+ins_status ins_profile_enable(ins_ctx ctx, int enable);
+ins_status ins_profile_reset(ins_ctx ctx);
+ins_status ins_profile_count(ins_ctx ctx, int* count);
+ins_status ins_profile_read(ins_ctx ctx, int i, char* name, size_t name_len, int64_t* launches, double* total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* INS_H_ */

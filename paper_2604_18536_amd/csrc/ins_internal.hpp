@@ -1,0 +1,109 @@
+// Internal declarations shared by the runtime and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+namespace ins {
+
+// Complex float64 value of the spectral path.
+struct cd {
+    double x, y;
+};
+
+// Grid description handed to every kernel by value.
+struct Grid {
+    int dim;            // 2 or 3
+    int nx, ny, nz;     // nz == 1 in 2D
+    int batch;
+    int64_t ncell;      // nx * ny * nz
+    double ih[3];       // 1 / h_a
+    double ih2[3];      // 1 / h_a^2
+    double nu;
+};
+
+// One 1D FFT length: Stockham stages with their radices and twiddle tables.
+constexpr int kMaxStages = 12;
+struct FftPlan {
+    int n;                   // transform length
+    int nst;                 // number of stages
+    int rad[kMaxStages];     // radix of stage s (applied in order)
+    int tw_off[kMaxStages];  // offset of stage s twiddles: p*(R-1) entries
+    const cd* tw;            // device twiddle table (float64, forward sign)
+};
+
+// Which FFT pass shape a launch uses.
+struct FftPassCfg {
+    int lines;   // lines per workgroup (power of two)
+};
+
+// Spectral solve data: 4 sin^2(pi k / n) / h^2 per direction and 1/(#cells).
+struct SolveTab {
+    const double* lam[3];
+    double inv_ncell;
+};
+
+// Field-type tags for the stencil kernels.
+enum class Prec { F64 = 0, F32 = 1 };
+
+// ----------------------------------------------------------------------------
+// Launchers (defined in the kernel translation units). All return hipError_t
+// from hipGetLastError after the launch.
+// ----------------------------------------------------------------------------
+template <typename T>
+hipError_t launch_rhs(const Grid& g, const T* u, T* f, hipStream_t s);
+template <typename T>
+hipError_t launch_divergence(const Grid& g, const T* u, double* r, hipStream_t s);
+template <typename T>
+hipError_t launch_gradient(const Grid& g, const double* p, T* gout, hipStream_t s);
+template <typename T>
+hipError_t launch_div_vjp(const Grid& g, const double* rbar, T* ubar, hipStream_t s);
+template <typename T>
+hipError_t launch_grad_vjp(const Grid& g, const T* gbar, double* pbar, hipStream_t s);
+// u_out = w - G p (float64 arithmetic), u_out may equal w.
+template <typename T>
+hipError_t launch_apply_projection(const Grid& g, const T* w, const double* p, T* u_out, hipStream_t s);
+
+// RK4 stage: u_i = proj ? w - G p : w; F = rhs(u_i);
+//   if y: y = (yinit ? u0 : y) + cy F;  if wout: wout = u0 + cw F.
+template <typename T>
+hipError_t launch_stage(const Grid& g, const T* w, const double* p, bool proj, const T* u0, T* y, bool yinit, double cy,
+                        T* wout, double cw, hipStream_t s);
+
+// Spectral Poisson solve pieces.
+// Forward x pass: real rows -> half spectrum. If vel != nullptr the rows are
+// the divergence of vel computed on the fly; else rows come from r.
+template <typename T>
+hipError_t launch_fft_x_fwd(const Grid& g, const T* vel, const double* r, cd* spec, const FftPlan& px, const cd* post_tw,
+                            int lines, hipStream_t s);
+hipError_t launch_fft_x_inv(const Grid& g, const cd* spec, double* p, const FftPlan& px, const cd* post_tw, int lines,
+                            hipStream_t s);
+// Strided C2C pass over the half spectrum. mode 0: forward, 1: inverse,
+// 2: forward + spectral divide + inverse. axis 1 = y, 2 = z.
+hipError_t launch_fft_strided(const Grid& g, cd* spec, const FftPlan& pl, int axis, int mode, int lines,
+                              const SolveTab& st, hipStream_t s);
+
+// Reverse-pass kernels.
+template <typename T>
+hipError_t launch_rhs_vjp(const Grid& g, const T* u, const T* fbar, T* ubar, hipStream_t s);
+// Reverse RK4 stage: u_i = (proj_u ? w - G p : w),
+// Fbar_i = cb ybar + (has_w ? cw (un - G q) : 0), out = J_F(u_i)^T Fbar_i,
+// u0bar = (mode == 0 ? ybar : u0bar) + (has_w ? un - G q : 0) + (mode == 2 ? out : 0),
+// ubar_out (if not null) = out.
+template <typename T>
+hipError_t launch_stage_vjp(const Grid& g, const T* w, const double* p, bool proj_u, const T* ybar, const T* un,
+                            const double* q, bool has_w, double cb, double cw, T* u0bar, int mode, T* ubar_out,
+                            hipStream_t s);
+
+// Utilities.
+template <typename T>
+hipError_t launch_stats(const Grid& g, const T* u, double* partial, int nblocks, hipStream_t s);
+hipError_t launch_stream_copy(const void* src, void* dst, size_t nbytes, hipStream_t s);
+
+// Number of workgroups used by launch_stats (partials buffer holds 4 per block).
+int stats_blocks(const Grid& g);
+
+}  // namespace ins

@@ -1,0 +1,726 @@
+// Runtime behind the C ABI of include/ins.h: context, FFT plans, workspace,
+// the forward and reverse RK4 schedules, error state and kernel timing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/ins.h"
+#include "ins_internal.hpp"
+
+using ins::cd;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct InsError {
+    ins_status st;
+    std::string msg;
+};
+
+[[noreturn]] void raise(ins_status st, const std::string& msg) { throw InsError{st, msg}; }
+
+void hip_check(hipError_t e, const char* what) {
+    if (e != hipSuccess) raise(INS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+constexpr int kMaxLen = 4096;
+constexpr int kVmaxHost = 16;   // must match kVmax of the FFT kernels
+constexpr int kBlockHost = 256; // must match kBlock
+constexpr size_t kMaxLds = 65536;
+
+bool factor(int n, std::vector<int>& rad) {
+    rad.clear();
+    int m = n, e2 = 0;
+    while (m % 2 == 0) {
+        m /= 2;
+        ++e2;
+    }
+    while (e2 >= 3) {
+        rad.push_back(8);
+        e2 -= 3;
+    }
+    if (e2 == 2) rad.push_back(4);
+    if (e2 == 1) rad.push_back(2);
+    for (int q : {7, 5, 3}) {
+        while (m % q == 0) {
+            rad.push_back(q);
+            m /= q;
+        }
+    }
+    if (m != 1) return false;
+    std::sort(rad.begin(), rad.end(), std::greater<int>());
+    return static_cast<int>(rad.size()) <= ins::kMaxStages;
+}
+
+// Twiddles exp(-2 pi i q k / (p R)), k < p, 1 <= q < R, for every stage; the
+// angle is reduced exactly in integers and evaluated in long double.
+void build_twiddles(int n, const std::vector<int>& rad, std::vector<cd>& tw, ins::FftPlan& pl) {
+    const long double two_pi = 6.283185307179586476925286766559005768L;
+    pl.n = n;
+    pl.nst = static_cast<int>(rad.size());
+    int p = 1;
+    for (int s = 0; s < pl.nst; ++s) {
+        const int R = rad[s];
+        pl.rad[s] = R;
+        pl.tw_off[s] = static_cast<int>(tw.size());
+        const long long pr = static_cast<long long>(p) * R;
+        for (int k = 0; k < p; ++k) {
+            for (int q = 1; q < R; ++q) {
+                const long long m = (static_cast<long long>(q) * k) % pr;
+                const long double ang = -two_pi * static_cast<long double>(m) / static_cast<long double>(pr);
+                tw.push_back(cd{static_cast<double>(cosl(ang)), static_cast<double>(sinl(ang))});
+            }
+        }
+        p *= R;
+    }
+}
+
+// Largest power-of-two line batch (<= maxl) whose every stage fits the
+// per-thread register budget and whose lines fit the LDS budget.
+int choose_lines(const ins::FftPlan& pl, int maxl) {
+    for (int nl = maxl; nl >= 1; nl >>= 1) {
+        if (static_cast<size_t>(nl) * pl.n * sizeof(cd) > kMaxLds) continue;
+        bool ok = true;
+        for (int s = 0; s < pl.nst; ++s) {
+            const int R = pl.rad[s];
+            const long long nb = static_cast<long long>(nl) * (pl.n / R);
+            if (nb > static_cast<long long>(kVmaxHost / R) * kBlockHost) ok = false;
+        }
+        if (ok) {
+            int l = 0;
+            while ((1 << l) < nl) ++l;
+            return l;
+        }
+    }
+    return -1;
+}
+
+struct Pending {
+    const char* name;
+    hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct ins_ctx_s {
+    ins::Grid g{};
+    ins_dtype dtype = INS_FP64;
+    int device = 0;
+    hipStream_t stream = nullptr;
+
+    ins::FftPlan px{}, py{}, pz{};
+    int lnl_x = 0, lnl_y = 0, lnl_z = 0;
+    cd* d_tw = nullptr;
+    cd* d_post = nullptr;
+    double* d_lam = nullptr;
+    ins::SolveTab st{};
+
+    cd* spec = nullptr;
+    double* p = nullptr;
+    void* ry = nullptr;
+    void* wa = nullptr;
+    void* wb = nullptr;
+    double* partials = nullptr;
+    int nstat = 0;
+
+    // reverse-pass stage storage (allocated on first use)
+    void* w2 = nullptr;
+    void* w3 = nullptr;
+    void* w4 = nullptr;
+    double* p2 = nullptr;
+    double* p3 = nullptr;
+    double* p4 = nullptr;
+
+    size_t bytes = 0;
+    std::vector<void*> allocs;
+
+    bool prof = false;
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+    std::map<std::string, std::pair<int64_t, double>> totals;
+    std::vector<std::string> order;
+
+    size_t vel_bytes() const {
+        return static_cast<size_t>(g.batch) * g.dim * g.ncell * (dtype == INS_FP64 ? 8 : 4);
+    }
+    size_t scal_bytes() const { return static_cast<size_t>(g.batch) * g.ncell * 8; }
+
+    void* alloc(size_t n) {
+        void* ptr = nullptr;
+        if (hipMalloc(&ptr, n) != hipSuccess) {
+            (void)hipGetLastError();
+            raise(INS_ERR_OOM, "hipMalloc of " + std::to_string(n) + " bytes failed");
+        }
+        allocs.push_back(ptr);
+        bytes += n;
+        return ptr;
+    }
+
+    hipEvent_t event() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e;
+        hip_check(hipEventCreate(&e), "hipEventCreate");
+        return e;
+    }
+
+    template <class F>
+    void launch(const char* name, F&& f) {
+        hipEvent_t a = nullptr, b = nullptr;
+        if (prof) {
+            a = event();
+            b = event();
+            hip_check(hipEventRecord(a, stream), "hipEventRecord");
+        }
+        const hipError_t e = f();
+        if (e != hipSuccess) raise(INS_ERR_HIP, std::string(name) + ": " + hipGetErrorString(e));
+        if (prof) {
+            hip_check(hipEventRecord(b, stream), "hipEventRecord");
+            pending.push_back({name, a, b});
+        }
+    }
+
+    void collect() {
+        if (pending.empty()) return;
+        hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize");
+        for (auto& pr : pending) {
+            float ms = 0.f;
+            hip_check(hipEventElapsedTime(&ms, pr.a, pr.b), "hipEventElapsedTime");
+            auto it = totals.find(pr.name);
+            if (it == totals.end()) {
+                totals[pr.name] = {1, ms};
+                order.push_back(pr.name);
+            } else {
+                it->second.first += 1;
+                it->second.second += ms;
+            }
+            pool.push_back(pr.a);
+            pool.push_back(pr.b);
+        }
+        pending.clear();
+    }
+
+    ~ins_ctx_s() {
+        for (auto& pr : pending) {
+            (void)hipEventDestroy(pr.a);
+            (void)hipEventDestroy(pr.b);
+        }
+        for (auto e : pool) (void)hipEventDestroy(e);
+        for (void* ptr : allocs) (void)hipFree(ptr);
+    }
+};
+
+namespace {
+
+template <class F>
+ins_status guarded(F&& f) {
+    try {
+        f();
+        return INS_OK;
+    } catch (const InsError& e) {
+        g_last_error = e.msg;
+        return e.st;
+    } catch (const std::exception& e) {
+        g_last_error = e.what();
+        return INS_ERR_INVALID;
+    } catch (...) {
+        g_last_error = "unknown error";
+        return INS_ERR_INVALID;
+    }
+}
+
+void need(const void* ptr, const char* what) {
+    if (!ptr) raise(INS_ERR_INVALID, std::string(what) + " is null");
+}
+
+ins_ctx checked(ins_ctx c) {
+    if (!c) raise(INS_ERR_INVALID, "context is null");
+    int dev = -1;
+    hip_check(hipGetDevice(&dev), "hipGetDevice");
+    if (dev != c->device) hip_check(hipSetDevice(c->device), "hipSetDevice");
+    return c;
+}
+
+template <class F>
+void with_type(ins_ctx c, F&& f) {
+    if (c->dtype == INS_FP64)
+        f(double{});
+    else
+        f(float{});
+}
+
+// p = (D G)^-1 of the divergence of vel (vel != null) or of r.
+void poisson(ins_ctx c, const void* vel, const double* r, double* p) {
+    const ins::Grid& g = c->g;
+    if (vel) {
+        with_type(c, [&](auto tag) {
+            using T = decltype(tag);
+            c->launch("fft_x_fwd_div", [&] {
+                return ins::launch_fft_x_fwd<T>(g, static_cast<const T*>(vel), nullptr, c->spec, c->px, c->d_post,
+                                                c->lnl_x, c->stream);
+            });
+        });
+    } else {
+        c->launch("fft_x_fwd", [&] {
+            return ins::launch_fft_x_fwd<double>(g, nullptr, r, c->spec, c->px, c->d_post, c->lnl_x, c->stream);
+        });
+    }
+    if (g.dim == 3) {
+        c->launch("fft_y_fwd", [&] { return ins::launch_fft_strided(g, c->spec, c->py, 1, 0, c->lnl_y, c->st, c->stream); });
+        c->launch("fft_z_solve", [&] { return ins::launch_fft_strided(g, c->spec, c->pz, 2, 2, c->lnl_z, c->st, c->stream); });
+        c->launch("fft_y_inv", [&] { return ins::launch_fft_strided(g, c->spec, c->py, 1, 1, c->lnl_y, c->st, c->stream); });
+    } else {
+        c->launch("fft_y_solve", [&] { return ins::launch_fft_strided(g, c->spec, c->py, 1, 2, c->lnl_y, c->st, c->stream); });
+    }
+    c->launch("fft_x_inv", [&] { return ins::launch_fft_x_inv(g, c->spec, p, c->px, c->d_post, c->lnl_x, c->stream); });
+}
+
+template <typename T>
+void stage(ins_ctx c, const T* w, const double* p, bool proj, const T* u0, T* y, bool yinit, double cy, T* wout,
+           double cw) {
+    // one profile name per data-movement variant (their byte counts differ)
+    const char* name = !proj ? (y ? "stage_first" : "stage_first_rec")
+                             : (y ? (wout ? "stage" : "stage_last") : "stage_rec");
+    c->launch(name, [&] {
+        return ins::launch_stage<T>(c->g, w, p, proj, u0, y, yinit, cy, wout, cw, c->stream);
+    });
+}
+
+template <typename T>
+void apply_projection(ins_ctx c, const T* w, const double* p, T* out) {
+    c->launch("apply_projection", [&] { return ins::launch_apply_projection<T>(c->g, w, p, out, c->stream); });
+}
+
+// Classical RK4, projection after every stage (Sec. 2.5.2), low-storage
+// schedule: accumulator y, stage registers wa/wb, one pressure per stage.
+template <typename T>
+void step_rk4(ins_ctx c, const T* u0, T* u1, double dt) {
+    T* y = static_cast<T*>(c->ry);
+    T* wa = static_cast<T*>(c->wa);
+    T* wb = static_cast<T*>(c->wb);
+    double* p = c->p;
+    stage<T>(c, u0, nullptr, false, u0, y, true, dt / 6.0, wa, dt / 2.0);
+    poisson(c, wa, nullptr, p);
+    stage<T>(c, wa, p, true, u0, y, false, dt / 3.0, wb, dt / 2.0);
+    poisson(c, wb, nullptr, p);
+    stage<T>(c, wb, p, true, u0, y, false, dt / 3.0, wa, dt);
+    poisson(c, wa, nullptr, p);
+    stage<T>(c, wa, p, true, u0, y, false, dt / 6.0, nullptr, 0.0);
+    poisson(c, y, nullptr, p);
+    apply_projection<T>(c, y, p, u1);
+}
+
+void ensure_vjp_storage(ins_ctx c) {
+    if (c->w2) return;
+    c->w2 = c->alloc(c->vel_bytes());
+    c->w3 = c->alloc(c->vel_bytes());
+    c->w4 = c->alloc(c->vel_bytes());
+    c->p2 = static_cast<double*>(c->alloc(c->scal_bytes()));
+    c->p3 = static_cast<double*>(c->alloc(c->scal_bytes()));
+    c->p4 = static_cast<double*>(c->alloc(c->scal_bytes()));
+}
+
+template <typename T>
+void stage_vjp(ins_ctx c, const T* w, const double* p, bool proj_u, const T* ybar, const T* un, const double* q,
+               bool has_w, double cb, double cw, T* u0bar, int mode, T* out) {
+    const char* name = mode == 0 ? "stage_vjp_first" : (mode == 2 ? "stage_vjp_last" : "stage_vjp");
+    c->launch(name, [&] {
+        return ins::launch_stage_vjp<T>(c->g, w, p, proj_u, ybar, un, q, has_w, cb, cw, u0bar, mode, out, c->stream);
+    });
+}
+
+// Reverse pass of step_rk4 (Sec. 3.4): recompute the stage states
+// u_i = w_i - G p_i, project the incoming cotangent, then run the stages
+// backwards. With ybar = P u1bar and wbar_{i+1} the projected cotangent of
+// stage i+1's input:
+//   Fbar_i = dt b_i ybar + dt a_{i+1} wbar_{i+1},  ubar_i = J_F(u_i)^T Fbar_i,
+//   wbar_i = P ubar_i,  u0bar = ybar + sum_i wbar_i + ubar_1.
+template <typename T>
+void step_rk4_vjp(ins_ctx c, const T* u0, const T* u1bar, T* u0bar, double dt) {
+    ensure_vjp_storage(c);
+    T* W2 = static_cast<T*>(c->w2);
+    T* W3 = static_cast<T*>(c->w3);
+    T* W4 = static_cast<T*>(c->w4);
+    double *P2 = c->p2, *P3 = c->p3, *P4 = c->p4;
+    stage<T>(c, u0, nullptr, false, u0, nullptr, false, 0.0, W2, dt / 2.0);
+    poisson(c, W2, nullptr, P2);
+    stage<T>(c, W2, P2, true, u0, nullptr, false, 0.0, W3, dt / 2.0);
+    poisson(c, W3, nullptr, P3);
+    stage<T>(c, W3, P3, true, u0, nullptr, false, 0.0, W4, dt);
+    poisson(c, W4, nullptr, P4);
+
+    T* YB = static_cast<T*>(c->ry);
+    T* UA = static_cast<T*>(c->wa);
+    T* UB = static_cast<T*>(c->wb);
+    double* Q = c->p;
+    poisson(c, u1bar, nullptr, Q);
+    apply_projection<T>(c, u1bar, Q, YB);
+    stage_vjp<T>(c, W4, P4, true, YB, nullptr, nullptr, false, dt / 6.0, 0.0, u0bar, 0, UA);
+    poisson(c, UA, nullptr, Q);
+    stage_vjp<T>(c, W3, P3, true, YB, UA, Q, true, dt / 3.0, dt, u0bar, 1, UB);
+    poisson(c, UB, nullptr, Q);
+    stage_vjp<T>(c, W2, P2, true, YB, UB, Q, true, dt / 3.0, dt / 2.0, u0bar, 1, UA);
+    poisson(c, UA, nullptr, Q);
+    stage_vjp<T>(c, u0, nullptr, false, YB, UA, Q, true, dt / 6.0, dt / 2.0, u0bar, 2, nullptr);
+}
+
+void check_dt(double dt) {
+    if (!(dt > 0.0) || !std::isfinite(dt)) raise(INS_ERR_INVALID, "dt must be positive and finite");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ins_last_error(void) { return g_last_error.c_str(); }
+
+ins_status ins_create(const ins_grid* grid, ins_bc bc, double nu, ins_dtype dtype, ins_ctx* out) {
+    if (out) *out = nullptr;
+    ins_ctx_s* c = nullptr;
+    const ins_status st = guarded([&] {
+        need(grid, "grid");
+        need(out, "out");
+        if (bc != INS_BC_PERIODIC) raise(INS_ERR_UNSUPPORTED, "only periodic boundaries are supported");
+        if (dtype != INS_FP64 && dtype != INS_FP32) raise(INS_ERR_INVALID, "unknown dtype");
+        if (grid->dim != 2 && grid->dim != 3) raise(INS_ERR_UNSUPPORTED, "dim must be 2 or 3");
+        if (!(nu >= 0.0) || !std::isfinite(nu)) raise(INS_ERR_INVALID, "nu must be finite and >= 0");
+        if (grid->batch < 1 || grid->batch > (1 << 20)) raise(INS_ERR_INVALID, "batch must be >= 1");
+        const int d = grid->dim;
+        int64_t n[3] = {grid->n[0], grid->n[1], d == 3 ? grid->n[2] : 1};
+        for (int a = 0; a < d; ++a) {
+            if (n[a] < 2 || n[a] > kMaxLen) raise(INS_ERR_UNSUPPORTED, "cell counts must lie in [2, 4096]");
+            if (!(grid->hi[a] > grid->lo[a]) || !std::isfinite(grid->hi[a] - grid->lo[a]))
+                raise(INS_ERR_INVALID, "box must have hi > lo");
+        }
+        if (n[0] % 2 != 0 || n[0] < 4) raise(INS_ERR_UNSUPPORTED, "n_x must be even and >= 4 (real-to-complex FFT)");
+        const int64_t ncell = n[0] * n[1] * n[2];
+        if (ncell * d >= (int64_t(1) << 31)) raise(INS_ERR_UNSUPPORTED, "grid too large for 32-bit in-field indexing");
+
+        std::vector<int> rx, ry, rz;
+        if (!factor(int(n[0] / 2), rx) || !factor(int(n[1]), ry) || (d == 3 && !factor(int(n[2]), rz)))
+            raise(INS_ERR_UNSUPPORTED, "n_x/2, n_y, n_z must be products of 2, 3, 5, 7");
+
+        c = new ins_ctx_s();
+        hip_check(hipGetDevice(&c->device), "hipGetDevice");
+        c->dtype = dtype;
+        ins::Grid& g = c->g;
+        g.dim = d;
+        g.nx = int(n[0]);
+        g.ny = int(n[1]);
+        g.nz = int(n[2]);
+        g.batch = int(grid->batch);
+        g.ncell = ncell;
+        for (int a = 0; a < 3; ++a) {
+            const double h = a < d ? (grid->hi[a] - grid->lo[a]) / double(n[a]) : 1.0;
+            g.ih[a] = a < d ? 1.0 / h : 0.0;
+            g.ih2[a] = a < d ? 1.0 / (h * h) : 0.0;
+        }
+        g.nu = nu;
+
+        // FFT plans: x works on n_x/2 complex points.
+        std::vector<cd> tw;
+        build_twiddles(g.nx / 2, rx, tw, c->px);
+        build_twiddles(g.ny, ry, tw, c->py);
+        if (d == 3) build_twiddles(g.nz, rz, tw, c->pz);
+        c->lnl_x = choose_lines(c->px, 16);
+        c->lnl_y = choose_lines(c->py, 16);
+        c->lnl_z = d == 3 ? choose_lines(c->pz, 16) : 0;
+        if (c->lnl_x < 0 || c->lnl_y < 0 || c->lnl_z < 0) raise(INS_ERR_UNSUPPORTED, "FFT length too long");
+
+        const long double two_pi = 6.283185307179586476925286766559005768L;
+        std::vector<cd> post(g.nx / 2 + 1);
+        for (int k = 0; k <= g.nx / 2; ++k) {
+            const long double ang = -two_pi * k / static_cast<long double>(g.nx);
+            post[k] = cd{double(cosl(ang)), double(sinl(ang))};
+        }
+        // 4 sin^2(pi k / n) / h^2 per direction (Sec. 2.5.1 transfer function).
+        std::vector<double> lam;
+        size_t off[3] = {0, 0, 0};
+        const int cnt[3] = {g.nx / 2 + 1, g.ny, d == 3 ? g.nz : 1};
+        const int nn[3] = {g.nx, g.ny, g.nz};
+        for (int a = 0; a < 3; ++a) {
+            off[a] = lam.size();
+            for (int k = 0; k < cnt[a]; ++k) {
+                if (a >= d) {
+                    lam.push_back(0.0);
+                    continue;
+                }
+                const long double s = sinl(two_pi * 0.5L * k / static_cast<long double>(nn[a]));
+                lam.push_back(double(4.0L * s * s * static_cast<long double>(g.ih2[a])));
+            }
+        }
+        c->d_tw = static_cast<cd*>(c->alloc(std::max<size_t>(tw.size(), 1) * sizeof(cd)));
+        c->d_post = static_cast<cd*>(c->alloc(post.size() * sizeof(cd)));
+        c->d_lam = static_cast<double*>(c->alloc(lam.size() * sizeof(double)));
+        hip_check(hipMemcpy(c->d_tw, tw.data(), tw.size() * sizeof(cd), hipMemcpyHostToDevice), "upload twiddles");
+        hip_check(hipMemcpy(c->d_post, post.data(), post.size() * sizeof(cd), hipMemcpyHostToDevice), "upload twiddles");
+        hip_check(hipMemcpy(c->d_lam, lam.data(), lam.size() * sizeof(double), hipMemcpyHostToDevice), "upload eigenvalues");
+        c->px.tw = c->d_tw;
+        c->py.tw = c->d_tw;
+        c->pz.tw = c->d_tw;
+        for (int a = 0; a < 3; ++a) c->st.lam[a] = c->d_lam + off[a];
+        c->st.inv_ncell = 1.0 / double(ncell);
+
+        const size_t nxh = size_t(g.nx / 2 + 1);
+        c->spec = static_cast<cd*>(c->alloc(size_t(g.batch) * g.nz * g.ny * nxh * sizeof(cd)));
+        c->p = static_cast<double*>(c->alloc(c->scal_bytes()));
+        c->ry = c->alloc(c->vel_bytes());
+        c->wa = c->alloc(c->vel_bytes());
+        c->wb = c->alloc(c->vel_bytes());
+        c->nstat = ins::stats_blocks(g);
+        c->partials = static_cast<double*>(c->alloc(size_t(c->nstat) * 4 * sizeof(double)));
+        *out = c;
+    });
+    if (st != INS_OK) delete c;
+    return st;
+}
+
+ins_status ins_destroy(ins_ctx ctx) {
+    return guarded([&] {
+        if (!ctx) return;
+        (void)hipStreamSynchronize(ctx->stream);
+        delete ctx;
+    });
+}
+
+ins_status ins_set_stream(ins_ctx ctx, void* stream) {
+    return guarded([&] {
+        checked(ctx);
+        ctx->collect();
+        ctx->stream = static_cast<hipStream_t>(stream);
+    });
+}
+
+ins_status ins_workspace_bytes(ins_ctx ctx, size_t* bytes) {
+    return guarded([&] {
+        checked(ctx);
+        need(bytes, "bytes");
+        *bytes = ctx->bytes;
+    });
+}
+
+ins_status ins_rhs(ins_ctx ctx, const void* u, void* f) {
+    return guarded([&] {
+        checked(ctx);
+        need(u, "u");
+        need(f, "f");
+        with_type(ctx, [&](auto tag) {
+            using T = decltype(tag);
+            ctx->launch("rhs", [&] { return ins::launch_rhs<T>(ctx->g, static_cast<const T*>(u), static_cast<T*>(f), ctx->stream); });
+        });
+    });
+}
+
+ins_status ins_divergence(ins_ctx ctx, const void* u, double* r) {
+    return guarded([&] {
+        checked(ctx);
+        need(u, "u");
+        need(r, "r");
+        with_type(ctx, [&](auto tag) {
+            using T = decltype(tag);
+            ctx->launch("divergence", [&] { return ins::launch_divergence<T>(ctx->g, static_cast<const T*>(u), r, ctx->stream); });
+        });
+    });
+}
+
+ins_status ins_gradient(ins_ctx ctx, const double* p, void* gout) {
+    return guarded([&] {
+        checked(ctx);
+        need(p, "p");
+        need(gout, "g");
+        with_type(ctx, [&](auto tag) {
+            using T = decltype(tag);
+            ctx->launch("gradient", [&] { return ins::launch_gradient<T>(ctx->g, p, static_cast<T*>(gout), ctx->stream); });
+        });
+    });
+}
+
+ins_status ins_poisson_solve(ins_ctx ctx, const double* r, double* p) {
+    return guarded([&] {
+        checked(ctx);
+        need(r, "r");
+        need(p, "p");
+        poisson(ctx, nullptr, r, p);
+    });
+}
+
+ins_status ins_project(ins_ctx ctx, const void* u, void* u_out, double* p_out) {
+    return guarded([&] {
+        checked(ctx);
+        need(u, "u");
+        need(u_out, "u_out");
+        double* pp = p_out ? p_out : ctx->p;
+        poisson(ctx, u, nullptr, pp);
+        with_type(ctx, [&](auto tag) {
+            using T = decltype(tag);
+            apply_projection<T>(ctx, static_cast<const T*>(u), pp, static_cast<T*>(u_out));
+        });
+    });
+}
+
+ins_status ins_step_rk4(ins_ctx ctx, const void* u0, void* u1, double dt) {
+    return guarded([&] {
+        checked(ctx);
+        need(u0, "u0");
+        need(u1, "u1");
+        check_dt(dt);
+        with_type(ctx, [&](auto tag) {
+            using T = decltype(tag);
+            step_rk4<T>(ctx, static_cast<const T*>(u0), static_cast<T*>(u1), dt);
+        });
+    });
+}
+
+ins_status ins_rhs_vjp(ins_ctx ctx, const void* u, const void* fbar, void* ubar) {
+    return guarded([&] {
+        checked(ctx);
+        need(u, "u");
+        need(fbar, "fbar");
+        need(ubar, "ubar");
+        with_type(ctx, [&](auto tag) {
+            using T = decltype(tag);
+            ctx->launch("rhs_vjp", [&] {
+                return ins::launch_rhs_vjp<T>(ctx->g, static_cast<const T*>(u), static_cast<const T*>(fbar),
+                                              static_cast<T*>(ubar), ctx->stream);
+            });
+        });
+    });
+}
+
+ins_status ins_divergence_vjp(ins_ctx ctx, const double* rbar, void* ubar) {
+    return guarded([&] {
+        checked(ctx);
+        need(rbar, "rbar");
+        need(ubar, "ubar");
+        with_type(ctx, [&](auto tag) {
+            using T = decltype(tag);
+            ctx->launch("divergence_vjp", [&] { return ins::launch_div_vjp<T>(ctx->g, rbar, static_cast<T*>(ubar), ctx->stream); });
+        });
+    });
+}
+
+ins_status ins_gradient_vjp(ins_ctx ctx, const void* gbar, double* pbar) {
+    return guarded([&] {
+        checked(ctx);
+        need(gbar, "gbar");
+        need(pbar, "pbar");
+        with_type(ctx, [&](auto tag) {
+            using T = decltype(tag);
+            ctx->launch("gradient_vjp", [&] { return ins::launch_grad_vjp<T>(ctx->g, static_cast<const T*>(gbar), pbar, ctx->stream); });
+        });
+    });
+}
+
+ins_status ins_poisson_solve_vjp(ins_ctx ctx, const double* pbar, double* rbar) {
+    return ins_poisson_solve(ctx, pbar, rbar);
+}
+
+ins_status ins_project_vjp(ins_ctx ctx, const void* ubar_out, void* ubar) { return ins_project(ctx, ubar_out, ubar, nullptr); }
+
+ins_status ins_step_rk4_vjp(ins_ctx ctx, const void* u0, const void* u1bar, void* u0bar, double dt) {
+    return guarded([&] {
+        checked(ctx);
+        need(u0, "u0");
+        need(u1bar, "u1bar");
+        need(u0bar, "u0bar");
+        check_dt(dt);
+        if (u0bar == u0 || u0bar == u1bar) raise(INS_ERR_INVALID, "u0bar must not alias u0 or u1bar");
+        with_type(ctx, [&](auto tag) {
+            using T = decltype(tag);
+            step_rk4_vjp<T>(ctx, static_cast<const T*>(u0), static_cast<const T*>(u1bar), static_cast<T*>(u0bar), dt);
+        });
+    });
+}
+
+ins_status ins_stats(ins_ctx ctx, const void* u, double out[4]) {
+    return guarded([&] {
+        checked(ctx);
+        need(u, "u");
+        need(out, "out");
+        with_type(ctx, [&](auto tag) {
+            using T = decltype(tag);
+            ctx->launch("stats", [&] {
+                return ins::launch_stats<T>(ctx->g, static_cast<const T*>(u), ctx->partials, ctx->nstat, ctx->stream);
+            });
+        });
+        std::vector<double> h(size_t(ctx->nstat) * 4);
+        hip_check(hipMemcpyAsync(h.data(), ctx->partials, h.size() * sizeof(double), hipMemcpyDeviceToHost, ctx->stream),
+                  "copy partials");
+        hip_check(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+        double s2 = 0.0, mu = 0.0, md = 0.0, nf = 0.0;
+        for (int b = 0; b < ctx->nstat; ++b) {
+            s2 += h[4 * b];
+            mu = std::max(mu, h[4 * b + 1]);
+            md = std::max(md, h[4 * b + 2]);
+            nf += h[4 * b + 3];
+        }
+        out[0] = 0.5 * s2 / (double(ctx->g.ncell) * ctx->g.batch);
+        out[1] = mu;
+        out[2] = md;
+        out[3] = nf == 0.0 ? 1.0 : 0.0;
+    });
+}
+
+ins_status ins_stream_copy(ins_ctx ctx, const void* src, void* dst, size_t nbytes) {
+    return guarded([&] {
+        checked(ctx);
+        need(src, "src");
+        need(dst, "dst");
+        if (nbytes % 16 != 0) raise(INS_ERR_INVALID, "nbytes must be a multiple of 16");
+        ctx->launch("stream_copy", [&] { return ins::launch_stream_copy(src, dst, nbytes, ctx->stream); });
+    });
+}
+
+ins_status ins_profile_enable(ins_ctx ctx, int enable) {
+    return guarded([&] {
+        checked(ctx);
+        ctx->prof = enable != 0;
+    });
+}
+
+ins_status ins_profile_reset(ins_ctx ctx) {
+    return guarded([&] {
+        checked(ctx);
+        ctx->collect();
+        ctx->totals.clear();
+        ctx->order.clear();
+    });
+}
+
+ins_status ins_profile_count(ins_ctx ctx, int* count) {
+    return guarded([&] {
+        checked(ctx);
+        need(count, "count");
+        ctx->collect();
+        *count = int(ctx->order.size());
+    });
+}
+
+ins_status ins_profile_read(ins_ctx ctx, int i, char* name, size_t name_len, int64_t* launches, double* total_ms) {
+    return guarded([&] {
+        checked(ctx);
+        ctx->collect();
+        if (i < 0 || i >= int(ctx->order.size())) raise(INS_ERR_INVALID, "profile index out of range");
+        const std::string& nm = ctx->order[size_t(i)];
+        if (name && name_len > 0) {
+            std::strncpy(name, nm.c_str(), name_len - 1);
+            name[name_len - 1] = '\0';
+        }
+        const auto& tot = ctx->totals[nm];
+        if (launches) *launches = tot.first;
+        if (total_ms) *total_ms = tot.second;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,243 @@
+// Forward stencil kernels of the staggered periodic grid (App. B of the paper):
+// divergence, pressure gradient, diffusion + skew-symmetric convection, the
+// projection u - G p, and the fused RK4 stage.
+//
+// Memory-bound work (about 3 flop per byte in float64): one thread per cell,
+// all components of a cell in one thread so each neighbour load is shared by
+// the three component stencils, tiles of 64 x 4 cells ordered per XCD so halo
+// rows are reused from the L2 of the XCD that loaded them.
+#include "k_common.hpp"
+
+namespace ins {
+
+// F^a at the current cell: diffusion (eq. diff-kernel) + convection
+// (eq. conv-kernel with weights 1/2). The flux through the b-face of the
+// a-velocity volume is F^{ab}[K] = (u^a[K] + u^a[K+e_b]) (u^b[K] + u^b[K+e_a]) / 4,
+// formed at K = I and K = I - e_b and consumed at once (lazy components, Sec. 3.3).
+template <typename T, int DIM, class Src>
+__device__ __forceinline__ void rhs_cell(const Grid& g, const Src& U, const Nb& nb, T F[DIM]) {
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const int ax = a == 0, ay = a == 1, az = a == 2;
+        const T uc = U(a, nb, 0, 0, 0);
+        T diff = T(0), conv = T(0);
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) {
+            const int bx = b == 0, by = b == 1, bz = b == 2;
+            const T up = U(a, nb, bx, by, bz);
+            const T um = U(a, nb, -bx, -by, -bz);
+            diff += ((up - uc) - (uc - um)) * T(g.ih2[b]);
+            const T vr = U(b, nb, 0, 0, 0) + U(b, nb, ax, ay, az);
+            const T vl = U(b, nb, -bx, -by, -bz) + U(b, nb, ax - bx, ay - by, az - bz);
+            const T fr = (uc + up) * vr * T(0.25);
+            const T fl = (um + uc) * vl * T(0.25);
+            conv -= (fr - fl) * T(g.ih[b]);
+        }
+        F[a] = conv + T(g.nu) * diff;
+    }
+}
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_rhs(Grid g, const T* __restrict__ u, T* __restrict__ f) {
+    const TileIdx t = tile_of(g);
+    if (!t.valid) return;
+    const Nb nb = make_nb<DIM>(g, t.x, t.y, t.z);
+    const int64_t boff = int64_t(t.b) * DIM * g.ncell;
+    VelSrc<T, false> U{u + boff, nullptr, int(g.ncell), g.ih[0], g.ih[1], g.ih[2]};
+    T F[DIM];
+    rhs_cell<T, DIM>(g, U, nb, F);
+    const int c0 = nb.at(0, 0, 0);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) f[boff + a * g.ncell + c0] = F[a];
+}
+
+// RK4 stage: u_i = (PROJ ? w - G p : w), F = F(u_i),
+// (if y) y = (yinit ? u0 : y) + cy F, and (if wout) wout = u0 + cw F.
+template <typename T, int DIM, bool PROJ>
+__global__ __launch_bounds__(kBlock) void k_stage(Grid g, const T* __restrict__ w, const double* __restrict__ p,
+                                                   const T* __restrict__ u0, T* __restrict__ y, int yinit, T cy,
+                                                   T* __restrict__ wout, T cw) {
+    const TileIdx t = tile_of(g);
+    if (!t.valid) return;
+    const Nb nb = make_nb<DIM>(g, t.x, t.y, t.z);
+    const int64_t boff = int64_t(t.b) * DIM * g.ncell;
+    VelSrc<T, PROJ> U{w + boff, PROJ ? p + int64_t(t.b) * g.ncell : nullptr, int(g.ncell), g.ih[0], g.ih[1], g.ih[2]};
+    T F[DIM];
+    rhs_cell<T, DIM>(g, U, nb, F);
+    const int c0 = nb.at(0, 0, 0);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const int64_t k = boff + a * g.ncell + c0;
+        const T base = (wout || yinit) ? u0[k] : T(0);
+        if (y) y[k] = (yinit ? base : y[k]) + cy * F[a];
+        if (wout) wout[k] = base + cw * F[a];
+    }
+}
+
+// r = D u (float64), eq. div-kernel.
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_divergence(Grid g, const T* __restrict__ u, double* __restrict__ r) {
+    const TileIdx t = tile_of(g);
+    if (!t.valid) return;
+    const Nb nb = make_nb<DIM>(g, t.x, t.y, t.z);
+    const T* ub = u + int64_t(t.b) * DIM * g.ncell;
+    const int c0 = nb.at(0, 0, 0);
+    double acc = 0.0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const int cm = nb.at(-(a == 0), -(a == 1), -(a == 2));
+        acc += (double(ub[a * g.ncell + c0]) - double(ub[a * g.ncell + cm])) * g.ih[a];
+    }
+    r[int64_t(t.b) * g.ncell + c0] = acc;
+}
+
+// g = G p, eq. presgrad-kernel.
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_gradient(Grid g, const double* __restrict__ p, T* __restrict__ out) {
+    const TileIdx t = tile_of(g);
+    if (!t.valid) return;
+    const Nb nb = make_nb<DIM>(g, t.x, t.y, t.z);
+    const double* pb = p + int64_t(t.b) * g.ncell;
+    T* ob = out + int64_t(t.b) * DIM * g.ncell;
+    const int c0 = nb.at(0, 0, 0);
+    const double pc = pb[c0];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const int cp = nb.at(a == 0, a == 1, a == 2);
+        ob[a * g.ncell + c0] = T((pb[cp] - pc) * g.ih[a]);
+    }
+}
+
+// u_out = w - G p, in float64; u_out may alias w (pointwise in w).
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_apply_projection(Grid g, const T* w, const double* __restrict__ p, T* u_out) {
+    const TileIdx t = tile_of(g);
+    if (!t.valid) return;
+    const Nb nb = make_nb<DIM>(g, t.x, t.y, t.z);
+    const double* pb = p + int64_t(t.b) * g.ncell;
+    const int64_t boff = int64_t(t.b) * DIM * g.ncell;
+    const int c0 = nb.at(0, 0, 0);
+    const double pc = pb[c0];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const int cp = nb.at(a == 0, a == 1, a == 2);
+        const int64_t k = boff + a * g.ncell + c0;
+        u_out[k] = T(double(w[k]) - (pb[cp] - pc) * g.ih[a]);
+    }
+}
+
+// ubar = D^T rbar: ubar_a[J] = (rbar[J] - rbar[J + e_a]) / h_a.
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_div_vjp(Grid g, const double* __restrict__ rbar, T* __restrict__ ubar) {
+    const TileIdx t = tile_of(g);
+    if (!t.valid) return;
+    const Nb nb = make_nb<DIM>(g, t.x, t.y, t.z);
+    const double* rb = rbar + int64_t(t.b) * g.ncell;
+    T* ob = ubar + int64_t(t.b) * DIM * g.ncell;
+    const int c0 = nb.at(0, 0, 0);
+    const double rc = rb[c0];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const int cp = nb.at(a == 0, a == 1, a == 2);
+        ob[a * g.ncell + c0] = T((rc - rb[cp]) * g.ih[a]);
+    }
+}
+
+// pbar = G^T gbar: pbar[I] = sum_a (gbar_a[I - e_a] - gbar_a[I]) / h_a.
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_grad_vjp(Grid g, const T* __restrict__ gbar, double* __restrict__ pbar) {
+    const TileIdx t = tile_of(g);
+    if (!t.valid) return;
+    const Nb nb = make_nb<DIM>(g, t.x, t.y, t.z);
+    const T* gb = gbar + int64_t(t.b) * DIM * g.ncell;
+    const int c0 = nb.at(0, 0, 0);
+    double acc = 0.0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const int cm = nb.at(-(a == 0), -(a == 1), -(a == 2));
+        acc += (double(gb[a * g.ncell + cm]) - double(gb[a * g.ncell + c0])) * g.ih[a];
+    }
+    pbar[int64_t(t.b) * g.ncell + c0] = acc;
+}
+
+// ----------------------------------------------------------------------------
+// Launchers
+// ----------------------------------------------------------------------------
+#define INS_DISPATCH_DIM(g, KER, ...)                                                          \
+    do {                                                                                       \
+        const int nblk = stencil_blocks(g);                                                    \
+        if ((g).dim == 3)                                                                      \
+            hipLaunchKernelGGL((KER<T, 3>), dim3(nblk), dim3(kBlock), 0, s, __VA_ARGS__);      \
+        else                                                                                   \
+            hipLaunchKernelGGL((KER<T, 2>), dim3(nblk), dim3(kBlock), 0, s, __VA_ARGS__);      \
+    } while (0)
+
+template <typename T>
+hipError_t launch_rhs(const Grid& g, const T* u, T* f, hipStream_t s) {
+    INS_DISPATCH_DIM(g, k_rhs, g, u, f);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_divergence(const Grid& g, const T* u, double* r, hipStream_t s) {
+    INS_DISPATCH_DIM(g, k_divergence, g, u, r);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gradient(const Grid& g, const double* p, T* out, hipStream_t s) {
+    INS_DISPATCH_DIM(g, k_gradient, g, p, out);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_apply_projection(const Grid& g, const T* w, const double* p, T* u_out, hipStream_t s) {
+    INS_DISPATCH_DIM(g, k_apply_projection, g, w, p, u_out);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_div_vjp(const Grid& g, const double* rbar, T* ubar, hipStream_t s) {
+    INS_DISPATCH_DIM(g, k_div_vjp, g, rbar, ubar);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_grad_vjp(const Grid& g, const T* gbar, double* pbar, hipStream_t s) {
+    INS_DISPATCH_DIM(g, k_grad_vjp, g, gbar, pbar);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_stage(const Grid& g, const T* w, const double* p, bool proj, const T* u0, T* y, bool yinit, double cy,
+                        T* wout, double cw, hipStream_t s) {
+    const int nblk = stencil_blocks(g);
+    const int yi = yinit ? 1 : 0;
+    if (g.dim == 3) {
+        if (proj)
+            hipLaunchKernelGGL((k_stage<T, 3, true>), dim3(nblk), dim3(kBlock), 0, s, g, w, p, u0, y, yi, T(cy), wout, T(cw));
+        else
+            hipLaunchKernelGGL((k_stage<T, 3, false>), dim3(nblk), dim3(kBlock), 0, s, g, w, p, u0, y, yi, T(cy), wout, T(cw));
+    } else {
+        if (proj)
+            hipLaunchKernelGGL((k_stage<T, 2, true>), dim3(nblk), dim3(kBlock), 0, s, g, w, p, u0, y, yi, T(cy), wout, T(cw));
+        else
+            hipLaunchKernelGGL((k_stage<T, 2, false>), dim3(nblk), dim3(kBlock), 0, s, g, w, p, u0, y, yi, T(cy), wout, T(cw));
+    }
+    return hipGetLastError();
+}
+
+#define INS_INSTANTIATE(T)                                                                                          \
+    template hipError_t launch_rhs<T>(const Grid&, const T*, T*, hipStream_t);                                      \
+    template hipError_t launch_divergence<T>(const Grid&, const T*, double*, hipStream_t);                          \
+    template hipError_t launch_gradient<T>(const Grid&, const double*, T*, hipStream_t);                            \
+    template hipError_t launch_apply_projection<T>(const Grid&, const T*, const double*, T*, hipStream_t);          \
+    template hipError_t launch_div_vjp<T>(const Grid&, const double*, T*, hipStream_t);                             \
+    template hipError_t launch_grad_vjp<T>(const Grid&, const T*, double*, hipStream_t);                            \
+    template hipError_t launch_stage<T>(const Grid&, const T*, const double*, bool, const T*, T*, bool, double, T*, \
+                                        double, hipStream_t);
+
+INS_INSTANTIATE(double)
+INS_INSTANTIATE(float)
+
+}  // namespace ins

@@ -1,0 +1,174 @@
+// Reverse-mode stencils of the right-hand side (Sec. 3.4 pullback rule,
+// App. B): ubar = J_C(u)^T fbar + nu Lap(fbar), alone and fused into the
+// reverse RK4 stage.
+//
+// The convection pullback is written in gather form, so each thread owns its
+// output and no atomics are needed (results are bitwise deterministic). From
+// the forward flux F^{ab}[K] = a^{ab}[K] b^{ab}[K] with
+// a^{ab} = (u^a[K] + u^a[K+e_b])/2, b^{ab} = (u^b[K] + u^b[K+e_a])/2, the
+// cotangent of component g at J collects
+//   ubar^g[J] = 1/2 sum_b ( H^{gb}[J] + H^{gb}[J - e_b] ),
+//   H^{gb}[K] = (u^b[K] + u^b[K+e_g])/2 * ( (fbar^g[K+e_b] - fbar^g[K]) / h_b
+//                                         + (fbar^b[K+e_g] - fbar^b[K]) / h_g ),
+// i.e. the a-factor and b-factor cotangents of the two fluxes that contain
+// u^g[J]. (The printed eight-term pullback of App. B places the primal factor
+// of four of its terms one cell off; this form is derived from the forward
+// kernel instead.)
+#include "k_common.hpp"
+
+namespace ins {
+
+template <typename T, int DIM, class USrc, class FSrc>
+__device__ __forceinline__ void rhs_vjp_cell(const Grid& g, const USrc& U, const FSrc& Fb, const Nb& nb, T out[DIM]) {
+#pragma unroll
+    for (int gm = 0; gm < DIM; ++gm) {
+        const int gx = gm == 0, gy = gm == 1, gz = gm == 2;
+        const T ihg = T(g.ih[gm]);
+        const T fc = Fb(gm, nb, 0, 0, 0);
+        T diff = T(0), acc = T(0);
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) {
+            const int bx = b == 0, by = b == 1, bz = b == 2;
+            const T ihb = T(g.ih[b]);
+            const T fp = Fb(gm, nb, bx, by, bz);
+            const T fm = Fb(gm, nb, -bx, -by, -bz);
+            diff += ((fp - fc) - (fc - fm)) * T(g.ih2[b]);
+            const T m0 = U(b, nb, 0, 0, 0) + U(b, nb, gx, gy, gz);
+            const T g0 = (fp - fc) * ihb + (Fb(b, nb, gx, gy, gz) - Fb(b, nb, 0, 0, 0)) * ihg;
+            const T m1 = U(b, nb, -bx, -by, -bz) + U(b, nb, gx - bx, gy - by, gz - bz);
+            const T g1 = (fc - fm) * ihb + (Fb(b, nb, gx - bx, gy - by, gz - bz) - Fb(b, nb, -bx, -by, -bz)) * ihg;
+            acc += m0 * g0 + m1 * g1;
+        }
+        out[gm] = T(0.25) * acc + T(g.nu) * diff;
+    }
+}
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_rhs_vjp(Grid g, const T* __restrict__ u, const T* __restrict__ fbar,
+                                                      T* __restrict__ ubar) {
+    const TileIdx t = tile_of(g);
+    if (!t.valid) return;
+    const Nb nb = make_nb<DIM>(g, t.x, t.y, t.z);
+    const int64_t boff = int64_t(t.b) * DIM * g.ncell;
+    VelSrc<T, false> U{u + boff, nullptr, int(g.ncell), g.ih[0], g.ih[1], g.ih[2]};
+    VelSrc<T, false> F{fbar + boff, nullptr, int(g.ncell), g.ih[0], g.ih[1], g.ih[2]};
+    T out[DIM];
+    rhs_vjp_cell<T, DIM>(g, U, F, nb, out);
+    const int c0 = nb.at(0, 0, 0);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) ubar[boff + a * g.ncell + c0] = out[a];
+}
+
+// Cotangent of the stage right-hand side F_i, formed on the fly:
+// Fbar_i = cb * ybar + cw * (ubar_next - G q_next), where ubar_next - G q_next is
+// the projected cotangent of the next stage's unprojected input.
+template <typename T, bool HAS_W>
+struct FbarSrc {
+    const T* __restrict__ ybar;
+    const T* __restrict__ un;
+    const double* __restrict__ q;
+    T cb, cw;
+    int ncell;
+    double ih0, ih1, ih2;
+    __device__ __forceinline__ T operator()(int c, const Nb& nb, int dx, int dy, int dz) const {
+        const int j = nb.at(dx, dy, dz);
+        T v = cb * ybar[c * ncell + j];
+        if constexpr (HAS_W) {
+            const int jp = nb.at(dx + (c == 0), dy + (c == 1), dz + (c == 2));
+            const double ih = c == 0 ? ih0 : (c == 1 ? ih1 : ih2);
+            v += cw * T(double(un[c * ncell + j]) - (q[jp] - q[j]) * ih);
+        }
+        return v;
+    }
+};
+
+// Reverse RK4 stage i (see launch_stage_vjp for the bookkeeping).
+template <typename T, int DIM, bool PROJ_U, bool HAS_W>
+__global__ __launch_bounds__(kBlock) void k_stage_vjp(Grid g, const T* __restrict__ w, const double* __restrict__ p,
+                                                        const T* __restrict__ ybar, const T* __restrict__ un,
+                                                        const double* __restrict__ q, T cb, T cw, T* __restrict__ u0bar,
+                                                        int u0bar_mode, T* __restrict__ ubar_out) {
+    const TileIdx t = tile_of(g);
+    if (!t.valid) return;
+    const Nb nb = make_nb<DIM>(g, t.x, t.y, t.z);
+    const int64_t boff = int64_t(t.b) * DIM * g.ncell;
+    const int64_t soff = int64_t(t.b) * g.ncell;
+    const int nc = int(g.ncell);
+    VelSrc<T, PROJ_U> U{w + boff, PROJ_U ? p + soff : nullptr, nc, g.ih[0], g.ih[1], g.ih[2]};
+    FbarSrc<T, HAS_W> F{ybar + boff, HAS_W ? un + boff : nullptr, HAS_W ? q + soff : nullptr, cb, cw, nc,
+                        g.ih[0], g.ih[1], g.ih[2]};
+    T out[DIM];
+    rhs_vjp_cell<T, DIM>(g, U, F, nb, out);
+    const int c0 = nb.at(0, 0, 0);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const int64_t k = boff + a * g.ncell + c0;
+        T acc;
+        if (u0bar_mode == 0) {
+            acc = ybar[k];  // u0bar = ybar (first reverse stage)
+        } else {
+            acc = u0bar[k];
+        }
+        if constexpr (HAS_W) {
+            const int cp = nb.at(a == 0, a == 1, a == 2);
+            acc += T(double(un[k]) - (q[soff + cp] - q[soff + c0]) * g.ih[a]);
+        }
+        if (u0bar_mode == 2) acc += out[a];
+        u0bar[k] = acc;
+        if (ubar_out) ubar_out[k] = out[a];
+    }
+}
+
+template <typename T>
+hipError_t launch_rhs_vjp(const Grid& g, const T* u, const T* fbar, T* ubar, hipStream_t s) {
+    const int nblk = stencil_blocks(g);
+    if (g.dim == 3)
+        hipLaunchKernelGGL((k_rhs_vjp<T, 3>), dim3(nblk), dim3(kBlock), 0, s, g, u, fbar, ubar);
+    else
+        hipLaunchKernelGGL((k_rhs_vjp<T, 2>), dim3(nblk), dim3(kBlock), 0, s, g, u, fbar, ubar);
+    return hipGetLastError();
+}
+
+template <typename T, int DIM>
+static void stage_vjp_dim(const Grid& g, int nblk, const T* w, const double* p, bool proj_u, const T* ybar, const T* un,
+                          const double* q, bool has_w, T cb, T cw, T* u0bar, int mode, T* ubar_out, hipStream_t s) {
+    if (proj_u && has_w)
+        hipLaunchKernelGGL((k_stage_vjp<T, DIM, true, true>), dim3(nblk), dim3(kBlock), 0, s, g, w, p, ybar, un, q, cb, cw,
+                           u0bar, mode, ubar_out);
+    else if (proj_u)
+        hipLaunchKernelGGL((k_stage_vjp<T, DIM, true, false>), dim3(nblk), dim3(kBlock), 0, s, g, w, p, ybar, un, q, cb,
+                           cw, u0bar, mode, ubar_out);
+    else if (has_w)
+        hipLaunchKernelGGL((k_stage_vjp<T, DIM, false, true>), dim3(nblk), dim3(kBlock), 0, s, g, w, p, ybar, un, q, cb,
+                           cw, u0bar, mode, ubar_out);
+    else
+        hipLaunchKernelGGL((k_stage_vjp<T, DIM, false, false>), dim3(nblk), dim3(kBlock), 0, s, g, w, p, ybar, un, q, cb,
+                           cw, u0bar, mode, ubar_out);
+}
+
+// Reverse stage i: with u_i = (proj_u ? w - G p : w) and
+// Fbar_i = cb ybar + (has_w ? cw (un - G q) : 0),
+//   out = J_F(u_i)^T Fbar_i;
+//   u0bar = (mode == 0 ? ybar : u0bar) + (has_w ? un - G q : 0) + (mode == 2 ? out : 0);
+//   ubar_out (if not null) = out.
+template <typename T>
+hipError_t launch_stage_vjp(const Grid& g, const T* w, const double* p, bool proj_u, const T* ybar, const T* un,
+                            const double* q, bool has_w, double cb, double cw, T* u0bar, int mode, T* ubar_out,
+                            hipStream_t s) {
+    const int nblk = stencil_blocks(g);
+    if (g.dim == 3)
+        stage_vjp_dim<T, 3>(g, nblk, w, p, proj_u, ybar, un, q, has_w, T(cb), T(cw), u0bar, mode, ubar_out, s);
+    else
+        stage_vjp_dim<T, 2>(g, nblk, w, p, proj_u, ybar, un, q, has_w, T(cb), T(cw), u0bar, mode, ubar_out, s);
+    return hipGetLastError();
+}
+
+template hipError_t launch_rhs_vjp<double>(const Grid&, const double*, const double*, double*, hipStream_t);
+template hipError_t launch_rhs_vjp<float>(const Grid&, const float*, const float*, float*, hipStream_t);
+template hipError_t launch_stage_vjp<double>(const Grid&, const double*, const double*, bool, const double*,
+                                             const double*, const double*, bool, double, double, double*, int, double*,
+                                             hipStream_t);
+template hipError_t launch_stage_vjp<float>(const Grid&, const float*, const double*, bool, const float*, const float*,
+                                            const double*, bool, double, double, float*, int, float*, hipStream_t);
+
+}  // namespace ins

@@ -1,0 +1,227 @@
+"""Python face of the C ABI: a ``Solver`` owning one library context.
+
+Only marshalling happens here (shape, dtype, device and contiguity checks,
+pointer and stream hand-over); every step of the computation runs in the HIP
+kernels of ``libins.so``. torch supplies device memory and the stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+
+import torch
+
+from . import _lib as L
+
+_DTYPES = {"fp64": (L.INS_FP64, torch.float64), "fp32": (L.INS_FP32, torch.float32)}
+
+
+class Solver:
+    """Staggered periodic incompressible Navier-Stokes operators on one GPU.
+
+    Args:
+        n: cells per direction, (n_x, n_y) or (n_x, n_y, n_z).
+        nu: kinematic viscosity.
+        precision: "fp64" (everything float64) or "fp32" (float32 velocity
+            fields, stencils and RK stages; float64 divergence, Poisson solve
+            and projection).
+        batch: number of independent fields per call.
+        lo, hi: box corners (default [0, 2 pi] per direction).
+    """
+
+    def __init__(self, n, nu=0.0, precision="fp64", batch=1, lo=None, hi=None, device=None):
+        if precision not in _DTYPES:
+            raise ValueError(f"precision must be one of {list(_DTYPES)}")
+        self.n = tuple(int(v) for v in n)
+        self.dim = len(self.n)
+        if self.dim not in (2, 3):
+            raise ValueError("n must have 2 or 3 entries")
+        self.nu = float(nu)
+        self.batch = int(batch)
+        self.precision = precision
+        self._code, self.dtype = _DTYPES[precision]
+        self.lo = tuple(float(v) for v in (lo if lo is not None else [0.0] * self.dim))
+        self.hi = tuple(float(v) for v in (hi if hi is not None else [2 * math.pi] * self.dim))
+        self.h = tuple((self.hi[a] - self.lo[a]) / self.n[a] for a in range(self.dim))
+        if not torch.cuda.is_available():
+            raise RuntimeError("Solver needs a HIP device (torch.cuda.is_available() is False)")
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else torch.device(device).index or 0)
+        g = L.Grid()
+        g.dim = self.dim
+        for a in range(3):
+            g.n[a] = self.n[a] if a < self.dim else 1
+            g.lo[a] = self.lo[a] if a < self.dim else 0.0
+            g.hi[a] = self.hi[a] if a < self.dim else 1.0
+        g.batch = self.batch
+        self._ctx = C.c_void_p()
+        with torch.cuda.device(self.device):
+            L.call("ins_create", C.byref(g), L.INS_BC_PERIODIC, self.nu, self._code, C.byref(self._ctx))
+        spatial = tuple(reversed(self.n))
+        self.vel_shape = (self.batch, self.dim) + spatial
+        self.scal_shape = (self.batch,) + spatial
+
+    # ------------------------------------------------------------------ utils
+    def close(self):
+        if getattr(self, "_ctx", None) is not None and self._ctx.value:
+            L.call("ins_destroy", self._ctx)
+            self._ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _sync_stream(self):
+        L.call("ins_set_stream", self._ctx, C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream))
+
+    def _check(self, t, kind, name):
+        shape = self.vel_shape if kind == "vel" else self.scal_shape
+        dtype = self.dtype if kind == "vel" else torch.float64
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch tensor")
+        if t.device != self.device:
+            raise ValueError(f"{name} must be on {self.device}, got {t.device}")
+        if t.dtype != dtype:
+            raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+        if tuple(t.shape) != shape and not (self.batch == 1 and tuple(t.shape) == shape[1:]):
+            raise ValueError(f"{name} must have shape {shape}, got {tuple(t.shape)}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        return C.c_void_p(t.data_ptr())
+
+    def _unbatched(self, t):
+        return self.batch == 1 and t is not None and t.dim() in (len(self.vel_shape) - 1, len(self.scal_shape) - 1) \
+            and tuple(t.shape) in (self.vel_shape[1:], self.scal_shape[1:])
+
+    def _out(self, out, like, kind):
+        if out is None:
+            shape = self.vel_shape if kind == "vel" else self.scal_shape
+            if self._unbatched(like):
+                shape = shape[1:]
+            dtype = self.dtype if kind == "vel" else torch.float64
+            return torch.empty(shape, dtype=dtype, device=self.device)
+        return out
+
+    def new_velocity(self, fill=None):
+        t = torch.empty(self.vel_shape, dtype=self.dtype, device=self.device)
+        return t.zero_() if fill is None else t.fill_(fill)
+
+    def new_scalar(self):
+        return torch.zeros(self.scal_shape, dtype=torch.float64, device=self.device)
+
+    def workspace_bytes(self):
+        v = C.c_size_t()
+        L.call("ins_workspace_bytes", self._ctx, C.byref(v))
+        return int(v.value)
+
+    # -------------------------------------------------------------- forward
+    def rhs(self, u, out=None):
+        out = self._out(out, u, "vel")
+        self._sync_stream()
+        L.call("ins_rhs", self._ctx, self._check(u, "vel", "u"), self._check(out, "vel", "out"))
+        return out
+
+    def divergence(self, u, out=None):
+        out = self._out(out, u, "scal")
+        self._sync_stream()
+        L.call("ins_divergence", self._ctx, self._check(u, "vel", "u"), self._check(out, "scal", "out"))
+        return out
+
+    def gradient(self, p, out=None):
+        out = self._out(out, p, "vel")
+        self._sync_stream()
+        L.call("ins_gradient", self._ctx, self._check(p, "scal", "p"), self._check(out, "vel", "out"))
+        return out
+
+    def poisson_solve(self, r, out=None):
+        out = self._out(out, r, "scal")
+        self._sync_stream()
+        L.call("ins_poisson_solve", self._ctx, self._check(r, "scal", "r"), self._check(out, "scal", "out"))
+        return out
+
+    def project(self, u, out=None, p_out=None):
+        out = self._out(out, u, "vel")
+        self._sync_stream()
+        pp = self._check(p_out, "scal", "p_out") if p_out is not None else None
+        L.call("ins_project", self._ctx, self._check(u, "vel", "u"), self._check(out, "vel", "out"), pp)
+        return out
+
+    def step(self, u0, dt, out=None):
+        """One RK4 step; out may be u0 (in place)."""
+        out = self._out(out, u0, "vel")
+        self._sync_stream()
+        L.call("ins_step_rk4", self._ctx, self._check(u0, "vel", "u0"), self._check(out, "vel", "out"), float(dt))
+        return out
+
+    # ------------------------------------------------------------- pullbacks
+    def rhs_vjp(self, u, fbar, out=None):
+        out = self._out(out, u, "vel")
+        self._sync_stream()
+        L.call("ins_rhs_vjp", self._ctx, self._check(u, "vel", "u"), self._check(fbar, "vel", "fbar"),
+               self._check(out, "vel", "out"))
+        return out
+
+    def divergence_vjp(self, rbar, out=None):
+        out = self._out(out, rbar, "vel")
+        self._sync_stream()
+        L.call("ins_divergence_vjp", self._ctx, self._check(rbar, "scal", "rbar"), self._check(out, "vel", "out"))
+        return out
+
+    def gradient_vjp(self, gbar, out=None):
+        out = self._out(out, gbar, "scal")
+        self._sync_stream()
+        L.call("ins_gradient_vjp", self._ctx, self._check(gbar, "vel", "gbar"), self._check(out, "scal", "out"))
+        return out
+
+    def poisson_solve_vjp(self, pbar, out=None):
+        out = self._out(out, pbar, "scal")
+        self._sync_stream()
+        L.call("ins_poisson_solve_vjp", self._ctx, self._check(pbar, "scal", "pbar"), self._check(out, "scal", "out"))
+        return out
+
+    def project_vjp(self, ubar_out, out=None):
+        out = self._out(out, ubar_out, "vel")
+        self._sync_stream()
+        L.call("ins_project_vjp", self._ctx, self._check(ubar_out, "vel", "ubar_out"), self._check(out, "vel", "out"))
+        return out
+
+    def step_vjp(self, u0, u1bar, dt, out=None):
+        out = self._out(out, u0, "vel")
+        self._sync_stream()
+        L.call("ins_step_rk4_vjp", self._ctx, self._check(u0, "vel", "u0"), self._check(u1bar, "vel", "u1bar"),
+               self._check(out, "vel", "out"), float(dt))
+        return out
+
+    # ------------------------------------------------------------ utilities
+    def stats(self, u):
+        """(kinetic energy, max|u|, max|Du|, all finite) of a velocity field."""
+        out = (C.c_double * 4)()
+        self._sync_stream()
+        L.call("ins_stats", self._ctx, self._check(u, "vel", "u"), out)
+        return float(out[0]), float(out[1]), float(out[2]), bool(out[3] != 0.0)
+
+    def stream_copy(self, src, dst):
+        if src.numel() * src.element_size() != dst.numel() * dst.element_size():
+            raise ValueError("size mismatch")
+        self._sync_stream()
+        L.call("ins_stream_copy", self._ctx, C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()),
+               src.numel() * src.element_size())
+
+    def profile(self, enable=True):
+        L.call("ins_profile_enable", self._ctx, 1 if enable else 0)
+
+    def profile_reset(self):
+        L.call("ins_profile_reset", self._ctx)
+
+    def profile_read(self):
+        """{kernel name: (launches, total ms)} since the last reset (synchronises)."""
+        cnt = C.c_int()
+        L.call("ins_profile_count", self._ctx, C.byref(cnt))
+        res = {}
+        buf = C.create_string_buffer(128)
+        for i in range(cnt.value):
+            nl, ms = C.c_int64(), C.c_double()
+            L.call("ins_profile_read", self._ctx, i, buf, 128, C.byref(nl), C.byref(ms))
+            res[buf.value.decode()] = (int(nl.value), float(ms.value))
+        return res
