@@ -142,6 +142,29 @@ def run_mode(n, nu, dt, precision, steps, warmup, u0_np, adjoint):
     return ms, ms_p, prof, ok, ws
 
 
+def stream_copy_gbs(nbytes=2 << 30, reps=10):
+    """Bandwidth of the library's plain copy kernel (read + write bytes / time)."""
+    import torch
+
+    from paper_2604_18536_amd import Solver
+
+    s = Solver((8, 8, 8))
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    s.stream_copy(a, b)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        s.stream_copy(a, b)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    s.close()
+    del a, b
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
 def cpu_baseline(n, nu, dt, u0_np, budget_s=30.0):
     """The float64 numpy oracle, as written, on the host: RK4 steps of the same field."""
     import oracle as O
@@ -196,6 +219,8 @@ def main():
     u0 = S.turbulence_ic(n, seed=0, k0=4.0)
     print(f"[bench] initial field ready {n}", file=sys.stderr, flush=True)
 
+    copy_gbs = stream_copy_gbs()
+    print(f"[bench] streaming copy {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
     modes = {}
     kernels = {}
     for mode in args.modes.split(","):
@@ -269,6 +294,7 @@ def main():
             "dt": dt,
         },
         "roofline": roofline,
+        "stream_copy_gbs": round(copy_gbs, 1),
         "cpu_baseline": cpu,
         "modes": modes,
         "kernels": kernels,

@@ -1,0 +1,119 @@
+"""Summarise rocprofv3 output into the text files under profiles/.
+
+  python profile_summary.py trace  <kernel_stats.csv> <out.md> <command...>
+  python profile_summary.py traffic <fetch counter_collection.csv> <write counter_collection.csv> <out.md> <command...>
+
+`traffic` also updates profiles/traffic.json, the measured HBM bytes per
+launch that bench.py reports as roofline.traffic. Counters are calibrated with
+the library's plain copy kernel (k_stream_copy, bytes known): the measured
+FETCH_SIZE and WRITE_SIZE of every kernel are scaled by
+(bytes the copy moved) / (what the counter read for it). A record carries a
+hash of the kernel's source files and is ignored once they change.
+
+Per-variant records: one template instance can serve several launch variants
+(the RK stage kernel runs as `stage` twice and `stage_last` once per step);
+their dispatches interleave in a fixed order, given in VARIANT_ORDER.
+"""
+import csv
+import hashlib
+import json
+import os
+import sys
+from collections import defaultdict
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(ROOT, "paper_2604_18536_amd", "csrc")
+
+# template instance (prefix of the demangled name) -> (variant names in dispatch order, source files)
+VARIANT_ORDER = {
+    "void ins::k_stage<double, 3, true>": (["stage", "stage", "stage_last"], ["k_stencil.hip", "k_common.hpp"]),
+    "void ins::k_stage<double, 3, false>": (["stage_first"], ["k_stencil.hip", "k_common.hpp"]),
+    "void ins::k_stage_zm<double, true>": (["stage", "stage", "stage_last"], ["k_stage3d.hip", "k_common.hpp"]),
+    "void ins::k_stage_zm<double, false>": (["stage_first"], ["k_stage3d.hip", "k_common.hpp"]),
+    "void ins::k_fft_x_fwd<double, 3, true>": (["fft_x_fwd_div"], ["k_fft.hip", "k_common.hpp"]),
+    "void ins::k_fft_strided<0>": (["fft_y_fwd"], ["k_fft.hip", "k_common.hpp"]),
+    "void ins::k_fft_strided<2>": (["fft_z_solve"], ["k_fft.hip", "k_common.hpp"]),
+    "void ins::k_fft_strided<1>": (["fft_y_inv"], ["k_fft.hip", "k_common.hpp"]),
+    "ins::k_fft_x_inv": (["fft_x_inv"], ["k_fft.hip", "k_common.hpp"]),
+    "void ins::k_apply_projection<double, 3>": (["apply_projection"], ["k_stencil.hip", "k_common.hpp"]),
+}
+COPY = "ins::k_stream_copy"
+
+
+def source_hash(files):
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def trace(stats_csv, out_md, command):
+    rows = list(csv.DictReader(open(stats_csv)))
+    lines = ["# rocprofv3 kernel trace summary", "", "Command:", "", "```", command, "```", "",
+             "| kernel | calls | avg us | min us | max us | % time |", "|---|---|---|---|---|---|"]
+    for r in rows:
+        name = r["Name"].split("(")[0]
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
+    open(out_md, "w").write("\n".join(lines) + "\n")
+
+
+def _per_dispatch(path, counter):
+    d = defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        if r.get("Counter_Name") != counter:
+            continue
+        d[r["Kernel_Name"].split("(")[0]].append((int(r["Dispatch_Id"]), float(r["Counter_Value"]) * 1024.0))
+    for k in d:
+        d[k].sort()
+    return d
+
+
+def traffic(fetch_csv, write_csv, out_md, command, copy_bytes=None):
+    f = _per_dispatch(fetch_csv, "FETCH_SIZE")
+    w = _per_dispatch(write_csv, "WRITE_SIZE")
+    # copy calibration: the copy kernel reads and writes copy_bytes each
+    cf = [v for _, v in f[COPY]][1:]  # first launch is a warm-up of the same size
+    cw = [v for _, v in w[COPY]][1:]
+    if copy_bytes is None:
+        copy_bytes = 2 << 30
+    kf = copy_bytes / (sum(cf) / len(cf))
+    kw = copy_bytes / (sum(cw) / len(cw))
+    lines = ["# HBM traffic per launch from rocprofv3 counters", "", "Commands (one counter per run):", "", "```",
+             command, "```", "",
+             f"Calibration with the plain copy kernel (reads and writes {copy_bytes / 2**20:.0f} MiB): "
+             f"FETCH_SIZE x {kf:.3f}, WRITE_SIZE x {kw:.3f}.", "",
+             "| kernel variant | launches | fetched MiB | written MiB | total MiB |", "|---|---|---|---|---|"]
+    rec = {}
+    jpath = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(jpath):
+        rec = json.load(open(jpath))
+    for inst, (variants, srcs) in VARIANT_ORDER.items():
+        if inst not in f:
+            continue
+        fv = [v for _, v in f[inst]]
+        wv = [v for _, v in w.get(inst, [])]
+        per = defaultdict(lambda: [0.0, 0.0, 0])
+        for i in range(min(len(fv), len(wv))):
+            name = variants[i % len(variants)]
+            per[name][0] += fv[i] * kf
+            per[name][1] += wv[i] * kw
+            per[name][2] += 1
+        for name, (a, b, n) in per.items():
+            lines.append(f"| `{inst.replace('void ', '')}` as {name} | {n} | {a / n / 2**20:.1f} | {b / n / 2**20:.1f} | "
+                         f"{(a + b) / n / 2**20:.1f} |")
+            rec[name] = {"bytes_per_launch": round((a + b) / n), "fetch": round(a / n), "write": round(b / n),
+                         "sources": srcs, "source_hash": source_hash(srcs)}
+    open(out_md, "w").write("\n".join(lines) + "\n")
+    json.dump(rec, open(jpath, "w"), indent=1, sort_keys=True)
+
+
+if __name__ == "__main__":
+    mode = sys.argv[1]
+    if mode == "trace":
+        trace(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))
+    elif mode == "traffic":
+        traffic(sys.argv[2], sys.argv[3], sys.argv[4], " ".join(sys.argv[5:]))
+    else:
+        raise SystemExit(__doc__)
