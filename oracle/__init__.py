@@ -29,5 +29,7 @@ from .ins import (  # noqa: F401
     step_rk4_vjp,
     rk4_stages,
     kinetic_energy,
+    rollout_loss,
+    rollout_loss_grad,
 )
 from .aux import face_filter, energy_spectrum  # noqa: F401

@@ -159,26 +159,28 @@ RK4_A = (0.5, 0.5, 1.0)
 RK4_B = (1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0)
 
 
-def rk4_stages(u0, h, nu, dt):
+def rk4_stages(u0, h, nu, dt, rhs_fn=None):
     """Stage velocities u_1..u_4 and stage right-hand sides F_1..F_4 of one step.
 
     u_1 = u0 and u_{i+1} = P(u0 + dt a_{i+1} F(u_i)); returns (us, Fs).
+    rhs_fn(u) replaces F when given (e.g. F plus a closure term).
     """
+    F = rhs_fn if rhs_fn is not None else (lambda v: rhs(v, h, nu))
     us = [np.array(u0, dtype=np.float64)]
     fs = []
     for i in range(4):
-        fs.append(rhs(us[i], h, nu))
+        fs.append(F(us[i]))
         if i < 3:
             us.append(project(u0 + dt * RK4_A[i] * fs[i], h)[0])
     return us, fs
 
 
-def step_rk4(u0, h, nu, dt):
+def step_rk4(u0, h, nu, dt, rhs_fn=None):
     """One classical RK4 step with the velocity projected at every stage.
 
     u_{n+1} = P(u0 + dt (F_1 + 2 F_2 + 2 F_3 + F_4) / 6).
     """
-    _, fs = rk4_stages(u0, h, nu, dt)
+    _, fs = rk4_stages(u0, h, nu, dt, rhs_fn)
     y = u0 + dt * (fs[0] + 2.0 * fs[1] + 2.0 * fs[2] + fs[3]) / 6.0
     return project(y, h)[0]
 
@@ -249,18 +251,20 @@ def project_vjp(ubar_out, h):
     return project(ubar_out, h)[0]
 
 
-def step_rk4_vjp(u0, u1bar, h, nu, dt):
+def step_rk4_vjp(u0, u1bar, h, nu, dt, rhs_fn=None, rhs_vjp_fn=None):
     """Reverse pass of ``step_rk4``: the stage loop run backwards with the pullbacks above.
 
     Stage states are recomputed from u0 first (the forward states must exist
-    before back-propagation, Sec. 3.4).
+    before back-propagation, Sec. 3.4). rhs_vjp_fn(u, fbar) replaces the
+    right-hand-side pullback when given (it may accumulate parameter gradients).
     """
-    us, _ = rk4_stages(u0, h, nu, dt)
+    us, _ = rk4_stages(u0, h, nu, dt, rhs_fn)
+    G = rhs_vjp_fn if rhs_vjp_fn is not None else (lambda v, fb: rhs_vjp(v, fb, h, nu))
     ybar = project_vjp(u1bar, h)
     u0bar = ybar.copy()
     fbar = [dt * RK4_B[i] * ybar for i in range(4)]
     for i in range(3, -1, -1):
-        ubar_i = rhs_vjp(us[i], fbar[i], h, nu)
+        ubar_i = G(us[i], fbar[i])
         if i == 0:
             u0bar += ubar_i
         else:
@@ -268,3 +272,32 @@ def step_rk4_vjp(u0, u1bar, h, nu, dt):
             u0bar += wbar
             fbar[i - 1] = fbar[i - 1] + dt * RK4_A[i - 1] * wbar
     return u0bar
+
+
+# ----------------------------------------------------------------------------
+# Unrolled trajectory loss and its gradient (back-propagation relation, Sec. 3.4)
+# ----------------------------------------------------------------------------
+
+def rollout_loss(u0, refs, h, nu, dt):
+    """L(u0) = (1/S) sum_{s=1..S} mean((u_s - refs[s-1])^2), u_s = step_rk4^s(u0)."""
+    S = len(refs)
+    u = np.array(u0, dtype=np.float64)
+    total = 0.0
+    for s in range(S):
+        u = step_rk4(u, h, nu, dt)
+        total += float(np.mean((u - refs[s]) ** 2)) / S
+    return total
+
+
+def rollout_loss_grad(u0, refs, h, nu, dt):
+    """dL/du0: store the states, then run x_bar_n = pullback_n(x_bar_{n+1}) from the last step back."""
+    S = len(refs)
+    states = [np.array(u0, dtype=np.float64)]
+    for s in range(S):
+        states.append(step_rk4(states[-1], h, nu, dt))
+    m = states[0].size
+    ubar = np.zeros_like(states[0])
+    for s in range(S, 0, -1):
+        ubar = ubar + 2.0 * (states[s] - refs[s - 1]) / (m * S)
+        ubar = step_rk4_vjp(states[s - 1], ubar, h, nu, dt)
+    return ubar

@@ -166,3 +166,16 @@ def test_step_vjp_against_torch_autograd_and_fd(n):
         v = S.random_field(n, seed)
         fd = _dot(ubar, _central(lambda x: O.step_rk4(x, h, nu, dt), u0, v, 1e-4))
         assert abs(fd - _dot(g, v)) < 1e-7 * np.abs(g * v).sum()
+
+
+def test_rollout_loss_gradient_central_difference():
+    n = (8, 6)
+    h = S.spacing(n)
+    nu, dt = 0.05, 0.05
+    u0 = S.turbulence_ic(n, seed=3, k0=2)
+    refs = [S.turbulence_ic(n, seed=10 + s, k0=2) for s in range(4)]
+    g = O.rollout_loss_grad(u0, refs, h, nu, dt)
+    for seed in (40, 41):
+        v = S.random_field(n, seed)
+        fd = (O.rollout_loss(u0 + 1e-5 * v, refs, h, nu, dt) - O.rollout_loss(u0 - 1e-5 * v, refs, h, nu, dt)) / 2e-5
+        assert abs(fd - _dot(g, v)) < 1e-7 * np.abs(g * v).sum()
