@@ -181,6 +181,30 @@ ins_status ins_project_vjp(ins_ctx ctx, const void* ubar_out, void* ubar);
 ins_status ins_step_rk4_vjp(ins_ctx ctx, const void* u0, const void* u1bar, void* u0bar, double dt);
 
 /* ---------------------------------------------------------------------------
+ * LES data helpers (filtered DNS and its spectrum). The paper names the
+ * pipeline DNS -> filter -> LES (Sec. 4) but not the filter or the spectrum
+ * binning; the readings are stated with each call.
+ * ------------------------------------------------------------------------- */
+
+/* Face filter from the context's (fine) grid to a grid coarser by `factor` in
+ * every direction: coarse cell I covers fine cells factor*I .. factor*I +
+ * factor - 1, and its a-velocity is the mean of the factor^(dim-1) fine
+ * a-velocities on its right a-face. Maps solenoidal to solenoidal (the coarse
+ * divergence is the volume mean of the fine one). u: fine velocity field;
+ * u_coarse: [batch][dim][n_z/f][n_y/f][n_x/f], context dtype. Every n must be
+ * divisible by factor (else INS_ERR_INVALID). */
+ins_status ins_face_filter(ins_ctx ctx, const void* u, int factor, void* u_coarse);
+
+/* Kinetic-energy spectrum E(k) = 1/2 sum over the shell k - 1/2 <= |k| < k + 1/2
+ * of sum_a |uhat_a(k)|^2 / N^2 (integer wavenumber index k, N cells, uhat the
+ * unnormalised DFT), k = 0 .. nbins-1, per field of the batch. e: device
+ * float64 array [batch][nbins], overwritten; shells beyond nbins are dropped
+ * (nbins = floor(sqrt(dim) * n_max / 2 + 1/2) + 1 keeps every mode, so the sum
+ * of e equals the mean kinetic energy). Uses the context's spectrum buffer;
+ * shell sums are accumulated with atomic adds (order-dependent rounding). */
+ins_status ins_energy_spectrum(ins_ctx ctx, const void* u, double* e, int nbins);
+
+/* ---------------------------------------------------------------------------
  * Utilities (diagnostics, benchmarking)
  * ------------------------------------------------------------------------- */
 

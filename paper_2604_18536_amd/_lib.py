@@ -59,6 +59,8 @@ _SIGS = {
     "ins_poisson_solve_vjp": ([_P, _P, _P]),
     "ins_project_vjp": ([_P, _P, _P]),
     "ins_step_rk4_vjp": ([_P, _P, _P, _P, _D]),
+    "ins_face_filter": ([_P, _P, C.c_int, _P]),
+    "ins_energy_spectrum": ([_P, _P, _P, C.c_int]),
     "ins_stats": ([_P, _P, C.POINTER(_D)]),
     "ins_stream_copy": ([_P, _P, _P, C.c_size_t]),
     "ins_profile_enable": ([_P, C.c_int]),

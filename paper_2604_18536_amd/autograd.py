@@ -1,0 +1,109 @@
+"""Reverse-mode differentiation through the solver (Sec. 3.4) with checkpointed unrolls.
+
+``step(solver, u, dt)`` is a ``torch.autograd.Function`` whose backward is the
+library's hand-written RK4-step pullback (``ins_step_rk4_vjp``); torch only
+chains the steps. ``rollout_loss`` unrolls many steps and keeps only every
+``checkpoint_every``-th state: the backward recomputes each segment from its
+first state, so memory grows with (steps / k + k) fields instead of with the
+number of steps (the paper's outlook, Sec. 6.2, names checkpointing as the
+remedy for storing every state).
+"""
+from __future__ import annotations
+
+import torch
+import torch.utils.checkpoint as _ckpt
+
+
+class _Step(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, u0, solver, dt):
+        ctx.solver = solver
+        ctx.dt = float(dt)
+        ctx.save_for_backward(u0)
+        return solver.step(u0.contiguous(), dt)
+
+    @staticmethod
+    def backward(ctx, u1bar):
+        (u0,) = ctx.saved_tensors
+        g = ctx.solver.step_vjp(u0.contiguous(), u1bar.contiguous(), ctx.dt)
+        return g, None, None
+
+
+class _Rhs(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, u, solver):
+        ctx.solver = solver
+        ctx.save_for_backward(u)
+        return solver.rhs(u.contiguous())
+
+    @staticmethod
+    def backward(ctx, fbar):
+        (u,) = ctx.saved_tensors
+        return ctx.solver.rhs_vjp(u.contiguous(), fbar.contiguous()), None
+
+
+class _Project(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, u, solver):
+        ctx.solver = solver
+        return solver.project(u.contiguous())
+
+    @staticmethod
+    def backward(ctx, ubar):
+        return ctx.solver.project_vjp(ubar.contiguous()), None
+
+
+def step(solver, u, dt):
+    """One differentiable RK4 step."""
+    return _Step.apply(u, solver, dt)
+
+
+def rhs(solver, u):
+    """Differentiable right-hand side F(u)."""
+    return _Rhs.apply(u, solver)
+
+
+def project(solver, u):
+    """Differentiable projection P u."""
+    return _Project.apply(u, solver)
+
+
+def rollout(solver, u0, dt, nsteps):
+    """States u_1..u_n (every state kept by autograd; use rollout_loss for long unrolls)."""
+    out = []
+    u = u0
+    for _ in range(nsteps):
+        u = step(solver, u, dt)
+        out.append(u)
+    return out
+
+
+def rollout_loss(solver, u0, dt, refs, checkpoint_every=10, per_step_loss=None):
+    """Sum over s = 1..len(refs) of per_step_loss(u_s, refs[s-1]), differentiable in u0.
+
+    Default per-step loss: mean over cells and components of (u_s - ref_s)^2,
+    divided by the number of steps (so the total is the trajectory MSE).
+    Only the state at the start of every segment of ``checkpoint_every`` steps
+    is kept; each segment is recomputed in the backward pass.
+    """
+    nsteps = len(refs)
+    if per_step_loss is None:
+
+        def per_step_loss(u, r):
+            return ((u - r) ** 2).mean() / nsteps
+
+    def segment(u, s0, s1):
+        total = u.new_zeros(())
+        for s in range(s0, s1):
+            u = step(solver, u, dt)
+            total = total + per_step_loss(u, refs[s])
+        return u, total
+
+    k = max(1, int(checkpoint_every))
+    u = u0
+    loss = u0.new_zeros(())
+    for s0 in range(0, nsteps, k):
+        s1 = min(s0 + k, nsteps)
+        u, seg = _ckpt.checkpoint(segment, u, s0, s1, use_reentrant=False)
+        loss = loss + seg
+    return loss

@@ -73,12 +73,18 @@ template <typename T>
 hipError_t launch_stage(const Grid& g, const T* w, const double* p, bool proj, const T* u0, T* y, bool yinit, double cy,
                         T* wout, double cw, hipStream_t s);
 
+// 3D variant of launch_stage: 2.5D z-march with an LDS ring of projected planes.
+template <typename T>
+hipError_t launch_stage_zm(const Grid& g, const T* w, const double* p, bool proj, const T* u0, T* y, bool yinit,
+                           double cy, T* wout, double cw, hipStream_t s);
+
 // Spectral Poisson solve pieces.
-// Forward x pass: real rows -> half spectrum. If vel != nullptr the rows are
-// the divergence of vel computed on the fly; else rows come from r.
+// Forward x pass: real rows -> half spectrum. vel != nullptr and comp < 0:
+// rows are the divergence of vel computed on the fly; vel != nullptr and
+// comp >= 0: rows of velocity component comp; else rows come from r.
 template <typename T>
 hipError_t launch_fft_x_fwd(const Grid& g, const T* vel, const double* r, cd* spec, const FftPlan& px, const cd* post_tw,
-                            int lines, hipStream_t s);
+                            int lines, hipStream_t s, int comp = -1);
 hipError_t launch_fft_x_inv(const Grid& g, const cd* spec, double* p, const FftPlan& px, const cd* post_tw, int lines,
                             hipStream_t s);
 // Strided C2C pass over the half spectrum. mode 0: forward, 1: inverse,
@@ -97,6 +103,20 @@ template <typename T>
 hipError_t launch_stage_vjp(const Grid& g, const T* w, const double* p, bool proj_u, const T* ybar, const T* un,
                             const double* q, bool has_w, double cb, double cw, T* u0bar, int mode, T* ubar_out,
                             hipStream_t s);
+
+template <typename T>
+hipError_t launch_stage_vjp_zm(const Grid& g, const T* w, const double* p, bool proj_u, const T* ybar, const T* un,
+                               const double* q, bool has_w, double cb, double cw, T* u0bar, int mode, T* ubar_out,
+                               hipStream_t s);
+
+// LES data helpers.
+// Coarse staggered field: mean of the f^(d-1) fine a-faces on each coarse a-face.
+template <typename T>
+hipError_t launch_face_filter(const Grid& fine, int f, const T* u, T* uc, hipStream_t s);
+// Accumulate 1/2 |X|^2 / N^2 of one half spectrum into integer-|k| shells (atomic adds).
+hipError_t launch_spectrum_bins(const Grid& g, const cd* spec, double* bins, int nbins, hipStream_t s);
+// p[0..n) = 0 with a kernel (kept out of hipMemsetAsync so callers may capture it).
+hipError_t launch_fill_zero(double* p, size_t n, hipStream_t s);
 
 // Utilities.
 template <typename T>

@@ -643,6 +643,47 @@ ins_status ins_step_rk4_vjp(ins_ctx ctx, const void* u0, const void* u1bar, void
     });
 }
 
+ins_status ins_face_filter(ins_ctx ctx, const void* u, int factor, void* u_coarse) {
+    return guarded([&] {
+        checked(ctx);
+        need(u, "u");
+        need(u_coarse, "u_coarse");
+        const ins::Grid& g = ctx->g;
+        if (factor < 1 || g.nx % factor || g.ny % factor || (g.dim == 3 && g.nz % factor))
+            raise(INS_ERR_INVALID, "every cell count must be divisible by the filter factor");
+        with_type(ctx, [&](auto tag) {
+            using T = decltype(tag);
+            ctx->launch("face_filter", [&] {
+                return ins::launch_face_filter<T>(g, factor, static_cast<const T*>(u), static_cast<T*>(u_coarse), ctx->stream);
+            });
+        });
+    });
+}
+
+ins_status ins_energy_spectrum(ins_ctx ctx, const void* u, double* e, int nbins) {
+    return guarded([&] {
+        checked(ctx);
+        need(u, "u");
+        need(e, "e");
+        if (nbins < 1) raise(INS_ERR_INVALID, "nbins must be >= 1");
+        const ins::Grid& g = ctx->g;
+        ctx->launch("fill_zero", [&] { return ins::launch_fill_zero(e, size_t(nbins) * g.batch, ctx->stream); });
+        for (int a = 0; a < g.dim; ++a) {
+            with_type(ctx, [&](auto tag) {
+                using T = decltype(tag);
+                ctx->launch("fft_x_fwd", [&] {
+                    return ins::launch_fft_x_fwd<T>(g, static_cast<const T*>(u), nullptr, ctx->spec, ctx->px, ctx->d_post,
+                                                    ctx->lnl_x, ctx->stream, a);
+                });
+            });
+            ctx->launch("fft_y_fwd", [&] { return ins::launch_fft_strided(g, ctx->spec, ctx->py, 1, 0, ctx->lnl_y, ctx->st, ctx->stream); });
+            if (g.dim == 3)
+                ctx->launch("fft_z_fwd", [&] { return ins::launch_fft_strided(g, ctx->spec, ctx->pz, 2, 0, ctx->lnl_z, ctx->st, ctx->stream); });
+            ctx->launch("spectrum_bins", [&] { return ins::launch_spectrum_bins(g, ctx->spec, e, nbins, ctx->stream); });
+        }
+    });
+}
+
 ins_status ins_stats(ins_ctx ctx, const void* u, double out[4]) {
     return guarded([&] {
         checked(ctx);

@@ -93,6 +93,59 @@ struct VelSrc {
     }
 };
 
+// F^a at the current cell: diffusion (eq. diff-kernel) + convection
+// (eq. conv-kernel with weights 1/2). The flux through the b-face of the
+// a-velocity volume is F^{ab}[K] = (u^a[K] + u^a[K+e_b]) (u^b[K] + u^b[K+e_a]) / 4,
+// formed at K = I and K = I - e_b and consumed at once (lazy components, Sec. 3.3).
+template <typename T, int DIM, class Src>
+__device__ __forceinline__ void rhs_cell(const Grid& g, const Src& U, const Nb& nb, T F[DIM]) {
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const int ax = a == 0, ay = a == 1, az = a == 2;
+        const T uc = U(a, nb, 0, 0, 0);
+        T diff = T(0), conv = T(0);
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) {
+            const int bx = b == 0, by = b == 1, bz = b == 2;
+            const T up = U(a, nb, bx, by, bz);
+            const T um = U(a, nb, -bx, -by, -bz);
+            diff += ((up - uc) - (uc - um)) * T(g.ih2[b]);
+            const T vr = U(b, nb, 0, 0, 0) + U(b, nb, ax, ay, az);
+            const T vl = U(b, nb, -bx, -by, -bz) + U(b, nb, ax - bx, ay - by, az - bz);
+            const T fr = (uc + up) * vr * T(0.25);
+            const T fl = (um + uc) * vl * T(0.25);
+            conv -= (fr - fl) * T(g.ih[b]);
+        }
+        F[a] = conv + T(g.nu) * diff;
+    }
+}
+
+// Pullback of the right-hand side at one cell (gather form; see k_vjp.hip).
+template <typename T, int DIM, class USrc, class FSrc>
+__device__ __forceinline__ void rhs_vjp_cell(const Grid& g, const USrc& U, const FSrc& Fb, const Nb& nb, T out[DIM]) {
+#pragma unroll
+    for (int gm = 0; gm < DIM; ++gm) {
+        const int gx = gm == 0, gy = gm == 1, gz = gm == 2;
+        const T ihg = T(g.ih[gm]);
+        const T fc = Fb(gm, nb, 0, 0, 0);
+        T diff = T(0), acc = T(0);
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) {
+            const int bx = b == 0, by = b == 1, bz = b == 2;
+            const T ihb = T(g.ih[b]);
+            const T fp = Fb(gm, nb, bx, by, bz);
+            const T fm = Fb(gm, nb, -bx, -by, -bz);
+            diff += ((fp - fc) - (fc - fm)) * T(g.ih2[b]);
+            const T m0 = U(b, nb, 0, 0, 0) + U(b, nb, gx, gy, gz);
+            const T g0 = (fp - fc) * ihb + (Fb(b, nb, gx, gy, gz) - Fb(b, nb, 0, 0, 0)) * ihg;
+            const T m1 = U(b, nb, -bx, -by, -bz) + U(b, nb, gx - bx, gy - by, gz - bz);
+            const T g1 = (fc - fm) * ihb + (Fb(b, nb, gx - bx, gy - by, gz - bz) - Fb(b, nb, -bx, -by, -bz)) * ihg;
+            acc += m0 * g0 + m1 * g1;
+        }
+        out[gm] = T(0.25) * acc + T(g.nu) * diff;
+    }
+}
+
 inline int stencil_blocks(const Grid& g) {
     const int ntx = (g.nx + kTileX - 1) / kTileX;
     const int nty = (g.ny + kTileY - 1) / kTileY;

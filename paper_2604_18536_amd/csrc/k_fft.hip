@@ -187,10 +187,12 @@ __device__ void fft_lines(cd* lds, int lnl, const FftPlan& P) {
 // Packing: z[m] = x[2m] + i x[2m+1]; Z = FFT_M(z);
 // X[k] = (Z[k] + conj Z[M-k]) / 2 + W^k (Z[k] - conj Z[M-k]) / (2i), W = exp(-2 pi i / n_x).
 // ----------------------------------------------------------------------------
-template <typename T, int DIM, bool FROM_VEL>
+// SRC 0: rows are the divergence of the velocity field `vel`;
+// SRC 1: rows of the float64 scalar field r; SRC 2: rows of component `comp` of vel.
+template <typename T, int DIM, int SRC>
 __global__ __launch_bounds__(kBlock) void k_fft_x_fwd(Grid g, const T* __restrict__ vel, const double* __restrict__ r,
                                                         cd* __restrict__ spec, FftPlan P, const cd* __restrict__ post,
-                                                        int lnl) {
+                                                        int lnl, int comp) {
     extern __shared__ cd lds[];
     const int nl = 1 << lnl;
     const int M = P.n;
@@ -201,7 +203,7 @@ __global__ __launch_bounds__(kBlock) void k_fft_x_fwd(Grid g, const T* __restric
         const int row = row0 + l;
         cd val = {0.0, 0.0};
         if (row < nrows) {
-            if constexpr (FROM_VEL) {
+            if constexpr (SRC == 0) {
                 const int yy = row % g.ny;
                 const int zb = row / g.ny;
                 const int zz = zb % g.nz;
@@ -227,8 +229,15 @@ __global__ __launch_bounds__(kBlock) void k_fft_x_fwd(Grid g, const T* __restric
                     r1 += (double(wz[rowoff + x0 + 1]) - double(wz[rowz + x0 + 1])) * g.ih[2];
                 }
                 val = {r0, r1};
-            } else {
+            } else if constexpr (SRC == 1) {
                 val = reinterpret_cast<const cd*>(r + int64_t(row) * g.nx)[m];
+            } else {
+                const int yy = row % g.ny;
+                const int zb = row / g.ny;
+                const int zz = zb % g.nz;
+                const int b = zb / g.nz;
+                const T* src = vel + (int64_t(b) * DIM + comp) * g.ncell + int64_t(zz * g.ny + yy) * g.nx;
+                val = {double(src[2 * m]), double(src[2 * m + 1])};
             }
         }
         lds[m * nl + l] = val;
@@ -353,19 +362,21 @@ __global__ __launch_bounds__(kBlock) void k_fft_strided(Grid g, cd* __restrict__
 // ----------------------------------------------------------------------------
 template <typename T>
 hipError_t launch_fft_x_fwd(const Grid& g, const T* vel, const double* r, cd* spec, const FftPlan& px, const cd* post,
-                            int lnl, hipStream_t s) {
+                            int lnl, hipStream_t s, int comp) {
     const int nl = 1 << lnl;
     const int nrows = g.batch * g.nz * g.ny;
     const int nblk = (nrows + nl - 1) / nl;
     const size_t shm = size_t(nl) * px.n * sizeof(cd);
-    if (vel) {
-        if (g.dim == 3)
-            hipLaunchKernelGGL((k_fft_x_fwd<T, 3, true>), dim3(nblk), dim3(kBlock), shm, s, g, vel, r, spec, px, post, lnl);
-        else
-            hipLaunchKernelGGL((k_fft_x_fwd<T, 2, true>), dim3(nblk), dim3(kBlock), shm, s, g, vel, r, spec, px, post, lnl);
+#define INS_XF(D, SRC) \
+    hipLaunchKernelGGL((k_fft_x_fwd<T, D, SRC>), dim3(nblk), dim3(kBlock), shm, s, g, vel, r, spec, px, post, lnl, comp)
+    if (vel && comp < 0) {
+        if (g.dim == 3) INS_XF(3, 0); else INS_XF(2, 0);
+    } else if (vel) {
+        if (g.dim == 3) INS_XF(3, 2); else INS_XF(2, 2);
     } else {
-        hipLaunchKernelGGL((k_fft_x_fwd<T, 3, false>), dim3(nblk), dim3(kBlock), shm, s, g, vel, r, spec, px, post, lnl);
+        INS_XF(3, 1);
     }
+#undef INS_XF
     return hipGetLastError();
 }
 
@@ -397,8 +408,8 @@ hipError_t launch_fft_strided(const Grid& g, cd* spec, const FftPlan& pl, int ax
 }
 
 template hipError_t launch_fft_x_fwd<double>(const Grid&, const double*, const double*, cd*, const FftPlan&, const cd*,
-                                             int, hipStream_t);
+                                             int, hipStream_t, int);
 template hipError_t launch_fft_x_fwd<float>(const Grid&, const float*, const double*, cd*, const FftPlan&, const cd*,
-                                            int, hipStream_t);
+                                            int, hipStream_t, int);
 
 }  // namespace ins

@@ -1,0 +1,328 @@
+// Fused RK4 stage for 3D grids as a 2.5D z-march (the forward counterpart of
+// k_stage in k_stencil.hip; same arithmetic, different data movement).
+//
+// A workgroup owns a 32 x 8 tile of an x-y plane and a chunk of consecutive z
+// planes. For every plane it forms the stage velocity u = w - G p (float64
+// projection, Sec. 2.5.2) on the tile plus a one-cell halo exactly once and
+// keeps it in a 4-plane LDS ring; the right-hand side of plane z then reads
+// planes z-1, z, z+1 from LDS only. Each plane of w and p is therefore fetched
+// once per tile (plus the x-y halo, which neighbouring tiles of the same XCD
+// share through L2) instead of three times. With four ring slots the plane
+// being filled is never one being read, so one barrier per plane suffices.
+#include "k_common.hpp"
+
+namespace ins {
+
+constexpr int kZmTX = 32, kZmTY = 8;
+constexpr int kZmHX = kZmTX + 2, kZmHY = kZmTY + 2, kZmHP = kZmHX * kZmHY;  // 340 halo-plane cells
+
+template <typename T>
+struct LdsSrc {
+    const T* zm;  // ring slot of plane z-1
+    const T* z0;  // plane z
+    const T* zp;  // plane z+1
+    int centre;   // index of the cell in the halo plane
+    __device__ __forceinline__ T operator()(int c, const Nb&, int dx, int dy, int dz) const {
+        const T* b = dz < 0 ? zm : (dz > 0 ? zp : z0);
+        return b[c * kZmHP + centre + dy * kZmHX + dx];
+    }
+};
+
+__device__ __forceinline__ int pmod(int v, int n) {
+    const int r = v % n;
+    return r < 0 ? r + n : r;
+}
+
+// Streams touched exactly once per step (u0, y, the new stage register) bypass
+// the caches' normal allocation.
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T* p) {
+    return __builtin_nontemporal_load(p);
+}
+template <typename T>
+__device__ __forceinline__ void st_stream(T v, T* p) {
+    __builtin_nontemporal_store(v, p);
+}
+
+template <typename T, bool PROJ>
+__global__ __launch_bounds__(kBlock) void k_stage_zm(Grid g, const T* __restrict__ w, const double* __restrict__ p,
+                                                       const T* __restrict__ u0, T* __restrict__ y, int yinit, T cy,
+                                                       T* __restrict__ wout, T cw, int zc) {
+    __shared__ T ring[4][3][kZmHP];
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const int ntx = (nx + kZmTX - 1) / kZmTX, nty = (ny + kZmTY - 1) / kZmTY, nzc = (nz + zc - 1) / zc;
+    int L = xcd_logical(blockIdx.x, gridDim.x);
+    const int tx = L % ntx;
+    L /= ntx;
+    const int ty = L % nty;
+    L /= nty;
+    const int zci = L % nzc;
+    const int b = L / nzc;
+    const int x0 = tx * kZmTX, y0 = ty * kZmTY, z0 = zci * zc;
+    const int z1 = min(z0 + zc, nz);
+    const int64_t boff = int64_t(b) * 3 * g.ncell;
+    const T* wb = w + boff;
+    const double* pb = PROJ ? p + int64_t(b) * g.ncell : nullptr;
+    const int nc = int(g.ncell);
+    const int plane = nx * ny;
+
+    // halo-plane positions loaded by this thread
+    int hq[2], hxy[2], hxp[2], hyp[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const int q = threadIdx.x + s * kBlock;
+        hq[s] = q;
+        const int qq = q < kZmHP ? q : 0;
+        const int gx = pmod(x0 - 1 + qq % kZmHX, nx);
+        const int gy = pmod(y0 - 1 + qq / kZmHX, ny);
+        hxy[s] = gy * nx + gx;
+        hxp[s] = gy * nx + (gx + 1 == nx ? 0 : gx + 1);
+        hyp[s] = (gy + 1 == ny ? 0 : gy + 1) * nx + gx;
+    }
+    const int lx = threadIdx.x % kZmTX, ly = threadIdx.x / kZmTX;
+    const int cxg = x0 + lx, cyg = y0 + ly;
+    const bool valid = cxg < nx && cyg < ny;
+    const int centre = (ly + 1) * kZmHX + (lx + 1);
+
+    // projected velocity of the halo plane zz at this thread's positions
+    T pre[2][3];
+    auto fetch = [&](int zz) {
+        const int zoff = zz * plane;
+        const int zpo = (zz + 1 == nz ? 0 : zz + 1) * plane;
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            if (hq[s] < kZmHP) {
+                const int j = zoff + hxy[s];
+                if constexpr (PROJ) {
+                    const double pc = pb[j];
+                    pre[s][0] = T(double(wb[j]) - (pb[zoff + hxp[s]] - pc) * g.ih[0]);
+                    pre[s][1] = T(double(wb[nc + j]) - (pb[zoff + hyp[s]] - pc) * g.ih[1]);
+                    pre[s][2] = T(double(wb[2 * nc + j]) - (pb[zpo + hxy[s]] - pc) * g.ih[2]);
+                } else {
+                    pre[s][0] = wb[j];
+                    pre[s][1] = wb[nc + j];
+                    pre[s][2] = wb[2 * nc + j];
+                }
+            }
+        }
+    };
+    auto park = [&](int k) {
+        T* slot = &ring[k & 3][0][0];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            if (hq[s] < kZmHP) {
+                slot[hq[s]] = pre[s][0];
+                slot[kZmHP + hq[s]] = pre[s][1];
+                slot[2 * kZmHP + hq[s]] = pre[s][2];
+            }
+        }
+    };
+
+    // Pipeline: iteration k computes plane z0+k-2 from ring slots k-2, k-1, k
+    // while the loads of plane k+1 are in flight; they land in slot k+1, which
+    // no thread reads during iteration k.
+    const int nk = (z1 - z0) + 2;
+    fetch(pmod(z0 - 1, nz));
+    park(0);
+    fetch(pmod(z0, nz));
+    park(1);
+    if (nk > 2) fetch(pmod(z0 + 1, nz));
+    park(2);
+    __syncthreads();
+    for (int k = 2; k < nk; ++k) {
+        const int z = z0 + k - 2;
+        const bool more = k + 1 < nk;
+        if (more) fetch(pmod(z0 - 1 + k + 1, nz));
+        if (valid) {
+            const int c0 = z * plane + cyg * nx + cxg;
+            T base[3], yv[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int64_t kk = boff + int64_t(a) * nc + c0;
+                base[a] = (wout || yinit) ? ld_stream(u0 + kk) : T(0);
+                yv[a] = (y && !yinit) ? ld_stream(y + kk) : base[a];
+            }
+            LdsSrc<T> U{&ring[(k - 2) & 3][0][0], &ring[(k - 1) & 3][0][0], &ring[k & 3][0][0], centre};
+            T F[3];
+            rhs_cell<T, 3>(g, U, Nb{}, F);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int64_t kk = boff + int64_t(a) * nc + c0;
+                if (y) st_stream(yv[a] + cy * F[a], y + kk);
+                if (wout) st_stream(base[a] + cw * F[a], wout + kk);
+            }
+        }
+        if (more) park(k + 1);
+        __syncthreads();
+    }
+}
+
+// z planes per workgroup: long enough that the two extra halo planes are a
+// small overhead, short enough to give the chip several workgroups per CU.
+int zm_chunk(const Grid& g) {
+    const int ntiles = ((g.nx + kZmTX - 1) / kZmTX) * ((g.ny + kZmTY - 1) / kZmTY) * g.batch;
+    int zc = 32;
+    while (zc > 4 && int64_t(ntiles) * ((g.nz + zc - 1) / zc) < 2048) zc /= 2;
+    return zc;
+}
+
+template <typename T>
+hipError_t launch_stage_zm(const Grid& g, const T* w, const double* p, bool proj, const T* u0, T* y, bool yinit,
+                           double cy, T* wout, double cw, hipStream_t s) {
+    const int zc = zm_chunk(g);
+    const int nblk = ((g.nx + kZmTX - 1) / kZmTX) * ((g.ny + kZmTY - 1) / kZmTY) * ((g.nz + zc - 1) / zc) * g.batch;
+    const int yi = yinit ? 1 : 0;
+    if (proj)
+        hipLaunchKernelGGL((k_stage_zm<T, true>), dim3(nblk), dim3(kBlock), 0, s, g, w, p, u0, y, yi, T(cy), wout, T(cw), zc);
+    else
+        hipLaunchKernelGGL((k_stage_zm<T, false>), dim3(nblk), dim3(kBlock), 0, s, g, w, p, u0, y, yi, T(cy), wout, T(cw), zc);
+    return hipGetLastError();
+}
+
+template hipError_t launch_stage_zm<double>(const Grid&, const double*, const double*, bool, const double*, double*, bool,
+                                            double, double*, double, hipStream_t);
+template hipError_t launch_stage_zm<float>(const Grid&, const float*, const double*, bool, const float*, float*, bool,
+                                           double, float*, double, hipStream_t);
+
+}  // namespace ins
+
+namespace ins {
+
+// Reverse RK4 stage for 3D grids as a z-march (counterpart of k_stage_vjp in
+// k_vjp.hip, same arithmetic). Two LDS rings hold, per plane, the stage
+// velocity u_i = w - G p and the right-hand-side cotangent
+// Fbar_i = cb ybar + cw (un - G q) on the tile plus halo; three slots each,
+// two barriers per plane.
+template <typename T, bool PROJ_U, bool HAS_W>
+__global__ __launch_bounds__(kBlock) void k_stage_vjp_zm(Grid g, const T* __restrict__ w, const double* __restrict__ p,
+                                                           const T* __restrict__ ybar, const T* __restrict__ un,
+                                                           const double* __restrict__ q, T cb, T cw,
+                                                           T* __restrict__ u0bar, int mode, T* __restrict__ ubar_out,
+                                                           int zc) {
+    __shared__ T ru[3][3][kZmHP];
+    __shared__ T rf[3][3][kZmHP];
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const int ntx = (nx + kZmTX - 1) / kZmTX, nty = (ny + kZmTY - 1) / kZmTY, nzc = (nz + zc - 1) / zc;
+    int L = xcd_logical(blockIdx.x, gridDim.x);
+    const int tx = L % ntx;
+    L /= ntx;
+    const int ty = L % nty;
+    L /= nty;
+    const int zci = L % nzc;
+    const int b = L / nzc;
+    const int x0 = tx * kZmTX, y0 = ty * kZmTY, z0 = zci * zc;
+    const int z1 = min(z0 + zc, nz);
+    const int64_t boff = int64_t(b) * 3 * g.ncell;
+    const int64_t soff = int64_t(b) * g.ncell;
+    const T* wb = w + boff;
+    const double* pb = PROJ_U ? p + soff : nullptr;
+    const T* yb = ybar + boff;
+    const T* ub = HAS_W ? un + boff : nullptr;
+    const double* qb = HAS_W ? q + soff : nullptr;
+    const int nc = int(g.ncell);
+    const int plane = nx * ny;
+
+    int hq[2], hxy[2], hxp[2], hyp[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const int qi = threadIdx.x + s * kBlock;
+        hq[s] = qi;
+        const int qq = qi < kZmHP ? qi : 0;
+        const int gx = pmod(x0 - 1 + qq % kZmHX, nx);
+        const int gy = pmod(y0 - 1 + qq / kZmHX, ny);
+        hxy[s] = gy * nx + gx;
+        hxp[s] = gy * nx + (gx + 1 == nx ? 0 : gx + 1);
+        hyp[s] = (gy + 1 == ny ? 0 : gy + 1) * nx + gx;
+    }
+    const int lx = threadIdx.x % kZmTX, ly = threadIdx.x / kZmTX;
+    const int cxg = x0 + lx, cyg = y0 + ly;
+    const bool valid = cxg < nx && cyg < ny;
+    const int centre = (ly + 1) * kZmHX + (lx + 1);
+
+    const int nk = (z1 - z0) + 2;
+    for (int k = 0; k < nk; ++k) {
+        const int zz = pmod(z0 - 1 + k, nz);
+        const int zoff = zz * plane;
+        const int zpo = (zz + 1 == nz ? 0 : zz + 1) * plane;
+        T* su = &ru[k % 3][0][0];
+        T* sf = &rf[k % 3][0][0];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            if (hq[s] < kZmHP) {
+                const int j = zoff + hxy[s];
+                const int jp[3] = {zoff + hxp[s], zoff + hyp[s], zpo + hxy[s]};
+                double pc = 0.0, qc = 0.0;
+                if constexpr (PROJ_U) pc = pb[j];
+                if constexpr (HAS_W) qc = qb[j];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    T uv;
+                    if constexpr (PROJ_U)
+                        uv = T(double(wb[c * nc + j]) - (pb[jp[c]] - pc) * g.ih[c]);
+                    else
+                        uv = wb[c * nc + j];
+                    T fv = cb * yb[c * nc + j];
+                    if constexpr (HAS_W) fv += cw * T(double(ub[c * nc + j]) - (qb[jp[c]] - qc) * g.ih[c]);
+                    su[c * kZmHP + hq[s]] = uv;
+                    sf[c * kZmHP + hq[s]] = fv;
+                }
+            }
+        }
+        __syncthreads();
+        if (k >= 2 && valid) {
+            const int z = z0 + k - 2;
+            LdsSrc<T> U{&ru[(k - 2) % 3][0][0], &ru[(k - 1) % 3][0][0], &ru[k % 3][0][0], centre};
+            LdsSrc<T> F{&rf[(k - 2) % 3][0][0], &rf[(k - 1) % 3][0][0], &rf[k % 3][0][0], centre};
+            T out[3];
+            rhs_vjp_cell<T, 3>(g, U, F, Nb{}, out);
+            const int cyx = cyg * nx + cxg;
+            const int c0 = z * plane + cyx;
+            const int zpc = (z + 1 == nz ? 0 : z + 1) * plane + cyx;
+            const int xpc = z * plane + cyg * nx + (cxg + 1 == nx ? 0 : cxg + 1);
+            const int ypc = z * plane + (cyg + 1 == ny ? 0 : cyg + 1) * nx + cxg;
+            const int jpc[3] = {xpc, ypc, zpc};
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int64_t kk = boff + int64_t(a) * nc + c0;
+                T acc = mode == 0 ? yb[int64_t(a) * nc + c0] : u0bar[kk];
+                if constexpr (HAS_W)
+                    acc += T(double(ub[int64_t(a) * nc + c0]) - (qb[jpc[a]] - qb[c0]) * g.ih[a]);
+                if (mode == 2) acc += out[a];
+                u0bar[kk] = acc;
+                if (ubar_out) ubar_out[kk] = out[a];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T>
+hipError_t launch_stage_vjp_zm(const Grid& g, const T* w, const double* p, bool proj_u, const T* ybar, const T* un,
+                               const double* q, bool has_w, double cb, double cw, T* u0bar, int mode, T* ubar_out,
+                               hipStream_t s) {
+    const int zc = zm_chunk(g);
+    const int nblk = ((g.nx + kZmTX - 1) / kZmTX) * ((g.ny + kZmTY - 1) / kZmTY) * ((g.nz + zc - 1) / zc) * g.batch;
+    const T tb = T(cb), tw = T(cw);
+#define INS_VJP_ZM(PU, HW)                                                                                           \
+    hipLaunchKernelGGL((k_stage_vjp_zm<T, PU, HW>), dim3(nblk), dim3(kBlock), 0, s, g, w, p, ybar, un, q, tb, tw, u0bar, \
+                       mode, ubar_out, zc)
+    if (proj_u && has_w)
+        INS_VJP_ZM(true, true);
+    else if (proj_u)
+        INS_VJP_ZM(true, false);
+    else if (has_w)
+        INS_VJP_ZM(false, true);
+    else
+        INS_VJP_ZM(false, false);
+#undef INS_VJP_ZM
+    return hipGetLastError();
+}
+
+template hipError_t launch_stage_vjp_zm<double>(const Grid&, const double*, const double*, bool, const double*,
+                                                const double*, const double*, bool, double, double, double*, int,
+                                                double*, hipStream_t);
+template hipError_t launch_stage_vjp_zm<float>(const Grid&, const float*, const double*, bool, const float*,
+                                               const float*, const double*, bool, double, double, float*, int, float*,
+                                               hipStream_t);
+
+}  // namespace ins

@@ -10,33 +10,6 @@
 
 namespace ins {
 
-// F^a at the current cell: diffusion (eq. diff-kernel) + convection
-// (eq. conv-kernel with weights 1/2). The flux through the b-face of the
-// a-velocity volume is F^{ab}[K] = (u^a[K] + u^a[K+e_b]) (u^b[K] + u^b[K+e_a]) / 4,
-// formed at K = I and K = I - e_b and consumed at once (lazy components, Sec. 3.3).
-template <typename T, int DIM, class Src>
-__device__ __forceinline__ void rhs_cell(const Grid& g, const Src& U, const Nb& nb, T F[DIM]) {
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-        const int ax = a == 0, ay = a == 1, az = a == 2;
-        const T uc = U(a, nb, 0, 0, 0);
-        T diff = T(0), conv = T(0);
-#pragma unroll
-        for (int b = 0; b < DIM; ++b) {
-            const int bx = b == 0, by = b == 1, bz = b == 2;
-            const T up = U(a, nb, bx, by, bz);
-            const T um = U(a, nb, -bx, -by, -bz);
-            diff += ((up - uc) - (uc - um)) * T(g.ih2[b]);
-            const T vr = U(b, nb, 0, 0, 0) + U(b, nb, ax, ay, az);
-            const T vl = U(b, nb, -bx, -by, -bz) + U(b, nb, ax - bx, ay - by, az - bz);
-            const T fr = (uc + up) * vr * T(0.25);
-            const T fl = (um + uc) * vl * T(0.25);
-            conv -= (fr - fl) * T(g.ih[b]);
-        }
-        F[a] = conv + T(g.nu) * diff;
-    }
-}
-
 template <typename T, int DIM>
 __global__ __launch_bounds__(kBlock) void k_rhs(Grid g, const T* __restrict__ u, T* __restrict__ f) {
     const TileIdx t = tile_of(g);
@@ -51,7 +24,8 @@ __global__ __launch_bounds__(kBlock) void k_rhs(Grid g, const T* __restrict__ u,
     for (int a = 0; a < DIM; ++a) f[boff + a * g.ncell + c0] = F[a];
 }
 
-// RK4 stage: u_i = (PROJ ? w - G p : w), F = F(u_i),
+// RK4 stage on 2D grids (3D grids use the z-march of k_stage3d.hip):
+// u_i = (PROJ ? w - G p : w), F = F(u_i),
 // (if y) y = (yinit ? u0 : y) + cy F, and (if wout) wout = u0 + cw F.
 template <typename T, int DIM, bool PROJ>
 __global__ __launch_bounds__(kBlock) void k_stage(Grid g, const T* __restrict__ w, const double* __restrict__ p,
@@ -211,19 +185,13 @@ hipError_t launch_grad_vjp(const Grid& g, const T* gbar, double* pbar, hipStream
 template <typename T>
 hipError_t launch_stage(const Grid& g, const T* w, const double* p, bool proj, const T* u0, T* y, bool yinit, double cy,
                         T* wout, double cw, hipStream_t s) {
+    if (g.dim == 3) return launch_stage_zm<T>(g, w, p, proj, u0, y, yinit, cy, wout, cw, s);
     const int nblk = stencil_blocks(g);
     const int yi = yinit ? 1 : 0;
-    if (g.dim == 3) {
-        if (proj)
-            hipLaunchKernelGGL((k_stage<T, 3, true>), dim3(nblk), dim3(kBlock), 0, s, g, w, p, u0, y, yi, T(cy), wout, T(cw));
-        else
-            hipLaunchKernelGGL((k_stage<T, 3, false>), dim3(nblk), dim3(kBlock), 0, s, g, w, p, u0, y, yi, T(cy), wout, T(cw));
-    } else {
-        if (proj)
-            hipLaunchKernelGGL((k_stage<T, 2, true>), dim3(nblk), dim3(kBlock), 0, s, g, w, p, u0, y, yi, T(cy), wout, T(cw));
-        else
-            hipLaunchKernelGGL((k_stage<T, 2, false>), dim3(nblk), dim3(kBlock), 0, s, g, w, p, u0, y, yi, T(cy), wout, T(cw));
-    }
+    if (proj)
+        hipLaunchKernelGGL((k_stage<T, 2, true>), dim3(nblk), dim3(kBlock), 0, s, g, w, p, u0, y, yi, T(cy), wout, T(cw));
+    else
+        hipLaunchKernelGGL((k_stage<T, 2, false>), dim3(nblk), dim3(kBlock), 0, s, g, w, p, u0, y, yi, T(cy), wout, T(cw));
     return hipGetLastError();
 }
 

@@ -18,31 +18,6 @@
 
 namespace ins {
 
-template <typename T, int DIM, class USrc, class FSrc>
-__device__ __forceinline__ void rhs_vjp_cell(const Grid& g, const USrc& U, const FSrc& Fb, const Nb& nb, T out[DIM]) {
-#pragma unroll
-    for (int gm = 0; gm < DIM; ++gm) {
-        const int gx = gm == 0, gy = gm == 1, gz = gm == 2;
-        const T ihg = T(g.ih[gm]);
-        const T fc = Fb(gm, nb, 0, 0, 0);
-        T diff = T(0), acc = T(0);
-#pragma unroll
-        for (int b = 0; b < DIM; ++b) {
-            const int bx = b == 0, by = b == 1, bz = b == 2;
-            const T ihb = T(g.ih[b]);
-            const T fp = Fb(gm, nb, bx, by, bz);
-            const T fm = Fb(gm, nb, -bx, -by, -bz);
-            diff += ((fp - fc) - (fc - fm)) * T(g.ih2[b]);
-            const T m0 = U(b, nb, 0, 0, 0) + U(b, nb, gx, gy, gz);
-            const T g0 = (fp - fc) * ihb + (Fb(b, nb, gx, gy, gz) - Fb(b, nb, 0, 0, 0)) * ihg;
-            const T m1 = U(b, nb, -bx, -by, -bz) + U(b, nb, gx - bx, gy - by, gz - bz);
-            const T g1 = (fc - fm) * ihb + (Fb(b, nb, gx - bx, gy - by, gz - bz) - Fb(b, nb, -bx, -by, -bz)) * ihg;
-            acc += m0 * g0 + m1 * g1;
-        }
-        out[gm] = T(0.25) * acc + T(g.nu) * diff;
-    }
-}
-
 template <typename T, int DIM>
 __global__ __launch_bounds__(kBlock) void k_rhs_vjp(Grid g, const T* __restrict__ u, const T* __restrict__ fbar,
                                                       T* __restrict__ ubar) {
@@ -82,7 +57,7 @@ struct FbarSrc {
     }
 };
 
-// Reverse RK4 stage i (see launch_stage_vjp for the bookkeeping).
+// Reverse RK4 stage i on 2D grids (3D: k_stage_vjp_zm); see launch_stage_vjp.
 template <typename T, int DIM, bool PROJ_U, bool HAS_W>
 __global__ __launch_bounds__(kBlock) void k_stage_vjp(Grid g, const T* __restrict__ w, const double* __restrict__ p,
                                                         const T* __restrict__ ybar, const T* __restrict__ un,
@@ -155,11 +130,8 @@ template <typename T>
 hipError_t launch_stage_vjp(const Grid& g, const T* w, const double* p, bool proj_u, const T* ybar, const T* un,
                             const double* q, bool has_w, double cb, double cw, T* u0bar, int mode, T* ubar_out,
                             hipStream_t s) {
-    const int nblk = stencil_blocks(g);
-    if (g.dim == 3)
-        stage_vjp_dim<T, 3>(g, nblk, w, p, proj_u, ybar, un, q, has_w, T(cb), T(cw), u0bar, mode, ubar_out, s);
-    else
-        stage_vjp_dim<T, 2>(g, nblk, w, p, proj_u, ybar, un, q, has_w, T(cb), T(cw), u0bar, mode, ubar_out, s);
+    if (g.dim == 3) return launch_stage_vjp_zm<T>(g, w, p, proj_u, ybar, un, q, has_w, cb, cw, u0bar, mode, ubar_out, s);
+    stage_vjp_dim<T, 2>(g, stencil_blocks(g), w, p, proj_u, ybar, un, q, has_w, T(cb), T(cw), u0bar, mode, ubar_out, s);
     return hipGetLastError();
 }
 

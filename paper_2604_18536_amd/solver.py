@@ -193,6 +193,30 @@ class Solver:
                self._check(out, "vel", "out"), float(dt))
         return out
 
+    # ------------------------------------------------------- LES data helpers
+    def face_filter(self, u, factor=4, out=None):
+        """Coarse staggered field: mean of the fine faces on each coarse face."""
+        if out is None:
+            cn = tuple(v // factor for v in reversed(self.n))
+            shape = (self.dim,) + cn if self._unbatched(u) else (self.batch, self.dim) + cn
+            out = torch.empty(shape, dtype=self.dtype, device=self.device)
+        if out.dtype != self.dtype or not out.is_contiguous() or out.numel() * factor ** self.dim != self.batch * self.dim * math.prod(self.n):
+            raise ValueError("out must be a contiguous coarse field of the solver dtype")
+        self._sync_stream()
+        L.call("ins_face_filter", self._ctx, self._check(u, "vel", "u"), int(factor), C.c_void_p(out.data_ptr()))
+        return out
+
+    def spectrum_bins(self):
+        return int(math.floor(math.sqrt(self.dim) * max(self.n) / 2 + 0.5)) + 1
+
+    def energy_spectrum(self, u, nbins=None):
+        """E(k), k = 0..nbins-1 (float64, shape (batch, nbins), or (nbins,) for an unbatched input)."""
+        nbins = self.spectrum_bins() if nbins is None else int(nbins)
+        e = torch.empty((self.batch, nbins), dtype=torch.float64, device=self.device)
+        self._sync_stream()
+        L.call("ins_energy_spectrum", self._ctx, self._check(u, "vel", "u"), C.c_void_p(e.data_ptr()), nbins)
+        return e[0] if self._unbatched(u) else e
+
     # ------------------------------------------------------------ utilities
     def stats(self, u):
         """(kinetic energy, max|u|, max|Du|, all finite) of a velocity field."""

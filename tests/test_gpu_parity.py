@@ -249,3 +249,31 @@ def test_abi_errors_on_gpu():
         s.rhs(dev(S.random_field((8, 6, 12), 1)))
     with pytest.raises(TypeError):
         s.rhs(dev(S.random_field((8, 6, 10), 1), torch.float32))
+
+
+# ------------------------------------------------- full size, bench launch shape
+def test_full_size_256_step_fp64():
+    """The benchmark workload itself: one float64 step of the 256^3 turbulence field vs the oracle."""
+    n = (256, 256, 256)
+    nu, dt = 1.0 / 1600.0, 1e-3
+    u0 = S.turbulence_ic(n, seed=0, k0=4.0)
+    s = _solver(n, nu)
+    u1 = host(s.step(dev(u0), dt))
+    s.close()
+    assert max_rel(u1, O.step_rk4(u0, S.spacing(n), nu, dt)) < TOL64
+
+
+def test_full_size_256_step_vjp_adjoint_identity():
+    """<ubar, J v> = <J^T ubar, v> at 256^3, J v by central differences of GPU steps (float64)."""
+    n = (256, 256, 256)
+    nu, dt, eps = 1.0 / 1600.0, 1e-3, 1e-4
+    s = _solver(n, nu)
+    u0 = dev(S.turbulence_ic(n, seed=0, k0=4.0))
+    v = dev(S.turbulence_ic(n, seed=1, k0=8.0))
+    ubar = dev(S.random_field(n, 2))
+    g = s.step_vjp(u0, ubar, dt)
+    jv = (s.step(u0 + eps * v, dt) - s.step(u0 - eps * v, dt)) / (2 * eps)
+    lhs = float((ubar * jv).sum())
+    rhs = float((g * v).sum())
+    s.close()
+    assert abs(lhs - rhs) < 1e-9 * float((ubar.abs() * jv.abs()).sum())
