@@ -181,6 +181,43 @@ ins_status ins_project_vjp(ins_ctx ctx, const void* ubar_out, void* ubar);
 ins_status ins_step_rk4_vjp(ins_ctx ctx, const void* u0, const void* u1bar, void* u0bar, double dt);
 
 /* ---------------------------------------------------------------------------
+ * Learned closure (Sec. 4: a neural closure inside the solver, trained
+ * a-posteriori through it). The paper does not fix an architecture; this one
+ * is a 3D CNN 3 -> 32 -> 32 -> 3 channels, 3x3x3 kernels with circular
+ * padding, biases, exact-erf GELU between layers, no output activation. The
+ * three staggered velocity components are its input channels on the cell grid
+ * and output channel a is added to the a-velocity right-hand side, so the
+ * step integrates du/dt = P(F(u) + m_theta(u)). Convolutions run on bfloat16
+ * matrix cores with float32 accumulation: u, the weights and every GELU output
+ * are rounded to bfloat16 (nearest even); in the backward pass the cotangent
+ * entering each convolution is rounded to bfloat16. 3D only; n_x must be a
+ * multiple of 32.
+ *
+ * Parameters: 32,899 float32 values on the device, per layer in order
+ * W[out][in][kz][ky][kx] then b[out]; tap (kz, ky, kx) multiplies
+ * u[I + (kx-1, ky-1, kz-1)] (cross-correlation).
+ * ------------------------------------------------------------------------- */
+
+/* Set (params != NULL: copied, packed to bfloat16 for the kernels) or clear
+ * (params == NULL) the closure. While set, ins_rhs, ins_step_rk4, ins_rhs_vjp
+ * and ins_step_rk4_vjp include it, and the *_vjp calls accumulate the
+ * parameter gradient. Allocates the closure workspace (about 330 bytes per
+ * cell of the batch) on first use. */
+ins_status ins_closure_set(ins_ctx ctx, const float* params);
+
+/* Copy the accumulated parameter gradient (float32, 32,899 values, device) to
+ * params_bar and reset the accumulator to zero. */
+ins_status ins_closure_grad(ins_ctx ctx, float* params_bar);
+
+/* m = m_theta(u) alone (velocity layout, context dtype). */
+ins_status ins_cnn_forward(ins_ctx ctx, const void* u, void* m);
+
+/* ubar = (d m_theta / d u)^T mbar (overwritten) and params_bar =
+ * (d m_theta / d theta)^T mbar (overwritten; the accumulator of
+ * ins_closure_grad is left at zero). */
+ins_status ins_cnn_backward(ins_ctx ctx, const void* u, const void* mbar, void* ubar, float* params_bar);
+
+/* ---------------------------------------------------------------------------
  * LES data helpers (filtered DNS and its spectrum). The paper names the
  * pipeline DNS -> filter -> LES (Sec. 4) but not the filter or the spectrum
  * binning; the readings are stated with each call.

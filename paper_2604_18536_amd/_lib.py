@@ -59,6 +59,10 @@ _SIGS = {
     "ins_poisson_solve_vjp": ([_P, _P, _P]),
     "ins_project_vjp": ([_P, _P, _P]),
     "ins_step_rk4_vjp": ([_P, _P, _P, _P, _D]),
+    "ins_closure_set": ([_P, _P]),
+    "ins_closure_grad": ([_P, _P]),
+    "ins_cnn_forward": ([_P, _P, _P]),
+    "ins_cnn_backward": ([_P, _P, _P, _P, _P]),
     "ins_face_filter": ([_P, _P, C.c_int, _P]),
     "ins_energy_spectrum": ([_P, _P, _P, C.c_int]),
     "ins_stats": ([_P, _P, C.POINTER(_D)]),

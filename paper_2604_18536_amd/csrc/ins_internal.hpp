@@ -33,6 +33,7 @@ struct FftPlan {
     int rad[kMaxStages];     // radix of stage s (applied in order)
     int tw_off[kMaxStages];  // offset of stage s twiddles: p*(R-1) entries
     const cd* tw;            // device twiddle table (float64, forward sign)
+    int vm;                  // complex values a thread holds per stage (8 or 16)
 };
 
 // Which FFT pass shape a launch uses.
@@ -53,8 +54,9 @@ enum class Prec { F64 = 0, F32 = 1 };
 // Launchers (defined in the kernel translation units). All return hipError_t
 // from hipGetLastError after the launch.
 // ----------------------------------------------------------------------------
+// f = F(u) (+ mc when mc != nullptr: the closure term).
 template <typename T>
-hipError_t launch_rhs(const Grid& g, const T* u, T* f, hipStream_t s);
+hipError_t launch_rhs(const Grid& g, const T* u, T* f, hipStream_t s, const T* mc = nullptr);
 template <typename T>
 hipError_t launch_divergence(const Grid& g, const T* u, double* r, hipStream_t s);
 template <typename T>
@@ -67,16 +69,16 @@ hipError_t launch_grad_vjp(const Grid& g, const T* gbar, double* pbar, hipStream
 template <typename T>
 hipError_t launch_apply_projection(const Grid& g, const T* w, const double* p, T* u_out, hipStream_t s);
 
-// RK4 stage: u_i = proj ? w - G p : w; F = rhs(u_i);
+// RK4 stage: u_i = proj ? w - G p : w; F = rhs(u_i) (+ mc, the closure term at u_i);
 //   if y: y = (yinit ? u0 : y) + cy F;  if wout: wout = u0 + cw F.
 template <typename T>
 hipError_t launch_stage(const Grid& g, const T* w, const double* p, bool proj, const T* u0, T* y, bool yinit, double cy,
-                        T* wout, double cw, hipStream_t s);
+                        T* wout, double cw, hipStream_t s, const T* mc = nullptr);
 
 // 3D variant of launch_stage: 2.5D z-march with an LDS ring of projected planes.
 template <typename T>
 hipError_t launch_stage_zm(const Grid& g, const T* w, const double* p, bool proj, const T* u0, T* y, bool yinit,
-                           double cy, T* wout, double cw, hipStream_t s);
+                           double cy, T* wout, double cw, hipStream_t s, const T* mc);
 
 // Spectral Poisson solve pieces.
 // Forward x pass: real rows -> half spectrum. vel != nullptr and comp < 0:
@@ -98,16 +100,16 @@ hipError_t launch_rhs_vjp(const Grid& g, const T* u, const T* fbar, T* ubar, hip
 // Reverse RK4 stage: u_i = (proj_u ? w - G p : w),
 // Fbar_i = cb ybar + (has_w ? cw (un - G q) : 0), out = J_F(u_i)^T Fbar_i,
 // u0bar = (mode == 0 ? ybar : u0bar) + (has_w ? un - G q : 0) + (mode == 2 ? out : 0),
-// ubar_out (if not null) = out.
+// ubar_out (if not null) = out, fbar_out (if not null) = Fbar_i.
 template <typename T>
 hipError_t launch_stage_vjp(const Grid& g, const T* w, const double* p, bool proj_u, const T* ybar, const T* un,
                             const double* q, bool has_w, double cb, double cw, T* u0bar, int mode, T* ubar_out,
-                            hipStream_t s);
+                            hipStream_t s, T* fbar_out = nullptr);
 
 template <typename T>
 hipError_t launch_stage_vjp_zm(const Grid& g, const T* w, const double* p, bool proj_u, const T* ybar, const T* un,
                                const double* q, bool has_w, double cb, double cw, T* u0bar, int mode, T* ubar_out,
-                               hipStream_t s);
+                               hipStream_t s, T* fbar_out);
 
 // LES data helpers.
 // Coarse staggered field: mean of the f^(d-1) fine a-faces on each coarse a-face.
@@ -117,6 +119,22 @@ hipError_t launch_face_filter(const Grid& fine, int f, const T* u, T* uc, hipStr
 hipError_t launch_spectrum_bins(const Grid& g, const cd* spec, double* bins, int nbins, hipStream_t s);
 // p[0..n) = 0 with a kernel (kept out of hipMemsetAsync so callers may capture it).
 hipError_t launch_fill_zero(double* p, size_t n, hipStream_t s);
+hipError_t launch_fill_zero_f(float* p, size_t n, hipStream_t s);
+
+// Learned closure (bfloat16 MFMA convolutions). Activations are channels-last
+// bfloat16 stored as 16-bit words.
+template <typename T>
+hipError_t launch_closure_pack_input(const Grid& g, const T* u, unsigned short* x0, hipStream_t s);
+hipError_t launch_closure_pack_weights(const float* w, int cin, int cout, int cinp, int ntf, unsigned short* wf,
+                                       int coutp, int ntd, unsigned short* wd, hipStream_t s);
+// which: 0, 1 hidden layers, 2 output layer; 10, 11 dgrad into hidden layers; 12 dgrad to the input.
+template <typename T>
+hipError_t launch_closure_conv(const Grid& g, int which, const unsigned short* in, const unsigned short* wpk,
+                               const float* bias, const float* zin, float* zout, unsigned short* aout, T* fout,
+                               hipStream_t s);
+hipError_t launch_closure_wgrad(const Grid& g, int which, const unsigned short* gin, const unsigned short* xin,
+                                float* partial, float* wbar, float* bbar, hipStream_t s);
+size_t closure_wgrad_partial_floats(int64_t ncells);
 
 // Utilities.
 template <typename T>

@@ -32,7 +32,6 @@ void hip_check(hipError_t e, const char* what) {
 }
 
 constexpr int kMaxLen = 4096;
-constexpr int kVmaxHost = 16;   // must match kVmax of the FFT kernels
 constexpr int kBlockHost = 256; // must match kBlock
 constexpr size_t kMaxLds = 65536;
 
@@ -84,15 +83,16 @@ void build_twiddles(int n, const std::vector<int>& rad, std::vector<cd>& tw, ins
 }
 
 // Largest power-of-two line batch (<= maxl) whose every stage fits the
-// per-thread register budget and whose lines fit the LDS budget.
-int choose_lines(const ins::FftPlan& pl, int maxl) {
+// per-thread register budget vm and whose padded lines fit the LDS budget.
+int lines_for(const ins::FftPlan& pl, int maxl, int vm) {
     for (int nl = maxl; nl >= 1; nl >>= 1) {
-        if (static_cast<size_t>(nl) * pl.n * sizeof(cd) > kMaxLds) continue;
+        if (static_cast<size_t>(nl + 1) * pl.n * sizeof(cd) > kMaxLds) continue;
         bool ok = true;
         for (int s = 0; s < pl.nst; ++s) {
             const int R = pl.rad[s];
+            const int bmax = vm / R > 0 ? vm / R : 1;
             const long long nb = static_cast<long long>(nl) * (pl.n / R);
-            if (nb > static_cast<long long>(kVmaxHost / R) * kBlockHost) ok = false;
+            if (nb > static_cast<long long>(bmax) * kBlockHost) ok = false;
         }
         if (ok) {
             int l = 0;
@@ -101,6 +101,18 @@ int choose_lines(const ins::FftPlan& pl, int maxl) {
         }
     }
     return -1;
+}
+
+// Pick the register budget (8 complex values per thread keeps occupancy high)
+// unless it would force batches of fewer than `want` lines.
+int choose_lines(ins::FftPlan& pl, int maxl, int want) {
+    const int l8 = lines_for(pl, maxl, 8);
+    if (l8 >= 0 && (1 << l8) >= want) {
+        pl.vm = 8;
+        return l8;
+    }
+    pl.vm = 16;
+    return lines_for(pl, maxl, 16);
 }
 
 struct Pending {
@@ -138,6 +150,19 @@ struct ins_ctx_s {
     double* p2 = nullptr;
     double* p3 = nullptr;
     double* p4 = nullptr;
+
+    // learned closure (allocated by ins_closure_set)
+    bool clos_on = false;
+    bool clos_alloc = false;
+    float* theta = nullptr;      // float32 parameters (device copy)
+    float* theta_bar = nullptr;  // accumulated parameter gradient
+    unsigned short* wf[3] = {nullptr, nullptr, nullptr};  // packed forward weights per layer
+    unsigned short* wd[3] = {nullptr, nullptr, nullptr};  // packed dgrad weights per layer
+    unsigned short *x0 = nullptr, *a1 = nullptr, *a2 = nullptr, *gm = nullptr, *gz1 = nullptr, *gz2 = nullptr;
+    float *z1 = nullptr, *z2 = nullptr, *partial = nullptr;
+    void* mclos = nullptr;  // closure term at the current stage (velocity layout)
+    void* ui = nullptr;     // materialised stage velocity
+    void* fbar = nullptr;   // right-hand-side cotangent of the current reverse stage
 
     size_t bytes = 0;
     std::vector<void*> allocs;
@@ -286,20 +311,114 @@ void poisson(ins_ctx c, const void* vel, const double* r, double* p) {
     c->launch("fft_x_inv", [&] { return ins::launch_fft_x_inv(g, c->spec, p, c->px, c->d_post, c->lnl_x, c->stream); });
 }
 
-template <typename T>
-void stage(ins_ctx c, const T* w, const double* p, bool proj, const T* u0, T* y, bool yinit, double cy, T* wout,
-           double cw) {
-    // one profile name per data-movement variant (their byte counts differ)
-    const char* name = !proj ? (y ? "stage_first" : "stage_first_rec")
-                             : (y ? (wout ? "stage" : "stage_last") : "stage_rec");
-    c->launch(name, [&] {
-        return ins::launch_stage<T>(c->g, w, p, proj, u0, y, yinit, cy, wout, cw, c->stream);
-    });
-}
 
 template <typename T>
 void apply_projection(ins_ctx c, const T* w, const double* p, T* out) {
     c->launch("apply_projection", [&] { return ins::launch_apply_projection<T>(c->g, w, p, out, c->stream); });
+}
+
+// ----------------------------------------------------------------------------
+// Learned closure m_theta (Sec. 4): parameter layout per layer W[out][in][kz][ky][kx]
+// then b[out], layers (3->32), (32->32), (32->3).
+// ----------------------------------------------------------------------------
+constexpr int kClosParams = 32899;
+constexpr int kW1 = 0, kB1 = 2592, kW2 = 2624, kB2 = 30272, kW3 = 30304, kB3 = 32896;
+
+void closure_alloc(ins_ctx c) {
+    if (c->clos_alloc) return;
+    const size_t n = size_t(c->g.ncell) * c->g.batch;
+    c->theta = static_cast<float*>(c->alloc(kClosParams * sizeof(float)));
+    c->theta_bar = static_cast<float*>(c->alloc(kClosParams * sizeof(float)));
+    // packed sizes: forward NKT(cinp) * ntf * 512, dgrad NKT(coutp) * ntd * 512 (bf16 words)
+    const size_t wf_sz[3] = {7 * 2 * 512, 27 * 2 * 512, 27 * 1 * 512};
+    const size_t wd_sz[3] = {27 * 1 * 512, 27 * 2 * 512, 7 * 2 * 512};
+    for (int l = 0; l < 3; ++l) {
+        c->wf[l] = static_cast<unsigned short*>(c->alloc(wf_sz[l] * 2));
+        c->wd[l] = static_cast<unsigned short*>(c->alloc(wd_sz[l] * 2));
+    }
+    c->x0 = static_cast<unsigned short*>(c->alloc(n * 8 * 2));
+    c->gm = static_cast<unsigned short*>(c->alloc(n * 8 * 2));
+    c->a1 = static_cast<unsigned short*>(c->alloc(n * 32 * 2));
+    c->a2 = static_cast<unsigned short*>(c->alloc(n * 32 * 2));
+    c->gz1 = static_cast<unsigned short*>(c->alloc(n * 32 * 2));
+    c->gz2 = static_cast<unsigned short*>(c->alloc(n * 32 * 2));
+    c->z1 = static_cast<float*>(c->alloc(n * 32 * 4));
+    c->z2 = static_cast<float*>(c->alloc(n * 32 * 4));
+    c->partial = static_cast<float*>(c->alloc(ins::closure_wgrad_partial_floats(int64_t(n)) * 4));
+    c->mclos = c->alloc(c->vel_bytes());
+    c->ui = c->alloc(c->vel_bytes());
+    c->fbar = c->alloc(c->vel_bytes());
+    c->clos_alloc = true;
+    c->launch("fill_zero", [&] { return ins::launch_fill_zero_f(c->theta_bar, kClosParams, c->stream); });
+}
+
+// m = m_theta(u); leaves x0, z1, a1, z2, a2 for a following pullback.
+template <typename T>
+void closure_forward(ins_ctx c, const T* u, T* m) {
+    const ins::Grid& g = c->g;
+    c->launch("cnn_pack_input", [&] { return ins::launch_closure_pack_input<T>(g, u, c->x0, c->stream); });
+    c->launch("cnn_conv1", [&] {
+        return ins::launch_closure_conv<T>(g, 0, c->x0, c->wf[0], c->theta + kB1, nullptr, c->z1, c->a1, nullptr, c->stream);
+    });
+    c->launch("cnn_conv2", [&] {
+        return ins::launch_closure_conv<T>(g, 1, c->a1, c->wf[1], c->theta + kB2, nullptr, c->z2, c->a2, nullptr, c->stream);
+    });
+    c->launch("cnn_conv3", [&] {
+        return ins::launch_closure_conv<T>(g, 2, c->a2, c->wf[2], c->theta + kB3, nullptr, nullptr, nullptr, m, c->stream);
+    });
+}
+
+// ubar += (d m / d u)^T mbar and theta_bar += (d m / d theta)^T mbar, at the u of
+// the last closure_forward.
+template <typename T>
+void closure_backward(ins_ctx c, const T* mbar, T* ubar) {
+    const ins::Grid& g = c->g;
+    c->launch("cnn_pack_cotangent", [&] { return ins::launch_closure_pack_input<T>(g, mbar, c->gm, c->stream); });
+    c->launch("cnn_dgrad3", [&] {
+        return ins::launch_closure_conv<T>(g, 10, c->gm, c->wd[2], nullptr, c->z2, nullptr, c->gz2, nullptr, c->stream);
+    });
+    c->launch("cnn_wgrad3", [&] {
+        return ins::launch_closure_wgrad(g, 2, c->gm, c->a2, c->partial, c->theta_bar + kW3, c->theta_bar + kB3, c->stream);
+    });
+    c->launch("cnn_dgrad2", [&] {
+        return ins::launch_closure_conv<T>(g, 11, c->gz2, c->wd[1], nullptr, c->z1, nullptr, c->gz1, nullptr, c->stream);
+    });
+    c->launch("cnn_wgrad2", [&] {
+        return ins::launch_closure_wgrad(g, 1, c->gz2, c->a1, c->partial, c->theta_bar + kW2, c->theta_bar + kB2, c->stream);
+    });
+    c->launch("cnn_dgrad1", [&] {
+        return ins::launch_closure_conv<T>(g, 12, c->gz1, c->wd[0], nullptr, nullptr, nullptr, nullptr, ubar, c->stream);
+    });
+    c->launch("cnn_wgrad1", [&] {
+        return ins::launch_closure_wgrad(g, 0, c->gz1, c->x0, c->partial, c->theta_bar + kW1, c->theta_bar + kB1, c->stream);
+    });
+}
+
+// Closure term at the stage velocity u_i = (p ? w - G p : w); returns m or nullptr.
+template <typename T>
+const T* closure_at_stage(ins_ctx c, const T* w, const double* p) {
+    if (!c->clos_on) return nullptr;
+    const T* u = w;
+    if (p) {
+        T* ui = static_cast<T*>(c->ui);
+        apply_projection<T>(c, w, p, ui);
+        u = ui;
+    }
+    T* m = static_cast<T*>(c->mclos);
+    closure_forward<T>(c, u, m);
+    return m;
+}
+
+template <typename T>
+void stage(ins_ctx c, const T* w, const double* p, bool proj, const T* u0, T* y, bool yinit, double cy, T* wout,
+           double cw) {
+    const T* mc = closure_at_stage<T>(c, w, proj ? p : nullptr);
+    // one profile name per data-movement variant (their byte counts differ)
+    const char* name = !proj ? (y ? "stage_first" : "stage_first_rec")
+                             : (y ? (wout ? "stage" : "stage_last") : "stage_rec");
+    c->launch(name, [&] {
+        return ins::launch_stage<T>(c->g, w, p, proj, u0, y, yinit, cy, wout, cw, c->stream, mc);
+    });
 }
 
 // Classical RK4, projection after every stage (Sec. 2.5.2), low-storage
@@ -334,10 +453,16 @@ void ensure_vjp_storage(ins_ctx c) {
 template <typename T>
 void stage_vjp(ins_ctx c, const T* w, const double* p, bool proj_u, const T* ybar, const T* un, const double* q,
                bool has_w, double cb, double cw, T* u0bar, int mode, T* out) {
+    T* fb = c->clos_on ? static_cast<T*>(c->fbar) : nullptr;
     const char* name = mode == 0 ? "stage_vjp_first" : (mode == 2 ? "stage_vjp_last" : "stage_vjp");
     c->launch(name, [&] {
-        return ins::launch_stage_vjp<T>(c->g, w, p, proj_u, ybar, un, q, has_w, cb, cw, u0bar, mode, out, c->stream);
+        return ins::launch_stage_vjp<T>(c->g, w, p, proj_u, ybar, un, q, has_w, cb, cw, u0bar, mode, out, c->stream, fb);
     });
+    if (c->clos_on) {
+        // the closure's share of the stage pullback: m_bar = Fbar_i, at u_i
+        closure_at_stage<T>(c, w, proj_u ? p : nullptr);
+        closure_backward<T>(c, fb, mode == 2 ? u0bar : out);
+    }
 }
 
 // Reverse pass of step_rk4 (Sec. 3.4): recompute the stage states
@@ -433,9 +558,9 @@ ins_status ins_create(const ins_grid* grid, ins_bc bc, double nu, ins_dtype dtyp
         build_twiddles(g.nx / 2, rx, tw, c->px);
         build_twiddles(g.ny, ry, tw, c->py);
         if (d == 3) build_twiddles(g.nz, rz, tw, c->pz);
-        c->lnl_x = choose_lines(c->px, 16);
-        c->lnl_y = choose_lines(c->py, 16);
-        c->lnl_z = d == 3 ? choose_lines(c->pz, 16) : 0;
+        c->lnl_x = choose_lines(c->px, 16, 8);
+        c->lnl_y = choose_lines(c->py, 16, 8);
+        c->lnl_z = d == 3 ? choose_lines(c->pz, 16, 8) : 0;
         if (c->lnl_x < 0 || c->lnl_y < 0 || c->lnl_z < 0) raise(INS_ERR_UNSUPPORTED, "FFT length too long");
 
         const long double two_pi = 6.283185307179586476925286766559005768L;
@@ -517,7 +642,10 @@ ins_status ins_rhs(ins_ctx ctx, const void* u, void* f) {
         need(f, "f");
         with_type(ctx, [&](auto tag) {
             using T = decltype(tag);
-            ctx->launch("rhs", [&] { return ins::launch_rhs<T>(ctx->g, static_cast<const T*>(u), static_cast<T*>(f), ctx->stream); });
+            const T* mc = closure_at_stage<T>(ctx, static_cast<const T*>(u), nullptr);
+            ctx->launch("rhs", [&] {
+                return ins::launch_rhs<T>(ctx->g, static_cast<const T*>(u), static_cast<T*>(f), ctx->stream, mc);
+            });
         });
     });
 }
@@ -594,6 +722,10 @@ ins_status ins_rhs_vjp(ins_ctx ctx, const void* u, const void* fbar, void* ubar)
                 return ins::launch_rhs_vjp<T>(ctx->g, static_cast<const T*>(u), static_cast<const T*>(fbar),
                                               static_cast<T*>(ubar), ctx->stream);
             });
+            if (ctx->clos_on) {
+                closure_forward<T>(ctx, static_cast<const T*>(u), static_cast<T*>(ctx->mclos));
+                closure_backward<T>(ctx, static_cast<const T*>(fbar), static_cast<T*>(ubar));
+            }
         });
     });
 }
@@ -681,6 +813,83 @@ ins_status ins_energy_spectrum(ins_ctx ctx, const void* u, double* e, int nbins)
                 ctx->launch("fft_z_fwd", [&] { return ins::launch_fft_strided(g, ctx->spec, ctx->pz, 2, 0, ctx->lnl_z, ctx->st, ctx->stream); });
             ctx->launch("spectrum_bins", [&] { return ins::launch_spectrum_bins(g, ctx->spec, e, nbins, ctx->stream); });
         }
+    });
+}
+
+ins_status ins_closure_set(ins_ctx ctx, const float* params) {
+    return guarded([&] {
+        checked(ctx);
+        if (!params) {
+            ctx->clos_on = false;
+            return;
+        }
+        const ins::Grid& g = ctx->g;
+        if (g.dim != 3) raise(INS_ERR_UNSUPPORTED, "the closure is a 3D convolutional network");
+        if (g.nx % 32 != 0) raise(INS_ERR_UNSUPPORTED, "the closure needs n_x divisible by 32");
+        closure_alloc(ctx);
+        hip_check(hipMemcpyAsync(ctx->theta, params, kClosParams * sizeof(float), hipMemcpyDeviceToDevice, ctx->stream),
+                  "copy closure parameters");
+        const int cin[3] = {3, 32, 32}, cout[3] = {32, 32, 3}, cinp[3] = {8, 32, 32}, ntf[3] = {2, 2, 1},
+                  coutp[3] = {32, 32, 8}, ntd[3] = {1, 2, 2};
+        const int woff[3] = {kW1, kW2, kW3};
+        for (int l = 0; l < 3; ++l) {
+            ctx->launch("cnn_pack_weights", [&] {
+                return ins::launch_closure_pack_weights(ctx->theta + woff[l], cin[l], cout[l], cinp[l], ntf[l], ctx->wf[l],
+                                                        coutp[l], ntd[l], ctx->wd[l], ctx->stream);
+            });
+        }
+        ctx->clos_on = true;
+    });
+}
+
+ins_status ins_closure_grad(ins_ctx ctx, float* params_bar) {
+    return guarded([&] {
+        checked(ctx);
+        need(params_bar, "params_bar");
+        if (!ctx->clos_alloc) raise(INS_ERR_INVALID, "no closure has been set");
+        hip_check(hipMemcpyAsync(params_bar, ctx->theta_bar, kClosParams * sizeof(float), hipMemcpyDeviceToDevice,
+                                 ctx->stream),
+                  "copy closure gradient");
+        ctx->launch("fill_zero", [&] { return ins::launch_fill_zero_f(ctx->theta_bar, kClosParams, ctx->stream); });
+    });
+}
+
+ins_status ins_cnn_forward(ins_ctx ctx, const void* u, void* m) {
+    return guarded([&] {
+        checked(ctx);
+        need(u, "u");
+        need(m, "m");
+        if (!ctx->clos_on) raise(INS_ERR_INVALID, "no closure has been set");
+        with_type(ctx, [&](auto tag) {
+            using T = decltype(tag);
+            closure_forward<T>(ctx, static_cast<const T*>(u), static_cast<T*>(m));
+        });
+    });
+}
+
+ins_status ins_cnn_backward(ins_ctx ctx, const void* u, const void* mbar, void* ubar, float* params_bar) {
+    return guarded([&] {
+        checked(ctx);
+        need(u, "u");
+        need(mbar, "mbar");
+        need(ubar, "ubar");
+        need(params_bar, "params_bar");
+        if (!ctx->clos_on) raise(INS_ERR_INVALID, "no closure has been set");
+        with_type(ctx, [&](auto tag) {
+            using T = decltype(tag);
+            const size_t nv = ctx->vel_bytes() / sizeof(T);
+            ctx->launch("fill_zero", [&] {
+                return sizeof(T) == 8 ? ins::launch_fill_zero(reinterpret_cast<double*>(ubar), nv, ctx->stream)
+                                      : ins::launch_fill_zero_f(reinterpret_cast<float*>(ubar), nv, ctx->stream);
+            });
+            ctx->launch("fill_zero", [&] { return ins::launch_fill_zero_f(ctx->theta_bar, kClosParams, ctx->stream); });
+            closure_forward<T>(ctx, static_cast<const T*>(u), static_cast<T*>(ctx->mclos));
+            closure_backward<T>(ctx, static_cast<const T*>(mbar), static_cast<T*>(ubar));
+        });
+        hip_check(hipMemcpyAsync(params_bar, ctx->theta_bar, kClosParams * sizeof(float), hipMemcpyDeviceToDevice,
+                                 ctx->stream),
+                  "copy closure gradient");
+        ctx->launch("fill_zero", [&] { return ins::launch_fill_zero_f(ctx->theta_bar, kClosParams, ctx->stream); });
     });
 }
 

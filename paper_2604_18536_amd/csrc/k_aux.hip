@@ -167,6 +167,16 @@ hipError_t launch_fill_zero(double* p, size_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
+__global__ void k_fill_zero_f(float* __restrict__ p, int64_t n) {
+    const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (i < n) p[i] = 0.0f;
+}
+
+hipError_t launch_fill_zero_f(float* p, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_zero_f, dim3(int((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, p, int64_t(n));
+    return hipGetLastError();
+}
+
 hipError_t launch_spectrum_bins(const Grid& g, const cd* spec, double* bins, int nbins, hipStream_t s) {
     const int64_t n = int64_t(g.nx / 2 + 1) * g.ny * g.nz * g.batch;
     hipLaunchKernelGGL(k_spectrum_bins, dim3(int((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, g, spec, bins, nbins);

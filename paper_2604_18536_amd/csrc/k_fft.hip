@@ -18,7 +18,9 @@
 
 namespace ins {
 
-constexpr int kVmax = 16;  // complex values held per thread during a stage
+// LDS layout of a batch of `nl` lines of length N: element j of line l lives at
+// lds[j * ls + l] with the padded line stride ls = nl + 1 (odd), so that
+// neighbouring elements of one line fall in different banks.
 
 // cos(2 pi j / R), sin(2 pi j / R), correctly rounded.
 __device__ __forceinline__ constexpr double kcos(int R, int j) {
@@ -126,10 +128,11 @@ __device__ __forceinline__ void dft(cd* v) {
 // (element j of line l at lds[j*nl + l]). Butterfly i of a line reads
 // elements i + q N/R, multiplies by exp(SIGN 2 pi i q k / (p R)) with k = i mod p,
 // applies DFT_R and writes elements (i - k) R + k + q p.
-template <int R, int SIGN>
+template <int R, int SIGN, int VM>
 __device__ __forceinline__ void fft_stage(cd* __restrict__ lds, int lnl, int N, int p, const cd* __restrict__ tw) {
-    constexpr int BMAX = kVmax / R;
+    constexpr int BMAX = VM / R > 0 ? VM / R : 1;
     const int nl = 1 << lnl;
+    const int ls = nl + 1;
     const int s = N / R;
     const int nb = s << lnl;
     cd v[BMAX][R];
@@ -139,7 +142,7 @@ __device__ __forceinline__ void fft_stage(cd* __restrict__ lds, int lnl, int N, 
         if (t < nb) {
             const int l = t & (nl - 1), i = t >> lnl;
 #pragma unroll
-            for (int q = 0; q < R; ++q) v[b][q] = lds[((i + q * s) << lnl) + l];
+            for (int q = 0; q < R; ++q) v[b][q] = lds[(i + q * s) * ls + l];
         }
     }
     __syncthreads();
@@ -157,26 +160,26 @@ __device__ __forceinline__ void fft_stage(cd* __restrict__ lds, int lnl, int N, 
             dft<R, SIGN>(v[b]);
             const int base = (i - k) * R + k;
 #pragma unroll
-            for (int q = 0; q < R; ++q) lds[((base + q * p) << lnl) + l] = v[b][q];
+            for (int q = 0; q < R; ++q) lds[(base + q * p) * ls + l] = v[b][q];
         }
     }
     __syncthreads();
 }
 
 // Full FFT of the lines in LDS; the caller has synchronised after filling LDS.
-template <int SIGN>
+template <int SIGN, int VM>
 __device__ void fft_lines(cd* lds, int lnl, const FftPlan& P) {
     int p = 1;
     for (int st = 0; st < P.nst; ++st) {
         const int R = P.rad[st];
         const cd* tw = P.tw + P.tw_off[st];
         switch (R) {
-            case 8: fft_stage<8, SIGN>(lds, lnl, P.n, p, tw); break;
-            case 7: fft_stage<7, SIGN>(lds, lnl, P.n, p, tw); break;
-            case 5: fft_stage<5, SIGN>(lds, lnl, P.n, p, tw); break;
-            case 4: fft_stage<4, SIGN>(lds, lnl, P.n, p, tw); break;
-            case 3: fft_stage<3, SIGN>(lds, lnl, P.n, p, tw); break;
-            default: fft_stage<2, SIGN>(lds, lnl, P.n, p, tw); break;
+            case 8: fft_stage<8, SIGN, VM>(lds, lnl, P.n, p, tw); break;
+            case 7: fft_stage<7, SIGN, VM>(lds, lnl, P.n, p, tw); break;
+            case 5: fft_stage<5, SIGN, VM>(lds, lnl, P.n, p, tw); break;
+            case 4: fft_stage<4, SIGN, VM>(lds, lnl, P.n, p, tw); break;
+            case 3: fft_stage<3, SIGN, VM>(lds, lnl, P.n, p, tw); break;
+            default: fft_stage<2, SIGN, VM>(lds, lnl, P.n, p, tw); break;
         }
         p *= R;
     }
@@ -189,7 +192,7 @@ __device__ void fft_lines(cd* lds, int lnl, const FftPlan& P) {
 // ----------------------------------------------------------------------------
 // SRC 0: rows are the divergence of the velocity field `vel`;
 // SRC 1: rows of the float64 scalar field r; SRC 2: rows of component `comp` of vel.
-template <typename T, int DIM, int SRC>
+template <typename T, int DIM, int SRC, int VM>
 __global__ __launch_bounds__(kBlock) void k_fft_x_fwd(Grid g, const T* __restrict__ vel, const double* __restrict__ r,
                                                         cd* __restrict__ spec, FftPlan P, const cd* __restrict__ post,
                                                         int lnl, int comp) {
@@ -240,17 +243,17 @@ __global__ __launch_bounds__(kBlock) void k_fft_x_fwd(Grid g, const T* __restric
                 val = {double(src[2 * m]), double(src[2 * m + 1])};
             }
         }
-        lds[m * nl + l] = val;
+        lds[m * (nl + 1) + l] = val;
     }
     __syncthreads();
-    fft_lines<-1>(lds, lnl, P);
+    fft_lines<-1, VM>(lds, lnl, P);
     const int M1 = M + 1;
     for (int t = threadIdx.x; t < nl * M1; t += kBlock) {
         const int l = t / M1, k = t - l * M1;
         const int row = row0 + l;
         if (row >= nrows) continue;
-        const cd zk = lds[(k == M ? 0 : k) * nl + l];
-        const cd zc = cconj(lds[(k == 0 ? 0 : M - k) * nl + l]);
+        const cd zk = lds[(k == M ? 0 : k) * (nl + 1) + l];
+        const cd zc = cconj(lds[(k == 0 ? 0 : M - k) * (nl + 1) + l]);
         const cd e = cscale(cadd(zk, zc), 0.5);
         const cd dd = csub(zk, zc);
         const cd o = {0.5 * dd.y, -0.5 * dd.x};
@@ -261,6 +264,7 @@ __global__ __launch_bounds__(kBlock) void k_fft_x_fwd(Grid g, const T* __restric
 // x pass, inverse: half spectrum -> real rows, scaled by n_x (unnormalised).
 // Z[k] = (X[k] + conj X[M-k]) + i (X[k] - conj X[M-k]) conj(W^k), z = IFFT_M(Z),
 // x[2m] = Re z[m], x[2m+1] = Im z[m].
+template <int VM>
 __global__ __launch_bounds__(kBlock) void k_fft_x_inv(Grid g, const cd* __restrict__ spec, double* __restrict__ p,
                                                         FftPlan P, const cd* __restrict__ post, int lnl) {
     extern __shared__ cd lds[];
@@ -280,21 +284,21 @@ __global__ __launch_bounds__(kBlock) void k_fft_x_inv(Grid g, const cd* __restri
             const cd o = cmulc(csub(xk, xc), post[k]);
             z = {e.x - o.y, e.y + o.x};
         }
-        lds[k * nl + l] = z;
+        lds[k * (nl + 1) + l] = z;
     }
     __syncthreads();
-    fft_lines<1>(lds, lnl, P);
+    fft_lines<1, VM>(lds, lnl, P);
     for (int t = threadIdx.x; t < nl * M; t += kBlock) {
         const int l = t / M, m = t - l * M;
         const int row = row0 + l;
         if (row >= nrows) continue;
-        reinterpret_cast<cd*>(p + int64_t(row) * g.nx)[m] = lds[m * nl + l];
+        reinterpret_cast<cd*>(p + int64_t(row) * g.nx)[m] = lds[m * (nl + 1) + l];
     }
 }
 
 // Strided complex pass along y (axis 1) or z (axis 2) of the half spectrum
 // [batch][n_z][n_y][n_x/2+1]. MODE 0 forward, 1 inverse, 2 forward + divide + inverse.
-template <int MODE>
+template <int MODE, int VM>
 __global__ __launch_bounds__(kBlock) void k_fft_strided(Grid g, cd* __restrict__ spec, FftPlan P, int axis, int lnl,
                                                           SolveTab st) {
     extern __shared__ cd lds[];
@@ -321,15 +325,16 @@ __global__ __launch_bounds__(kBlock) void k_fft_strided(Grid g, cd* __restrict__
     const int kx0 = chunk << lnl;
     base += kx0;
     const int ntot = N << lnl;
+    const int ls = nl + 1;
     for (int t = threadIdx.x; t < ntot; t += kBlock) {
         const int c = t & (nl - 1), j = t >> lnl;
-        lds[t] = (kx0 + c < nxh) ? spec[base + j * stride + c] : cd{0.0, 0.0};
+        lds[j * ls + c] = (kx0 + c < nxh) ? spec[base + j * stride + c] : cd{0.0, 0.0};
     }
     __syncthreads();
     if constexpr (MODE == 1) {
-        fft_lines<1>(lds, lnl, P);
+        fft_lines<1, VM>(lds, lnl, P);
     } else {
-        fft_lines<-1>(lds, lnl, P);
+        fft_lines<-1, VM>(lds, lnl, P);
     }
     if constexpr (MODE == 2) {
         // divide by L(k) * #cells; L(0) := 1.
@@ -346,14 +351,14 @@ __global__ __launch_bounds__(kBlock) void k_fft_strided(Grid g, cd* __restrict__
                 kzero = (kx == 0 && j == 0);
             }
             const double sc = kzero ? st.inv_ncell : -st.inv_ncell / lam;
-            lds[t] = cscale(lds[t], sc);
+            lds[j * ls + c] = cscale(lds[j * ls + c], sc);
         }
         __syncthreads();
-        fft_lines<1>(lds, lnl, P);
+        fft_lines<1, VM>(lds, lnl, P);
     }
     for (int t = threadIdx.x; t < ntot; t += kBlock) {
         const int c = t & (nl - 1), j = t >> lnl;
-        if (kx0 + c < nxh) spec[base + j * stride + c] = lds[t];
+        if (kx0 + c < nxh) spec[base + j * stride + c] = lds[j * ls + c];
     }
 }
 
@@ -366,16 +371,19 @@ hipError_t launch_fft_x_fwd(const Grid& g, const T* vel, const double* r, cd* sp
     const int nl = 1 << lnl;
     const int nrows = g.batch * g.nz * g.ny;
     const int nblk = (nrows + nl - 1) / nl;
-    const size_t shm = size_t(nl) * px.n * sizeof(cd);
-#define INS_XF(D, SRC) \
-    hipLaunchKernelGGL((k_fft_x_fwd<T, D, SRC>), dim3(nblk), dim3(kBlock), shm, s, g, vel, r, spec, px, post, lnl, comp)
+    const size_t shm = size_t(nl + 1) * px.n * sizeof(cd);
+#define INS_XF(D, SRC, VM) \
+    hipLaunchKernelGGL((k_fft_x_fwd<T, D, SRC, VM>), dim3(nblk), dim3(kBlock), shm, s, g, vel, r, spec, px, post, lnl, comp)
+#define INS_XF_VM(D, SRC) \
+    do { if (px.vm == 8) INS_XF(D, SRC, 8); else INS_XF(D, SRC, 16); } while (0)
     if (vel && comp < 0) {
-        if (g.dim == 3) INS_XF(3, 0); else INS_XF(2, 0);
+        if (g.dim == 3) INS_XF_VM(3, 0); else INS_XF_VM(2, 0);
     } else if (vel) {
-        if (g.dim == 3) INS_XF(3, 2); else INS_XF(2, 2);
+        if (g.dim == 3) INS_XF_VM(3, 2); else INS_XF_VM(2, 2);
     } else {
-        INS_XF(3, 1);
+        INS_XF_VM(3, 1);
     }
+#undef INS_XF_VM
 #undef INS_XF
     return hipGetLastError();
 }
@@ -385,8 +393,11 @@ hipError_t launch_fft_x_inv(const Grid& g, const cd* spec, double* p, const FftP
     const int nl = 1 << lnl;
     const int nrows = g.batch * g.nz * g.ny;
     const int nblk = (nrows + nl - 1) / nl;
-    const size_t shm = size_t(nl) * px.n * sizeof(cd);
-    hipLaunchKernelGGL(k_fft_x_inv, dim3(nblk), dim3(kBlock), shm, s, g, spec, p, px, post, lnl);
+    const size_t shm = size_t(nl + 1) * px.n * sizeof(cd);
+    if (px.vm == 8)
+        hipLaunchKernelGGL(k_fft_x_inv<8>, dim3(nblk), dim3(kBlock), shm, s, g, spec, p, px, post, lnl);
+    else
+        hipLaunchKernelGGL(k_fft_x_inv<16>, dim3(nblk), dim3(kBlock), shm, s, g, spec, p, px, post, lnl);
     return hipGetLastError();
 }
 
@@ -397,13 +408,19 @@ hipError_t launch_fft_strided(const Grid& g, cd* spec, const FftPlan& pl, int ax
     const int nchunk = (nxh + nl - 1) / nl;
     const int nouter = axis == 1 ? g.batch * g.nz : g.batch * g.ny;
     const int nblk = nchunk * nouter;
-    const size_t shm = size_t(nl) * pl.n * sizeof(cd);
+    const size_t shm = size_t(nl + 1) * pl.n * sizeof(cd);
+#define INS_ST(MODE, VM) \
+    hipLaunchKernelGGL((k_fft_strided<MODE, VM>), dim3(nblk), dim3(kBlock), shm, s, g, spec, pl, axis, lnl, st)
+#define INS_ST_VM(MODE) \
+    do { if (pl.vm == 8) INS_ST(MODE, 8); else INS_ST(MODE, 16); } while (0)
     if (mode == 0)
-        hipLaunchKernelGGL(k_fft_strided<0>, dim3(nblk), dim3(kBlock), shm, s, g, spec, pl, axis, lnl, st);
+        INS_ST_VM(0);
     else if (mode == 1)
-        hipLaunchKernelGGL(k_fft_strided<1>, dim3(nblk), dim3(kBlock), shm, s, g, spec, pl, axis, lnl, st);
+        INS_ST_VM(1);
     else
-        hipLaunchKernelGGL(k_fft_strided<2>, dim3(nblk), dim3(kBlock), shm, s, g, spec, pl, axis, lnl, st);
+        INS_ST_VM(2);
+#undef INS_ST_VM
+#undef INS_ST
     return hipGetLastError();
 }
 

@@ -47,7 +47,7 @@ __device__ __forceinline__ void st_stream(T v, T* p) {
 template <typename T, bool PROJ>
 __global__ __launch_bounds__(kBlock) void k_stage_zm(Grid g, const T* __restrict__ w, const double* __restrict__ p,
                                                        const T* __restrict__ u0, T* __restrict__ y, int yinit, T cy,
-                                                       T* __restrict__ wout, T cw, int zc) {
+                                                       T* __restrict__ wout, T cw, int zc, const T* __restrict__ mc) {
     __shared__ T ring[4][3][kZmHP];
     const int nx = g.nx, ny = g.ny, nz = g.nz;
     const int ntx = (nx + kZmTX - 1) / kZmTX, nty = (ny + kZmTY - 1) / kZmTY, nzc = (nz + zc - 1) / zc;
@@ -148,6 +148,7 @@ __global__ __launch_bounds__(kBlock) void k_stage_zm(Grid g, const T* __restrict
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const int64_t kk = boff + int64_t(a) * nc + c0;
+                if (mc) F[a] += mc[kk];
                 if (y) st_stream(yv[a] + cy * F[a], y + kk);
                 if (wout) st_stream(base[a] + cw * F[a], wout + kk);
             }
@@ -168,21 +169,21 @@ int zm_chunk(const Grid& g) {
 
 template <typename T>
 hipError_t launch_stage_zm(const Grid& g, const T* w, const double* p, bool proj, const T* u0, T* y, bool yinit,
-                           double cy, T* wout, double cw, hipStream_t s) {
+                           double cy, T* wout, double cw, hipStream_t s, const T* mc) {
     const int zc = zm_chunk(g);
     const int nblk = ((g.nx + kZmTX - 1) / kZmTX) * ((g.ny + kZmTY - 1) / kZmTY) * ((g.nz + zc - 1) / zc) * g.batch;
     const int yi = yinit ? 1 : 0;
     if (proj)
-        hipLaunchKernelGGL((k_stage_zm<T, true>), dim3(nblk), dim3(kBlock), 0, s, g, w, p, u0, y, yi, T(cy), wout, T(cw), zc);
+        hipLaunchKernelGGL((k_stage_zm<T, true>), dim3(nblk), dim3(kBlock), 0, s, g, w, p, u0, y, yi, T(cy), wout, T(cw), zc, mc);
     else
-        hipLaunchKernelGGL((k_stage_zm<T, false>), dim3(nblk), dim3(kBlock), 0, s, g, w, p, u0, y, yi, T(cy), wout, T(cw), zc);
+        hipLaunchKernelGGL((k_stage_zm<T, false>), dim3(nblk), dim3(kBlock), 0, s, g, w, p, u0, y, yi, T(cy), wout, T(cw), zc, mc);
     return hipGetLastError();
 }
 
 template hipError_t launch_stage_zm<double>(const Grid&, const double*, const double*, bool, const double*, double*, bool,
-                                            double, double*, double, hipStream_t);
+                                            double, double*, double, hipStream_t, const double*);
 template hipError_t launch_stage_zm<float>(const Grid&, const float*, const double*, bool, const float*, float*, bool,
-                                           double, float*, double, hipStream_t);
+                                           double, float*, double, hipStream_t, const float*);
 
 }  // namespace ins
 
@@ -191,16 +192,16 @@ namespace ins {
 // Reverse RK4 stage for 3D grids as a z-march (counterpart of k_stage_vjp in
 // k_vjp.hip, same arithmetic). Two LDS rings hold, per plane, the stage
 // velocity u_i = w - G p and the right-hand-side cotangent
-// Fbar_i = cb ybar + cw (un - G q) on the tile plus halo; three slots each,
-// two barriers per plane.
+// Fbar_i = cb ybar + cw (un - G q) on the tile plus halo; four slots each and
+// the same load/compute pipeline as k_stage_zm.
 template <typename T, bool PROJ_U, bool HAS_W>
 __global__ __launch_bounds__(kBlock) void k_stage_vjp_zm(Grid g, const T* __restrict__ w, const double* __restrict__ p,
                                                            const T* __restrict__ ybar, const T* __restrict__ un,
                                                            const double* __restrict__ q, T cb, T cw,
                                                            T* __restrict__ u0bar, int mode, T* __restrict__ ubar_out,
-                                                           int zc) {
-    __shared__ T ru[3][3][kZmHP];
-    __shared__ T rf[3][3][kZmHP];
+                                                           int zc, T* __restrict__ fbar_out) {
+    __shared__ T ru[4][3][kZmHP];
+    __shared__ T rf[4][3][kZmHP];
     const int nx = g.nx, ny = g.ny, nz = g.nz;
     const int ntx = (nx + kZmTX - 1) / kZmTX, nty = (ny + kZmTY - 1) / kZmTY, nzc = (nz + zc - 1) / zc;
     int L = xcd_logical(blockIdx.x, gridDim.x);
@@ -239,13 +240,10 @@ __global__ __launch_bounds__(kBlock) void k_stage_vjp_zm(Grid g, const T* __rest
     const bool valid = cxg < nx && cyg < ny;
     const int centre = (ly + 1) * kZmHX + (lx + 1);
 
-    const int nk = (z1 - z0) + 2;
-    for (int k = 0; k < nk; ++k) {
-        const int zz = pmod(z0 - 1 + k, nz);
+    T pu[2][3], pf[2][3];
+    auto fetch = [&](int zz) {
         const int zoff = zz * plane;
         const int zpo = (zz + 1 == nz ? 0 : zz + 1) * plane;
-        T* su = &ru[k % 3][0][0];
-        T* sf = &rf[k % 3][0][0];
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             if (hq[s] < kZmHP) {
@@ -256,42 +254,72 @@ __global__ __launch_bounds__(kBlock) void k_stage_vjp_zm(Grid g, const T* __rest
                 if constexpr (HAS_W) qc = qb[j];
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    T uv;
                     if constexpr (PROJ_U)
-                        uv = T(double(wb[c * nc + j]) - (pb[jp[c]] - pc) * g.ih[c]);
+                        pu[s][c] = T(double(wb[c * nc + j]) - (pb[jp[c]] - pc) * g.ih[c]);
                     else
-                        uv = wb[c * nc + j];
+                        pu[s][c] = wb[c * nc + j];
                     T fv = cb * yb[c * nc + j];
                     if constexpr (HAS_W) fv += cw * T(double(ub[c * nc + j]) - (qb[jp[c]] - qc) * g.ih[c]);
-                    su[c * kZmHP + hq[s]] = uv;
-                    sf[c * kZmHP + hq[s]] = fv;
+                    pf[s][c] = fv;
                 }
             }
         }
-        __syncthreads();
-        if (k >= 2 && valid) {
-            const int z = z0 + k - 2;
-            LdsSrc<T> U{&ru[(k - 2) % 3][0][0], &ru[(k - 1) % 3][0][0], &ru[k % 3][0][0], centre};
-            LdsSrc<T> F{&rf[(k - 2) % 3][0][0], &rf[(k - 1) % 3][0][0], &rf[k % 3][0][0], centre};
-            T out[3];
-            rhs_vjp_cell<T, 3>(g, U, F, Nb{}, out);
+    };
+    auto park = [&](int k) {
+        T* su = &ru[k & 3][0][0];
+        T* sf = &rf[k & 3][0][0];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            if (hq[s] < kZmHP) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    su[c * kZmHP + hq[s]] = pu[s][c];
+                    sf[c * kZmHP + hq[s]] = pf[s][c];
+                }
+            }
+        }
+    };
+
+    const int nk = (z1 - z0) + 2;
+    fetch(pmod(z0 - 1, nz));
+    park(0);
+    fetch(pmod(z0, nz));
+    park(1);
+    fetch(pmod(z0 + 1, nz));
+    park(2);
+    __syncthreads();
+    for (int k = 2; k < nk; ++k) {
+        const int z = z0 + k - 2;
+        const bool more = k + 1 < nk;
+        if (more) fetch(pmod(z0 - 1 + k + 1, nz));
+        if (valid) {
             const int cyx = cyg * nx + cxg;
             const int c0 = z * plane + cyx;
             const int zpc = (z + 1 == nz ? 0 : z + 1) * plane + cyx;
             const int xpc = z * plane + cyg * nx + (cxg + 1 == nx ? 0 : cxg + 1);
             const int ypc = z * plane + (cyg + 1 == ny ? 0 : cyg + 1) * nx + cxg;
             const int jpc[3] = {xpc, ypc, zpc};
+            T acc[3];
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const int64_t kk = boff + int64_t(a) * nc + c0;
-                T acc = mode == 0 ? yb[int64_t(a) * nc + c0] : u0bar[kk];
+                acc[a] = mode == 0 ? yb[int64_t(a) * nc + c0] : ld_stream(u0bar + kk);
                 if constexpr (HAS_W)
-                    acc += T(double(ub[int64_t(a) * nc + c0]) - (qb[jpc[a]] - qb[c0]) * g.ih[a]);
-                if (mode == 2) acc += out[a];
-                u0bar[kk] = acc;
-                if (ubar_out) ubar_out[kk] = out[a];
+                    acc[a] += T(double(ub[int64_t(a) * nc + c0]) - (qb[jpc[a]] - qb[c0]) * g.ih[a]);
+            }
+            LdsSrc<T> U{&ru[(k - 2) & 3][0][0], &ru[(k - 1) & 3][0][0], &ru[k & 3][0][0], centre};
+            LdsSrc<T> F{&rf[(k - 2) & 3][0][0], &rf[(k - 1) & 3][0][0], &rf[k & 3][0][0], centre};
+            T out[3];
+            rhs_vjp_cell<T, 3>(g, U, F, Nb{}, out);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int64_t kk = boff + int64_t(a) * nc + c0;
+                st_stream(mode == 2 ? acc[a] + out[a] : acc[a], u0bar + kk);
+                if (ubar_out) st_stream(out[a], ubar_out + kk);
+                if (fbar_out) fbar_out[kk] = rf[(k - 1) & 3][a][centre];
             }
         }
+        if (more) park(k + 1);
         __syncthreads();
     }
 }
@@ -299,13 +327,13 @@ __global__ __launch_bounds__(kBlock) void k_stage_vjp_zm(Grid g, const T* __rest
 template <typename T>
 hipError_t launch_stage_vjp_zm(const Grid& g, const T* w, const double* p, bool proj_u, const T* ybar, const T* un,
                                const double* q, bool has_w, double cb, double cw, T* u0bar, int mode, T* ubar_out,
-                               hipStream_t s) {
+                               hipStream_t s, T* fbar_out) {
     const int zc = zm_chunk(g);
     const int nblk = ((g.nx + kZmTX - 1) / kZmTX) * ((g.ny + kZmTY - 1) / kZmTY) * ((g.nz + zc - 1) / zc) * g.batch;
     const T tb = T(cb), tw = T(cw);
 #define INS_VJP_ZM(PU, HW)                                                                                           \
     hipLaunchKernelGGL((k_stage_vjp_zm<T, PU, HW>), dim3(nblk), dim3(kBlock), 0, s, g, w, p, ybar, un, q, tb, tw, u0bar, \
-                       mode, ubar_out, zc)
+                       mode, ubar_out, zc, fbar_out)
     if (proj_u && has_w)
         INS_VJP_ZM(true, true);
     else if (proj_u)
@@ -320,9 +348,9 @@ hipError_t launch_stage_vjp_zm(const Grid& g, const T* w, const double* p, bool 
 
 template hipError_t launch_stage_vjp_zm<double>(const Grid&, const double*, const double*, bool, const double*,
                                                 const double*, const double*, bool, double, double, double*, int,
-                                                double*, hipStream_t);
+                                                double*, hipStream_t, double*);
 template hipError_t launch_stage_vjp_zm<float>(const Grid&, const float*, const double*, bool, const float*,
                                                const float*, const double*, bool, double, double, float*, int, float*,
-                                               hipStream_t);
+                                               hipStream_t, float*);
 
 }  // namespace ins

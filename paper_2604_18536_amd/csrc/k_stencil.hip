@@ -11,7 +11,8 @@
 namespace ins {
 
 template <typename T, int DIM>
-__global__ __launch_bounds__(kBlock) void k_rhs(Grid g, const T* __restrict__ u, T* __restrict__ f) {
+__global__ __launch_bounds__(kBlock) void k_rhs(Grid g, const T* __restrict__ u, T* __restrict__ f,
+                                                  const T* __restrict__ mc) {
     const TileIdx t = tile_of(g);
     if (!t.valid) return;
     const Nb nb = make_nb<DIM>(g, t.x, t.y, t.z);
@@ -21,7 +22,7 @@ __global__ __launch_bounds__(kBlock) void k_rhs(Grid g, const T* __restrict__ u,
     rhs_cell<T, DIM>(g, U, nb, F);
     const int c0 = nb.at(0, 0, 0);
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) f[boff + a * g.ncell + c0] = F[a];
+    for (int a = 0; a < DIM; ++a) f[boff + a * g.ncell + c0] = mc ? F[a] + mc[boff + a * g.ncell + c0] : F[a];
 }
 
 // RK4 stage on 2D grids (3D grids use the z-march of k_stage3d.hip):
@@ -147,8 +148,8 @@ __global__ __launch_bounds__(kBlock) void k_grad_vjp(Grid g, const T* __restrict
     } while (0)
 
 template <typename T>
-hipError_t launch_rhs(const Grid& g, const T* u, T* f, hipStream_t s) {
-    INS_DISPATCH_DIM(g, k_rhs, g, u, f);
+hipError_t launch_rhs(const Grid& g, const T* u, T* f, hipStream_t s, const T* mc) {
+    INS_DISPATCH_DIM(g, k_rhs, g, u, f, mc);
     return hipGetLastError();
 }
 
@@ -184,8 +185,8 @@ hipError_t launch_grad_vjp(const Grid& g, const T* gbar, double* pbar, hipStream
 
 template <typename T>
 hipError_t launch_stage(const Grid& g, const T* w, const double* p, bool proj, const T* u0, T* y, bool yinit, double cy,
-                        T* wout, double cw, hipStream_t s) {
-    if (g.dim == 3) return launch_stage_zm<T>(g, w, p, proj, u0, y, yinit, cy, wout, cw, s);
+                        T* wout, double cw, hipStream_t s, const T* mc) {
+    if (g.dim == 3) return launch_stage_zm<T>(g, w, p, proj, u0, y, yinit, cy, wout, cw, s, mc);
     const int nblk = stencil_blocks(g);
     const int yi = yinit ? 1 : 0;
     if (proj)
@@ -196,14 +197,14 @@ hipError_t launch_stage(const Grid& g, const T* w, const double* p, bool proj, c
 }
 
 #define INS_INSTANTIATE(T)                                                                                          \
-    template hipError_t launch_rhs<T>(const Grid&, const T*, T*, hipStream_t);                                      \
+    template hipError_t launch_rhs<T>(const Grid&, const T*, T*, hipStream_t, const T*);                            \
     template hipError_t launch_divergence<T>(const Grid&, const T*, double*, hipStream_t);                          \
     template hipError_t launch_gradient<T>(const Grid&, const double*, T*, hipStream_t);                            \
     template hipError_t launch_apply_projection<T>(const Grid&, const T*, const double*, T*, hipStream_t);          \
     template hipError_t launch_div_vjp<T>(const Grid&, const double*, T*, hipStream_t);                             \
     template hipError_t launch_grad_vjp<T>(const Grid&, const T*, double*, hipStream_t);                            \
     template hipError_t launch_stage<T>(const Grid&, const T*, const double*, bool, const T*, T*, bool, double, T*, \
-                                        double, hipStream_t);
+                                        double, hipStream_t, const T*);
 
 INS_INSTANTIATE(double)
 INS_INSTANTIATE(float)

@@ -62,7 +62,7 @@ template <typename T, int DIM, bool PROJ_U, bool HAS_W>
 __global__ __launch_bounds__(kBlock) void k_stage_vjp(Grid g, const T* __restrict__ w, const double* __restrict__ p,
                                                         const T* __restrict__ ybar, const T* __restrict__ un,
                                                         const double* __restrict__ q, T cb, T cw, T* __restrict__ u0bar,
-                                                        int u0bar_mode, T* __restrict__ ubar_out) {
+                                                        int u0bar_mode, T* __restrict__ ubar_out, T* __restrict__ fbar_out) {
     const TileIdx t = tile_of(g);
     if (!t.valid) return;
     const Nb nb = make_nb<DIM>(g, t.x, t.y, t.z);
@@ -91,6 +91,7 @@ __global__ __launch_bounds__(kBlock) void k_stage_vjp(Grid g, const T* __restric
         if (u0bar_mode == 2) acc += out[a];
         u0bar[k] = acc;
         if (ubar_out) ubar_out[k] = out[a];
+        if (fbar_out) fbar_out[k] = F(a, nb, 0, 0, 0);
     }
 }
 
@@ -106,19 +107,20 @@ hipError_t launch_rhs_vjp(const Grid& g, const T* u, const T* fbar, T* ubar, hip
 
 template <typename T, int DIM>
 static void stage_vjp_dim(const Grid& g, int nblk, const T* w, const double* p, bool proj_u, const T* ybar, const T* un,
-                          const double* q, bool has_w, T cb, T cw, T* u0bar, int mode, T* ubar_out, hipStream_t s) {
+                          const double* q, bool has_w, T cb, T cw, T* u0bar, int mode, T* ubar_out, hipStream_t s,
+                          T* fbar_out) {
     if (proj_u && has_w)
         hipLaunchKernelGGL((k_stage_vjp<T, DIM, true, true>), dim3(nblk), dim3(kBlock), 0, s, g, w, p, ybar, un, q, cb, cw,
-                           u0bar, mode, ubar_out);
+                           u0bar, mode, ubar_out, fbar_out);
     else if (proj_u)
         hipLaunchKernelGGL((k_stage_vjp<T, DIM, true, false>), dim3(nblk), dim3(kBlock), 0, s, g, w, p, ybar, un, q, cb,
-                           cw, u0bar, mode, ubar_out);
+                           cw, u0bar, mode, ubar_out, fbar_out);
     else if (has_w)
         hipLaunchKernelGGL((k_stage_vjp<T, DIM, false, true>), dim3(nblk), dim3(kBlock), 0, s, g, w, p, ybar, un, q, cb,
-                           cw, u0bar, mode, ubar_out);
+                           cw, u0bar, mode, ubar_out, fbar_out);
     else
         hipLaunchKernelGGL((k_stage_vjp<T, DIM, false, false>), dim3(nblk), dim3(kBlock), 0, s, g, w, p, ybar, un, q, cb,
-                           cw, u0bar, mode, ubar_out);
+                           cw, u0bar, mode, ubar_out, fbar_out);
 }
 
 // Reverse stage i: with u_i = (proj_u ? w - G p : w) and
@@ -129,9 +131,11 @@ static void stage_vjp_dim(const Grid& g, int nblk, const T* w, const double* p, 
 template <typename T>
 hipError_t launch_stage_vjp(const Grid& g, const T* w, const double* p, bool proj_u, const T* ybar, const T* un,
                             const double* q, bool has_w, double cb, double cw, T* u0bar, int mode, T* ubar_out,
-                            hipStream_t s) {
-    if (g.dim == 3) return launch_stage_vjp_zm<T>(g, w, p, proj_u, ybar, un, q, has_w, cb, cw, u0bar, mode, ubar_out, s);
-    stage_vjp_dim<T, 2>(g, stencil_blocks(g), w, p, proj_u, ybar, un, q, has_w, T(cb), T(cw), u0bar, mode, ubar_out, s);
+                            hipStream_t s, T* fbar_out) {
+    if (g.dim == 3)
+        return launch_stage_vjp_zm<T>(g, w, p, proj_u, ybar, un, q, has_w, cb, cw, u0bar, mode, ubar_out, s, fbar_out);
+    stage_vjp_dim<T, 2>(g, stencil_blocks(g), w, p, proj_u, ybar, un, q, has_w, T(cb), T(cw), u0bar, mode, ubar_out, s,
+                        fbar_out);
     return hipGetLastError();
 }
 
@@ -139,8 +143,9 @@ template hipError_t launch_rhs_vjp<double>(const Grid&, const double*, const dou
 template hipError_t launch_rhs_vjp<float>(const Grid&, const float*, const float*, float*, hipStream_t);
 template hipError_t launch_stage_vjp<double>(const Grid&, const double*, const double*, bool, const double*,
                                              const double*, const double*, bool, double, double, double*, int, double*,
-                                             hipStream_t);
+                                             hipStream_t, double*);
 template hipError_t launch_stage_vjp<float>(const Grid&, const float*, const double*, bool, const float*, const float*,
-                                            const double*, bool, double, double, float*, int, float*, hipStream_t);
+                                            const double*, bool, double, double, float*, int, float*, hipStream_t,
+                                            float*);
 
 }  // namespace ins

@@ -193,6 +193,42 @@ class Solver:
                self._check(out, "vel", "out"), float(dt))
         return out
 
+    # ------------------------------------------------------- learned closure
+    N_CLOSURE_PARAMS = 32899
+
+    def _params(self, t, name):
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or t.device != self.device \
+                or t.numel() != self.N_CLOSURE_PARAMS or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous float32 tensor of {self.N_CLOSURE_PARAMS} values on {self.device}")
+        return C.c_void_p(t.data_ptr())
+
+    def set_closure(self, params):
+        """Attach the CNN closure with float32 parameters (None detaches it)."""
+        self._sync_stream()
+        L.call("ins_closure_set", self._ctx, None if params is None else self._params(params, "params"))
+
+    def closure_grad(self, out=None):
+        """Parameter gradient accumulated by the *_vjp calls since the last read (resets it)."""
+        out = torch.empty(self.N_CLOSURE_PARAMS, dtype=torch.float32, device=self.device) if out is None else out
+        self._sync_stream()
+        L.call("ins_closure_grad", self._ctx, self._params(out, "out"))
+        return out
+
+    def cnn_forward(self, u, out=None):
+        out = self._out(out, u, "vel")
+        self._sync_stream()
+        L.call("ins_cnn_forward", self._ctx, self._check(u, "vel", "u"), self._check(out, "vel", "out"))
+        return out
+
+    def cnn_backward(self, u, mbar):
+        """(ubar, params_bar) of the closure alone."""
+        ubar = self._out(None, u, "vel")
+        pbar = torch.empty(self.N_CLOSURE_PARAMS, dtype=torch.float32, device=self.device)
+        self._sync_stream()
+        L.call("ins_cnn_backward", self._ctx, self._check(u, "vel", "u"), self._check(mbar, "vel", "mbar"),
+               self._check(ubar, "vel", "ubar"), self._params(pbar, "params_bar"))
+        return ubar, pbar
+
     # ------------------------------------------------------- LES data helpers
     def face_filter(self, u, factor=4, out=None):
         """Coarse staggered field: mean of the fine faces on each coarse face."""
