@@ -200,8 +200,8 @@ __global__ __launch_bounds__(kBlock) void k_stage_vjp_zm(Grid g, const T* __rest
                                                            const double* __restrict__ q, T cb, T cw,
                                                            T* __restrict__ u0bar, int mode, T* __restrict__ ubar_out,
                                                            int zc, T* __restrict__ fbar_out) {
-    __shared__ T ru[4][3][kZmHP];
-    __shared__ T rf[4][3][kZmHP];
+    __shared__ T ru[3][3][kZmHP];
+    __shared__ T rf[3][3][kZmHP];
     const int nx = g.nx, ny = g.ny, nz = g.nz;
     const int ntx = (nx + kZmTX - 1) / kZmTX, nty = (ny + kZmTY - 1) / kZmTY, nzc = (nz + zc - 1) / zc;
     int L = xcd_logical(blockIdx.x, gridDim.x);
@@ -266,8 +266,8 @@ __global__ __launch_bounds__(kBlock) void k_stage_vjp_zm(Grid g, const T* __rest
         }
     };
     auto park = [&](int k) {
-        T* su = &ru[k & 3][0][0];
-        T* sf = &rf[k & 3][0][0];
+        T* su = &ru[k % 3][0][0];
+        T* sf = &rf[k % 3][0][0];
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             if (hq[s] < kZmHP) {
@@ -307,8 +307,8 @@ __global__ __launch_bounds__(kBlock) void k_stage_vjp_zm(Grid g, const T* __rest
                 if constexpr (HAS_W)
                     acc[a] += T(double(ub[int64_t(a) * nc + c0]) - (qb[jpc[a]] - qb[c0]) * g.ih[a]);
             }
-            LdsSrc<T> U{&ru[(k - 2) & 3][0][0], &ru[(k - 1) & 3][0][0], &ru[k & 3][0][0], centre};
-            LdsSrc<T> F{&rf[(k - 2) & 3][0][0], &rf[(k - 1) & 3][0][0], &rf[k & 3][0][0], centre};
+            LdsSrc<T> U{&ru[(k - 2) % 3][0][0], &ru[(k - 1) % 3][0][0], &ru[k % 3][0][0], centre};
+            LdsSrc<T> F{&rf[(k - 2) % 3][0][0], &rf[(k - 1) % 3][0][0], &rf[k % 3][0][0], centre};
             T out[3];
             rhs_vjp_cell<T, 3>(g, U, F, Nb{}, out);
 #pragma unroll
@@ -316,9 +316,11 @@ __global__ __launch_bounds__(kBlock) void k_stage_vjp_zm(Grid g, const T* __rest
                 const int64_t kk = boff + int64_t(a) * nc + c0;
                 st_stream(mode == 2 ? acc[a] + out[a] : acc[a], u0bar + kk);
                 if (ubar_out) st_stream(out[a], ubar_out + kk);
-                if (fbar_out) fbar_out[kk] = rf[(k - 1) & 3][a][centre];
+                if (fbar_out) fbar_out[kk] = rf[(k - 1) % 3][a][centre];
             }
         }
+        // slot (k+1) % 3 is the one just read as plane z-1: wait for every reader
+        __syncthreads();
         if (more) park(k + 1);
         __syncthreads();
     }
