@@ -29,6 +29,14 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+
+CONFIGS = {
+    # the benchmark workload: 3D decaying turbulence at 256^3
+    "turb256": {"n": 256, "nu": 1.0 / 1600.0, "dt": 1e-3, "k0": 4.0, "seed": 0,
+                "modes": "fp64,fp64_adj,fp32,fp32_adj"},
+    # the largest single-GPU DNS: 840^3 = 2^3*3*5*7 (mixed-radix FFT), FP64 and FP32 mode
+    "dns840": {"n": 840, "nu": 1.0 / 5000.0, "dt": 1e-3, "k0": 8.0, "seed": 3, "modes": "fp64,fp32"},
+}
 METRIC = "Mcell-updates/s per RK4 step (fwd, fwd+adjoint), FP32 vs FP64, % HBM peak"
 
 
@@ -118,7 +126,7 @@ def run_mode(n, nu, dt, precision, steps, warmup, u0_np, adjoint):
     from paper_2604_18536_amd import Solver
 
     s = Solver(n, nu=nu, precision=precision)
-    u0 = torch.tensor(u0_np, dtype=s.dtype, device="cuda")
+    u0 = torch.as_tensor(u0_np).to(device="cuda", dtype=s.dtype).contiguous()
     s.project(u0, out=u0)
     u1 = torch.empty_like(u0)
     ubar = torch.empty_like(u0)
@@ -165,6 +173,45 @@ def stream_copy_gbs(nbytes=2 << 30, reps=10):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
+def les_closure_timing(steps, warmup):
+    """LES with the learned closure (128^3, batch 4, FP32, nu = 1/2000, dt = 4e-3)
+    next to the 512^3 FP32 DNS step it stands in for (4 DNS steps of dt = 1e-3
+    per LES step, per field)."""
+    import torch
+
+    import synth as S
+    from paper_2604_18536_amd import Solver
+    from paper_2604_18536_amd.les import init_params
+
+    nu = 1.0 / 2000.0
+    les = Solver((128, 128, 128), nu=nu, precision="fp32", batch=4)
+    th = init_params(0)
+    th[30304:30304 + 2592].uniform_(-0.02, 0.02)  # a non-zero output layer so the closure does work
+    les.set_closure(th)
+    u = torch.stack([S.turbulence_ic_torch((128,) * 3, seed=10 + b, k0=4.0).float() for b in range(4)]).contiguous()
+    les.project(u, out=u)
+    u1 = torch.empty_like(u)
+    ubar = torch.randn_like(u)
+    g = torch.empty_like(u)
+    ms_fwd, prof_fwd = time_steps(lambda: les.step(u, 4e-3, out=u1), steps, warmup, solver=les)
+    ms_adj, _ = time_steps(lambda: (les.step(u, 4e-3, out=u1), les.step_vjp(u, ubar, 4e-3, out=g)), max(2, steps // 4), 1)
+    les.close()
+    dns = Solver((512, 512, 512), nu=nu, precision="fp32")
+    v = S.turbulence_ic_torch((512,) * 3, seed=10, k0=4.0).float().contiguous()
+    dns.project(v, out=v)
+    ms_dns, _ = time_steps(lambda: dns.step(v, 1e-3, out=v), max(2, steps // 4), 1)
+    dns.close()
+    cnn_ms = sum(t for k, (c, t) in prof_fwd.items() if k.startswith("cnn_")) / steps
+    return {
+        "workload": "LES 128^3 x batch 4, FP32, CNN closure 3-32-32-3 (bf16 MFMA), dt=4e-3; vs DNS 512^3 FP32 dt=1e-3",
+        "les_step_ms": round(ms_fwd, 3),
+        "les_closure_ms_per_step": round(cnn_ms, 3),
+        "les_step_plus_vjp_ms": round(ms_adj, 3),
+        "dns512_step_ms": round(ms_dns, 3),
+        "speedup_vs_dns_same_time_span": round(4 * 4 * ms_dns / ms_fwd, 1),
+    }
+
+
 def cpu_baseline(n, nu, dt, u0_np, budget_s=30.0):
     """The float64 numpy oracle, as written, on the host: RK4 steps of the same field."""
     import oracle as O
@@ -195,10 +242,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--config", default="turb256", choices=sorted(CONFIGS))
+    ap.add_argument("--n", type=int, default=None, help="override the grid size of the config")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--modes", default="fp64,fp64_adj,fp32,fp32_adj")
+    ap.add_argument("--no-les", action="store_true", help="skip the closure-LES step timing")
+    ap.add_argument("--modes", default=None)
     args = ap.parse_args()
+    cfg = dict(CONFIGS[args.config])
+    if args.n is not None:
+        cfg["n"] = args.n
+    if args.modes is None:
+        args.modes = cfg["modes"]
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); multi-GPU runs are not part "
               "of this build.", file=sys.stderr)
@@ -213,10 +267,14 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
-    n = (args.n,) * 3
-    nu, dt = 1.0 / 1600.0, 1e-3
+    n = (cfg["n"],) * 3
+    nu, dt = cfg["nu"], cfg["dt"]
     ncell = n[0] * n[1] * n[2]
-    u0 = S.turbulence_ic(n, seed=0, k0=4.0)
+    if cfg["n"] <= 256:
+        u0 = S.turbulence_ic(n, seed=cfg["seed"], k0=cfg["k0"])
+    else:  # too large for numpy in reasonable time: same construction on the GPU
+        u0 = S.turbulence_ic_torch(n, seed=cfg["seed"], k0=cfg["k0"], device="cuda")
+        args.no_cpu = True
     print(f"[bench] initial field ready {n}", file=sys.stderr, flush=True)
 
     copy_gbs = stream_copy_gbs()
@@ -272,6 +330,7 @@ def main():
         "avg_ms": kprof[dom]["avg_ms"],
     }
     cpu = None if args.no_cpu else cpu_baseline(n, nu, dt, u0)
+    les = None if args.no_les or args.config != "turb256" else les_closure_timing(args.steps, args.warmup)
     ms = modes[main_mode]["ms_per_step"]
     line = {
         "metric": METRIC,
@@ -287,14 +346,15 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"3D periodic decaying turbulence {n[0]}^3 staggered grid, nu=1/1600, dt=1e-3, "
-                        "E(k)~k^4 exp(-2(k/4)^2), unit KE; float64 RK4 step",
+            "workload": f"3D periodic decaying turbulence {n[0]}^3 staggered grid, nu=1/{round(1 / nu)}, dt={dt}, "
+                        f"E(k)~k^4 exp(-2(k/{cfg['k0']:g})^2), unit KE; {main_mode} RK4 step",
             "grid": list(n),
             "nu": nu,
             "dt": dt,
         },
         "roofline": roofline,
         "stream_copy_gbs": round(copy_gbs, 1),
+        "les_closure": les,
         "cpu_baseline": cpu,
         "modes": modes,
         "kernels": kernels,

@@ -190,3 +190,30 @@ def step_rk4_closure_vjp(u0, u1bar, h, nu, dt, theta):
 
     u0bar = ins.step_rk4_vjp(u0, u1bar, h, nu, dt, rhs_fn=lambda v: rhs_with_closure(v, h, nu, theta), rhs_vjp_fn=gv)
     return u0bar, tbar
+
+
+def rollout_loss_closure(u0, refs, h, nu, dt, theta):
+    """(1/S) sum_s mean((u_s - refs[s-1])^2) for the closure-coupled step."""
+    S = len(refs)
+    u = np.array(u0, dtype=np.float64)
+    total = 0.0
+    for s in range(S):
+        u = step_rk4_closure(u, h, nu, dt, theta)
+        total += float(np.mean((u - refs[s]) ** 2)) / S
+    return total
+
+
+def rollout_loss_closure_grad(u0, refs, h, nu, dt, theta):
+    """(dL/du0, dL/dtheta) by reverse accumulation over the steps (Sec. 3.4 back-propagation)."""
+    S = len(refs)
+    states = [np.array(u0, dtype=np.float64)]
+    for s in range(S):
+        states.append(step_rk4_closure(states[-1], h, nu, dt, theta))
+    m = states[0].size
+    ubar = np.zeros_like(states[0])
+    tbar = np.zeros(n_params())
+    for s in range(S, 0, -1):
+        ubar = ubar + 2.0 * (states[s] - refs[s - 1]) / (m * S)
+        ubar, tb = step_rk4_closure_vjp(states[s - 1], ubar, h, nu, dt, theta)
+        tbar += tb
+    return ubar, tbar

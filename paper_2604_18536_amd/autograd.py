@@ -53,8 +53,29 @@ class _Project(torch.autograd.Function):
         return ctx.solver.project_vjp(ubar.contiguous()), None
 
 
-def step(solver, u, dt):
-    """One differentiable RK4 step."""
+class _StepClosure(torch.autograd.Function):
+    """RK4 step with the closure; theta (the parameters the solver's closure was
+    set from) is an input so that autograd routes its gradient."""
+
+    @staticmethod
+    def forward(ctx, u0, theta, solver, dt):
+        ctx.solver = solver
+        ctx.dt = float(dt)
+        ctx.save_for_backward(u0)
+        return solver.step(u0.contiguous(), dt)
+
+    @staticmethod
+    def backward(ctx, u1bar):
+        (u0,) = ctx.saved_tensors
+        ctx.solver.closure_grad()  # start from an empty accumulator
+        g = ctx.solver.step_vjp(u0.contiguous(), u1bar.contiguous(), ctx.dt)
+        return g, ctx.solver.closure_grad(), None, None
+
+
+def step(solver, u, dt, theta=None):
+    """One differentiable RK4 step (with the closure when theta is given)."""
+    if theta is not None:
+        return _StepClosure.apply(u, theta, solver, dt)
     return _Step.apply(u, solver, dt)
 
 
@@ -78,13 +99,15 @@ def rollout(solver, u0, dt, nsteps):
     return out
 
 
-def rollout_loss(solver, u0, dt, refs, checkpoint_every=10, per_step_loss=None):
+def rollout_loss(solver, u0, dt, refs, checkpoint_every=10, per_step_loss=None, theta=None):
     """Sum over s = 1..len(refs) of per_step_loss(u_s, refs[s-1]), differentiable in u0.
 
     Default per-step loss: mean over cells and components of (u_s - ref_s)^2,
     divided by the number of steps (so the total is the trajectory MSE).
     Only the state at the start of every segment of ``checkpoint_every`` steps
-    is kept; each segment is recomputed in the backward pass.
+    is kept; each segment is recomputed in the backward pass. With ``theta``
+    (the closure parameters the solver was set with) the loss is also
+    differentiable in theta.
     """
     nsteps = len(refs)
     if per_step_loss is None:
@@ -95,7 +118,7 @@ def rollout_loss(solver, u0, dt, refs, checkpoint_every=10, per_step_loss=None):
     def segment(u, s0, s1):
         total = u.new_zeros(())
         for s in range(s0, s1):
-            u = step(solver, u, dt)
+            u = step(solver, u, dt, theta)
             total = total + per_step_loss(u, refs[s])
         return u, total
 

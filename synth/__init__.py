@@ -21,6 +21,7 @@ import math
 import numpy as np
 
 __all__ = [
+    "turbulence_ic_torch",
     "spacing",
     "face_coords",
     "taylor_green_2d",
@@ -177,3 +178,63 @@ def turbulence_ic(n, seed, k0=4.0, energy=1.0):
     ke = 0.5 * np.mean(np.sum(u * u, axis=0))
     u *= math.sqrt(energy / ke)
     return u
+
+
+def turbulence_ic_torch(n, seed, k0=4.0, energy=1.0, device="cuda", dtype=None):
+    """``turbulence_ic`` built on the GPU with torch (for grids too large for numpy).
+
+    Same construction (staggered curl of a potential with spectral amplitude
+    sqrt(E(|k|)/S_d(|k|))/|k|, then scaling to the mean kinetic energy), but the
+    white noise comes from torch's seeded generator, so the field differs from
+    ``turbulence_ic`` for the same seed. Returns a float64 (or ``dtype``) tensor
+    of shape (d, *reversed(n)).
+    """
+    import torch
+
+    n = tuple(int(v) for v in n)
+    d = len(n)
+    dtype = torch.float64 if dtype is None else dtype
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    h = spacing(n)
+    shape = tuple(reversed(n))
+    # wavenumbers on the half spectrum of the last (x) axis
+    kk = torch.zeros((), dtype=torch.float64, device=device)
+    for b in range(d):
+        ax = d - 1 - b
+        if b == 0:
+            k = torch.fft.rfftfreq(n[0], 1.0 / n[0], dtype=torch.float64, device=device)
+        else:
+            k = torch.fft.fftfreq(n[b], 1.0 / n[b], dtype=torch.float64, device=device)
+        s = [1] * d
+        s[ax] = k.numel()
+        kk = kk + (k * k).reshape(s)
+    kmag = torch.sqrt(kk)
+    shell = 2 * math.pi * kmag if d == 2 else 4 * math.pi * kmag ** 2
+    e = kmag ** 4 * torch.exp(-2.0 * (kmag / k0) ** 2)
+    amp = torch.where(kmag > 0, torch.sqrt(e / torch.where(shell > 0, shell, 1.0)) / torch.where(kmag > 0, kmag, 1.0),
+                      torch.zeros_like(kmag))
+
+    def noise_field():
+        w = torch.randn(shape, generator=gen, dtype=torch.float64, device=device)
+        return torch.fft.irfftn(torch.fft.rfftn(w) * amp, s=shape)
+
+    def back(f, b):
+        return torch.roll(f, 1, dims=d - 1 - b)
+
+    u = torch.empty((d,) + shape, dtype=torch.float64, device=device)
+    if d == 2:
+        psi = noise_field()
+        u[0] = (psi - back(psi, 1)) / h[1]
+        u[1] = -(psi - back(psi, 0)) / h[0]
+    else:
+        ax_ = noise_field()
+        ay_ = noise_field()
+        az_ = noise_field()
+        u[0] = (az_ - back(az_, 1)) / h[1] - (ay_ - back(ay_, 2)) / h[2]
+        u[1] = (ax_ - back(ax_, 2)) / h[2] - (az_ - back(az_, 0)) / h[0]
+        u[2] = (ay_ - back(ay_, 0)) / h[0] - (ax_ - back(ax_, 1)) / h[1]
+        del ax_, ay_, az_
+    ke = 0.5 * (u * u).sum(0).mean()
+    u *= torch.sqrt(energy / ke)
+    return u.to(dtype)
