@@ -194,8 +194,15 @@ def les_closure_timing(steps, warmup):
     ubar = torch.randn_like(u)
     g = torch.empty_like(u)
     ms_fwd, prof_fwd = time_steps(lambda: les.step(u, 4e-3, out=u1), steps, warmup, solver=les)
-    ms_adj, _ = time_steps(lambda: (les.step(u, 4e-3, out=u1), les.step_vjp(u, ubar, 4e-3, out=g)), max(2, steps // 4), 1)
+    nadj = max(2, steps // 4)
+    ms_adj, prof_adj = time_steps(lambda: (les.step(u, 4e-3, out=u1), les.step_vjp(u, ubar, 4e-3, out=g)), nadj, 1,
+                                  solver=les)
     les.close()
+    ncl = 4 * 128 ** 3
+    conv2 = prof_fwd.get("cnn_conv2")
+    conv2_ms = conv2[1] / conv2[0] if conv2 else None
+    cnn_kernels = {k: {"avg_ms": round(t / c, 4), "per_step": round(c / nadj, 2)}
+                   for k, (c, t) in prof_adj.items() if k.startswith("cnn_")}
     dns = Solver((512, 512, 512), nu=nu, precision="fp32")
     v = S.turbulence_ic_torch((512,) * 3, seed=10, k0=4.0).float().contiguous()
     dns.project(v, out=v)
@@ -209,6 +216,11 @@ def les_closure_timing(steps, warmup):
         "les_step_plus_vjp_ms": round(ms_adj, 3),
         "dns512_step_ms": round(ms_dns, 3),
         "speedup_vs_dns_same_time_span": round(4 * 4 * ms_dns / ms_fwd, 1),
+        # layer 2 (32 -> 32, 3x3x3) is the MFMA-bound contraction: 2 * 864 * 32 flop per cell
+        "conv2_mfma": None if conv2_ms is None else {
+            "bound": "mfma", "achieved": round(2 * 864 * 32 * ncl / (conv2_ms * 1e-3) / 1e12, 1),
+            "peak": 2500.0, "unit": "TFLOP/s", "avg_ms": round(conv2_ms, 4)},
+        "cnn_kernels_fwd_and_vjp": cnn_kernels,
     }
 
 

@@ -34,6 +34,7 @@ struct FftPlan {
     int tw_off[kMaxStages];  // offset of stage s twiddles: p*(R-1) entries
     const cd* tw;            // device twiddle table (float64, forward sign)
     int vm;                  // complex values a thread holds per stage (8 or 16)
+    int pad;                 // LDS line-stride padding (0 or 1)
 };
 
 // Which FFT pass shape a launch uses.

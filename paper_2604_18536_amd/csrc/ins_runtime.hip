@@ -83,10 +83,10 @@ void build_twiddles(int n, const std::vector<int>& rad, std::vector<cd>& tw, ins
 }
 
 // Largest power-of-two line batch (<= maxl) whose every stage fits the
-// per-thread register budget vm and whose padded lines fit the LDS budget.
-int lines_for(const ins::FftPlan& pl, int maxl, int vm) {
+// per-thread register budget vm and whose lines (stride nl + pad) fit the LDS budget.
+int lines_for(const ins::FftPlan& pl, int maxl, int vm, int pad) {
     for (int nl = maxl; nl >= 1; nl >>= 1) {
-        if (static_cast<size_t>(nl + 1) * pl.n * sizeof(cd) > kMaxLds) continue;
+        if (static_cast<size_t>(nl + pad) * pl.n * sizeof(cd) > kMaxLds) continue;
         bool ok = true;
         for (int s = 0; s < pl.nst; ++s) {
             const int R = pl.rad[s];
@@ -104,15 +104,21 @@ int lines_for(const ins::FftPlan& pl, int maxl, int vm) {
 }
 
 // Pick the register budget (8 complex values per thread keeps occupancy high)
-// unless it would force batches of fewer than `want` lines.
+// unless it would force batches of fewer than `want` lines, then the widest
+// batch, padding the LDS stride when that does not narrow the batch.
 int choose_lines(ins::FftPlan& pl, int maxl, int want) {
-    const int l8 = lines_for(pl, maxl, 8);
-    if (l8 >= 0 && (1 << l8) >= want) {
-        pl.vm = 8;
-        return l8;
+    int best = -1;
+    for (int vm : {8, 16}) {
+        const int lp = lines_for(pl, maxl, vm, 1);
+        const int l0 = lines_for(pl, maxl, vm, 0);
+        const int l = std::max(lp, l0);
+        if (l < 0) continue;
+        pl.vm = vm;
+        pl.pad = lp >= l0 ? 1 : 0;
+        best = l;
+        if ((1 << l) >= want) break;
     }
-    pl.vm = 16;
-    return lines_for(pl, maxl, 16);
+    return best;
 }
 
 struct Pending {

@@ -37,20 +37,29 @@ __device__ __forceinline__ float gelu_grad_f(float z) {
     return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
 }
 
-// Periodic neighbour of linear cell `cell` (x fastest) shifted by (dx, dy, dz).
-__device__ __forceinline__ int64_t shifted_cell(const Grid& g, int64_t cell, int dx, int dy, int dz) {
-    const int64_t plane = int64_t(g.nx) * g.ny;
-    const int64_t vol = plane * g.nz;
-    const int64_t b = cell / vol;
-    const int64_t r = cell - b * vol;
-    int z = int(r / plane), y = int((r / g.nx) % g.ny), x = int(r % g.nx);
-    x += dx;
-    x += x < 0 ? g.nx : (x >= g.nx ? -g.nx : 0);
-    y += dy;
-    y += y < 0 ? g.ny : (y >= g.ny ? -g.ny : 0);
-    z += dz;
-    z += z < 0 ? g.nz : (z >= g.nz ? -g.nz : 0);
-    return b * vol + (int64_t(z) * g.ny + y) * g.nx + x;
+// A run of cells inside one x-row (n_x is a multiple of 32, so a 16-cell tile or
+// a 32-cell strip never straddles rows): its row coordinates, in 32-bit
+// arithmetic (the closure requires fewer than 2^31 cells in the batch).
+struct RowPos {
+    int x0, y, z, b;
+};
+
+__device__ __forceinline__ RowPos row_of(const Grid& g, int first_cell) {
+    RowPos r;
+    const int row = first_cell / g.nx;
+    r.x0 = first_cell - row * g.nx;
+    r.y = row % g.ny;
+    const int zb = row / g.ny;
+    r.z = zb % g.nz;
+    r.b = zb / g.nz;
+    return r;
+}
+
+__device__ __forceinline__ int wrapi(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// First cell of the row shifted by (dy, dz) with periodic wrap.
+__device__ __forceinline__ int row_start(const Grid& g, const RowPos& r, int dy, int dz) {
+    return ((r.b * g.nz + wrapi(r.z + dz, g.nz)) * g.ny + wrapi(r.y + dy, g.ny)) * g.nx;
 }
 
 // K tile kt, lane group gq: which tap and which first channel the lane's 8 operands hold.
@@ -101,17 +110,25 @@ __global__ __launch_bounds__(kBlock) void k_conv(Grid g, int64_t ncells, const u
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-        int64_t cell[MT];
+        RowPos rp[MT];
+        int xs[MT][3];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
-            const int64_t c = base + mt * 16 + lm;
-            cell[mt] = c < ncells ? c : ncells - 1;
+            int c = int(base) + mt * 16;
+            c = c < ncells ? c : int(ncells) - 16;  // a tail tile reads valid cells; its results are not stored
+            rp[mt] = row_of(g, c);
+            const int x = rp[mt].x0 + lm;
+            xs[mt][0] = wrapi(x - 1, g.nx);
+            xs[mt][1] = x;
+            xs[mt][2] = wrapi(x + 1, g.nx);
         }
+#pragma unroll 3
         for (int kt = 0; kt < NKT; ++kt) {
             int tap, c0;
             ktile_tap<CIN>(kt, gq, tap, c0);
             const bool tap_ok = tap < kTaps;
-            const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+            const int t = tap_ok ? tap : 0;
+            const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dxi = t % 3;
             bf16x8 bv[NT];
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt)
@@ -120,8 +137,8 @@ __global__ __launch_bounds__(kBlock) void k_conv(Grid g, int64_t ncells, const u
             for (int mt = 0; mt < MT; ++mt) {
                 bf16x8 av;
                 if (tap_ok) {
-                    const int64_t nc = shifted_cell(g, cell[mt], dx, dy, dz);
-                    av = *reinterpret_cast<const bf16x8*>(in + nc * CIN + c0);
+                    const int nc = row_start(g, rp[mt], dy, dz) + xs[mt][dxi];
+                    av = *reinterpret_cast<const bf16x8*>(in + int64_t(nc) * CIN + c0);
                 } else {
 #pragma unroll
                     for (int j = 0; j < 8; ++j) av[j] = __bf16(0.0f);
@@ -255,28 +272,40 @@ __global__ __launch_bounds__(kBlock) void k_wgrad(Grid g, int64_t ncells, const 
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt) acc[r][d][mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
     float bacc = 0.f;  // bias partial for channel tid (tid < COUTP)
+    // padding rows (output channels >= COUTP, input channels >= CIN) stay zero
+    if constexpr (MT * 16 > COUTP) {
+        constexpr int PN = MT * 16 - COUTP;
+        for (int e = tid; e < 3 * PN * 32; e += kBlock) gt[e / (PN * 32)][COUTP + (e / 32) % PN][e % 32] = 0;
+    }
+    if constexpr (NT * 16 > CIN) {
+        constexpr int PC = NT * 16 - CIN;
+        for (int e = tid; e < 9 * PC * 32; e += kBlock) xt[e / (PC * 32)][CIN + (e / 32) % PC][e % 32] = 0;
+    }
     const int64_t nstrip = ncells / 32;
     for (int64_t s = blockIdx.x; s < nstrip; s += gridDim.x) {
-        const int64_t q0 = s * 32;
+        const int q0 = int(s) * 32;
+        const RowPos rp = row_of(g, q0);
         __syncthreads();
-        // gt: 3 shifted copies x 32 q x COUTP channels
-        for (int e = tid; e < 3 * 32 * COUTP; e += kBlock) {
-            const int n = e % COUTP, q = (e / COUTP) % 32, d = e / (32 * COUTP);
-            const int64_t p = shifted_cell(g, q0 + q, -(d - 1), 0, 0);  // g at q - dx, dx = d - 1
-            gt[d][n][q] = gin[p * GC + n];
+        // gt[d][n][q] = g[q - dx][n], dx = d - 1: 8 channels per 16-byte load
+        constexpr int G8 = COUTP / 8;
+        const int rs0 = row_start(g, rp, 0, 0);
+        for (int e = tid; e < 3 * 32 * G8; e += kBlock) {
+            const int j8 = e % G8, q = (e / G8) % 32, d = e / (32 * G8);
+            const int p = rs0 + wrapi(rp.x0 + q - (d - 1), g.nx);
+            const uint4 v = *reinterpret_cast<const uint4*>(gin + int64_t(p) * GC + 8 * j8);
+            const unsigned w4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int i = 0; i < 8; ++i) gt[d][8 * j8 + i][q] = u16((w4[i >> 1] >> ((i & 1) * 16)) & 0xffffu);
         }
-        for (int e = tid; e < 3 * 32 * (MT * 16 - COUTP); e += kBlock) {
-            const int n = COUTP + e % (MT * 16 - COUTP), q = (e / (MT * 16 - COUTP)) % 32,
-                      d = e / (32 * (MT * 16 - COUTP));
-            gt[d][n][q] = 0;
-        }
-        // xt: 9 rows x 32 q x CIN channels (channels past CIN up to 16*NT are zero)
-        for (int e = tid; e < 9 * 32 * NT * 16; e += kBlock) {
-            const int c = e % (NT * 16), q = (e / (NT * 16)) % 32, row = e / (32 * NT * 16);
-            const int dy = row % 3 - 1, dz = row / 3 - 1;
-            u16 v = 0;
-            if (c < CIN) v = xin[shifted_cell(g, q0 + q, 0, dy, dz) * CIN + c];
-            xt[row][c][q] = v;
+        // xt[row][c][q] = x[q + (0, dy, dz)][c]
+        constexpr int C8 = CIN / 8;
+        for (int e = tid; e < 9 * 32 * C8; e += kBlock) {
+            const int c8 = e % C8, q = (e / C8) % 32, row = e / (32 * C8);
+            const int p = row_start(g, rp, row % 3 - 1, row / 3 - 1) + rp.x0 + q;
+            const uint4 v = *reinterpret_cast<const uint4*>(xin + int64_t(p) * CIN + 8 * c8);
+            const unsigned w4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int i = 0; i < 8; ++i) xt[row][8 * c8 + i][q] = u16((w4[i >> 1] >> ((i & 1) * 16)) & 0xffffu);
         }
         __syncthreads();
         if (tid < COUTP) {

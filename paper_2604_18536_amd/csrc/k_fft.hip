@@ -19,8 +19,9 @@
 namespace ins {
 
 // LDS layout of a batch of `nl` lines of length N: element j of line l lives at
-// lds[j * ls + l] with the padded line stride ls = nl + 1 (odd), so that
-// neighbouring elements of one line fall in different banks.
+// lds[j * ls + l] with the line stride ls = nl + pad. The plan pads (pad = 1,
+// an odd stride, so neighbouring elements of one line fall in different banks)
+// whenever the padded batch still fits the LDS budget.
 
 // cos(2 pi j / R), sin(2 pi j / R), correctly rounded.
 __device__ __forceinline__ constexpr double kcos(int R, int j) {
@@ -129,10 +130,9 @@ __device__ __forceinline__ void dft(cd* v) {
 // elements i + q N/R, multiplies by exp(SIGN 2 pi i q k / (p R)) with k = i mod p,
 // applies DFT_R and writes elements (i - k) R + k + q p.
 template <int R, int SIGN, int VM>
-__device__ __forceinline__ void fft_stage(cd* __restrict__ lds, int lnl, int N, int p, const cd* __restrict__ tw) {
+__device__ __forceinline__ void fft_stage(cd* __restrict__ lds, int lnl, int ls, int N, int p, const cd* __restrict__ tw) {
     constexpr int BMAX = VM / R > 0 ? VM / R : 1;
     const int nl = 1 << lnl;
-    const int ls = nl + 1;
     const int s = N / R;
     const int nb = s << lnl;
     cd v[BMAX][R];
@@ -169,17 +169,18 @@ __device__ __forceinline__ void fft_stage(cd* __restrict__ lds, int lnl, int N, 
 // Full FFT of the lines in LDS; the caller has synchronised after filling LDS.
 template <int SIGN, int VM>
 __device__ void fft_lines(cd* lds, int lnl, const FftPlan& P) {
+    const int ls = (1 << lnl) + P.pad;
     int p = 1;
     for (int st = 0; st < P.nst; ++st) {
         const int R = P.rad[st];
         const cd* tw = P.tw + P.tw_off[st];
         switch (R) {
-            case 8: fft_stage<8, SIGN, VM>(lds, lnl, P.n, p, tw); break;
-            case 7: fft_stage<7, SIGN, VM>(lds, lnl, P.n, p, tw); break;
-            case 5: fft_stage<5, SIGN, VM>(lds, lnl, P.n, p, tw); break;
-            case 4: fft_stage<4, SIGN, VM>(lds, lnl, P.n, p, tw); break;
-            case 3: fft_stage<3, SIGN, VM>(lds, lnl, P.n, p, tw); break;
-            default: fft_stage<2, SIGN, VM>(lds, lnl, P.n, p, tw); break;
+            case 8: fft_stage<8, SIGN, VM>(lds, lnl, ls, P.n, p, tw); break;
+            case 7: fft_stage<7, SIGN, VM>(lds, lnl, ls, P.n, p, tw); break;
+            case 5: fft_stage<5, SIGN, VM>(lds, lnl, ls, P.n, p, tw); break;
+            case 4: fft_stage<4, SIGN, VM>(lds, lnl, ls, P.n, p, tw); break;
+            case 3: fft_stage<3, SIGN, VM>(lds, lnl, ls, P.n, p, tw); break;
+            default: fft_stage<2, SIGN, VM>(lds, lnl, ls, P.n, p, tw); break;
         }
         p *= R;
     }
@@ -243,7 +244,7 @@ __global__ __launch_bounds__(kBlock) void k_fft_x_fwd(Grid g, const T* __restric
                 val = {double(src[2 * m]), double(src[2 * m + 1])};
             }
         }
-        lds[m * (nl + 1) + l] = val;
+        lds[m * (nl + P.pad) + l] = val;
     }
     __syncthreads();
     fft_lines<-1, VM>(lds, lnl, P);
@@ -252,8 +253,8 @@ __global__ __launch_bounds__(kBlock) void k_fft_x_fwd(Grid g, const T* __restric
         const int l = t / M1, k = t - l * M1;
         const int row = row0 + l;
         if (row >= nrows) continue;
-        const cd zk = lds[(k == M ? 0 : k) * (nl + 1) + l];
-        const cd zc = cconj(lds[(k == 0 ? 0 : M - k) * (nl + 1) + l]);
+        const cd zk = lds[(k == M ? 0 : k) * (nl + P.pad) + l];
+        const cd zc = cconj(lds[(k == 0 ? 0 : M - k) * (nl + P.pad) + l]);
         const cd e = cscale(cadd(zk, zc), 0.5);
         const cd dd = csub(zk, zc);
         const cd o = {0.5 * dd.y, -0.5 * dd.x};
@@ -284,7 +285,7 @@ __global__ __launch_bounds__(kBlock) void k_fft_x_inv(Grid g, const cd* __restri
             const cd o = cmulc(csub(xk, xc), post[k]);
             z = {e.x - o.y, e.y + o.x};
         }
-        lds[k * (nl + 1) + l] = z;
+        lds[k * (nl + P.pad) + l] = z;
     }
     __syncthreads();
     fft_lines<1, VM>(lds, lnl, P);
@@ -292,7 +293,7 @@ __global__ __launch_bounds__(kBlock) void k_fft_x_inv(Grid g, const cd* __restri
         const int l = t / M, m = t - l * M;
         const int row = row0 + l;
         if (row >= nrows) continue;
-        reinterpret_cast<cd*>(p + int64_t(row) * g.nx)[m] = lds[m * (nl + 1) + l];
+        reinterpret_cast<cd*>(p + int64_t(row) * g.nx)[m] = lds[m * (nl + P.pad) + l];
     }
 }
 
@@ -325,7 +326,7 @@ __global__ __launch_bounds__(kBlock) void k_fft_strided(Grid g, cd* __restrict__
     const int kx0 = chunk << lnl;
     base += kx0;
     const int ntot = N << lnl;
-    const int ls = nl + 1;
+    const int ls = nl + P.pad;
     for (int t = threadIdx.x; t < ntot; t += kBlock) {
         const int c = t & (nl - 1), j = t >> lnl;
         lds[j * ls + c] = (kx0 + c < nxh) ? spec[base + j * stride + c] : cd{0.0, 0.0};
@@ -371,7 +372,7 @@ hipError_t launch_fft_x_fwd(const Grid& g, const T* vel, const double* r, cd* sp
     const int nl = 1 << lnl;
     const int nrows = g.batch * g.nz * g.ny;
     const int nblk = (nrows + nl - 1) / nl;
-    const size_t shm = size_t(nl + 1) * px.n * sizeof(cd);
+    const size_t shm = size_t(nl + px.pad) * px.n * sizeof(cd);
 #define INS_XF(D, SRC, VM) \
     hipLaunchKernelGGL((k_fft_x_fwd<T, D, SRC, VM>), dim3(nblk), dim3(kBlock), shm, s, g, vel, r, spec, px, post, lnl, comp)
 #define INS_XF_VM(D, SRC) \
@@ -393,7 +394,7 @@ hipError_t launch_fft_x_inv(const Grid& g, const cd* spec, double* p, const FftP
     const int nl = 1 << lnl;
     const int nrows = g.batch * g.nz * g.ny;
     const int nblk = (nrows + nl - 1) / nl;
-    const size_t shm = size_t(nl + 1) * px.n * sizeof(cd);
+    const size_t shm = size_t(nl + px.pad) * px.n * sizeof(cd);
     if (px.vm == 8)
         hipLaunchKernelGGL(k_fft_x_inv<8>, dim3(nblk), dim3(kBlock), shm, s, g, spec, p, px, post, lnl);
     else
@@ -408,7 +409,7 @@ hipError_t launch_fft_strided(const Grid& g, cd* spec, const FftPlan& pl, int ax
     const int nchunk = (nxh + nl - 1) / nl;
     const int nouter = axis == 1 ? g.batch * g.nz : g.batch * g.ny;
     const int nblk = nchunk * nouter;
-    const size_t shm = size_t(nl + 1) * pl.n * sizeof(cd);
+    const size_t shm = size_t(nl + pl.pad) * pl.n * sizeof(cd);
 #define INS_ST(MODE, VM) \
     hipLaunchKernelGGL((k_fft_strided<MODE, VM>), dim3(nblk), dim3(kBlock), shm, s, g, spec, pl, axis, lnl, st)
 #define INS_ST_VM(MODE) \

@@ -121,6 +121,19 @@ __global__ __launch_bounds__(kBlock) void k_stage_zm(Grid g, const T* __restrict
     // Pipeline: iteration k computes plane z0+k-2 from ring slots k-2, k-1, k
     // while the loads of plane k+1 are in flight; they land in slot k+1, which
     // no thread reads during iteration k.
+    // pointwise streams of the plane to be computed next, loaded one plane ahead
+    T base[3], yv[3];
+    auto fetch_point = [&](int z) {
+        if (!valid) return;
+        const int c0 = z * plane + cyg * nx + cxg;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int64_t kk = boff + int64_t(a) * nc + c0;
+            base[a] = (wout || yinit) ? ld_stream(u0 + kk) : T(0);
+            yv[a] = (y && !yinit) ? ld_stream(y + kk) : base[a];
+        }
+    };
+
     const int nk = (z1 - z0) + 2;
     fetch(pmod(z0 - 1, nz));
     park(0);
@@ -128,20 +141,21 @@ __global__ __launch_bounds__(kBlock) void k_stage_zm(Grid g, const T* __restrict
     park(1);
     if (nk > 2) fetch(pmod(z0 + 1, nz));
     park(2);
+    fetch_point(z0);
     __syncthreads();
     for (int k = 2; k < nk; ++k) {
         const int z = z0 + k - 2;
         const bool more = k + 1 < nk;
         if (more) fetch(pmod(z0 - 1 + k + 1, nz));
+        T cb[3], cyv[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            cb[a] = base[a];
+            cyv[a] = yv[a];
+        }
+        if (more) fetch_point(z + 1);
         if (valid) {
             const int c0 = z * plane + cyg * nx + cxg;
-            T base[3], yv[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const int64_t kk = boff + int64_t(a) * nc + c0;
-                base[a] = (wout || yinit) ? ld_stream(u0 + kk) : T(0);
-                yv[a] = (y && !yinit) ? ld_stream(y + kk) : base[a];
-            }
             LdsSrc<T> U{&ring[(k - 2) & 3][0][0], &ring[(k - 1) & 3][0][0], &ring[k & 3][0][0], centre};
             T F[3];
             rhs_cell<T, 3>(g, U, Nb{}, F);
@@ -149,8 +163,8 @@ __global__ __launch_bounds__(kBlock) void k_stage_zm(Grid g, const T* __restrict
             for (int a = 0; a < 3; ++a) {
                 const int64_t kk = boff + int64_t(a) * nc + c0;
                 if (mc) F[a] += mc[kk];
-                if (y) st_stream(yv[a] + cy * F[a], y + kk);
-                if (wout) st_stream(base[a] + cw * F[a], wout + kk);
+                if (y) st_stream(cyv[a] + cy * F[a], y + kk);
+                if (wout) st_stream(cb[a] + cw * F[a], wout + kk);
             }
         }
         if (more) park(k + 1);

@@ -26,15 +26,13 @@ CSRC = os.path.join(ROOT, "paper_2604_18536_amd", "csrc")
 
 # template instance (prefix of the demangled name) -> (variant names in dispatch order, source files)
 VARIANT_ORDER = {
-    "void ins::k_stage<double, 3, true>": (["stage", "stage", "stage_last"], ["k_stencil.hip", "k_common.hpp"]),
-    "void ins::k_stage<double, 3, false>": (["stage_first"], ["k_stencil.hip", "k_common.hpp"]),
     "void ins::k_stage_zm<double, true>": (["stage", "stage", "stage_last"], ["k_stage3d.hip", "k_common.hpp"]),
     "void ins::k_stage_zm<double, false>": (["stage_first"], ["k_stage3d.hip", "k_common.hpp"]),
-    "void ins::k_fft_x_fwd<double, 3, true>": (["fft_x_fwd_div"], ["k_fft.hip", "k_common.hpp"]),
-    "void ins::k_fft_strided<0>": (["fft_y_fwd"], ["k_fft.hip", "k_common.hpp"]),
-    "void ins::k_fft_strided<2>": (["fft_z_solve"], ["k_fft.hip", "k_common.hpp"]),
-    "void ins::k_fft_strided<1>": (["fft_y_inv"], ["k_fft.hip", "k_common.hpp"]),
-    "ins::k_fft_x_inv": (["fft_x_inv"], ["k_fft.hip", "k_common.hpp"]),
+    "void ins::k_fft_x_fwd<double, 3, 0,": (["fft_x_fwd_div"], ["k_fft.hip", "k_common.hpp"]),
+    "void ins::k_fft_strided<0,": (["fft_y_fwd"], ["k_fft.hip", "k_common.hpp"]),
+    "void ins::k_fft_strided<2,": (["fft_z_solve"], ["k_fft.hip", "k_common.hpp"]),
+    "void ins::k_fft_strided<1,": (["fft_y_inv"], ["k_fft.hip", "k_common.hpp"]),
+    "void ins::k_fft_x_inv<": (["fft_x_inv"], ["k_fft.hip", "k_common.hpp"]),
     "void ins::k_apply_projection<double, 3>": (["apply_projection"], ["k_stencil.hip", "k_common.hpp"]),
 }
 COPY = "ins::k_stream_copy"
@@ -90,10 +88,12 @@ def traffic(fetch_csv, write_csv, out_md, command, copy_bytes=None):
     if os.path.exists(jpath):
         rec = json.load(open(jpath))
     for inst, (variants, srcs) in VARIANT_ORDER.items():
-        if inst not in f:
+        # a key is the demangled name or, for kernels templated on the FFT plan, its prefix
+        names = [k for k in f if k == inst or (inst.endswith((",", "<")) and k.startswith(inst))]
+        if not names:
             continue
-        fv = [v for _, v in f[inst]]
-        wv = [v for _, v in w.get(inst, [])]
+        fv = [v for _, v in sorted(x for k in names for x in f[k])]
+        wv = [v for _, v in sorted(x for k in names for x in w.get(k, []))]
         per = defaultdict(lambda: [0.0, 0.0, 0])
         for i in range(min(len(fv), len(wv))):
             name = variants[i % len(variants)]
@@ -101,7 +101,7 @@ def traffic(fetch_csv, write_csv, out_md, command, copy_bytes=None):
             per[name][1] += wv[i] * kw
             per[name][2] += 1
         for name, (a, b, n) in per.items():
-            lines.append(f"| `{inst.replace('void ', '')}` as {name} | {n} | {a / n / 2**20:.1f} | {b / n / 2**20:.1f} | "
+            lines.append(f"| `{names[0].replace('void ', '')}` as {name} | {n} | {a / n / 2**20:.1f} | {b / n / 2**20:.1f} | "
                          f"{(a + b) / n / 2**20:.1f} |")
             rec[name] = {"bytes_per_launch": round((a + b) / n), "fetch": round(a / n), "write": round(b / n),
                          "sources": srcs, "source_hash": source_hash(srcs)}
