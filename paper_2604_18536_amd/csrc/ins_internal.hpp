@@ -91,9 +91,11 @@ hipError_t launch_fft_x_fwd(const Grid& g, const T* vel, const double* r, cd* sp
 hipError_t launch_fft_x_inv(const Grid& g, const cd* spec, double* p, const FftPlan& px, const cd* post_tw, int lines,
                             hipStream_t s);
 // Strided C2C pass over the half spectrum. mode 0: forward, 1: inverse,
-// 2: forward + spectral divide + inverse. axis 1 = y, 2 = z.
-hipError_t launch_fft_strided(const Grid& g, cd* spec, const FftPlan& pl, int axis, int mode, int lines,
-                              const SolveTab& st, hipStream_t s);
+// 2: forward + spectral divide + inverse, the inverse running plan `rev` (the
+// same length with the radices in reverse order; unused by modes 0 and 1).
+// axis 1 = y, 2 = z.
+hipError_t launch_fft_strided(const Grid& g, cd* spec, const FftPlan& pl, const FftPlan& rev, int axis, int mode,
+                              int lines, const SolveTab& st, hipStream_t s);
 
 // Reverse-pass kernels.
 template <typename T>

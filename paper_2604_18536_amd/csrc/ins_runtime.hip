@@ -135,6 +135,7 @@ struct ins_ctx_s {
     hipStream_t stream = nullptr;
 
     ins::FftPlan px{}, py{}, pz{};
+    ins::FftPlan py_rev{}, pz_rev{};  // radices reversed: inverse half of the fused last-axis solve
     int lnl_x = 0, lnl_y = 0, lnl_z = 0;
     cd* d_tw = nullptr;
     cd* d_post = nullptr;
@@ -308,11 +309,11 @@ void poisson(ins_ctx c, const void* vel, const double* r, double* p) {
         });
     }
     if (g.dim == 3) {
-        c->launch("fft_y_fwd", [&] { return ins::launch_fft_strided(g, c->spec, c->py, 1, 0, c->lnl_y, c->st, c->stream); });
-        c->launch("fft_z_solve", [&] { return ins::launch_fft_strided(g, c->spec, c->pz, 2, 2, c->lnl_z, c->st, c->stream); });
-        c->launch("fft_y_inv", [&] { return ins::launch_fft_strided(g, c->spec, c->py, 1, 1, c->lnl_y, c->st, c->stream); });
+        c->launch("fft_y_fwd", [&] { return ins::launch_fft_strided(g, c->spec, c->py, c->py, 1, 0, c->lnl_y, c->st, c->stream); });
+        c->launch("fft_z_solve", [&] { return ins::launch_fft_strided(g, c->spec, c->pz, c->pz_rev, 2, 2, c->lnl_z, c->st, c->stream); });
+        c->launch("fft_y_inv", [&] { return ins::launch_fft_strided(g, c->spec, c->py, c->py, 1, 1, c->lnl_y, c->st, c->stream); });
     } else {
-        c->launch("fft_y_solve", [&] { return ins::launch_fft_strided(g, c->spec, c->py, 1, 2, c->lnl_y, c->st, c->stream); });
+        c->launch("fft_y_solve", [&] { return ins::launch_fft_strided(g, c->spec, c->py, c->py_rev, 1, 2, c->lnl_y, c->st, c->stream); });
     }
     c->launch("fft_x_inv", [&] { return ins::launch_fft_x_inv(g, c->spec, p, c->px, c->d_post, c->lnl_x, c->stream); });
 }
@@ -567,6 +568,15 @@ ins_status ins_create(const ins_grid* grid, ins_bc bc, double nu, ins_dtype dtyp
         c->lnl_x = choose_lines(c->px, 16, 8);
         c->lnl_y = choose_lines(c->py, 16, 8);
         c->lnl_z = d == 3 ? choose_lines(c->pz, 16, 8) : 0;
+        // the fused solve along the last axis runs its inverse with the radices
+        // reversed, so it starts from the registers the forward's last stage filled
+        ins::FftPlan& last = d == 3 ? c->pz : c->py;
+        ins::FftPlan& rev = d == 3 ? c->pz_rev : c->py_rev;
+        std::vector<int> rr(d == 3 ? rz : ry);
+        std::reverse(rr.begin(), rr.end());
+        build_twiddles(last.n, rr, tw, rev);
+        rev.vm = last.vm;
+        rev.pad = last.pad;
         if (c->lnl_x < 0 || c->lnl_y < 0 || c->lnl_z < 0) raise(INS_ERR_UNSUPPORTED, "FFT length too long");
 
         const long double two_pi = 6.283185307179586476925286766559005768L;
@@ -600,6 +610,8 @@ ins_status ins_create(const ins_grid* grid, ins_bc bc, double nu, ins_dtype dtyp
         c->px.tw = c->d_tw;
         c->py.tw = c->d_tw;
         c->pz.tw = c->d_tw;
+        c->py_rev.tw = c->d_tw;
+        c->pz_rev.tw = c->d_tw;
         for (int a = 0; a < 3; ++a) c->st.lam[a] = c->d_lam + off[a];
         c->st.inv_ncell = 1.0 / double(ncell);
 
@@ -814,9 +826,9 @@ ins_status ins_energy_spectrum(ins_ctx ctx, const void* u, double* e, int nbins)
                                                     ctx->lnl_x, ctx->stream, a);
                 });
             });
-            ctx->launch("fft_y_fwd", [&] { return ins::launch_fft_strided(g, ctx->spec, ctx->py, 1, 0, ctx->lnl_y, ctx->st, ctx->stream); });
+            ctx->launch("fft_y_fwd", [&] { return ins::launch_fft_strided(g, ctx->spec, ctx->py, ctx->py, 1, 0, ctx->lnl_y, ctx->st, ctx->stream); });
             if (g.dim == 3)
-                ctx->launch("fft_z_fwd", [&] { return ins::launch_fft_strided(g, ctx->spec, ctx->pz, 2, 0, ctx->lnl_z, ctx->st, ctx->stream); });
+                ctx->launch("fft_z_fwd", [&] { return ins::launch_fft_strided(g, ctx->spec, ctx->pz, ctx->pz, 2, 0, ctx->lnl_z, ctx->st, ctx->stream); });
             ctx->launch("spectrum_bins", [&] { return ins::launch_spectrum_bins(g, ctx->spec, e, nbins, ctx->stream); });
         }
     });

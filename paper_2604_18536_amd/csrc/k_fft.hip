@@ -18,6 +18,8 @@
 
 namespace ins {
 
+#define INS_INLINE __attribute__((always_inline))
+
 // LDS layout of a batch of `nl` lines of length N: element j of line l lives at
 // lds[j * ls + l] with the line stride ls = nl + pad. The plan pads (pad = 1,
 // an odd stride, so neighbouring elements of one line fall in different banks)
@@ -125,65 +127,190 @@ __device__ __forceinline__ void dft(cd* v) {
     else dft_odd<R, SIGN>(v);
 }
 
-// One Stockham stage over `nl` lines of length N stored element-major in LDS
-// (element j of line l at lds[j*nl + l]). Butterfly i of a line reads
-// elements i + q N/R, multiplies by exp(SIGN 2 pi i q k / (p R)) with k = i mod p,
-// applies DFT_R and writes elements (i - k) R + k + q p.
-template <int R, int SIGN, int VM>
-__device__ __forceinline__ void fft_stage(cd* __restrict__ lds, int lnl, int ls, int N, int p, const cd* __restrict__ tw) {
+// q = n / d and r = n % d for 0 <= n < 2^21 and d >= 1, given rd ~ 1/d in float
+// to within 2 ulp: the float quotient is then within one unit of the true one,
+// and one correction each way makes it exact.
+__device__ __forceinline__ int fdivmod(int n, int d, float rd, int& r) {
+    int q = static_cast<int>(static_cast<float>(n) * rd);
+    r = n - q * d;
+    if (r < 0) {
+        --q;
+        r += d;
+    }
+    if (r >= d) {
+        ++q;
+        r -= d;
+    }
+    return q;
+}
+
+// How the butterflies t = 0 .. S*nl-1 of a stage map to (line l, index i):
+// line-fast keeps neighbouring threads on neighbouring lines (contiguous in LDS
+// and, for a strided axis, in memory); element-fast keeps them on neighbouring
+// elements of one line (contiguous in memory along x).
+enum : int { kLineFast = 0, kElemFast = 1 };
+
+template <int MAP>
+__device__ __forceinline__ void slot_of(int t, int lnl, int S, float rS, int& l, int& i) {
+    if constexpr (MAP == kLineFast) {
+        l = t & ((1 << lnl) - 1);
+        i = t >> lnl;
+    } else {
+        l = fdivmod(t, S, rS, i);
+    }
+}
+
+// One Stockham stage of radix R over the nl lines of length N, p = product of
+// the earlier radices. Butterfly (l, i) takes elements i + q S (S = N / R) of
+// line l, multiplies element q by exp(SIGN 2 pi i q k / (p R)) with k = i mod p,
+// applies DFT_R and produces elements (i - k) R + k + q p. A thread runs
+// butterflies t = threadIdx.x + b kBlock, b < VM / R, in registers.
+//   IN  0: inputs from load(l, e) (global memory);  1: from LDS.
+//   OUT 0: outputs to LDS, then a barrier;
+//       1: outputs handed to sink(l, e, z) (last stage: element i + q S);
+//       2: pivot of a forward solve along this axis: every output z of the
+//          last forward stage is replaced by divf(l, e, z), and the first stage
+//          of the inverse (the same radix, p = 1, so the same butterflies) is
+//          applied at once; its outputs i R + q go to LDS when the inverse has
+//          more stages (`more`), else to sink.
+// The LDS reads of an IN 1 stage that writes LDS are followed by a barrier.
+template <int R, int SIGN, int VM, int IN, int OUT, int MAP, class Load, class Sink, class Div>
+__device__ __forceinline__ void fft_stage(cd* __restrict__ lds, int lnl, int ls, int N, int p, const cd* __restrict__ tw,
+                                          const Load& load, const Sink& sink, const Div& divf, bool more) {
     constexpr int BMAX = VM / R > 0 ? VM / R : 1;
-    const int nl = 1 << lnl;
-    const int s = N / R;
-    const int nb = s << lnl;
-    cd v[BMAX][R];
+    const int S = N / R;
+    const int nb = S << lnl;
+    const float rS = __builtin_amdgcn_rcpf(static_cast<float>(S));
+    const float rp = __builtin_amdgcn_rcpf(static_cast<float>(p));
+    cd w[BMAX * R];
 #pragma unroll
     for (int b = 0; b < BMAX; ++b) {
         const int t = threadIdx.x + b * kBlock;
         if (t < nb) {
-            const int l = t & (nl - 1), i = t >> lnl;
+            int l, i;
+            slot_of<MAP>(t, lnl, S, rS, l, i);
 #pragma unroll
-            for (int q = 0; q < R; ++q) v[b][q] = lds[(i + q * s) * ls + l];
+            for (int q = 0; q < R; ++q) {
+                if constexpr (IN == 0) w[b * R + q] = load(l, i + q * S);
+                else w[b * R + q] = lds[(i + q * S) * ls + l];
+            }
         }
     }
-    __syncthreads();
+    if constexpr (IN == 1 && OUT != 1) __syncthreads();
 #pragma unroll
     for (int b = 0; b < BMAX; ++b) {
         const int t = threadIdx.x + b * kBlock;
         if (t < nb) {
-            const int l = t & (nl - 1), i = t >> lnl;
-            const int k = i % p;
+            int l, i;
+            slot_of<MAP>(t, lnl, S, rS, l, i);
+            int k;
+            fdivmod(i, p, rp, k);
+            cd* x = w + b * R;
             if (k != 0) {
                 const cd* twk = tw + k * (R - 1) - 1;
 #pragma unroll
-                for (int q = 1; q < R; ++q) v[b][q] = SIGN < 0 ? cmul(v[b][q], twk[q]) : cmulc(v[b][q], twk[q]);
+                for (int q = 1; q < R; ++q) x[q] = SIGN < 0 ? cmul(x[q], twk[q]) : cmulc(x[q], twk[q]);
             }
-            dft<R, SIGN>(v[b]);
-            const int base = (i - k) * R + k;
+            dft<R, SIGN>(x);
+            if constexpr (OUT == 0) {
+                const int base = (i - k) * R + k;
 #pragma unroll
-            for (int q = 0; q < R; ++q) lds[(base + q * p) * ls + l] = v[b][q];
+                for (int q = 0; q < R; ++q) lds[(base + q * p) * ls + l] = x[q];
+            } else if constexpr (OUT == 1) {
+#pragma unroll
+                for (int q = 0; q < R; ++q) sink(l, i + q * S, x[q]);
+            } else {
+#pragma unroll
+                for (int q = 0; q < R; ++q) x[q] = divf(l, i + q * S, x[q]);
+                dft<R, -SIGN>(x);
+                if (more) {
+#pragma unroll
+                    for (int q = 0; q < R; ++q) lds[(i * R + q) * ls + l] = x[q];
+                } else {
+#pragma unroll
+                    for (int q = 0; q < R; ++q) sink(l, i * R + q, x[q]);
+                }
+            }
         }
     }
-    __syncthreads();
+    if constexpr (OUT == 0 || OUT == 2) {
+        if (OUT == 0 || more) __syncthreads();
+    }
 }
 
-// Full FFT of the lines in LDS; the caller has synchronised after filling LDS.
-template <int SIGN, int VM>
-__device__ void fft_lines(cd* lds, int lnl, const FftPlan& P) {
-    const int ls = (1 << lnl) + P.pad;
-    int p = 1;
-    for (int st = 0; st < P.nst; ++st) {
-        const int R = P.rad[st];
-        const cd* tw = P.tw + P.tw_off[st];
-        switch (R) {
-            case 8: fft_stage<8, SIGN, VM>(lds, lnl, ls, P.n, p, tw); break;
-            case 7: fft_stage<7, SIGN, VM>(lds, lnl, ls, P.n, p, tw); break;
-            case 5: fft_stage<5, SIGN, VM>(lds, lnl, ls, P.n, p, tw); break;
-            case 4: fft_stage<4, SIGN, VM>(lds, lnl, ls, P.n, p, tw); break;
-            case 3: fft_stage<3, SIGN, VM>(lds, lnl, ls, P.n, p, tw); break;
-            default: fft_stage<2, SIGN, VM>(lds, lnl, ls, P.n, p, tw); break;
-        }
-        p *= R;
+template <int SIGN, int VM, int IN, int OUT, int MAP, class Load, class Sink, class Div>
+__device__ __forceinline__ void fft_stage_r(int R, cd* lds, int lnl, int ls, int N, int p, const cd* tw,
+                                            const Load& load, const Sink& sink, const Div& divf, bool more) {
+    switch (R) {
+        case 8: fft_stage<8, SIGN, VM, IN, OUT, MAP>(lds, lnl, ls, N, p, tw, load, sink, divf, more); break;
+        case 7: fft_stage<7, SIGN, VM, IN, OUT, MAP>(lds, lnl, ls, N, p, tw, load, sink, divf, more); break;
+        case 5: fft_stage<5, SIGN, VM, IN, OUT, MAP>(lds, lnl, ls, N, p, tw, load, sink, divf, more); break;
+        case 4: fft_stage<4, SIGN, VM, IN, OUT, MAP>(lds, lnl, ls, N, p, tw, load, sink, divf, more); break;
+        case 3: fft_stage<3, SIGN, VM, IN, OUT, MAP>(lds, lnl, ls, N, p, tw, load, sink, divf, more); break;
+        default: fft_stage<2, SIGN, VM, IN, OUT, MAP>(lds, lnl, ls, N, p, tw, load, sink, divf, more); break;
     }
+}
+
+struct NoOp {
+    __device__ cd operator()(int, int, cd z) const { return z; }
+};
+
+// Every stage of plan P on nl = 2^lnl lines (LDS line stride ls); LDS must be
+// free on entry. The first stage reads through `load` with mapping MAP0 (IN0 0)
+// or from LDS (IN0 1); stages in between go LDS to LDS, line-fast; the last
+// stage, with mapping MAPL (a single stage uses MAP0), writes per OUTL: 0 to
+// LDS (element e of line l at lds[e ls + l], synchronised), 1 to sink, 2 as the
+// pivot of a solve whose inverse plan is Q (then call fft_inverse_rest).
+// The first and last stages are peeled off the loop so that the address
+// arithmetic of the memory-facing stages is not kept live across the others.
+template <int SIGN, int VM, int IN0, int OUTL, int MAP0, int MAPL, class Load, class Sink, class Div>
+__device__ __forceinline__ void fft_run(cd* lds, int lnl, int ls, const FftPlan& P, const Load& load, const Sink& sink,
+                                        const Div& divf, const FftPlan* Q) {
+    const int ns = P.nst;
+    const bool more = OUTL == 2 && Q->nst > 1;
+    if (ns == 1) {
+        fft_stage_r<SIGN, VM, IN0, OUTL, MAP0>(P.rad[0], lds, lnl, ls, P.n, 1, P.tw + P.tw_off[0], load, sink, divf,
+                                                more);
+        return;
+    }
+    fft_stage_r<SIGN, VM, IN0, 0, MAP0>(P.rad[0], lds, lnl, ls, P.n, 1, P.tw + P.tw_off[0], load, sink, divf, false);
+    int p = P.rad[0];
+    for (int st = 1; st < ns - 1; ++st) {
+        fft_stage_r<SIGN, VM, 1, 0, kLineFast>(P.rad[st], lds, lnl, ls, P.n, p, P.tw + P.tw_off[st], load, sink, divf,
+                                               false);
+        p *= P.rad[st];
+    }
+    fft_stage_r<SIGN, VM, 1, OUTL, MAPL>(P.rad[ns - 1], lds, lnl, ls, P.n, p, P.tw + P.tw_off[ns - 1], load, sink,
+                                         divf, more);
+}
+
+// The stages of inverse plan Q after a pivot consumed its first one (nothing
+// when Q has a single stage): LDS to LDS, the last one to sink (mapping MAPL).
+template <int SIGN, int VM, int MAPL, class Sink>
+__device__ __forceinline__ void fft_inverse_rest(cd* lds, int lnl, int ls, const FftPlan& Q, const Sink& sink) {
+    const int ns = Q.nst;
+    if (ns == 1) return;
+    const NoOp nop;
+    int p = Q.rad[0];
+    for (int st = 1; st < ns - 1; ++st) {
+        fft_stage_r<SIGN, VM, 1, 0, kLineFast>(Q.rad[st], lds, lnl, ls, Q.n, p, Q.tw + Q.tw_off[st], nop, sink, nop,
+                                               false);
+        p *= Q.rad[st];
+    }
+    fft_stage_r<SIGN, VM, 1, 1, MAPL>(Q.rad[ns - 1], lds, lnl, ls, Q.n, p, Q.tw + Q.tw_off[ns - 1], nop, sink, nop,
+                                      false);
+}
+
+// Two consecutive values of a row (x even), as one load.
+__device__ __forceinline__ void ld_pair(const double* p, double& a, double& b) {
+    const double2 t = *reinterpret_cast<const double2*>(p);
+    a = t.x;
+    b = t.y;
+}
+__device__ __forceinline__ void ld_pair(const float* p, double& a, double& b) {
+    const float2 t = *reinterpret_cast<const float2*>(p);
+    a = t.x;
+    b = t.y;
 }
 
 // ----------------------------------------------------------------------------
@@ -193,68 +320,71 @@ __device__ void fft_lines(cd* lds, int lnl, const FftPlan& P) {
 // ----------------------------------------------------------------------------
 // SRC 0: rows are the divergence of the velocity field `vel`;
 // SRC 1: rows of the float64 scalar field r; SRC 2: rows of component `comp` of vel.
+// The first stage reads its inputs straight from memory (element-fast); the
+// untangling needs Z[k] and Z[M-k] together, so the last stage writes to LDS.
 template <typename T, int DIM, int SRC, int VM>
 __global__ __launch_bounds__(kBlock) void k_fft_x_fwd(Grid g, const T* __restrict__ vel, const double* __restrict__ r,
                                                         cd* __restrict__ spec, FftPlan P, const cd* __restrict__ post,
                                                         int lnl, int comp) {
     extern __shared__ cd lds[];
     const int nl = 1 << lnl;
+    const int ls = nl + P.pad;
     const int M = P.n;
     const int nrows = g.batch * g.nz * g.ny;
     const int row0 = xcd_logical(blockIdx.x, gridDim.x) * nl;
-    for (int t = threadIdx.x; t < nl * M; t += kBlock) {
-        const int l = t / M, m = t - l * M;
+    auto load = [&](int l, int m) INS_INLINE -> cd {
         const int row = row0 + l;
-        cd val = {0.0, 0.0};
-        if (row < nrows) {
-            if constexpr (SRC == 0) {
-                const int yy = row % g.ny;
-                const int zb = row / g.ny;
-                const int zz = zb % g.nz;
-                const int b = zb / g.nz;
+        if (row >= nrows) return cd{0.0, 0.0};
+        if constexpr (SRC == 1) {
+            return reinterpret_cast<const cd*>(r + int64_t(row) * g.nx)[m];
+        } else {
+            const int yy = row % g.ny;
+            const int zb = row / g.ny;
+            const int zz = zb % g.nz;
+            const int b = zb / g.nz;
+            const int rowoff = (zz * g.ny + yy) * g.nx;
+            const int x0 = 2 * m;
+            if constexpr (SRC == 2) {
+                double a0, a1;
+                ld_pair(vel + (int64_t(b) * DIM + comp) * g.ncell + rowoff + x0, a0, a1);
+                return cd{a0, a1};
+            } else {
                 const T* wb = vel + int64_t(b) * DIM * g.ncell;
-                const int rowoff = (zz * g.ny + yy) * g.nx;
-                const int x0 = 2 * m;
                 const int xm = x0 == 0 ? g.nx - 1 : x0 - 1;
-                const T* wx = wb + rowoff;
-                const double ux_m = wx[xm], ux_0 = wx[x0], ux_1 = wx[x0 + 1];
-                double r0 = (ux_0 - ux_m) * g.ih[0];
-                double r1 = (ux_1 - ux_0) * g.ih[0];
+                double ux0, ux1;
+                ld_pair(wb + rowoff + x0, ux0, ux1);
+                const double uxm = wb[rowoff + xm];
+                double r0 = (ux0 - uxm) * g.ih[0];
+                double r1 = (ux1 - ux0) * g.ih[0];
                 const int ym = yy == 0 ? g.ny - 1 : yy - 1;
                 const T* wy = wb + g.ncell;
-                const int rowy = (zz * g.ny + ym) * g.nx;
-                r0 += (double(wy[rowoff + x0]) - double(wy[rowy + x0])) * g.ih[1];
-                r1 += (double(wy[rowoff + x0 + 1]) - double(wy[rowy + x0 + 1])) * g.ih[1];
+                double uy0, uy1, vy0, vy1;
+                ld_pair(wy + rowoff + x0, uy0, uy1);
+                ld_pair(wy + (zz * g.ny + ym) * g.nx + x0, vy0, vy1);
+                r0 += (uy0 - vy0) * g.ih[1];
+                r1 += (uy1 - vy1) * g.ih[1];
                 if constexpr (DIM == 3) {
                     const int zm = zz == 0 ? g.nz - 1 : zz - 1;
                     const T* wz = wb + 2 * g.ncell;
-                    const int rowz = (zm * g.ny + yy) * g.nx;
-                    r0 += (double(wz[rowoff + x0]) - double(wz[rowz + x0])) * g.ih[2];
-                    r1 += (double(wz[rowoff + x0 + 1]) - double(wz[rowz + x0 + 1])) * g.ih[2];
+                    double uz0, uz1, vz0, vz1;
+                    ld_pair(wz + rowoff + x0, uz0, uz1);
+                    ld_pair(wz + (zm * g.ny + yy) * g.nx + x0, vz0, vz1);
+                    r0 += (uz0 - vz0) * g.ih[2];
+                    r1 += (uz1 - vz1) * g.ih[2];
                 }
-                val = {r0, r1};
-            } else if constexpr (SRC == 1) {
-                val = reinterpret_cast<const cd*>(r + int64_t(row) * g.nx)[m];
-            } else {
-                const int yy = row % g.ny;
-                const int zb = row / g.ny;
-                const int zz = zb % g.nz;
-                const int b = zb / g.nz;
-                const T* src = vel + (int64_t(b) * DIM + comp) * g.ncell + int64_t(zz * g.ny + yy) * g.nx;
-                val = {double(src[2 * m]), double(src[2 * m + 1])};
+                return cd{r0, r1};
             }
         }
-        lds[m * (nl + P.pad) + l] = val;
-    }
-    __syncthreads();
-    fft_lines<-1, VM>(lds, lnl, P);
+    };
+    const NoOp nop;
+    fft_run<-1, VM, 0, 0, kElemFast, kLineFast>(lds, lnl, ls, P, load, nop, nop, nullptr);
     const int M1 = M + 1;
     for (int t = threadIdx.x; t < nl * M1; t += kBlock) {
         const int l = t / M1, k = t - l * M1;
         const int row = row0 + l;
         if (row >= nrows) continue;
-        const cd zk = lds[(k == M ? 0 : k) * (nl + P.pad) + l];
-        const cd zc = cconj(lds[(k == 0 ? 0 : M - k) * (nl + P.pad) + l]);
+        const cd zk = lds[(k == M ? 0 : k) * ls + l];
+        const cd zc = cconj(lds[(k == 0 ? 0 : M - k) * ls + l]);
         const cd e = cscale(cadd(zk, zc), 0.5);
         const cd dd = csub(zk, zc);
         const cd o = {0.5 * dd.y, -0.5 * dd.x};
@@ -264,102 +394,118 @@ __global__ __launch_bounds__(kBlock) void k_fft_x_fwd(Grid g, const T* __restric
 
 // x pass, inverse: half spectrum -> real rows, scaled by n_x (unnormalised).
 // Z[k] = (X[k] + conj X[M-k]) + i (X[k] - conj X[M-k]) conj(W^k), z = IFFT_M(Z),
-// x[2m] = Re z[m], x[2m+1] = Im z[m].
+// x[2m] = Re z[m], x[2m+1] = Im z[m]. First stage reads the spectrum rows and
+// last stage writes the real rows directly (both element-fast).
 template <int VM>
 __global__ __launch_bounds__(kBlock) void k_fft_x_inv(Grid g, const cd* __restrict__ spec, double* __restrict__ p,
                                                         FftPlan P, const cd* __restrict__ post, int lnl) {
     extern __shared__ cd lds[];
     const int nl = 1 << lnl;
+    const int ls = nl + P.pad;
     const int M = P.n, M1 = M + 1;
     const int nrows = g.batch * g.nz * g.ny;
     const int row0 = xcd_logical(blockIdx.x, gridDim.x) * nl;
-    for (int t = threadIdx.x; t < nl * M; t += kBlock) {
-        const int l = t / M, k = t - l * M;
+    auto load = [&](int l, int k) INS_INLINE -> cd {
         const int row = row0 + l;
-        cd z = {0.0, 0.0};
-        if (row < nrows) {
-            const cd* sr = spec + int64_t(row) * M1;
-            const cd xk = sr[k];
-            const cd xc = cconj(sr[M - k]);
-            const cd e = cadd(xk, xc);
-            const cd o = cmulc(csub(xk, xc), post[k]);
-            z = {e.x - o.y, e.y + o.x};
-        }
-        lds[k * (nl + P.pad) + l] = z;
-    }
-    __syncthreads();
-    fft_lines<1, VM>(lds, lnl, P);
-    for (int t = threadIdx.x; t < nl * M; t += kBlock) {
-        const int l = t / M, m = t - l * M;
+        if (row >= nrows) return cd{0.0, 0.0};
+        const cd* sr = spec + int64_t(row) * M1;
+        const cd xk = sr[k];
+        const cd xc = cconj(sr[M - k]);
+        const cd e = cadd(xk, xc);
+        const cd o = cmulc(csub(xk, xc), post[k]);
+        return cd{e.x - o.y, e.y + o.x};
+    };
+    auto sink = [&](int l, int m, cd z) INS_INLINE {
         const int row = row0 + l;
-        if (row >= nrows) continue;
-        reinterpret_cast<cd*>(p + int64_t(row) * g.nx)[m] = lds[m * (nl + P.pad) + l];
-    }
+        if (row < nrows) reinterpret_cast<cd*>(p + int64_t(row) * g.nx)[m] = z;
+    };
+    const NoOp nop;
+    fft_run<1, VM, 0, 1, kElemFast, kElemFast>(lds, lnl, ls, P, load, sink, nop, nullptr);
 }
 
 // Strided complex pass along y (axis 1) or z (axis 2) of the half spectrum
-// [batch][n_z][n_y][n_x/2+1]. MODE 0 forward, 1 inverse, 2 forward + divide + inverse.
+// [batch][n_z][n_y][n_x/2+1]. MODE 0 forward, 1 inverse, 2 forward + divide +
+// inverse. Columns kx < n_x/2 go in chunks of nl adjacent kx per workgroup (each
+// access a contiguous run of nl values); the Nyquist column kx = n_x/2 is taken
+// by extra workgroups, nl lines of it (adjacent values of the other non-x
+// index) each, so no workgroup transforms a chunk that is mostly padding. Either
+// way line l of a workgroup starts at lb0 + l*lstep, has wavenumbers
+// (kx0 + l*kxstep, fk0 + l*fkstep) and exists for l < nvalid.
+// First and last stages touch memory directly; in MODE 2 the forward run leaves
+// its outputs in registers, they are divided there, and the inverse runs the
+// stages in reverse radix order (plan Q, whose first radix is P's last) from
+// those same registers.
 template <int MODE, int VM>
-__global__ __launch_bounds__(kBlock) void k_fft_strided(Grid g, cd* __restrict__ spec, FftPlan P, int axis, int lnl,
-                                                          SolveTab st) {
+__global__ __launch_bounds__(kBlock) void k_fft_strided(Grid g, cd* __restrict__ spec, FftPlan P, FftPlan Q, int axis,
+                                                          int lnl, SolveTab st) {
     extern __shared__ cd lds[];
     const int nl = 1 << lnl;
-    const int nxh = g.nx / 2 + 1;
-    const int nchunk = (nxh + nl - 1) >> lnl;
+    const int M = g.nx / 2;
+    const int nxh = M + 1;
+    const int nchunk = (M + nl - 1) >> lnl;
+    const int nfix = axis == 1 ? g.nz : g.ny;  // the other non-x index
+    const int nouter = g.batch * nfix;
     const int wg = xcd_logical(blockIdx.x, gridDim.x);
-    const int chunk = wg % nchunk;
-    const int outer = wg / nchunk;
-    const int N = P.n;
-    int64_t base;
-    int64_t stride;
-    int fixed_k = 0;  // the other (non-line, non-x) wavenumber of this line
-    if (axis == 1) {
-        stride = nxh;
-        base = int64_t(outer) * g.ny * nxh;  // outer = (b, z)
-        fixed_k = outer % g.nz;
+    const int64_t plane = int64_t(g.nz) * g.ny * nxh;                         // one batch entry
+    const int64_t stride = axis == 1 ? int64_t(nxh) : int64_t(nxh) * g.ny;   // along the line
+    const int64_t fstride = axis == 1 ? int64_t(nxh) * g.ny : int64_t(nxh);  // along the other index
+    int64_t lb0, lstep;
+    int kx0, kxstep, fk0, fkstep, nvalid;
+    if (wg < nchunk * nouter) {
+        const int outer = wg / nchunk;
+        const int b = outer / nfix, f = outer - b * nfix;
+        kx0 = (wg - outer * nchunk) << lnl;
+        kxstep = 1;
+        fk0 = f;
+        fkstep = 0;
+        lb0 = b * plane + f * fstride + kx0;
+        lstep = 1;
+        nvalid = M - kx0;
     } else {
-        stride = int64_t(nxh) * g.ny;
-        const int yy = outer % g.ny, b = outer / g.ny;
-        base = int64_t(b) * g.nz * g.ny * nxh + int64_t(yy) * nxh;
-        fixed_k = yy;
+        const int nfc = (nfix + nl - 1) >> lnl;
+        const int j = wg - nchunk * nouter;
+        const int b = j / nfc;
+        const int f0 = (j - b * nfc) << lnl;
+        kx0 = M;
+        kxstep = 0;
+        fk0 = f0;
+        fkstep = 1;
+        lb0 = b * plane + f0 * fstride + M;
+        lstep = fstride;
+        nvalid = nfix - f0;
     }
-    const int kx0 = chunk << lnl;
-    base += kx0;
-    const int ntot = N << lnl;
     const int ls = nl + P.pad;
-    for (int t = threadIdx.x; t < ntot; t += kBlock) {
-        const int c = t & (nl - 1), j = t >> lnl;
-        lds[j * ls + c] = (kx0 + c < nxh) ? spec[base + j * stride + c] : cd{0.0, 0.0};
-    }
-    __syncthreads();
+    auto load = [&](int l, int e) INS_INLINE -> cd {
+        return l < nvalid ? spec[lb0 + l * lstep + e * stride] : cd{0.0, 0.0};
+    };
+    auto store = [&](int l, int e, cd z) INS_INLINE {
+        if (l < nvalid) spec[lb0 + l * lstep + e * stride] = z;
+    };
+    const NoOp nop;
     if constexpr (MODE == 1) {
-        fft_lines<1, VM>(lds, lnl, P);
+        fft_run<1, VM, 0, 1, kLineFast, kLineFast>(lds, lnl, ls, P, load, store, nop, nullptr);
+    } else if constexpr (MODE == 0) {
+        fft_run<-1, VM, 0, 1, kLineFast, kLineFast>(lds, lnl, ls, P, load, store, nop, nullptr);
     } else {
-        fft_lines<-1, VM>(lds, lnl, P);
-    }
-    if constexpr (MODE == 2) {
         // divide by L(k) * #cells; L(0) := 1.
-        for (int t = threadIdx.x; t < ntot; t += kBlock) {
-            const int c = t & (nl - 1), j = t >> lnl;
-            const int kx = kx0 + c;
-            if (kx >= nxh) continue;
-            double lam, kzero;
+        auto divide = [&](int l, int e, cd z) INS_INLINE -> cd {
+            if (l >= nvalid) return z;
+            const int kx = kx0 + l * kxstep;
+            const int fk = fk0 + l * fkstep;
+            double lam;
+            bool kzero;
             if (axis == 2) {
-                lam = st.lam[0][kx] + st.lam[1][fixed_k] + st.lam[2][j];
-                kzero = (kx == 0 && fixed_k == 0 && j == 0);
+                lam = st.lam[0][kx] + st.lam[1][fk] + st.lam[2][e];
+                kzero = (kx == 0 && fk == 0 && e == 0);
             } else {
-                lam = st.lam[0][kx] + st.lam[1][j];
-                kzero = (kx == 0 && j == 0);
+                lam = st.lam[0][kx] + st.lam[1][e];
+                kzero = (kx == 0 && e == 0);
             }
             const double sc = kzero ? st.inv_ncell : -st.inv_ncell / lam;
-            lds[j * ls + c] = cscale(lds[j * ls + c], sc);
-        }
-        __syncthreads();
-        fft_lines<1, VM>(lds, lnl, P);
-    }
-    for (int t = threadIdx.x; t < ntot; t += kBlock) {
-        const int c = t & (nl - 1), j = t >> lnl;
-        if (kx0 + c < nxh) spec[base + j * stride + c] = lds[j * ls + c];
+            return cscale(z, sc);
+        };
+        fft_run<-1, VM, 0, 2, kLineFast, kLineFast>(lds, lnl, ls, P, load, store, divide, &Q);
+        fft_inverse_rest<1, VM, kLineFast>(lds, lnl, ls, Q, store);
     }
 }
 
@@ -402,16 +548,16 @@ hipError_t launch_fft_x_inv(const Grid& g, const cd* spec, double* p, const FftP
     return hipGetLastError();
 }
 
-hipError_t launch_fft_strided(const Grid& g, cd* spec, const FftPlan& pl, int axis, int mode, int lnl,
-                              const SolveTab& st, hipStream_t s) {
+hipError_t launch_fft_strided(const Grid& g, cd* spec, const FftPlan& pl, const FftPlan& rev, int axis, int mode,
+                              int lnl, const SolveTab& st, hipStream_t s) {
     const int nl = 1 << lnl;
-    const int nxh = g.nx / 2 + 1;
-    const int nchunk = (nxh + nl - 1) / nl;
+    const int nchunk = (g.nx / 2 + nl - 1) / nl;
     const int nouter = axis == 1 ? g.batch * g.nz : g.batch * g.ny;
-    const int nblk = nchunk * nouter;
+    const int nfix = axis == 1 ? g.nz : g.ny;
+    const int nblk = nchunk * nouter + g.batch * ((nfix + nl - 1) / nl);  // + the Nyquist-column workgroups
     const size_t shm = size_t(nl + pl.pad) * pl.n * sizeof(cd);
 #define INS_ST(MODE, VM) \
-    hipLaunchKernelGGL((k_fft_strided<MODE, VM>), dim3(nblk), dim3(kBlock), shm, s, g, spec, pl, axis, lnl, st)
+    hipLaunchKernelGGL((k_fft_strided<MODE, VM>), dim3(nblk), dim3(kBlock), shm, s, g, spec, pl, rev, axis, lnl, st)
 #define INS_ST_VM(MODE) \
     do { if (pl.vm == 8) INS_ST(MODE, 8); else INS_ST(MODE, 16); } while (0)
     if (mode == 0)
