@@ -28,6 +28,11 @@ from .ins import (  # noqa: F401
     project_vjp,
     step_rk4_vjp,
     rk4_stages,
+    wray3_stages,
+    step_wray3,
+    step_wray3_vjp,
+    WRAY3_G,
+    WRAY3_Z,
     kinetic_energy,
     rollout_loss,
     rollout_loss_grad,

@@ -1,4 +1,4 @@
-"""Float64 numpy oracle of the discrete operators, pressure solve, RK4 step and their adjoints.
+"""Float64 numpy oracle of the discrete operators, pressure solve, RK4 and Wray3 steps and their adjoints.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring). Not used by the product path.
 
@@ -186,6 +186,39 @@ def step_rk4(u0, h, nu, dt, rhs_fn=None):
 
 
 # ----------------------------------------------------------------------------
+# Wray's low-storage three-stage Runge-Kutta scheme (one of the explicit
+# integrators named in Sec. 2.5.2 and the low-storage method of Sec. 3.3),
+# velocity projected after every stage as for RK4. The paper cites the scheme
+# without its coefficients; they are Wray's two-register ones:
+#   u_1 = P(u_0 + dt g1 F(u_0))
+#   u_2 = P(u_1 + dt (g2 F(u_1) + z1 F(u_0)))
+#   u_3 = P(u_2 + dt (g3 F(u_2) + z2 F(u_1)))
+# with g = (8/15, 5/12, 3/4), z = (-17/60, -5/12); u_3 is the new state.
+# ----------------------------------------------------------------------------
+
+WRAY3_G = (8.0 / 15.0, 5.0 / 12.0, 3.0 / 4.0)
+WRAY3_Z = (-17.0 / 60.0, -5.0 / 12.0)
+
+
+def wray3_stages(u0, h, nu, dt, rhs_fn=None):
+    """Stage velocities (u_0, u_1, u_2) and right-hand sides F(u_0), F(u_1), F(u_2)."""
+    F = rhs_fn if rhs_fn is not None else (lambda v: rhs(v, h, nu))
+    us = [np.array(u0, dtype=np.float64)]
+    fs = [F(us[0])]
+    us.append(project(us[0] + dt * WRAY3_G[0] * fs[0], h)[0])
+    fs.append(F(us[1]))
+    us.append(project(us[1] + dt * (WRAY3_G[1] * fs[1] + WRAY3_Z[0] * fs[0]), h)[0])
+    fs.append(F(us[2]))
+    return us, fs
+
+
+def step_wray3(u0, h, nu, dt, rhs_fn=None):
+    """One step of Wray's scheme: u_3 = P(u_2 + dt (g3 F(u_2) + z2 F(u_1)))."""
+    us, fs = wray3_stages(u0, h, nu, dt, rhs_fn)
+    return project(us[2] + dt * (WRAY3_G[2] * fs[2] + WRAY3_Z[1] * fs[1]), h)[0]
+
+
+# ----------------------------------------------------------------------------
 # Pullbacks (Sec. 3.4 general pullback rule, App. B adjoint kernels)
 # ----------------------------------------------------------------------------
 
@@ -272,6 +305,26 @@ def step_rk4_vjp(u0, u1bar, h, nu, dt, rhs_fn=None, rhs_vjp_fn=None):
             u0bar += wbar
             fbar[i - 1] = fbar[i - 1] + dt * RK4_A[i - 1] * wbar
     return u0bar
+
+
+def step_wray3_vjp(u0, u1bar, h, nu, dt, rhs_fn=None, rhs_vjp_fn=None):
+    """Reverse pass of ``step_wray3``, transposing its two-register recurrence.
+
+    With w_k the unprojected stage sums (u_k = P w_k) and wbar_k = P^T ubar(u_k):
+      wbar_3 = P u3bar;  u2bar = wbar_3 + J(u_2)^T (dt g3 wbar_3);  F1bar = dt z2 wbar_3
+      wbar_2 = P u2bar;  u1bar = wbar_2 + J(u_1)^T (dt g2 wbar_2 + F1bar);  F0bar = dt z1 wbar_2
+      wbar_1 = P u1bar;  u0bar = wbar_1 + J(u_0)^T (dt g1 wbar_1 + F0bar).
+    """
+    us, _ = wray3_stages(u0, h, nu, dt, rhs_fn)
+    G = rhs_vjp_fn if rhs_vjp_fn is not None else (lambda v, fb: rhs_vjp(v, fb, h, nu))
+    wbar = project_vjp(u1bar, h)
+    ubar = wbar + G(us[2], dt * WRAY3_G[2] * wbar)
+    f1bar = dt * WRAY3_Z[1] * wbar
+    wbar = project_vjp(ubar, h)
+    ubar = wbar + G(us[1], dt * WRAY3_G[1] * wbar + f1bar)
+    f0bar = dt * WRAY3_Z[0] * wbar
+    wbar = project_vjp(ubar, h)
+    return wbar + G(us[0], dt * WRAY3_G[0] * wbar + f0bar)
 
 
 # ----------------------------------------------------------------------------
