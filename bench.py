@@ -6,8 +6,9 @@ E(k) ~ k^4 exp(-2 (k/4)^2) and unit kinetic energy.
 
 `value` is the float64 forward step rate in Mcell-updates/s (one cell update =
 one full RK4 step of one cell; inputs resident in HBM). The same line reports
-the float64 forward+adjoint rate and the FP32-stencil mode (float32 fields,
-float64 divergence/Poisson/projection), the HBM-roofline fraction of each
+the float64 forward+adjoint rate, the FP32-stencil mode (float32 fields,
+float64 divergence/Poisson/projection), Wray's low-storage RK3 step (modes
+*_wray3: three stages and solves per step), the HBM-roofline fraction of each
 step and of the dominant kernel (per-kernel durations from HIP events recorded
 on the library's stream), and the float64 CPU oracle timed on a bounded
 sample of the same workload.
@@ -33,7 +34,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 CONFIGS = {
     # the benchmark workload: 3D decaying turbulence at 256^3
     "turb256": {"n": 256, "nu": 1.0 / 1600.0, "dt": 1e-3, "k0": 4.0, "seed": 0,
-                "modes": "fp64,fp64_adj,fp32,fp32_adj"},
+                "modes": "fp64,fp64_adj,fp32,fp32_adj,fp64_wray3,fp32_wray3"},
     # the largest single-GPU DNS: 840^3 = 2^3*3*5*7 (mixed-radix FFT), FP64 and FP32 mode
     "dns840": {"n": 840, "nu": 1.0 / 5000.0, "dt": 1e-3, "k0": 8.0, "seed": 3, "modes": "fp64,fp32"},
 }
@@ -58,6 +59,9 @@ def kernel_bytes(name, n, elem, batch=1):
         "stage": (5 * v + S) * N,                 # read w, p, u0, y; write y, w
         "stage_last": (3 * v + S) * N,            # read w, p, y; write y
         "stage_rec": (3 * v + S) * N,             # read w, p, u0; write w
+        "wray_stage1": 3 * v * N,                 # read u0; write yacc, w
+        "wray_stage2": (3 * v + S) * N,           # read w, p, yacc; write w
+        "wray_stage3": (3 * v + S) * N,
         "fft_x_fwd_div": v * N + C * Ns,          # read w; write spectrum
         "fft_x_fwd": S * N + C * Ns,
         "fft_y_fwd": 2 * C * Ns,
@@ -120,7 +124,7 @@ def time_steps(fn, steps, warmup, solver=None):
     return a.elapsed_time(b) / steps, prof
 
 
-def run_mode(n, nu, dt, precision, steps, warmup, u0_np, adjoint):
+def run_mode(n, nu, dt, precision, steps, warmup, u0_np, adjoint, scheme="rk4"):
     import torch
 
     from paper_2604_18536_amd import Solver
@@ -136,12 +140,12 @@ def run_mode(n, nu, dt, precision, steps, warmup, u0_np, adjoint):
         ubar.copy_(torch.randn_like(u0))
 
         def fn():
-            s.step(u0, dt, out=u1)
-            s.step_vjp(u0, ubar, dt, out=gbar)
+            s.step(u0, dt, out=u1, scheme=scheme)
+            s.step_vjp(u0, ubar, dt, out=gbar, scheme=scheme)
     else:
 
         def fn():
-            s.step(u0, dt, out=u1)
+            s.step(u0, dt, out=u1, scheme=scheme)
     ms, _ = time_steps(fn, steps, warmup)
     ms_p, prof = time_steps(fn, steps, 1, solver=s)
     ok = s.stats(u1)[3]
@@ -296,7 +300,8 @@ def main():
     for mode in args.modes.split(","):
         precision = "fp64" if mode.startswith("fp64") else "fp32"
         adjoint = mode.endswith("_adj")
-        ms, ms_p, prof, ok, ws = run_mode(n, nu, dt, precision, args.steps, args.warmup, u0, adjoint)
+        scheme = "wray3" if "_wray3" in mode else "rk4"
+        ms, ms_p, prof, ok, ws = run_mode(n, nu, dt, precision, args.steps, args.warmup, u0, adjoint, scheme)
         elem = 8 if precision == "fp64" else 4
         alg = 0
         for name, (cnt, tot) in prof.items():

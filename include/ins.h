@@ -180,6 +180,24 @@ ins_status ins_project_vjp(ins_ctx ctx, const void* ubar_out, void* ubar);
  * storage on first use. u0bar must not alias u0 or u1bar. */
 ins_status ins_step_rk4_vjp(ins_ctx ctx, const void* u0, const void* u1bar, void* u0bar, double dt);
 
+/* One step of Wray's low-storage three-stage, third-order Runge-Kutta
+ * scheme (Sec. 2.5.2 lists it among the explicit integrators; Sec. 3.3 cites
+ * it as the low-storage method), velocity projected after every stage like
+ * ins_step_rk4. The paper gives no coefficients; these are Wray's:
+ *   u_1 = P(u0 + dt g1 F(u0)),  u_2 = P(u_1 + dt (g2 F(u_1) + z1 F(u0))),
+ *   u1 = P(u_2 + dt (g3 F(u_2) + z2 F(u_1))),
+ *   g = (8/15, 5/12, 3/4), z = (-17/60, -5/12)
+ * (Butcher form: c = (0, 8/15, 2/3), b = (1/4, 0, 3/4)). Three stage kernels
+ * and three pressure solves per step instead of four of each. Same buffers,
+ * aliasing (u0 == u1 allowed), closure coupling and errors as ins_step_rk4. */
+ins_status ins_step_wray3(ins_ctx ctx, const void* u0, void* u1, double dt);
+
+/* u0bar = (d u1 / d u0)^T u1bar for u1 = ins_step_wray3(u0, dt): recomputes
+ * the two inner stage states, then runs the stages backwards. Same storage,
+ * aliasing rules, closure-gradient accumulation and errors as
+ * ins_step_rk4_vjp. */
+ins_status ins_step_wray3_vjp(ins_ctx ctx, const void* u0, const void* u1bar, void* u0bar, double dt);
+
 /* ---------------------------------------------------------------------------
  * Learned closure (Sec. 4: a neural closure inside the solver, trained
  * a-posteriori through it). The paper does not fix an architecture; this one

@@ -59,6 +59,8 @@ _SIGS = {
     "ins_poisson_solve_vjp": ([_P, _P, _P]),
     "ins_project_vjp": ([_P, _P, _P]),
     "ins_step_rk4_vjp": ([_P, _P, _P, _P, _D]),
+    "ins_step_wray3": ([_P, _P, _P, _D]),
+    "ins_step_wray3_vjp": ([_P, _P, _P, _P, _D]),
     "ins_closure_set": ([_P, _P]),
     "ins_closure_grad": ([_P, _P]),
     "ins_cnn_forward": ([_P, _P, _P]),

@@ -16,17 +16,18 @@ import torch.utils.checkpoint as _ckpt
 
 class _Step(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, u0, solver, dt):
+    def forward(ctx, u0, solver, dt, scheme):
         ctx.solver = solver
         ctx.dt = float(dt)
+        ctx.scheme = scheme
         ctx.save_for_backward(u0)
-        return solver.step(u0.contiguous(), dt)
+        return solver.step(u0.contiguous(), dt, scheme=scheme)
 
     @staticmethod
     def backward(ctx, u1bar):
         (u0,) = ctx.saved_tensors
-        g = ctx.solver.step_vjp(u0.contiguous(), u1bar.contiguous(), ctx.dt)
-        return g, None, None
+        g = ctx.solver.step_vjp(u0.contiguous(), u1bar.contiguous(), ctx.dt, scheme=ctx.scheme)
+        return g, None, None, None
 
 
 class _Rhs(torch.autograd.Function):
@@ -58,25 +59,26 @@ class _StepClosure(torch.autograd.Function):
     set from) is an input so that autograd routes its gradient."""
 
     @staticmethod
-    def forward(ctx, u0, theta, solver, dt):
+    def forward(ctx, u0, theta, solver, dt, scheme):
         ctx.solver = solver
         ctx.dt = float(dt)
+        ctx.scheme = scheme
         ctx.save_for_backward(u0)
-        return solver.step(u0.contiguous(), dt)
+        return solver.step(u0.contiguous(), dt, scheme=scheme)
 
     @staticmethod
     def backward(ctx, u1bar):
         (u0,) = ctx.saved_tensors
         ctx.solver.closure_grad()  # start from an empty accumulator
-        g = ctx.solver.step_vjp(u0.contiguous(), u1bar.contiguous(), ctx.dt)
-        return g, ctx.solver.closure_grad(), None, None
+        g = ctx.solver.step_vjp(u0.contiguous(), u1bar.contiguous(), ctx.dt, scheme=ctx.scheme)
+        return g, ctx.solver.closure_grad(), None, None, None
 
 
-def step(solver, u, dt, theta=None):
-    """One differentiable RK4 step (with the closure when theta is given)."""
+def step(solver, u, dt, theta=None, scheme="rk4"):
+    """One differentiable time step (RK4, or "wray3"; with the closure when theta is given)."""
     if theta is not None:
-        return _StepClosure.apply(u, theta, solver, dt)
-    return _Step.apply(u, solver, dt)
+        return _StepClosure.apply(u, theta, solver, dt, scheme)
+    return _Step.apply(u, solver, dt, scheme)
 
 
 def rhs(solver, u):
@@ -89,17 +91,17 @@ def project(solver, u):
     return _Project.apply(u, solver)
 
 
-def rollout(solver, u0, dt, nsteps):
+def rollout(solver, u0, dt, nsteps, scheme="rk4"):
     """States u_1..u_n (every state kept by autograd; use rollout_loss for long unrolls)."""
     out = []
     u = u0
     for _ in range(nsteps):
-        u = step(solver, u, dt)
+        u = step(solver, u, dt, scheme=scheme)
         out.append(u)
     return out
 
 
-def rollout_loss(solver, u0, dt, refs, checkpoint_every=10, per_step_loss=None, theta=None):
+def rollout_loss(solver, u0, dt, refs, checkpoint_every=10, per_step_loss=None, theta=None, scheme="rk4"):
     """Sum over s = 1..len(refs) of per_step_loss(u_s, refs[s-1]), differentiable in u0.
 
     Default per-step loss: mean over cells and components of (u_s - ref_s)^2,
@@ -118,7 +120,7 @@ def rollout_loss(solver, u0, dt, refs, checkpoint_every=10, per_step_loss=None, 
     def segment(u, s0, s1):
         total = u.new_zeros(())
         for s in range(s0, s1):
-            u = step(solver, u, dt, theta)
+            u = step(solver, u, dt, theta, scheme)
             total = total + per_step_loss(u, refs[s])
         return u, total
 

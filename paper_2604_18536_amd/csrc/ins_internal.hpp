@@ -100,10 +100,11 @@ hipError_t launch_fft_strided(const Grid& g, cd* spec, const FftPlan& pl, const 
 // Reverse-pass kernels.
 template <typename T>
 hipError_t launch_rhs_vjp(const Grid& g, const T* u, const T* fbar, T* ubar, hipStream_t s);
-// Reverse RK4 stage: u_i = (proj_u ? w - G p : w),
+// Reverse Runge-Kutta stage: u_i = (proj_u ? w - G p : w),
 // Fbar_i = cb ybar + (has_w ? cw (un - G q) : 0), out = J_F(u_i)^T Fbar_i,
-// u0bar = (mode == 0 ? ybar : u0bar) + (has_w ? un - G q : 0) + (mode == 2 ? out : 0),
-// ubar_out (if not null) = out, fbar_out (if not null) = Fbar_i.
+// u0bar = (mode 0 or 3 ? ybar : u0bar) + (has_w ? un - G q : 0) + (mode 2 or 3 ? out : 0),
+// ubar_out (if not null) = out, fbar_out (if not null) = Fbar_i; a null u0bar
+// (modes 0 and 3, which do not read it) skips that output.
 template <typename T>
 hipError_t launch_stage_vjp(const Grid& g, const T* w, const double* p, bool proj_u, const T* ybar, const T* un,
                             const double* q, bool has_w, double cb, double cw, T* u0bar, int mode, T* ubar_out,

@@ -418,11 +418,12 @@ const T* closure_at_stage(ins_ctx c, const T* w, const double* p) {
 
 template <typename T>
 void stage(ins_ctx c, const T* w, const double* p, bool proj, const T* u0, T* y, bool yinit, double cy, T* wout,
-           double cw) {
+           double cw, const char* label = nullptr) {
     const T* mc = closure_at_stage<T>(c, w, proj ? p : nullptr);
     // one profile name per data-movement variant (their byte counts differ)
-    const char* name = !proj ? (y ? "stage_first" : "stage_first_rec")
-                             : (y ? (wout ? "stage" : "stage_last") : "stage_rec");
+    const char* name = label ? label
+                             : !proj ? (y ? "stage_first" : "stage_first_rec")
+                                     : (y ? (wout ? "stage" : "stage_last") : "stage_rec");
     c->launch(name, [&] {
         return ins::launch_stage<T>(c->g, w, p, proj, u0, y, yinit, cy, wout, cw, c->stream, mc);
     });
@@ -461,14 +462,14 @@ template <typename T>
 void stage_vjp(ins_ctx c, const T* w, const double* p, bool proj_u, const T* ybar, const T* un, const double* q,
                bool has_w, double cb, double cw, T* u0bar, int mode, T* out) {
     T* fb = c->clos_on ? static_cast<T*>(c->fbar) : nullptr;
-    const char* name = mode == 0 ? "stage_vjp_first" : (mode == 2 ? "stage_vjp_last" : "stage_vjp");
+    const char* name = mode == 0 ? "stage_vjp_first" : (mode >= 2 ? "stage_vjp_last" : "stage_vjp");
     c->launch(name, [&] {
         return ins::launch_stage_vjp<T>(c->g, w, p, proj_u, ybar, un, q, has_w, cb, cw, u0bar, mode, out, c->stream, fb);
     });
     if (c->clos_on) {
         // the closure's share of the stage pullback: m_bar = Fbar_i, at u_i
         closure_at_stage<T>(c, w, proj_u ? p : nullptr);
-        closure_backward<T>(c, fb, mode == 2 ? u0bar : out);
+        closure_backward<T>(c, fb, mode >= 2 ? u0bar : out);
     }
 }
 
@@ -505,6 +506,59 @@ void step_rk4_vjp(ins_ctx c, const T* u0, const T* u1bar, T* u0bar, double dt) {
     stage_vjp<T>(c, W2, P2, true, YB, UB, Q, true, dt / 3.0, dt / 2.0, u0bar, 1, UA);
     poisson(c, UA, nullptr, Q);
     stage_vjp<T>(c, u0, nullptr, false, YB, UA, Q, true, dt / 6.0, dt / 2.0, u0bar, 2, nullptr);
+}
+
+// Wray's low-storage three-stage scheme (Sec. 2.5.2 names it among the
+// integrators, Sec. 3.3 as the low-storage one), projection after every
+// stage. In Butcher form its stages are u_2 = P(u0 + dt 8/15 F_1),
+// u_3 = P(u0 + dt (1/4 F_1 + 5/12 F_2)), u_new = P(u0 + dt (1/4 F_1 + 3/4 F_3));
+// since both later sums start from yacc = u0 + dt/4 F_1, the schedule keeps
+// yacc and one stage register: three stage kernels and three solves.
+template <typename T>
+void step_wray3(ins_ctx c, const T* u0, T* u1, double dt) {
+    T* yacc = static_cast<T*>(c->ry);
+    T* wa = static_cast<T*>(c->wa);
+    T* wb = static_cast<T*>(c->wb);
+    double* p = c->p;
+    stage<T>(c, u0, nullptr, false, u0, yacc, true, dt / 4.0, wa, dt * 8.0 / 15.0, "wray_stage1");
+    poisson(c, wa, nullptr, p);
+    stage<T>(c, wa, p, true, yacc, nullptr, false, 0.0, wb, dt * 5.0 / 12.0, "wray_stage2");
+    poisson(c, wb, nullptr, p);
+    stage<T>(c, wb, p, true, yacc, nullptr, false, 0.0, wa, dt * 3.0 / 4.0, "wray_stage3");
+    poisson(c, wa, nullptr, p);
+    apply_projection<T>(c, wa, p, u1);
+}
+
+// Reverse pass of step_wray3. With w_2 = u0 + dt 8/15 F_1, yacc = u0 + dt/4 F_1,
+// w_3 = yacc + dt 5/12 F_2(u_2), w_4 = yacc + dt 3/4 F_3(u_3), u_k = P w_k:
+//   wbar_4 = P u1bar = yaccbar (so far); ubar_3 = J_F(u_3)^T (dt 3/4 wbar_4)
+//   wbar_3 = P ubar_3; yaccbar += wbar_3; ubar_2 = J_F(u_2)^T (dt 5/12 wbar_3)
+//   wbar_2 = P ubar_2; u0bar = yaccbar + wbar_2 + J_F(u0)^T (dt/4 yaccbar + dt 8/15 wbar_2).
+template <typename T>
+void step_wray3_vjp(ins_ctx c, const T* u0, const T* u1bar, T* u0bar, double dt) {
+    ensure_vjp_storage(c);
+    T* W2 = static_cast<T*>(c->w2);
+    T* W3 = static_cast<T*>(c->w3);
+    double *P2 = c->p2, *P3 = c->p3;
+    T* YB = static_cast<T*>(c->ry);
+    T* UA = static_cast<T*>(c->wa);
+    T* UB = static_cast<T*>(c->wb);
+    double* Q = c->p;
+    // recompute the stage states (yacc lives in YB until the reverse pass overwrites it)
+    stage<T>(c, u0, nullptr, false, u0, YB, true, dt / 4.0, W2, dt * 8.0 / 15.0, "wray_stage1");
+    poisson(c, W2, nullptr, P2);
+    stage<T>(c, W2, P2, true, YB, nullptr, false, 0.0, W3, dt * 5.0 / 12.0, "wray_stage2");
+    poisson(c, W3, nullptr, P3);
+
+    poisson(c, u1bar, nullptr, Q);
+    apply_projection<T>(c, u1bar, Q, YB);  // YB = wbar_4, the running yaccbar
+    // the accumulator starts as YB itself, so this stage writes no accumulator
+    stage_vjp<T>(c, W3, P3, true, YB, nullptr, nullptr, false, dt * 3.0 / 4.0, 0.0, nullptr, 0, UA);
+    poisson(c, UA, nullptr, Q);
+    // Fbar_2 = dt 5/12 wbar_3 (cb = 0, so the ybar operand is not YB, which this kernel updates)
+    stage_vjp<T>(c, W2, P2, true, UA, UA, Q, true, 0.0, dt * 5.0 / 12.0, YB, 1, UB);
+    poisson(c, UB, nullptr, Q);
+    stage_vjp<T>(c, u0, nullptr, false, YB, UB, Q, true, dt / 4.0, dt * 8.0 / 15.0, u0bar, 3, nullptr);
 }
 
 void check_dt(double dt) {
@@ -789,6 +843,35 @@ ins_status ins_step_rk4_vjp(ins_ctx ctx, const void* u0, const void* u1bar, void
         with_type(ctx, [&](auto tag) {
             using T = decltype(tag);
             step_rk4_vjp<T>(ctx, static_cast<const T*>(u0), static_cast<const T*>(u1bar), static_cast<T*>(u0bar), dt);
+        });
+    });
+}
+
+ins_status ins_step_wray3(ins_ctx ctx, const void* u0, void* u1, double dt) {
+    return guarded([&] {
+        checked(ctx);
+        need(u0, "u0");
+        need(u1, "u1");
+        check_dt(dt);
+        with_type(ctx, [&](auto tag) {
+            using T = decltype(tag);
+            step_wray3<T>(ctx, static_cast<const T*>(u0), static_cast<T*>(u1), dt);
+        });
+    });
+}
+
+ins_status ins_step_wray3_vjp(ins_ctx ctx, const void* u0, const void* u1bar, void* u0bar, double dt) {
+    return guarded([&] {
+        checked(ctx);
+        need(u0, "u0");
+        need(u1bar, "u1bar");
+        need(u0bar, "u0bar");
+        check_dt(dt);
+        if (u0bar == u0 || u0bar == u1bar) raise(INS_ERR_INVALID, "u0bar must not alias u0 or u1bar");
+        with_type(ctx, [&](auto tag) {
+            using T = decltype(tag);
+            step_wray3_vjp<T>(ctx, static_cast<const T*>(u0), static_cast<const T*>(u1bar), static_cast<T*>(u0bar),
+                              dt);
         });
     });
 }

@@ -317,7 +317,7 @@ __global__ __launch_bounds__(kBlock) void k_stage_vjp_zm(Grid g, const T* __rest
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const int64_t kk = boff + int64_t(a) * nc + c0;
-                acc[a] = mode == 0 ? yb[int64_t(a) * nc + c0] : ld_stream(u0bar + kk);
+                acc[a] = (mode == 0 || mode == 3) ? yb[int64_t(a) * nc + c0] : ld_stream(u0bar + kk);
                 if constexpr (HAS_W)
                     acc[a] += T(double(ub[int64_t(a) * nc + c0]) - (qb[jpc[a]] - qb[c0]) * g.ih[a]);
             }
@@ -328,7 +328,7 @@ __global__ __launch_bounds__(kBlock) void k_stage_vjp_zm(Grid g, const T* __rest
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const int64_t kk = boff + int64_t(a) * nc + c0;
-                st_stream(mode == 2 ? acc[a] + out[a] : acc[a], u0bar + kk);
+                if (u0bar) st_stream(mode >= 2 ? acc[a] + out[a] : acc[a], u0bar + kk);
                 if (ubar_out) st_stream(out[a], ubar_out + kk);
                 if (fbar_out) fbar_out[kk] = rf[(k - 1) % 3][a][centre];
             }

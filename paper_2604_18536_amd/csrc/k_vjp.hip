@@ -79,8 +79,8 @@ __global__ __launch_bounds__(kBlock) void k_stage_vjp(Grid g, const T* __restric
     for (int a = 0; a < DIM; ++a) {
         const int64_t k = boff + a * g.ncell + c0;
         T acc;
-        if (u0bar_mode == 0) {
-            acc = ybar[k];  // u0bar = ybar (first reverse stage)
+        if (u0bar_mode == 0 || u0bar_mode == 3) {
+            acc = ybar[k];  // start from ybar (first reverse stage, or a last stage whose accumulator is ybar)
         } else {
             acc = u0bar[k];
         }
@@ -88,8 +88,8 @@ __global__ __launch_bounds__(kBlock) void k_stage_vjp(Grid g, const T* __restric
             const int cp = nb.at(a == 0, a == 1, a == 2);
             acc += T(double(un[k]) - (q[soff + cp] - q[soff + c0]) * g.ih[a]);
         }
-        if (u0bar_mode == 2) acc += out[a];
-        u0bar[k] = acc;
+        if (u0bar_mode >= 2) acc += out[a];
+        if (u0bar) u0bar[k] = acc;
         if (ubar_out) ubar_out[k] = out[a];
         if (fbar_out) fbar_out[k] = F(a, nb, 0, 0, 0);
     }
@@ -126,8 +126,8 @@ static void stage_vjp_dim(const Grid& g, int nblk, const T* w, const double* p, 
 // Reverse stage i: with u_i = (proj_u ? w - G p : w) and
 // Fbar_i = cb ybar + (has_w ? cw (un - G q) : 0),
 //   out = J_F(u_i)^T Fbar_i;
-//   u0bar = (mode == 0 ? ybar : u0bar) + (has_w ? un - G q : 0) + (mode == 2 ? out : 0);
-//   ubar_out (if not null) = out.
+//   u0bar = (mode 0 or 3 ? ybar : u0bar) + (has_w ? un - G q : 0) + (mode 2 or 3 ? out : 0);
+//   ubar_out (if not null) = out; u0bar null (modes 0 and 3 only) skips that output.
 template <typename T>
 hipError_t launch_stage_vjp(const Grid& g, const T* w, const double* p, bool proj_u, const T* ybar, const T* un,
                             const double* q, bool has_w, double cb, double cw, T* u0bar, int mode, T* ubar_out,

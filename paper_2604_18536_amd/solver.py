@@ -147,11 +147,20 @@ class Solver:
         L.call("ins_project", self._ctx, self._check(u, "vel", "u"), self._check(out, "vel", "out"), pp)
         return out
 
-    def step(self, u0, dt, out=None):
-        """One RK4 step; out may be u0 (in place)."""
+    _SCHEMES = {"rk4": ("ins_step_rk4", "ins_step_rk4_vjp"), "wray3": ("ins_step_wray3", "ins_step_wray3_vjp")}
+
+    def _scheme(self, scheme):
+        if scheme not in self._SCHEMES:
+            raise ValueError(f"scheme must be one of {sorted(self._SCHEMES)}")
+        return self._SCHEMES[scheme]
+
+    def step(self, u0, dt, out=None, scheme="rk4"):
+        """One time step (classical RK4, or Wray's low-storage RK3 with scheme="wray3");
+        out may be u0 (in place)."""
+        fn = self._scheme(scheme)[0]
         out = self._out(out, u0, "vel")
         self._sync_stream()
-        L.call("ins_step_rk4", self._ctx, self._check(u0, "vel", "u0"), self._check(out, "vel", "out"), float(dt))
+        L.call(fn, self._ctx, self._check(u0, "vel", "u0"), self._check(out, "vel", "out"), float(dt))
         return out
 
     # ------------------------------------------------------------- pullbacks
@@ -186,10 +195,11 @@ class Solver:
         L.call("ins_project_vjp", self._ctx, self._check(ubar_out, "vel", "ubar_out"), self._check(out, "vel", "out"))
         return out
 
-    def step_vjp(self, u0, u1bar, dt, out=None):
+    def step_vjp(self, u0, u1bar, dt, out=None, scheme="rk4"):
+        fn = self._scheme(scheme)[1]
         out = self._out(out, u0, "vel")
         self._sync_stream()
-        L.call("ins_step_rk4_vjp", self._ctx, self._check(u0, "vel", "u0"), self._check(u1bar, "vel", "u1bar"),
+        L.call(fn, self._ctx, self._check(u0, "vel", "u0"), self._check(u1bar, "vel", "u1bar"),
                self._check(out, "vel", "out"), float(dt))
         return out
 

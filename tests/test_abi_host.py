@@ -30,7 +30,7 @@ def test_header_declares_the_boundary():
     names = _declared()
     for must in ["ins_create", "ins_destroy", "ins_rhs", "ins_divergence", "ins_poisson_solve", "ins_project",
                  "ins_step_rk4", "ins_rhs_vjp", "ins_divergence_vjp", "ins_poisson_solve_vjp", "ins_project_vjp",
-                 "ins_step_rk4_vjp"]:
+                 "ins_step_rk4_vjp", "ins_step_wray3", "ins_step_wray3_vjp"]:
         assert must in names
 
 
@@ -84,6 +84,8 @@ def test_null_context_is_rejected(lib):
         assert getattr(lib, name)(*([p] * nargs)) == -1
     assert lib.ins_step_rk4(p, p, p, 1e-3) == -1
     assert lib.ins_step_rk4_vjp(p, p, p, p, 1e-3) == -1
+    assert lib.ins_step_wray3(p, p, p, 1e-3) == -1
+    assert lib.ins_step_wray3_vjp(p, p, p, p, 1e-3) == -1
     assert b"null" in lib.ins_last_error()
     assert lib.ins_destroy(p) == 0
 
