@@ -361,14 +361,17 @@ void closure_alloc(ins_ctx c) {
 
 // m = m_theta(u); leaves x0, z1, a1, z2, a2 for a following pullback.
 template <typename T>
-void closure_forward(ins_ctx c, const T* u, T* m) {
+void closure_forward(ins_ctx c, const T* u, T* m, bool keep_z = true) {
+    // the float32 pre-activations are kept only when a pullback will need them
     const ins::Grid& g = c->g;
+    float* z1 = keep_z ? c->z1 : nullptr;
+    float* z2 = keep_z ? c->z2 : nullptr;
     c->launch("cnn_pack_input", [&] { return ins::launch_closure_pack_input<T>(g, u, c->x0, c->stream); });
     c->launch("cnn_conv1", [&] {
-        return ins::launch_closure_conv<T>(g, 0, c->x0, c->wf[0], c->theta + kB1, nullptr, c->z1, c->a1, nullptr, c->stream);
+        return ins::launch_closure_conv<T>(g, 0, c->x0, c->wf[0], c->theta + kB1, nullptr, z1, c->a1, nullptr, c->stream);
     });
     c->launch("cnn_conv2", [&] {
-        return ins::launch_closure_conv<T>(g, 1, c->a1, c->wf[1], c->theta + kB2, nullptr, c->z2, c->a2, nullptr, c->stream);
+        return ins::launch_closure_conv<T>(g, 1, c->a1, c->wf[1], c->theta + kB2, nullptr, z2, c->a2, nullptr, c->stream);
     });
     c->launch("cnn_conv3", [&] {
         return ins::launch_closure_conv<T>(g, 2, c->a2, c->wf[2], c->theta + kB3, nullptr, nullptr, nullptr, m, c->stream);
@@ -403,7 +406,7 @@ void closure_backward(ins_ctx c, const T* mbar, T* ubar) {
 
 // Closure term at the stage velocity u_i = (p ? w - G p : w); returns m or nullptr.
 template <typename T>
-const T* closure_at_stage(ins_ctx c, const T* w, const double* p) {
+const T* closure_at_stage(ins_ctx c, const T* w, const double* p, bool keep_z = false) {
     if (!c->clos_on) return nullptr;
     const T* u = w;
     if (p) {
@@ -412,7 +415,7 @@ const T* closure_at_stage(ins_ctx c, const T* w, const double* p) {
         u = ui;
     }
     T* m = static_cast<T*>(c->mclos);
-    closure_forward<T>(c, u, m);
+    closure_forward<T>(c, u, m, keep_z);
     return m;
 }
 
@@ -468,7 +471,7 @@ void stage_vjp(ins_ctx c, const T* w, const double* p, bool proj_u, const T* yba
     });
     if (c->clos_on) {
         // the closure's share of the stage pullback: m_bar = Fbar_i, at u_i
-        closure_at_stage<T>(c, w, proj_u ? p : nullptr);
+        closure_at_stage<T>(c, w, proj_u ? p : nullptr, true);
         closure_backward<T>(c, fb, mode >= 2 ? u0bar : out);
     }
 }
@@ -963,7 +966,7 @@ ins_status ins_cnn_forward(ins_ctx ctx, const void* u, void* m) {
         if (!ctx->clos_on) raise(INS_ERR_INVALID, "no closure has been set");
         with_type(ctx, [&](auto tag) {
             using T = decltype(tag);
-            closure_forward<T>(ctx, static_cast<const T*>(u), static_cast<T*>(m));
+            closure_forward<T>(ctx, static_cast<const T*>(u), static_cast<T*>(m), false);
         });
     });
 }

@@ -9,11 +9,13 @@
 // v_mfma_f32_16x16x32_bf16 tiles (lane l holds A[m = l%16][k = 8(l/16)+j],
 // B[k = 8(l/16)+j][n = l%16], D[m = 4(l/16)+i][n = l%16]). A K tile of 32 is
 // one tap x 32 channels (C = 32) or four taps x 8 channels (C = 8); every lane
-// fetches its 8 bfloat16 operands with one 16-byte load. Weights are packed per
-// K tile ([kt][n][32]) and staged once per workgroup in LDS. The input
-// gradient (dgrad) is the same kernel with flipped taps and transposed
-// weights; the weight gradient (wgrad) reduces over cells with operands
-// transposed through LDS and per-workgroup partial sums.
+// fetches its 8 bfloat16 operands with one 16-byte load. A workgroup stages
+// its input block (with the periodic halo) in LDS once and reads all 27 taps'
+// A operands from there; weights are packed per K tile ([kt][n][32]) and read
+// from global memory, where they stay cache-resident. The input gradient
+// (dgrad) is the same kernel with flipped taps and transposed weights; the
+// weight gradient (wgrad) reduces over cells with operands transposed through
+// LDS and per-workgroup partial sums.
 #include <hip/hip_bf16.h>
 
 #include "k_common.hpp"
@@ -56,6 +58,10 @@ __device__ __forceinline__ RowPos row_of(const Grid& g, int first_cell) {
 }
 
 __device__ __forceinline__ int wrapi(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+__device__ __forceinline__ int pmod_i(int v, int n) {
+    const int r = v % n;
+    return r < 0 ? r + n : r;
+}
 
 // First cell of the row shifted by (dy, dz) with periodic wrap.
 __device__ __forceinline__ int row_start(const Grid& g, const RowPos& r, int dy, int dz) {
@@ -79,102 +85,182 @@ enum { EPI_HIDDEN = 0, EPI_OUT = 1, EPI_DGRAD_HIDDEN = 2, EPI_DGRAD_INPUT = 3 };
 // Implicit-GEMM 3x3x3 convolution over all cells of the batch.
 //   in   : [cells][CIN] bfloat16
 //   wpk  : [NKT][NT*16][32] bfloat16 packed weights (zero where k or n is padding)
-//   EPI_HIDDEN      : z = acc + bias -> zout [cells][32] fp32, a = bf16(gelu(z)) -> aout [cells][32]
+//   EPI_HIDDEN      : z = acc + bias -> zout [cells][32] fp32 (unless null), a = bf16(gelu(z)) -> aout [cells][32]
 //   EPI_OUT         : m[b][n][cell] = acc + bias (n < nout), field type T (planar velocity layout)
 //   EPI_DGRAD_HIDDEN: zbar = acc * gelu'(zin[cell][n]) -> aout [cells][32] bf16
 //   EPI_DGRAD_INPUT : ubar[b][n][cell] += acc (n < nout), field type T
+// The input block is staged in LDS. A workgroup owns a
+// 32 x 4 x 2 block of output cells (x, y, z); it copies the 34 x 6 x 4 input
+// block (periodic halo included) into LDS once, so the 27 taps read their A
+// operands from LDS instead of re-fetching them from memory. Wave w computes
+// the output rows (y, z) = (r % 4, r / 4), r = 2w, 2w + 1: four 16-cell M tiles.
+// B operands (packed weights) come from global memory (every wave of every
+// workgroup reads the same few KB per tap; they stay cache-resident). Hidden
+// layer outputs are staged through LDS so that every global store is a full
+// 16-byte chunk of one cell. In LDS the input block is split by 8-channel
+// chunk, xs[chunk][cell][8]: the 16 lanes of an operand fetch read 16
+// consecutive 16-byte cells (no bank conflicts, every access 16-byte aligned).
+constexpr int kCbX = 32, kCbY = 4, kCbZ = 2, kCbCells = kCbX * kCbY * kCbZ;
+constexpr int kChX = kCbX + 2, kChY = kCbY + 2, kChZ = kCbZ + 2, kChCells = kChX * kChY * kChZ;
+
+template <int CIN>
+constexpr size_t conv_t_lds_bytes() {
+    constexpr size_t halo = size_t(kChCells) * CIN * 2;
+    constexpr size_t epi = size_t(kCbCells) * 32 * (4 + 2);  // float32 z (or zin) + bfloat16 out
+    return halo > epi ? halo : epi;
+}
+
 template <typename T, int CIN, int NT, int EPI>
-__global__ __launch_bounds__(kBlock) void k_conv(Grid g, int64_t ncells, const u16* __restrict__ in,
-                                                   const u16* __restrict__ wpk, const float* __restrict__ bias,
-                                                   const float* __restrict__ zin, float* __restrict__ zout,
-                                                   u16* __restrict__ aout, T* __restrict__ fout, int nout) {
+__global__ __launch_bounds__(kBlock) void k_conv_t(Grid g, const u16* __restrict__ in, const u16* __restrict__ wpk,
+                                                     const float* __restrict__ bias, const float* __restrict__ zin,
+                                                     float* __restrict__ zout, u16* __restrict__ aout,
+                                                     T* __restrict__ fout, int nout) {
     constexpr int NKT = (kTaps * CIN + 31) / 32;
-    constexpr int MT = 2;                       // M tiles (16 cells each) per wave
-    constexpr int SEG = 4 * MT * 16;            // cells per workgroup iteration
-    extern __shared__ __attribute__((aligned(16))) u16 wl[];  // NKT * NT*16 * 32
+    constexpr int MT = 4;
+    constexpr int CH = CIN / 8;  // 16-byte chunks per cell
+    extern __shared__ __attribute__((aligned(16))) u16 xs[];
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const int nbx = nx / kCbX, nby = (ny + kCbY - 1) / kCbY, nbz = (nz + kCbZ - 1) / kCbZ;
+    int L = xcd_logical(blockIdx.x, gridDim.x);
+    const int bx = L % nbx;
+    L /= nbx;
+    const int by = L % nby;
+    L /= nby;
+    const int bz = L % nbz;
+    const int b = L / nbz;
+    const int x0 = bx * kCbX, y0 = by * kCbY, z0 = bz * kCbZ;
     const int tid = threadIdx.x;
-    {
-        const int n16 = NKT * NT * 16 * 32 / 8;  // 16-byte chunks
-        const uint4* src = reinterpret_cast<const uint4*>(wpk);
-        uint4* dst = reinterpret_cast<uint4*>(wl);
-        for (int i = tid; i < n16; i += kBlock) dst[i] = src[i];
+    const int64_t bcell = int64_t(b) * nz * ny * nx;
+    // 1. input block with periodic halo -> LDS
+    for (int cell = tid; cell < kChCells; cell += kBlock) {
+        const int hx = cell % kChX, hy = (cell / kChX) % kChY, hz = cell / (kChX * kChY);
+        const int gx = wrapi(x0 - 1 + hx, nx);
+        const int gy = pmod_i(y0 - 1 + hy, ny), gz = pmod_i(z0 - 1 + hz, nz);
+        const int64_t gc = bcell + (int64_t(gz) * ny + gy) * nx + gx;
+        uint4 v[CH];
+#pragma unroll
+        for (int ch = 0; ch < CH; ++ch) v[ch] = *reinterpret_cast<const uint4*>(in + gc * CIN + ch * 8);
+#pragma unroll
+        for (int ch = 0; ch < CH; ++ch) *reinterpret_cast<uint4*>(xs + (ch * kChCells + cell) * 8) = v[ch];
     }
     __syncthreads();
+    // 2. implicit GEMM from LDS
     const int lane = tid & 63, wave = tid >> 6;
     const int lm = lane & 15, gq = lane >> 4;
-    const int64_t nseg = (ncells + SEG - 1) / SEG;
-    for (int64_t seg = blockIdx.x; seg < nseg; seg += gridDim.x) {
-        const int64_t base = seg * SEG + int64_t(wave) * MT * 16;
-        f32x4 acc[MT][NT];
+    f32x4 acc[MT][NT];
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
+    for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-        RowPos rp[MT];
-        int xs[MT][3];
+        for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    int hbase[MT];  // halo cell of (tap offset 0, 0, 0) for this lane's row of each M tile
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        const int r = 2 * wave + (mt >> 1);
+        const int yy = r % kCbY, zz = r / kCbY;
+        hbase[mt] = (zz * kChY + yy) * kChX + (mt & 1) * 16 + lm;
+    }
+#pragma unroll 3
+    for (int kt = 0; kt < NKT; ++kt) {
+        int tap, c0;
+        ktile_tap<CIN>(kt, gq, tap, c0);
+        const bool tap_ok = tap < kTaps;
+        const int t = tap_ok ? tap : 0;
+        const int toff = ((t / 9) * kChY + (t / 3) % 3) * kChX + t % 3;
+        bf16x8 bv[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+            bv[nt] = *reinterpret_cast<const bf16x8*>(wpk + ((kt * NT * 16 + nt * 16 + lm) * 32 + 8 * gq));
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
-            int c = int(base) + mt * 16;
-            c = c < ncells ? c : int(ncells) - 16;  // a tail tile reads valid cells; its results are not stored
-            rp[mt] = row_of(g, c);
-            const int x = rp[mt].x0 + lm;
-            xs[mt][0] = wrapi(x - 1, g.nx);
-            xs[mt][1] = x;
-            xs[mt][2] = wrapi(x + 1, g.nx);
-        }
-#pragma unroll 3
-        for (int kt = 0; kt < NKT; ++kt) {
-            int tap, c0;
-            ktile_tap<CIN>(kt, gq, tap, c0);
-            const bool tap_ok = tap < kTaps;
-            const int t = tap_ok ? tap : 0;
-            const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dxi = t % 3;
-            bf16x8 bv[NT];
+            bf16x8 av;
+            if (tap_ok) {
+                av = *reinterpret_cast<const bf16x8*>(xs + ((c0 >> 3) * kChCells + hbase[mt] + toff) * 8);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) av[j] = __bf16(0.0f);
+            }
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt)
-                bv[nt] = *reinterpret_cast<const bf16x8*>(wl + ((kt * NT * 16 + nt * 16 + lm) * 32 + 8 * gq));
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) {
-                bf16x8 av;
-                if (tap_ok) {
-                    const int nc = row_start(g, rp[mt], dy, dz) + xs[mt][dxi];
-                    av = *reinterpret_cast<const bf16x8*>(in + int64_t(nc) * CIN + c0);
-                } else {
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) av[j] = __bf16(0.0f);
-                }
-#pragma unroll
-                for (int nt = 0; nt < NT; ++nt)
-                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[nt], acc[mt][nt], 0, 0, 0);
-            }
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[nt], acc[mt][nt], 0, 0, 0);
         }
-        // epilogue: lane holds D[m = 4 gq + i][n = nt*16 + lm]
-        const int64_t vol = int64_t(g.nx) * g.ny * g.nz;
+    }
+    // 3. epilogue: lane holds D[m = 4 gq + i][n = nt*16 + lm] of M tile mt, i.e. block
+    // cell q = r * 32 + (mt & 1) * 16 + 4 gq + i with r = 2 wave + (mt >> 1)
+    auto block_cell = [&](int q, int64_t& c) -> bool {
+        const int r = q >> 5, xx = q & 31;
+        const int yy = y0 + r % kCbY, zz = z0 + r / kCbY;
+        c = bcell + (int64_t(zz) * ny + yy) * nx + x0 + xx;
+        return yy < ny && zz < nz;
+    };
+    if constexpr (EPI == EPI_HIDDEN || EPI == EPI_DGRAD_HIDDEN) {
+        float* zt = reinterpret_cast<float*>(xs);                 // [256][32] float32
+        u16* at = reinterpret_cast<u16*>(xs + kCbCells * 32 * 2);  // [256][32] bfloat16
+        __syncthreads();  // every wave is done reading the input block
+        if constexpr (EPI == EPI_DGRAD_HIDDEN) {
+            for (int e = tid; e < kCbCells * 8; e += kBlock) {  // zin block, 16-byte chunks
+                const int q = e >> 3, ch = e & 7;
+                int64_t c;
+                float4 v = {0.f, 0.f, 0.f, 0.f};
+                if (block_cell(q, c)) v = *reinterpret_cast<const float4*>(zin + c * 32 + ch * 4);
+                *reinterpret_cast<float4*>(zt + q * 32 + ch * 4) = v;
+            }
+            __syncthreads();
+        }
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
+            const int qb = (2 * wave + (mt >> 1)) * 32 + (mt & 1) * 16 + 4 * gq;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int64_t c = base + mt * 16 + 4 * gq + i;
-                if (c >= ncells) continue;
+                const int q = qb + i;
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt) {
                     const int n = nt * 16 + lm;
                     const float v = acc[mt][nt][i];
                     if constexpr (EPI == EPI_HIDDEN) {
                         const float z = v + bias[n];
-                        zout[c * 32 + n] = z;
-                        aout[c * 32 + n] = bf16_bits(gelu_f(z));
-                    } else if constexpr (EPI == EPI_DGRAD_HIDDEN) {
-                        aout[c * 32 + n] = bf16_bits(v * gelu_grad_f(zin[c * 32 + n]));
+                        zt[q * 32 + n] = z;
+                        at[q * 32 + n] = bf16_bits(gelu_f(z));
                     } else {
-                        if (n < nout) {
-                            const int64_t b = c / vol, r = c - b * vol;
-                            T* dst = fout + (b * 3 + n) * vol + r;
-                            if constexpr (EPI == EPI_OUT)
-                                *dst = T(v + bias[n]);
-                            else
-                                *dst = T(double(*dst) + double(v));
-                        }
+                        at[q * 32 + n] = bf16_bits(v * gelu_grad_f(zt[q * 32 + n]));
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        for (int e = tid; e < kCbCells * 4; e += kBlock) {  // bfloat16 out: 4 chunks per cell
+            const int q = e >> 2, ch = e & 3;
+            int64_t c;
+            if (block_cell(q, c))
+                *reinterpret_cast<uint4*>(aout + c * 32 + ch * 8) = *reinterpret_cast<const uint4*>(at + q * 32 + ch * 8);
+        }
+        if (EPI == EPI_HIDDEN && zout) {
+            for (int e = tid; e < kCbCells * 8; e += kBlock) {  // float32 z: 8 chunks per cell
+                const int q = e >> 3, ch = e & 7;
+                int64_t c;
+                if (block_cell(q, c))
+                    *reinterpret_cast<float4*>(zout + c * 32 + ch * 4) = *reinterpret_cast<const float4*>(zt + q * 32 + ch * 4);
+            }
+        }
+    } else {
+        const int64_t vol = int64_t(nx) * ny * nz;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            const int qb = (2 * wave + (mt >> 1)) * 32 + (mt & 1) * 16 + 4 * gq;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                int64_t c;
+                if (!block_cell(qb + i, c)) continue;
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) {
+                    const int n = nt * 16 + lm;
+                    if (n < nout) {
+                        const int64_t r = c - int64_t(b) * vol;
+                        T* dst = fout + (int64_t(b) * 3 + n) * vol + r;
+                        const float v = acc[mt][nt][i];
+                        if constexpr (EPI == EPI_OUT)
+                            *dst = T(v + bias[n]);
+                        else
+                            *dst = T(double(*dst) + double(v));
                     }
                 }
             }
@@ -378,11 +464,6 @@ __global__ void k_wgrad_reduce(const float* __restrict__ partial, int nwg, int c
 // ----------------------------------------------------------------------------
 // Launchers
 // ----------------------------------------------------------------------------
-int conv_grid(int64_t ncells) {
-    const int64_t nseg = (ncells + 127) / 128;
-    return int(nseg < 2048 ? nseg : 2048);
-}
-
 template <typename T>
 hipError_t launch_closure_pack_input(const Grid& g, const T* u, u16* x0, hipStream_t s) {
     const int64_t vol = int64_t(g.nx) * g.ny * g.nz, n = vol * g.batch;
@@ -403,35 +484,19 @@ hipError_t launch_closure_pack_weights(const float* w, int cin, int cout, int ci
 template <typename T>
 hipError_t launch_closure_conv(const Grid& g, int which, const u16* in, const u16* wpk, const float* bias,
                                const float* zin, float* zout, u16* aout, T* fout, hipStream_t s) {
-    const int64_t n = int64_t(g.nx) * g.ny * g.nz * g.batch;
-    const int grid = conv_grid(n);
-    auto shm = [](int cin, int nt) { return size_t((kTaps * cin + 31) / 32) * nt * 16 * 32 * 2; };
+    const int grid = (g.nx / kCbX) * ((g.ny + kCbY - 1) / kCbY) * ((g.nz + kCbZ - 1) / kCbZ) * g.batch;
+#define INS_CONV(CIN, NT, EPI, NOUT)                                                                              \
+    hipLaunchKernelGGL((k_conv_t<T, CIN, NT, EPI>), dim3(grid), dim3(kBlock), conv_t_lds_bytes<CIN>(), s, g, in, wpk, \
+                       bias, zin, zout, aout, fout, NOUT)
     switch (which) {
-        case 0:
-            hipLaunchKernelGGL((k_conv<T, 8, 2, EPI_HIDDEN>), dim3(grid), dim3(kBlock), shm(8, 2), s, g, n, in, wpk, bias,
-                               zin, zout, aout, fout, 32);
-            break;
-        case 1:
-            hipLaunchKernelGGL((k_conv<T, 32, 2, EPI_HIDDEN>), dim3(grid), dim3(kBlock), shm(32, 2), s, g, n, in, wpk,
-                               bias, zin, zout, aout, fout, 32);
-            break;
-        case 2:
-            hipLaunchKernelGGL((k_conv<T, 32, 1, EPI_OUT>), dim3(grid), dim3(kBlock), shm(32, 1), s, g, n, in, wpk, bias,
-                               zin, zout, aout, fout, 3);
-            break;
-        case 10:
-            hipLaunchKernelGGL((k_conv<T, 8, 2, EPI_DGRAD_HIDDEN>), dim3(grid), dim3(kBlock), shm(8, 2), s, g, n, in, wpk,
-                               bias, zin, zout, aout, fout, 32);
-            break;
-        case 11:
-            hipLaunchKernelGGL((k_conv<T, 32, 2, EPI_DGRAD_HIDDEN>), dim3(grid), dim3(kBlock), shm(32, 2), s, g, n, in,
-                               wpk, bias, zin, zout, aout, fout, 32);
-            break;
-        default:
-            hipLaunchKernelGGL((k_conv<T, 32, 1, EPI_DGRAD_INPUT>), dim3(grid), dim3(kBlock), shm(32, 1), s, g, n, in,
-                               wpk, bias, zin, zout, aout, fout, 3);
-            break;
+        case 0: INS_CONV(8, 2, EPI_HIDDEN, 32); break;
+        case 1: INS_CONV(32, 2, EPI_HIDDEN, 32); break;
+        case 2: INS_CONV(32, 1, EPI_OUT, 3); break;
+        case 10: INS_CONV(8, 2, EPI_DGRAD_HIDDEN, 32); break;
+        case 11: INS_CONV(32, 2, EPI_DGRAD_HIDDEN, 32); break;
+        default: INS_CONV(32, 1, EPI_DGRAD_INPUT, 3); break;
     }
+#undef INS_CONV
     return hipGetLastError();
 }
 
