@@ -38,3 +38,4 @@ from .ins import (  # noqa: F401
     rollout_loss_grad,
 )
 from .aux import face_filter, energy_spectrum  # noqa: F401
+from . import eddy  # noqa: F401,E402
