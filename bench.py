@@ -201,6 +201,11 @@ def les_closure_timing(steps, warmup):
     nadj = max(2, steps // 4)
     ms_adj, prof_adj = time_steps(lambda: (les.step(u, 4e-3, out=u1), les.step_vjp(u, ubar, 4e-3, out=g)), nadj, 1,
                                   solver=les)
+    # the classical baseline closure on the same LES: Smagorinsky eddy viscosity (C_s = 0.17)
+    les.set_closure(None)
+    les.set_eddy(0.17)
+    ms_smag, _ = time_steps(lambda: les.step(u, 4e-3, out=u1), steps, warmup)
+    ms_smag_adj, _ = time_steps(lambda: (les.step(u, 4e-3, out=u1), les.step_vjp(u, ubar, 4e-3, out=g)), nadj, 1)
     les.close()
     ncl = 4 * 128 ** 3
     conv2 = prof_fwd.get("cnn_conv2")
@@ -219,6 +224,8 @@ def les_closure_timing(steps, warmup):
         "les_closure_ms_per_step": round(cnn_ms, 3),
         "les_step_plus_vjp_ms": round(ms_adj, 3),
         "dns512_step_ms": round(ms_dns, 3),
+        "les_smagorinsky_step_ms": round(ms_smag, 3),
+        "les_smagorinsky_step_plus_vjp_ms": round(ms_smag_adj, 3),
         "speedup_vs_dns_same_time_span": round(4 * 4 * ms_dns / ms_fwd, 1),
         # layer 2 (32 -> 32, 3x3x3) is the MFMA-bound contraction: 2 * 864 * 32 flop per cell
         "conv2_mfma": None if conv2_ms is None else {

@@ -236,6 +236,36 @@ ins_status ins_cnn_forward(ins_ctx ctx, const void* u, void* m);
 ins_status ins_cnn_backward(ins_ctx ctx, const void* u, const void* mbar, void* ubar, float* params_bar);
 
 /* ---------------------------------------------------------------------------
+ * Smagorinsky eddy-viscosity closure (appendix on eddy-viscosity models:
+ * general framework and eq. smagorinsky), the classical LES baseline.
+ * On the staggered grid: D_a = delta_a u^a at pressure points, G_ab =
+ * delta_b u^a on the (a, b) edges; the velocity gradient at a pressure point
+ * averages G_ab over its four (a, b) edges; nu_t = (C_s Delta)^2 sqrt(2 S:S)
+ * at pressure points and, on an edge, the mean of its four pressure points.
+ * The right-hand side gains M^a = sum_b delta_b (2 nu_t S_ab) on the a-faces
+ * (the appendix's sub-grid stress with the sign that dissipates energy), so
+ * steps integrate du/dt = P(F(u) + M(u)). 2D and 3D. One closure at a time:
+ * setting this one replaces a learned closure and vice versa.
+ * ------------------------------------------------------------------------- */
+
+/* Set (cs > 0) or clear (cs == 0, if this closure is the one set) the
+ * Smagorinsky closure with constant cs (the paper proposes 0.17) and filter
+ * width delta (delta <= 0: the geometric mean of the spacings). While set,
+ * ins_rhs, the steps and their pullbacks include it (it has no learnable
+ * parameters). Allocates its workspace (1 + d(d+1)/2 pressure-point fields
+ * of the context type, plus three velocity fields) on first use.
+ * INS_ERR_INVALID for cs < 0 or non-finite arguments. */
+ins_status ins_eddy_set(ins_ctx ctx, double cs, double delta);
+
+/* m = M(u) alone (velocity layout, context type). INS_ERR_INVALID when the
+ * Smagorinsky closure is not set. */
+ins_status ins_eddy_forward(ins_ctx ctx, const void* u, void* m);
+
+/* ubar = (dM/du)^T mbar (overwritten). Where S = 0 the square root has no
+ * derivative and its pullback is taken as 0. ubar must not alias u or mbar. */
+ins_status ins_eddy_backward(ins_ctx ctx, const void* u, const void* mbar, void* ubar);
+
+/* ---------------------------------------------------------------------------
  * LES data helpers (filtered DNS and its spectrum). The paper names the
  * pipeline DNS -> filter -> LES (Sec. 4) but not the filter or the spectrum
  * binning; the readings are stated with each call.

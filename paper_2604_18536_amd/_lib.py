@@ -61,6 +61,9 @@ _SIGS = {
     "ins_step_rk4_vjp": ([_P, _P, _P, _P, _D]),
     "ins_step_wray3": ([_P, _P, _P, _D]),
     "ins_step_wray3_vjp": ([_P, _P, _P, _P, _D]),
+    "ins_eddy_set": ([_P, _D, _D]),
+    "ins_eddy_forward": ([_P, _P, _P]),
+    "ins_eddy_backward": ([_P, _P, _P, _P]),
     "ins_closure_set": ([_P, _P]),
     "ins_closure_grad": ([_P, _P]),
     "ins_cnn_forward": ([_P, _P, _P]),

@@ -115,6 +115,16 @@ hipError_t launch_stage_vjp_zm(const Grid& g, const T* w, const double* p, bool 
                                const double* q, bool has_w, double cb, double cw, T* u0bar, int mode, T* ubar_out,
                                hipStream_t s, T* fbar_out);
 
+// Smagorinsky closure (k_eddy.hip). forward: nu = c2 sqrt(2 S:S) at pressure
+// points, m = sum_b delta_b (2 nu S_ab) on the faces (overwritten). backward:
+// ubar += (dm/du)^T mbar at the u of the forward whose nu is passed; P is
+// scratch of DIM (DIM + 1) / 2 pressure-point fields per batch entry.
+template <typename T>
+hipError_t launch_eddy_forward(const Grid& g, const T* u, T* nu, T* m, double c2, hipStream_t s);
+template <typename T>
+hipError_t launch_eddy_backward(const Grid& g, const T* u, const T* nu, const T* mbar, T* P, T* ubar, double c2,
+                                hipStream_t s);
+
 // LES data helpers.
 // Coarse staggered field: mean of the f^(d-1) fine a-faces on each coarse a-face.
 template <typename T>

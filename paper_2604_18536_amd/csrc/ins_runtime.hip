@@ -159,8 +159,14 @@ struct ins_ctx_s {
     double* p4 = nullptr;
 
     // learned closure (allocated by ins_closure_set)
-    bool clos_on = false;
-    bool clos_alloc = false;
+    bool clos_on = false;     // a closure term is part of the right-hand side
+    int clos_kind = 0;        // 1: learned CNN, 2: Smagorinsky eddy viscosity
+    bool clos_alloc = false;  // CNN workspace allocated
+    bool clos_common = false; // stage / cotangent buffers shared by both kinds allocated
+    double eddy_c2 = 0.0;     // (C_s Delta)^2
+    void* eddy_nu = nullptr;  // eddy viscosity at the pressure points of the last closure_forward
+    void* eddy_P = nullptr;   // pullback scratch
+    const void* eddy_u = nullptr;  // velocity of the last closure_forward (read by its pullback)
     float* theta = nullptr;      // float32 parameters (device copy)
     float* theta_bar = nullptr;  // accumulated parameter gradient
     unsigned short* wf[3] = {nullptr, nullptr, nullptr};  // packed forward weights per layer
@@ -331,6 +337,14 @@ void apply_projection(ins_ctx c, const T* w, const double* p, T* out) {
 constexpr int kClosParams = 32899;
 constexpr int kW1 = 0, kB1 = 2592, kW2 = 2624, kB2 = 30272, kW3 = 30304, kB3 = 32896;
 
+void closure_alloc_common(ins_ctx c) {
+    if (c->clos_common) return;
+    c->mclos = c->alloc(c->vel_bytes());
+    c->ui = c->alloc(c->vel_bytes());
+    c->fbar = c->alloc(c->vel_bytes());
+    c->clos_common = true;
+}
+
 void closure_alloc(ins_ctx c) {
     if (c->clos_alloc) return;
     const size_t n = size_t(c->g.ncell) * c->g.batch;
@@ -352,18 +366,33 @@ void closure_alloc(ins_ctx c) {
     c->z1 = static_cast<float*>(c->alloc(n * 32 * 4));
     c->z2 = static_cast<float*>(c->alloc(n * 32 * 4));
     c->partial = static_cast<float*>(c->alloc(ins::closure_wgrad_partial_floats(int64_t(n)) * 4));
-    c->mclos = c->alloc(c->vel_bytes());
-    c->ui = c->alloc(c->vel_bytes());
-    c->fbar = c->alloc(c->vel_bytes());
+    closure_alloc_common(c);
     c->clos_alloc = true;
     c->launch("fill_zero", [&] { return ins::launch_fill_zero_f(c->theta_bar, kClosParams, c->stream); });
+}
+
+void eddy_alloc(ins_ctx c) {
+    if (c->eddy_nu) return;
+    const size_t es = c->dtype == INS_FP64 ? 8 : 4;
+    const size_t n = size_t(c->g.ncell) * c->g.batch;
+    const int d = c->g.dim;
+    c->eddy_nu = c->alloc(n * es);
+    c->eddy_P = c->alloc(n * es * size_t(d * (d + 1) / 2));
+    closure_alloc_common(c);
 }
 
 // m = m_theta(u); leaves x0, z1, a1, z2, a2 for a following pullback.
 template <typename T>
 void closure_forward(ins_ctx c, const T* u, T* m, bool keep_z = true) {
-    // the float32 pre-activations are kept only when a pullback will need them
     const ins::Grid& g = c->g;
+    if (c->clos_kind == 2) {
+        c->eddy_u = u;
+        c->launch("eddy_forward", [&] {
+            return ins::launch_eddy_forward<T>(g, u, static_cast<T*>(c->eddy_nu), m, c->eddy_c2, c->stream);
+        });
+        return;
+    }
+    // the float32 pre-activations are kept only when a pullback will need them
     float* z1 = keep_z ? c->z1 : nullptr;
     float* z2 = keep_z ? c->z2 : nullptr;
     c->launch("cnn_pack_input", [&] { return ins::launch_closure_pack_input<T>(g, u, c->x0, c->stream); });
@@ -383,6 +412,14 @@ void closure_forward(ins_ctx c, const T* u, T* m, bool keep_z = true) {
 template <typename T>
 void closure_backward(ins_ctx c, const T* mbar, T* ubar) {
     const ins::Grid& g = c->g;
+    if (c->clos_kind == 2) {
+        // at the u of the last closure_forward (the stage velocity, or the caller's u)
+        c->launch("eddy_backward", [&] {
+            return ins::launch_eddy_backward<T>(g, static_cast<const T*>(c->eddy_u), static_cast<const T*>(c->eddy_nu), mbar,
+                                                static_cast<T*>(c->eddy_P), ubar, c->eddy_c2, c->stream);
+        });
+        return;
+    }
     c->launch("cnn_pack_cotangent", [&] { return ins::launch_closure_pack_input<T>(g, mbar, c->gm, c->stream); });
     c->launch("cnn_dgrad3", [&] {
         return ins::launch_closure_conv<T>(g, 10, c->gm, c->wd[2], nullptr, c->z2, nullptr, c->gz2, nullptr, c->stream);
@@ -924,7 +961,10 @@ ins_status ins_closure_set(ins_ctx ctx, const float* params) {
     return guarded([&] {
         checked(ctx);
         if (!params) {
-            ctx->clos_on = false;
+            if (ctx->clos_kind == 1) {
+                ctx->clos_on = false;
+                ctx->clos_kind = 0;
+            }
             return;
         }
         const ins::Grid& g = ctx->g;
@@ -943,6 +983,67 @@ ins_status ins_closure_set(ins_ctx ctx, const float* params) {
             });
         }
         ctx->clos_on = true;
+        ctx->clos_kind = 1;
+    });
+}
+
+ins_status ins_eddy_set(ins_ctx ctx, double cs, double delta) {
+    return guarded([&] {
+        checked(ctx);
+        if (!(cs >= 0.0) || !std::isfinite(cs)) raise(INS_ERR_INVALID, "cs must be finite and >= 0");
+        if (!std::isfinite(delta)) raise(INS_ERR_INVALID, "delta must be finite");
+        if (cs == 0.0) {
+            if (ctx->clos_kind == 2) {
+                ctx->clos_on = false;
+                ctx->clos_kind = 0;
+            }
+            return;
+        }
+        const ins::Grid& g = ctx->g;
+        double width = delta;
+        if (!(width > 0.0)) {  // geometric mean of the spacings
+            double prod = 1.0;
+            for (int a = 0; a < g.dim; ++a) prod /= g.ih[a];
+            width = std::pow(prod, 1.0 / g.dim);
+        }
+        eddy_alloc(ctx);
+        ctx->eddy_c2 = (cs * width) * (cs * width);
+        ctx->clos_on = true;
+        ctx->clos_kind = 2;
+    });
+}
+
+ins_status ins_eddy_forward(ins_ctx ctx, const void* u, void* m) {
+    return guarded([&] {
+        checked(ctx);
+        need(u, "u");
+        need(m, "m");
+        if (ctx->clos_kind != 2) raise(INS_ERR_INVALID, "no eddy-viscosity closure has been set");
+        with_type(ctx, [&](auto tag) {
+            using T = decltype(tag);
+            closure_forward<T>(ctx, static_cast<const T*>(u), static_cast<T*>(m));
+        });
+    });
+}
+
+ins_status ins_eddy_backward(ins_ctx ctx, const void* u, const void* mbar, void* ubar) {
+    return guarded([&] {
+        checked(ctx);
+        need(u, "u");
+        need(mbar, "mbar");
+        need(ubar, "ubar");
+        if (ctx->clos_kind != 2) raise(INS_ERR_INVALID, "no eddy-viscosity closure has been set");
+        if (ubar == u || ubar == mbar) raise(INS_ERR_INVALID, "ubar must not alias u or mbar");
+        with_type(ctx, [&](auto tag) {
+            using T = decltype(tag);
+            const size_t nv = ctx->vel_bytes() / sizeof(T);
+            ctx->launch("fill_zero", [&] {
+                return sizeof(T) == 8 ? ins::launch_fill_zero(reinterpret_cast<double*>(ubar), nv, ctx->stream)
+                                      : ins::launch_fill_zero_f(reinterpret_cast<float*>(ubar), nv, ctx->stream);
+            });
+            closure_forward<T>(ctx, static_cast<const T*>(u), static_cast<T*>(ctx->mclos));
+            closure_backward<T>(ctx, static_cast<const T*>(mbar), static_cast<T*>(ubar));
+        });
     });
 }
 
@@ -963,7 +1064,7 @@ ins_status ins_cnn_forward(ins_ctx ctx, const void* u, void* m) {
         checked(ctx);
         need(u, "u");
         need(m, "m");
-        if (!ctx->clos_on) raise(INS_ERR_INVALID, "no closure has been set");
+        if (ctx->clos_kind != 1) raise(INS_ERR_INVALID, "no learned closure has been set");
         with_type(ctx, [&](auto tag) {
             using T = decltype(tag);
             closure_forward<T>(ctx, static_cast<const T*>(u), static_cast<T*>(m), false);
@@ -978,7 +1079,7 @@ ins_status ins_cnn_backward(ins_ctx ctx, const void* u, const void* mbar, void* 
         need(mbar, "mbar");
         need(ubar, "ubar");
         need(params_bar, "params_bar");
-        if (!ctx->clos_on) raise(INS_ERR_INVALID, "no closure has been set");
+        if (ctx->clos_kind != 1) raise(INS_ERR_INVALID, "no learned closure has been set");
         with_type(ctx, [&](auto tag) {
             using T = decltype(tag);
             const size_t nv = ctx->vel_bytes() / sizeof(T);

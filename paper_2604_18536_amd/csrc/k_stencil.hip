@@ -26,12 +26,12 @@ __global__ __launch_bounds__(kBlock) void k_rhs(Grid g, const T* __restrict__ u,
 }
 
 // RK4 stage on 2D grids (3D grids use the z-march of k_stage3d.hip):
-// u_i = (PROJ ? w - G p : w), F = F(u_i),
+// u_i = (PROJ ? w - G p : w), F = F(u_i) (+ mc, the closure term at u_i, if given),
 // (if y) y = (yinit ? u0 : y) + cy F, and (if wout) wout = u0 + cw F.
 template <typename T, int DIM, bool PROJ>
 __global__ __launch_bounds__(kBlock) void k_stage(Grid g, const T* __restrict__ w, const double* __restrict__ p,
                                                    const T* __restrict__ u0, T* __restrict__ y, int yinit, T cy,
-                                                   T* __restrict__ wout, T cw) {
+                                                   T* __restrict__ wout, T cw, const T* __restrict__ mc) {
     const TileIdx t = tile_of(g);
     if (!t.valid) return;
     const Nb nb = make_nb<DIM>(g, t.x, t.y, t.z);
@@ -43,6 +43,7 @@ __global__ __launch_bounds__(kBlock) void k_stage(Grid g, const T* __restrict__ 
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
         const int64_t k = boff + a * g.ncell + c0;
+        if (mc) F[a] += mc[k];
         const T base = (wout || yinit) ? u0[k] : T(0);
         if (y) y[k] = (yinit ? base : y[k]) + cy * F[a];
         if (wout) wout[k] = base + cw * F[a];
@@ -190,9 +191,11 @@ hipError_t launch_stage(const Grid& g, const T* w, const double* p, bool proj, c
     const int nblk = stencil_blocks(g);
     const int yi = yinit ? 1 : 0;
     if (proj)
-        hipLaunchKernelGGL((k_stage<T, 2, true>), dim3(nblk), dim3(kBlock), 0, s, g, w, p, u0, y, yi, T(cy), wout, T(cw));
+        hipLaunchKernelGGL((k_stage<T, 2, true>), dim3(nblk), dim3(kBlock), 0, s, g, w, p, u0, y, yi, T(cy), wout, T(cw),
+                           mc);
     else
-        hipLaunchKernelGGL((k_stage<T, 2, false>), dim3(nblk), dim3(kBlock), 0, s, g, w, p, u0, y, yi, T(cy), wout, T(cw));
+        hipLaunchKernelGGL((k_stage<T, 2, false>), dim3(nblk), dim3(kBlock), 0, s, g, w, p, u0, y, yi, T(cy), wout, T(cw),
+                           mc);
     return hipGetLastError();
 }
 

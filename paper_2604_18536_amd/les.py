@@ -11,8 +11,10 @@ on the GPU path of this library:
    back-propagates the trajectory MSE through the hand-written step pullback
    (which also returns the closure's parameter gradient), checkpointing inside
    the unroll.
-3. ``spectrum_error``: LES with and without the closure against the filtered
-   DNS, compared by mean_k |log E_LES(k) - log E_fDNS(k)|.
+3. ``spectrum_error`` / ``rollout_mse``: LES with no model, with the
+   Smagorinsky eddy viscosity (the classical baseline of the paper's appendix)
+   and with the trained closure against the filtered DNS, compared by
+   mean_k |log E_LES(k) - log E_fDNS(k)| and by the trajectory MSE.
 
 ``python -m paper_2604_18536_amd.les`` runs the full-size workload (DNS 512^3
 FP32, nu = 1/2000, k0 = 4, dt = 1e-3, 4x face filter to 128^3, LES dt = 4e-3,
@@ -103,12 +105,26 @@ def train(data, nu, dt, iters, unroll=10, batch=4, lr=1e-3, seed=0, checkpoint_e
     return theta.detach(), history
 
 
+SMAGORINSKY = "smagorinsky"
+
+
+def _attach(les, closure):
+    """closure: None (no model), SMAGORINSKY (eddy viscosity, C_s = 0.17) or CNN parameters."""
+    if closure is None:
+        return
+    if isinstance(closure, str):
+        if closure != SMAGORINSKY:
+            raise ValueError(f"unknown closure {closure!r}")
+        les.set_eddy(0.17)
+    else:
+        les.set_closure(closure)
+
+
 def rollout_mse(data, theta, nu, dt, windows, unroll):
-    """Trajectory MSE of the LES (closure if theta is not None) on given windows, no gradient."""
+    """Trajectory MSE of the LES (closure per _attach) on given windows, no gradient."""
     nc = data[0].shape[-1]
     les = Solver((nc,) * 3, nu=nu, precision="fp32" if data[0].dtype == torch.float32 else "fp64", batch=len(windows))
-    if theta is not None:
-        les.set_closure(theta)
+    _attach(les, theta)
     with torch.no_grad():
         loss = les_loss(les, None, data, windows, unroll, dt, unroll)
     les.close()
@@ -120,8 +136,7 @@ def spectrum_error(snaps, theta, nu, dt, start, nsteps):
     mean over k = 1..n/2 of |log E_LES(k) - log E_ref(k)|."""
     nc = snaps.shape[-1]
     les = Solver((nc,) * 3, nu=nu, precision="fp32" if snaps.dtype == torch.float32 else "fp64")
-    if theta is not None:
-        les.set_closure(theta)
+    _attach(les, theta)
     u = snaps[start].clone()
     for _ in range(nsteps):
         les.step(u, dt, out=u)
@@ -164,11 +179,13 @@ def main():
         "train_loss_first": hist[0], "train_loss_last": hist[-1],
         "heldout_mse_no_closure": rollout_mse([test], None, args.nu, dt_les, windows, args.unroll),
         "heldout_mse_closure": rollout_mse([test], theta, args.nu, dt_les, windows, args.unroll),
+        "heldout_mse_smagorinsky": rollout_mse([test], SMAGORINSKY, args.nu, dt_les, windows, args.unroll),
     }
     ns = min(args.eval_steps, test.shape[0] - 1)
     res["spectrum_err_no_closure"], f0 = spectrum_error(test, None, args.nu, dt_les, 0, ns)
     res["spectrum_err_closure"], f1 = spectrum_error(test, theta, args.nu, dt_les, 0, ns)
-    res.update({"finite": f0 and f1, "dns_seconds": round(t_dns, 1), "train_seconds": round(t_train, 1)})
+    res["spectrum_err_smagorinsky"], f2 = spectrum_error(test, SMAGORINSKY, args.nu, dt_les, 0, ns)
+    res.update({"finite": f0 and f1 and f2, "dns_seconds": round(t_dns, 1), "train_seconds": round(t_train, 1)})
     print(json.dumps(res))
 
 

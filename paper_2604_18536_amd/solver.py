@@ -239,6 +239,26 @@ class Solver:
                self._check(ubar, "vel", "ubar"), self._params(pbar, "params_bar"))
         return ubar, pbar
 
+    # ------------------------------------------------ Smagorinsky closure
+    def set_eddy(self, cs=0.17, delta=None):
+        """Attach the Smagorinsky eddy-viscosity closure (cs = 0 detaches it);
+        delta = None takes the geometric mean of the spacings as filter width."""
+        self._sync_stream()
+        L.call("ins_eddy_set", self._ctx, float(cs), 0.0 if delta is None else float(delta))
+
+    def eddy_forward(self, u, out=None):
+        out = self._out(out, u, "vel")
+        self._sync_stream()
+        L.call("ins_eddy_forward", self._ctx, self._check(u, "vel", "u"), self._check(out, "vel", "out"))
+        return out
+
+    def eddy_backward(self, u, mbar, out=None):
+        out = self._out(out, u, "vel")
+        self._sync_stream()
+        L.call("ins_eddy_backward", self._ctx, self._check(u, "vel", "u"), self._check(mbar, "vel", "mbar"),
+               self._check(out, "vel", "out"))
+        return out
+
     # ------------------------------------------------------- LES data helpers
     def face_filter(self, u, factor=4, out=None):
         """Coarse staggered field: mean of the fine faces on each coarse face."""

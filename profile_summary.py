@@ -1,6 +1,9 @@
 """Summarise rocprofv3 output into the text files under profiles/.
 
   python profile_summary.py trace  <kernel_stats.csv> <out.md> <command...>
+  python profile_summary.py trace-variants <kernel_stats.csv> <out.md> <command...>
+      (adds per-variant averages from the run_kernel_trace.csv beside it; for a
+      run of the float64 forward step only, whose dispatch order is fixed)
   python profile_summary.py traffic <fetch counter_collection.csv> <write counter_collection.csv> <out.md> <command...>
 
 `traffic` also updates profiles/traffic.json, the measured HBM bytes per
@@ -46,7 +49,7 @@ def source_hash(files):
     return h.hexdigest()[:16]
 
 
-def trace(stats_csv, out_md, command):
+def trace(stats_csv, out_md, command, variants=False):
     rows = list(csv.DictReader(open(stats_csv)))
     lines = ["# rocprofv3 kernel trace summary", "", "Command:", "", "```", command, "```", "",
              "| kernel | calls | avg us | min us | max us | % time |", "|---|---|---|---|---|---|"]
@@ -54,6 +57,23 @@ def trace(stats_csv, out_md, command):
         name = r["Name"].split("(")[0]
         lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
                      f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
+    if variants:
+        # per launch variant (one template instance serves several, in a fixed dispatch order)
+        tpath = os.path.join(os.path.dirname(stats_csv), os.path.basename(stats_csv).replace("kernel_stats", "kernel_trace"))
+        per = defaultdict(list)
+        disp = defaultdict(list)
+        for r in csv.DictReader(open(tpath)):
+            disp[r["Kernel_Name"].split("(")[0]].append(
+                (int(r["Dispatch_Id"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+        for inst, (vnames, _) in VARIANT_ORDER.items():
+            names = [k for k in disp if k == inst or (inst.endswith((",", "<")) and k.startswith(inst))]
+            durs = [d for _, d in sorted(x for k in names for x in disp[k])]
+            for i, d in enumerate(durs):
+                per[vnames[i % len(vnames)]].append(d)
+        lines += ["", "Per launch variant (dispatches of one template instance assigned in their fixed order):", "",
+                  "| variant | launches | avg us |", "|---|---|---|"]
+        for v, ds in per.items():
+            lines.append(f"| {v} | {len(ds)} | {sum(ds) / len(ds) / 1e3:.1f} |")
     open(out_md, "w").write("\n".join(lines) + "\n")
 
 
@@ -111,8 +131,8 @@ def traffic(fetch_csv, write_csv, out_md, command, copy_bytes=None):
 
 if __name__ == "__main__":
     mode = sys.argv[1]
-    if mode == "trace":
-        trace(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))
+    if mode in ("trace", "trace-variants"):
+        trace(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]), variants=mode == "trace-variants")
     elif mode == "traffic":
         traffic(sys.argv[2], sys.argv[3], sys.argv[4], " ".join(sys.argv[5:]))
     else:

@@ -30,7 +30,8 @@ def test_header_declares_the_boundary():
     names = _declared()
     for must in ["ins_create", "ins_destroy", "ins_rhs", "ins_divergence", "ins_poisson_solve", "ins_project",
                  "ins_step_rk4", "ins_rhs_vjp", "ins_divergence_vjp", "ins_poisson_solve_vjp", "ins_project_vjp",
-                 "ins_step_rk4_vjp", "ins_step_wray3", "ins_step_wray3_vjp"]:
+                 "ins_step_rk4_vjp", "ins_step_wray3", "ins_step_wray3_vjp", "ins_eddy_set", "ins_eddy_forward",
+                 "ins_eddy_backward"]:
         assert must in names
 
 
