@@ -39,33 +39,10 @@ __device__ __forceinline__ float gelu_grad_f(float z) {
     return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
 }
 
-// A run of cells inside one x-row (n_x is a multiple of 32, so a 16-cell tile or
-// a 32-cell strip never straddles rows): its row coordinates, in 32-bit
-// arithmetic (the closure requires fewer than 2^31 cells in the batch).
-struct RowPos {
-    int x0, y, z, b;
-};
-
-__device__ __forceinline__ RowPos row_of(const Grid& g, int first_cell) {
-    RowPos r;
-    const int row = first_cell / g.nx;
-    r.x0 = first_cell - row * g.nx;
-    r.y = row % g.ny;
-    const int zb = row / g.ny;
-    r.z = zb % g.nz;
-    r.b = zb / g.nz;
-    return r;
-}
-
 __device__ __forceinline__ int wrapi(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 __device__ __forceinline__ int pmod_i(int v, int n) {
     const int r = v % n;
     return r < 0 ? r + n : r;
-}
-
-// First cell of the row shifted by (dy, dz) with periodic wrap.
-__device__ __forceinline__ int row_start(const Grid& g, const RowPos& r, int dy, int dz) {
-    return ((r.b * g.nz + wrapi(r.z + dz, g.nz)) * g.ny + wrapi(r.y + dy, g.ny)) * g.nx;
 }
 
 // K tile kt, lane group gq: which tap and which first channel the lane's 8 operands hold.
@@ -329,117 +306,165 @@ __global__ void k_pack_weights(const float* __restrict__ w, int cin, int cout, i
     }
 }
 
-// Weight gradient of one layer: W'[n][tap][c] = sum_p g[p][n] x[p + off(tap)][c],
-// bias' [n] = sum_p g[p][n]. The reduction over cells runs over strips of 32
-// cells along x (n_x must be a multiple of 32): with q = p + dx the strip is
-// aligned in q, and the operands are transposed into LDS as
-//   gt[dx][n][q] = g[q - dx][n] (three shifted copies), xt[row][c][q] = x[q, row][c]
-// for the 9 (dy, dz) rows. Wave w accumulates the rows r = w, w+4, w+8.
-// Each workgroup writes its partial sums; k_wgrad_reduce adds them in order.
+// Weight gradient on the same 32 x 4 x 2 cell blocks as k_conv_t:
+// W'[n][tap][c] = sum_p g[p][n] x[p + off(tap)][c], bias'[n] = sum_p g[p][n].
+// A workgroup stages, transposed to channel-major in LDS, the cotangent g of
+// its block (gT[n][p]) and the input x of the block's halo (xT[c][z][y][x]);
+// the K dimension of each MFMA is 32 cells of one block row. Wave w owns the
+// taps w, w + 4, ...; for each block row it loads its A operands (g) once and
+// reuses them for all its taps. A tap's B operand starts dx cells into the
+// halo row, i.e. 0, 2 or 4 bytes past a 16-byte boundary: two aligned reads
+// and a byte-align select it. Cells outside the grid (partial blocks in y or
+// z) stage g = 0. Workgroups loop over blocks and write per-workgroup partial
+// sums (reduced in order by k_wgrad_reduce).
+constexpr int kGtStride = kCbCells + 8;  // gT row: 256 cells + pad (conflict-free A reads)
+constexpr int kXtRow = 40;               // xT halo row: 34 cells padded to 40
+constexpr int kXtStride = kChZ * kChY * kXtRow + 8;
+
 template <int CIN, int COUTP>
-__global__ __launch_bounds__(kBlock) void k_wgrad(Grid g, int64_t ncells, const u16* __restrict__ gin,
-                                                    const u16* __restrict__ xin, float* __restrict__ partial) {
+__global__ __launch_bounds__(kBlock) void k_wgrad_t(Grid g, const u16* __restrict__ gin, const u16* __restrict__ xin,
+                                                      float* __restrict__ partial) {
     constexpr int MT = COUTP == 32 ? 2 : 1;  // tiles of output channels n
     constexpr int NT = CIN == 32 ? 2 : 1;    // tiles of input channels c
-    constexpr int GC = COUTP;                // channels stored per cell in gin
-    __shared__ __attribute__((aligned(16))) u16 gt[3][MT * 16][32];
-    __shared__ __attribute__((aligned(16))) u16 xt[9][NT * 16][32];
+    constexpr int NTAP = 7;                  // taps per wave (27 over 4 waves)
+    extern __shared__ __attribute__((aligned(16))) u16 ws[];
+    u16* gT = ws;                                // [MT*16][kGtStride]
+    u16* xT = ws + MT * 16 * kGtStride;          // [NT*16][kXtStride]
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int lm = lane & 15, gq = lane >> 4;
-    constexpr int NR = 3;  // rows per wave (the ninth row belongs to wave 0)
-    f32x4 acc[NR][3][MT][NT];
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    // padding channels stay zero
+    if constexpr (MT * 16 > COUTP)
+        for (int e = tid; e < (MT * 16 - COUTP) * kGtStride; e += kBlock) gT[COUTP * kGtStride + e] = 0;
+    if constexpr (NT * 16 > CIN)
+        for (int e = tid; e < (NT * 16 - CIN) * kXtStride; e += kBlock) xT[CIN * kXtStride + e] = 0;
+    f32x4 acc[NTAP][MT][NT];
 #pragma unroll
-    for (int r = 0; r < NR; ++r)
+    for (int j = 0; j < NTAP; ++j)
 #pragma unroll
-        for (int d = 0; d < 3; ++d)
+        for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-                for (int nt = 0; nt < NT; ++nt) acc[r][d][mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-    float bacc = 0.f;  // bias partial for channel tid (tid < COUTP)
-    // padding rows (output channels >= COUTP, input channels >= CIN) stay zero
-    if constexpr (MT * 16 > COUTP) {
-        constexpr int PN = MT * 16 - COUTP;
-        for (int e = tid; e < 3 * PN * 32; e += kBlock) gt[e / (PN * 32)][COUTP + (e / 32) % PN][e % 32] = 0;
-    }
-    if constexpr (NT * 16 > CIN) {
-        constexpr int PC = NT * 16 - CIN;
-        for (int e = tid; e < 9 * PC * 32; e += kBlock) xt[e / (PC * 32)][CIN + (e / 32) % PC][e % 32] = 0;
-    }
-    const int64_t nstrip = ncells / 32;
-    for (int64_t s = blockIdx.x; s < nstrip; s += gridDim.x) {
-        const int q0 = int(s) * 32;
-        const RowPos rp = row_of(g, q0);
-        __syncthreads();
-        // gt[d][n][q] = g[q - dx][n], dx = d - 1: 8 channels per 16-byte load
+            for (int nt = 0; nt < NT; ++nt) acc[j][mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float bacc = 0.f;
+    const int nbx = nx / kCbX, nby = (ny + kCbY - 1) / kCbY, nbz = (nz + kCbZ - 1) / kCbZ;
+    const int nblocks = nbx * nby * nbz * g.batch;
+    for (int blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
+        int L = blk;
+        const int bx = L % nbx;
+        L /= nbx;
+        const int by = L % nby;
+        L /= nby;
+        const int bz = L % nbz;
+        const int b = L / nbz;
+        const int x0 = bx * kCbX, y0 = by * kCbY, z0 = bz * kCbZ;
+        const int64_t bcell = int64_t(b) * nz * ny * nx;
+        __syncthreads();  // the previous block's operands are no longer read
+        // g of the block, cell pairs along x: gT[n][q], q = row * 32 + x
         constexpr int G8 = COUTP / 8;
-        const int rs0 = row_start(g, rp, 0, 0);
-        for (int e = tid; e < 3 * 32 * G8; e += kBlock) {
-            const int j8 = e % G8, q = (e / G8) % 32, d = e / (32 * G8);
-            const int p = rs0 + wrapi(rp.x0 + q - (d - 1), g.nx);
-            const uint4 v = *reinterpret_cast<const uint4*>(gin + int64_t(p) * GC + 8 * j8);
-            const unsigned w4[4] = {v.x, v.y, v.z, v.w};
+        for (int e = tid; e < (kCbCells / 2) * G8; e += kBlock) {
+            const int ch = e % G8, pr = e / G8;
+            const int q = 2 * pr, r = q >> 5, xx = q & 31;
+            const int yy = y0 + r % kCbY, zz = z0 + r / kCbY;
+            uint4 v0 = {0u, 0u, 0u, 0u}, v1 = {0u, 0u, 0u, 0u};
+            if (yy < ny && zz < nz) {
+                const int64_t c = bcell + (int64_t(zz) * ny + yy) * nx + x0 + xx;
+                v0 = *reinterpret_cast<const uint4*>(gin + c * COUTP + ch * 8);
+                v1 = *reinterpret_cast<const uint4*>(gin + (c + 1) * COUTP + ch * 8);
+            }
+            const unsigned a[4] = {v0.x, v0.y, v0.z, v0.w}, bb[4] = {v1.x, v1.y, v1.z, v1.w};
 #pragma unroll
-            for (int i = 0; i < 8; ++i) gt[d][8 * j8 + i][q] = u16((w4[i >> 1] >> ((i & 1) * 16)) & 0xffffu);
+            for (int i = 0; i < 8; ++i) {
+                const unsigned lo = (a[i >> 1] >> ((i & 1) * 16)) & 0xffffu;
+                const unsigned hi = (bb[i >> 1] >> ((i & 1) * 16)) & 0xffffu;
+                *reinterpret_cast<unsigned*>(gT + (ch * 8 + i) * kGtStride + q) = lo | (hi << 16);
+            }
         }
-        // xt[row][c][q] = x[q + (0, dy, dz)][c]
+        // x of the halo block, cell pairs along x: xT[c][(hz * 6 + hy) * 40 + hx]
         constexpr int C8 = CIN / 8;
-        for (int e = tid; e < 9 * 32 * C8; e += kBlock) {
-            const int c8 = e % C8, q = (e / C8) % 32, row = e / (32 * C8);
-            const int p = row_start(g, rp, row % 3 - 1, row / 3 - 1) + rp.x0 + q;
-            const uint4 v = *reinterpret_cast<const uint4*>(xin + int64_t(p) * CIN + 8 * c8);
-            const unsigned w4[4] = {v.x, v.y, v.z, v.w};
+        constexpr int NPAIR = kChZ * kChY * (kChX / 2);
+        for (int e = tid; e < NPAIR * C8; e += kBlock) {
+            const int ch = e % C8, pr = e / C8;
+            const int hx = 2 * (pr % (kChX / 2)), hrow = pr / (kChX / 2);
+            const int hy = hrow % kChY, hz = hrow / kChY;
+            const int gy = pmod_i(y0 - 1 + hy, ny), gz = pmod_i(z0 - 1 + hz, nz);
+            const int64_t rowc = bcell + (int64_t(gz) * ny + gy) * nx;
+            const int gx0 = wrapi(x0 - 1 + hx, nx), gx1 = wrapi(x0 + hx, nx);
+            const uint4 v0 = *reinterpret_cast<const uint4*>(xin + (rowc + gx0) * CIN + ch * 8);
+            const uint4 v1 = *reinterpret_cast<const uint4*>(xin + (rowc + gx1) * CIN + ch * 8);
+            const unsigned a[4] = {v0.x, v0.y, v0.z, v0.w}, bb[4] = {v1.x, v1.y, v1.z, v1.w};
 #pragma unroll
-            for (int i = 0; i < 8; ++i) xt[row][8 * c8 + i][q] = u16((w4[i >> 1] >> ((i & 1) * 16)) & 0xffffu);
+            for (int i = 0; i < 8; ++i) {
+                const unsigned lo = (a[i >> 1] >> ((i & 1) * 16)) & 0xffffu;
+                const unsigned hi = (bb[i >> 1] >> ((i & 1) * 16)) & 0xffffu;
+                *reinterpret_cast<unsigned*>(xT + (ch * 8 + i) * kXtStride + hrow * kXtRow + hx) = lo | (hi << 16);
+            }
         }
         __syncthreads();
         if (tid < COUTP) {
-            for (int q = 0; q < 32; ++q) bacc += bf16_val(gt[1][tid][q]);
+            const u16* row = gT + tid * kGtStride;
+            for (int q = 0; q < kCbCells; q += 8) {
+                const uint4 v = *reinterpret_cast<const uint4*>(row + q);
+                const unsigned w4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int i = 0; i < 8; ++i) bacc += bf16_val(u16((w4[i >> 1] >> ((i & 1) * 16)) & 0xffffu));
+            }
         }
-        bf16x8 av[3][MT];
+#pragma unroll 1
+        for (int r = 0; r < kCbY * kCbZ; ++r) {
+            const int yy = r % kCbY, zz = r / kCbY;
+            bf16x8 av[MT];
 #pragma unroll
-        for (int d = 0; d < 3; ++d)
+            for (int mt = 0; mt < MT; ++mt)
+                av[mt] = *reinterpret_cast<const bf16x8*>(gT + (mt * 16 + lm) * kGtStride + r * 32 + 8 * gq);
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt) av[d][mt] = *reinterpret_cast<const bf16x8*>(&gt[d][mt * 16 + lm][8 * gq]);
+            for (int j = 0; j < NTAP; ++j) {
+                const int tap = wave + 4 * j;
+                if (tap >= kTaps) continue;
+                const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
+                const int off = ((zz + dz) * kChY + (yy + dy)) * kXtRow + 8 * gq;
+                const unsigned bs = 2u * unsigned(dx & 1);  // byte shift within a dword
+                const bool wsh = dx == 2;                    // whole-dword shift
 #pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            const int row = wave + 4 * r;
-            if (row >= 9) continue;
-            bf16x8 bv[NT];
+                for (int nt = 0; nt < NT; ++nt) {
+                    const u16* rowp = xT + (nt * 16 + lm) * kXtStride + off;
+                    const uint4 c0 = *reinterpret_cast<const uint4*>(rowp);
+                    const uint4 c1 = *reinterpret_cast<const uint4*>(rowp + 8);
+                    const unsigned d[5] = {wsh ? c0.y : c0.x, wsh ? c0.z : c0.y, wsh ? c0.w : c0.z,
+                                           wsh ? c1.x : c0.w, wsh ? c1.y : c1.x};
+                    unsigned o[4];
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) bv[nt] = *reinterpret_cast<const bf16x8*>(&xt[row][nt * 16 + lm][8 * gq]);
+                    for (int i = 0; i < 4; ++i) o[i] = __builtin_amdgcn_alignbyte(d[i + 1], d[i], bs);
+                    const bf16x8 bv = __builtin_bit_cast(bf16x8, (uint4{o[0], o[1], o[2], o[3]}));
 #pragma unroll
-            for (int d = 0; d < 3; ++d)
-#pragma unroll
-                for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-                    for (int nt = 0; nt < NT; ++nt)
-                        acc[r][d][mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[d][mt], bv[nt], acc[r][d][mt][nt], 0, 0, 0);
+                    for (int mt = 0; mt < MT; ++mt)
+                        acc[j][mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[mt], bv, acc[j][mt][nt], 0, 0, 0);
+                }
+            }
         }
     }
     // partial layout per workgroup: [n (COUTP)][tap][c (CIN)] then bias [COUTP]
     float* out = partial + int64_t(blockIdx.x) * (COUTP * kTaps * CIN + COUTP);
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        const int row = wave + 4 * r;
-        if (row >= 9) continue;
-        const int dy = row % 3, dz = row / 3;
+    for (int j = 0; j < NTAP; ++j) {
+        const int tap = wave + 4 * j;
+        if (tap >= kTaps) continue;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const int tap = dz * 9 + dy * 3 + d;
+        for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
+            for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
-                for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const int n = mt * 16 + 4 * gq + i, c = nt * 16 + lm;
-                        if (n < COUTP && c < CIN) out[(n * kTaps + tap) * CIN + c] = acc[r][d][mt][nt][i];
-                    }
-        }
+                for (int i = 0; i < 4; ++i) {
+                    const int n = mt * 16 + 4 * gq + i, c = nt * 16 + lm;
+                    if (n < COUTP && c < CIN) out[(n * kTaps + tap) * CIN + c] = acc[j][mt][nt][i];
+                }
     }
     if (tid < COUTP) out[COUTP * kTaps * CIN + tid] = bacc;
+}
+
+template <int CIN, int COUTP>
+constexpr size_t wgrad_t_lds_bytes() {
+    return (size_t((COUTP == 32 ? 2 : 1) * 16) * kGtStride + size_t((CIN == 32 ? 2 : 1) * 16) * kXtStride) * 2;
 }
 
 // theta_bar += sum over workgroups of the partials, in workgroup order (deterministic).
@@ -513,14 +538,16 @@ hipError_t launch_closure_wgrad(const Grid& g, int which, const u16* gin, const 
     const int64_t n = int64_t(g.nx) * g.ny * g.nz * g.batch;
     const int grid = wgrad_grid(n);
     int cinp, coutp, cin, cout;
+    constexpr size_t shm0 = wgrad_t_lds_bytes<8, 32>(), shm1 = wgrad_t_lds_bytes<32, 32>(),
+                     shm2 = wgrad_t_lds_bytes<32, 8>();
     if (which == 0) {
-        hipLaunchKernelGGL((k_wgrad<8, 32>), dim3(grid), dim3(kBlock), 0, s, g, n, gin, xin, partial);
+        hipLaunchKernelGGL((k_wgrad_t<8, 32>), dim3(grid), dim3(kBlock), shm0, s, g, gin, xin, partial);
         cinp = 8, coutp = 32, cin = 3, cout = 32;
     } else if (which == 1) {
-        hipLaunchKernelGGL((k_wgrad<32, 32>), dim3(grid), dim3(kBlock), 0, s, g, n, gin, xin, partial);
+        hipLaunchKernelGGL((k_wgrad_t<32, 32>), dim3(grid), dim3(kBlock), shm1, s, g, gin, xin, partial);
         cinp = 32, coutp = 32, cin = 32, cout = 32;
     } else {
-        hipLaunchKernelGGL((k_wgrad<32, 8>), dim3(grid), dim3(kBlock), 0, s, g, n, gin, xin, partial);
+        hipLaunchKernelGGL((k_wgrad_t<32, 8>), dim3(grid), dim3(kBlock), shm2, s, g, gin, xin, partial);
         cinp = 32, coutp = 8, cin = 32, cout = 3;
     }
     hipError_t e = hipGetLastError();
