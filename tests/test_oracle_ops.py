@@ -282,7 +282,7 @@ def _rk4_factor(z):
 
 
 def test_taylor_green_2d_rk4_closed_form():
-    """BASELINE config: 64^2, nu = 0.01, dt = 1e-3, 100 steps.
+    """Taylor-Green vortex, 64^2, nu = 0.01, dt = 1e-3, 100 steps.
 
     The stage map keeps the TG shape (convection is a gradient, removed by the
     projection; the Laplacian scales it by lam = -2*4 sin^2(h/2)/h^2), so
