@@ -235,6 +235,45 @@ def les_closure_timing(steps, warmup):
     }
 
 
+def small_grid_timing(steps):
+    """2D grids that live in the last-level cache (launch-bound): eager steps
+    against the same steps replayed from a recorded HIP graph, and the
+    checkpointed 50-step trajectory-loss gradient on 256^2."""
+    import torch
+
+    import synth as S
+    from paper_2604_18536_amd import Solver
+    from paper_2604_18536_amd import autograd as A
+    from paper_2604_18536_amd.graphs import StepGraph
+
+    out = {}
+    cases = {"taylor_green_64x64_fp64": ((64, 64), "fp64", 0.01, 1e-3, S.taylor_green_2d(64)),
+             "turbulence_256x256_fp32": ((256, 256), "fp32", 5e-4, 2e-3, S.turbulence_ic((256, 256), seed=1, k0=4.0))}
+    for name, (n, prec, nu, dt, u0) in cases.items():
+        s = Solver(n, nu=nu, precision=prec)
+        u = torch.as_tensor(u0).to(device="cuda", dtype=s.dtype).contiguous()
+        ms_eager, _ = time_steps(lambda: s.step(u, dt, out=u), steps, 3)
+        g = StepGraph(s, u, dt, steps)
+        ms_graph, _ = time_steps(g.replay, 3, 1)
+        ms_graph /= steps
+        out[name] = {"eager_ms_per_step": round(ms_eager, 4), "graph_ms_per_step": round(ms_graph, 4),
+                     "graph_mcell_per_s": round(n[0] * n[1] / (ms_graph * 1e-3) / 1e6, 1)}
+        s.close()
+    # 50-step trajectory loss and its gradient (checkpoint every 10), 256^2 FP32
+    n = (256, 256)
+    s = Solver(n, nu=5e-4, precision="fp32")
+    u0 = torch.as_tensor(S.turbulence_ic(n, seed=1, k0=4.0)).to(device="cuda", dtype=torch.float32).contiguous()
+    refs = [torch.zeros_like(u0) for _ in range(50)]
+
+    def grad():
+        t = u0.clone().requires_grad_(True)
+        A.rollout_loss(s, t, 2e-3, refs, checkpoint_every=10).backward()
+    ms_grad, _ = time_steps(grad, 3, 1)
+    out["loss_gradient_50_steps_256x256_fp32_ms"] = round(ms_grad, 3)
+    s.close()
+    return out
+
+
 def cpu_baseline(n, nu, dt, u0_np, budget_s=30.0):
     """The float64 numpy oracle, as written, on the host: RK4 steps of the same field."""
     import oracle as O
@@ -268,7 +307,7 @@ def main():
     ap.add_argument("--config", default="turb256", choices=sorted(CONFIGS))
     ap.add_argument("--n", type=int, default=None, help="override the grid size of the config")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-les", action="store_true", help="skip the closure-LES step timing")
+    ap.add_argument("--no-les", action="store_true", help="skip the closure-LES and small-grid timings")
     ap.add_argument("--modes", default=None)
     args = ap.parse_args()
     cfg = dict(CONFIGS[args.config])
@@ -355,6 +394,7 @@ def main():
     }
     cpu = None if args.no_cpu else cpu_baseline(n, nu, dt, u0)
     les = None if args.no_les or args.config != "turb256" else les_closure_timing(args.steps, args.warmup)
+    small = None if args.no_les or args.config != "turb256" else small_grid_timing(50)
     ms = modes[main_mode]["ms_per_step"]
     line = {
         "metric": METRIC,
@@ -379,6 +419,7 @@ def main():
         "roofline": roofline,
         "stream_copy_gbs": round(copy_gbs, 1),
         "les_closure": les,
+        "small_grids": small,
         "cpu_baseline": cpu,
         "modes": modes,
         "kernels": kernels,

@@ -1,8 +1,9 @@
 /*
  * ins.h - C ABI of the MI355X (gfx950) staggered-grid incompressible
  * Navier-Stokes hot path: matrix-free operators, spectral pressure solve,
- * projection, classical RK4 step, and the pullback (vector-Jacobian product)
- * of each, plus the learned convolutional closure and LES data helpers.
+ * projection, classical RK4 and Wray's low-storage RK3 steps, and the
+ * pullback (vector-Jacobian product) of each, plus the learned convolutional
+ * closure, the Smagorinsky eddy-viscosity closure and LES data helpers.
  *
  * Method: Agdestein & Sanderse, "A differentiable software suite for
  * accelerated simulation of turbulent flows" (arXiv 2604.18536):
@@ -13,6 +14,7 @@
  *   Sec. 3.3   memory: array reuse, low-storage stepping, lazy fluxes
  *   Sec. 3.4   pullback rule and hand-written adjoint kernels
  *   Sec. 4     neural closure inside the solver, a-posteriori training
+ *   App.       eddy-viscosity models (general framework, Smagorinsky)
  *
  * ----------------------------------------------------------------------------
  * Conventions shared by every entry point
@@ -42,7 +44,8 @@
  * context owns its FFT plans, twiddle tables, spectrum, pressure and RK
  * stage registers. Forward workspace is allocated in ins_create; the
  * reverse-pass stage storage on the first *_vjp call that needs it; the
- * closure workspace in ins_closure_set. ins_workspace_bytes reports the total.
+ * closure workspace in ins_closure_set / ins_eddy_set. ins_workspace_bytes
+ * reports the total.
  *
  * Streams. Every call enqueues its kernels on the context's stream
  * (default: the null stream) and returns without a host synchronisation,

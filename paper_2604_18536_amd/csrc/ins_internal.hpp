@@ -35,6 +35,7 @@ struct FftPlan {
     const cd* tw;            // device twiddle table (float64, forward sign)
     int vm;                  // complex values a thread holds per stage (8 or 16)
     int pad;                 // LDS line-stride padding (0 or 1)
+    int nth;                 // threads per workgroup: 256; with vm 8 also 1024 (x pass) or 512 (strided)
 };
 
 // Which FFT pass shape a launch uses.

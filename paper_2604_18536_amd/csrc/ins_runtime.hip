@@ -83,8 +83,9 @@ void build_twiddles(int n, const std::vector<int>& rad, std::vector<cd>& tw, ins
 }
 
 // Largest power-of-two line batch (<= maxl) whose every stage fits the
-// per-thread register budget vm and whose lines (stride nl + pad) fit the LDS budget.
-int lines_for(const ins::FftPlan& pl, int maxl, int vm, int pad) {
+// per-thread register budget vm with nth threads and whose lines (stride
+// nl + pad) fit the LDS budget.
+int lines_for(const ins::FftPlan& pl, int maxl, int vm, int pad, int nth) {
     for (int nl = maxl; nl >= 1; nl >>= 1) {
         if (static_cast<size_t>(nl + pad) * pl.n * sizeof(cd) > kMaxLds) continue;
         bool ok = true;
@@ -92,7 +93,7 @@ int lines_for(const ins::FftPlan& pl, int maxl, int vm, int pad) {
             const int R = pl.rad[s];
             const int bmax = vm / R > 0 ? vm / R : 1;
             const long long nb = static_cast<long long>(nl) * (pl.n / R);
-            if (nb > static_cast<long long>(bmax) * kBlockHost) ok = false;
+            if (nb > static_cast<long long>(bmax) * nth) ok = false;
         }
         if (ok) {
             int l = 0;
@@ -103,17 +104,27 @@ int lines_for(const ins::FftPlan& pl, int maxl, int vm, int pad) {
     return -1;
 }
 
-// Pick the register budget (8 complex values per thread keeps occupancy high)
-// unless it would force batches of fewer than `want` lines, then the widest
-// batch, padding the LDS stride when that does not narrow the batch.
-int choose_lines(ins::FftPlan& pl, int maxl, int want) {
+// Pick the workgroup shape: 8 complex values per thread and 256 threads keep
+// occupancy high and are preferred; when that gives batches of fewer than
+// `want` lines, a wider workgroup with 8 values per thread (`wide` threads),
+// and only then 16 values per thread with 256 threads. The LDS stride is
+// padded when that does not narrow the batch. Measured choices: the x pass
+// may use 1024 threads (10-15% faster at n_x/2 = 420); the strided passes at
+// most 512 (1024 slowed them at 840; 16-line batches of 512 threads were 7%
+// slower than 8 lines of 256 at 256^3).
+int choose_lines(ins::FftPlan& pl, int maxl, int want, int wide) {
+    struct Shape {
+        int vm, nth;
+    };
+    const Shape shapes[3] = {{8, kBlockHost}, {8, wide}, {16, kBlockHost}};
     int best = -1;
-    for (int vm : {8, 16}) {
-        const int lp = lines_for(pl, maxl, vm, 1);
-        const int l0 = lines_for(pl, maxl, vm, 0);
+    for (const Shape& sh : shapes) {
+        const int lp = lines_for(pl, maxl, sh.vm, 1, sh.nth);
+        const int l0 = lines_for(pl, maxl, sh.vm, 0, sh.nth);
         const int l = std::max(lp, l0);
-        if (l < 0) continue;
-        pl.vm = vm;
+        if (l <= best) continue;
+        pl.vm = sh.vm;
+        pl.nth = sh.nth;
         pl.pad = lp >= l0 ? 1 : 0;
         best = l;
         if ((1 << l) >= want) break;
@@ -659,9 +670,9 @@ ins_status ins_create(const ins_grid* grid, ins_bc bc, double nu, ins_dtype dtyp
         build_twiddles(g.nx / 2, rx, tw, c->px);
         build_twiddles(g.ny, ry, tw, c->py);
         if (d == 3) build_twiddles(g.nz, rz, tw, c->pz);
-        c->lnl_x = choose_lines(c->px, 16, 8);
-        c->lnl_y = choose_lines(c->py, 16, 8);
-        c->lnl_z = d == 3 ? choose_lines(c->pz, 16, 8) : 0;
+        c->lnl_x = choose_lines(c->px, 16, 8, 1024);
+        c->lnl_y = choose_lines(c->py, 16, 8, 512);
+        c->lnl_z = d == 3 ? choose_lines(c->pz, 16, 8, 512) : 0;
         // the fused solve along the last axis runs its inverse with the radices
         // reversed, so it starts from the registers the forward's last stage filled
         ins::FftPlan& last = d == 3 ? c->pz : c->py;
@@ -671,6 +682,7 @@ ins_status ins_create(const ins_grid* grid, ins_bc bc, double nu, ins_dtype dtyp
         build_twiddles(last.n, rr, tw, rev);
         rev.vm = last.vm;
         rev.pad = last.pad;
+        rev.nth = last.nth;
         if (c->lnl_x < 0 || c->lnl_y < 0 || c->lnl_z < 0) raise(INS_ERR_UNSUPPORTED, "FFT length too long");
 
         const long double two_pi = 6.283185307179586476925286766559005768L;

@@ -164,7 +164,7 @@ __device__ __forceinline__ void slot_of(int t, int lnl, int S, float rS, int& l,
 // the earlier radices. Butterfly (l, i) takes elements i + q S (S = N / R) of
 // line l, multiplies element q by exp(SIGN 2 pi i q k / (p R)) with k = i mod p,
 // applies DFT_R and produces elements (i - k) R + k + q p. A thread runs
-// butterflies t = threadIdx.x + b kBlock, b < VM / R, in registers.
+// butterflies t = threadIdx.x + b NTH (NTH threads per workgroup), b < VM / R, in registers.
 //   IN  0: inputs from load(l, e) (global memory);  1: from LDS.
 //   OUT 0: outputs to LDS, then a barrier;
 //       1: outputs handed to sink(l, e, z) (last stage: element i + q S);
@@ -174,7 +174,7 @@ __device__ __forceinline__ void slot_of(int t, int lnl, int S, float rS, int& l,
 //          applied at once; its outputs i R + q go to LDS when the inverse has
 //          more stages (`more`), else to sink.
 // The LDS reads of an IN 1 stage that writes LDS are followed by a barrier.
-template <int R, int SIGN, int VM, int IN, int OUT, int MAP, class Load, class Sink, class Div>
+template <int R, int SIGN, int VM, int NTH, int IN, int OUT, int MAP, class Load, class Sink, class Div>
 __device__ __forceinline__ void fft_stage(cd* __restrict__ lds, int lnl, int ls, int N, int p, const cd* __restrict__ tw,
                                           const Load& load, const Sink& sink, const Div& divf, bool more) {
     constexpr int BMAX = VM / R > 0 ? VM / R : 1;
@@ -185,7 +185,7 @@ __device__ __forceinline__ void fft_stage(cd* __restrict__ lds, int lnl, int ls,
     cd w[BMAX * R];
 #pragma unroll
     for (int b = 0; b < BMAX; ++b) {
-        const int t = threadIdx.x + b * kBlock;
+        const int t = threadIdx.x + b * NTH;
         if (t < nb) {
             int l, i;
             slot_of<MAP>(t, lnl, S, rS, l, i);
@@ -199,7 +199,7 @@ __device__ __forceinline__ void fft_stage(cd* __restrict__ lds, int lnl, int ls,
     if constexpr (IN == 1 && OUT != 1) __syncthreads();
 #pragma unroll
     for (int b = 0; b < BMAX; ++b) {
-        const int t = threadIdx.x + b * kBlock;
+        const int t = threadIdx.x + b * NTH;
         if (t < nb) {
             int l, i;
             slot_of<MAP>(t, lnl, S, rS, l, i);
@@ -238,16 +238,16 @@ __device__ __forceinline__ void fft_stage(cd* __restrict__ lds, int lnl, int ls,
     }
 }
 
-template <int SIGN, int VM, int IN, int OUT, int MAP, class Load, class Sink, class Div>
+template <int SIGN, int VM, int NTH, int IN, int OUT, int MAP, class Load, class Sink, class Div>
 __device__ __forceinline__ void fft_stage_r(int R, cd* lds, int lnl, int ls, int N, int p, const cd* tw,
                                             const Load& load, const Sink& sink, const Div& divf, bool more) {
     switch (R) {
-        case 8: fft_stage<8, SIGN, VM, IN, OUT, MAP>(lds, lnl, ls, N, p, tw, load, sink, divf, more); break;
-        case 7: fft_stage<7, SIGN, VM, IN, OUT, MAP>(lds, lnl, ls, N, p, tw, load, sink, divf, more); break;
-        case 5: fft_stage<5, SIGN, VM, IN, OUT, MAP>(lds, lnl, ls, N, p, tw, load, sink, divf, more); break;
-        case 4: fft_stage<4, SIGN, VM, IN, OUT, MAP>(lds, lnl, ls, N, p, tw, load, sink, divf, more); break;
-        case 3: fft_stage<3, SIGN, VM, IN, OUT, MAP>(lds, lnl, ls, N, p, tw, load, sink, divf, more); break;
-        default: fft_stage<2, SIGN, VM, IN, OUT, MAP>(lds, lnl, ls, N, p, tw, load, sink, divf, more); break;
+        case 8: fft_stage<8, SIGN, VM, NTH, IN, OUT, MAP>(lds, lnl, ls, N, p, tw, load, sink, divf, more); break;
+        case 7: fft_stage<7, SIGN, VM, NTH, IN, OUT, MAP>(lds, lnl, ls, N, p, tw, load, sink, divf, more); break;
+        case 5: fft_stage<5, SIGN, VM, NTH, IN, OUT, MAP>(lds, lnl, ls, N, p, tw, load, sink, divf, more); break;
+        case 4: fft_stage<4, SIGN, VM, NTH, IN, OUT, MAP>(lds, lnl, ls, N, p, tw, load, sink, divf, more); break;
+        case 3: fft_stage<3, SIGN, VM, NTH, IN, OUT, MAP>(lds, lnl, ls, N, p, tw, load, sink, divf, more); break;
+        default: fft_stage<2, SIGN, VM, NTH, IN, OUT, MAP>(lds, lnl, ls, N, p, tw, load, sink, divf, more); break;
     }
 }
 
@@ -263,41 +263,41 @@ struct NoOp {
 // pivot of a solve whose inverse plan is Q (then call fft_inverse_rest).
 // The first and last stages are peeled off the loop so that the address
 // arithmetic of the memory-facing stages is not kept live across the others.
-template <int SIGN, int VM, int IN0, int OUTL, int MAP0, int MAPL, class Load, class Sink, class Div>
+template <int SIGN, int VM, int NTH, int IN0, int OUTL, int MAP0, int MAPL, class Load, class Sink, class Div>
 __device__ __forceinline__ void fft_run(cd* lds, int lnl, int ls, const FftPlan& P, const Load& load, const Sink& sink,
                                         const Div& divf, const FftPlan* Q) {
     const int ns = P.nst;
     const bool more = OUTL == 2 && Q->nst > 1;
     if (ns == 1) {
-        fft_stage_r<SIGN, VM, IN0, OUTL, MAP0>(P.rad[0], lds, lnl, ls, P.n, 1, P.tw + P.tw_off[0], load, sink, divf,
+        fft_stage_r<SIGN, VM, NTH, IN0, OUTL, MAP0>(P.rad[0], lds, lnl, ls, P.n, 1, P.tw + P.tw_off[0], load, sink, divf,
                                                 more);
         return;
     }
-    fft_stage_r<SIGN, VM, IN0, 0, MAP0>(P.rad[0], lds, lnl, ls, P.n, 1, P.tw + P.tw_off[0], load, sink, divf, false);
+    fft_stage_r<SIGN, VM, NTH, IN0, 0, MAP0>(P.rad[0], lds, lnl, ls, P.n, 1, P.tw + P.tw_off[0], load, sink, divf, false);
     int p = P.rad[0];
     for (int st = 1; st < ns - 1; ++st) {
-        fft_stage_r<SIGN, VM, 1, 0, kLineFast>(P.rad[st], lds, lnl, ls, P.n, p, P.tw + P.tw_off[st], load, sink, divf,
+        fft_stage_r<SIGN, VM, NTH, 1, 0, kLineFast>(P.rad[st], lds, lnl, ls, P.n, p, P.tw + P.tw_off[st], load, sink, divf,
                                                false);
         p *= P.rad[st];
     }
-    fft_stage_r<SIGN, VM, 1, OUTL, MAPL>(P.rad[ns - 1], lds, lnl, ls, P.n, p, P.tw + P.tw_off[ns - 1], load, sink,
+    fft_stage_r<SIGN, VM, NTH, 1, OUTL, MAPL>(P.rad[ns - 1], lds, lnl, ls, P.n, p, P.tw + P.tw_off[ns - 1], load, sink,
                                          divf, more);
 }
 
 // The stages of inverse plan Q after a pivot consumed its first one (nothing
 // when Q has a single stage): LDS to LDS, the last one to sink (mapping MAPL).
-template <int SIGN, int VM, int MAPL, class Sink>
+template <int SIGN, int VM, int NTH, int MAPL, class Sink>
 __device__ __forceinline__ void fft_inverse_rest(cd* lds, int lnl, int ls, const FftPlan& Q, const Sink& sink) {
     const int ns = Q.nst;
     if (ns == 1) return;
     const NoOp nop;
     int p = Q.rad[0];
     for (int st = 1; st < ns - 1; ++st) {
-        fft_stage_r<SIGN, VM, 1, 0, kLineFast>(Q.rad[st], lds, lnl, ls, Q.n, p, Q.tw + Q.tw_off[st], nop, sink, nop,
+        fft_stage_r<SIGN, VM, NTH, 1, 0, kLineFast>(Q.rad[st], lds, lnl, ls, Q.n, p, Q.tw + Q.tw_off[st], nop, sink, nop,
                                                false);
         p *= Q.rad[st];
     }
-    fft_stage_r<SIGN, VM, 1, 1, MAPL>(Q.rad[ns - 1], lds, lnl, ls, Q.n, p, Q.tw + Q.tw_off[ns - 1], nop, sink, nop,
+    fft_stage_r<SIGN, VM, NTH, 1, 1, MAPL>(Q.rad[ns - 1], lds, lnl, ls, Q.n, p, Q.tw + Q.tw_off[ns - 1], nop, sink, nop,
                                       false);
 }
 
@@ -322,8 +322,8 @@ __device__ __forceinline__ void ld_pair(const float* p, double& a, double& b) {
 // SRC 1: rows of the float64 scalar field r; SRC 2: rows of component `comp` of vel.
 // The first stage reads its inputs straight from memory (element-fast); the
 // untangling needs Z[k] and Z[M-k] together, so the last stage writes to LDS.
-template <typename T, int DIM, int SRC, int VM>
-__global__ __launch_bounds__(kBlock) void k_fft_x_fwd(Grid g, const T* __restrict__ vel, const double* __restrict__ r,
+template <typename T, int DIM, int SRC, int VM, int NTH>
+__global__ __launch_bounds__(NTH) void k_fft_x_fwd(Grid g, const T* __restrict__ vel, const double* __restrict__ r,
                                                         cd* __restrict__ spec, FftPlan P, const cd* __restrict__ post,
                                                         int lnl, int comp) {
     extern __shared__ cd lds[];
@@ -377,9 +377,9 @@ __global__ __launch_bounds__(kBlock) void k_fft_x_fwd(Grid g, const T* __restric
         }
     };
     const NoOp nop;
-    fft_run<-1, VM, 0, 0, kElemFast, kLineFast>(lds, lnl, ls, P, load, nop, nop, nullptr);
+    fft_run<-1, VM, NTH, 0, 0, kElemFast, kLineFast>(lds, lnl, ls, P, load, nop, nop, nullptr);
     const int M1 = M + 1;
-    for (int t = threadIdx.x; t < nl * M1; t += kBlock) {
+    for (int t = threadIdx.x; t < nl * M1; t += NTH) {
         const int l = t / M1, k = t - l * M1;
         const int row = row0 + l;
         if (row >= nrows) continue;
@@ -396,8 +396,8 @@ __global__ __launch_bounds__(kBlock) void k_fft_x_fwd(Grid g, const T* __restric
 // Z[k] = (X[k] + conj X[M-k]) + i (X[k] - conj X[M-k]) conj(W^k), z = IFFT_M(Z),
 // x[2m] = Re z[m], x[2m+1] = Im z[m]. First stage reads the spectrum rows and
 // last stage writes the real rows directly (both element-fast).
-template <int VM>
-__global__ __launch_bounds__(kBlock) void k_fft_x_inv(Grid g, const cd* __restrict__ spec, double* __restrict__ p,
+template <int VM, int NTH>
+__global__ __launch_bounds__(NTH) void k_fft_x_inv(Grid g, const cd* __restrict__ spec, double* __restrict__ p,
                                                         FftPlan P, const cd* __restrict__ post, int lnl) {
     extern __shared__ cd lds[];
     const int nl = 1 << lnl;
@@ -420,7 +420,7 @@ __global__ __launch_bounds__(kBlock) void k_fft_x_inv(Grid g, const cd* __restri
         if (row < nrows) reinterpret_cast<cd*>(p + int64_t(row) * g.nx)[m] = z;
     };
     const NoOp nop;
-    fft_run<1, VM, 0, 1, kElemFast, kElemFast>(lds, lnl, ls, P, load, sink, nop, nullptr);
+    fft_run<1, VM, NTH, 0, 1, kElemFast, kElemFast>(lds, lnl, ls, P, load, sink, nop, nullptr);
 }
 
 // Strided complex pass along y (axis 1) or z (axis 2) of the half spectrum
@@ -435,8 +435,8 @@ __global__ __launch_bounds__(kBlock) void k_fft_x_inv(Grid g, const cd* __restri
 // its outputs in registers, they are divided there, and the inverse runs the
 // stages in reverse radix order (plan Q, whose first radix is P's last) from
 // those same registers.
-template <int MODE, int VM>
-__global__ __launch_bounds__(kBlock) void k_fft_strided(Grid g, cd* __restrict__ spec, FftPlan P, FftPlan Q, int axis,
+template <int MODE, int VM, int NTH>
+__global__ __launch_bounds__(NTH) void k_fft_strided(Grid g, cd* __restrict__ spec, FftPlan P, FftPlan Q, int axis,
                                                           int lnl, SolveTab st) {
     extern __shared__ cd lds[];
     const int nl = 1 << lnl;
@@ -483,9 +483,9 @@ __global__ __launch_bounds__(kBlock) void k_fft_strided(Grid g, cd* __restrict__
     };
     const NoOp nop;
     if constexpr (MODE == 1) {
-        fft_run<1, VM, 0, 1, kLineFast, kLineFast>(lds, lnl, ls, P, load, store, nop, nullptr);
+        fft_run<1, VM, NTH, 0, 1, kLineFast, kLineFast>(lds, lnl, ls, P, load, store, nop, nullptr);
     } else if constexpr (MODE == 0) {
-        fft_run<-1, VM, 0, 1, kLineFast, kLineFast>(lds, lnl, ls, P, load, store, nop, nullptr);
+        fft_run<-1, VM, NTH, 0, 1, kLineFast, kLineFast>(lds, lnl, ls, P, load, store, nop, nullptr);
     } else {
         // divide by L(k) * #cells; L(0) := 1.
         auto divide = [&](int l, int e, cd z) INS_INLINE -> cd {
@@ -504,8 +504,8 @@ __global__ __launch_bounds__(kBlock) void k_fft_strided(Grid g, cd* __restrict__
             const double sc = kzero ? st.inv_ncell : -st.inv_ncell / lam;
             return cscale(z, sc);
         };
-        fft_run<-1, VM, 0, 2, kLineFast, kLineFast>(lds, lnl, ls, P, load, store, divide, &Q);
-        fft_inverse_rest<1, VM, kLineFast>(lds, lnl, ls, Q, store);
+        fft_run<-1, VM, NTH, 0, 2, kLineFast, kLineFast>(lds, lnl, ls, P, load, store, divide, &Q);
+        fft_inverse_rest<1, VM, NTH, kLineFast>(lds, lnl, ls, Q, store);
     }
 }
 
@@ -519,10 +519,15 @@ hipError_t launch_fft_x_fwd(const Grid& g, const T* vel, const double* r, cd* sp
     const int nrows = g.batch * g.nz * g.ny;
     const int nblk = (nrows + nl - 1) / nl;
     const size_t shm = size_t(nl + px.pad) * px.n * sizeof(cd);
-#define INS_XF(D, SRC, VM) \
-    hipLaunchKernelGGL((k_fft_x_fwd<T, D, SRC, VM>), dim3(nblk), dim3(kBlock), shm, s, g, vel, r, spec, px, post, lnl, comp)
-#define INS_XF_VM(D, SRC) \
-    do { if (px.vm == 8) INS_XF(D, SRC, 8); else INS_XF(D, SRC, 16); } while (0)
+#define INS_XF(D, SRC, VM, NTH)                                                                                \
+    hipLaunchKernelGGL((k_fft_x_fwd<T, D, SRC, VM, NTH>), dim3(nblk), dim3(NTH), shm, s, g, vel, r, spec, px, post, lnl, \
+                       comp)
+#define INS_XF_VM(D, SRC)                                    \
+    do {                                                     \
+        if (px.nth == 1024) INS_XF(D, SRC, 8, 1024);         \
+        else if (px.vm == 8) INS_XF(D, SRC, 8, 256);         \
+        else INS_XF(D, SRC, 16, 256);                        \
+    } while (0)
     if (vel && comp < 0) {
         if (g.dim == 3) INS_XF_VM(3, 0); else INS_XF_VM(2, 0);
     } else if (vel) {
@@ -541,10 +546,12 @@ hipError_t launch_fft_x_inv(const Grid& g, const cd* spec, double* p, const FftP
     const int nrows = g.batch * g.nz * g.ny;
     const int nblk = (nrows + nl - 1) / nl;
     const size_t shm = size_t(nl + px.pad) * px.n * sizeof(cd);
-    if (px.vm == 8)
-        hipLaunchKernelGGL(k_fft_x_inv<8>, dim3(nblk), dim3(kBlock), shm, s, g, spec, p, px, post, lnl);
+    if (px.nth == 1024)
+        hipLaunchKernelGGL((k_fft_x_inv<8, 1024>), dim3(nblk), dim3(1024), shm, s, g, spec, p, px, post, lnl);
+    else if (px.vm == 8)
+        hipLaunchKernelGGL((k_fft_x_inv<8, 256>), dim3(nblk), dim3(256), shm, s, g, spec, p, px, post, lnl);
     else
-        hipLaunchKernelGGL(k_fft_x_inv<16>, dim3(nblk), dim3(kBlock), shm, s, g, spec, p, px, post, lnl);
+        hipLaunchKernelGGL((k_fft_x_inv<16, 256>), dim3(nblk), dim3(256), shm, s, g, spec, p, px, post, lnl);
     return hipGetLastError();
 }
 
@@ -556,10 +563,14 @@ hipError_t launch_fft_strided(const Grid& g, cd* spec, const FftPlan& pl, const 
     const int nfix = axis == 1 ? g.nz : g.ny;
     const int nblk = nchunk * nouter + g.batch * ((nfix + nl - 1) / nl);  // + the Nyquist-column workgroups
     const size_t shm = size_t(nl + pl.pad) * pl.n * sizeof(cd);
-#define INS_ST(MODE, VM) \
-    hipLaunchKernelGGL((k_fft_strided<MODE, VM>), dim3(nblk), dim3(kBlock), shm, s, g, spec, pl, rev, axis, lnl, st)
-#define INS_ST_VM(MODE) \
-    do { if (pl.vm == 8) INS_ST(MODE, 8); else INS_ST(MODE, 16); } while (0)
+#define INS_ST(MODE, VM, NTH) \
+    hipLaunchKernelGGL((k_fft_strided<MODE, VM, NTH>), dim3(nblk), dim3(NTH), shm, s, g, spec, pl, rev, axis, lnl, st)
+#define INS_ST_VM(MODE)                                  \
+    do {                                                 \
+        if (pl.nth == 512) INS_ST(MODE, 8, 512);         \
+        else if (pl.vm == 8) INS_ST(MODE, 8, 256);       \
+        else INS_ST(MODE, 16, 256);                      \
+    } while (0)
     if (mode == 0)
         INS_ST_VM(0);
     else if (mode == 1)
