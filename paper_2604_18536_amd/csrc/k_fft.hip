@@ -301,6 +301,23 @@ __device__ __forceinline__ void fft_inverse_rest(cd* lds, int lnl, int ls, const
                                       false);
 }
 
+// Copy the nl lines into LDS element-major (lds[e ls + l]) with element-fast
+// threads, so the global reads run along the rows and the LDS writes (odd
+// stride ls) are conflict-free; then synchronise. (Along x a first stage that
+// read memory directly would write its butterfly outputs i R + q from
+// neighbouring threads R elements apart: bank conflicts.)
+template <int NTH, class Load>
+__device__ __forceinline__ void stage_rows(cd* __restrict__ lds, int lnl, int ls, int N, const Load& load) {
+    const int nl = 1 << lnl;
+    const float rN = __builtin_amdgcn_rcpf(static_cast<float>(N));
+    for (int t = threadIdx.x; t < nl * N; t += NTH) {
+        int e;
+        const int l = fdivmod(t, N, rN, e);
+        lds[e * ls + l] = load(l, e);
+    }
+    __syncthreads();
+}
+
 // Two consecutive values of a row (x even), as one load.
 __device__ __forceinline__ void ld_pair(const double* p, double& a, double& b) {
     const double2 t = *reinterpret_cast<const double2*>(p);
@@ -320,8 +337,8 @@ __device__ __forceinline__ void ld_pair(const float* p, double& a, double& b) {
 // ----------------------------------------------------------------------------
 // SRC 0: rows are the divergence of the velocity field `vel`;
 // SRC 1: rows of the float64 scalar field r; SRC 2: rows of component `comp` of vel.
-// The first stage reads its inputs straight from memory (element-fast); the
-// untangling needs Z[k] and Z[M-k] together, so the last stage writes to LDS.
+// The rows are staged in LDS first (see stage_rows); the untangling needs Z[k]
+// and Z[M-k] together, so the last stage writes to LDS as well.
 template <typename T, int DIM, int SRC, int VM, int NTH>
 __global__ __launch_bounds__(NTH) void k_fft_x_fwd(Grid g, const T* __restrict__ vel, const double* __restrict__ r,
                                                         cd* __restrict__ spec, FftPlan P, const cd* __restrict__ post,
@@ -332,16 +349,22 @@ __global__ __launch_bounds__(NTH) void k_fft_x_fwd(Grid g, const T* __restrict__
     const int M = P.n;
     const int nrows = g.batch * g.nz * g.ny;
     const int row0 = xcd_logical(blockIdx.x, gridDim.x) * nl;
+    // (y, z, batch) of the first row; row0 + l follows by carrying (l < nl <= 16)
+    const int yy0 = row0 % g.ny, zb0 = row0 / g.ny, zz0 = zb0 % g.nz, b0 = zb0 / g.nz;
     auto load = [&](int l, int m) INS_INLINE -> cd {
         const int row = row0 + l;
         if (row >= nrows) return cd{0.0, 0.0};
         if constexpr (SRC == 1) {
             return reinterpret_cast<const cd*>(r + int64_t(row) * g.nx)[m];
         } else {
-            const int yy = row % g.ny;
-            const int zb = row / g.ny;
-            const int zz = zb % g.nz;
-            const int b = zb / g.nz;
+            int yy = yy0 + l, zz = zz0, b = b0;
+            while (yy >= g.ny) {
+                yy -= g.ny;
+                if (++zz == g.nz) {
+                    zz = 0;
+                    ++b;
+                }
+            }
             const int rowoff = (zz * g.ny + yy) * g.nx;
             const int x0 = 2 * m;
             if constexpr (SRC == 2) {
@@ -377,10 +400,13 @@ __global__ __launch_bounds__(NTH) void k_fft_x_fwd(Grid g, const T* __restrict__
         }
     };
     const NoOp nop;
-    fft_run<-1, VM, NTH, 0, 0, kElemFast, kLineFast>(lds, lnl, ls, P, load, nop, nop, nullptr);
+    stage_rows<NTH>(lds, lnl, ls, M, load);
+    fft_run<-1, VM, NTH, 1, 0, kLineFast, kLineFast>(lds, lnl, ls, P, load, nop, nop, nullptr);
     const int M1 = M + 1;
+    const float rM1 = __builtin_amdgcn_rcpf(static_cast<float>(M1));
     for (int t = threadIdx.x; t < nl * M1; t += NTH) {
-        const int l = t / M1, k = t - l * M1;
+        int k;
+        const int l = fdivmod(t, M1, rM1, k);
         const int row = row0 + l;
         if (row >= nrows) continue;
         const cd zk = lds[(k == M ? 0 : k) * ls + l];
@@ -394,8 +420,8 @@ __global__ __launch_bounds__(NTH) void k_fft_x_fwd(Grid g, const T* __restrict__
 
 // x pass, inverse: half spectrum -> real rows, scaled by n_x (unnormalised).
 // Z[k] = (X[k] + conj X[M-k]) + i (X[k] - conj X[M-k]) conj(W^k), z = IFFT_M(Z),
-// x[2m] = Re z[m], x[2m+1] = Im z[m]. First stage reads the spectrum rows and
-// last stage writes the real rows directly (both element-fast).
+// x[2m] = Re z[m], x[2m+1] = Im z[m]. The tangled rows are staged in LDS; the
+// last stage writes the real rows directly (element-fast).
 template <int VM, int NTH>
 __global__ __launch_bounds__(NTH) void k_fft_x_inv(Grid g, const cd* __restrict__ spec, double* __restrict__ p,
                                                         FftPlan P, const cd* __restrict__ post, int lnl) {
@@ -420,7 +446,8 @@ __global__ __launch_bounds__(NTH) void k_fft_x_inv(Grid g, const cd* __restrict_
         if (row < nrows) reinterpret_cast<cd*>(p + int64_t(row) * g.nx)[m] = z;
     };
     const NoOp nop;
-    fft_run<1, VM, NTH, 0, 1, kElemFast, kElemFast>(lds, lnl, ls, P, load, sink, nop, nullptr);
+    stage_rows<NTH>(lds, lnl, ls, M, load);
+    fft_run<1, VM, NTH, 1, 1, kLineFast, kElemFast>(lds, lnl, ls, P, load, sink, nop, nullptr);
 }
 
 // Strided complex pass along y (axis 1) or z (axis 2) of the half spectrum
