@@ -8,7 +8,9 @@ E(k) ~ k^4 exp(-2 (k/4)^2) and unit kinetic energy.
 one full RK4 step of one cell; inputs resident in HBM). The same line reports
 the float64 forward+adjoint rate, the FP32-stencil mode (float32 fields,
 float64 divergence/Poisson/projection), Wray's low-storage RK3 step (modes
-*_wray3: three stages and solves per step), the HBM-roofline fraction of each
+*_wray3: three stages and solves per step), forward+adjoint with the stage
+inputs kept from the forward instead of recomputed (modes *_adj_kept), the
+HBM-roofline fraction of each
 step and of the dominant kernel (per-kernel durations from HIP events recorded
 on the library's stream), and the float64 CPU oracle timed on a bounded
 sample of the same workload.
@@ -34,7 +36,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 CONFIGS = {
     # the benchmark workload: 3D decaying turbulence at 256^3
     "turb256": {"n": 256, "nu": 1.0 / 1600.0, "dt": 1e-3, "k0": 4.0, "seed": 0,
-                "modes": "fp64,fp64_adj,fp32,fp32_adj,fp64_wray3,fp32_wray3"},
+                "modes": "fp64,fp64_adj,fp32,fp32_adj,fp64_adj_kept,fp32_adj_kept,fp64_wray3,fp32_wray3"},
     # the largest single-GPU DNS: 840^3 = 2^3*3*5*7 (mixed-radix FFT), FP64 and FP32 mode
     "dns840": {"n": 840, "nu": 1.0 / 5000.0, "dt": 1e-3, "k0": 8.0, "seed": 3, "modes": "fp64,fp32"},
 }
@@ -124,7 +126,7 @@ def time_steps(fn, steps, warmup, solver=None):
     return a.elapsed_time(b) / steps, prof
 
 
-def run_mode(n, nu, dt, precision, steps, warmup, u0_np, adjoint, scheme="rk4"):
+def run_mode(n, nu, dt, precision, steps, warmup, u0_np, adjoint, scheme="rk4", keep=False):
     import torch
 
     from paper_2604_18536_amd import Solver
@@ -138,10 +140,11 @@ def run_mode(n, nu, dt, precision, steps, warmup, u0_np, adjoint, scheme="rk4"):
     if adjoint:
         torch.manual_seed(0)
         ubar.copy_(torch.randn_like(u0))
+        kept = s.stage_buffers(scheme) if keep else None
 
         def fn():
-            s.step(u0, dt, out=u1, scheme=scheme)
-            s.step_vjp(u0, ubar, dt, out=gbar, scheme=scheme)
+            s.step(u0, dt, out=u1, scheme=scheme, keep=kept)
+            s.step_vjp(u0, ubar, dt, out=gbar, scheme=scheme, kept=kept)
     else:
 
         def fn():
@@ -150,6 +153,8 @@ def run_mode(n, nu, dt, precision, steps, warmup, u0_np, adjoint, scheme="rk4"):
     ms_p, prof = time_steps(fn, steps, 1, solver=s)
     ok = s.stats(u1)[3]
     ws = s.workspace_bytes()
+    if adjoint and keep:  # the caller-owned stage buffers count as workspace too
+        ws += sum(t.numel() * t.element_size() for t in kept)
     s.close()
     return ms, ms_p, prof, ok, ws
 
@@ -345,9 +350,10 @@ def main():
     kernels = {}
     for mode in args.modes.split(","):
         precision = "fp64" if mode.startswith("fp64") else "fp32"
-        adjoint = mode.endswith("_adj")
+        adjoint = mode.endswith("_adj") or mode.endswith("_adj_kept")
+        keep = mode.endswith("_adj_kept")
         scheme = "wray3" if "_wray3" in mode else "rk4"
-        ms, ms_p, prof, ok, ws = run_mode(n, nu, dt, precision, args.steps, args.warmup, u0, adjoint, scheme)
+        ms, ms_p, prof, ok, ws = run_mode(n, nu, dt, precision, args.steps, args.warmup, u0, adjoint, scheme, keep)
         elem = 8 if precision == "fp64" else 4
         alg = 0
         for name, (cnt, tot) in prof.items():

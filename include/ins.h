@@ -202,6 +202,35 @@ ins_status ins_step_wray3(ins_ctx ctx, const void* u0, void* u1, double dt);
 ins_status ins_step_wray3_vjp(ins_ctx ctx, const void* u0, const void* u1bar, void* u0bar, double dt);
 
 /* ---------------------------------------------------------------------------
+ * Steps that keep their stage inputs for the pullback. Reverse-mode training
+ * stores the forward states of every sub-step for the backward pass (Sec. 4);
+ * ins_step_*_vjp instead recompute them from u0 (less memory, one more
+ * forward per step). These variants let the caller hold the stage inputs:
+ * the unprojected stage sums W_i and their pressures P_i (u_i = W_i - G P_i),
+ * i.e. ins_scheme_stage_count(scheme) velocity fields and as many float64
+ * pressure-point fields, contiguous:
+ *   stages  [count][batch][dim][n_z][n_y][n_x]  (context type),
+ *   pstages [count][batch][n_z][n_y][n_x]        (float64).
+ * ins_step_save does the same work as the plain step, writing the stage
+ * registers to these buffers; ins_step_vjp_saved skips the recomputation and
+ * must get the stages of the same (u0, dt), with the same closure setting.
+ * ------------------------------------------------------------------------- */
+typedef enum { INS_RK4 = 0, INS_WRAY3 = 1 } ins_scheme;
+
+/* Stage inputs a scheme keeps: 3 for RK4, 2 for Wray3; -1 for an unknown scheme. */
+int ins_scheme_stage_count(int scheme);
+
+/* u1 = step(u0, dt) (scheme per ins_scheme; u0 == u1 allowed), keeping the
+ * stage inputs in stages / pstages (overwritten). */
+ins_status ins_step_save(ins_ctx ctx, int scheme, const void* u0, void* u1, double dt, void* stages,
+                         double* pstages);
+
+/* u0bar = (d u1 / d u0)^T u1bar from the stage inputs of ins_step_save (read
+ * only). u0bar must not alias u0, u1bar or stages. */
+ins_status ins_step_vjp_saved(ins_ctx ctx, int scheme, const void* u0, const void* stages, const double* pstages,
+                              const void* u1bar, void* u0bar, double dt);
+
+/* ---------------------------------------------------------------------------
  * Learned closure (Sec. 4: a neural closure inside the solver, trained
  * a-posteriori through it). The paper does not fix an architecture; this one
  * is a 3D CNN 3 -> 32 -> 32 -> 3 channels, 3x3x3 kernels with circular

@@ -15,6 +15,8 @@ INS_ERR_HIP = -4
 INS_FP64 = 0
 INS_FP32 = 1
 INS_BC_PERIODIC = 0
+INS_RK4 = 0
+INS_WRAY3 = 1
 
 _STATUS_NAMES = {
     INS_ERR_INVALID: "INS_ERR_INVALID",
@@ -61,6 +63,9 @@ _SIGS = {
     "ins_step_rk4_vjp": ([_P, _P, _P, _P, _D]),
     "ins_step_wray3": ([_P, _P, _P, _D]),
     "ins_step_wray3_vjp": ([_P, _P, _P, _P, _D]),
+    "ins_step_save": ([_P, C.c_int, _P, _P, _D, _P, _P]),
+    "ins_step_vjp_saved": ([_P, C.c_int, _P, _P, _P, _P, _P, _D]),
+    "ins_scheme_stage_count": ([C.c_int]),
     "ins_eddy_set": ([_P, _D, _D]),
     "ins_eddy_forward": ([_P, _P, _P]),
     "ins_eddy_backward": ([_P, _P, _P, _P]),

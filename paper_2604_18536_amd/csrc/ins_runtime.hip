@@ -480,21 +480,44 @@ void stage(ins_ctx c, const T* w, const double* p, bool proj, const T* u0, T* y,
     });
 }
 
+// Stage inputs of one step kept for its pullback: the unprojected stage sums
+// W_i (velocity fields) and their pressures P_i (u_i = W_i - G P_i), i = 2..4
+// for RK4 and 2..3 for Wray3. Either the context's reverse-pass storage or
+// caller buffers (ins_step_save / ins_step_vjp_saved).
+template <typename T>
+struct Stages {
+    T* w[3];
+    double* p[3];
+};
+
+template <typename T>
+Stages<T> own_stages(ins_ctx c) {
+    return {{static_cast<T*>(c->w2), static_cast<T*>(c->w3), static_cast<T*>(c->w4)}, {c->p2, c->p3, c->p4}};
+}
+
 // Classical RK4, projection after every stage (Sec. 2.5.2), low-storage
 // schedule: accumulator y, stage registers wa/wb, one pressure per stage.
+// With `keep` the stage registers and pressures are the given buffers (the
+// same work, their contents left for the pullback).
 template <typename T>
-void step_rk4(ins_ctx c, const T* u0, T* u1, double dt) {
+void step_rk4(ins_ctx c, const T* u0, T* u1, double dt, const Stages<T>* keep = nullptr) {
     T* y = static_cast<T*>(c->ry);
     T* wa = static_cast<T*>(c->wa);
     T* wb = static_cast<T*>(c->wb);
     double* p = c->p;
-    stage<T>(c, u0, nullptr, false, u0, y, true, dt / 6.0, wa, dt / 2.0);
-    poisson(c, wa, nullptr, p);
-    stage<T>(c, wa, p, true, u0, y, false, dt / 3.0, wb, dt / 2.0);
-    poisson(c, wb, nullptr, p);
-    stage<T>(c, wb, p, true, u0, y, false, dt / 3.0, wa, dt);
-    poisson(c, wa, nullptr, p);
-    stage<T>(c, wa, p, true, u0, y, false, dt / 6.0, nullptr, 0.0);
+    T* W2 = keep ? keep->w[0] : wa;
+    T* W3 = keep ? keep->w[1] : wb;
+    T* W4 = keep ? keep->w[2] : wa;
+    double* P2 = keep ? keep->p[0] : p;
+    double* P3 = keep ? keep->p[1] : p;
+    double* P4 = keep ? keep->p[2] : p;
+    stage<T>(c, u0, nullptr, false, u0, y, true, dt / 6.0, W2, dt / 2.0);
+    poisson(c, W2, nullptr, P2);
+    stage<T>(c, W2, P2, true, u0, y, false, dt / 3.0, W3, dt / 2.0);
+    poisson(c, W3, nullptr, P3);
+    stage<T>(c, W3, P3, true, u0, y, false, dt / 3.0, W4, dt);
+    poisson(c, W4, nullptr, P4);
+    stage<T>(c, W4, P4, true, u0, y, false, dt / 6.0, nullptr, 0.0);
     poisson(c, y, nullptr, p);
     apply_projection<T>(c, y, p, u1);
 }
@@ -524,39 +547,40 @@ void stage_vjp(ins_ctx c, const T* w, const double* p, bool proj_u, const T* yba
     }
 }
 
-// Reverse pass of step_rk4 (Sec. 3.4): recompute the stage states
-// u_i = w_i - G p_i, project the incoming cotangent, then run the stages
-// backwards. With ybar = P u1bar and wbar_{i+1} the projected cotangent of
-// stage i+1's input:
+// Reverse pass of step_rk4 (Sec. 3.4) from the stage inputs S: project the
+// incoming cotangent, then run the stages backwards. With ybar = P u1bar and
+// wbar_{i+1} the projected cotangent of stage i+1's input:
 //   Fbar_i = dt b_i ybar + dt a_{i+1} wbar_{i+1},  ubar_i = J_F(u_i)^T Fbar_i,
 //   wbar_i = P ubar_i,  u0bar = ybar + sum_i wbar_i + ubar_1.
 template <typename T>
-void step_rk4_vjp(ins_ctx c, const T* u0, const T* u1bar, T* u0bar, double dt) {
-    ensure_vjp_storage(c);
-    T* W2 = static_cast<T*>(c->w2);
-    T* W3 = static_cast<T*>(c->w3);
-    T* W4 = static_cast<T*>(c->w4);
-    double *P2 = c->p2, *P3 = c->p3, *P4 = c->p4;
-    stage<T>(c, u0, nullptr, false, u0, nullptr, false, 0.0, W2, dt / 2.0);
-    poisson(c, W2, nullptr, P2);
-    stage<T>(c, W2, P2, true, u0, nullptr, false, 0.0, W3, dt / 2.0);
-    poisson(c, W3, nullptr, P3);
-    stage<T>(c, W3, P3, true, u0, nullptr, false, 0.0, W4, dt);
-    poisson(c, W4, nullptr, P4);
-
+void step_rk4_reverse(ins_ctx c, const T* u0, const Stages<T>& S, const T* u1bar, T* u0bar, double dt) {
     T* YB = static_cast<T*>(c->ry);
     T* UA = static_cast<T*>(c->wa);
     T* UB = static_cast<T*>(c->wb);
     double* Q = c->p;
     poisson(c, u1bar, nullptr, Q);
     apply_projection<T>(c, u1bar, Q, YB);
-    stage_vjp<T>(c, W4, P4, true, YB, nullptr, nullptr, false, dt / 6.0, 0.0, u0bar, 0, UA);
+    stage_vjp<T>(c, S.w[2], S.p[2], true, YB, nullptr, nullptr, false, dt / 6.0, 0.0, u0bar, 0, UA);
     poisson(c, UA, nullptr, Q);
-    stage_vjp<T>(c, W3, P3, true, YB, UA, Q, true, dt / 3.0, dt, u0bar, 1, UB);
+    stage_vjp<T>(c, S.w[1], S.p[1], true, YB, UA, Q, true, dt / 3.0, dt, u0bar, 1, UB);
     poisson(c, UB, nullptr, Q);
-    stage_vjp<T>(c, W2, P2, true, YB, UB, Q, true, dt / 3.0, dt / 2.0, u0bar, 1, UA);
+    stage_vjp<T>(c, S.w[0], S.p[0], true, YB, UB, Q, true, dt / 3.0, dt / 2.0, u0bar, 1, UA);
     poisson(c, UA, nullptr, Q);
     stage_vjp<T>(c, u0, nullptr, false, YB, UA, Q, true, dt / 6.0, dt / 2.0, u0bar, 2, nullptr);
+}
+
+// Pullback of step_rk4 that first recomputes the stage inputs from u0.
+template <typename T>
+void step_rk4_vjp(ins_ctx c, const T* u0, const T* u1bar, T* u0bar, double dt) {
+    ensure_vjp_storage(c);
+    const Stages<T> S = own_stages<T>(c);
+    stage<T>(c, u0, nullptr, false, u0, nullptr, false, 0.0, S.w[0], dt / 2.0);
+    poisson(c, S.w[0], nullptr, S.p[0]);
+    stage<T>(c, S.w[0], S.p[0], true, u0, nullptr, false, 0.0, S.w[1], dt / 2.0);
+    poisson(c, S.w[1], nullptr, S.p[1]);
+    stage<T>(c, S.w[1], S.p[1], true, u0, nullptr, false, 0.0, S.w[2], dt);
+    poisson(c, S.w[2], nullptr, S.p[2]);
+    step_rk4_reverse<T>(c, u0, S, u1bar, u0bar, dt);
 }
 
 // Wray's low-storage three-stage scheme (Sec. 2.5.2 names it among the
@@ -564,52 +588,60 @@ void step_rk4_vjp(ins_ctx c, const T* u0, const T* u1bar, T* u0bar, double dt) {
 // stage. In Butcher form its stages are u_2 = P(u0 + dt 8/15 F_1),
 // u_3 = P(u0 + dt (1/4 F_1 + 5/12 F_2)), u_new = P(u0 + dt (1/4 F_1 + 3/4 F_3));
 // since both later sums start from yacc = u0 + dt/4 F_1, the schedule keeps
-// yacc and one stage register: three stage kernels and three solves.
+// yacc and one stage register: three stage kernels and three solves. With
+// `keep`, W_2, W_3 and their pressures go to the given buffers.
 template <typename T>
-void step_wray3(ins_ctx c, const T* u0, T* u1, double dt) {
+void step_wray3(ins_ctx c, const T* u0, T* u1, double dt, const Stages<T>* keep = nullptr) {
     T* yacc = static_cast<T*>(c->ry);
     T* wa = static_cast<T*>(c->wa);
     T* wb = static_cast<T*>(c->wb);
     double* p = c->p;
-    stage<T>(c, u0, nullptr, false, u0, yacc, true, dt / 4.0, wa, dt * 8.0 / 15.0, "wray_stage1");
-    poisson(c, wa, nullptr, p);
-    stage<T>(c, wa, p, true, yacc, nullptr, false, 0.0, wb, dt * 5.0 / 12.0, "wray_stage2");
-    poisson(c, wb, nullptr, p);
-    stage<T>(c, wb, p, true, yacc, nullptr, false, 0.0, wa, dt * 3.0 / 4.0, "wray_stage3");
+    T* W2 = keep ? keep->w[0] : wa;
+    T* W3 = keep ? keep->w[1] : wb;
+    double* P2 = keep ? keep->p[0] : p;
+    double* P3 = keep ? keep->p[1] : p;
+    stage<T>(c, u0, nullptr, false, u0, yacc, true, dt / 4.0, W2, dt * 8.0 / 15.0, "wray_stage1");
+    poisson(c, W2, nullptr, P2);
+    stage<T>(c, W2, P2, true, yacc, nullptr, false, 0.0, W3, dt * 5.0 / 12.0, "wray_stage2");
+    poisson(c, W3, nullptr, P3);
+    stage<T>(c, W3, P3, true, yacc, nullptr, false, 0.0, wa, dt * 3.0 / 4.0, "wray_stage3");
     poisson(c, wa, nullptr, p);
     apply_projection<T>(c, wa, p, u1);
 }
 
-// Reverse pass of step_wray3. With w_2 = u0 + dt 8/15 F_1, yacc = u0 + dt/4 F_1,
-// w_3 = yacc + dt 5/12 F_2(u_2), w_4 = yacc + dt 3/4 F_3(u_3), u_k = P w_k:
+// Reverse pass of step_wray3 from the stage inputs S. With w_2 = u0 + dt 8/15 F_1,
+// yacc = u0 + dt/4 F_1, w_3 = yacc + dt 5/12 F_2(u_2), w_4 = yacc + dt 3/4 F_3(u_3), u_k = P w_k:
 //   wbar_4 = P u1bar = yaccbar (so far); ubar_3 = J_F(u_3)^T (dt 3/4 wbar_4)
 //   wbar_3 = P ubar_3; yaccbar += wbar_3; ubar_2 = J_F(u_2)^T (dt 5/12 wbar_3)
 //   wbar_2 = P ubar_2; u0bar = yaccbar + wbar_2 + J_F(u0)^T (dt/4 yaccbar + dt 8/15 wbar_2).
 template <typename T>
-void step_wray3_vjp(ins_ctx c, const T* u0, const T* u1bar, T* u0bar, double dt) {
-    ensure_vjp_storage(c);
-    T* W2 = static_cast<T*>(c->w2);
-    T* W3 = static_cast<T*>(c->w3);
-    double *P2 = c->p2, *P3 = c->p3;
+void step_wray3_reverse(ins_ctx c, const T* u0, const Stages<T>& S, const T* u1bar, T* u0bar, double dt) {
     T* YB = static_cast<T*>(c->ry);
     T* UA = static_cast<T*>(c->wa);
     T* UB = static_cast<T*>(c->wb);
     double* Q = c->p;
-    // recompute the stage states (yacc lives in YB until the reverse pass overwrites it)
-    stage<T>(c, u0, nullptr, false, u0, YB, true, dt / 4.0, W2, dt * 8.0 / 15.0, "wray_stage1");
-    poisson(c, W2, nullptr, P2);
-    stage<T>(c, W2, P2, true, YB, nullptr, false, 0.0, W3, dt * 5.0 / 12.0, "wray_stage2");
-    poisson(c, W3, nullptr, P3);
-
     poisson(c, u1bar, nullptr, Q);
     apply_projection<T>(c, u1bar, Q, YB);  // YB = wbar_4, the running yaccbar
     // the accumulator starts as YB itself, so this stage writes no accumulator
-    stage_vjp<T>(c, W3, P3, true, YB, nullptr, nullptr, false, dt * 3.0 / 4.0, 0.0, nullptr, 0, UA);
+    stage_vjp<T>(c, S.w[1], S.p[1], true, YB, nullptr, nullptr, false, dt * 3.0 / 4.0, 0.0, nullptr, 0, UA);
     poisson(c, UA, nullptr, Q);
     // Fbar_2 = dt 5/12 wbar_3 (cb = 0, so the ybar operand is not YB, which this kernel updates)
-    stage_vjp<T>(c, W2, P2, true, UA, UA, Q, true, 0.0, dt * 5.0 / 12.0, YB, 1, UB);
+    stage_vjp<T>(c, S.w[0], S.p[0], true, UA, UA, Q, true, 0.0, dt * 5.0 / 12.0, YB, 1, UB);
     poisson(c, UB, nullptr, Q);
     stage_vjp<T>(c, u0, nullptr, false, YB, UB, Q, true, dt / 4.0, dt * 8.0 / 15.0, u0bar, 3, nullptr);
+}
+
+// Pullback of step_wray3 that first recomputes W_2, W_3 (yacc passes through YB).
+template <typename T>
+void step_wray3_vjp(ins_ctx c, const T* u0, const T* u1bar, T* u0bar, double dt) {
+    ensure_vjp_storage(c);
+    const Stages<T> S = own_stages<T>(c);
+    T* YB = static_cast<T*>(c->ry);
+    stage<T>(c, u0, nullptr, false, u0, YB, true, dt / 4.0, S.w[0], dt * 8.0 / 15.0, "wray_stage1");
+    poisson(c, S.w[0], nullptr, S.p[0]);
+    stage<T>(c, S.w[0], S.p[0], true, YB, nullptr, false, 0.0, S.w[1], dt * 5.0 / 12.0, "wray_stage2");
+    poisson(c, S.w[1], nullptr, S.p[1]);
+    step_wray3_reverse<T>(c, u0, S, u1bar, u0bar, dt);
 }
 
 void check_dt(double dt) {
@@ -924,6 +956,66 @@ ins_status ins_step_wray3_vjp(ins_ctx ctx, const void* u0, const void* u1bar, vo
             using T = decltype(tag);
             step_wray3_vjp<T>(ctx, static_cast<const T*>(u0), static_cast<const T*>(u1bar), static_cast<T*>(u0bar),
                               dt);
+        });
+    });
+}
+
+int ins_scheme_stage_count(int scheme) { return scheme == INS_RK4 ? 3 : (scheme == INS_WRAY3 ? 2 : -1); }
+
+ins_status ins_step_save(ins_ctx ctx, int scheme, const void* u0, void* u1, double dt, void* stages,
+                         double* pstages) {
+    return guarded([&] {
+        checked(ctx);
+        need(u0, "u0");
+        need(u1, "u1");
+        need(stages, "stages");
+        need(pstages, "pstages");
+        check_dt(dt);
+        const int ns = ins_scheme_stage_count(scheme);
+        if (ns < 0) raise(INS_ERR_INVALID, "unknown scheme");
+        with_type(ctx, [&](auto tag) {
+            using T = decltype(tag);
+            const size_t nv = ctx->vel_bytes() / sizeof(T), np = ctx->scal_bytes() / sizeof(double);
+            Stages<T> S{};
+            for (int i = 0; i < ns; ++i) {
+                S.w[i] = static_cast<T*>(stages) + i * nv;
+                S.p[i] = pstages + i * np;
+            }
+            if (scheme == INS_RK4)
+                step_rk4<T>(ctx, static_cast<const T*>(u0), static_cast<T*>(u1), dt, &S);
+            else
+                step_wray3<T>(ctx, static_cast<const T*>(u0), static_cast<T*>(u1), dt, &S);
+        });
+    });
+}
+
+ins_status ins_step_vjp_saved(ins_ctx ctx, int scheme, const void* u0, const void* stages, const double* pstages,
+                              const void* u1bar, void* u0bar, double dt) {
+    return guarded([&] {
+        checked(ctx);
+        need(u0, "u0");
+        need(stages, "stages");
+        need(pstages, "pstages");
+        need(u1bar, "u1bar");
+        need(u0bar, "u0bar");
+        check_dt(dt);
+        const int ns = ins_scheme_stage_count(scheme);
+        if (ns < 0) raise(INS_ERR_INVALID, "unknown scheme");
+        if (u0bar == u0 || u0bar == u1bar || u0bar == stages) raise(INS_ERR_INVALID, "u0bar must not alias an input");
+        with_type(ctx, [&](auto tag) {
+            using T = decltype(tag);
+            const size_t nv = ctx->vel_bytes() / sizeof(T), np = ctx->scal_bytes() / sizeof(double);
+            Stages<T> S{};
+            for (int i = 0; i < ns; ++i) {
+                S.w[i] = const_cast<T*>(static_cast<const T*>(stages)) + i * nv;
+                S.p[i] = const_cast<double*>(pstages) + i * np;
+            }
+            if (scheme == INS_RK4)
+                step_rk4_reverse<T>(ctx, static_cast<const T*>(u0), S, static_cast<const T*>(u1bar),
+                                    static_cast<T*>(u0bar), dt);
+            else
+                step_wray3_reverse<T>(ctx, static_cast<const T*>(u0), S, static_cast<const T*>(u1bar),
+                                      static_cast<T*>(u0bar), dt);
         });
     });
 }

@@ -154,13 +154,39 @@ class Solver:
             raise ValueError(f"scheme must be one of {sorted(self._SCHEMES)}")
         return self._SCHEMES[scheme]
 
-    def step(self, u0, dt, out=None, scheme="rk4"):
+    _SCHEME_IDS = {"rk4": 0, "wray3": 1}
+
+    def stage_buffers(self, scheme="rk4"):
+        """(stages, pstages) buffers for step(..., keep=) / step_vjp(..., kept=)."""
+        k = L.load().ins_scheme_stage_count(self._SCHEME_IDS[scheme])
+        stages = torch.empty((k,) + self.vel_shape, dtype=self.dtype, device=self.device)
+        pstages = torch.empty((k,) + self.scal_shape, dtype=torch.float64, device=self.device)
+        return stages, pstages
+
+    def _kept(self, kept, scheme):
+        stages, pstages = kept
+        k = L.load().ins_scheme_stage_count(self._SCHEME_IDS[scheme])
+        if (not isinstance(stages, torch.Tensor) or tuple(stages.shape) != (k,) + self.vel_shape
+                or stages.dtype != self.dtype or stages.device != self.device or not stages.is_contiguous()):
+            raise ValueError("stages must come from stage_buffers(scheme)")
+        if (not isinstance(pstages, torch.Tensor) or tuple(pstages.shape) != (k,) + self.scal_shape
+                or pstages.dtype != torch.float64 or pstages.device != self.device or not pstages.is_contiguous()):
+            raise ValueError("pstages must come from stage_buffers(scheme)")
+        return stages.data_ptr(), pstages.data_ptr()
+
+    def step(self, u0, dt, out=None, scheme="rk4", keep=None):
         """One time step (classical RK4, or Wray's low-storage RK3 with scheme="wray3");
-        out may be u0 (in place)."""
+        out may be u0 (in place). keep=(stages, pstages) from stage_buffers() keeps the
+        stage inputs there for step_vjp(..., kept=)."""
         fn = self._scheme(scheme)[0]
         out = self._out(out, u0, "vel")
         self._sync_stream()
-        L.call(fn, self._ctx, self._check(u0, "vel", "u0"), self._check(out, "vel", "out"), float(dt))
+        if keep is None:
+            L.call(fn, self._ctx, self._check(u0, "vel", "u0"), self._check(out, "vel", "out"), float(dt))
+        else:
+            sp, pp = self._kept(keep, scheme)
+            L.call("ins_step_save", self._ctx, self._SCHEME_IDS[scheme], self._check(u0, "vel", "u0"),
+                   self._check(out, "vel", "out"), float(dt), sp, pp)
         return out
 
     # ------------------------------------------------------------- pullbacks
@@ -195,10 +221,17 @@ class Solver:
         L.call("ins_project_vjp", self._ctx, self._check(ubar_out, "vel", "ubar_out"), self._check(out, "vel", "out"))
         return out
 
-    def step_vjp(self, u0, u1bar, dt, out=None, scheme="rk4"):
+    def step_vjp(self, u0, u1bar, dt, out=None, scheme="rk4", kept=None):
+        """(d u1 / d u0)^T u1bar; kept=(stages, pstages) filled by step(u0, dt, keep=) skips
+        the recomputation of the stage inputs."""
         fn = self._scheme(scheme)[1]
         out = self._out(out, u0, "vel")
         self._sync_stream()
+        if kept is not None:
+            sp, pp = self._kept(kept, scheme)
+            L.call("ins_step_vjp_saved", self._ctx, self._SCHEME_IDS[scheme], self._check(u0, "vel", "u0"), sp, pp,
+                   self._check(u1bar, "vel", "u1bar"), self._check(out, "vel", "out"), float(dt))
+            return out
         L.call(fn, self._ctx, self._check(u0, "vel", "u0"), self._check(u1bar, "vel", "u1bar"),
                self._check(out, "vel", "out"), float(dt))
         return out
