@@ -39,3 +39,4 @@ from .ins import (  # noqa: F401
 )
 from .aux import face_filter, energy_spectrum  # noqa: F401
 from . import eddy  # noqa: F401,E402
+from . import walls  # noqa: F401,E402

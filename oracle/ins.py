@@ -159,30 +159,36 @@ RK4_A = (0.5, 0.5, 1.0)
 RK4_B = (1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0)
 
 
-def rk4_stages(u0, h, nu, dt, rhs_fn=None):
+def _proj_fn(h, project_fn):
+    return project_fn if project_fn is not None else (lambda v: project(v, h)[0])
+
+
+def rk4_stages(u0, h, nu, dt, rhs_fn=None, project_fn=None):
     """Stage velocities u_1..u_4 and stage right-hand sides F_1..F_4 of one step.
 
     u_1 = u0 and u_{i+1} = P(u0 + dt a_{i+1} F(u_i)); returns (us, Fs).
-    rhs_fn(u) replaces F when given (e.g. F plus a closure term).
+    rhs_fn(u) replaces F when given (e.g. F plus a closure term), project_fn(u)
+    replaces P (e.g. the projection of a wall-bounded grid).
     """
     F = rhs_fn if rhs_fn is not None else (lambda v: rhs(v, h, nu))
+    P = _proj_fn(h, project_fn)
     us = [np.array(u0, dtype=np.float64)]
     fs = []
     for i in range(4):
         fs.append(F(us[i]))
         if i < 3:
-            us.append(project(u0 + dt * RK4_A[i] * fs[i], h)[0])
+            us.append(P(u0 + dt * RK4_A[i] * fs[i]))
     return us, fs
 
 
-def step_rk4(u0, h, nu, dt, rhs_fn=None):
+def step_rk4(u0, h, nu, dt, rhs_fn=None, project_fn=None):
     """One classical RK4 step with the velocity projected at every stage.
 
     u_{n+1} = P(u0 + dt (F_1 + 2 F_2 + 2 F_3 + F_4) / 6).
     """
-    _, fs = rk4_stages(u0, h, nu, dt, rhs_fn)
+    _, fs = rk4_stages(u0, h, nu, dt, rhs_fn, project_fn)
     y = u0 + dt * (fs[0] + 2.0 * fs[1] + 2.0 * fs[2] + fs[3]) / 6.0
-    return project(y, h)[0]
+    return _proj_fn(h, project_fn)(y)
 
 
 # ----------------------------------------------------------------------------
@@ -200,22 +206,23 @@ WRAY3_G = (8.0 / 15.0, 5.0 / 12.0, 3.0 / 4.0)
 WRAY3_Z = (-17.0 / 60.0, -5.0 / 12.0)
 
 
-def wray3_stages(u0, h, nu, dt, rhs_fn=None):
+def wray3_stages(u0, h, nu, dt, rhs_fn=None, project_fn=None):
     """Stage velocities (u_0, u_1, u_2) and right-hand sides F(u_0), F(u_1), F(u_2)."""
     F = rhs_fn if rhs_fn is not None else (lambda v: rhs(v, h, nu))
+    P = _proj_fn(h, project_fn)
     us = [np.array(u0, dtype=np.float64)]
     fs = [F(us[0])]
-    us.append(project(us[0] + dt * WRAY3_G[0] * fs[0], h)[0])
+    us.append(P(us[0] + dt * WRAY3_G[0] * fs[0]))
     fs.append(F(us[1]))
-    us.append(project(us[1] + dt * (WRAY3_G[1] * fs[1] + WRAY3_Z[0] * fs[0]), h)[0])
+    us.append(P(us[1] + dt * (WRAY3_G[1] * fs[1] + WRAY3_Z[0] * fs[0])))
     fs.append(F(us[2]))
     return us, fs
 
 
-def step_wray3(u0, h, nu, dt, rhs_fn=None):
+def step_wray3(u0, h, nu, dt, rhs_fn=None, project_fn=None):
     """One step of Wray's scheme: u_3 = P(u_2 + dt (g3 F(u_2) + z2 F(u_1)))."""
-    us, fs = wray3_stages(u0, h, nu, dt, rhs_fn)
-    return project(us[2] + dt * (WRAY3_G[2] * fs[2] + WRAY3_Z[1] * fs[1]), h)[0]
+    us, fs = wray3_stages(u0, h, nu, dt, rhs_fn, project_fn)
+    return _proj_fn(h, project_fn)(us[2] + dt * (WRAY3_G[2] * fs[2] + WRAY3_Z[1] * fs[1]))
 
 
 # ----------------------------------------------------------------------------
@@ -284,16 +291,18 @@ def project_vjp(ubar_out, h):
     return project(ubar_out, h)[0]
 
 
-def step_rk4_vjp(u0, u1bar, h, nu, dt, rhs_fn=None, rhs_vjp_fn=None):
+def step_rk4_vjp(u0, u1bar, h, nu, dt, rhs_fn=None, rhs_vjp_fn=None, project_fn=None, project_vjp_fn=None):
     """Reverse pass of ``step_rk4``: the stage loop run backwards with the pullbacks above.
 
     Stage states are recomputed from u0 first (the forward states must exist
     before back-propagation, Sec. 3.4). rhs_vjp_fn(u, fbar) replaces the
-    right-hand-side pullback when given (it may accumulate parameter gradients).
+    right-hand-side pullback when given (it may accumulate parameter gradients);
+    project_fn / project_vjp_fn replace P and its pullback.
     """
-    us, _ = rk4_stages(u0, h, nu, dt, rhs_fn)
+    us, _ = rk4_stages(u0, h, nu, dt, rhs_fn, project_fn)
     G = rhs_vjp_fn if rhs_vjp_fn is not None else (lambda v, fb: rhs_vjp(v, fb, h, nu))
-    ybar = project_vjp(u1bar, h)
+    PT = project_vjp_fn if project_vjp_fn is not None else (lambda v: project_vjp(v, h))
+    ybar = PT(u1bar)
     u0bar = ybar.copy()
     fbar = [dt * RK4_B[i] * ybar for i in range(4)]
     for i in range(3, -1, -1):
@@ -301,13 +310,13 @@ def step_rk4_vjp(u0, u1bar, h, nu, dt, rhs_fn=None, rhs_vjp_fn=None):
         if i == 0:
             u0bar += ubar_i
         else:
-            wbar = project_vjp(ubar_i, h)
+            wbar = PT(ubar_i)
             u0bar += wbar
             fbar[i - 1] = fbar[i - 1] + dt * RK4_A[i - 1] * wbar
     return u0bar
 
 
-def step_wray3_vjp(u0, u1bar, h, nu, dt, rhs_fn=None, rhs_vjp_fn=None):
+def step_wray3_vjp(u0, u1bar, h, nu, dt, rhs_fn=None, rhs_vjp_fn=None, project_fn=None, project_vjp_fn=None):
     """Reverse pass of ``step_wray3``, transposing its two-register recurrence.
 
     With w_k the unprojected stage sums (u_k = P w_k) and wbar_k = P^T ubar(u_k):
@@ -315,15 +324,16 @@ def step_wray3_vjp(u0, u1bar, h, nu, dt, rhs_fn=None, rhs_vjp_fn=None):
       wbar_2 = P u2bar;  u1bar = wbar_2 + J(u_1)^T (dt g2 wbar_2 + F1bar);  F0bar = dt z1 wbar_2
       wbar_1 = P u1bar;  u0bar = wbar_1 + J(u_0)^T (dt g1 wbar_1 + F0bar).
     """
-    us, _ = wray3_stages(u0, h, nu, dt, rhs_fn)
+    us, _ = wray3_stages(u0, h, nu, dt, rhs_fn, project_fn)
     G = rhs_vjp_fn if rhs_vjp_fn is not None else (lambda v, fb: rhs_vjp(v, fb, h, nu))
-    wbar = project_vjp(u1bar, h)
+    PT = project_vjp_fn if project_vjp_fn is not None else (lambda v: project_vjp(v, h))
+    wbar = PT(u1bar)
     ubar = wbar + G(us[2], dt * WRAY3_G[2] * wbar)
     f1bar = dt * WRAY3_Z[1] * wbar
-    wbar = project_vjp(ubar, h)
+    wbar = PT(ubar)
     ubar = wbar + G(us[1], dt * WRAY3_G[1] * wbar + f1bar)
     f0bar = dt * WRAY3_Z[0] * wbar
-    wbar = project_vjp(ubar, h)
+    wbar = PT(ubar)
     return wbar + G(us[0], dt * WRAY3_G[0] * wbar + f0bar)
 
 

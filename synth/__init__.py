@@ -31,6 +31,10 @@ __all__ = [
     "random_scalar",
     "turbulence_ic",
     "energy_spectrum_shape",
+    "channel_box",
+    "channel_shear",
+    "channel_ic",
+    "channel_random",
 ]
 
 TWO_PI = 2.0 * math.pi
@@ -238,3 +242,106 @@ def turbulence_ic_torch(n, seed, k0=4.0, energy=1.0, device="cuda", dtype=None):
     ke = 0.5 * (u * u).sum(0).mean()
     u *= torch.sqrt(energy / ke)
     return u.to(dtype)
+
+
+# ----------------------------------------------------------------------------
+# Channel inputs: no-slip walls at both ends of y (x, z periodic). The normal
+# velocity u^y[..., N_y - 1, ...] is the upper-wall face and is always 0.
+# ----------------------------------------------------------------------------
+
+def channel_box(n):
+    """Box of the channel inputs: x in [0, 2pi], y in [0, 2] (walls), z in [0, pi]."""
+    d = len(n)
+    lo = [0.0] * d
+    hi = [TWO_PI, 2.0, math.pi][:d]
+    return lo, hi
+
+
+def channel_shear(n, m=1, amplitude=1.0, component=0):
+    """u^c = A sin(pi m (y - lo_y) / L_y) (c = x or z) sampled at the cell centres in y."""
+    lo, hi = channel_box(n)
+    d = len(n)
+    u = np.zeros((d,) + tuple(reversed(n)))
+    y = face_coords(n, component, lo, hi)[1]
+    u[component] = amplitude * np.sin(math.pi * m * (y - lo[1]) / (hi[1] - lo[1])) * np.ones(tuple(reversed(n)))
+    return u
+
+
+def _wall_potential(n, rng, modes, lo, hi, yoff):
+    """Smooth random potential sampled at y faces j = 0 .. N_y - 1 (y = lo + (j + 1) h_y), exactly
+    zero on the upper wall row; other coordinates at the offsets given by yoff (x, z offsets)."""
+    d = len(n)
+    h = spacing(n, lo, hi)
+    shape = tuple(reversed(n))
+    grids = []
+    for b in range(d):
+        off = 1.0 if b == 1 else yoff[b]
+        c = lo[b] + (np.arange(n[b]) + off) * h[b]
+        sh = [1] * d
+        sh[d - 1 - b] = n[b]
+        grids.append(c.reshape(sh))
+    ly = hi[1] - lo[1]
+    psi = np.zeros(shape)
+    for _ in range(modes):
+        m = int(rng.integers(1, 4))
+        kx = int(rng.integers(0, 4))
+        kz = int(rng.integers(0, 3)) if d == 3 else 0
+        ph = rng.uniform(0, 2 * math.pi)
+        amp = rng.normal() / (1.0 + m + kx + kz)
+        arg = kx * TWO_PI * grids[0] / (hi[0] - lo[0]) + ph
+        if d == 3:
+            arg = arg + kz * TWO_PI * grids[2] / (hi[2] - lo[2])
+        psi = psi + amp * np.sin(math.pi * m * (grids[1] - lo[1]) / ly) * np.cos(arg)
+    psi[(Ellipsis, slice(n[1] - 1, n[1]), slice(None))] = 0.0  # upper wall row, exactly
+    return psi
+
+
+def channel_ic(n, seed, bulk=1.0, noise=0.2, modes=12):
+    """Laminar profile u^x = 1.5 bulk (1 - eta^2), eta = 2 (y - lo_y) / L_y - 1, plus a
+    perturbation that is the discrete curl of a random potential vanishing on both walls.
+
+    The curl is taken on the staggered positions (potential on cell edges, j the
+    y-face index, the row below the grid being the lower wall where it is 0), so the
+    field has zero discrete divergence and zero normal velocity on the walls.
+    ``noise`` is the RMS of the perturbation relative to the bulk velocity.
+    """
+    d = len(n)
+    lo, hi = channel_box(n)
+    h = spacing(n, lo, hi)
+    rng = np.random.default_rng(seed)
+    shape = tuple(reversed(n))
+    yax = d - 2
+
+    def below(f):  # f at y-face j - 1, zero below the lower wall
+        return np.concatenate([np.zeros_like(np.take(f, [0], axis=yax)), np.take(f, range(n[1] - 1), axis=yax)],
+                              axis=yax)
+
+    def prev(f, a):  # f at I - e_a along a periodic direction
+        return np.roll(f, 1, axis=d - 1 - a)
+
+    up = np.zeros((d,) + shape)
+    # psi_z on (x-face, y-face) edges: u^x += d_y psi_z, u^y -= d_x psi_z
+    psz = _wall_potential(n, rng, modes, lo, hi, [1.0, 1.0, 0.5])
+    up[0] += (psz - below(psz)) / h[1]
+    up[1] -= (psz - prev(psz, 0)) / h[0]
+    if d == 3:
+        # psi_x on (y-face, z-face) edges: u^y += d_z psi_x, u^z -= d_y psi_x
+        psx = _wall_potential(n, rng, modes, lo, hi, [0.5, 1.0, 1.0])
+        up[1] += (psx - prev(psx, 2)) / h[2]
+        up[2] -= (psx - below(psx)) / h[1]
+    rms = float(np.sqrt(np.mean(up ** 2)))
+    if rms > 0:
+        up *= noise * bulk / rms
+    y = face_coords(n, 0, lo, hi)[1]
+    eta = 2.0 * (y - lo[1]) / (hi[1] - lo[1]) - 1.0
+    u = up
+    u[0] += 1.5 * bulk * (1.0 - eta ** 2) * np.ones(shape)
+    u[(1, Ellipsis, slice(n[1] - 1, n[1]), slice(None))] = 0.0
+    return u
+
+
+def channel_random(n, seed):
+    """Seeded standard-normal velocity with the upper-wall face of u^y set to 0."""
+    u = random_field(n, seed)
+    u[(1, Ellipsis, slice(n[1] - 1, n[1]), slice(None))] = 0.0
+    return u
