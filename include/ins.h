@@ -9,7 +9,8 @@
  * accelerated simulation of turbulent flows" (arXiv 2604.18536):
  *   Sec. 2.1   staggered Harlow-Welch grid, code-index convention (Sec. 3.1)
  *   Sec. 2.2   discrete operators; App. B explicit kernels and pullbacks
- *   Sec. 2.5.1 pressure Poisson equation, spectral (DFT) solver
+ *   Sec. 2.1   boundary conditions (no-slip walls through ghost volumes)
+ *   Sec. 2.5.1 pressure Poisson equation, spectral (DFT) and iterative (CG) solvers
  *   Sec. 2.5.2 explicit Runge-Kutta with a projection at every stage
  *   Sec. 3.3   memory: array reuse, low-storage stepping, lazy fluxes
  *   Sec. 3.4   pullback rule and hand-written adjoint kernels
@@ -19,9 +20,11 @@
  * ----------------------------------------------------------------------------
  * Conventions shared by every entry point
  * ----------------------------------------------------------------------------
- * Grid. Uniform, periodic in every direction, dim 2 or 3, cell counts n[0]
- * (x), n[1] (y), n[2] (z; ignored in 2D), box [lo, hi] per direction, and
- * `batch` independent fields processed by every call.
+ * Grid. Uniform, dim 2 or 3, cell counts n[0] (x), n[1] (y), n[2] (z;
+ * ignored in 2D), box [lo, hi] per direction, and `batch` independent fields
+ * processed by every call. Periodic in every direction (INS_BC_PERIODIC), or
+ * a channel (INS_BC_WALLS_Y): no-slip walls at y = lo[1] and y = hi[1], x and
+ * z periodic; see the channel section below.
  *
  * Layout. All field arguments are device pointers to dense arrays, x fastest:
  *   velocity-point field (u, f, ubar, ...):  [batch][dim][n_z][n_y][n_x]
@@ -86,7 +89,18 @@ typedef enum {
 
 typedef enum { INS_FP64 = 0, INS_FP32 = 1 } ins_dtype;
 
-typedef enum { INS_BC_PERIODIC = 0 } ins_bc;
+/* INS_BC_PERIODIC: periodic in every direction; pressure by FFT.
+ * INS_BC_WALLS_Y:  channel: no-slip walls at both y ends (Sec. 2.1 Dirichlet
+ *   condition u = 0 imposed through ghost volumes), x and z periodic;
+ *   pressure by matrix-free conjugate gradients (Sec. 2.5.1 iterative solver).
+ *   The layout is unchanged: u^y[..][n_y - 1][..] is the upper-wall face, a
+ *   boundary value, not an unknown. Every operator reads it (and the lower-wall
+ *   face) as 0 and every velocity output, forward or pullback, writes 0 there.
+ *   A tangential component one cell beyond a wall reads as minus the first
+ *   interior value (zero linear interpolant on the wall). The gradient lives
+ *   on interior faces only, so D G is the Neumann Laplacian; the pressure solve
+ *   returns the zero-mean solution of D G p = r - mean(r). */
+typedef enum { INS_BC_PERIODIC = 0, INS_BC_WALLS_Y = 1 } ins_bc;
 
 typedef struct {
     int32_t dim;     /* 2 or 3 */
@@ -101,12 +115,13 @@ typedef struct {
  * ------------------------------------------------------------------------- */
 
 /* Create a context on the current HIP device.
- * Requirements (else INS_ERR_UNSUPPORTED): n_x even; n_x/2, n_y and n_z each
- * a product of the primes 2, 3, 5, 7 and at most 4096; n_y, n_z >= 2, n_x >= 4.
- * (The real-to-complex FFT along x works on n_x/2 complex points; the spectral
- * solver of Sec. 2.5.1 needs a uniform periodic grid.) nu >= 0 is the
- * kinematic viscosity of the diffusion term. Allocates the forward
- * workspace: stage registers (3 velocity fields), pressure and half spectrum. */
+ * Requirements (else INS_ERR_UNSUPPORTED): every n in [2, 4096]; for
+ * INS_BC_PERIODIC also n_x even and >= 4 and n_x/2, n_y, n_z products of the
+ * primes 2, 3, 5, 7 (the real-to-complex FFT along x works on n_x/2 complex
+ * points; the spectral solver of Sec. 2.5.1 needs a uniform periodic grid).
+ * nu >= 0 is the kinematic viscosity of the diffusion term. Allocates the
+ * forward workspace: stage registers (3 velocity fields), pressure, and the
+ * half spectrum (periodic) or four CG pressure-point fields (channel). */
 ins_status ins_create(const ins_grid* grid, ins_bc bc, double nu, ins_dtype dtype, ins_ctx* out);
 ins_status ins_destroy(ins_ctx ctx);
 /* stream: a hipStream_t (NULL = null stream). */
@@ -114,6 +129,32 @@ ins_status ins_set_stream(ins_ctx ctx, void* stream);
 /* Device bytes currently held by the context. */
 ins_status ins_workspace_bytes(ins_ctx ctx, size_t* bytes);
 const char* ins_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Channel grid (INS_BC_WALLS_Y): conjugate-gradient pressure solve
+ *
+ * Every pressure solve (ins_poisson_solve, ins_project, the steps and their
+ * pullbacks) runs CG on A = -D G, the Laplace operator applied as the
+ * divergence of the gradient without assembling it (Sec. 2.5.1 iterative
+ * solver), from p = 0, for A p = mean(r) - r, independently per batch field.
+ * A field stops once ||res|| <= rtol ||res_0|| (res the recursively updated
+ * residual) or after maxiter iterations. Iterations run back to back on the
+ * stream; every check_every iterations the call reads the convergence flags
+ * to the host once (a stream synchronisation), and stops launching when all
+ * fields are done. check_every = 0 never synchronises and always launches
+ * maxiter iterations (done fields skip the work), which keeps a captured
+ * graph free of host reads. The pressure solve is self-adjoint: its pullback
+ * is the same solve. Closures, the face filter and the energy spectrum need
+ * the periodic grid (INS_ERR_UNSUPPORTED).
+ * ------------------------------------------------------------------------- */
+
+/* Defaults: rtol 1e-10, maxiter 20000, check_every 16. INS_ERR_UNSUPPORTED
+ * on a periodic context; INS_ERR_INVALID for rtol < 0, maxiter < 1 or
+ * check_every < 0. */
+ins_status ins_cg_set(ins_ctx ctx, double rtol, int maxiter, int check_every);
+/* Iterations and final relative residual ||res|| / ||res_0|| of the last
+ * solve (maxima over the batch). Synchronises the context's stream. */
+ins_status ins_cg_info(ins_ctx ctx, int* iterations, double* relres);
 
 /* ---------------------------------------------------------------------------
  * Forward operators (App. B kernels; Sec. 2.5)

@@ -15,6 +15,7 @@ INS_ERR_HIP = -4
 INS_FP64 = 0
 INS_FP32 = 1
 INS_BC_PERIODIC = 0
+INS_BC_WALLS_Y = 1
 INS_RK4 = 0
 INS_WRAY3 = 1
 
@@ -64,6 +65,8 @@ _SIGS = {
     "ins_step_wray3": ([_P, _P, _P, _D]),
     "ins_step_wray3_vjp": ([_P, _P, _P, _P, _D]),
     "ins_step_save": ([_P, C.c_int, _P, _P, _D, _P, _P]),
+    "ins_cg_set": ([_P, _D, C.c_int, C.c_int]),
+    "ins_cg_info": ([_P, C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     "ins_step_vjp_saved": ([_P, C.c_int, _P, _P, _P, _P, _P, _D]),
     "ins_scheme_stage_count": ([C.c_int]),
     "ins_eddy_set": ([_P, _D, _D]),

@@ -151,6 +151,53 @@ hipError_t launch_closure_wgrad(const Grid& g, int which, const unsigned short* 
                                 float* partial, float* wbar, float* bbar, hipStream_t s);
 size_t closure_wgrad_partial_floats(int64_t ncells);
 
+// Channel grid (k_walls.hip): no-slip walls at both y ends, x and z periodic.
+// Same contracts as the periodic launchers above; the wall face of u^y is
+// written as 0 by every velocity output.
+template <typename T>
+hipError_t launch_wall_rhs(const Grid& g, const T* u, T* f, hipStream_t s);
+template <typename T>
+hipError_t launch_wall_divergence(const Grid& g, const T* u, double* r, hipStream_t s);
+template <typename T>
+hipError_t launch_wall_gradient(const Grid& g, const double* p, T* out, hipStream_t s);
+template <typename T>
+hipError_t launch_wall_project(const Grid& g, const T* w, const double* p, T* u_out, hipStream_t s);
+template <typename T>
+hipError_t launch_wall_rhs_vjp(const Grid& g, const T* u, const T* fbar, T* ubar, hipStream_t s);
+template <typename T>
+hipError_t launch_wall_div_vjp(const Grid& g, const double* rbar, T* ubar, hipStream_t s);
+template <typename T>
+hipError_t launch_wall_grad_vjp(const Grid& g, const T* gbar, double* pbar, hipStream_t s);
+template <typename T>
+hipError_t launch_wall_stage(const Grid& g, const T* w, const double* p, bool proj, const T* u0, T* y, bool yinit,
+                             double cy, T* wout, double cw, hipStream_t s);
+template <typename T>
+hipError_t launch_wall_stage_vjp(const Grid& g, const T* w, const double* p, bool proj_u, const T* ybar, const T* un,
+                                 const double* q, bool has_w, double cb, double cw, T* u0bar, int mode, T* ubar_out,
+                                 hipStream_t s);
+
+// Scalars of one field's conjugate-gradient solve, kept in device memory.
+struct CgScal {
+    double rr, rr0, pq, alpha, beta, mean, relres;
+    int it, done;
+};
+// Reductions use `partials` (stencil_blocks(g) doubles) and `counter` (0
+// between launches; each kernel's last workgroup resets it).
+// r = D vel (vel != null) or rin; st.mean = mean of r per field.
+template <typename T>
+hipError_t launch_cg_div(const Grid& g, const T* vel, const double* rin, double* r, double* partials,
+                         unsigned int* counter, CgScal* st, hipStream_t s);
+// r = mean - r, x = 0, p0 = 0, st.rr = st.rr0 = r.r, flags cleared.
+hipError_t launch_cg_init(const Grid& g, double* r, double* x, double* p0, double* partials, unsigned int* counter,
+                          CgScal* st, int maxiter, hipStream_t s);
+// pout = r + beta pin, q = -D G pout, st.alpha = rr / pout.q.
+hipError_t launch_cg_apply(const Grid& g, const double* r, const double* pin, double* pout, double* q, double* partials,
+                           unsigned int* counter, CgScal* st, hipStream_t s);
+// x += alpha p, r -= alpha q, st.beta / rr / it / relres, st.done once rr <= rtol2 rr0 or it == maxiter.
+hipError_t launch_cg_update(const Grid& g, double* x, const double* p, double* r, const double* q, double* partials,
+                            unsigned int* counter, CgScal* st, double rtol2, int maxiter, hipStream_t s);
+int stencil_block_count(const Grid& g);
+
 // Utilities.
 template <typename T>
 hipError_t launch_stats(const Grid& g, const T* u, double* partial, int nblocks, hipStream_t s);

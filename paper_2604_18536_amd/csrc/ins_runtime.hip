@@ -145,6 +145,20 @@ struct ins_ctx_s {
     int device = 0;
     hipStream_t stream = nullptr;
 
+    bool walls = false;  // no-slip walls at both y ends (INS_BC_WALLS_Y): CG pressure solve
+
+    // conjugate-gradient solve of the channel grid
+    double cg_rtol = 1e-10;
+    int cg_maxiter = 20000;
+    int cg_check = 16;  // iterations between host convergence checks (0: never; all cg_maxiter launched)
+    double* cg_r = nullptr;
+    double* cg_p[2] = {nullptr, nullptr};
+    double* cg_q = nullptr;
+    double* cg_part = nullptr;
+    unsigned int* cg_cnt = nullptr;
+    ins::CgScal* cg_st = nullptr;
+    ins::CgScal* cg_host = nullptr;  // pinned host copy of cg_st
+
     ins::FftPlan px{}, py{}, pz{};
     ins::FftPlan py_rev{}, pz_rev{};  // radices reversed: inverse half of the fused last-axis solve
     int lnl_x = 0, lnl_y = 0, lnl_z = 0;
@@ -267,6 +281,7 @@ struct ins_ctx_s {
         }
         for (auto e : pool) (void)hipEventDestroy(e);
         for (void* ptr : allocs) (void)hipFree(ptr);
+        if (cg_host) (void)hipHostFree(cg_host);
     }
 };
 
@@ -293,6 +308,10 @@ void need(const void* ptr, const char* what) {
     if (!ptr) raise(INS_ERR_INVALID, std::string(what) + " is null");
 }
 
+void periodic_only(ins_ctx c, const char* what) {
+    if (c->walls) raise(INS_ERR_UNSUPPORTED, std::string(what) + " needs the periodic grid");
+}
+
 ins_ctx checked(ins_ctx c) {
     if (!c) raise(INS_ERR_INVALID, "context is null");
     int dev = -1;
@@ -309,9 +328,60 @@ void with_type(ins_ctx c, F&& f) {
         f(float{});
 }
 
+bool cg_all_done(ins_ctx c) {
+    const size_t nb = size_t(c->g.batch) * sizeof(ins::CgScal);
+    hip_check(hipMemcpyAsync(c->cg_host, c->cg_st, nb, hipMemcpyDeviceToHost, c->stream), "hipMemcpyAsync");
+    hip_check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    for (int b = 0; b < c->g.batch; ++b)
+        if (!c->cg_host[b].done) return false;
+    return true;
+}
+
+// Channel grid: x = (D G)^+ of the divergence of vel or of r, by conjugate
+// gradients on -D G (Sec. 2.5.1, iterative solver) from x = 0; the mean of
+// the right-hand side is removed first (the zero-mean solution of the
+// consistent part). Iterations are launched back to back; every cg_check
+// iterations the host reads the convergence flags once.
+void cg_solve(ins_ctx c, const void* vel, const double* r, double* x) {
+    const ins::Grid& g = c->g;
+    if (vel) {
+        with_type(c, [&](auto tag) {
+            using T = decltype(tag);
+            c->launch("cg_div", [&] {
+                return ins::launch_cg_div<T>(g, static_cast<const T*>(vel), nullptr, c->cg_r, c->cg_part, c->cg_cnt,
+                                             c->cg_st, c->stream);
+            });
+        });
+    } else {
+        c->launch("cg_copy", [&] {
+            return ins::launch_cg_div<double>(g, nullptr, r, c->cg_r, c->cg_part, c->cg_cnt, c->cg_st, c->stream);
+        });
+    }
+    c->launch("cg_init", [&] {
+        return ins::launch_cg_init(g, c->cg_r, x, c->cg_p[0], c->cg_part, c->cg_cnt, c->cg_st, c->cg_maxiter, c->stream);
+    });
+    const double rtol2 = c->cg_rtol * c->cg_rtol;
+    for (int k = 0; k < c->cg_maxiter; ++k) {
+        double* pin = c->cg_p[k & 1];
+        double* pout = c->cg_p[(k + 1) & 1];
+        c->launch("cg_apply", [&] {
+            return ins::launch_cg_apply(g, c->cg_r, pin, pout, c->cg_q, c->cg_part, c->cg_cnt, c->cg_st, c->stream);
+        });
+        c->launch("cg_update", [&] {
+            return ins::launch_cg_update(g, x, pout, c->cg_r, c->cg_q, c->cg_part, c->cg_cnt, c->cg_st, rtol2,
+                                         c->cg_maxiter, c->stream);
+        });
+        if (c->cg_check > 0 && (k + 1) % c->cg_check == 0 && k + 1 < c->cg_maxiter && cg_all_done(c)) break;
+    }
+}
+
 // p = (D G)^-1 of the divergence of vel (vel != null) or of r.
 void poisson(ins_ctx c, const void* vel, const double* r, double* p) {
     const ins::Grid& g = c->g;
+    if (c->walls) {
+        cg_solve(c, vel, r, p);
+        return;
+    }
     if (vel) {
         with_type(c, [&](auto tag) {
             using T = decltype(tag);
@@ -338,6 +408,10 @@ void poisson(ins_ctx c, const void* vel, const double* r, double* p) {
 
 template <typename T>
 void apply_projection(ins_ctx c, const T* w, const double* p, T* out) {
+    if (c->walls) {
+        c->launch("wall_projection", [&] { return ins::launch_wall_project<T>(c->g, w, p, out, c->stream); });
+        return;
+    }
     c->launch("apply_projection", [&] { return ins::launch_apply_projection<T>(c->g, w, p, out, c->stream); });
 }
 
@@ -470,11 +544,15 @@ const T* closure_at_stage(ins_ctx c, const T* w, const double* p, bool keep_z = 
 template <typename T>
 void stage(ins_ctx c, const T* w, const double* p, bool proj, const T* u0, T* y, bool yinit, double cy, T* wout,
            double cw, const char* label = nullptr) {
-    const T* mc = closure_at_stage<T>(c, w, proj ? p : nullptr);
     // one profile name per data-movement variant (their byte counts differ)
     const char* name = label ? label
                              : !proj ? (y ? "stage_first" : "stage_first_rec")
                                      : (y ? (wout ? "stage" : "stage_last") : "stage_rec");
+    if (c->walls) {
+        c->launch(name, [&] { return ins::launch_wall_stage<T>(c->g, w, p, proj, u0, y, yinit, cy, wout, cw, c->stream); });
+        return;
+    }
+    const T* mc = closure_at_stage<T>(c, w, proj ? p : nullptr);
     c->launch(name, [&] {
         return ins::launch_stage<T>(c->g, w, p, proj, u0, y, yinit, cy, wout, cw, c->stream, mc);
     });
@@ -535,8 +613,15 @@ void ensure_vjp_storage(ins_ctx c) {
 template <typename T>
 void stage_vjp(ins_ctx c, const T* w, const double* p, bool proj_u, const T* ybar, const T* un, const double* q,
                bool has_w, double cb, double cw, T* u0bar, int mode, T* out) {
-    T* fb = c->clos_on ? static_cast<T*>(c->fbar) : nullptr;
     const char* name = mode == 0 ? "stage_vjp_first" : (mode >= 2 ? "stage_vjp_last" : "stage_vjp");
+    if (c->walls) {
+        c->launch(name, [&] {
+            return ins::launch_wall_stage_vjp<T>(c->g, w, p, proj_u, ybar, un, q, has_w, cb, cw, u0bar, mode, out,
+                                                 c->stream);
+        });
+        return;
+    }
+    T* fb = c->clos_on ? static_cast<T*>(c->fbar) : nullptr;
     c->launch(name, [&] {
         return ins::launch_stage_vjp<T>(c->g, w, p, proj_u, ybar, un, q, has_w, cb, cw, u0bar, mode, out, c->stream, fb);
     });
@@ -660,7 +745,8 @@ ins_status ins_create(const ins_grid* grid, ins_bc bc, double nu, ins_dtype dtyp
     const ins_status st = guarded([&] {
         need(grid, "grid");
         need(out, "out");
-        if (bc != INS_BC_PERIODIC) raise(INS_ERR_UNSUPPORTED, "only periodic boundaries are supported");
+        if (bc != INS_BC_PERIODIC && bc != INS_BC_WALLS_Y) raise(INS_ERR_UNSUPPORTED, "unknown boundary condition");
+        const bool walls = bc == INS_BC_WALLS_Y;
         if (dtype != INS_FP64 && dtype != INS_FP32) raise(INS_ERR_INVALID, "unknown dtype");
         if (grid->dim != 2 && grid->dim != 3) raise(INS_ERR_UNSUPPORTED, "dim must be 2 or 3");
         if (!(nu >= 0.0) || !std::isfinite(nu)) raise(INS_ERR_INVALID, "nu must be finite and >= 0");
@@ -672,15 +758,17 @@ ins_status ins_create(const ins_grid* grid, ins_bc bc, double nu, ins_dtype dtyp
             if (!(grid->hi[a] > grid->lo[a]) || !std::isfinite(grid->hi[a] - grid->lo[a]))
                 raise(INS_ERR_INVALID, "box must have hi > lo");
         }
-        if (n[0] % 2 != 0 || n[0] < 4) raise(INS_ERR_UNSUPPORTED, "n_x must be even and >= 4 (real-to-complex FFT)");
+        if (!walls && (n[0] % 2 != 0 || n[0] < 4))
+            raise(INS_ERR_UNSUPPORTED, "n_x must be even and >= 4 (real-to-complex FFT)");
         const int64_t ncell = n[0] * n[1] * n[2];
         if (ncell * d >= (int64_t(1) << 31)) raise(INS_ERR_UNSUPPORTED, "grid too large for 32-bit in-field indexing");
 
         std::vector<int> rx, ry, rz;
-        if (!factor(int(n[0] / 2), rx) || !factor(int(n[1]), ry) || (d == 3 && !factor(int(n[2]), rz)))
+        if (!walls && (!factor(int(n[0] / 2), rx) || !factor(int(n[1]), ry) || (d == 3 && !factor(int(n[2]), rz))))
             raise(INS_ERR_UNSUPPORTED, "n_x/2, n_y, n_z must be products of 2, 3, 5, 7");
 
         c = new ins_ctx_s();
+        c->walls = walls;
         hip_check(hipGetDevice(&c->device), "hipGetDevice");
         c->dtype = dtype;
         ins::Grid& g = c->g;
@@ -696,6 +784,31 @@ ins_status ins_create(const ins_grid* grid, ins_bc bc, double nu, ins_dtype dtyp
             g.ih2[a] = a < d ? 1.0 / (h * h) : 0.0;
         }
         g.nu = nu;
+
+        if (walls) {
+            // channel grid: CG workspace instead of FFT plans and spectrum
+            const size_t sb = c->scal_bytes();
+            c->cg_r = static_cast<double*>(c->alloc(sb));
+            c->cg_p[0] = static_cast<double*>(c->alloc(sb));
+            c->cg_p[1] = static_cast<double*>(c->alloc(sb));
+            c->cg_q = static_cast<double*>(c->alloc(sb));
+            c->cg_part = static_cast<double*>(c->alloc(size_t(ins::stencil_block_count(g)) * sizeof(double)));
+            c->cg_cnt = static_cast<unsigned int*>(c->alloc(256));
+            c->cg_st = static_cast<ins::CgScal*>(c->alloc(size_t(g.batch) * sizeof(ins::CgScal)));
+            hip_check(hipMemset(c->cg_cnt, 0, 256), "hipMemset");
+            hip_check(hipMemset(c->cg_st, 0, size_t(g.batch) * sizeof(ins::CgScal)), "hipMemset");
+            hip_check(hipHostMalloc(reinterpret_cast<void**>(&c->cg_host), size_t(g.batch) * sizeof(ins::CgScal)),
+                      "hipHostMalloc");
+            c->p = static_cast<double*>(c->alloc(c->scal_bytes()));
+            c->ry = c->alloc(c->vel_bytes());
+            c->wa = c->alloc(c->vel_bytes());
+            c->wb = c->alloc(c->vel_bytes());
+            c->nstat = ins::stats_blocks(g);
+            c->partials = static_cast<double*>(c->alloc(size_t(c->nstat) * 4 * sizeof(double)));
+            hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+            *out = c;
+            return;
+        }
 
         // FFT plans: x works on n_x/2 complex points.
         std::vector<cd> tw;
@@ -798,6 +911,12 @@ ins_status ins_rhs(ins_ctx ctx, const void* u, void* f) {
         need(f, "f");
         with_type(ctx, [&](auto tag) {
             using T = decltype(tag);
+            if (ctx->walls) {
+                ctx->launch("wall_rhs", [&] {
+                    return ins::launch_wall_rhs<T>(ctx->g, static_cast<const T*>(u), static_cast<T*>(f), ctx->stream);
+                });
+                return;
+            }
             const T* mc = closure_at_stage<T>(ctx, static_cast<const T*>(u), nullptr);
             ctx->launch("rhs", [&] {
                 return ins::launch_rhs<T>(ctx->g, static_cast<const T*>(u), static_cast<T*>(f), ctx->stream, mc);
@@ -813,7 +932,12 @@ ins_status ins_divergence(ins_ctx ctx, const void* u, double* r) {
         need(r, "r");
         with_type(ctx, [&](auto tag) {
             using T = decltype(tag);
-            ctx->launch("divergence", [&] { return ins::launch_divergence<T>(ctx->g, static_cast<const T*>(u), r, ctx->stream); });
+            if (ctx->walls)
+                ctx->launch("wall_divergence", [&] {
+                    return ins::launch_wall_divergence<T>(ctx->g, static_cast<const T*>(u), r, ctx->stream);
+                });
+            else
+                ctx->launch("divergence", [&] { return ins::launch_divergence<T>(ctx->g, static_cast<const T*>(u), r, ctx->stream); });
         });
     });
 }
@@ -825,7 +949,10 @@ ins_status ins_gradient(ins_ctx ctx, const double* p, void* gout) {
         need(gout, "g");
         with_type(ctx, [&](auto tag) {
             using T = decltype(tag);
-            ctx->launch("gradient", [&] { return ins::launch_gradient<T>(ctx->g, p, static_cast<T*>(gout), ctx->stream); });
+            if (ctx->walls)
+                ctx->launch("wall_gradient", [&] { return ins::launch_wall_gradient<T>(ctx->g, p, static_cast<T*>(gout), ctx->stream); });
+            else
+                ctx->launch("gradient", [&] { return ins::launch_gradient<T>(ctx->g, p, static_cast<T*>(gout), ctx->stream); });
         });
     });
 }
@@ -874,6 +1001,13 @@ ins_status ins_rhs_vjp(ins_ctx ctx, const void* u, const void* fbar, void* ubar)
         need(ubar, "ubar");
         with_type(ctx, [&](auto tag) {
             using T = decltype(tag);
+            if (ctx->walls) {
+                ctx->launch("wall_rhs_vjp", [&] {
+                    return ins::launch_wall_rhs_vjp<T>(ctx->g, static_cast<const T*>(u), static_cast<const T*>(fbar),
+                                                       static_cast<T*>(ubar), ctx->stream);
+                });
+                return;
+            }
             ctx->launch("rhs_vjp", [&] {
                 return ins::launch_rhs_vjp<T>(ctx->g, static_cast<const T*>(u), static_cast<const T*>(fbar),
                                               static_cast<T*>(ubar), ctx->stream);
@@ -893,7 +1027,10 @@ ins_status ins_divergence_vjp(ins_ctx ctx, const double* rbar, void* ubar) {
         need(ubar, "ubar");
         with_type(ctx, [&](auto tag) {
             using T = decltype(tag);
-            ctx->launch("divergence_vjp", [&] { return ins::launch_div_vjp<T>(ctx->g, rbar, static_cast<T*>(ubar), ctx->stream); });
+            if (ctx->walls)
+                ctx->launch("wall_divergence_vjp", [&] { return ins::launch_wall_div_vjp<T>(ctx->g, rbar, static_cast<T*>(ubar), ctx->stream); });
+            else
+                ctx->launch("divergence_vjp", [&] { return ins::launch_div_vjp<T>(ctx->g, rbar, static_cast<T*>(ubar), ctx->stream); });
         });
     });
 }
@@ -905,7 +1042,10 @@ ins_status ins_gradient_vjp(ins_ctx ctx, const void* gbar, double* pbar) {
         need(pbar, "pbar");
         with_type(ctx, [&](auto tag) {
             using T = decltype(tag);
-            ctx->launch("gradient_vjp", [&] { return ins::launch_grad_vjp<T>(ctx->g, static_cast<const T*>(gbar), pbar, ctx->stream); });
+            if (ctx->walls)
+                ctx->launch("wall_gradient_vjp", [&] { return ins::launch_wall_grad_vjp<T>(ctx->g, static_cast<const T*>(gbar), pbar, ctx->stream); });
+            else
+                ctx->launch("gradient_vjp", [&] { return ins::launch_grad_vjp<T>(ctx->g, static_cast<const T*>(gbar), pbar, ctx->stream); });
         });
     });
 }
@@ -1020,9 +1160,40 @@ ins_status ins_step_vjp_saved(ins_ctx ctx, int scheme, const void* u0, const voi
     });
 }
 
+ins_status ins_cg_set(ins_ctx ctx, double rtol, int maxiter, int check_every) {
+    return guarded([&] {
+        checked(ctx);
+        if (!ctx->walls) raise(INS_ERR_UNSUPPORTED, "the periodic grid solves by FFT, not CG");
+        if (!(rtol >= 0.0) || !std::isfinite(rtol)) raise(INS_ERR_INVALID, "rtol must be finite and >= 0");
+        if (maxiter < 1 || check_every < 0) raise(INS_ERR_INVALID, "maxiter must be >= 1 and check_every >= 0");
+        ctx->cg_rtol = rtol;
+        ctx->cg_maxiter = maxiter;
+        ctx->cg_check = check_every;
+    });
+}
+
+ins_status ins_cg_info(ins_ctx ctx, int* iterations, double* relres) {
+    return guarded([&] {
+        checked(ctx);
+        need(iterations, "iterations");
+        need(relres, "relres");
+        if (!ctx->walls) raise(INS_ERR_UNSUPPORTED, "the periodic grid solves by FFT, not CG");
+        cg_all_done(ctx);
+        int it = 0;
+        double rr = 0.0;
+        for (int b = 0; b < ctx->g.batch; ++b) {
+            it = std::max(it, ctx->cg_host[b].it);
+            rr = std::max(rr, ctx->cg_host[b].relres);
+        }
+        *iterations = it;
+        *relres = rr;
+    });
+}
+
 ins_status ins_face_filter(ins_ctx ctx, const void* u, int factor, void* u_coarse) {
     return guarded([&] {
         checked(ctx);
+        periodic_only(ctx, "ins_face_filter");
         need(u, "u");
         need(u_coarse, "u_coarse");
         const ins::Grid& g = ctx->g;
@@ -1040,6 +1211,7 @@ ins_status ins_face_filter(ins_ctx ctx, const void* u, int factor, void* u_coars
 ins_status ins_energy_spectrum(ins_ctx ctx, const void* u, double* e, int nbins) {
     return guarded([&] {
         checked(ctx);
+        periodic_only(ctx, "ins_energy_spectrum");
         need(u, "u");
         need(e, "e");
         if (nbins < 1) raise(INS_ERR_INVALID, "nbins must be >= 1");
@@ -1064,6 +1236,7 @@ ins_status ins_energy_spectrum(ins_ctx ctx, const void* u, double* e, int nbins)
 ins_status ins_closure_set(ins_ctx ctx, const float* params) {
     return guarded([&] {
         checked(ctx);
+        periodic_only(ctx, "ins_closure_set");
         if (!params) {
             if (ctx->clos_kind == 1) {
                 ctx->clos_on = false;
@@ -1094,6 +1267,7 @@ ins_status ins_closure_set(ins_ctx ctx, const float* params) {
 ins_status ins_eddy_set(ins_ctx ctx, double cs, double delta) {
     return guarded([&] {
         checked(ctx);
+        periodic_only(ctx, "ins_eddy_set");
         if (!(cs >= 0.0) || !std::isfinite(cs)) raise(INS_ERR_INVALID, "cs must be finite and >= 0");
         if (!std::isfinite(delta)) raise(INS_ERR_INVALID, "delta must be finite");
         if (cs == 0.0) {
@@ -1120,6 +1294,7 @@ ins_status ins_eddy_set(ins_ctx ctx, double cs, double delta) {
 ins_status ins_eddy_forward(ins_ctx ctx, const void* u, void* m) {
     return guarded([&] {
         checked(ctx);
+        periodic_only(ctx, "ins_eddy_forward");
         need(u, "u");
         need(m, "m");
         if (ctx->clos_kind != 2) raise(INS_ERR_INVALID, "no eddy-viscosity closure has been set");
@@ -1133,6 +1308,7 @@ ins_status ins_eddy_forward(ins_ctx ctx, const void* u, void* m) {
 ins_status ins_eddy_backward(ins_ctx ctx, const void* u, const void* mbar, void* ubar) {
     return guarded([&] {
         checked(ctx);
+        periodic_only(ctx, "ins_eddy_backward");
         need(u, "u");
         need(mbar, "mbar");
         need(ubar, "ubar");
@@ -1166,6 +1342,7 @@ ins_status ins_closure_grad(ins_ctx ctx, float* params_bar) {
 ins_status ins_cnn_forward(ins_ctx ctx, const void* u, void* m) {
     return guarded([&] {
         checked(ctx);
+        periodic_only(ctx, "ins_cnn_forward");
         need(u, "u");
         need(m, "m");
         if (ctx->clos_kind != 1) raise(INS_ERR_INVALID, "no learned closure has been set");
@@ -1179,6 +1356,7 @@ ins_status ins_cnn_forward(ins_ctx ctx, const void* u, void* m) {
 ins_status ins_cnn_backward(ins_ctx ctx, const void* u, const void* mbar, void* ubar, float* params_bar) {
     return guarded([&] {
         checked(ctx);
+        periodic_only(ctx, "ins_cnn_backward");
         need(u, "u");
         need(mbar, "mbar");
         need(ubar, "ubar");

@@ -14,10 +14,11 @@ import torch
 from . import _lib as L
 
 _DTYPES = {"fp64": (L.INS_FP64, torch.float64), "fp32": (L.INS_FP32, torch.float32)}
+_BCS = {"periodic": L.INS_BC_PERIODIC, "walls": L.INS_BC_WALLS_Y}
 
 
 class Solver:
-    """Staggered periodic incompressible Navier-Stokes operators on one GPU.
+    """Staggered-grid incompressible Navier-Stokes operators on one GPU.
 
     Args:
         n: cells per direction, (n_x, n_y) or (n_x, n_y, n_z).
@@ -27,11 +28,19 @@ class Solver:
             and projection).
         batch: number of independent fields per call.
         lo, hi: box corners (default [0, 2 pi] per direction).
+        bc: "periodic" (every direction; FFT pressure solve) or "walls"
+            (channel: no-slip walls at y = lo[1] and hi[1], x and z periodic;
+            conjugate-gradient pressure solve, see cg_set). In the channel the
+            stored u^y face of the last cell row is the upper wall: it reads as
+            0 and every output writes 0 there.
     """
 
-    def __init__(self, n, nu=0.0, precision="fp64", batch=1, lo=None, hi=None, device=None):
+    def __init__(self, n, nu=0.0, precision="fp64", batch=1, lo=None, hi=None, device=None, bc="periodic"):
         if precision not in _DTYPES:
             raise ValueError(f"precision must be one of {list(_DTYPES)}")
+        if bc not in _BCS:
+            raise ValueError(f"bc must be one of {list(_BCS)}")
+        self.bc = bc
         self.n = tuple(int(v) for v in n)
         self.dim = len(self.n)
         if self.dim not in (2, 3):
@@ -55,7 +64,7 @@ class Solver:
         g.batch = self.batch
         self._ctx = C.c_void_p()
         with torch.cuda.device(self.device):
-            L.call("ins_create", C.byref(g), L.INS_BC_PERIODIC, self.nu, self._code, C.byref(self._ctx))
+            L.call("ins_create", C.byref(g), _BCS[bc], self.nu, self._code, C.byref(self._ctx))
         spatial = tuple(reversed(self.n))
         self.vel_shape = (self.batch, self.dim) + spatial
         self.scal_shape = (self.batch,) + spatial
@@ -109,6 +118,17 @@ class Solver:
 
     def new_scalar(self):
         return torch.zeros(self.scal_shape, dtype=torch.float64, device=self.device)
+
+    def cg_set(self, rtol=1e-10, maxiter=20000, check_every=16):
+        """Stopping rule of the channel's conjugate-gradient pressure solves."""
+        L.call("ins_cg_set", self._ctx, float(rtol), int(maxiter), int(check_every))
+
+    def cg_info(self):
+        """(iterations, relative residual) of the last pressure solve (maxima over the batch)."""
+        self._sync_stream()
+        it, rel = C.c_int(), C.c_double()
+        L.call("ins_cg_info", self._ctx, C.byref(it), C.byref(rel))
+        return int(it.value), float(rel.value)
 
     def workspace_bytes(self):
         v = C.c_size_t()

@@ -31,7 +31,8 @@ def test_header_declares_the_boundary():
     for must in ["ins_create", "ins_destroy", "ins_rhs", "ins_divergence", "ins_poisson_solve", "ins_project",
                  "ins_step_rk4", "ins_rhs_vjp", "ins_divergence_vjp", "ins_poisson_solve_vjp", "ins_project_vjp",
                  "ins_step_rk4_vjp", "ins_step_wray3", "ins_step_wray3_vjp", "ins_eddy_set", "ins_eddy_forward",
-                 "ins_eddy_backward", "ins_step_save", "ins_step_vjp_saved", "ins_scheme_stage_count"]:
+                 "ins_eddy_backward", "ins_step_save", "ins_step_vjp_saved", "ins_scheme_stage_count", "ins_cg_set",
+                 "ins_cg_info"]:
         assert must in names
 
 
@@ -91,6 +92,9 @@ def test_null_context_is_rejected(lib):
     assert lib.ins_step_vjp_saved(p, 0, p, p, p, p, p, 1e-3) == -1
     assert lib.ins_scheme_stage_count(0) == 3 and lib.ins_scheme_stage_count(1) == 2
     assert lib.ins_scheme_stage_count(7) == -1
+    assert lib.ins_cg_set(p, 1e-8, 10, 2) == -1
+    it, rel = C.c_int(), C.c_double()
+    assert lib.ins_cg_info(p, C.byref(it), C.byref(rel)) == -1
     assert b"null" in lib.ins_last_error()
     assert lib.ins_destroy(p) == 0
 
