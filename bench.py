@@ -77,6 +77,13 @@ def kernel_bytes(name, n, elem, batch=1):
         "stage_vjp_last": (5 * v + S) * N,        # read u0, ybar, ubar', q, u0bar; write u0bar
         "rhs": 2 * v * N,
         "rhs_vjp": 3 * v * N,
+        # channel grid: conjugate-gradient pressure solve (float64 pressure-point fields)
+        "cg_div": (v + S) * N,                    # read w; write r
+        "cg_copy": 2 * S * N,
+        "cg_init": 4 * S * N,                     # read r; write r, x, p
+        "cg_apply": 4 * S * N,                    # read r, p_old; write p, q
+        "cg_update": 6 * S * N,                   # read x, p, r, q; write x, r
+        "wall_projection": (2 * v + S) * N,       # read w, p; write u
     }
     return table.get(name)
 
@@ -126,12 +133,16 @@ def time_steps(fn, steps, warmup, solver=None):
     return a.elapsed_time(b) / steps, prof
 
 
-def run_mode(n, nu, dt, precision, steps, warmup, u0_np, adjoint, scheme="rk4", keep=False):
+def run_mode(n, nu, dt, precision, steps, warmup, u0_np, adjoint, scheme="rk4", keep=False, channel=None):
     import torch
 
     from paper_2604_18536_amd import Solver
 
-    s = Solver(n, nu=nu, precision=precision)
+    if channel is None:
+        s = Solver(n, nu=nu, precision=precision)
+    else:
+        s = Solver(n, nu=nu, precision=precision, lo=channel["lo"], hi=channel["hi"], bc="walls")
+        s.cg_set(rtol=channel["rtol"], maxiter=20000, check_every=channel["check"])
     u0 = torch.as_tensor(u0_np).to(device="cuda", dtype=s.dtype).contiguous()
     s.project(u0, out=u0)
     u1 = torch.empty_like(u0)
@@ -151,12 +162,69 @@ def run_mode(n, nu, dt, precision, steps, warmup, u0_np, adjoint, scheme="rk4", 
             s.step(u0, dt, out=u1, scheme=scheme)
     ms, _ = time_steps(fn, steps, warmup)
     ms_p, prof = time_steps(fn, steps, 1, solver=s)
+    if channel is not None:
+        channel["iterations_last_solve"] = s.cg_info()[0]
     ok = s.stats(u1)[3]
     ws = s.workspace_bytes()
     if adjoint and keep:  # the caller-owned stage buffers count as workspace too
         ws += sum(t.numel() * t.element_size() for t in kept)
     s.close()
     return ms, ms_p, prof, ok, ws
+
+
+CHANNEL = {"n": (256, 256, 256), "nu": 1.0 / 1000.0, "dt": 1e-3, "seed": 5, "rtol": 1e-8, "check": 16,
+           "modes": "fp64,fp64_adj_kept,fp32"}
+
+
+def channel_timing(steps, warmup, modes=None):
+    """Channel flow (no-slip walls at both y ends, x and z periodic) on a 256^3
+    grid over [0, 2pi] x [0, 2] x [0, pi]: laminar profile of bulk velocity 1
+    plus a 20% solenoidal perturbation, nu = 1/1000, dt = 1e-3; every pressure
+    solve is matrix-free CG stopped at a relative residual of 1e-8."""
+    import synth as S
+
+    cfg = dict(CHANNEL)
+    n = cfg["n"]
+    lo, hi = S.channel_box(n)
+    u0 = S.channel_ic(n, cfg["seed"])
+    ncell = n[0] * n[1] * n[2]
+    out = {"workload": f"channel {n[0]}x{n[1]}x{n[2]}, walls at y=0,2, nu=1/{round(1 / cfg['nu'])}, "
+                       f"dt={cfg['dt']}, CG rtol={cfg['rtol']:g}", "modes": {}, "kernels": {}}
+    for mode in (modes or cfg["modes"]).split(","):
+        precision = "fp64" if mode.startswith("fp64") else "fp32"
+        adjoint = "_adj" in mode
+        ch = {"lo": lo, "hi": hi, "rtol": cfg["rtol"], "check": cfg["check"]}
+        print(f"[bench] channel {mode} starts", file=sys.stderr, flush=True)
+        ms, ms_p, prof, ok, ws = run_mode(n, cfg["nu"], cfg["dt"], precision, steps, warmup, u0, adjoint, "rk4",
+                                          mode.endswith("_kept"), ch)
+        elem = 8 if precision == "fp64" else 4
+        alg = sum(kernel_bytes(k, n, elem) * c for k, (c, t) in prof.items() if kernel_bytes(k, n, elem))
+        applies = prof.get("cg_apply", (0, 0.0))[0] / steps
+        solves = prof.get("cg_init", (0, 0.0))[0] / steps
+        out["modes"][mode] = {
+            "mcell_per_s": round(ncell / (ms * 1e-3) / 1e6, 3),
+            "ms_per_step": round(ms, 2),
+            "cg_solves_per_step": solves,
+            "cg_iterations_per_solve": round(applies / solves, 1) if solves else None,
+            "cg_iterations_last_solve": ch["iterations_last_solve"],
+            "hbm_frac": round(alg / steps / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+            "finite": bool(ok),
+            "workspace_gb": round(ws / 1e9, 3),
+        }
+        out["kernels"][mode] = {
+            k: {"launches_per_step": c / steps, "avg_ms": round(t / c, 5),
+                "gbs": round(kernel_bytes(k, n, elem) / (t / c * 1e-3) / 1e9, 1) if kernel_bytes(k, n, elem) else None}
+            for k, (c, t) in prof.items()
+        }
+        print(f"[bench] channel {mode}: {out['modes'][mode]}", file=sys.stderr, flush=True)
+    kp = out["kernels"]["fp64"] if "fp64" in out["kernels"] else next(iter(out["kernels"].values()))
+    dom = max(kp, key=lambda k: kp[k]["avg_ms"] * kp[k]["launches_per_step"])
+    b = kernel_bytes(dom, n, 8)
+    achieved = b / (kp[dom]["avg_ms"] * 1e-3) / 1e9
+    out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": _traffic_record(dom),
+                       "alg_bytes_per_launch": b, "avg_ms": kp[dom]["avg_ms"]}
+    return out
 
 
 def stream_copy_gbs(nbytes=2 << 30, reps=10):
@@ -309,12 +377,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="turb256", choices=sorted(CONFIGS))
+    ap.add_argument("--config", default="turb256", choices=sorted(CONFIGS) + ["channel256"])
     ap.add_argument("--n", type=int, default=None, help="override the grid size of the config")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-les", action="store_true", help="skip the closure-LES and small-grid timings")
+    ap.add_argument("--no-channel", action="store_true", help="skip the channel (wall-bounded, CG) timing")
     ap.add_argument("--modes", default=None)
     args = ap.parse_args()
+    if args.config == "channel256":
+        return channel_main(args)
     cfg = dict(CONFIGS[args.config])
     if args.n is not None:
         cfg["n"] = args.n
@@ -401,6 +472,7 @@ def main():
     cpu = None if args.no_cpu else cpu_baseline(n, nu, dt, u0)
     les = None if args.no_les or args.config != "turb256" else les_closure_timing(args.steps, args.warmup)
     small = None if args.no_les or args.config != "turb256" else small_grid_timing(50)
+    channel = None if args.no_channel or args.config != "turb256" else channel_timing(2, 1)
     ms = modes[main_mode]["ms_per_step"]
     line = {
         "metric": METRIC,
@@ -426,9 +498,45 @@ def main():
         "stream_copy_gbs": round(copy_gbs, 1),
         "les_closure": les,
         "small_grids": small,
+        "channel": channel,
         "cpu_baseline": cpu,
         "modes": modes,
         "kernels": kernels,
+    }
+    print(json.dumps(line))
+
+
+def channel_main(args):
+    """Bench line of the channel workload alone (for its profiles)."""
+    import torch
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (--gpus {args.gpus} requested)", file=sys.stderr)
+        sys.exit(2)
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    ch = channel_timing(args.steps, args.warmup, args.modes)
+    main_mode = "fp64" if "fp64" in ch["modes"] else next(iter(ch["modes"]))
+    line = {
+        "metric": METRIC,
+        "value": ch["modes"][main_mode]["mcell_per_s"],
+        "unit": "Mcell/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ch["modes"][main_mode]["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if main_mode.startswith("fp64") else "f32",
+        "data": "synthetic",
+        "config": {"workload": ch["workload"] + f"; {main_mode} RK4 step"},
+        "roofline": ch["roofline"],
+        "cpu_baseline": None,
+        "modes": ch["modes"],
+        "kernels": ch["kernels"],
     }
     print(json.dumps(line))
 

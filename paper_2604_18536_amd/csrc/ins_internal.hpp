@@ -176,27 +176,35 @@ hipError_t launch_wall_stage_vjp(const Grid& g, const T* w, const double* p, boo
                                  const double* q, bool has_w, double cb, double cw, T* u0bar, int mode, T* ubar_out,
                                  hipStream_t s);
 
-// Scalars of one field's conjugate-gradient solve, kept in device memory.
+// Scalars of one field's conjugate-gradient solve that the host reads: rr_0,
+// the final rr and relres = sqrt(rr / rr_0), iterations done, stop flag (set
+// by each iteration's first kernel), mean of the right-hand side.
 struct CgScal {
-    double rr, rr0, pq, alpha, beta, mean, relres;
+    double rr, rr0, relres, mean;
     int it, done;
 };
-// Reductions use `partials` (stencil_blocks(g) doubles) and `counter` (0
-// between launches; each kernel's last workgroup resets it).
-// r = D vel (vel != null) or rin; st.mean = mean of r per field.
+// Work split of the CG kernels: workgroups per field (<= kCgMaxBlocks); every
+// partial-sum buffer holds cg_blocks(g) * batch doubles.
+constexpr int kCgMaxBlocks = 2048;
+int cg_blocks(const Grid& g);
+// r = D vel (vel != null) or rin; partial sums of r into msum.
 template <typename T>
-hipError_t launch_cg_div(const Grid& g, const T* vel, const double* rin, double* r, double* partials,
-                         unsigned int* counter, CgScal* st, hipStream_t s);
-// r = mean - r, x = 0, p0 = 0, st.rr = st.rr0 = r.r, flags cleared.
-hipError_t launch_cg_init(const Grid& g, double* r, double* x, double* p0, double* partials, unsigned int* counter,
-                          CgScal* st, int maxiter, hipStream_t s);
-// pout = r + beta pin, q = -D G pout, st.alpha = rr / pout.q.
-hipError_t launch_cg_apply(const Grid& g, const double* r, const double* pin, double* pout, double* q, double* partials,
-                           unsigned int* counter, CgScal* st, hipStream_t s);
-// x += alpha p, r -= alpha q, st.beta / rr / it / relres, st.done once rr <= rtol2 rr0 or it == maxiter.
-hipError_t launch_cg_update(const Grid& g, double* x, const double* p, double* r, const double* q, double* partials,
-                            unsigned int* counter, CgScal* st, double rtol2, int maxiter, hipStream_t s);
-int stencil_block_count(const Grid& g);
+hipError_t launch_cg_div(const Grid& g, const T* vel, const double* rin, double* r, double* msum, hipStream_t s);
+// r = mean - r, x = 0, partial sums of r.r into rb0; resets st.it / st.done.
+hipError_t launch_cg_init(const Grid& g, double* r, double* x, const double* msum, double* rb0, CgScal* st,
+                          hipStream_t s);
+// Iteration k: stop test from rr_k (partials rbk); pout = r + beta pin (beta =
+// rr_k / rr_{k-1}, partials rbm), q = -D G pout, partial sums of pout.q into pqs.
+hipError_t launch_cg_apply(const Grid& g, const double* r, const double* pin, double* pout, double* q,
+                           const double* rbk, const double* rbm, double* pqs, CgScal* st, int k, double rtol2,
+                           int maxiter, hipStream_t s);
+// Iteration k: x += alpha p, r -= alpha q (alpha = rr_k / p.q), partial sums of r.r into rbn.
+hipError_t launch_cg_update(const Grid& g, double* x, const double* p, double* r, const double* q, const double* rbk,
+                            const double* pqs, double* rbn, CgScal* st, int k, double rtol2, int maxiter,
+                            hipStream_t s);
+// st.rr / st.relres from the newest rr partials.
+hipError_t launch_cg_finish(const Grid& g, const double* rb, CgScal* st, hipStream_t s);
+
 
 // Utilities.
 template <typename T>

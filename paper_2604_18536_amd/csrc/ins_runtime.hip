@@ -154,8 +154,7 @@ struct ins_ctx_s {
     double* cg_r = nullptr;
     double* cg_p[2] = {nullptr, nullptr};
     double* cg_q = nullptr;
-    double* cg_part = nullptr;
-    unsigned int* cg_cnt = nullptr;
+    double* cg_part = nullptr;  // partial sums: mean, rr (two generations), p.q; cg_blocks * batch each
     ins::CgScal* cg_st = nullptr;
     ins::CgScal* cg_host = nullptr;  // pinned host copy of cg_st
 
@@ -341,38 +340,42 @@ bool cg_all_done(ins_ctx c) {
 // gradients on -D G (Sec. 2.5.1, iterative solver) from x = 0; the mean of
 // the right-hand side is removed first (the zero-mean solution of the
 // consistent part). Iterations are launched back to back; every cg_check
-// iterations the host reads the convergence flags once.
+// iterations the host reads the stop flags once and stops launching when
+// every field is done.
 void cg_solve(ins_ctx c, const void* vel, const double* r, double* x) {
     const ins::Grid& g = c->g;
+    const size_t np = size_t(ins::cg_blocks(g)) * g.batch;
+    double* msum = c->cg_part;
+    double* rb[2] = {c->cg_part + np, c->cg_part + 2 * np};
+    double* pqs = c->cg_part + 3 * np;
     if (vel) {
         with_type(c, [&](auto tag) {
             using T = decltype(tag);
             c->launch("cg_div", [&] {
-                return ins::launch_cg_div<T>(g, static_cast<const T*>(vel), nullptr, c->cg_r, c->cg_part, c->cg_cnt,
-                                             c->cg_st, c->stream);
+                return ins::launch_cg_div<T>(g, static_cast<const T*>(vel), nullptr, c->cg_r, msum, c->stream);
             });
         });
     } else {
-        c->launch("cg_copy", [&] {
-            return ins::launch_cg_div<double>(g, nullptr, r, c->cg_r, c->cg_part, c->cg_cnt, c->cg_st, c->stream);
-        });
+        c->launch("cg_copy", [&] { return ins::launch_cg_div<double>(g, nullptr, r, c->cg_r, msum, c->stream); });
     }
-    c->launch("cg_init", [&] {
-        return ins::launch_cg_init(g, c->cg_r, x, c->cg_p[0], c->cg_part, c->cg_cnt, c->cg_st, c->cg_maxiter, c->stream);
-    });
+    c->launch("cg_init", [&] { return ins::launch_cg_init(g, c->cg_r, x, msum, rb[0], c->cg_st, c->stream); });
     const double rtol2 = c->cg_rtol * c->cg_rtol;
-    for (int k = 0; k < c->cg_maxiter; ++k) {
+    int k = 0;
+    while (k < c->cg_maxiter) {
         double* pin = c->cg_p[k & 1];
         double* pout = c->cg_p[(k + 1) & 1];
         c->launch("cg_apply", [&] {
-            return ins::launch_cg_apply(g, c->cg_r, pin, pout, c->cg_q, c->cg_part, c->cg_cnt, c->cg_st, c->stream);
+            return ins::launch_cg_apply(g, c->cg_r, pin, pout, c->cg_q, rb[k & 1], rb[(k + 1) & 1], pqs, c->cg_st, k,
+                                        rtol2, c->cg_maxiter, c->stream);
         });
         c->launch("cg_update", [&] {
-            return ins::launch_cg_update(g, x, pout, c->cg_r, c->cg_q, c->cg_part, c->cg_cnt, c->cg_st, rtol2,
-                                         c->cg_maxiter, c->stream);
+            return ins::launch_cg_update(g, x, pout, c->cg_r, c->cg_q, rb[k & 1], pqs, rb[(k + 1) & 1], c->cg_st, k,
+                                         rtol2, c->cg_maxiter, c->stream);
         });
-        if (c->cg_check > 0 && (k + 1) % c->cg_check == 0 && k + 1 < c->cg_maxiter && cg_all_done(c)) break;
+        ++k;
+        if (c->cg_check > 0 && k % c->cg_check == 0 && k < c->cg_maxiter && cg_all_done(c)) break;
     }
+    c->launch("cg_finish", [&] { return ins::launch_cg_finish(g, rb[k & 1], c->cg_st, c->stream); });
 }
 
 // p = (D G)^-1 of the divergence of vel (vel != null) or of r.
@@ -792,10 +795,8 @@ ins_status ins_create(const ins_grid* grid, ins_bc bc, double nu, ins_dtype dtyp
             c->cg_p[0] = static_cast<double*>(c->alloc(sb));
             c->cg_p[1] = static_cast<double*>(c->alloc(sb));
             c->cg_q = static_cast<double*>(c->alloc(sb));
-            c->cg_part = static_cast<double*>(c->alloc(size_t(ins::stencil_block_count(g)) * sizeof(double)));
-            c->cg_cnt = static_cast<unsigned int*>(c->alloc(256));
+            c->cg_part = static_cast<double*>(c->alloc(4 * size_t(ins::cg_blocks(g)) * g.batch * sizeof(double)));
             c->cg_st = static_cast<ins::CgScal*>(c->alloc(size_t(g.batch) * sizeof(ins::CgScal)));
-            hip_check(hipMemset(c->cg_cnt, 0, 256), "hipMemset");
             hip_check(hipMemset(c->cg_st, 0, size_t(g.batch) * sizeof(ins::CgScal)), "hipMemset");
             hip_check(hipHostMalloc(reinterpret_cast<void**>(&c->cg_host), size_t(g.batch) * sizeof(ins::CgScal)),
                       "hipHostMalloc");

@@ -18,13 +18,12 @@
 // CG (fp64 throughout): A = -D G on each field of the batch, b = mean(r) - r,
 // x_0 = 0. One iteration is two fused kernels:
 //   k_cg_apply:  p = r + beta p_old (formed at the stencil points), q = A p,
-//                partial sums of p.q        -> alpha = rr / p.q
-//   k_cg_update: x += alpha p, r -= alpha q, partial sums of r.r
-//                                           -> beta, rr, convergence flag
-// Each reduction is finished by the workgroup that completes last (fixed
-// summation order, so results are bitwise reproducible); the scalars live in
-// device memory, so iterations run back to back without the host. A field
-// whose flag is set skips the work of later iterations.
+//                partial sums of p.q
+//   k_cg_update: alpha = rr / p.q; x += alpha p, r -= alpha q, partial sums of r.r
+// Every scalar (rr, beta, alpha, the stop test) is recomputed from partial
+// sums in every workgroup, so iterations run back to back without the host
+// and results are bitwise reproducible. A stopped field skips the work of
+// later iterations.
 #include "k_common.hpp"
 
 namespace ins {
@@ -317,6 +316,14 @@ __global__ __launch_bounds__(kBlock) void k_wall_grad_vjp(Grid g, const T* __res
 
 // ----------------------------------------------------------------------------
 // Conjugate gradients
+//
+// Work split: the tiles of each field (64 x 4 cells, ordered as in tile_of)
+// are dealt in contiguous runs to cg_blocks(g) workgroups per field; the
+// workgroup with logical id b * nblk + blk serves field b. Every partial sum
+// goes to a buffer of nblk doubles per field; a kernel that needs the total
+// reduces that field's nblk partials in every workgroup, in one fixed order,
+// so all workgroups agree bitwise. No atomics, fences or inter-workgroup
+// waits: each kernel only reads sums its predecessors finished writing.
 // ----------------------------------------------------------------------------
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -325,189 +332,419 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// Sum over the workgroup, returned to every thread (fixed order).
+// Sum over a workgroup of NT threads, returned to every thread (fixed order).
+template <int NT = kBlock>
 __device__ __forceinline__ double block_sum(double v, double* sh) {
     v = wave_sum(v);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
     __syncthreads();
     double s = 0.0;
 #pragma unroll
-    for (int i = 0; i < kBlock / 64; ++i) s += sh[i];
+    for (int i = 0; i < NT / 64; ++i) s += sh[i];
     __syncthreads();
     return s;
 }
 
-// Stores this workgroup's partial sum; true in every thread of the workgroup
-// that arrives last, after which all partials are visible to it.
-__device__ __forceinline__ bool publish(double part, double* partials, int slot, unsigned int* counter, int nblocks) {
-    __shared__ int last;
-    if (threadIdx.x == 0) {
-        partials[slot] = part;
-        __threadfence();
-        last = atomicAdd(counter, 1u) == unsigned(nblocks - 1) ? 1 : 0;
-    }
-    __syncthreads();
-    const bool am = last != 0;
-    if (am) __threadfence();
-    return am;
-}
-
-// Sum of the partials of batch entry b (blocks b*per .. (b+1)*per - 1), every thread.
-__device__ __forceinline__ double batch_total(const double* partials, int b, int per, double* sh) {
-    double s = 0.0;
-    for (int i = threadIdx.x; i < per; i += kBlock) s += partials[int64_t(b) * per + i];
-    return block_sum(s, sh);
-}
-
-__device__ __forceinline__ int logical_block() { return xcd_logical(blockIdx.x, gridDim.x); }
-
-__device__ __forceinline__ int blocks_per_field(const Grid& g) {
+__host__ __device__ inline int cg_tiles_of(const Grid& g) {
     return ((g.nx + kTileX - 1) / kTileX) * ((g.ny + kTileY - 1) / kTileY) * g.nz;
 }
 
-// r = D vel (vel != null, wall rules) or a copy of rin; mean of r per field.
+// 3D apply kernel: 64 x kCgTy tile columns, each split into z-chunks.
+constexpr int kCgTy = 8;
+constexpr int kCgThreads3 = kTileX * kCgTy;
+
+__host__ __device__ inline int cg_cols3(const Grid& g) {
+    return ((g.nx + kTileX - 1) / kTileX) * ((g.ny + kCgTy - 1) / kCgTy);
+}
+
+__host__ __device__ inline int cg_zchunks(const Grid& g) {
+    int n = kCgMaxBlocks / cg_cols3(g);
+    if (n < 1) n = 1;
+    return n < g.nz ? n : g.nz;
+}
+
+// Workgroups per field, the same for every CG kernel (their partial sums are
+// reduced by the next kernel): tile columns x z-chunks in 3D, tiles (at most
+// kCgMaxBlocks) in 2D. Never more than the 64 x 4 tiles of a field.
+__host__ __device__ inline int cg_blocks_of(const Grid& g) {
+    if (g.dim == 3) return cg_cols3(g) * cg_zchunks(g);
+    const int t = cg_tiles_of(g);
+    return t < kCgMaxBlocks ? t : kCgMaxBlocks;
+}
+
+struct CgSplit {
+    int b, blk, nblk;  // field, workgroup within the field, workgroups per field
+    int t0, t1;        // tiles [t0, t1) of the field
+    __device__ int64_t slot() const { return int64_t(b) * nblk + blk; }
+};
+
+__device__ __forceinline__ CgSplit cg_split(const Grid& g) {
+    const int tiles = cg_tiles_of(g);
+    CgSplit c;
+    c.nblk = cg_blocks_of(g);
+    const int id = xcd_logical(blockIdx.x, gridDim.x);
+    c.b = id / c.nblk;
+    c.blk = id - c.b * c.nblk;
+    c.t0 = int(int64_t(tiles) * c.blk / c.nblk);
+    c.t1 = int(int64_t(tiles) * (c.blk + 1) / c.nblk);
+    return c;
+}
+
+// This thread's cell of tile t; false outside the grid. Tiles are numbered
+// with z fastest, so a workgroup's run of tiles walks a tile column along z.
+__device__ __forceinline__ bool cg_cell(const Grid& g, int t, int& x, int& y, int& z) {
+    const int ntx = (g.nx + kTileX - 1) / kTileX;
+    z = t % g.nz;
+    t /= g.nz;
+    const int tx = t % ntx;
+    const int ty = t / ntx;
+    x = tx * kTileX + (threadIdx.x & (kTileX - 1));
+    y = ty * kTileY + (threadIdx.x / kTileX);
+    return x < g.nx && y < g.ny;
+}
+
+__device__ __forceinline__ int64_t cg_index(const Grid& g, int b, int x, int y, int z) {
+    return int64_t(b) * g.ncell + (int64_t(z) * g.ny + y) * g.nx + x;
+}
+
+// Total of field b's partials, in every thread of an NT-thread workgroup.
+template <int NT = kBlock>
+__device__ __forceinline__ double field_total(const double* part, const CgSplit& c, double* sh) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < c.nblk; i += NT) s += part[int64_t(c.b) * c.nblk + i];
+    return block_sum<NT>(s, sh);
+}
+
+// Stop test of iteration k (the oracle's loop condition, negated).
+__device__ __forceinline__ bool cg_stopped(double rrk, double rr0, int k, double rtol2, int maxiter) {
+    return !(rr0 > 0.0) || rrk <= rtol2 * rr0 || k >= maxiter;
+}
+
+// r = D vel (vel != null, wall rules) or a copy of rin; partial sums of r.
 template <typename T, int DIM>
 __global__ __launch_bounds__(kBlock) void k_cg_div(Grid g, const T* __restrict__ vel, const double* __restrict__ rin,
-                                                    double* __restrict__ r, double* partials, unsigned int* counter,
-                                                    CgScal* st) {
+                                                    double* __restrict__ r, double* __restrict__ msum) {
     __shared__ double sh[kBlock / 64];
-    const TileIdx t = tile_of(g);
-    double v = 0.0;
-    if (t.valid) {
-        const Nb nb = make_nb<DIM>(g, t.x, t.y, t.z);
-        const int64_t k = int64_t(t.b) * g.ncell + nb.at(0, 0, 0);
-        v = vel ? wall_div_cell<T, DIM>(g, vel + int64_t(t.b) * DIM * g.ncell, nb, t.y) : rin[k];
+    const CgSplit c = cg_split(g);
+    double acc = 0.0;
+    for (int t = c.t0; t < c.t1; ++t) {
+        int x, y, z;
+        if (!cg_cell(g, t, x, y, z)) continue;
+        const Nb nb = make_nb<DIM>(g, x, y, z);
+        const int64_t k = cg_index(g, c.b, x, y, z);
+        const double v = vel ? wall_div_cell<T, DIM>(g, vel + int64_t(c.b) * DIM * g.ncell, nb, y) : rin[k];
         r[k] = v;
+        acc += v;
     }
-    const double part = block_sum(v, sh);
-    if (!publish(part, partials, logical_block(), counter, gridDim.x)) return;
-    const int per = blocks_per_field(g);
-    for (int b = 0; b < g.batch; ++b) {
-        const double s = batch_total(partials, b, per, sh);
-        if (threadIdx.x == 0) st[b].mean = s / double(g.ncell);
-    }
-    if (threadIdx.x == 0) *counter = 0u;
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) msum[c.slot()] = s;
 }
 
-// r = mean - r (the right-hand side of A x = b), x = 0, p_old = 0; rr0 = r.r.
-template <int DIM>
+// r = mean(r) - r, x = 0; partial sums of r.r (rr_0).
 __global__ __launch_bounds__(kBlock) void k_cg_init(Grid g, double* __restrict__ r, double* __restrict__ x,
-                                                     double* __restrict__ p0, double* partials, unsigned int* counter,
-                                                     CgScal* st, int maxiter) {
+                                                     const double* __restrict__ msum, double* __restrict__ rb0,
+                                                     CgScal* st) {
     __shared__ double sh[kBlock / 64];
-    const TileIdx t = tile_of(g);
-    double v2 = 0.0;
-    if (t.valid) {
-        const int64_t k = int64_t(t.b) * g.ncell + int64_t(t.z) * g.nx * g.ny + int64_t(t.y) * g.nx + t.x;
-        const double v = st[t.b].mean - r[k];
+    const CgSplit c = cg_split(g);
+    const double mean = field_total(msum, c, sh) / double(g.ncell);
+    double acc = 0.0;
+    for (int t = c.t0; t < c.t1; ++t) {
+        int cx, cy, cz;
+        if (!cg_cell(g, t, cx, cy, cz)) continue;
+        const int64_t k = cg_index(g, c.b, cx, cy, cz);
+        const double v = mean - r[k];
         r[k] = v;
         x[k] = 0.0;
-        p0[k] = 0.0;
-        v2 = v * v;
+        acc += v * v;
     }
-    const double part = block_sum(v2, sh);
-    if (!publish(part, partials, logical_block(), counter, gridDim.x)) return;
-    const int per = blocks_per_field(g);
-    for (int b = 0; b < g.batch; ++b) {
-        const double s = batch_total(partials, b, per, sh);
-        if (threadIdx.x == 0) {
-            st[b].rr = s;
-            st[b].rr0 = s;
-            st[b].beta = 0.0;
-            st[b].it = 0;
-            st[b].relres = s > 0.0 ? 1.0 : 0.0;
-            st[b].done = (s > 0.0 && maxiter > 0) ? 0 : 1;
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) {
+        rb0[c.slot()] = s;
+        if (c.blk == 0) {
+            st[c.b].mean = mean;
+            st[c.b].it = 0;
+            st[c.b].done = 0;
         }
     }
-    if (threadIdx.x == 0) *counter = 0u;
 }
 
-// p = r + beta p_old, q = A p = -D G p, partial p.q; alpha = rr / p.q.
-template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_cg_apply(Grid g, const double* __restrict__ r, const double* __restrict__ pin,
-                                                      double* __restrict__ pout, double* __restrict__ q, double* partials,
-                                                      unsigned int* counter, CgScal* st) {
-    __shared__ double sh[kBlock / 64];
-    const TileIdx t = tile_of(g);
-    double pq = 0.0;
-    if (t.valid && !st[t.b].done) {
-        const double beta = st[t.b].beta;
-        const Nb nb = make_nb<DIM>(g, t.x, t.y, t.z);
-        const int64_t soff = int64_t(t.b) * g.ncell;
-        const double* rb = r + soff;
-        const double* pb = pin + soff;
-        const int c0 = nb.at(0, 0, 0);
-        const double pc = rb[c0] + beta * pb[c0];
-        double ap = 0.0;
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            const bool up = a != 1 || t.y < g.ny - 1;
-            const bool dn = a != 1 || t.y > 0;
-            double s = 0.0;
-            if (up) {
-                const int j = nb.at(a == 0, a == 1, a == 2);
-                s += pc - (rb[j] + beta * pb[j]);
-            }
-            if (dn) {
-                const int j = nb.at(-(a == 0), -(a == 1), -(a == 2));
-                s += pc - (rb[j] + beta * pb[j]);
-            }
-            ap += s * g.ih2[a];
-        }
-        pout[soff + c0] = pc;
-        q[soff + c0] = ap;
-        pq = pc * ap;
+// Search direction p = r + beta p_old at a cell (p = r when FIRST).
+template <bool FIRST>
+__device__ __forceinline__ double cg_dir(const double* rb, const double* pb, int64_t j, double beta) {
+    if constexpr (FIRST) {
+        return rb[j];
+    } else {
+        return rb[j] + beta * pb[j];
     }
-    const double part = block_sum(pq, sh);
-    if (!publish(part, partials, logical_block(), counter, gridDim.x)) return;
-    const int per = blocks_per_field(g);
-    for (int b = 0; b < g.batch; ++b) {
-        const double s = batch_total(partials, b, per, sh);
-        if (threadIdx.x == 0 && !st[b].done) {
-            st[b].pq = s;
-            if (s > 0.0) {
-                st[b].alpha = st[b].rr / s;
+}
+
+// q = A p at one cell from p at the cell (pc), at z -/+ 1 (pm, pp; unused in
+// 2D) and at the x/y neighbours read from r, p_old. Wall rule: no y-face
+// beyond the first/last row.
+template <bool FIRST, int DIM>
+__device__ __forceinline__ double cg_ap(const Grid& g, const double* rb, const double* pb, double beta, int64_t c0,
+                                        int x, int y, double pc, double pm, double pp) {
+    const int xm = x == 0 ? g.nx - 1 : x - 1;
+    const int xp = x == g.nx - 1 ? 0 : x + 1;
+    const int64_t row = c0 - x;
+    double ap = (2.0 * pc - cg_dir<FIRST>(rb, pb, row + xm, beta) - cg_dir<FIRST>(rb, pb, row + xp, beta)) * g.ih2[0];
+    double sy = 0.0;
+    if (y > 0) sy += pc - cg_dir<FIRST>(rb, pb, c0 - g.nx, beta);
+    if (y < g.ny - 1) sy += pc - cg_dir<FIRST>(rb, pb, c0 + g.nx, beta);
+    ap += sy * g.ih2[1];
+    if constexpr (DIM == 3) ap += (2.0 * pc - pm - pp) * g.ih2[2];
+    return ap;
+}
+
+// Iteration k. rr_k from rbk, rr_{k-1} from rbm (k > 0). Unless stopped:
+// p = r + beta p_old with beta = rr_k / rr_{k-1} (p = r at k = 0), formed at
+// every stencil point; q = A p = -D G p; partial sums of p.q. Workgroup 0 of
+// each field publishes the stop flag (and rr_0 at k = 0). In 3D each thread
+// walks its (x, y) along z keeping p at z - 1, z, z + 1 in registers.
+template <bool FIRST, int DIM>
+__device__ __forceinline__ double cg_apply_run(const Grid& g, const CgSplit& c, const double* rb, const double* pb,
+                                               double* pout, double* q, double beta) {
+    double acc = 0.0;
+    const int64_t plane = int64_t(g.nx) * g.ny;
+    double pm = 0.0, pc = 0.0, pp = 0.0;
+    bool fresh = true;
+    for (int t = c.t0; t < c.t1; ++t) {
+        int x, y, z;
+        const bool in = cg_cell(g, t, x, y, z);
+        if (!in) continue;
+        const int64_t c0 = (int64_t(z) * g.ny + y) * g.nx + x;
+        if constexpr (DIM == 3) {
+            if (fresh || z == 0) {
+                const int zm = z == 0 ? g.nz - 1 : z - 1;
+                pm = cg_dir<FIRST>(rb, pb, c0 + (zm - z) * plane, beta);
+                pc = cg_dir<FIRST>(rb, pb, c0, beta);
             } else {
-                st[b].alpha = 0.0;
-                st[b].done = 1;
+                pm = pc;
+                pc = pp;
             }
+            const int zp = z == g.nz - 1 ? 0 : z + 1;
+            pp = cg_dir<FIRST>(rb, pb, c0 + (zp - z) * plane, beta);
+            fresh = false;
+        } else {
+            pc = cg_dir<FIRST>(rb, pb, c0, beta);
         }
+        const double ap = cg_ap<FIRST, DIM>(g, rb, pb, beta, c0, x, y, pc, pm, pp);
+        pout[c0] = pc;
+        q[c0] = ap;
+        acc += pc * ap;
     }
-    if (threadIdx.x == 0) *counter = 0u;
+    return acc;
 }
 
-// x += alpha p, r -= alpha q, partial r.r; beta, rr, iteration count, flag.
+// 2D: each workgroup takes a run of 64 x 4 tiles.
+__global__ __launch_bounds__(kBlock) void k_cg_apply2(Grid g, const double* __restrict__ r,
+                                                       const double* __restrict__ pin, double* __restrict__ pout,
+                                                       double* __restrict__ q, const double* __restrict__ rbk,
+                                                       const double* __restrict__ rbm, double* __restrict__ pqs,
+                                                       CgScal* st, int k, double rtol2, int maxiter) {
+    __shared__ double sh[kBlock / 64];
+    const CgSplit c = cg_split(g);
+    const double rrk = field_total(rbk, c, sh);
+    const double rr0 = k == 0 ? rrk : st[c.b].rr0;
+    const bool stop = cg_stopped(rrk, rr0, k, rtol2, maxiter);
+    if (c.blk == 0 && threadIdx.x == 0) {
+        if (k == 0) st[c.b].rr0 = rrk;
+        st[c.b].done = stop ? 1 : 0;
+    }
+    if (stop) return;
+    const int64_t soff = int64_t(c.b) * g.ncell;
+    double acc;
+    if (k == 0) {
+        acc = cg_apply_run<true, 2>(g, c, r + soff, pin + soff, pout + soff, q + soff, 0.0);
+    } else {
+        const double beta = rrk / field_total(rbm, c, sh);
+        acc = cg_apply_run<false, 2>(g, c, r + soff, pin + soff, pout + soff, q + soff, beta);
+    }
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) pqs[c.slot()] = s;
+}
+
+// 3D: a workgroup of 64 x 8 threads walks one tile column through its
+// z-chunk. p at z - 1, z, z + 1 stays in registers; the x/y neighbours come
+// from a two-plane LDS ring holding each plane of the tile with a one-cell
+// x/y halo (filled by the first 144 threads). Lanes past n_x load the
+// periodic image so the last column's +x neighbour is in place; rows past
+// n_y and halo rows beyond a wall are never read (no y-face there).
+template <bool FIRST>
+__device__ __forceinline__ double cg_apply3_run(const Grid& g, const CgSplit& c, const double* __restrict__ r,
+                                                const double* __restrict__ pin, double* __restrict__ pout,
+                                                double* __restrict__ q, double beta,
+                                                double (*pl)[kCgTy + 2][kTileX + 2]) {
+    const int cols = cg_cols3(g);
+    const int ntx = (g.nx + kTileX - 1) / kTileX;
+    const int nzc = cg_zchunks(g);
+    const int col = c.blk % cols, zc = c.blk / cols;
+    const int z0 = int(int64_t(g.nz) * zc / nzc), z1 = int(int64_t(g.nz) * (zc + 1) / nzc);
+    const int x0 = (col % ntx) * kTileX, y0 = (col / ntx) * kCgTy;
+    const int lx = threadIdx.x & (kTileX - 1), ly = threadIdx.x / kTileX;
+    const int xw = (x0 + lx) % g.nx;
+    const int y = y0 + ly;
+    const bool yin = y < g.ny;
+    const bool valid = yin && x0 + lx < g.nx;
+    const int64_t plane = int64_t(g.nx) * g.ny;
+    // halo cell of this thread (threads < 144)
+    int hx = 0, hy = 0, hrow = 0, hcol = 0;
+    bool hal = false;
+    const bool hthr = threadIdx.x < 2 * kCgTy + 2 * kTileX;
+    if (threadIdx.x < 2 * kCgTy) {
+        const int row = threadIdx.x >> 1, side = threadIdx.x & 1;
+        hy = y0 + row;
+        hrow = row + 1;
+        hcol = side ? kTileX + 1 : 0;
+        hx = side ? (x0 + kTileX) % g.nx : (x0 + g.nx - 1) % g.nx;
+        hal = hy < g.ny;
+    } else if (hthr) {
+        const int i = threadIdx.x - 2 * kCgTy;
+        const int side = i / kTileX, cx = i % kTileX;
+        hy = side ? y0 + kCgTy : y0 - 1;
+        hrow = side ? kCgTy + 1 : 0;
+        hcol = cx + 1;
+        hx = (x0 + cx) % g.nx;
+        hal = hy >= 0 && hy < g.ny;
+    }
+    const int64_t own = int64_t(y) * g.nx + xw;
+    const int64_t hal_off = int64_t(hy) * g.nx + hx;
+    const int zm0 = z0 == 0 ? g.nz - 1 : z0 - 1;
+    double pm = yin ? cg_dir<FIRST>(r, pin, int64_t(zm0) * plane + own, beta) : 0.0;
+    double pc = yin ? cg_dir<FIRST>(r, pin, int64_t(z0) * plane + own, beta) : 0.0;
+    pl[0][ly + 1][lx + 1] = pc;
+    if (hthr) pl[0][hrow][hcol] = hal ? cg_dir<FIRST>(r, pin, int64_t(z0) * plane + hal_off, beta) : 0.0;
+    __syncthreads();
+    int cur = 0;
+    double acc = 0.0;
+    for (int z = z0; z < z1; ++z) {
+        const int zp = z == g.nz - 1 ? 0 : z + 1;
+        const double pp = yin ? cg_dir<FIRST>(r, pin, int64_t(zp) * plane + own, beta) : 0.0;
+        const double hv = (hthr && hal) ? cg_dir<FIRST>(r, pin, int64_t(zp) * plane + hal_off, beta) : 0.0;
+        if (valid) {
+            double ap = (2.0 * pc - pl[cur][ly + 1][lx] - pl[cur][ly + 1][lx + 2]) * g.ih2[0];
+            double sy = 0.0;
+            if (y > 0) sy += pc - pl[cur][ly][lx + 1];
+            if (y < g.ny - 1) sy += pc - pl[cur][ly + 2][lx + 1];
+            ap += sy * g.ih2[1] + (2.0 * pc - pm - pp) * g.ih2[2];
+            const int64_t c0 = int64_t(z) * plane + int64_t(y) * g.nx + x0 + lx;
+            pout[c0] = pc;
+            q[c0] = ap;
+            acc += pc * ap;
+        }
+        const int nxt = cur ^ 1;
+        pl[nxt][ly + 1][lx + 1] = pp;
+        if (hthr) pl[nxt][hrow][hcol] = hv;
+        __syncthreads();
+        cur = nxt;
+        pm = pc;
+        pc = pp;
+    }
+    return acc;
+}
+
+__global__ __launch_bounds__(kCgThreads3) void k_cg_apply3(Grid g, const double* __restrict__ r,
+                                                            const double* __restrict__ pin, double* __restrict__ pout,
+                                                            double* __restrict__ q, const double* __restrict__ rbk,
+                                                            const double* __restrict__ rbm, double* __restrict__ pqs,
+                                                            CgScal* st, int k, double rtol2, int maxiter) {
+    __shared__ double sh[kCgThreads3 / 64];
+    __shared__ double pl[2][kCgTy + 2][kTileX + 2];
+    CgSplit c;
+    c.nblk = cg_blocks_of(g);
+    const int id = xcd_logical(blockIdx.x, gridDim.x);
+    c.b = id / c.nblk;
+    c.blk = id - c.b * c.nblk;
+    c.t0 = c.t1 = 0;
+    const double rrk = field_total<kCgThreads3>(rbk, c, sh);
+    const double rr0 = k == 0 ? rrk : st[c.b].rr0;
+    const bool stop = cg_stopped(rrk, rr0, k, rtol2, maxiter);
+    if (c.blk == 0 && threadIdx.x == 0) {
+        if (k == 0) st[c.b].rr0 = rrk;
+        st[c.b].done = stop ? 1 : 0;
+    }
+    if (stop) return;
+    const int64_t soff = int64_t(c.b) * g.ncell;
+    double acc;
+    if (k == 0) {
+        acc = cg_apply3_run<true>(g, c, r + soff, pin + soff, pout + soff, q + soff, 0.0, pl);
+    } else {
+        const double beta = rrk / field_total<kCgThreads3>(rbm, c, sh);
+        acc = cg_apply3_run<false>(g, c, r + soff, pin + soff, pout + soff, q + soff, beta, pl);
+    }
+    const double s = block_sum<kCgThreads3>(acc, sh);
+    if (threadIdx.x == 0) pqs[c.slot()] = s;
+}
+
+// Iteration k, unless stopped: alpha = rr_k / p.q, x += alpha p, r -= alpha q,
+// partial sums of r.r (rr_{k+1}) into rbn; a stopped field copies its rr_k
+// partials forward instead, so the newest buffer always holds the final sum.
+// Pointwise: the workgroups of a field sweep it together (grid stride), two
+// cells per thread and access when the field size is even.
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_cg_update(Grid g, double* __restrict__ x, const double* __restrict__ p,
                                                        double* __restrict__ r, const double* __restrict__ q,
-                                                       double* partials, unsigned int* counter, CgScal* st, double rtol2,
+                                                       const double* __restrict__ rbk, const double* __restrict__ pqs,
+                                                       double* __restrict__ rbn, CgScal* st, int k, double rtol2,
                                                        int maxiter) {
     __shared__ double sh[kBlock / 64];
-    const TileIdx t = tile_of(g);
-    double rr = 0.0;
-    if (t.valid && !st[t.b].done) {
-        const double alpha = st[t.b].alpha;
-        const int64_t k = int64_t(t.b) * g.ncell + int64_t(t.z) * g.nx * g.ny + int64_t(t.y) * g.nx + t.x;
-        x[k] += alpha * p[k];
-        const double v = r[k] - alpha * q[k];
-        r[k] = v;
-        rr = v * v;
+    const CgSplit c = cg_split(g);
+    const double rrk = field_total(rbk, c, sh);
+    if (cg_stopped(rrk, st[c.b].rr0, k, rtol2, maxiter)) {
+        if (threadIdx.x == 0) rbn[c.slot()] = rbk[c.slot()];
+        return;
     }
-    const double part = block_sum(rr, sh);
-    if (!publish(part, partials, logical_block(), counter, gridDim.x)) return;
-    const int per = blocks_per_field(g);
-    for (int b = 0; b < g.batch; ++b) {
-        const double s = batch_total(partials, b, per, sh);
-        if (threadIdx.x == 0 && !st[b].done) {
-            const int it = st[b].it + 1;
-            st[b].it = it;
-            st[b].beta = s / st[b].rr;
-            st[b].rr = s;
-            st[b].relres = sqrt(s / st[b].rr0);
-            if (s <= rtol2 * st[b].rr0 || it >= maxiter) st[b].done = 1;
+    const double pq = field_total(pqs, c, sh);
+    const double alpha = pq > 0.0 ? rrk / pq : 0.0;
+    const int64_t base = int64_t(c.b) * g.ncell;
+    double acc = 0.0;
+    if ((g.ncell & 1) == 0) {
+        const int64_t npair = g.ncell / 2;
+        double2* x2 = reinterpret_cast<double2*>(x + base);
+        const double2* p2 = reinterpret_cast<const double2*>(p + base);
+        double2* r2 = reinterpret_cast<double2*>(r + base);
+        const double2* q2 = reinterpret_cast<const double2*>(q + base);
+        const int64_t stride = int64_t(c.nblk) * kBlock;
+        for (int64_t i = int64_t(c.blk) * kBlock + threadIdx.x; i < npair; i += stride) {
+            const double2 pv = p2[i], qv = q2[i];
+            double2 xv = x2[i], rv = r2[i];
+            xv.x += alpha * pv.x;
+            xv.y += alpha * pv.y;
+            rv.x -= alpha * qv.x;
+            rv.y -= alpha * qv.y;
+            x2[i] = xv;
+            r2[i] = rv;
+            acc += rv.x * rv.x + rv.y * rv.y;
+        }
+    } else {
+        const int64_t stride = int64_t(c.nblk) * kBlock;
+        for (int64_t j = int64_t(c.blk) * kBlock + threadIdx.x; j < g.ncell; j += stride) {
+            const int64_t i = base + j;
+            x[i] += alpha * p[i];
+            const double v = r[i] - alpha * q[i];
+            r[i] = v;
+            acc += v * v;
         }
     }
-    if (threadIdx.x == 0) *counter = 0u;
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) {
+        rbn[c.slot()] = s;
+        if (c.blk == 0) st[c.b].it = k + 1;
+    }
+}
+
+// Final residual of a solve from the newest rr partials: rr, relres.
+__global__ __launch_bounds__(kBlock) void k_cg_finish(Grid g, const double* __restrict__ rb, CgScal* st) {
+    __shared__ double sh[kBlock / 64];
+    CgSplit c;
+    c.nblk = cg_blocks_of(g);
+    c.b = blockIdx.x;
+    const double rr = field_total(rb, c, sh);
+    if (threadIdx.x == 0) {
+        const double rr0 = st[c.b].rr0;
+        st[c.b].rr = rr;
+        st[c.b].relres = rr0 > 0.0 ? sqrt(rr / rr0) : 0.0;
+    }
 }
 
 // ----------------------------------------------------------------------------
@@ -614,41 +851,54 @@ hipError_t launch_wall_stage_vjp(const Grid& g, const T* w, const double* p, boo
     return hipGetLastError();
 }
 
+int cg_blocks(const Grid& g) { return cg_blocks_of(g); }
+
 template <typename T>
-hipError_t launch_cg_div(const Grid& g, const T* vel, const double* rin, double* r, double* partials,
-                         unsigned int* counter, CgScal* st, hipStream_t s) {
-    INS_WALL_DIM(g, k_cg_div, g, vel, rin, r, partials, counter, st);
+hipError_t launch_cg_div(const Grid& g, const T* vel, const double* rin, double* r, double* msum, hipStream_t s) {
+    const int nblk = cg_blocks_of(g) * g.batch;
+    if (g.dim == 3)
+        hipLaunchKernelGGL((k_cg_div<T, 3>), dim3(nblk), dim3(kBlock), 0, s, g, vel, rin, r, msum);
+    else
+        hipLaunchKernelGGL((k_cg_div<T, 2>), dim3(nblk), dim3(kBlock), 0, s, g, vel, rin, r, msum);
     return hipGetLastError();
 }
 
-#define INS_CG_DIM(g, KER, ...)                                                               \
-    do {                                                                                      \
-        const int nblk = stencil_blocks(g);                                                   \
-        if ((g).dim == 3)                                                                     \
-            hipLaunchKernelGGL((KER<3>), dim3(nblk), dim3(kBlock), 0, s, __VA_ARGS__);        \
-        else                                                                                  \
-            hipLaunchKernelGGL((KER<2>), dim3(nblk), dim3(kBlock), 0, s, __VA_ARGS__);        \
-    } while (0)
-
-hipError_t launch_cg_init(const Grid& g, double* r, double* x, double* p0, double* partials, unsigned int* counter,
-                          CgScal* st, int maxiter, hipStream_t s) {
-    INS_CG_DIM(g, k_cg_init, g, r, x, p0, partials, counter, st, maxiter);
+hipError_t launch_cg_init(const Grid& g, double* r, double* x, const double* msum, double* rb0, CgScal* st,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_init, dim3(cg_blocks_of(g) * g.batch), dim3(kBlock), 0, s, g, r, x, msum, rb0, st);
     return hipGetLastError();
 }
 
-hipError_t launch_cg_apply(const Grid& g, const double* r, const double* pin, double* pout, double* q, double* partials,
-                           unsigned int* counter, CgScal* st, hipStream_t s) {
-    INS_CG_DIM(g, k_cg_apply, g, r, pin, pout, q, partials, counter, st);
+hipError_t launch_cg_apply(const Grid& g, const double* r, const double* pin, double* pout, double* q,
+                           const double* rbk, const double* rbm, double* pqs, CgScal* st, int k, double rtol2,
+                           int maxiter, hipStream_t s) {
+    const int nblk = cg_blocks_of(g) * g.batch;
+    if (g.dim == 3)
+        hipLaunchKernelGGL(k_cg_apply3, dim3(nblk), dim3(kCgThreads3), 0, s, g, r, pin, pout, q, rbk, rbm, pqs, st, k,
+                           rtol2, maxiter);
+    else
+        hipLaunchKernelGGL(k_cg_apply2, dim3(nblk), dim3(kBlock), 0, s, g, r, pin, pout, q, rbk, rbm, pqs, st, k,
+                           rtol2, maxiter);
     return hipGetLastError();
 }
 
-hipError_t launch_cg_update(const Grid& g, double* x, const double* p, double* r, const double* q, double* partials,
-                            unsigned int* counter, CgScal* st, double rtol2, int maxiter, hipStream_t s) {
-    INS_CG_DIM(g, k_cg_update, g, x, p, r, q, partials, counter, st, rtol2, maxiter);
+hipError_t launch_cg_update(const Grid& g, double* x, const double* p, double* r, const double* q, const double* rbk,
+                            const double* pqs, double* rbn, CgScal* st, int k, double rtol2, int maxiter,
+                            hipStream_t s) {
+    const int nblk = cg_blocks_of(g) * g.batch;
+    if (g.dim == 3)
+        hipLaunchKernelGGL((k_cg_update<3>), dim3(nblk), dim3(kBlock), 0, s, g, x, p, r, q, rbk, pqs, rbn, st, k,
+                           rtol2, maxiter);
+    else
+        hipLaunchKernelGGL((k_cg_update<2>), dim3(nblk), dim3(kBlock), 0, s, g, x, p, r, q, rbk, pqs, rbn, st, k,
+                           rtol2, maxiter);
     return hipGetLastError();
 }
 
-int stencil_block_count(const Grid& g) { return stencil_blocks(g); }
+hipError_t launch_cg_finish(const Grid& g, const double* rb, CgScal* st, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_finish, dim3(g.batch), dim3(kBlock), 0, s, g, rb, st);
+    return hipGetLastError();
+}
 
 #define INS_WALL_INSTANTIATE(T)                                                                                         \
     template hipError_t launch_wall_rhs<T>(const Grid&, const T*, T*, hipStream_t);                                     \
@@ -662,8 +912,7 @@ int stencil_block_count(const Grid& g) { return stencil_blocks(g); }
                                              T*, double, hipStream_t);                                                  \
     template hipError_t launch_wall_stage_vjp<T>(const Grid&, const T*, const double*, bool, const T*, const T*,        \
                                                  const double*, bool, double, double, T*, int, T*, hipStream_t);        \
-    template hipError_t launch_cg_div<T>(const Grid&, const T*, const double*, double*, double*, unsigned int*, CgScal*, \
-                                         hipStream_t);
+    template hipError_t launch_cg_div<T>(const Grid&, const T*, const double*, double*, double*, hipStream_t);
 
 INS_WALL_INSTANTIATE(double)
 INS_WALL_INSTANTIATE(float)
