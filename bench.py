@@ -517,6 +517,7 @@ def channel_main(args):
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    copy_gbs = stream_copy_gbs()
     ch = channel_timing(args.steps, args.warmup, args.modes)
     main_mode = "fp64" if "fp64" in ch["modes"] else next(iter(ch["modes"]))
     line = {
@@ -534,6 +535,7 @@ def channel_main(args):
         "data": "synthetic",
         "config": {"workload": ch["workload"] + f"; {main_mode} RK4 step"},
         "roofline": ch["roofline"],
+        "stream_copy_gbs": round(copy_gbs, 1),
         "cpu_baseline": None,
         "modes": ch["modes"],
         "kernels": ch["kernels"],

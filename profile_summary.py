@@ -37,6 +37,9 @@ VARIANT_ORDER = {
     "void ins::k_fft_strided<1,": (["fft_y_inv"], ["k_fft.hip", "k_common.hpp"]),
     "void ins::k_fft_x_inv<": (["fft_x_inv"], ["k_fft.hip", "k_common.hpp"]),
     "void ins::k_apply_projection<double, 3>": (["apply_projection"], ["k_stencil.hip", "k_common.hpp"]),
+    # channel grid (walls in y): the two kernels of a CG iteration
+    "ins::k_cg_apply3": (["cg_apply"], ["k_walls.hip", "k_common.hpp", "ins_internal.hpp"]),
+    "void ins::k_cg_update<3>": (["cg_update"], ["k_walls.hip", "k_common.hpp", "ins_internal.hpp"]),
 }
 COPY = "ins::k_stream_copy"
 
