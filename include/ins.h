@@ -143,10 +143,31 @@ const char* ins_last_error(void);
  * to the host once (a stream synchronisation), and stops launching when all
  * fields are done. check_every = 0 never synchronises and always launches
  * maxiter iterations (done fields skip the work), which keeps a captured
- * graph free of host reads. The pressure solve is self-adjoint: its pullback
- * is the same solve. Closures, the face filter and the energy spectrum need
+ * graph free of host reads. On a uniform channel the pressure solve is
+ * self-adjoint and its pullback is the same solve (see ins_set_y_faces for a
+ * stretched y). A search direction with no component outside the constants
+ * (p . A p <= 0, e.g. a constant right-hand side) ends the solve without an
+ * update (relres then reads 0). Closures, the face filter and the energy spectrum need
  * the periodic grid (INS_ERR_UNSUPPORTED).
  * ------------------------------------------------------------------------- */
+
+/* Stretched y (Sec. 2.1 non-uniform grids, e.g. the tanh grid of eq. tanh-grid):
+ * faces is a host array of the n_y + 1 y-face coordinates, strictly increasing
+ * (the walls are faces[0] and faces[n_y]); x and z stay uniform. Replaces the
+ * uniform spacing of the box for every later call. The operators follow App. B
+ * with the non-uniform widths: cell widths w_j, centre distances d_j across the
+ * y-faces (mirrored ghost rows beyond the walls); in the convection the
+ * transported component is averaged with weights 1/2 and the transporting one
+ * interpolated as the mass-flux average w_j / (w_j + w_{j+1}) (the weights that
+ * keep the discrete convection energy-conserving). The CG runs on the symmetric
+ * -Omega_p D G (pressure volumes Omega_p); the pressure solve returns the
+ * zero-mean p with D G p = r - mean_w(r), mean_w the volume-weighted mean. The
+ * projection is no longer its own transpose: ins_project_vjp applies
+ * Omega_u P Omega_u^{-1} (velocity volumes Omega_u) and ins_poisson_solve_vjp the
+ * transpose of the solve; the step pullbacks use both. Synchronises the stream.
+ * INS_ERR_UNSUPPORTED on a periodic context; INS_ERR_INVALID for non-increasing
+ * or non-finite coordinates. */
+ins_status ins_set_y_faces(ins_ctx ctx, const double* faces);
 
 /* Defaults: rtol 1e-10, maxiter 20000, check_every 16. INS_ERR_UNSUPPORTED
  * on a periodic context; INS_ERR_INVALID for rtol < 0, maxiter < 1 or

@@ -66,6 +66,7 @@ _SIGS = {
     "ins_step_wray3_vjp": ([_P, _P, _P, _P, _D]),
     "ins_step_save": ([_P, C.c_int, _P, _P, _D, _P, _P]),
     "ins_cg_set": ([_P, _D, C.c_int, C.c_int]),
+    "ins_set_y_faces": ([_P, C.POINTER(C.c_double)]),
     "ins_cg_info": ([_P, C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     "ins_step_vjp_saved": ([_P, C.c_int, _P, _P, _P, _P, _P, _D]),
     "ins_scheme_stage_count": ([C.c_int]),

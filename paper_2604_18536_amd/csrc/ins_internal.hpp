@@ -23,6 +23,12 @@ struct Grid {
     double ih[3];       // 1 / h_a
     double ih2[3];      // 1 / h_a^2
     double nu;
+    // channel grid only (null otherwise): y metrics, 5 arrays of stride n_y + 2:
+    // [0..n_y) 1 / w_j; [S..S+n_y] 1 / d_j for j = -1 .. n_y - 1; [2S..) theta_j;
+    // [3S..) w_j; [4S..4S+n_y] d_j for j = -1 .. n_y - 1. w_j is the width of
+    // row j, d_j the distance of the centres around y-face j (mirrored ghosts:
+    // d_{-1} = w_0, d_{n_y-1} = w_{n_y-1}), theta_j = w_j / (w_j + w_{j+1}).
+    const double* ym;
 };
 
 // One 1D FFT length: Stockham stages with their radices and twiddle tables.
@@ -160,8 +166,9 @@ template <typename T>
 hipError_t launch_wall_divergence(const Grid& g, const T* u, double* r, hipStream_t s);
 template <typename T>
 hipError_t launch_wall_gradient(const Grid& g, const double* p, T* out, hipStream_t s);
+// adj: u_out = w - Omega_u G p (the correction of the transposed projection).
 template <typename T>
-hipError_t launch_wall_project(const Grid& g, const T* w, const double* p, T* u_out, hipStream_t s);
+hipError_t launch_wall_project(const Grid& g, const T* w, const double* p, T* u_out, bool adj, hipStream_t s);
 template <typename T>
 hipError_t launch_wall_rhs_vjp(const Grid& g, const T* u, const T* fbar, T* ubar, hipStream_t s);
 template <typename T>
@@ -187,12 +194,15 @@ struct CgScal {
 // partial-sum buffer holds cg_blocks(g) * batch doubles.
 constexpr int kCgMaxBlocks = 2048;
 int cg_blocks(const Grid& g);
-// r = D vel (vel != null) or rin; partial sums of r into msum.
+// mode 0: r = D vel; 1: r = D Omega_u^{-1} vel; 2, 3: r = rin. Partial sums of
+// w_j r (modes 0-2) or r (mode 3) into msum.
 template <typename T>
-hipError_t launch_cg_div(const Grid& g, const T* vel, const double* rin, double* r, double* msum, hipStream_t s);
-// r = mean - r, x = 0, partial sums of r.r into rb0; resets st.it / st.done.
-hipError_t launch_cg_init(const Grid& g, double* r, double* x, const double* msum, double* rb0, CgScal* st,
-                          hipStream_t s);
+hipError_t launch_cg_div(const Grid& g, const T* vel, const double* rin, double* r, double* msum, int mode,
+                         hipStream_t s);
+// r = w_j (mean_w - r) (modes 0-2; wsum = sum of w_j over a field) or mean - r
+// (mode 3); x = 0; partial sums of r.r into rb0; resets st.it / st.done.
+hipError_t launch_cg_init(const Grid& g, double* r, double* x, const double* msum, double* rb0, CgScal* st, int mode,
+                          double wsum, hipStream_t s);
 // Iteration k: stop test from rr_k (partials rbk); pout = r + beta pin (beta =
 // rr_k / rr_{k-1}, partials rbm), q = -D G pout, partial sums of pout.q into pqs.
 hipError_t launch_cg_apply(const Grid& g, const double* r, const double* pin, double* pout, double* q,
@@ -204,6 +214,8 @@ hipError_t launch_cg_update(const Grid& g, double* x, const double* p, double* r
                             hipStream_t s);
 // st.rr / st.relres from the newest rr partials.
 hipError_t launch_cg_finish(const Grid& g, const double* rb, CgScal* st, hipStream_t s);
+// t = w_j (t - mean_w(t)) in place (msum: partial-sum scratch).
+hipError_t launch_cg_weighted_center(const Grid& g, double* t, double* msum, double wsum, hipStream_t s);
 
 
 // Utilities.

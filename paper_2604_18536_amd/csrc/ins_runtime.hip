@@ -157,6 +157,8 @@ struct ins_ctx_s {
     double* cg_part = nullptr;  // partial sums: mean, rr (two generations), p.q; cg_blocks * batch each
     ins::CgScal* cg_st = nullptr;
     ins::CgScal* cg_host = nullptr;  // pinned host copy of cg_st
+    double* d_ym = nullptr;          // y metrics of the channel grid (Grid::ym)
+    double wsum = 0.0;               // sum of the cell volumes' y widths over one field (n_x n_z sum_j w_j)
 
     ins::FftPlan px{}, py{}, pz{};
     ins::FftPlan py_rev{}, pz_rev{};  // radices reversed: inverse half of the fused last-axis solve
@@ -327,6 +329,47 @@ void with_type(ins_ctx c, F&& f) {
         f(float{});
 }
 
+// y metrics of the channel (Grid::ym) from the cell widths (uniform: every
+// width h_y, weights exactly 1/2) or from the face coordinates.
+void upload_y_metrics(ins_ctx c, const double* faces) {
+    ins::Grid& g = c->g;
+    const int ny = g.ny, S = ny + 2;
+    std::vector<double> w(ny), d(ny + 1), th(ny, 0.5);
+    if (faces) {
+        std::vector<double> cen(ny);
+        for (int j = 0; j < ny; ++j) {
+            w[j] = faces[j + 1] - faces[j];
+            cen[j] = 0.5 * (faces[j] + faces[j + 1]);
+        }
+        d[0] = w[0];
+        for (int j = 0; j + 1 < ny; ++j) {
+            d[j + 1] = cen[j + 1] - cen[j];
+            th[j] = w[j] / (w[j] + w[j + 1]);
+        }
+        d[ny] = w[ny - 1];
+    } else {
+        const double h = 1.0 / g.ih[1];
+        std::fill(w.begin(), w.end(), h);
+        std::fill(d.begin(), d.end(), h);
+    }
+    std::vector<double> m(5 * size_t(S), 0.0);
+    double sw = 0.0;
+    for (int j = 0; j < ny; ++j) {
+        m[j] = 1.0 / w[j];
+        m[2 * S + j] = th[j];
+        m[3 * S + j] = w[j];
+        sw += w[j];
+    }
+    for (int j = 0; j <= ny; ++j) {
+        m[S + j] = 1.0 / d[j];
+        m[4 * S + j] = d[j];
+    }
+    hip_check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    hip_check(hipMemcpy(c->d_ym, m.data(), m.size() * sizeof(double), hipMemcpyHostToDevice), "upload y metrics");
+    c->wsum = sw * double(g.nx) * double(g.nz);
+    g.ym = c->d_ym;
+}
+
 bool cg_all_done(ins_ctx c) {
     const size_t nb = size_t(c->g.batch) * sizeof(ins::CgScal);
     hip_check(hipMemcpyAsync(c->cg_host, c->cg_st, nb, hipMemcpyDeviceToHost, c->stream), "hipMemcpyAsync");
@@ -342,7 +385,12 @@ bool cg_all_done(ins_ctx c) {
 // consistent part). Iterations are launched back to back; every cg_check
 // iterations the host reads the stop flags once and stops launching when
 // every field is done.
-void cg_solve(ins_ctx c, const void* vel, const double* r, double* x) {
+// mode 0: x = L^+ D vel; 1: x = L^+ D Omega_u^{-1} vel (inside the transposed
+// projection Omega_u P Omega_u^{-1}); 2: x = L^+ r; 3: the inner solve of the
+// pullback of 2 (right-hand side mean(r) - r unscaled, see ins_poisson_solve_vjp).
+// The operator is the symmetric -Omega_p D G, the right-hand side of modes
+// 0-2 is Omega_p (mean_w - r) with mean_w the volume-weighted mean.
+void cg_solve(ins_ctx c, const void* vel, const double* r, double* x, int mode) {
     const ins::Grid& g = c->g;
     const size_t np = size_t(ins::cg_blocks(g)) * g.batch;
     double* msum = c->cg_part;
@@ -352,13 +400,15 @@ void cg_solve(ins_ctx c, const void* vel, const double* r, double* x) {
         with_type(c, [&](auto tag) {
             using T = decltype(tag);
             c->launch("cg_div", [&] {
-                return ins::launch_cg_div<T>(g, static_cast<const T*>(vel), nullptr, c->cg_r, msum, c->stream);
+                return ins::launch_cg_div<T>(g, static_cast<const T*>(vel), nullptr, c->cg_r, msum, mode, c->stream);
             });
         });
     } else {
-        c->launch("cg_copy", [&] { return ins::launch_cg_div<double>(g, nullptr, r, c->cg_r, msum, c->stream); });
+        c->launch("cg_copy", [&] { return ins::launch_cg_div<double>(g, nullptr, r, c->cg_r, msum, mode, c->stream); });
     }
-    c->launch("cg_init", [&] { return ins::launch_cg_init(g, c->cg_r, x, msum, rb[0], c->cg_st, c->stream); });
+    c->launch("cg_init", [&] {
+        return ins::launch_cg_init(g, c->cg_r, x, msum, rb[0], c->cg_st, mode, c->wsum, c->stream);
+    });
     const double rtol2 = c->cg_rtol * c->cg_rtol;
     int k = 0;
     while (k < c->cg_maxiter) {
@@ -378,11 +428,12 @@ void cg_solve(ins_ctx c, const void* vel, const double* r, double* x) {
     c->launch("cg_finish", [&] { return ins::launch_cg_finish(g, rb[k & 1], c->cg_st, c->stream); });
 }
 
-// p = (D G)^-1 of the divergence of vel (vel != null) or of r.
-void poisson(ins_ctx c, const void* vel, const double* r, double* p) {
+// p = (D G)^-1 of the divergence of vel (vel != null) or of r. adj (channel):
+// the solve inside the transposed projection, of D Omega_u^{-1} vel.
+void poisson(ins_ctx c, const void* vel, const double* r, double* p, bool adj = false) {
     const ins::Grid& g = c->g;
     if (c->walls) {
-        cg_solve(c, vel, r, p);
+        cg_solve(c, vel, r, p, vel ? (adj ? 1 : 0) : 2);
         return;
     }
     if (vel) {
@@ -409,10 +460,12 @@ void poisson(ins_ctx c, const void* vel, const double* r, double* p) {
 }
 
 
+// out = w - G p; adj (channel): w - Omega_u G p, completing the transposed
+// projection Omega_u P Omega_u^{-1} (on the periodic grid P^T = P).
 template <typename T>
-void apply_projection(ins_ctx c, const T* w, const double* p, T* out) {
+void apply_projection(ins_ctx c, const T* w, const double* p, T* out, bool adj = false) {
     if (c->walls) {
-        c->launch("wall_projection", [&] { return ins::launch_wall_project<T>(c->g, w, p, out, c->stream); });
+        c->launch("wall_projection", [&] { return ins::launch_wall_project<T>(c->g, w, p, out, adj, c->stream); });
         return;
     }
     c->launch("apply_projection", [&] { return ins::launch_apply_projection<T>(c->g, w, p, out, c->stream); });
@@ -646,14 +699,14 @@ void step_rk4_reverse(ins_ctx c, const T* u0, const Stages<T>& S, const T* u1bar
     T* UA = static_cast<T*>(c->wa);
     T* UB = static_cast<T*>(c->wb);
     double* Q = c->p;
-    poisson(c, u1bar, nullptr, Q);
-    apply_projection<T>(c, u1bar, Q, YB);
+    poisson(c, u1bar, nullptr, Q, true);
+    apply_projection<T>(c, u1bar, Q, YB, true);
     stage_vjp<T>(c, S.w[2], S.p[2], true, YB, nullptr, nullptr, false, dt / 6.0, 0.0, u0bar, 0, UA);
-    poisson(c, UA, nullptr, Q);
+    poisson(c, UA, nullptr, Q, true);
     stage_vjp<T>(c, S.w[1], S.p[1], true, YB, UA, Q, true, dt / 3.0, dt, u0bar, 1, UB);
-    poisson(c, UB, nullptr, Q);
+    poisson(c, UB, nullptr, Q, true);
     stage_vjp<T>(c, S.w[0], S.p[0], true, YB, UB, Q, true, dt / 3.0, dt / 2.0, u0bar, 1, UA);
-    poisson(c, UA, nullptr, Q);
+    poisson(c, UA, nullptr, Q, true);
     stage_vjp<T>(c, u0, nullptr, false, YB, UA, Q, true, dt / 6.0, dt / 2.0, u0bar, 2, nullptr);
 }
 
@@ -708,14 +761,14 @@ void step_wray3_reverse(ins_ctx c, const T* u0, const Stages<T>& S, const T* u1b
     T* UA = static_cast<T*>(c->wa);
     T* UB = static_cast<T*>(c->wb);
     double* Q = c->p;
-    poisson(c, u1bar, nullptr, Q);
-    apply_projection<T>(c, u1bar, Q, YB);  // YB = wbar_4, the running yaccbar
+    poisson(c, u1bar, nullptr, Q, true);
+    apply_projection<T>(c, u1bar, Q, YB, true);  // YB = wbar_4, the running yaccbar
     // the accumulator starts as YB itself, so this stage writes no accumulator
     stage_vjp<T>(c, S.w[1], S.p[1], true, YB, nullptr, nullptr, false, dt * 3.0 / 4.0, 0.0, nullptr, 0, UA);
-    poisson(c, UA, nullptr, Q);
+    poisson(c, UA, nullptr, Q, true);
     // Fbar_2 = dt 5/12 wbar_3 (cb = 0, so the ybar operand is not YB, which this kernel updates)
     stage_vjp<T>(c, S.w[0], S.p[0], true, UA, UA, Q, true, 0.0, dt * 5.0 / 12.0, YB, 1, UB);
-    poisson(c, UB, nullptr, Q);
+    poisson(c, UB, nullptr, Q, true);
     stage_vjp<T>(c, u0, nullptr, false, YB, UB, Q, true, dt / 4.0, dt * 8.0 / 15.0, u0bar, 3, nullptr);
 }
 
@@ -797,6 +850,8 @@ ins_status ins_create(const ins_grid* grid, ins_bc bc, double nu, ins_dtype dtyp
             c->cg_q = static_cast<double*>(c->alloc(sb));
             c->cg_part = static_cast<double*>(c->alloc(4 * size_t(ins::cg_blocks(g)) * g.batch * sizeof(double)));
             c->cg_st = static_cast<ins::CgScal*>(c->alloc(size_t(g.batch) * sizeof(ins::CgScal)));
+            c->d_ym = static_cast<double*>(c->alloc(5 * size_t(g.ny + 2) * sizeof(double)));
+            upload_y_metrics(c, nullptr);
             hip_check(hipMemset(c->cg_st, 0, size_t(g.batch) * sizeof(ins::CgScal)), "hipMemset");
             hip_check(hipHostMalloc(reinterpret_cast<void**>(&c->cg_host), size_t(g.batch) * sizeof(ins::CgScal)),
                       "hipHostMalloc");
@@ -1052,10 +1107,35 @@ ins_status ins_gradient_vjp(ins_ctx ctx, const void* gbar, double* pbar) {
 }
 
 ins_status ins_poisson_solve_vjp(ins_ctx ctx, const double* pbar, double* rbar) {
-    return ins_poisson_solve(ctx, pbar, rbar);
+    if (!ctx || !ctx->walls) return ins_poisson_solve(ctx, pbar, rbar);
+    return guarded([&] {
+        checked(ctx);
+        need(pbar, "pbar");
+        need(rbar, "rbar");
+        // channel: the solve is p = S^+ Omega_p (r - mean_w(r)) with S = -Omega_p D G
+        // symmetric (zero-mean p), so its transpose is
+        // rbar = Omega_p (t - mean_w(t)), t = S^+ (mean(pbar) - pbar)
+        cg_solve(ctx, nullptr, pbar, rbar, 3);
+        ctx->launch("cg_weighted_center", [&] {
+            return ins::launch_cg_weighted_center(ctx->g, rbar, ctx->cg_part, ctx->wsum, ctx->stream);
+        });
+    });
 }
 
-ins_status ins_project_vjp(ins_ctx ctx, const void* ubar_out, void* ubar) { return ins_project(ctx, ubar_out, ubar, nullptr); }
+ins_status ins_project_vjp(ins_ctx ctx, const void* ubar_out, void* ubar) {
+    if (!ctx || !ctx->walls) return ins_project(ctx, ubar_out, ubar, nullptr);
+    return guarded([&] {
+        checked(ctx);
+        need(ubar_out, "ubar_out");
+        need(ubar, "ubar");
+        // channel: P^T = Omega_u P Omega_u^{-1}
+        poisson(ctx, ubar_out, nullptr, ctx->p, true);
+        with_type(ctx, [&](auto tag) {
+            using T = decltype(tag);
+            apply_projection<T>(ctx, static_cast<const T*>(ubar_out), ctx->p, static_cast<T*>(ubar), true);
+        });
+    });
+}
 
 ins_status ins_step_rk4_vjp(ins_ctx ctx, const void* u0, const void* u1bar, void* u0bar, double dt) {
     return guarded([&] {
@@ -1170,6 +1250,19 @@ ins_status ins_cg_set(ins_ctx ctx, double rtol, int maxiter, int check_every) {
         ctx->cg_rtol = rtol;
         ctx->cg_maxiter = maxiter;
         ctx->cg_check = check_every;
+    });
+}
+
+ins_status ins_set_y_faces(ins_ctx ctx, const double* faces) {
+    return guarded([&] {
+        checked(ctx);
+        need(faces, "faces");
+        if (!ctx->walls) raise(INS_ERR_UNSUPPORTED, "a stretched y grid needs the channel (INS_BC_WALLS_Y)");
+        for (int j = 0; j <= ctx->g.ny; ++j)
+            if (!std::isfinite(faces[j])) raise(INS_ERR_INVALID, "face coordinates must be finite");
+        for (int j = 0; j < ctx->g.ny; ++j)
+            if (!(faces[j + 1] > faces[j])) raise(INS_ERR_INVALID, "face coordinates must increase strictly");
+        upload_y_metrics(ctx, faces);
     });
 }
 

@@ -25,7 +25,7 @@ __global__ __launch_bounds__(kBlock) void k_stats(Grid g, const T* __restrict__ 
             s2 += v * v;
             mu = fmax(mu, fabs(v));
             nf += isfinite(v) ? 0.0 : 1.0;
-            dv += (v - vm) * g.ih[a];
+            dv += (v - vm) * ((a == 1 && g.ym) ? g.ym[t.y] : g.ih[a]);  // channel: 1 / w_j along y
         }
         md = fabs(dv);
     }

@@ -1,32 +1,57 @@
 // Kernels of the channel grid: no-slip walls at both ends of y, x and z
-// periodic (Sec. 2.1, boundary conditions through ghost volumes), and the
-// matrix-free conjugate-gradient pressure solve (Sec. 2.5.1, iterative solver).
+// periodic and uniform, y uniform or stretched (Sec. 2.1 boundary conditions
+// through ghost volumes and non-uniform grids; App. B kernels with
+// non-uniform widths), and the matrix-free conjugate-gradient pressure solve
+// (Sec. 2.5.1, iterative solver).
 //
 // Wall rules, applied where a stencil reads a neighbour:
-//  * u^y on the face right of the last cell row (row N_y - 1) is the upper
-//    wall and the face left of row 0 the lower one: both read as 0, and every
+//  * u^y on the face on top of the last cell row (row N_y - 1) is the upper
+//    wall and the face below row 0 the lower one: both read as 0, and every
 //    output writes 0 on the stored wall face;
-//  * a tangential component one row beyond a wall is the ghost value minus
-//    the first interior value (zero interpolant on the wall);
+//  * a tangential component one row beyond a wall is minus the first
+//    interior value (zero interpolant on the wall; the ghost row mirrors the
+//    first/last row, widths included);
 //  * the pressure gradient exists on interior y-faces only, so D G is the
 //    Neumann Laplacian.
-// The forward and pullback stencils are the periodic ones of k_common.hpp
-// (rhs_cell, rhs_vjp_cell) fed through sources that apply these rules: with
-// them the diffusion stays symmetric and every convective wall flux vanishes
-// identically, so the gather-form pullback needs no extra terms.
+// y metrics (Grid::ym, filled by the runtime): w_j the width of row j, d_j the
+// distance of the centres around y-face j (d_{-1} = w_0, d_{N_y-1} = w_{N_y-1}),
+// theta_j = w_j / (w_j + w_{j+1}). Convection: the transported component is
+// averaged with weights 1/2, the transporting one interpolated as the
+// mass-flux average of the pressure-volume faces it spans (theta on a
+// stretched y, 1/2 otherwise), which keeps convection energy-conserving.
+// The pullback stencils are written in gather form from the same flux
+// definitions; the sources below apply the wall rules to both the primal
+// field and the cotangent, which is exact because every convective wall flux
+// vanishes identically and the mirrored ghost makes the diffusion transpose
+// the printed one.
 //
-// CG (fp64 throughout): A = -D G on each field of the batch, b = mean(r) - r,
-// x_0 = 0. One iteration is two fused kernels:
+// CG (fp64 throughout) on the symmetric A = -Omega_p D G (the pressure-volume
+// scaling, a factor w_j per row, makes it symmetric), from x_0 = 0. One
+// iteration is two fused kernels:
 //   k_cg_apply:  p = r + beta p_old (formed at the stencil points), q = A p,
 //                partial sums of p.q
 //   k_cg_update: alpha = rr / p.q; x += alpha p, r -= alpha q, partial sums of r.r
-// Every scalar (rr, beta, alpha, the stop test) is recomputed from partial
-// sums in every workgroup, so iterations run back to back without the host
-// and results are bitwise reproducible. A stopped field skips the work of
-// later iterations.
+// Every scalar (rr, beta, alpha, the stop test) is recomputed in every
+// workgroup from partial sums, so iterations run back to back without the
+// host and results are bitwise reproducible. A stopped field skips the work
+// of later iterations.
 #include "k_common.hpp"
 
 namespace ins {
+
+// Per-row y metrics, indices clamped to the ghost conventions above.
+struct YMetric {
+    const double* m;
+    int ny, S;
+    __device__ __forceinline__ explicit YMetric(const Grid& g) : m(g.ym), ny(g.ny), S(g.ny + 2) {}
+    __device__ __forceinline__ int rc(int r) const { return r < 0 ? 0 : (r > ny - 1 ? ny - 1 : r); }
+    __device__ __forceinline__ int rf(int r) const { return r < -1 ? -1 : (r > ny - 1 ? ny - 1 : r); }
+    __device__ __forceinline__ double iw(int r) const { return m[rc(r)]; }
+    __device__ __forceinline__ double id(int r) const { return m[S + rf(r) + 1]; }
+    __device__ __forceinline__ double th(int r) const { return (r >= 0 && r < ny) ? m[2 * S + r] : 0.5; }
+    __device__ __forceinline__ double w(int r) const { return m[3 * S + rc(r)]; }
+    __device__ __forceinline__ double d(int r) const { return m[4 * S + rf(r) + 1]; }
+};
 
 // Per-thread flags of the rows y - 1 .. y + 2 seen from cell row y.
 struct WallRows {
@@ -57,8 +82,10 @@ struct WallVel {
     const T* __restrict__ w;
     const double* __restrict__ p;
     int ncell;
-    double ih0, ih1, ih2;
+    double ih0, ih2;
     WallRows rows;
+    YMetric M;
+    int y;
     __device__ __forceinline__ T operator()(int c, const Nb& nb, int dx, int dy, int dz) const {
         const int k = dy + 1;
         const int j = nb.at(dx, dy, dz);
@@ -67,7 +94,7 @@ struct WallVel {
             if constexpr (!PROJ) {
                 return w[ncell + j];
             } else {
-                return T(double(w[ncell + j]) - (p[nb.at(dx, dy + 1, dz)] - p[j]) * ih1);
+                return T(double(w[ncell + j]) - (p[nb.at(dx, dy + 1, dz)] - p[j]) * M.id(y + dy));
             }
         }
         T v;
@@ -81,8 +108,9 @@ struct WallVel {
     }
 };
 
-// Stage cotangent Fbar = cb ybar + (HAS_W ? cw (un - G q) : 0) with the same rules
-// (it is read through the transposed stencils, which are the same stencils).
+// Stage cotangent Fbar = cb ybar + (HAS_W ? cw (un - Omega_u G q) : 0) with the
+// same rules; un - Omega_u G q is the transposed projection P^T = Omega_u P
+// Omega_u^{-1} of the next stage's cotangent (q solved from D Omega_u^{-1} un).
 template <typename T, bool HAS_W>
 struct WallFbar {
     const T* __restrict__ ybar;
@@ -90,8 +118,10 @@ struct WallFbar {
     const double* __restrict__ q;
     T cb, cw;
     int ncell;
-    double ih0, ih1, ih2;
+    double ih0, ih2;
     WallRows rows;
+    YMetric M;
+    int y;
     __device__ __forceinline__ T operator()(int c, const Nb& nb, int dx, int dy, int dz) const {
         const int k = dy + 1;
         if (c == 1 && !rows.unk[k]) return T(0);
@@ -99,12 +129,121 @@ struct WallFbar {
         T v = cb * ybar[c * ncell + j];
         if constexpr (HAS_W) {
             const int jp = nb.at(dx + (c == 0), dy + (c == 1), dz + (c == 2));
-            const double ih = c == 0 ? ih0 : (c == 1 ? ih1 : ih2);
-            v += cw * T(double(un[c * ncell + j]) - (q[jp] - q[j]) * ih);
+            const double og = c == 1 ? (q[jp] - q[j]) : M.w(y + dy) * (q[jp] - q[j]) * (c == 0 ? ih0 : ih2);
+            v += cw * T(double(un[c * ncell + j]) - og);
         }
         return (c != 1 && rows.ghost[k]) ? -v : v;
     }
 };
+
+// F^a at the current cell (row y): diffusion (eq. diff-kernel) and convection
+// (eq. conv-kernel with the weights described above) on the channel grid.
+template <typename T, int DIM, class Src>
+__device__ __forceinline__ void rhs_cell_wall(const Grid& g, const Src& U, const Nb& nb, int y, T F[DIM]) {
+    const YMetric M(g);
+    const T iwj = T(M.iw(y)), iwp = T(M.iw(y + 1)), idj = T(M.id(y)), idm = T(M.id(y - 1)), th = T(M.th(y));
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const int ax = a == 0, ay = a == 1, az = a == 2;
+        const T uc = U(a, nb, 0, 0, 0);
+        T diff = T(0), conv = T(0);
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) {
+            const int bx = b == 0, by = b == 1, bz = b == 2;
+            const T up = U(a, nb, bx, by, bz);
+            const T um = U(a, nb, -bx, -by, -bz);
+            if (b != 1)
+                diff += ((up - uc) - (uc - um)) * T(g.ih2[b]);
+            else if (a != 1)
+                diff += ((up - uc) * idj - (uc - um) * idm) * iwj;
+            else
+                diff += ((up - uc) * iwp - (uc - um) * iwj) * idj;
+            T vr, vl;
+            if (a == 1 && b != 1) {
+                vr = th * U(b, nb, 0, 0, 0) + (T(1) - th) * U(b, nb, 0, 1, 0);
+                vl = th * U(b, nb, -bx, 0, -bz) + (T(1) - th) * U(b, nb, -bx, 1, -bz);
+            } else {
+                vr = T(0.5) * (U(b, nb, 0, 0, 0) + U(b, nb, ax, ay, az));
+                vl = T(0.5) * (U(b, nb, -bx, -by, -bz) + U(b, nb, ax - bx, ay - by, az - bz));
+            }
+            const T fr = T(0.5) * (uc + up) * vr;
+            const T fl = T(0.5) * (um + uc) * vl;
+            const T s = b != 1 ? T(g.ih[b]) : (a == 1 ? idj : iwj);
+            conv -= (fr - fl) * s;
+        }
+        F[a] = conv + T(g.nu) * diff;
+    }
+}
+
+// 1 / |Delta^b| of the a-velocity volume whose point lies on row r.
+template <typename T>
+__device__ __forceinline__ T conv_s(const Grid& g, const YMetric& M, int a, int b, int r) {
+    return b != 1 ? T(g.ih[b]) : T(a == 1 ? M.id(r) : M.iw(r));
+}
+
+// Pullback of the right-hand side at one cell (row y), gather form: the
+// diffusion transpose (eq. diff-pullback) plus, for each flux
+// F^{ab}[K] = A^{ab}[K] B^{ab}[K] containing u^g[J], its other factor times
+// Fbar^{ab}[K] = -fbar^a[K] s(K) + fbar^a[K + e_b] s(K + e_b), with the
+// interpolation weight of u^g[J] in its own factor.
+template <typename T, int DIM, class USrc, class FSrc>
+__device__ __forceinline__ void rhs_vjp_cell_wall(const Grid& g, const USrc& U, const FSrc& Fb, const Nb& nb, int y,
+                                                  T out[DIM]) {
+    const YMetric M(g);
+    const T thy = T(M.th(y)), thm = T(M.th(y - 1));
+#pragma unroll
+    for (int gm = 0; gm < DIM; ++gm) {
+        const int gx = gm == 0, gy = gm == 1, gz = gm == 2;
+        const T fc = Fb(gm, nb, 0, 0, 0);
+        T diff = T(0), acc = T(0);
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) {
+            const int bx = b == 0, by = b == 1, bz = b == 2;
+            const T fp = Fb(gm, nb, bx, by, bz);
+            const T fm = Fb(gm, nb, -bx, -by, -bz);
+            if (b != 1) {
+                diff += (fp - T(2) * fc + fm) * T(g.ih2[b]);
+            } else if (gm != 1) {
+                diff += fm * T(M.iw(y - 1) * M.id(y - 1)) - fc * T(M.iw(y) * (M.id(y) + M.id(y - 1))) +
+                        fp * T(M.iw(y + 1) * M.id(y));
+            } else {
+                diff += fm * T(M.id(y - 1) * M.iw(y)) - fc * T(M.id(y) * (M.iw(y + 1) + M.iw(y))) +
+                        fp * T(M.id(y + 1) * M.iw(y + 1));
+            }
+            // u^gm transported in F^{gm b} at K = J and K = J - e_b (weights 1/2)
+            const T s0 = conv_s<T>(g, M, gm, b, y);
+            const T F0 = -fc * s0 + fp * conv_s<T>(g, M, gm, b, y + by);
+            const T F1 = -fm * conv_s<T>(g, M, gm, b, y - by) + fc * s0;
+            T B0, B1;
+            if (gm == 1 && b != 1) {
+                B0 = thy * U(b, nb, 0, 0, 0) + (T(1) - thy) * U(b, nb, 0, 1, 0);
+                B1 = thy * U(b, nb, -bx, 0, -bz) + (T(1) - thy) * U(b, nb, -bx, 1, -bz);
+            } else {
+                B0 = T(0.5) * (U(b, nb, 0, 0, 0) + U(b, nb, gx, gy, gz));
+                B1 = T(0.5) * (U(b, nb, -bx, -by, -bz) + U(b, nb, gx - bx, gy - by, gz - bz));
+            }
+            acc += T(0.5) * (F0 * B0 + F1 * B1);
+        }
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            const int ax = a == 0, ay = a == 1, az = a == 2;
+            // u^gm transporting in F^{a gm} at K = J and K = J - e_a
+            const T F0 = -Fb(a, nb, 0, 0, 0) * conv_s<T>(g, M, a, gm, y) +
+                         Fb(a, nb, gx, gy, gz) * conv_s<T>(g, M, a, gm, y + gy);
+            const T A0 = T(0.5) * (U(a, nb, 0, 0, 0) + U(a, nb, gx, gy, gz));
+            const T F1 = -Fb(a, nb, -ax, -ay, -az) * conv_s<T>(g, M, a, gm, y - ay) +
+                         Fb(a, nb, gx - ax, gy - ay, gz - az) * conv_s<T>(g, M, a, gm, y - ay + gy);
+            const T A1 = T(0.5) * (U(a, nb, -ax, -ay, -az) + U(a, nb, gx - ax, gy - ay, gz - az));
+            T w0 = T(0.5), w1 = T(0.5);
+            if (a == 1 && gm != 1) {
+                w0 = thy;
+                w1 = T(1) - thm;
+            }
+            acc += w0 * F0 * A0 + w1 * F1 * A1;
+        }
+        out[gm] = acc + T(g.nu) * diff;
+    }
+}
 
 // ----------------------------------------------------------------------------
 // Forward stencils
@@ -117,9 +256,9 @@ __global__ __launch_bounds__(kBlock) void k_wall_rhs(Grid g, const T* __restrict
     WallRows rows;
     const Nb nb = make_wall_nb<DIM>(g, t.x, t.y, t.z, rows);
     const int64_t boff = int64_t(t.b) * DIM * g.ncell;
-    WallVel<T, false> U{u + boff, nullptr, int(g.ncell), g.ih[0], g.ih[1], g.ih[2], rows};
+    WallVel<T, false> U{u + boff, nullptr, int(g.ncell), g.ih[0], g.ih[2], rows, YMetric(g), t.y};
     T F[DIM];
-    rhs_cell<T, DIM>(g, U, nb, F);
+    rhs_cell_wall<T, DIM>(g, U, nb, t.y, F);
     const int c0 = nb.at(0, 0, 0);
     const bool wall = t.y == g.ny - 1;
 #pragma unroll
@@ -137,10 +276,10 @@ __global__ __launch_bounds__(kBlock) void k_wall_stage(Grid g, const T* __restri
     WallRows rows;
     const Nb nb = make_wall_nb<DIM>(g, t.x, t.y, t.z, rows);
     const int64_t boff = int64_t(t.b) * DIM * g.ncell;
-    WallVel<T, PROJ> U{w + boff, PROJ ? p + int64_t(t.b) * g.ncell : nullptr, int(g.ncell), g.ih[0], g.ih[1], g.ih[2],
-                       rows};
+    WallVel<T, PROJ> U{w + boff, PROJ ? p + int64_t(t.b) * g.ncell : nullptr, int(g.ncell), g.ih[0], g.ih[2],
+                       rows, YMetric(g), t.y};
     T F[DIM];
-    rhs_cell<T, DIM>(g, U, nb, F);
+    rhs_cell_wall<T, DIM>(g, U, nb, t.y, F);
     const int c0 = nb.at(0, 0, 0);
     const bool wall = t.y == g.ny - 1;
 #pragma unroll
@@ -157,12 +296,14 @@ __global__ __launch_bounds__(kBlock) void k_wall_stage(Grid g, const T* __restri
     }
 }
 
-// u_out = w - G p (float64 arithmetic); 0 on the wall face. u_out may alias w.
-template <typename T, int DIM>
+// u_out = w - G p (ADJ: w - Omega_u G p, the transposed projection's
+// correction); float64 arithmetic; 0 on the wall face; u_out may alias w.
+template <typename T, int DIM, bool ADJ>
 __global__ __launch_bounds__(kBlock) void k_wall_project(Grid g, const T* w, const double* __restrict__ p, T* u_out) {
     const TileIdx t = tile_of(g);
     if (!t.valid) return;
     const Nb nb = make_nb<DIM>(g, t.x, t.y, t.z);
+    const YMetric M(g);
     const double* pb = p + int64_t(t.b) * g.ncell;
     const int64_t boff = int64_t(t.b) * DIM * g.ncell;
     const int c0 = nb.at(0, 0, 0);
@@ -175,8 +316,13 @@ __global__ __launch_bounds__(kBlock) void k_wall_project(Grid g, const T* w, con
             u_out[k] = T(0);
             continue;
         }
-        const int cp = nb.at(a == 0, a == 1, a == 2);
-        u_out[k] = T(double(w[k]) - (pb[cp] - pc) * g.ih[a]);
+        const double dp = pb[nb.at(a == 0, a == 1, a == 2)] - pc;
+        double gp;
+        if (a == 1)
+            gp = ADJ ? dp : dp * M.id(t.y);
+        else
+            gp = dp * g.ih[a] * (ADJ ? M.w(t.y) : 1.0);
+        u_out[k] = T(double(w[k]) - gp);
     }
 }
 
@@ -186,6 +332,7 @@ __global__ __launch_bounds__(kBlock) void k_wall_gradient(Grid g, const double* 
     const TileIdx t = tile_of(g);
     if (!t.valid) return;
     const Nb nb = make_nb<DIM>(g, t.x, t.y, t.z);
+    const YMetric M(g);
     const double* pb = p + int64_t(t.b) * g.ncell;
     T* ob = out + int64_t(t.b) * DIM * g.ncell;
     const int c0 = nb.at(0, 0, 0);
@@ -193,14 +340,16 @@ __global__ __launch_bounds__(kBlock) void k_wall_gradient(Grid g, const double* 
     const bool wall = t.y == g.ny - 1;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-        const int cp = nb.at(a == 0, a == 1, a == 2);
-        ob[a * g.ncell + c0] = (a == 1 && wall) ? T(0) : T((pb[cp] - pc) * g.ih[a]);
+        const double dp = pb[nb.at(a == 0, a == 1, a == 2)] - pc;
+        ob[a * g.ncell + c0] = (a == 1 && wall) ? T(0) : T(dp * (a == 1 ? M.id(t.y) : g.ih[a]));
     }
 }
 
-// D u at one cell with both wall faces of u^y read as 0.
-template <typename T, int DIM>
+// D u at one cell (row y) with both wall faces of u^y read as 0; SCALED reads
+// Omega_u^{-1} u (u^y / d_j, tangential / w_j) instead of u.
+template <typename T, int DIM, bool SCALED>
 __device__ __forceinline__ double wall_div_cell(const Grid& g, const T* ub, const Nb& nb, int y) {
+    const YMetric M(g);
     const int c0 = nb.at(0, 0, 0);
     double acc = 0.0;
 #pragma unroll
@@ -210,8 +359,14 @@ __device__ __forceinline__ double wall_div_cell(const Grid& g, const T* ub, cons
         if (a == 1) {
             if (y == g.ny - 1) up = 0.0;
             if (y == 0) dn = 0.0;
+            if constexpr (SCALED) {
+                up /= M.d(y);
+                dn /= M.d(y - 1);
+            }
+            acc += (up - dn) * M.iw(y);
+        } else {
+            acc += (up - dn) * g.ih[a] * (SCALED ? 1.0 / M.w(y) : 1.0);
         }
-        acc += (up - dn) * g.ih[a];
     }
     return acc;
 }
@@ -221,7 +376,8 @@ __global__ __launch_bounds__(kBlock) void k_wall_divergence(Grid g, const T* __r
     const TileIdx t = tile_of(g);
     if (!t.valid) return;
     const Nb nb = make_nb<DIM>(g, t.x, t.y, t.z);
-    r[int64_t(t.b) * g.ncell + nb.at(0, 0, 0)] = wall_div_cell<T, DIM>(g, u + int64_t(t.b) * DIM * g.ncell, nb, t.y);
+    r[int64_t(t.b) * g.ncell + nb.at(0, 0, 0)] =
+        wall_div_cell<T, DIM, false>(g, u + int64_t(t.b) * DIM * g.ncell, nb, t.y);
 }
 
 // ----------------------------------------------------------------------------
@@ -237,17 +393,19 @@ __global__ __launch_bounds__(kBlock) void k_wall_rhs_vjp(Grid g, const T* __rest
     const Nb nb = make_wall_nb<DIM>(g, t.x, t.y, t.z, rows);
     const int64_t boff = int64_t(t.b) * DIM * g.ncell;
     const int nc = int(g.ncell);
-    WallVel<T, false> U{u + boff, nullptr, nc, g.ih[0], g.ih[1], g.ih[2], rows};
-    WallFbar<T, false> F{fbar + boff, nullptr, nullptr, T(1), T(0), nc, g.ih[0], g.ih[1], g.ih[2], rows};
+    const YMetric M(g);
+    WallVel<T, false> U{u + boff, nullptr, nc, g.ih[0], g.ih[2], rows, M, t.y};
+    WallFbar<T, false> F{fbar + boff, nullptr, nullptr, T(1), T(0), nc, g.ih[0], g.ih[2], rows, M, t.y};
     T out[DIM];
-    rhs_vjp_cell<T, DIM>(g, U, F, nb, out);
+    rhs_vjp_cell_wall<T, DIM>(g, U, F, nb, t.y, out);
     const int c0 = nb.at(0, 0, 0);
     const bool wall = t.y == g.ny - 1;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) ubar[boff + a * g.ncell + c0] = (a == 1 && wall) ? T(0) : out[a];
 }
 
-// Reverse stage (same contract as k_stage_vjp, without the closure output).
+// Reverse stage (same contract as k_stage_vjp, without the closure output;
+// the projected cotangent of the next stage is un - Omega_u G q).
 template <typename T, int DIM, bool PROJ_U, bool HAS_W>
 __global__ __launch_bounds__(kBlock) void k_wall_stage_vjp(Grid g, const T* __restrict__ w, const double* __restrict__ p,
                                                             const T* __restrict__ ybar, const T* __restrict__ un,
@@ -260,11 +418,12 @@ __global__ __launch_bounds__(kBlock) void k_wall_stage_vjp(Grid g, const T* __re
     const int64_t boff = int64_t(t.b) * DIM * g.ncell;
     const int64_t soff = int64_t(t.b) * g.ncell;
     const int nc = int(g.ncell);
-    WallVel<T, PROJ_U> U{w + boff, PROJ_U ? p + soff : nullptr, nc, g.ih[0], g.ih[1], g.ih[2], rows};
+    const YMetric M(g);
+    WallVel<T, PROJ_U> U{w + boff, PROJ_U ? p + soff : nullptr, nc, g.ih[0], g.ih[2], rows, M, t.y};
     WallFbar<T, HAS_W> F{ybar + boff, HAS_W ? un + boff : nullptr, HAS_W ? q + soff : nullptr, cb, cw, nc,
-                         g.ih[0], g.ih[1], g.ih[2], rows};
+                         g.ih[0], g.ih[2], rows, M, t.y};
     T out[DIM];
-    rhs_vjp_cell<T, DIM>(g, U, F, nb, out);
+    rhs_vjp_cell_wall<T, DIM>(g, U, F, nb, t.y, out);
     const int c0 = nb.at(0, 0, 0);
     const bool wall = t.y == g.ny - 1;
 #pragma unroll
@@ -277,8 +436,9 @@ __global__ __launch_bounds__(kBlock) void k_wall_stage_vjp(Grid g, const T* __re
         }
         T acc = (mode == 0 || mode == 3) ? ybar[k] : u0bar[k];
         if constexpr (HAS_W) {
-            const int cp = nb.at(a == 0, a == 1, a == 2);
-            acc += T(double(un[k]) - (q[soff + cp] - q[soff + c0]) * g.ih[a]);
+            const double dq = q[soff + nb.at(a == 0, a == 1, a == 2)] - q[soff + c0];
+            const double og = a == 1 ? dq : M.w(t.y) * dq * g.ih[a];
+            acc += T(double(un[k]) - og);
         }
         if (mode >= 2) acc += out[a];
         if (u0bar) u0bar[k] = acc;
@@ -286,12 +446,13 @@ __global__ __launch_bounds__(kBlock) void k_wall_stage_vjp(Grid g, const T* __re
     }
 }
 
-// ubar^a[J] = (rbar[J] - rbar[J + e_a]) / h_a; 0 on the wall face.
+// D^T: ubar^a[J] = rbar[J] / |Delta^a_J| - rbar[J + e_a] / |Delta^a_{J+e_a}| (cell widths); 0 on the wall face.
 template <typename T, int DIM>
 __global__ __launch_bounds__(kBlock) void k_wall_div_vjp(Grid g, const double* __restrict__ rbar, T* __restrict__ ubar) {
     const TileIdx t = tile_of(g);
     if (!t.valid) return;
     const Nb nb = make_nb<DIM>(g, t.x, t.y, t.z);
+    const YMetric M(g);
     const double* rb = rbar + int64_t(t.b) * g.ncell;
     T* ob = ubar + int64_t(t.b) * DIM * g.ncell;
     const int c0 = nb.at(0, 0, 0);
@@ -299,31 +460,51 @@ __global__ __launch_bounds__(kBlock) void k_wall_div_vjp(Grid g, const double* _
     const bool wall = t.y == g.ny - 1;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-        const int cp = nb.at(a == 0, a == 1, a == 2);
-        ob[a * g.ncell + c0] = (a == 1 && wall) ? T(0) : T((rc - rb[cp]) * g.ih[a]);
+        const double rp = rb[nb.at(a == 0, a == 1, a == 2)];
+        double v;
+        if (a == 1)
+            v = wall ? 0.0 : rc * M.iw(t.y) - rp * M.iw(t.y + 1);
+        else
+            v = (rc - rp) * g.ih[a];
+        ob[a * g.ncell + c0] = T(v);
     }
 }
 
-// pbar[I] = sum_a (gbar^a[I - e_a] - gbar^a[I]) / h_a over the interior faces.
+// G^T: pbar[I] = sum_a (gbar^a[I - e_a] s[I - e_a] - gbar^a[I] s[I]) over interior faces.
 template <typename T, int DIM>
 __global__ __launch_bounds__(kBlock) void k_wall_grad_vjp(Grid g, const T* __restrict__ gbar, double* __restrict__ pbar) {
     const TileIdx t = tile_of(g);
     if (!t.valid) return;
     const Nb nb = make_nb<DIM>(g, t.x, t.y, t.z);
-    pbar[int64_t(t.b) * g.ncell + nb.at(0, 0, 0)] =
-        -wall_div_cell<T, DIM>(g, gbar + int64_t(t.b) * DIM * g.ncell, nb, t.y);
+    const YMetric M(g);
+    const T* gb = gbar + int64_t(t.b) * DIM * g.ncell;
+    const int c0 = nb.at(0, 0, 0);
+    double acc = 0.0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const double gc = double(gb[a * g.ncell + c0]);
+        const double gm = double(gb[a * g.ncell + nb.at(-(a == 0), -(a == 1), -(a == 2))]);
+        if (a == 1) {
+            if (t.y > 0) acc += gm * M.id(t.y - 1);
+            if (t.y < g.ny - 1) acc -= gc * M.id(t.y);
+        } else {
+            acc += (gm - gc) * g.ih[a];
+        }
+    }
+    pbar[int64_t(t.b) * g.ncell + c0] = acc;
 }
 
 // ----------------------------------------------------------------------------
 // Conjugate gradients
 //
-// Work split: the tiles of each field (64 x 4 cells, ordered as in tile_of)
-// are dealt in contiguous runs to cg_blocks(g) workgroups per field; the
-// workgroup with logical id b * nblk + blk serves field b. Every partial sum
-// goes to a buffer of nblk doubles per field; a kernel that needs the total
-// reduces that field's nblk partials in every workgroup, in one fixed order,
-// so all workgroups agree bitwise. No atomics, fences or inter-workgroup
-// waits: each kernel only reads sums its predecessors finished writing.
+// Work split: the tiles of each field (64 x 4 cells) are dealt in contiguous
+// runs to cg_blocks(g) workgroups per field (the 3D apply kernel uses 64 x 8
+// tile columns and z-chunks instead, the same count); the workgroup with
+// logical id b * nblk + blk serves field b. Every partial sum goes to a buffer
+// of nblk doubles per field; a kernel that needs the total reduces that
+// field's nblk partials in every workgroup, in one fixed order, so all
+// workgroups agree bitwise. No atomics, fences or inter-workgroup waits: each
+// kernel only reads sums its predecessors finished writing.
 // ----------------------------------------------------------------------------
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -420,39 +601,51 @@ __device__ __forceinline__ bool cg_stopped(double rrk, double rr0, int k, double
     return !(rr0 > 0.0) || rrk <= rtol2 * rr0 || k >= maxiter;
 }
 
-// r = D vel (vel != null, wall rules) or a copy of rin; partial sums of r.
+// Right-hand side of the solve. mode 0: r = D vel; 1: r = D Omega_u^{-1} vel
+// (transposed projection); 2, 3: r = rin. Partial sums of w_j r (modes 0-2,
+// for the volume-weighted mean) or of r (mode 3).
 template <typename T, int DIM>
 __global__ __launch_bounds__(kBlock) void k_cg_div(Grid g, const T* __restrict__ vel, const double* __restrict__ rin,
-                                                    double* __restrict__ r, double* __restrict__ msum) {
+                                                    double* __restrict__ r, double* __restrict__ msum, int mode) {
     __shared__ double sh[kBlock / 64];
     const CgSplit c = cg_split(g);
+    const YMetric M(g);
     double acc = 0.0;
     for (int t = c.t0; t < c.t1; ++t) {
         int x, y, z;
         if (!cg_cell(g, t, x, y, z)) continue;
         const Nb nb = make_nb<DIM>(g, x, y, z);
         const int64_t k = cg_index(g, c.b, x, y, z);
-        const double v = vel ? wall_div_cell<T, DIM>(g, vel + int64_t(c.b) * DIM * g.ncell, nb, y) : rin[k];
+        double v;
+        if (mode == 0)
+            v = wall_div_cell<T, DIM, false>(g, vel + int64_t(c.b) * DIM * g.ncell, nb, y);
+        else if (mode == 1)
+            v = wall_div_cell<T, DIM, true>(g, vel + int64_t(c.b) * DIM * g.ncell, nb, y);
+        else
+            v = rin[k];
         r[k] = v;
-        acc += v;
+        acc += mode == 3 ? v : M.w(y) * v;
     }
     const double s = block_sum(acc, sh);
     if (threadIdx.x == 0) msum[c.slot()] = s;
 }
 
-// r = mean(r) - r, x = 0; partial sums of r.r (rr_0).
+// b = w_j (mean_w - r) (modes 0-2; mean_w the volume-weighted mean, wsum the
+// field's sum of w_j) or b = mean - r (mode 3), stored in r; x = 0; partial
+// sums of b.b (rr_0).
 __global__ __launch_bounds__(kBlock) void k_cg_init(Grid g, double* __restrict__ r, double* __restrict__ x,
                                                      const double* __restrict__ msum, double* __restrict__ rb0,
-                                                     CgScal* st) {
+                                                     CgScal* st, int mode, double wsum) {
     __shared__ double sh[kBlock / 64];
     const CgSplit c = cg_split(g);
-    const double mean = field_total(msum, c, sh) / double(g.ncell);
+    const YMetric M(g);
+    const double mean = field_total(msum, c, sh) / (mode == 3 ? double(g.ncell) : wsum);
     double acc = 0.0;
     for (int t = c.t0; t < c.t1; ++t) {
         int cx, cy, cz;
         if (!cg_cell(g, t, cx, cy, cz)) continue;
         const int64_t k = cg_index(g, c.b, cx, cy, cz);
-        const double v = mean - r[k];
+        const double v = mode == 3 ? mean - r[k] : M.w(cy) * (mean - r[k]);
         r[k] = v;
         x[k] = 0.0;
         acc += v * v;
@@ -478,57 +671,31 @@ __device__ __forceinline__ double cg_dir(const double* rb, const double* pb, int
     }
 }
 
-// q = A p at one cell from p at the cell (pc), at z -/+ 1 (pm, pp; unused in
-// 2D) and at the x/y neighbours read from r, p_old. Wall rule: no y-face
-// beyond the first/last row.
-template <bool FIRST, int DIM>
-__device__ __forceinline__ double cg_ap(const Grid& g, const double* rb, const double* pb, double beta, int64_t c0,
-                                        int x, int y, double pc, double pm, double pp) {
+// 2D: q = A p at one cell of row y (no faces beyond the walls).
+template <bool FIRST>
+__device__ __forceinline__ double cg_ap2(const Grid& g, const YMetric& M, const double* rb, const double* pb,
+                                         double beta, int64_t c0, int x, int y, double pc) {
     const int xm = x == 0 ? g.nx - 1 : x - 1;
     const int xp = x == g.nx - 1 ? 0 : x + 1;
     const int64_t row = c0 - x;
-    double ap = (2.0 * pc - cg_dir<FIRST>(rb, pb, row + xm, beta) - cg_dir<FIRST>(rb, pb, row + xp, beta)) * g.ih2[0];
-    double sy = 0.0;
-    if (y > 0) sy += pc - cg_dir<FIRST>(rb, pb, c0 - g.nx, beta);
-    if (y < g.ny - 1) sy += pc - cg_dir<FIRST>(rb, pb, c0 + g.nx, beta);
-    ap += sy * g.ih2[1];
-    if constexpr (DIM == 3) ap += (2.0 * pc - pm - pp) * g.ih2[2];
+    double ap = (2.0 * pc - cg_dir<FIRST>(rb, pb, row + xm, beta) - cg_dir<FIRST>(rb, pb, row + xp, beta)) *
+                g.ih2[0] * M.w(y);
+    if (y > 0) ap += (pc - cg_dir<FIRST>(rb, pb, c0 - g.nx, beta)) * M.id(y - 1);
+    if (y < g.ny - 1) ap += (pc - cg_dir<FIRST>(rb, pb, c0 + g.nx, beta)) * M.id(y);
     return ap;
 }
 
-// Iteration k. rr_k from rbk, rr_{k-1} from rbm (k > 0). Unless stopped:
-// p = r + beta p_old with beta = rr_k / rr_{k-1} (p = r at k = 0), formed at
-// every stencil point; q = A p = -D G p; partial sums of p.q. Workgroup 0 of
-// each field publishes the stop flag (and rr_0 at k = 0). In 3D each thread
-// walks its (x, y) along z keeping p at z - 1, z, z + 1 in registers.
-template <bool FIRST, int DIM>
-__device__ __forceinline__ double cg_apply_run(const Grid& g, const CgSplit& c, const double* rb, const double* pb,
-                                               double* pout, double* q, double beta) {
+template <bool FIRST>
+__device__ __forceinline__ double cg_apply2_run(const Grid& g, const CgSplit& c, const double* rb, const double* pb,
+                                                double* pout, double* q, double beta) {
+    const YMetric M(g);
     double acc = 0.0;
-    const int64_t plane = int64_t(g.nx) * g.ny;
-    double pm = 0.0, pc = 0.0, pp = 0.0;
-    bool fresh = true;
     for (int t = c.t0; t < c.t1; ++t) {
         int x, y, z;
-        const bool in = cg_cell(g, t, x, y, z);
-        if (!in) continue;
-        const int64_t c0 = (int64_t(z) * g.ny + y) * g.nx + x;
-        if constexpr (DIM == 3) {
-            if (fresh || z == 0) {
-                const int zm = z == 0 ? g.nz - 1 : z - 1;
-                pm = cg_dir<FIRST>(rb, pb, c0 + (zm - z) * plane, beta);
-                pc = cg_dir<FIRST>(rb, pb, c0, beta);
-            } else {
-                pm = pc;
-                pc = pp;
-            }
-            const int zp = z == g.nz - 1 ? 0 : z + 1;
-            pp = cg_dir<FIRST>(rb, pb, c0 + (zp - z) * plane, beta);
-            fresh = false;
-        } else {
-            pc = cg_dir<FIRST>(rb, pb, c0, beta);
-        }
-        const double ap = cg_ap<FIRST, DIM>(g, rb, pb, beta, c0, x, y, pc, pm, pp);
+        if (!cg_cell(g, t, x, y, z)) continue;
+        const int64_t c0 = int64_t(y) * g.nx + x;
+        const double pc = cg_dir<FIRST>(rb, pb, c0, beta);
+        const double ap = cg_ap2<FIRST>(g, M, rb, pb, beta, c0, x, y, pc);
         pout[c0] = pc;
         q[c0] = ap;
         acc += pc * ap;
@@ -536,7 +703,10 @@ __device__ __forceinline__ double cg_apply_run(const Grid& g, const CgSplit& c, 
     return acc;
 }
 
-// 2D: each workgroup takes a run of 64 x 4 tiles.
+// Iteration k. rr_k from rbk, rr_{k-1} from rbm (k > 0). Unless stopped:
+// p = r + beta p_old with beta = rr_k / rr_{k-1} (p = r at k = 0), formed at
+// every stencil point; q = A p; partial sums of p.q. Workgroup 0 of each field
+// publishes the stop flag (and rr_0 at k = 0). 2D: runs of 64 x 4 tiles.
 __global__ __launch_bounds__(kBlock) void k_cg_apply2(Grid g, const double* __restrict__ r,
                                                        const double* __restrict__ pin, double* __restrict__ pout,
                                                        double* __restrict__ q, const double* __restrict__ rbk,
@@ -555,10 +725,10 @@ __global__ __launch_bounds__(kBlock) void k_cg_apply2(Grid g, const double* __re
     const int64_t soff = int64_t(c.b) * g.ncell;
     double acc;
     if (k == 0) {
-        acc = cg_apply_run<true, 2>(g, c, r + soff, pin + soff, pout + soff, q + soff, 0.0);
+        acc = cg_apply2_run<true>(g, c, r + soff, pin + soff, pout + soff, q + soff, 0.0);
     } else {
         const double beta = rrk / field_total(rbm, c, sh);
-        acc = cg_apply_run<false, 2>(g, c, r + soff, pin + soff, pout + soff, q + soff, beta);
+        acc = cg_apply2_run<false>(g, c, r + soff, pin + soff, pout + soff, q + soff, beta);
     }
     const double s = block_sum(acc, sh);
     if (threadIdx.x == 0) pqs[c.slot()] = s;
@@ -575,6 +745,7 @@ __device__ __forceinline__ double cg_apply3_run(const Grid& g, const CgSplit& c,
                                                 const double* __restrict__ pin, double* __restrict__ pout,
                                                 double* __restrict__ q, double beta,
                                                 double (*pl)[kCgTy + 2][kTileX + 2]) {
+    const YMetric M(g);
     const int cols = cg_cols3(g);
     const int ntx = (g.nx + kTileX - 1) / kTileX;
     const int nzc = cg_zchunks(g);
@@ -587,6 +758,11 @@ __device__ __forceinline__ double cg_apply3_run(const Grid& g, const CgSplit& c,
     const bool yin = y < g.ny;
     const bool valid = yin && x0 + lx < g.nx;
     const int64_t plane = int64_t(g.nx) * g.ny;
+    // scaled coefficients of this row: w_y / h^2 in x and z, 1 / d across the y-faces
+    const double wy = yin ? M.w(y) : 0.0;
+    const double cx = wy * g.ih2[0], cz = wy * g.ih2[2];
+    const double cyp = (yin && y < g.ny - 1) ? M.id(y) : 0.0;
+    const double cym = (yin && y > 0) ? M.id(y - 1) : 0.0;
     // halo cell of this thread (threads < 144)
     int hx = 0, hy = 0, hrow = 0, hcol = 0;
     bool hal = false;
@@ -600,11 +776,11 @@ __device__ __forceinline__ double cg_apply3_run(const Grid& g, const CgSplit& c,
         hal = hy < g.ny;
     } else if (hthr) {
         const int i = threadIdx.x - 2 * kCgTy;
-        const int side = i / kTileX, cx = i % kTileX;
+        const int side = i / kTileX, cxl = i % kTileX;
         hy = side ? y0 + kCgTy : y0 - 1;
         hrow = side ? kCgTy + 1 : 0;
-        hcol = cx + 1;
-        hx = (x0 + cx) % g.nx;
+        hcol = cxl + 1;
+        hx = (x0 + cxl) % g.nx;
         hal = hy >= 0 && hy < g.ny;
     }
     const int64_t own = int64_t(y) * g.nx + xw;
@@ -622,11 +798,9 @@ __device__ __forceinline__ double cg_apply3_run(const Grid& g, const CgSplit& c,
         const double pp = yin ? cg_dir<FIRST>(r, pin, int64_t(zp) * plane + own, beta) : 0.0;
         const double hv = (hthr && hal) ? cg_dir<FIRST>(r, pin, int64_t(zp) * plane + hal_off, beta) : 0.0;
         if (valid) {
-            double ap = (2.0 * pc - pl[cur][ly + 1][lx] - pl[cur][ly + 1][lx + 2]) * g.ih2[0];
-            double sy = 0.0;
-            if (y > 0) sy += pc - pl[cur][ly][lx + 1];
-            if (y < g.ny - 1) sy += pc - pl[cur][ly + 2][lx + 1];
-            ap += sy * g.ih2[1] + (2.0 * pc - pm - pp) * g.ih2[2];
+            double ap = (2.0 * pc - pl[cur][ly + 1][lx] - pl[cur][ly + 1][lx + 2]) * cx;
+            ap += (pc - pl[cur][ly][lx + 1]) * cym + (pc - pl[cur][ly + 2][lx + 1]) * cyp;
+            ap += (2.0 * pc - pm - pp) * cz;
             const int64_t c0 = int64_t(z) * plane + int64_t(y) * g.nx + x0 + lx;
             pout[c0] = pc;
             q[c0] = ap;
@@ -679,6 +853,8 @@ __global__ __launch_bounds__(kCgThreads3) void k_cg_apply3(Grid g, const double*
 // Iteration k, unless stopped: alpha = rr_k / p.q, x += alpha p, r -= alpha q,
 // partial sums of r.r (rr_{k+1}) into rbn; a stopped field copies its rr_k
 // partials forward instead, so the newest buffer always holds the final sum.
+// A search direction with p.q <= 0 (no component outside the constants)
+// ends the solve without an update: its partials are written as 0.
 // Pointwise: the workgroups of a field sweep it together (grid stride), two
 // cells per thread and access when the field size is even.
 template <int DIM>
@@ -695,7 +871,11 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(Grid g, double* __restrict
         return;
     }
     const double pq = field_total(pqs, c, sh);
-    const double alpha = pq > 0.0 ? rrk / pq : 0.0;
+    if (!(pq > 0.0)) {
+        if (threadIdx.x == 0) rbn[c.slot()] = 0.0;
+        return;
+    }
+    const double alpha = rrk / pq;
     const int64_t base = int64_t(c.b) * g.ncell;
     double acc = 0.0;
     if ((g.ncell & 1) == 0) {
@@ -747,6 +927,36 @@ __global__ __launch_bounds__(kBlock) void k_cg_finish(Grid g, const double* __re
     }
 }
 
+// Partial sums of w_j t (volume-weighted mean of a solution).
+__global__ __launch_bounds__(kBlock) void k_cg_wsum(Grid g, const double* __restrict__ t, double* __restrict__ msum) {
+    __shared__ double sh[kBlock / 64];
+    const CgSplit c = cg_split(g);
+    const YMetric M(g);
+    double acc = 0.0;
+    for (int tt = c.t0; tt < c.t1; ++tt) {
+        int x, y, z;
+        if (!cg_cell(g, tt, x, y, z)) continue;
+        acc += M.w(y) * t[cg_index(g, c.b, x, y, z)];
+    }
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) msum[c.slot()] = s;
+}
+
+// t = w_j (t - mean_w(t)), in place (the output side of the solve's pullback).
+__global__ __launch_bounds__(kBlock) void k_cg_post(Grid g, double* __restrict__ t, const double* __restrict__ msum,
+                                                     double wsum) {
+    __shared__ double sh[kBlock / 64];
+    const CgSplit c = cg_split(g);
+    const YMetric M(g);
+    const double mean = field_total(msum, c, sh) / wsum;
+    for (int tt = c.t0; tt < c.t1; ++tt) {
+        int x, y, z;
+        if (!cg_cell(g, tt, x, y, z)) continue;
+        const int64_t k = cg_index(g, c.b, x, y, z);
+        t[k] = M.w(y) * (t[k] - mean);
+    }
+}
+
 // ----------------------------------------------------------------------------
 // Launchers
 // ----------------------------------------------------------------------------
@@ -778,8 +988,19 @@ hipError_t launch_wall_gradient(const Grid& g, const double* p, T* out, hipStrea
 }
 
 template <typename T>
-hipError_t launch_wall_project(const Grid& g, const T* w, const double* p, T* u_out, hipStream_t s) {
-    INS_WALL_DIM(g, k_wall_project, g, w, p, u_out);
+hipError_t launch_wall_project(const Grid& g, const T* w, const double* p, T* u_out, bool adj, hipStream_t s) {
+    const int nblk = stencil_blocks(g);
+    if (g.dim == 3) {
+        if (adj)
+            hipLaunchKernelGGL((k_wall_project<T, 3, true>), dim3(nblk), dim3(kBlock), 0, s, g, w, p, u_out);
+        else
+            hipLaunchKernelGGL((k_wall_project<T, 3, false>), dim3(nblk), dim3(kBlock), 0, s, g, w, p, u_out);
+    } else {
+        if (adj)
+            hipLaunchKernelGGL((k_wall_project<T, 2, true>), dim3(nblk), dim3(kBlock), 0, s, g, w, p, u_out);
+        else
+            hipLaunchKernelGGL((k_wall_project<T, 2, false>), dim3(nblk), dim3(kBlock), 0, s, g, w, p, u_out);
+    }
     return hipGetLastError();
 }
 
@@ -854,18 +1075,20 @@ hipError_t launch_wall_stage_vjp(const Grid& g, const T* w, const double* p, boo
 int cg_blocks(const Grid& g) { return cg_blocks_of(g); }
 
 template <typename T>
-hipError_t launch_cg_div(const Grid& g, const T* vel, const double* rin, double* r, double* msum, hipStream_t s) {
+hipError_t launch_cg_div(const Grid& g, const T* vel, const double* rin, double* r, double* msum, int mode,
+                         hipStream_t s) {
     const int nblk = cg_blocks_of(g) * g.batch;
     if (g.dim == 3)
-        hipLaunchKernelGGL((k_cg_div<T, 3>), dim3(nblk), dim3(kBlock), 0, s, g, vel, rin, r, msum);
+        hipLaunchKernelGGL((k_cg_div<T, 3>), dim3(nblk), dim3(kBlock), 0, s, g, vel, rin, r, msum, mode);
     else
-        hipLaunchKernelGGL((k_cg_div<T, 2>), dim3(nblk), dim3(kBlock), 0, s, g, vel, rin, r, msum);
+        hipLaunchKernelGGL((k_cg_div<T, 2>), dim3(nblk), dim3(kBlock), 0, s, g, vel, rin, r, msum, mode);
     return hipGetLastError();
 }
 
-hipError_t launch_cg_init(const Grid& g, double* r, double* x, const double* msum, double* rb0, CgScal* st,
-                          hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_init, dim3(cg_blocks_of(g) * g.batch), dim3(kBlock), 0, s, g, r, x, msum, rb0, st);
+hipError_t launch_cg_init(const Grid& g, double* r, double* x, const double* msum, double* rb0, CgScal* st, int mode,
+                          double wsum, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_init, dim3(cg_blocks_of(g) * g.batch), dim3(kBlock), 0, s, g, r, x, msum, rb0, st, mode,
+                       wsum);
     return hipGetLastError();
 }
 
@@ -900,19 +1123,28 @@ hipError_t launch_cg_finish(const Grid& g, const double* rb, CgScal* st, hipStre
     return hipGetLastError();
 }
 
-#define INS_WALL_INSTANTIATE(T)                                                                                         \
-    template hipError_t launch_wall_rhs<T>(const Grid&, const T*, T*, hipStream_t);                                     \
-    template hipError_t launch_wall_divergence<T>(const Grid&, const T*, double*, hipStream_t);                         \
-    template hipError_t launch_wall_gradient<T>(const Grid&, const double*, T*, hipStream_t);                           \
-    template hipError_t launch_wall_project<T>(const Grid&, const T*, const double*, T*, hipStream_t);                  \
-    template hipError_t launch_wall_rhs_vjp<T>(const Grid&, const T*, const T*, T*, hipStream_t);                       \
-    template hipError_t launch_wall_div_vjp<T>(const Grid&, const double*, T*, hipStream_t);                            \
-    template hipError_t launch_wall_grad_vjp<T>(const Grid&, const T*, double*, hipStream_t);                           \
-    template hipError_t launch_wall_stage<T>(const Grid&, const T*, const double*, bool, const T*, T*, bool, double,    \
-                                             T*, double, hipStream_t);                                                  \
-    template hipError_t launch_wall_stage_vjp<T>(const Grid&, const T*, const double*, bool, const T*, const T*,        \
-                                                 const double*, bool, double, double, T*, int, T*, hipStream_t);        \
-    template hipError_t launch_cg_div<T>(const Grid&, const T*, const double*, double*, double*, hipStream_t);
+hipError_t launch_cg_weighted_center(const Grid& g, double* t, double* msum, double wsum, hipStream_t s) {
+    const int nblk = cg_blocks_of(g) * g.batch;
+    hipLaunchKernelGGL(k_cg_wsum, dim3(nblk), dim3(kBlock), 0, s, g, t, msum);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cg_post, dim3(nblk), dim3(kBlock), 0, s, g, t, msum, wsum);
+    return hipGetLastError();
+}
+
+#define INS_WALL_INSTANTIATE(T)                                                                                      \
+    template hipError_t launch_wall_rhs<T>(const Grid&, const T*, T*, hipStream_t);                                  \
+    template hipError_t launch_wall_divergence<T>(const Grid&, const T*, double*, hipStream_t);                      \
+    template hipError_t launch_wall_gradient<T>(const Grid&, const double*, T*, hipStream_t);                        \
+    template hipError_t launch_wall_project<T>(const Grid&, const T*, const double*, T*, bool, hipStream_t);          \
+    template hipError_t launch_wall_rhs_vjp<T>(const Grid&, const T*, const T*, T*, hipStream_t);                    \
+    template hipError_t launch_wall_div_vjp<T>(const Grid&, const double*, T*, hipStream_t);                         \
+    template hipError_t launch_wall_grad_vjp<T>(const Grid&, const T*, double*, hipStream_t);                        \
+    template hipError_t launch_wall_stage<T>(const Grid&, const T*, const double*, bool, const T*, T*, bool, double, \
+                                             T*, double, hipStream_t);                                               \
+    template hipError_t launch_wall_stage_vjp<T>(const Grid&, const T*, const double*, bool, const T*, const T*,     \
+                                                 const double*, bool, double, double, T*, int, T*, hipStream_t);     \
+    template hipError_t launch_cg_div<T>(const Grid&, const T*, const double*, double*, double*, int, hipStream_t);
 
 INS_WALL_INSTANTIATE(double)
 INS_WALL_INSTANTIATE(float)

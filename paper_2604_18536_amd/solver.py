@@ -123,6 +123,17 @@ class Solver:
         """Stopping rule of the channel's conjugate-gradient pressure solves."""
         L.call("ins_cg_set", self._ctx, float(rtol), int(maxiter), int(check_every))
 
+    def set_y_faces(self, faces):
+        """Stretch the channel's y grid: the n_y + 1 face coordinates (host values, increasing)."""
+        import numpy as _np
+
+        f = _np.ascontiguousarray(_np.asarray(faces, dtype=_np.float64))
+        if f.shape != (self.n[1] + 1,):
+            raise ValueError(f"faces must hold n_y + 1 = {self.n[1] + 1} coordinates")
+        self._sync_stream()
+        L.call("ins_set_y_faces", self._ctx, f.ctypes.data_as(C.POINTER(C.c_double)))
+        self.y_faces = f.copy()
+
     def cg_info(self):
         """(iterations, relative residual) of the last pressure solve (maxima over the batch)."""
         self._sync_stream()
