@@ -579,9 +579,3 @@ def step_rk4_vjp(u0, u1bar, h, nu, dt):
 def step_wray3_vjp(u0, u1bar, h, nu, dt):
     return ins.step_wray3_vjp(u0, u1bar, h, nu, dt, rhs_vjp_fn=lambda v, fb: rhs_vjp(v, fb, h, nu),
                               project_vjp_fn=lambda v: project_vjp(v, h), **_fns(h, nu))
-
-
-def tanh_faces(ny, lo, hi, gamma):
-    """y-face coordinates of the hyperbolic-tangent grid (Sec. 2.1 non-uniform grids, eq. tanh-grid)."""
-    t = np.arange(ny + 1) / ny
-    return lo + 0.5 * (hi - lo) * (1.0 + np.tanh(gamma * (2.0 * t - 1.0)) / np.tanh(gamma))

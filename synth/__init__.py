@@ -35,6 +35,7 @@ __all__ = [
     "channel_shear",
     "channel_ic",
     "channel_random",
+    "tanh_faces",
 ]
 
 TWO_PI = 2.0 * math.pi
@@ -345,3 +346,10 @@ def channel_random(n, seed):
     u = random_field(n, seed)
     u[(1, Ellipsis, slice(n[1] - 1, n[1]), slice(None))] = 0.0
     return u
+
+
+def tanh_faces(ny, lo, hi, gamma):
+    """y-face coordinates of the hyperbolic-tangent grid (Sec. 2.1 non-uniform grids,
+    eq. tanh-grid): clustered at both ends, stretching set by gamma > 0."""
+    t = np.arange(ny + 1) / ny
+    return lo + 0.5 * (hi - lo) * (1.0 + np.tanh(gamma * (2.0 * t - 1.0)) / np.tanh(gamma))

@@ -30,7 +30,7 @@ def _gpu():
 
 def _faces(n, gamma=1.4):
     lo, hi = S.channel_box(n)
-    return W.tanh_faces(n[1], lo[1], hi[1], gamma)
+    return S.tanh_faces(n[1], lo[1], hi[1], gamma)
 
 
 def _h(n, gamma=1.4):

@@ -31,7 +31,7 @@ GRIDS = [(6, 7), (4, 6, 3)]
 def _h(n, gamma=1.4):
     lo, hi = S.channel_box(n)
     h = list(S.spacing(n, lo, hi))
-    h[1] = W.tanh_faces(n[1], lo[1], hi[1], gamma)
+    h[1] = S.tanh_faces(n[1], lo[1], hi[1], gamma)
     return tuple(h)
 
 
