@@ -52,14 +52,18 @@
  *
  * Streams. Every call enqueues its kernels on the context's stream
  * (default: the null stream) and returns without a host synchronisation,
- * except where a host scalar is returned (ins_stats, ins_profile_*).
+ * except where a host scalar is returned (ins_stats, ins_profile_*, ins_cg_info),
+ * in ins_set_y_faces, and in the channel's pressure solves, which read their
+ * convergence flags every check_every iterations (ins_cg_set; 0 turns it off).
  *
  * Aliasing. Outputs must not alias inputs, except where an entry point says
  * so. Outputs are overwritten, never accumulated into.
  *
  * Errors. Every entry point returns an ins_status and never throws or
  * aborts. INS_ERR_INVALID: null pointer, bad size or parameter.
- * INS_ERR_UNSUPPORTED: a grid the FFT cannot take (see ins_create).
+ * INS_ERR_UNSUPPORTED: a grid the context cannot take (see ins_create), or a
+ * feature the boundary condition lacks (closures and LES helpers on the
+ * channel, CG settings and stretching on the periodic grid).
  * INS_ERR_OOM: device allocation failed. INS_ERR_HIP: a HIP call or kernel
  * launch failed. ins_last_error() returns a thread-local message for the
  * last non-OK status of the calling thread. Faults inside a kernel surface
