@@ -80,9 +80,9 @@ def kernel_bytes(name, n, elem, batch=1):
         # channel grid: conjugate-gradient pressure solve (float64 pressure-point fields)
         "cg_div": (v + S) * N,                    # read w; write r
         "cg_copy": 2 * S * N,
-        "cg_init": 4 * S * N,                     # read r; write r, x, p
-        "cg_apply": 4 * S * N,                    # read r, p_old; write p, q
-        "cg_update": 6 * S * N,                   # read x, p, r, q; write x, r
+        "cg_init": 3 * S * N,                     # read r; write r, x
+        "cg_apply": 5 * S * N,                    # read r, p_old, x; write p, x
+        "cg_update": 3 * S * N,                   # read r, p; write r (A p recomputed)
         "wall_projection": (2 * v + S) * N,       # read w, p; write u
     }
     return table.get(name)

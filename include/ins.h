@@ -125,7 +125,7 @@ typedef struct {
  * points; the spectral solver of Sec. 2.5.1 needs a uniform periodic grid).
  * nu >= 0 is the kinematic viscosity of the diffusion term. Allocates the
  * forward workspace: stage registers (3 velocity fields), pressure, and the
- * half spectrum (periodic) or four CG pressure-point fields (channel). */
+ * half spectrum (periodic) or three CG pressure-point fields (channel). */
 ins_status ins_create(const ins_grid* grid, ins_bc bc, double nu, ins_dtype dtype, ins_ctx* out);
 ins_status ins_destroy(ins_ctx ctx);
 /* stream: a hipStream_t (NULL = null stream). */

@@ -203,15 +203,16 @@ hipError_t launch_cg_div(const Grid& g, const T* vel, const double* rin, double*
 // (mode 3); x = 0; partial sums of r.r into rb0; resets st.it / st.done.
 hipError_t launch_cg_init(const Grid& g, double* r, double* x, const double* msum, double* rb0, CgScal* st, int mode,
                           double wsum, hipStream_t s);
-// Iteration k: stop test from rr_k (partials rbk); pout = r + beta pin (beta =
-// rr_k / rr_{k-1}, partials rbm), q = -D G pout, partial sums of pout.q into pqs.
-hipError_t launch_cg_apply(const Grid& g, const double* r, const double* pin, double* pout, double* q,
-                           const double* rbk, const double* rbm, double* pqs, CgScal* st, int k, double rtol2,
-                           int maxiter, hipStream_t s);
-// Iteration k: x += alpha p, r -= alpha q (alpha = rr_k / p.q), partial sums of r.r into rbn.
-hipError_t launch_cg_update(const Grid& g, double* x, const double* p, double* r, const double* q, const double* rbk,
-                            const double* pqs, double* rbn, CgScal* st, int k, double rtol2, int maxiter,
-                            hipStream_t s);
+// Iteration k: stop test from rr_k (partials rbk); x += alpha_{k-1} p_{k-1}
+// if iteration k - 1 was performed (rr_{k-1} partials rbm, p.q partials pqm,
+// p_{k-1} = pin); unless stopped, pout = r + beta pin (beta = rr_k / rr_{k-1})
+// and partial sums of pout.(A pout) into pqs, A = -Omega_p D G.
+hipError_t launch_cg_apply(const Grid& g, const double* r, const double* pin, double* pout, double* x,
+                           const double* rbk, const double* rbm, const double* pqm, double* pqs, CgScal* st, int k,
+                           double rtol2, int maxiter, hipStream_t s);
+// Iteration k: r -= alpha A p (alpha = rr_k / p.q, A p recomputed from p), partial sums of r.r into rbn.
+hipError_t launch_cg_update(const Grid& g, double* r, const double* p, const double* rbk, const double* pqs,
+                            double* rbn, CgScal* st, int k, double rtol2, int maxiter, hipStream_t s);
 // st.rr / st.relres from the newest rr partials.
 hipError_t launch_cg_finish(const Grid& g, const double* rb, CgScal* st, hipStream_t s);
 // t = w_j (t - mean_w(t)) in place (msum: partial-sum scratch).

@@ -153,8 +153,7 @@ struct ins_ctx_s {
     int cg_check = 16;  // iterations between host convergence checks (0: never; all cg_maxiter launched)
     double* cg_r = nullptr;
     double* cg_p[2] = {nullptr, nullptr};
-    double* cg_q = nullptr;
-    double* cg_part = nullptr;  // partial sums: mean, rr (two generations), p.q; cg_blocks * batch each
+    double* cg_part = nullptr;  // partial sums: mean, rr and p.q (two generations each); cg_blocks * batch each
     ins::CgScal* cg_st = nullptr;
     ins::CgScal* cg_host = nullptr;  // pinned host copy of cg_st
     double* d_ym = nullptr;          // y metrics of the channel grid (Grid::ym)
@@ -395,7 +394,7 @@ void cg_solve(ins_ctx c, const void* vel, const double* r, double* x, int mode) 
     const size_t np = size_t(ins::cg_blocks(g)) * g.batch;
     double* msum = c->cg_part;
     double* rb[2] = {c->cg_part + np, c->cg_part + 2 * np};
-    double* pqs = c->cg_part + 3 * np;
+    double* pq[2] = {c->cg_part + 3 * np, c->cg_part + 4 * np};
     if (vel) {
         with_type(c, [&](auto tag) {
             using T = decltype(tag);
@@ -410,21 +409,25 @@ void cg_solve(ins_ctx c, const void* vel, const double* r, double* x, int mode) 
         return ins::launch_cg_init(g, c->cg_r, x, msum, rb[0], c->cg_st, mode, c->wsum, c->stream);
     });
     const double rtol2 = c->cg_rtol * c->cg_rtol;
+    auto apply = [&](int k) {
+        c->launch("cg_apply", [&] {
+            return ins::launch_cg_apply(g, c->cg_r, c->cg_p[k & 1], c->cg_p[(k + 1) & 1], x, rb[k & 1],
+                                        rb[(k + 1) & 1], pq[(k + 1) & 1], pq[k & 1], c->cg_st, k, rtol2, c->cg_maxiter,
+                                        c->stream);
+        });
+    };
     int k = 0;
     while (k < c->cg_maxiter) {
-        double* pin = c->cg_p[k & 1];
-        double* pout = c->cg_p[(k + 1) & 1];
-        c->launch("cg_apply", [&] {
-            return ins::launch_cg_apply(g, c->cg_r, pin, pout, c->cg_q, rb[k & 1], rb[(k + 1) & 1], pqs, c->cg_st, k,
-                                        rtol2, c->cg_maxiter, c->stream);
-        });
+        apply(k);
         c->launch("cg_update", [&] {
-            return ins::launch_cg_update(g, x, pout, c->cg_r, c->cg_q, rb[k & 1], pqs, rb[(k + 1) & 1], c->cg_st, k,
-                                         rtol2, c->cg_maxiter, c->stream);
+            return ins::launch_cg_update(g, c->cg_r, c->cg_p[(k + 1) & 1], rb[k & 1], pq[k & 1], rb[(k + 1) & 1],
+                                         c->cg_st, k, rtol2, c->cg_maxiter, c->stream);
         });
         ++k;
         if (c->cg_check > 0 && k % c->cg_check == 0 && k < c->cg_maxiter && cg_all_done(c)) break;
     }
+    // every field is stopped at k: this launch only applies the last pending x update
+    apply(k);
     c->launch("cg_finish", [&] { return ins::launch_cg_finish(g, rb[k & 1], c->cg_st, c->stream); });
 }
 
@@ -847,8 +850,7 @@ ins_status ins_create(const ins_grid* grid, ins_bc bc, double nu, ins_dtype dtyp
             c->cg_r = static_cast<double*>(c->alloc(sb));
             c->cg_p[0] = static_cast<double*>(c->alloc(sb));
             c->cg_p[1] = static_cast<double*>(c->alloc(sb));
-            c->cg_q = static_cast<double*>(c->alloc(sb));
-            c->cg_part = static_cast<double*>(c->alloc(4 * size_t(ins::cg_blocks(g)) * g.batch * sizeof(double)));
+            c->cg_part = static_cast<double*>(c->alloc(5 * size_t(ins::cg_blocks(g)) * g.batch * sizeof(double)));
             c->cg_st = static_cast<ins::CgScal*>(c->alloc(size_t(g.batch) * sizeof(ins::CgScal)));
             c->d_ym = static_cast<double*>(c->alloc(5 * size_t(g.ny + 2) * sizeof(double)));
             upload_y_metrics(c, nullptr);

@@ -28,9 +28,13 @@
 // CG (fp64 throughout) on the symmetric A = -Omega_p D G (the pressure-volume
 // scaling, a factor w_j per row, makes it symmetric), from x_0 = 0. One
 // iteration is two fused kernels:
-//   k_cg_apply:  p = r + beta p_old (formed at the stencil points), q = A p,
-//                partial sums of p.q
-//   k_cg_update: alpha = rr / p.q; x += alpha p, r -= alpha q, partial sums of r.r
+//   k_cg_apply:  x += alpha_old p_old (the previous iteration's update, folded
+//                in here since p_old is read anyway), p = r + beta p_old
+//                (formed at the stencil points), partial sums of p.(A p)
+//   k_cg_update: alpha = rr / p.(A p); r -= alpha A p with A p recomputed from
+//                the stored p, partial sums of r.r
+// (8 field sweeps per iteration: apply reads r, p_old, x and writes p, x;
+// update reads r, p and writes r; A p is never stored.)
 // Every scalar (rr, beta, alpha, the stop test) is recomputed in every
 // workgroup from partial sums, so iterations run back to back without the
 // host and results are bitwise reproducible. A stopped field skips the work
@@ -687,31 +691,43 @@ __device__ __forceinline__ double cg_ap2(const Grid& g, const YMetric& M, const 
 
 template <bool FIRST>
 __device__ __forceinline__ double cg_apply2_run(const Grid& g, const CgSplit& c, const double* rb, const double* pb,
-                                                double* pout, double* q, double beta) {
+                                                double* pout, double* x, double beta, double am) {
     const YMetric M(g);
     double acc = 0.0;
     for (int t = c.t0; t < c.t1; ++t) {
-        int x, y, z;
-        if (!cg_cell(g, t, x, y, z)) continue;
-        const int64_t c0 = int64_t(y) * g.nx + x;
+        int cx, y, z;
+        if (!cg_cell(g, t, cx, y, z)) continue;
+        const int64_t c0 = int64_t(y) * g.nx + cx;
         const double pc = cg_dir<FIRST>(rb, pb, c0, beta);
-        const double ap = cg_ap2<FIRST>(g, M, rb, pb, beta, c0, x, y, pc);
+        if (!FIRST && am != 0.0) x[c0] += am * pb[c0];
+        const double ap = cg_ap2<FIRST>(g, M, rb, pb, beta, c0, cx, y, pc);
         pout[c0] = pc;
-        q[c0] = ap;
         acc += pc * ap;
     }
     return acc;
 }
 
-// Iteration k. rr_k from rbk, rr_{k-1} from rbm (k > 0). Unless stopped:
+// Step length of iteration k - 1 if its solution update is still pending
+// (iteration k - 1 was performed: not stopped, p.q > 0), else 0. The update
+// x += alpha_{k-1} p_{k-1} is folded into iteration k's apply kernel (which
+// reads p_{k-1} anyway) or, once stopped, into the first stopped one.
+__device__ __forceinline__ double cg_pending(double rrm, double pqm, double rr0, int k, double rtol2, int maxiter) {
+    if (k == 0 || cg_stopped(rrm, rr0, k - 1, rtol2, maxiter) || !(pqm > 0.0)) return 0.0;
+    return rrm / pqm;
+}
+
+// Iteration k. rr_k from rbk; for k > 0, rr_{k-1} from rbm and p_{k-1}.q_{k-1}
+// from pqm. First x += alpha_{k-1} p_{k-1} if pending; then, unless stopped:
 // p = r + beta p_old with beta = rr_k / rr_{k-1} (p = r at k = 0), formed at
-// every stencil point; q = A p; partial sums of p.q. Workgroup 0 of each field
-// publishes the stop flag (and rr_0 at k = 0). 2D: runs of 64 x 4 tiles.
+// every stencil point and stored; q = A p enters only the partial sums of p.q
+// (pqs). Workgroup 0 of each field publishes the stop flag (and rr_0 at
+// k = 0). 2D: runs of 64 x 4 tiles.
 __global__ __launch_bounds__(kBlock) void k_cg_apply2(Grid g, const double* __restrict__ r,
                                                        const double* __restrict__ pin, double* __restrict__ pout,
-                                                       double* __restrict__ q, const double* __restrict__ rbk,
-                                                       const double* __restrict__ rbm, double* __restrict__ pqs,
-                                                       CgScal* st, int k, double rtol2, int maxiter) {
+                                                       double* __restrict__ x, const double* __restrict__ rbk,
+                                                       const double* __restrict__ rbm, const double* __restrict__ pqm,
+                                                       double* __restrict__ pqs, CgScal* st, int k, double rtol2,
+                                                       int maxiter) {
     __shared__ double sh[kBlock / 64];
     const CgSplit c = cg_split(g);
     const double rrk = field_total(rbk, c, sh);
@@ -721,94 +737,194 @@ __global__ __launch_bounds__(kBlock) void k_cg_apply2(Grid g, const double* __re
         if (k == 0) st[c.b].rr0 = rrk;
         st[c.b].done = stop ? 1 : 0;
     }
-    if (stop) return;
-    const int64_t soff = int64_t(c.b) * g.ncell;
-    double acc;
-    if (k == 0) {
-        acc = cg_apply2_run<true>(g, c, r + soff, pin + soff, pout + soff, q + soff, 0.0);
-    } else {
-        const double beta = rrk / field_total(rbm, c, sh);
-        acc = cg_apply2_run<false>(g, c, r + soff, pin + soff, pout + soff, q + soff, beta);
+    double rrm = 0.0, am = 0.0;
+    if (k > 0) {
+        rrm = field_total(rbm, c, sh);
+        am = cg_pending(rrm, field_total(pqm, c, sh), rr0, k, rtol2, maxiter);
     }
+    const int64_t soff = int64_t(c.b) * g.ncell;
+    if (stop) {
+        if (am != 0.0) {
+            for (int t = c.t0; t < c.t1; ++t) {
+                int cx, cy, cz;
+                if (!cg_cell(g, t, cx, cy, cz)) continue;
+                const int64_t i = cg_index(g, c.b, cx, cy, cz);
+                x[i] += am * pin[i];
+            }
+        }
+        return;
+    }
+    double acc;
+    if (k == 0)
+        acc = cg_apply2_run<true>(g, c, r + soff, pin + soff, pout + soff, x + soff, 0.0, 0.0);
+    else
+        acc = cg_apply2_run<false>(g, c, r + soff, pin + soff, pout + soff, x + soff, rrk / rrm, am);
     const double s = block_sum(acc, sh);
     if (threadIdx.x == 0) pqs[c.slot()] = s;
 }
 
-// 3D: a workgroup of 64 x 8 threads walks one tile column through its
-// z-chunk. p at z - 1, z, z + 1 stays in registers; the x/y neighbours come
-// from a two-plane LDS ring holding each plane of the tile with a one-cell
-// x/y halo (filled by the first 144 threads). Lanes past n_x load the
-// periodic image so the last column's +x neighbour is in place; rows past
-// n_y and halo rows beyond a wall are never read (no y-face there).
+// 2D update: r -= alpha A p with A p recomputed from the stored p.
+__device__ __forceinline__ double cg_update2_run(const Grid& g, const CgSplit& c, const double* p, double* r,
+                                                 double alpha) {
+    const YMetric M(g);
+    double acc = 0.0;
+    for (int t = c.t0; t < c.t1; ++t) {
+        int cx, y, z;
+        if (!cg_cell(g, t, cx, y, z)) continue;
+        const int64_t c0 = int64_t(y) * g.nx + cx;
+        const double pc = p[c0];
+        const double ap = cg_ap2<true>(g, M, p, nullptr, 0.0, c0, cx, y, pc);
+        const double v = r[c0] - alpha * ap;
+        r[c0] = v;
+        acc += v * v;
+    }
+    return acc;
+}
+
+// One 3D CG workgroup: a 64 x 8 tile column of its field, a z-chunk, the
+// thread's cell, its halo cell (threads < 144: x halo then y halo) and the
+// row-scaled coefficients of -Omega_p D G (w_y / h^2 in x and z, 1 / d
+// across the y-faces; no face beyond a wall). Lanes past n_x address the
+// periodic image, so the last column's +x neighbour is in place.
+struct CgTile3 {
+    int x0, y0, z0, z1, lx, ly, y;
+    bool yin, valid, hthr, hal;
+    int hrow, hcol;
+    int64_t plane, own, hal_off;
+    double cx, cz, cyp, cym;
+    __device__ __forceinline__ CgTile3(const Grid& g, const CgSplit& c) {
+        const YMetric M(g);
+        const int cols = cg_cols3(g);
+        const int ntx = (g.nx + kTileX - 1) / kTileX;
+        const int nzc = cg_zchunks(g);
+        const int col = c.blk % cols, zc = c.blk / cols;
+        z0 = int(int64_t(g.nz) * zc / nzc);
+        z1 = int(int64_t(g.nz) * (zc + 1) / nzc);
+        x0 = (col % ntx) * kTileX;
+        y0 = (col / ntx) * kCgTy;
+        lx = threadIdx.x & (kTileX - 1);
+        ly = threadIdx.x / kTileX;
+        const int xw = (x0 + lx) % g.nx;
+        y = y0 + ly;
+        yin = y < g.ny;
+        valid = yin && x0 + lx < g.nx;
+        plane = int64_t(g.nx) * g.ny;
+        const double wy = yin ? M.w(y) : 0.0;
+        cx = wy * g.ih2[0];
+        cz = wy * g.ih2[2];
+        cyp = (yin && y < g.ny - 1) ? M.id(y) : 0.0;
+        cym = (yin && y > 0) ? M.id(y - 1) : 0.0;
+        int hx = 0, hy = 0;
+        hrow = hcol = 0;
+        hal = false;
+        hthr = threadIdx.x < 2 * kCgTy + 2 * kTileX;
+        if (threadIdx.x < 2 * kCgTy) {
+            const int row = threadIdx.x >> 1, side = threadIdx.x & 1;
+            hy = y0 + row;
+            hrow = row + 1;
+            hcol = side ? kTileX + 1 : 0;
+            hx = side ? (x0 + kTileX) % g.nx : (x0 + g.nx - 1) % g.nx;
+            hal = hy < g.ny;
+        } else if (hthr) {
+            const int i = threadIdx.x - 2 * kCgTy;
+            const int side = i / kTileX, cxl = i % kTileX;
+            hy = side ? y0 + kCgTy : y0 - 1;
+            hrow = side ? kCgTy + 1 : 0;
+            hcol = cxl + 1;
+            hx = (x0 + cxl) % g.nx;
+            hal = hy >= 0 && hy < g.ny;
+        }
+        own = int64_t(y) * g.nx + xw;
+        hal_off = int64_t(hy) * g.nx + hx;
+    }
+    // A p at plane z of the centre, from the LDS plane and the z neighbours.
+    __device__ __forceinline__ double ap(const double (*P)[kTileX + 2], double pm, double pc, double pp) const {
+        double a = (2.0 * pc - P[ly + 1][lx] - P[ly + 1][lx + 2]) * cx;
+        a += (pc - P[ly][lx + 1]) * cym + (pc - P[ly + 2][lx + 1]) * cyp;
+        return a + (2.0 * pc - pm - pp) * cz;
+    }
+    __device__ __forceinline__ int64_t cell(const Grid& g, int z) const {
+        return int64_t(z) * plane + int64_t(y) * g.nx + x0 + lx;
+    }
+};
+
+// 3D apply: each thread walks its (x, y) along the z-chunk with p at z - 1,
+// z, z + 1 in registers and the x/y neighbours in a two-plane LDS ring; p_old
+// at the centre rides along for the pending solution update.
 template <bool FIRST>
 __device__ __forceinline__ double cg_apply3_run(const Grid& g, const CgSplit& c, const double* __restrict__ r,
                                                 const double* __restrict__ pin, double* __restrict__ pout,
-                                                double* __restrict__ q, double beta,
+                                                double* __restrict__ x, double beta, double am,
                                                 double (*pl)[kCgTy + 2][kTileX + 2]) {
-    const YMetric M(g);
-    const int cols = cg_cols3(g);
-    const int ntx = (g.nx + kTileX - 1) / kTileX;
-    const int nzc = cg_zchunks(g);
-    const int col = c.blk % cols, zc = c.blk / cols;
-    const int z0 = int(int64_t(g.nz) * zc / nzc), z1 = int(int64_t(g.nz) * (zc + 1) / nzc);
-    const int x0 = (col % ntx) * kTileX, y0 = (col / ntx) * kCgTy;
-    const int lx = threadIdx.x & (kTileX - 1), ly = threadIdx.x / kTileX;
-    const int xw = (x0 + lx) % g.nx;
-    const int y = y0 + ly;
-    const bool yin = y < g.ny;
-    const bool valid = yin && x0 + lx < g.nx;
-    const int64_t plane = int64_t(g.nx) * g.ny;
-    // scaled coefficients of this row: w_y / h^2 in x and z, 1 / d across the y-faces
-    const double wy = yin ? M.w(y) : 0.0;
-    const double cx = wy * g.ih2[0], cz = wy * g.ih2[2];
-    const double cyp = (yin && y < g.ny - 1) ? M.id(y) : 0.0;
-    const double cym = (yin && y > 0) ? M.id(y - 1) : 0.0;
-    // halo cell of this thread (threads < 144)
-    int hx = 0, hy = 0, hrow = 0, hcol = 0;
-    bool hal = false;
-    const bool hthr = threadIdx.x < 2 * kCgTy + 2 * kTileX;
-    if (threadIdx.x < 2 * kCgTy) {
-        const int row = threadIdx.x >> 1, side = threadIdx.x & 1;
-        hy = y0 + row;
-        hrow = row + 1;
-        hcol = side ? kTileX + 1 : 0;
-        hx = side ? (x0 + kTileX) % g.nx : (x0 + g.nx - 1) % g.nx;
-        hal = hy < g.ny;
-    } else if (hthr) {
-        const int i = threadIdx.x - 2 * kCgTy;
-        const int side = i / kTileX, cxl = i % kTileX;
-        hy = side ? y0 + kCgTy : y0 - 1;
-        hrow = side ? kCgTy + 1 : 0;
-        hcol = cxl + 1;
-        hx = (x0 + cxl) % g.nx;
-        hal = hy >= 0 && hy < g.ny;
+    const CgTile3 t(g, c);
+    const int zm0 = t.z0 == 0 ? g.nz - 1 : t.z0 - 1;
+    double pm = t.yin ? cg_dir<FIRST>(r, pin, int64_t(zm0) * t.plane + t.own, beta) : 0.0;
+    double oc = 0.0, pc = 0.0;
+    if (t.yin) {
+        const int64_t j = int64_t(t.z0) * t.plane + t.own;
+        oc = FIRST ? 0.0 : pin[j];
+        pc = FIRST ? r[j] : r[j] + beta * oc;
     }
-    const int64_t own = int64_t(y) * g.nx + xw;
-    const int64_t hal_off = int64_t(hy) * g.nx + hx;
-    const int zm0 = z0 == 0 ? g.nz - 1 : z0 - 1;
-    double pm = yin ? cg_dir<FIRST>(r, pin, int64_t(zm0) * plane + own, beta) : 0.0;
-    double pc = yin ? cg_dir<FIRST>(r, pin, int64_t(z0) * plane + own, beta) : 0.0;
-    pl[0][ly + 1][lx + 1] = pc;
-    if (hthr) pl[0][hrow][hcol] = hal ? cg_dir<FIRST>(r, pin, int64_t(z0) * plane + hal_off, beta) : 0.0;
+    pl[0][t.ly + 1][t.lx + 1] = pc;
+    if (t.hthr) pl[0][t.hrow][t.hcol] = t.hal ? cg_dir<FIRST>(r, pin, int64_t(t.z0) * t.plane + t.hal_off, beta) : 0.0;
     __syncthreads();
     int cur = 0;
     double acc = 0.0;
-    for (int z = z0; z < z1; ++z) {
+    for (int z = t.z0; z < t.z1; ++z) {
         const int zp = z == g.nz - 1 ? 0 : z + 1;
-        const double pp = yin ? cg_dir<FIRST>(r, pin, int64_t(zp) * plane + own, beta) : 0.0;
-        const double hv = (hthr && hal) ? cg_dir<FIRST>(r, pin, int64_t(zp) * plane + hal_off, beta) : 0.0;
-        if (valid) {
-            double ap = (2.0 * pc - pl[cur][ly + 1][lx] - pl[cur][ly + 1][lx + 2]) * cx;
-            ap += (pc - pl[cur][ly][lx + 1]) * cym + (pc - pl[cur][ly + 2][lx + 1]) * cyp;
-            ap += (2.0 * pc - pm - pp) * cz;
-            const int64_t c0 = int64_t(z) * plane + int64_t(y) * g.nx + x0 + lx;
+        double op = 0.0, pp = 0.0;
+        if (t.yin) {
+            const int64_t j = int64_t(zp) * t.plane + t.own;
+            op = FIRST ? 0.0 : pin[j];
+            pp = FIRST ? r[j] : r[j] + beta * op;
+        }
+        const double hv = (t.hthr && t.hal) ? cg_dir<FIRST>(r, pin, int64_t(zp) * t.plane + t.hal_off, beta) : 0.0;
+        if (t.valid) {
+            const double ap = t.ap(pl[cur], pm, pc, pp);
+            const int64_t c0 = t.cell(g, z);
+            if (!FIRST && am != 0.0) x[c0] += am * oc;
             pout[c0] = pc;
-            q[c0] = ap;
             acc += pc * ap;
         }
         const int nxt = cur ^ 1;
-        pl[nxt][ly + 1][lx + 1] = pp;
-        if (hthr) pl[nxt][hrow][hcol] = hv;
+        pl[nxt][t.ly + 1][t.lx + 1] = pp;
+        if (t.hthr) pl[nxt][t.hrow][t.hcol] = hv;
+        __syncthreads();
+        cur = nxt;
+        pm = pc;
+        pc = pp;
+        oc = op;
+    }
+    return acc;
+}
+
+// 3D update: the same walk over the stored p; r -= alpha A p at the centre.
+__device__ __forceinline__ double cg_update3_run(const Grid& g, const CgSplit& c, const double* __restrict__ p,
+                                                 double* __restrict__ r, double alpha,
+                                                 double (*pl)[kCgTy + 2][kTileX + 2]) {
+    const CgTile3 t(g, c);
+    const int zm0 = t.z0 == 0 ? g.nz - 1 : t.z0 - 1;
+    double pm = t.yin ? p[int64_t(zm0) * t.plane + t.own] : 0.0;
+    double pc = t.yin ? p[int64_t(t.z0) * t.plane + t.own] : 0.0;
+    pl[0][t.ly + 1][t.lx + 1] = pc;
+    if (t.hthr) pl[0][t.hrow][t.hcol] = t.hal ? p[int64_t(t.z0) * t.plane + t.hal_off] : 0.0;
+    __syncthreads();
+    int cur = 0;
+    double acc = 0.0;
+    for (int z = t.z0; z < t.z1; ++z) {
+        const int zp = z == g.nz - 1 ? 0 : z + 1;
+        const double pp = t.yin ? p[int64_t(zp) * t.plane + t.own] : 0.0;
+        const double hv = (t.hthr && t.hal) ? p[int64_t(zp) * t.plane + t.hal_off] : 0.0;
+        if (t.valid) {
+            const double ap = t.ap(pl[cur], pm, pc, pp);
+            const int64_t c0 = t.cell(g, z);
+            const double v = r[c0] - alpha * ap;
+            r[c0] = v;
+            acc += v * v;
+        }
+        const int nxt = cur ^ 1;
+        pl[nxt][t.ly + 1][t.lx + 1] = pp;
+        if (t.hthr) pl[nxt][t.hrow][t.hcol] = hv;
         __syncthreads();
         cur = nxt;
         pm = pc;
@@ -817,19 +933,25 @@ __device__ __forceinline__ double cg_apply3_run(const Grid& g, const CgSplit& c,
     return acc;
 }
 
-__global__ __launch_bounds__(kCgThreads3) void k_cg_apply3(Grid g, const double* __restrict__ r,
-                                                            const double* __restrict__ pin, double* __restrict__ pout,
-                                                            double* __restrict__ q, const double* __restrict__ rbk,
-                                                            const double* __restrict__ rbm, double* __restrict__ pqs,
-                                                            CgScal* st, int k, double rtol2, int maxiter) {
-    __shared__ double sh[kCgThreads3 / 64];
-    __shared__ double pl[2][kCgTy + 2][kTileX + 2];
+__device__ __forceinline__ CgSplit cg_split3(const Grid& g) {
     CgSplit c;
     c.nblk = cg_blocks_of(g);
     const int id = xcd_logical(blockIdx.x, gridDim.x);
     c.b = id / c.nblk;
     c.blk = id - c.b * c.nblk;
     c.t0 = c.t1 = 0;
+    return c;
+}
+
+__global__ __launch_bounds__(kCgThreads3) void k_cg_apply3(Grid g, const double* __restrict__ r,
+                                                            const double* __restrict__ pin, double* __restrict__ pout,
+                                                            double* __restrict__ x, const double* __restrict__ rbk,
+                                                            const double* __restrict__ rbm,
+                                                            const double* __restrict__ pqm, double* __restrict__ pqs,
+                                                            CgScal* st, int k, double rtol2, int maxiter) {
+    __shared__ double sh[kCgThreads3 / 64];
+    __shared__ double pl[2][kCgTy + 2][kTileX + 2];
+    const CgSplit c = cg_split3(g);
     const double rrk = field_total<kCgThreads3>(rbk, c, sh);
     const double rr0 = k == 0 ? rrk : st[c.b].rr0;
     const bool stop = cg_stopped(rrk, rr0, k, rtol2, maxiter);
@@ -837,76 +959,66 @@ __global__ __launch_bounds__(kCgThreads3) void k_cg_apply3(Grid g, const double*
         if (k == 0) st[c.b].rr0 = rrk;
         st[c.b].done = stop ? 1 : 0;
     }
-    if (stop) return;
-    const int64_t soff = int64_t(c.b) * g.ncell;
-    double acc;
-    if (k == 0) {
-        acc = cg_apply3_run<true>(g, c, r + soff, pin + soff, pout + soff, q + soff, 0.0, pl);
-    } else {
-        const double beta = rrk / field_total<kCgThreads3>(rbm, c, sh);
-        acc = cg_apply3_run<false>(g, c, r + soff, pin + soff, pout + soff, q + soff, beta, pl);
+    double rrm = 0.0, am = 0.0;
+    if (k > 0) {
+        rrm = field_total<kCgThreads3>(rbm, c, sh);
+        am = cg_pending(rrm, field_total<kCgThreads3>(pqm, c, sh), rr0, k, rtol2, maxiter);
     }
+    const int64_t soff = int64_t(c.b) * g.ncell;
+    if (stop) {
+        if (am != 0.0) {
+            const CgTile3 t(g, c);
+            if (t.valid)
+                for (int z = t.z0; z < t.z1; ++z) {
+                    const int64_t i = soff + t.cell(g, z);
+                    x[i] += am * pin[i];
+                }
+        }
+        return;
+    }
+    double acc;
+    if (k == 0)
+        acc = cg_apply3_run<true>(g, c, r + soff, pin + soff, pout + soff, x + soff, 0.0, 0.0, pl);
+    else
+        acc = cg_apply3_run<false>(g, c, r + soff, pin + soff, pout + soff, x + soff, rrk / rrm, am, pl);
     const double s = block_sum<kCgThreads3>(acc, sh);
     if (threadIdx.x == 0) pqs[c.slot()] = s;
 }
 
-// Iteration k, unless stopped: alpha = rr_k / p.q, x += alpha p, r -= alpha q,
-// partial sums of r.r (rr_{k+1}) into rbn; a stopped field copies its rr_k
-// partials forward instead, so the newest buffer always holds the final sum.
-// A search direction with p.q <= 0 (no component outside the constants)
-// ends the solve without an update: its partials are written as 0.
-// Pointwise: the workgroups of a field sweep it together (grid stride), two
-// cells per thread and access when the field size is even.
-template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_cg_update(Grid g, double* __restrict__ x, const double* __restrict__ p,
-                                                       double* __restrict__ r, const double* __restrict__ q,
-                                                       const double* __restrict__ rbk, const double* __restrict__ pqs,
-                                                       double* __restrict__ rbn, CgScal* st, int k, double rtol2,
-                                                       int maxiter) {
-    __shared__ double sh[kBlock / 64];
-    const CgSplit c = cg_split(g);
-    const double rrk = field_total(rbk, c, sh);
+// Iteration k, unless stopped: alpha = rr_k / p.q, r -= alpha A p with A p
+// recomputed from the stored p (same stencil, same arithmetic as the apply
+// kernel), partial sums of r.r (rr_{k+1}) into rbn; the matching x update is
+// pending until the next apply kernel. A stopped field copies its rr_k
+// partials forward instead, so the newest buffer always holds the final sum;
+// a search direction with p.q <= 0 (no component outside the constants) ends
+// the solve without an update (partials written as 0).
+template <int NT, int DIM>
+__global__ __launch_bounds__(NT) void k_cg_update(Grid g, double* __restrict__ r, const double* __restrict__ p,
+                                                  const double* __restrict__ rbk, const double* __restrict__ pqs,
+                                                  double* __restrict__ rbn, CgScal* st, int k, double rtol2,
+                                                  int maxiter) {
+    __shared__ double sh[NT / 64];
+    const CgSplit c = DIM == 3 ? cg_split3(g) : cg_split(g);
+    const double rrk = field_total<NT>(rbk, c, sh);
     if (cg_stopped(rrk, st[c.b].rr0, k, rtol2, maxiter)) {
         if (threadIdx.x == 0) rbn[c.slot()] = rbk[c.slot()];
         return;
     }
-    const double pq = field_total(pqs, c, sh);
+    const double pq = field_total<NT>(pqs, c, sh);
     if (!(pq > 0.0)) {
         if (threadIdx.x == 0) rbn[c.slot()] = 0.0;
         return;
     }
     const double alpha = rrk / pq;
-    const int64_t base = int64_t(c.b) * g.ncell;
-    double acc = 0.0;
-    if ((g.ncell & 1) == 0) {
-        const int64_t npair = g.ncell / 2;
-        double2* x2 = reinterpret_cast<double2*>(x + base);
-        const double2* p2 = reinterpret_cast<const double2*>(p + base);
-        double2* r2 = reinterpret_cast<double2*>(r + base);
-        const double2* q2 = reinterpret_cast<const double2*>(q + base);
-        const int64_t stride = int64_t(c.nblk) * kBlock;
-        for (int64_t i = int64_t(c.blk) * kBlock + threadIdx.x; i < npair; i += stride) {
-            const double2 pv = p2[i], qv = q2[i];
-            double2 xv = x2[i], rv = r2[i];
-            xv.x += alpha * pv.x;
-            xv.y += alpha * pv.y;
-            rv.x -= alpha * qv.x;
-            rv.y -= alpha * qv.y;
-            x2[i] = xv;
-            r2[i] = rv;
-            acc += rv.x * rv.x + rv.y * rv.y;
-        }
+    const int64_t soff = int64_t(c.b) * g.ncell;
+    double acc;
+    if constexpr (DIM == 3) {
+        __shared__ double pl[2][kCgTy + 2][kTileX + 2];
+        acc = cg_update3_run(g, c, p + soff, r + soff, alpha, pl);
     } else {
-        const int64_t stride = int64_t(c.nblk) * kBlock;
-        for (int64_t j = int64_t(c.blk) * kBlock + threadIdx.x; j < g.ncell; j += stride) {
-            const int64_t i = base + j;
-            x[i] += alpha * p[i];
-            const double v = r[i] - alpha * q[i];
-            r[i] = v;
-            acc += v * v;
-        }
+        acc = cg_update2_run(g, c, p + soff, r + soff, alpha);
     }
-    const double s = block_sum(acc, sh);
+    const double s = block_sum<NT>(acc, sh);
     if (threadIdx.x == 0) {
         rbn[c.slot()] = s;
         if (c.blk == 0) st[c.b].it = k + 1;
@@ -1092,28 +1204,27 @@ hipError_t launch_cg_init(const Grid& g, double* r, double* x, const double* msu
     return hipGetLastError();
 }
 
-hipError_t launch_cg_apply(const Grid& g, const double* r, const double* pin, double* pout, double* q,
-                           const double* rbk, const double* rbm, double* pqs, CgScal* st, int k, double rtol2,
-                           int maxiter, hipStream_t s) {
+hipError_t launch_cg_apply(const Grid& g, const double* r, const double* pin, double* pout, double* x,
+                           const double* rbk, const double* rbm, const double* pqm, double* pqs, CgScal* st, int k,
+                           double rtol2, int maxiter, hipStream_t s) {
     const int nblk = cg_blocks_of(g) * g.batch;
     if (g.dim == 3)
-        hipLaunchKernelGGL(k_cg_apply3, dim3(nblk), dim3(kCgThreads3), 0, s, g, r, pin, pout, q, rbk, rbm, pqs, st, k,
-                           rtol2, maxiter);
+        hipLaunchKernelGGL(k_cg_apply3, dim3(nblk), dim3(kCgThreads3), 0, s, g, r, pin, pout, x, rbk, rbm, pqm, pqs, st,
+                           k, rtol2, maxiter);
     else
-        hipLaunchKernelGGL(k_cg_apply2, dim3(nblk), dim3(kBlock), 0, s, g, r, pin, pout, q, rbk, rbm, pqs, st, k,
+        hipLaunchKernelGGL(k_cg_apply2, dim3(nblk), dim3(kBlock), 0, s, g, r, pin, pout, x, rbk, rbm, pqm, pqs, st, k,
                            rtol2, maxiter);
     return hipGetLastError();
 }
 
-hipError_t launch_cg_update(const Grid& g, double* x, const double* p, double* r, const double* q, const double* rbk,
-                            const double* pqs, double* rbn, CgScal* st, int k, double rtol2, int maxiter,
-                            hipStream_t s) {
+hipError_t launch_cg_update(const Grid& g, double* r, const double* p, const double* rbk, const double* pqs,
+                            double* rbn, CgScal* st, int k, double rtol2, int maxiter, hipStream_t s) {
     const int nblk = cg_blocks_of(g) * g.batch;
     if (g.dim == 3)
-        hipLaunchKernelGGL((k_cg_update<3>), dim3(nblk), dim3(kBlock), 0, s, g, x, p, r, q, rbk, pqs, rbn, st, k,
-                           rtol2, maxiter);
+        hipLaunchKernelGGL((k_cg_update<kCgThreads3, 3>), dim3(nblk), dim3(kCgThreads3), 0, s, g, r, p, rbk, pqs, rbn,
+                           st, k, rtol2, maxiter);
     else
-        hipLaunchKernelGGL((k_cg_update<2>), dim3(nblk), dim3(kBlock), 0, s, g, x, p, r, q, rbk, pqs, rbn, st, k,
+        hipLaunchKernelGGL((k_cg_update<kBlock, 2>), dim3(nblk), dim3(kBlock), 0, s, g, r, p, rbk, pqs, rbn, st, k,
                            rtol2, maxiter);
     return hipGetLastError();
 }
