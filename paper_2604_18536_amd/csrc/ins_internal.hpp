@@ -192,7 +192,7 @@ struct CgScal {
 };
 // Work split of the CG kernels: workgroups per field (<= kCgMaxBlocks); every
 // partial-sum buffer holds cg_blocks(g) * batch doubles.
-constexpr int kCgMaxBlocks = 2048;
+constexpr int kCgMaxBlocks = 1024;
 int cg_blocks(const Grid& g);
 // mode 0: r = D vel; 1: r = D Omega_u^{-1} vel; 2, 3: r = rin. Partial sums of
 // w_j r (modes 0-2) or r (mode 3) into msum.
