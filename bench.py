@@ -84,6 +84,10 @@ def kernel_bytes(name, n, elem, batch=1):
         "cg_apply": 5 * S * N,                    # read r, p_old, x; write p, x
         "cg_update": 3 * S * N,                   # read r, p; write r (A p recomputed)
         "wall_projection": (2 * v + S) * N,       # read w, p; write u
+        # channel grid: direct solve (x, z FFTs, tridiagonal solves along y)
+        "fft_z_fwd": 2 * C * Ns,
+        "fft_z_inv": 2 * C * Ns,
+        "channel_ysolve": 2 * C * Ns,             # read and write the half spectrum once
     }
     return table.get(name)
 
@@ -141,7 +145,8 @@ def run_mode(n, nu, dt, precision, steps, warmup, u0_np, adjoint, scheme="rk4", 
     if channel is None:
         s = Solver(n, nu=nu, precision=precision)
     else:
-        s = Solver(n, nu=nu, precision=precision, lo=channel["lo"], hi=channel["hi"], bc="walls")
+        s = Solver(n, nu=nu, precision=precision, lo=channel["lo"], hi=channel["hi"], bc="walls",
+                   pressure=channel["pressure"])
         if channel.get("faces") is not None:
             s.set_y_faces(channel["faces"])
         s.cg_set(rtol=channel["rtol"], maxiter=20000, check_every=channel["check"])
@@ -164,7 +169,7 @@ def run_mode(n, nu, dt, precision, steps, warmup, u0_np, adjoint, scheme="rk4", 
             s.step(u0, dt, out=u1, scheme=scheme)
     ms, _ = time_steps(fn, steps, warmup)
     ms_p, prof = time_steps(fn, steps, 1, solver=s)
-    if channel is not None:
+    if channel is not None and channel["pressure"] == "cg":
         channel["iterations_last_solve"] = s.cg_info()[0]
     ok = s.stats(u1)[3]
     ws = s.workspace_bytes()
@@ -175,16 +180,17 @@ def run_mode(n, nu, dt, precision, steps, warmup, u0_np, adjoint, scheme="rk4", 
 
 
 CHANNEL = {"n": (256, 256, 256), "nu": 1.0 / 1000.0, "dt": 1e-3, "seed": 5, "rtol": 1e-8, "check": 16,
-           "gamma": 1.5, "modes": "fp64,fp64_adj_kept,fp32,fp64_tanh"}
+           "gamma": 1.5, "modes": "fp64,fp64_adj,fp64_adj_kept,fp32,fp64_tanh,fp64_tanh_adj,fp64_cg,fp64_tanh_cg"}
 
 
 def channel_timing(steps, warmup, modes=None):
     """Channel flow (no-slip walls at both y ends, x and z periodic) on a 256^3
     grid over [0, 2pi] x [0, 2] x [0, pi]: laminar profile of bulk velocity 1
-    plus a 20% solenoidal perturbation, nu = 1/1000, dt = 1e-3; every pressure
-    solve is matrix-free CG stopped at a relative residual of 1e-8. Mode
-    *_tanh: the same on the tanh-stretched y grid (gamma = 1.5, cells 3x finer
-    at the walls than in the centre)."""
+    plus a 20% solenoidal perturbation, nu = 1/1000, dt = 1e-3. Pressure by the
+    direct solve (FFTs along x and z, tridiagonal solves along y); modes *_cg
+    by matrix-free CG stopped at a relative residual of 1e-8 (timed over at
+    most 2 steps after 1 warmup step). Modes *_tanh: the tanh-stretched y grid
+    (gamma = 1.5, cells 3x finer at the walls than in the centre)."""
     import synth as S
 
     cfg = dict(CHANNEL)
@@ -193,32 +199,40 @@ def channel_timing(steps, warmup, modes=None):
     u0 = S.channel_ic(n, cfg["seed"])
     ncell = n[0] * n[1] * n[2]
     out = {"workload": f"channel {n[0]}x{n[1]}x{n[2]}, walls at y=0,2, nu=1/{round(1 / cfg['nu'])}, "
-                       f"dt={cfg['dt']}, CG rtol={cfg['rtol']:g}", "modes": {}, "kernels": {}}
+                       f"dt={cfg['dt']}, direct pressure solve (CG rtol={cfg['rtol']:g} in *_cg modes)",
+           "modes": {}, "kernels": {}}
     for mode in (modes or cfg["modes"]).split(","):
         precision = "fp64" if mode.startswith("fp64") else "fp32"
         adjoint = "_adj" in mode
-        ch = {"lo": lo, "hi": hi, "rtol": cfg["rtol"], "check": cfg["check"]}
-        if mode.endswith("_tanh"):
+        cg = mode.endswith("_cg")
+        ch = {"lo": lo, "hi": hi, "rtol": cfg["rtol"], "check": cfg["check"], "pressure": "cg" if cg else "fft"}
+        if "_tanh" in mode:
             ch["faces"] = S.tanh_faces(n[1], lo[1], hi[1], cfg["gamma"])
+        k_steps, k_warm = (min(steps, 2), min(warmup, 1)) if cg else (steps, warmup)
         print(f"[bench] channel {mode} starts", file=sys.stderr, flush=True)
-        ms, ms_p, prof, ok, ws = run_mode(n, cfg["nu"], cfg["dt"], precision, steps, warmup, u0, adjoint, "rk4",
+        ms, ms_p, prof, ok, ws = run_mode(n, cfg["nu"], cfg["dt"], precision, k_steps, k_warm, u0, adjoint, "rk4",
                                           mode.endswith("_kept"), ch)
         elem = 8 if precision == "fp64" else 4
         alg = sum(kernel_bytes(k, n, elem) * c for k, (c, t) in prof.items() if kernel_bytes(k, n, elem))
-        applies = prof.get("cg_apply", (0, 0.0))[0] / steps
-        solves = prof.get("cg_init", (0, 0.0))[0] / steps
-        out["modes"][mode] = {
+        rec = {
             "mcell_per_s": round(ncell / (ms * 1e-3) / 1e6, 3),
-            "ms_per_step": round(ms, 2),
-            "cg_solves_per_step": solves,
-            "cg_iterations_per_solve": round(applies / solves, 1) if solves else None,
-            "cg_iterations_last_solve": ch["iterations_last_solve"],
-            "hbm_frac": round(alg / steps / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+            "ms_per_step": round(ms, 3),
+            "steps": k_steps,
+            "pressure": ch["pressure"],
+            "alg_bytes_per_cell": round(alg / k_steps / ncell, 1),
+            "hbm_frac": round(alg / k_steps / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
             "finite": bool(ok),
             "workspace_gb": round(ws / 1e9, 3),
         }
+        if cg:
+            applies = prof.get("cg_apply", (0, 0.0))[0] / k_steps
+            solves = prof.get("cg_init", (0, 0.0))[0] / k_steps
+            rec["cg_solves_per_step"] = solves
+            rec["cg_iterations_per_solve"] = round(applies / solves, 1) if solves else None
+            rec["cg_iterations_last_solve"] = ch["iterations_last_solve"]
+        out["modes"][mode] = rec
         out["kernels"][mode] = {
-            k: {"launches_per_step": c / steps, "avg_ms": round(t / c, 5),
+            k: {"launches_per_step": c / k_steps, "avg_ms": round(t / c, 5),
                 "gbs": round(kernel_bytes(k, n, elem) / (t / c * 1e-3) / 1e9, 1) if kernel_bytes(k, n, elem) else None}
             for k, (c, t) in prof.items()
         }
@@ -387,7 +401,7 @@ def main():
     ap.add_argument("--n", type=int, default=None, help="override the grid size of the config")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-les", action="store_true", help="skip the closure-LES and small-grid timings")
-    ap.add_argument("--no-channel", action="store_true", help="skip the channel (wall-bounded, CG) timing")
+    ap.add_argument("--no-channel", action="store_true", help="skip the channel (wall-bounded) timing")
     ap.add_argument("--modes", default=None)
     args = ap.parse_args()
     if args.config == "channel256":
@@ -478,7 +492,7 @@ def main():
     cpu = None if args.no_cpu else cpu_baseline(n, nu, dt, u0)
     les = None if args.no_les or args.config != "turb256" else les_closure_timing(args.steps, args.warmup)
     small = None if args.no_les or args.config != "turb256" else small_grid_timing(50)
-    channel = None if args.no_channel or args.config != "turb256" else channel_timing(2, 1)
+    channel = None if args.no_channel or args.config != "turb256" else channel_timing(args.steps, args.warmup)
     ms = modes[main_mode]["ms_per_step"]
     line = {
         "metric": METRIC,

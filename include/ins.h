@@ -53,7 +53,7 @@
  * Streams. Every call enqueues its kernels on the context's stream
  * (default: the null stream) and returns without a host synchronisation,
  * except where a host scalar is returned (ins_stats, ins_profile_*, ins_cg_info),
- * in ins_set_y_faces, and in the channel's pressure solves, which read their
+ * in ins_set_y_faces, and in the channel's CG pressure solves, which read their
  * convergence flags every check_every iterations (ins_cg_set; 0 turns it off).
  *
  * Aliasing. Outputs must not alias inputs, except where an entry point says
@@ -96,7 +96,9 @@ typedef enum { INS_FP64 = 0, INS_FP32 = 1 } ins_dtype;
 /* INS_BC_PERIODIC: periodic in every direction; pressure by FFT.
  * INS_BC_WALLS_Y:  channel: no-slip walls at both y ends (Sec. 2.1 Dirichlet
  *   condition u = 0 imposed through ghost volumes), x and z periodic;
- *   pressure by matrix-free conjugate gradients (Sec. 2.5.1 iterative solver).
+ *   pressure by a direct solve (FFTs along x and z, a tridiagonal solve along
+ *   y per mode) or by matrix-free conjugate gradients (Sec. 2.5.1 iterative
+ *   solver); see ins_set_pressure_solver.
  *   The layout is unchanged: u^y[..][n_y - 1][..] is the upper-wall face, a
  *   boundary value, not an unknown. Every operator reads it (and the lower-wall
  *   face) as 0 and every velocity output, forward or pullback, writes 0 there.
@@ -124,8 +126,9 @@ typedef struct {
  * primes 2, 3, 5, 7 (the real-to-complex FFT along x works on n_x/2 complex
  * points; the spectral solver of Sec. 2.5.1 needs a uniform periodic grid).
  * nu >= 0 is the kinematic viscosity of the diffusion term. Allocates the
- * forward workspace: stage registers (3 velocity fields), pressure, and the
- * half spectrum (periodic) or three CG pressure-point fields (channel). */
+ * forward workspace: stage registers (3 velocity fields), pressure, the half
+ * spectrum (periodic grid, and the channel when its direct solver applies) and
+ * three CG pressure-point fields (channel). */
 ins_status ins_create(const ins_grid* grid, ins_bc bc, double nu, ins_dtype dtype, ins_ctx* out);
 ins_status ins_destroy(ins_ctx ctx);
 /* stream: a hipStream_t (NULL = null stream). */
@@ -135,10 +138,25 @@ ins_status ins_workspace_bytes(ins_ctx ctx, size_t* bytes);
 const char* ins_last_error(void);
 
 /* ---------------------------------------------------------------------------
- * Channel grid (INS_BC_WALLS_Y): conjugate-gradient pressure solve
+ * Channel grid (INS_BC_WALLS_Y): pressure solvers
  *
- * Every pressure solve (ins_poisson_solve, ins_project, the steps and their
- * pullbacks) runs CG on A = -D G, the Laplace operator applied as the
+ * Both solvers return the same discrete solution, the zero-mean p with
+ * D G p = r - mean_w(r) (the augmented system of the direct solver of
+ * Sec. 2.5.1), up to rounding (direct) or up to the CG stopping rule.
+ *
+ * INS_PRESSURE_FFT (the default when it applies: n_x even, n_x/2 and n_z
+ * products of 2, 3, 5, 7, n_y <= 2048): FFTs along the periodic x and z leave
+ * one tridiagonal system along y per wavenumber pair (the Neumann second
+ * difference across the y widths, shifted by the periodic eigenvalue
+ * 4 sin^2(pi k / n) / h^2 of Sec. 2.5.1), solved exactly; the (0, 0) mode is
+ * the singular Neumann problem, solved with its weighted mean removed and its
+ * solution centred. On a uniform y this is the paper's channel solver (FFTs
+ * and a type-II cosine transform, Sec. 5, which diagonalises the same
+ * operator); it also holds on a stretched y. No host synchronisation; the
+ * spectrum is the only workspace.
+ *
+ * INS_PRESSURE_CG: every pressure solve (ins_poisson_solve, ins_project, the
+ * steps and their pullbacks) runs CG on A = -D G, the Laplace operator applied as the
  * divergence of the gradient without assembling it (Sec. 2.5.1 iterative
  * solver), from p = 0, for A p = mean(r) - r, independently per batch field.
  * A field stops once ||res|| <= rtol ||res_0|| (res the recursively updated
@@ -178,8 +196,20 @@ ins_status ins_set_y_faces(ins_ctx ctx, const double* faces);
  * check_every < 0. */
 ins_status ins_cg_set(ins_ctx ctx, double rtol, int maxiter, int check_every);
 /* Iterations and final relative residual ||res|| / ||res_0|| of the last
- * solve (maxima over the batch). Synchronises the context's stream. */
+ * CG solve (maxima over the batch; 0 and 0 before the first). Synchronises
+ * the context's stream. */
 ins_status ins_cg_info(ins_ctx ctx, int* iterations, double* relres);
+
+typedef enum { INS_PRESSURE_AUTO = 0, INS_PRESSURE_FFT = 1, INS_PRESSURE_CG = 2 } ins_pressure;
+
+/* Choose the pressure solver (an ins_pressure value) for every later call.
+ * INS_PRESSURE_AUTO: FFT where it applies, else CG (the default). Periodic
+ * grid: only FFT (INS_PRESSURE_CG gives INS_ERR_UNSUPPORTED). Channel:
+ * INS_PRESSURE_FFT gives INS_ERR_UNSUPPORTED when the sizes above rule it out.
+ * INS_ERR_INVALID for any other value. */
+ins_status ins_set_pressure_solver(ins_ctx ctx, int solver);
+/* The solver in use: INS_PRESSURE_FFT or INS_PRESSURE_CG. */
+ins_status ins_get_pressure_solver(ins_ctx ctx, int* solver);
 
 /* ---------------------------------------------------------------------------
  * Forward operators (App. B kernels; Sec. 2.5)

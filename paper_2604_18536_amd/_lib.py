@@ -18,6 +18,9 @@ INS_BC_PERIODIC = 0
 INS_BC_WALLS_Y = 1
 INS_RK4 = 0
 INS_WRAY3 = 1
+INS_PRESSURE_AUTO = 0
+INS_PRESSURE_FFT = 1
+INS_PRESSURE_CG = 2
 
 _STATUS_NAMES = {
     INS_ERR_INVALID: "INS_ERR_INVALID",
@@ -68,6 +71,8 @@ _SIGS = {
     "ins_cg_set": ([_P, _D, C.c_int, C.c_int]),
     "ins_set_y_faces": ([_P, C.POINTER(C.c_double)]),
     "ins_cg_info": ([_P, C.POINTER(C.c_int), C.POINTER(C.c_double)]),
+    "ins_set_pressure_solver": ([_P, C.c_int]),
+    "ins_get_pressure_solver": ([_P, C.POINTER(C.c_int)]),
     "ins_step_vjp_saved": ([_P, C.c_int, _P, _P, _P, _P, _P, _D]),
     "ins_scheme_stage_count": ([C.c_int]),
     "ins_eddy_set": ([_P, _D, _D]),

@@ -104,6 +104,22 @@ hipError_t launch_fft_x_inv(const Grid& g, const cd* spec, double* p, const FftP
 hipError_t launch_fft_strided(const Grid& g, cd* spec, const FftPlan& pl, const FftPlan& rev, int axis, int mode,
                               int lines, const SolveTab& st, hipStream_t s);
 
+// Channel grid, direct pressure solve (x, z FFTs + one tridiagonal system
+// along y per wavenumber pair). Forward x pass whose rows are the channel
+// divergence D vel (scaled: D Omega_u^{-1} vel).
+template <typename T>
+hipError_t launch_fft_x_fwd_wall(const Grid& g, const T* vel, bool scaled, cd* spec, const FftPlan& px, const cd* post_tw,
+                                 int lines, hipStream_t s);
+// Tridiagonal solves along y of the half spectrum [batch][n_z][n_y][n_x/2+1]
+// (in place), each mode's solution multiplied by `scale`; lamx, lamz the
+// periodic eigenvalues 4 sin^2(pi k / n) / h^2, wysum = sum_j w_j. adj: the
+// transpose of the solve map.
+hipError_t launch_channel_ysolve(const Grid& g, cd* spec, const double* lamx, const double* lamz, double wysum,
+                                 double scale, bool adj, hipStream_t s);
+// Segments per line (return) and rows per segment bound (mr) of that solve.
+int channel_ysolve_segments(int ny, int& mr);
+constexpr int kChannelDirectMaxNy = 2048;
+
 // Reverse-pass kernels.
 template <typename T>
 hipError_t launch_rhs_vjp(const Grid& g, const T* u, const T* fbar, T* ubar, hipStream_t s);

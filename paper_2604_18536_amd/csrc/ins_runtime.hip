@@ -145,7 +145,12 @@ struct ins_ctx_s {
     int device = 0;
     hipStream_t stream = nullptr;
 
-    bool walls = false;  // no-slip walls at both y ends (INS_BC_WALLS_Y): CG pressure solve
+    bool walls = false;  // no-slip walls at both y ends (INS_BC_WALLS_Y)
+    // channel pressure solver: direct (x, z FFTs + tridiagonal solves along y,
+    // when the sizes allow it) or conjugate gradients
+    bool direct_ok = false;
+    bool use_direct = false;
+    double wy = 0.0;  // sum_j w_j (the channel height)
 
     // conjugate-gradient solve of the channel grid
     double cg_rtol = 1e-10;
@@ -366,6 +371,7 @@ void upload_y_metrics(ins_ctx c, const double* faces) {
     hip_check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
     hip_check(hipMemcpy(c->d_ym, m.data(), m.size() * sizeof(double), hipMemcpyHostToDevice), "upload y metrics");
     c->wsum = sw * double(g.nx) * double(g.nz);
+    c->wy = sw;
     g.ym = c->d_ym;
 }
 
@@ -431,12 +437,46 @@ void cg_solve(ins_ctx c, const void* vel, const double* r, double* x, int mode) 
     c->launch("cg_finish", [&] { return ins::launch_cg_finish(g, rb[k & 1], c->cg_st, c->stream); });
 }
 
+// Channel grid, direct solve: x = the zero-mean solution of D G x = r' with r'
+// = r - mean_w(r), r the divergence of vel or given. Modes as for cg_solve
+// (0: D vel, 1: D Omega_u^{-1} vel, 2: r, 3: the transpose of mode 2's map).
+// Forward FFTs along x (fused with the divergence) and z, one tridiagonal
+// solve along y per wavenumber pair, inverse FFTs.
+void direct_solve(ins_ctx c, const void* vel, const double* r, double* x, int mode) {
+    const ins::Grid& g = c->g;
+    if (vel) {
+        with_type(c, [&](auto tag) {
+            using T = decltype(tag);
+            c->launch("fft_x_fwd_div", [&] {
+                return ins::launch_fft_x_fwd_wall<T>(g, static_cast<const T*>(vel), mode == 1, c->spec, c->px,
+                                                     c->d_post, c->lnl_x, c->stream);
+            });
+        });
+    } else {
+        c->launch("fft_x_fwd", [&] {
+            return ins::launch_fft_x_fwd<double>(g, nullptr, r, c->spec, c->px, c->d_post, c->lnl_x, c->stream);
+        });
+    }
+    if (g.dim == 3)
+        c->launch("fft_z_fwd", [&] { return ins::launch_fft_strided(g, c->spec, c->pz, c->pz, 2, 0, c->lnl_z, c->st, c->stream); });
+    const double scale = 1.0 / (double(g.nx) * double(g.nz));
+    c->launch("channel_ysolve", [&] {
+        return ins::launch_channel_ysolve(g, c->spec, c->st.lam[0], c->st.lam[2], c->wy, scale, mode == 3, c->stream);
+    });
+    if (g.dim == 3)
+        c->launch("fft_z_inv", [&] { return ins::launch_fft_strided(g, c->spec, c->pz, c->pz, 2, 1, c->lnl_z, c->st, c->stream); });
+    c->launch("fft_x_inv", [&] { return ins::launch_fft_x_inv(g, c->spec, x, c->px, c->d_post, c->lnl_x, c->stream); });
+}
+
 // p = (D G)^-1 of the divergence of vel (vel != null) or of r. adj (channel):
 // the solve inside the transposed projection, of D Omega_u^{-1} vel.
 void poisson(ins_ctx c, const void* vel, const double* r, double* p, bool adj = false) {
     const ins::Grid& g = c->g;
     if (c->walls) {
-        cg_solve(c, vel, r, p, vel ? (adj ? 1 : 0) : 2);
+        if (c->use_direct)
+            direct_solve(c, vel, r, p, vel ? (adj ? 1 : 0) : 2);
+        else
+            cg_solve(c, vel, r, p, vel ? (adj ? 1 : 0) : 2);
         return;
     }
     if (vel) {
@@ -798,6 +838,78 @@ extern "C" {
 
 const char* ins_last_error(void) { return g_last_error.c_str(); }
 
+// FFT plans (x works on n_x/2 complex points), twiddles, the x untangling
+// factors and the per-direction eigenvalues 4 sin^2(pi k / n) / h^2. Periodic
+// grid: x, y, z passes and the fused solve along the last axis (its inverse
+// runs the radices reversed). Channel: x and z passes only; returns false when
+// a length does not fit a workgroup (the periodic grid raises instead).
+bool setup_fft(ins_ctx c, const std::vector<int>& rx, const std::vector<int>& ry, const std::vector<int>& rz,
+               bool channel) {
+    ins::Grid& g = c->g;
+    const int d = g.dim;
+    std::vector<cd> tw;
+    build_twiddles(g.nx / 2, rx, tw, c->px);
+    if (!channel) build_twiddles(g.ny, ry, tw, c->py);
+    if (d == 3) build_twiddles(g.nz, rz, tw, c->pz);
+    c->lnl_x = choose_lines(c->px, 16, 8, 1024);
+    c->lnl_y = channel ? 0 : choose_lines(c->py, 16, 8, 512);
+    c->lnl_z = d == 3 ? choose_lines(c->pz, 16, 8, 512) : 0;
+    if (!channel) {
+        ins::FftPlan& last = d == 3 ? c->pz : c->py;
+        ins::FftPlan& rev = d == 3 ? c->pz_rev : c->py_rev;
+        std::vector<int> rr(d == 3 ? rz : ry);
+        std::reverse(rr.begin(), rr.end());
+        build_twiddles(last.n, rr, tw, rev);
+        rev.vm = last.vm;
+        rev.pad = last.pad;
+        rev.nth = last.nth;
+    }
+    if (c->lnl_x < 0 || c->lnl_y < 0 || c->lnl_z < 0) {
+        if (channel) return false;
+        raise(INS_ERR_UNSUPPORTED, "FFT length too long");
+    }
+
+    const long double two_pi = 6.283185307179586476925286766559005768L;
+    std::vector<cd> post(g.nx / 2 + 1);
+    for (int k = 0; k <= g.nx / 2; ++k) {
+        const long double ang = -two_pi * k / static_cast<long double>(g.nx);
+        post[k] = cd{double(cosl(ang)), double(sinl(ang))};
+    }
+    // 4 sin^2(pi k / n) / h^2 per direction (Sec. 2.5.1 transfer function);
+    // the channel's y entries are unused.
+    std::vector<double> lam;
+    size_t off[3] = {0, 0, 0};
+    const int cnt[3] = {g.nx / 2 + 1, g.ny, d == 3 ? g.nz : 1};
+    const int nn[3] = {g.nx, g.ny, g.nz};
+    for (int a = 0; a < 3; ++a) {
+        off[a] = lam.size();
+        for (int k = 0; k < cnt[a]; ++k) {
+            if (a >= d) {
+                lam.push_back(0.0);
+                continue;
+            }
+            const long double s = sinl(two_pi * 0.5L * k / static_cast<long double>(nn[a]));
+            lam.push_back(double(4.0L * s * s * static_cast<long double>(g.ih2[a])));
+        }
+    }
+    c->d_tw = static_cast<cd*>(c->alloc(std::max<size_t>(tw.size(), 1) * sizeof(cd)));
+    c->d_post = static_cast<cd*>(c->alloc(post.size() * sizeof(cd)));
+    c->d_lam = static_cast<double*>(c->alloc(lam.size() * sizeof(double)));
+    hip_check(hipMemcpy(c->d_tw, tw.data(), tw.size() * sizeof(cd), hipMemcpyHostToDevice), "upload twiddles");
+    hip_check(hipMemcpy(c->d_post, post.data(), post.size() * sizeof(cd), hipMemcpyHostToDevice), "upload twiddles");
+    hip_check(hipMemcpy(c->d_lam, lam.data(), lam.size() * sizeof(double), hipMemcpyHostToDevice), "upload eigenvalues");
+    c->px.tw = c->d_tw;
+    c->py.tw = c->d_tw;
+    c->pz.tw = c->d_tw;
+    c->py_rev.tw = c->d_tw;
+    c->pz_rev.tw = c->d_tw;
+    for (int a = 0; a < 3; ++a) c->st.lam[a] = c->d_lam + off[a];
+    c->st.inv_ncell = 1.0 / double(g.ncell);
+    const size_t nxh = size_t(g.nx / 2 + 1);
+    c->spec = static_cast<cd*>(c->alloc(size_t(g.batch) * g.nz * g.ny * nxh * sizeof(cd)));
+    return true;
+}
+
 ins_status ins_create(const ins_grid* grid, ins_bc bc, double nu, ins_dtype dtype, ins_ctx* out) {
     if (out) *out = nullptr;
     ins_ctx_s* c = nullptr;
@@ -863,69 +975,17 @@ ins_status ins_create(const ins_grid* grid, ins_bc bc, double nu, ins_dtype dtyp
             c->wb = c->alloc(c->vel_bytes());
             c->nstat = ins::stats_blocks(g);
             c->partials = static_cast<double*>(c->alloc(size_t(c->nstat) * 4 * sizeof(double)));
+            // direct solver: n_x even with n_x / 2 and n_z products of 2, 3, 5, 7
+            if (g.nx % 2 == 0 && g.nx >= 4 && factor(g.nx / 2, rx) && (d == 2 || factor(g.nz, rz)) &&
+                g.ny <= ins::kChannelDirectMaxNy)
+                c->direct_ok = setup_fft(c, rx, ry, rz, true);
+            c->use_direct = c->direct_ok;
             hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
             *out = c;
             return;
         }
 
-        // FFT plans: x works on n_x/2 complex points.
-        std::vector<cd> tw;
-        build_twiddles(g.nx / 2, rx, tw, c->px);
-        build_twiddles(g.ny, ry, tw, c->py);
-        if (d == 3) build_twiddles(g.nz, rz, tw, c->pz);
-        c->lnl_x = choose_lines(c->px, 16, 8, 1024);
-        c->lnl_y = choose_lines(c->py, 16, 8, 512);
-        c->lnl_z = d == 3 ? choose_lines(c->pz, 16, 8, 512) : 0;
-        // the fused solve along the last axis runs its inverse with the radices
-        // reversed, so it starts from the registers the forward's last stage filled
-        ins::FftPlan& last = d == 3 ? c->pz : c->py;
-        ins::FftPlan& rev = d == 3 ? c->pz_rev : c->py_rev;
-        std::vector<int> rr(d == 3 ? rz : ry);
-        std::reverse(rr.begin(), rr.end());
-        build_twiddles(last.n, rr, tw, rev);
-        rev.vm = last.vm;
-        rev.pad = last.pad;
-        rev.nth = last.nth;
-        if (c->lnl_x < 0 || c->lnl_y < 0 || c->lnl_z < 0) raise(INS_ERR_UNSUPPORTED, "FFT length too long");
-
-        const long double two_pi = 6.283185307179586476925286766559005768L;
-        std::vector<cd> post(g.nx / 2 + 1);
-        for (int k = 0; k <= g.nx / 2; ++k) {
-            const long double ang = -two_pi * k / static_cast<long double>(g.nx);
-            post[k] = cd{double(cosl(ang)), double(sinl(ang))};
-        }
-        // 4 sin^2(pi k / n) / h^2 per direction (Sec. 2.5.1 transfer function).
-        std::vector<double> lam;
-        size_t off[3] = {0, 0, 0};
-        const int cnt[3] = {g.nx / 2 + 1, g.ny, d == 3 ? g.nz : 1};
-        const int nn[3] = {g.nx, g.ny, g.nz};
-        for (int a = 0; a < 3; ++a) {
-            off[a] = lam.size();
-            for (int k = 0; k < cnt[a]; ++k) {
-                if (a >= d) {
-                    lam.push_back(0.0);
-                    continue;
-                }
-                const long double s = sinl(two_pi * 0.5L * k / static_cast<long double>(nn[a]));
-                lam.push_back(double(4.0L * s * s * static_cast<long double>(g.ih2[a])));
-            }
-        }
-        c->d_tw = static_cast<cd*>(c->alloc(std::max<size_t>(tw.size(), 1) * sizeof(cd)));
-        c->d_post = static_cast<cd*>(c->alloc(post.size() * sizeof(cd)));
-        c->d_lam = static_cast<double*>(c->alloc(lam.size() * sizeof(double)));
-        hip_check(hipMemcpy(c->d_tw, tw.data(), tw.size() * sizeof(cd), hipMemcpyHostToDevice), "upload twiddles");
-        hip_check(hipMemcpy(c->d_post, post.data(), post.size() * sizeof(cd), hipMemcpyHostToDevice), "upload twiddles");
-        hip_check(hipMemcpy(c->d_lam, lam.data(), lam.size() * sizeof(double), hipMemcpyHostToDevice), "upload eigenvalues");
-        c->px.tw = c->d_tw;
-        c->py.tw = c->d_tw;
-        c->pz.tw = c->d_tw;
-        c->py_rev.tw = c->d_tw;
-        c->pz_rev.tw = c->d_tw;
-        for (int a = 0; a < 3; ++a) c->st.lam[a] = c->d_lam + off[a];
-        c->st.inv_ncell = 1.0 / double(ncell);
-
-        const size_t nxh = size_t(g.nx / 2 + 1);
-        c->spec = static_cast<cd*>(c->alloc(size_t(g.batch) * g.nz * g.ny * nxh * sizeof(cd)));
+        setup_fft(c, rx, ry, rz, false);
         c->p = static_cast<double*>(c->alloc(c->scal_bytes()));
         c->ry = c->alloc(c->vel_bytes());
         c->wa = c->alloc(c->vel_bytes());
@@ -1117,6 +1177,10 @@ ins_status ins_poisson_solve_vjp(ins_ctx ctx, const double* pbar, double* rbar) 
         // channel: the solve is p = S^+ Omega_p (r - mean_w(r)) with S = -Omega_p D G
         // symmetric (zero-mean p), so its transpose is
         // rbar = Omega_p (t - mean_w(t)), t = S^+ (mean(pbar) - pbar)
+        if (ctx->use_direct) {
+            direct_solve(ctx, nullptr, pbar, rbar, 3);
+            return;
+        }
         cg_solve(ctx, nullptr, pbar, rbar, 3);
         ctx->launch("cg_weighted_center", [&] {
             return ins::launch_cg_weighted_center(ctx->g, rbar, ctx->cg_part, ctx->wsum, ctx->stream);
@@ -1283,6 +1347,30 @@ ins_status ins_cg_info(ins_ctx ctx, int* iterations, double* relres) {
         }
         *iterations = it;
         *relres = rr;
+    });
+}
+
+ins_status ins_set_pressure_solver(ins_ctx ctx, int solver) {
+    return guarded([&] {
+        checked(ctx);
+        if (solver != INS_PRESSURE_AUTO && solver != INS_PRESSURE_FFT && solver != INS_PRESSURE_CG)
+            raise(INS_ERR_INVALID, "unknown pressure solver");
+        if (!ctx->walls) {
+            if (solver == INS_PRESSURE_CG) raise(INS_ERR_UNSUPPORTED, "the periodic grid solves by FFT, not CG");
+            return;
+        }
+        if (solver == INS_PRESSURE_FFT && !ctx->direct_ok)
+            raise(INS_ERR_UNSUPPORTED,
+                  "the channel's FFT solve needs n_x even, n_x/2 and n_z products of 2, 3, 5, 7 and n_y <= 2048");
+        ctx->use_direct = solver == INS_PRESSURE_CG ? false : ctx->direct_ok;
+    });
+}
+
+ins_status ins_get_pressure_solver(ins_ctx ctx, int* solver) {
+    return guarded([&] {
+        checked(ctx);
+        need(solver, "solver");
+        *solver = (ctx->walls && !ctx->use_direct) ? INS_PRESSURE_CG : INS_PRESSURE_FFT;
     });
 }
 

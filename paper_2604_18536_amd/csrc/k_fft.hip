@@ -336,7 +336,11 @@ __device__ __forceinline__ void ld_pair(const float* p, double& a, double& b) {
 // X[k] = (Z[k] + conj Z[M-k]) / 2 + W^k (Z[k] - conj Z[M-k]) / (2i), W = exp(-2 pi i / n_x).
 // ----------------------------------------------------------------------------
 // SRC 0: rows are the divergence of the velocity field `vel`;
-// SRC 1: rows of the float64 scalar field r; SRC 2: rows of component `comp` of vel.
+// SRC 1: rows of the float64 scalar field r; SRC 2: rows of component `comp` of vel;
+// SRC 3: the channel divergence D u (both wall faces of u^y read as 0, row
+// widths from Grid::ym); SRC 4: the channel's D Omega_u^{-1} u (u^y / d_j,
+// tangential components / w_j), the right-hand side inside the transposed
+// projection.
 // The rows are staged in LDS first (see stage_rows); the untangling needs Z[k]
 // and Z[M-k] together, so the last stage writes to LDS as well.
 template <typename T, int DIM, int SRC, int VM, int NTH>
@@ -371,6 +375,44 @@ __global__ __launch_bounds__(NTH) void k_fft_x_fwd(Grid g, const T* __restrict__
                 double a0, a1;
                 ld_pair(vel + (int64_t(b) * DIM + comp) * g.ncell + rowoff + x0, a0, a1);
                 return cd{a0, a1};
+            } else if constexpr (SRC >= 3) {
+                const T* wb = vel + int64_t(b) * DIM * g.ncell;
+                const int S = g.ny + 2;
+                const double sp = SRC == 4 ? g.ym[3 * S + yy] : 1.0;  // w_j
+                const int xm = x0 == 0 ? g.nx - 1 : x0 - 1;
+                double ux0, ux1;
+                ld_pair(wb + rowoff + x0, ux0, ux1);
+                const double uxm = wb[rowoff + xm];
+                double r0 = (ux0 - uxm) * g.ih[0];
+                double r1 = (ux1 - ux0) * g.ih[0];
+                if constexpr (DIM == 3) {
+                    const int zm = zz == 0 ? g.nz - 1 : zz - 1;
+                    const T* wz = wb + 2 * g.ncell;
+                    double uz0, uz1, vz0, vz1;
+                    ld_pair(wz + rowoff + x0, uz0, uz1);
+                    ld_pair(wz + (zm * g.ny + yy) * g.nx + x0, vz0, vz1);
+                    r0 += (uz0 - vz0) * g.ih[2];
+                    r1 += (uz1 - vz1) * g.ih[2];
+                }
+                if constexpr (SRC == 4) {
+                    r0 /= sp;
+                    r1 /= sp;
+                }
+                const T* wy = wb + g.ncell;
+                double uy0 = 0.0, uy1 = 0.0, vy0 = 0.0, vy1 = 0.0;
+                if (yy < g.ny - 1) ld_pair(wy + rowoff + x0, uy0, uy1);
+                if (yy > 0) ld_pair(wy + rowoff - g.nx + x0, vy0, vy1);
+                if constexpr (SRC == 4) {
+                    const double iu = g.ym[S + yy + 1], id = g.ym[S + yy];  // 1 / d_j, 1 / d_{j-1}
+                    uy0 *= iu;
+                    uy1 *= iu;
+                    vy0 *= id;
+                    vy1 *= id;
+                }
+                const double iw = g.ym[yy];
+                r0 += (uy0 - vy0) * iw;
+                r1 += (uy1 - vy1) * iw;
+                return cd{r0, r1};
             } else {
                 const T* wb = vel + int64_t(b) * DIM * g.ncell;
                 const int xm = x0 == 0 ? g.nx - 1 : x0 - 1;
@@ -609,6 +651,36 @@ hipError_t launch_fft_strided(const Grid& g, cd* spec, const FftPlan& pl, const 
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_fft_x_fwd_wall(const Grid& g, const T* vel, bool scaled, cd* spec, const FftPlan& px, const cd* post,
+                                 int lnl, hipStream_t s) {
+    const int nl = 1 << lnl;
+    const int nrows = g.batch * g.nz * g.ny;
+    const int nblk = (nrows + nl - 1) / nl;
+    const size_t shm = size_t(nl + px.pad) * px.n * sizeof(cd);
+#define INS_XF(D, SRC, VM, NTH)                                                                                \
+    hipLaunchKernelGGL((k_fft_x_fwd<T, D, SRC, VM, NTH>), dim3(nblk), dim3(NTH), shm, s, g, vel, nullptr, spec, px, \
+                       post, lnl, 0)
+#define INS_XF_VM(D, SRC)                                    \
+    do {                                                     \
+        if (px.nth == 1024) INS_XF(D, SRC, 8, 1024);         \
+        else if (px.vm == 8) INS_XF(D, SRC, 8, 256);         \
+        else INS_XF(D, SRC, 16, 256);                        \
+    } while (0)
+    if (g.dim == 3) {
+        if (scaled) INS_XF_VM(3, 4); else INS_XF_VM(3, 3);
+    } else {
+        if (scaled) INS_XF_VM(2, 4); else INS_XF_VM(2, 3);
+    }
+#undef INS_XF_VM
+#undef INS_XF
+    return hipGetLastError();
+}
+
+template hipError_t launch_fft_x_fwd_wall<double>(const Grid&, const double*, bool, cd*, const FftPlan&, const cd*,
+                                                  int, hipStream_t);
+template hipError_t launch_fft_x_fwd_wall<float>(const Grid&, const float*, bool, cd*, const FftPlan&, const cd*, int,
+                                                 hipStream_t);
 template hipError_t launch_fft_x_fwd<double>(const Grid&, const double*, const double*, cd*, const FftPlan&, const cd*,
                                              int, hipStream_t, int);
 template hipError_t launch_fft_x_fwd<float>(const Grid&, const float*, const double*, cd*, const FftPlan&, const cd*,

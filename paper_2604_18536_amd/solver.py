@@ -15,6 +15,7 @@ from . import _lib as L
 
 _DTYPES = {"fp64": (L.INS_FP64, torch.float64), "fp32": (L.INS_FP32, torch.float32)}
 _BCS = {"periodic": L.INS_BC_PERIODIC, "walls": L.INS_BC_WALLS_Y}
+_PRESSURE = {"auto": L.INS_PRESSURE_AUTO, "fft": L.INS_PRESSURE_FFT, "cg": L.INS_PRESSURE_CG}
 
 
 class Solver:
@@ -29,13 +30,17 @@ class Solver:
         batch: number of independent fields per call.
         lo, hi: box corners (default [0, 2 pi] per direction).
         bc: "periodic" (every direction; FFT pressure solve) or "walls"
-            (channel: no-slip walls at y = lo[1] and hi[1], x and z periodic;
-            conjugate-gradient pressure solve, see cg_set). In the channel the
-            stored u^y face of the last cell row is the upper wall: it reads as
-            0 and every output writes 0 there.
+            (channel: no-slip walls at y = lo[1] and hi[1], x and z periodic).
+            In the channel the stored u^y face of the last cell row is the
+            upper wall: it reads as 0 and every output writes 0 there.
+        pressure: the pressure solver. "auto" (default): FFT where it applies,
+            else CG; "fft": spectral (channel: FFTs along x and z and a direct
+            tridiagonal solve along y per mode); "cg": matrix-free conjugate
+            gradients (channel only, see cg_set).
     """
 
-    def __init__(self, n, nu=0.0, precision="fp64", batch=1, lo=None, hi=None, device=None, bc="periodic"):
+    def __init__(self, n, nu=0.0, precision="fp64", batch=1, lo=None, hi=None, device=None, bc="periodic",
+                 pressure="auto"):
         if precision not in _DTYPES:
             raise ValueError(f"precision must be one of {list(_DTYPES)}")
         if bc not in _BCS:
@@ -65,6 +70,8 @@ class Solver:
         self._ctx = C.c_void_p()
         with torch.cuda.device(self.device):
             L.call("ins_create", C.byref(g), _BCS[bc], self.nu, self._code, C.byref(self._ctx))
+        if pressure != "auto":
+            self.set_pressure(pressure)
         spatial = tuple(reversed(self.n))
         self.vel_shape = (self.batch, self.dim) + spatial
         self.scal_shape = (self.batch,) + spatial
@@ -118,6 +125,19 @@ class Solver:
 
     def new_scalar(self):
         return torch.zeros(self.scal_shape, dtype=torch.float64, device=self.device)
+
+    def set_pressure(self, solver):
+        """Pressure solver for later calls: "auto", "fft" or "cg"."""
+        if solver not in _PRESSURE:
+            raise ValueError(f"pressure must be one of {list(_PRESSURE)}")
+        L.call("ins_set_pressure_solver", self._ctx, _PRESSURE[solver])
+
+    @property
+    def pressure(self):
+        """The pressure solver in use, "fft" or "cg"."""
+        v = C.c_int()
+        L.call("ins_get_pressure_solver", self._ctx, C.byref(v))
+        return "cg" if v.value == L.INS_PRESSURE_CG else "fft"
 
     def cg_set(self, rtol=1e-10, maxiter=20000, check_every=16):
         """Stopping rule of the channel's conjugate-gradient pressure solves."""

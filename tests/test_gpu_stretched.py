@@ -44,7 +44,7 @@ def _solver(n, nu=0.0, precision="fp64", batch=1, rtol=1e-14, gamma=1.4):
     from paper_2604_18536_amd import Solver
 
     lo, hi = S.channel_box(n)
-    s = Solver(n, nu=nu, precision=precision, batch=batch, lo=lo, hi=hi, bc="walls")
+    s = Solver(n, nu=nu, precision=precision, batch=batch, lo=lo, hi=hi, bc="walls", pressure="cg")
     s.set_y_faces(_faces(n, gamma))
     s.cg_set(rtol=rtol, maxiter=20000, check_every=16)
     return s
