@@ -83,6 +83,8 @@ template <typename T>
 hipError_t launch_stage(const Grid& g, const T* w, const double* p, bool proj, const T* u0, T* y, bool yinit, double cy,
                         T* wout, double cw, hipStream_t s, const T* mc = nullptr);
 
+// z planes per workgroup of a z-marching 3D stencil on TX x TY tiles.
+int zm_chunk(const Grid& g, int tx, int ty);
 // 3D variant of launch_stage: 2.5D z-march with an LDS ring of projected planes.
 template <typename T>
 hipError_t launch_stage_zm(const Grid& g, const T* w, const double* p, bool proj, const T* u0, T* y, bool yinit,

@@ -300,6 +300,166 @@ __global__ __launch_bounds__(kBlock) void k_wall_stage(Grid g, const T* __restri
     }
 }
 
+// 3D stage as a 2.5D z-march (same contract and arithmetic as k_wall_stage):
+// a workgroup owns a TX x TY tile of an x-y plane and a chunk of z planes; each
+// plane's stage velocity (w - G p with the wall rules: u^y 0 off the interior
+// faces, tangential ghosts beyond a wall minus the mirrored row) is formed once
+// on the tile plus a one-cell halo into a 4-plane LDS ring, and the stencil of
+// plane z reads planes z-1, z, z+1 from there.
+template <typename T, int TX, int TY>
+struct WallLds {
+    static constexpr int HX = TX + 2, HP = HX * (TY + 2);
+    const T* zm;
+    const T* z0;
+    const T* zp;
+    int centre;
+    __device__ __forceinline__ T operator()(int c, const Nb&, int dx, int dy, int dz) const {
+        const T* b = dz < 0 ? zm : (dz > 0 ? zp : z0);
+        return b[c * HP + centre + dy * HX + dx];
+    }
+};
+
+template <typename T, bool PROJ, int TX, int TY>
+__global__ __launch_bounds__(TX * TY) void k_wall_stage_zm(Grid g, const T* __restrict__ w,
+                                                             const double* __restrict__ p, const T* __restrict__ u0,
+                                                             T* __restrict__ y, int yinit, T cy, T* __restrict__ wout,
+                                                             T cw, int zc) {
+    constexpr int NT = TX * TY, HX = TX + 2, HP = HX * (TY + 2);
+    constexpr int NS = (HP + NT - 1) / NT;
+    __shared__ T ring[4][3][HP];
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY, nzc = (nz + zc - 1) / zc;
+    int L = xcd_logical(blockIdx.x, gridDim.x);
+    const int tx = L % ntx;
+    L /= ntx;
+    const int ty = L % nty;
+    L /= nty;
+    const int zci = L % nzc;
+    const int b = L / nzc;
+    const int x0 = tx * TX, y0 = ty * TY, z0 = zci * zc;
+    const int z1 = min(z0 + zc, nz);
+    const int64_t boff = int64_t(b) * 3 * g.ncell;
+    const T* wb = w + boff;
+    const double* pb = PROJ ? p + int64_t(b) * g.ncell : nullptr;
+    const int nc = int(g.ncell);
+    const int plane = nx * ny;
+    const YMetric M(g);
+
+    // halo positions of this thread: row offset of the (mirrored) row, x and
+    // x + 1 (periodic), ghost / interior-face flags, 1 / d of the y-face
+    int hq[NS], hrow[NS], hx[NS], hxp[NS];
+    bool hghost[NS], hunk[NS];
+    double hid[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int q = threadIdx.x + s * NT;
+        hq[s] = q;
+        const int qq = q < HP ? q : 0;
+        const int gx = ((x0 - 1 + qq % HX) % nx + nx) % nx;  // the tile may be wider than n_x
+        const int r = y0 - 1 + qq / HX;
+        const int m = r < 0 ? 0 : (r > ny - 1 ? ny - 1 : r);
+        hrow[s] = m * nx;
+        hx[s] = gx;
+        hxp[s] = gx + 1 == nx ? 0 : gx + 1;
+        hghost[s] = r < 0 || r > ny - 1;
+        hunk[s] = r >= 0 && r <= ny - 2;
+        hid[s] = hunk[s] ? M.id(r) : 0.0;
+    }
+    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+    const int cxg = x0 + lx, cyg = y0 + ly;
+    const bool valid = cxg < nx && cyg < ny;
+    const bool wallrow = cyg == ny - 1;
+    const int centre = (ly + 1) * HX + (lx + 1);
+
+    T pre[NS][3];
+    auto fetch = [&](int zz) {
+        const int zoff = zz * plane;
+        const int zpo = (zz + 1 == nz ? 0 : zz + 1) * plane;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            if (hq[s] < HP) {
+                const int j = zoff + hrow[s] + hx[s];
+                T v0, v1 = T(0), v2;
+                if constexpr (PROJ) {
+                    const double pc = pb[j];
+                    v0 = T(double(wb[j]) - (pb[zoff + hrow[s] + hxp[s]] - pc) * g.ih[0]);
+                    if (hunk[s]) v1 = T(double(wb[nc + j]) - (pb[j + nx] - pc) * hid[s]);
+                    v2 = T(double(wb[2 * nc + j]) - (pb[zpo + hrow[s] + hx[s]] - pc) * g.ih[2]);
+                } else {
+                    v0 = wb[j];
+                    if (hunk[s]) v1 = wb[nc + j];
+                    v2 = wb[2 * nc + j];
+                }
+                pre[s][0] = hghost[s] ? -v0 : v0;
+                pre[s][1] = v1;
+                pre[s][2] = hghost[s] ? -v2 : v2;
+            }
+        }
+    };
+    auto park = [&](int k) {
+        T* slot = &ring[k & 3][0][0];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            if (hq[s] < HP) {
+                slot[hq[s]] = pre[s][0];
+                slot[HP + hq[s]] = pre[s][1];
+                slot[2 * HP + hq[s]] = pre[s][2];
+            }
+        }
+    };
+    T base[3], yv[3];
+    auto fetch_point = [&](int z) {
+        if (!valid) return;
+        const int c0 = z * plane + cyg * nx + cxg;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int64_t kk = boff + int64_t(a) * nc + c0;
+            base[a] = (wout || yinit) ? __builtin_nontemporal_load(u0 + kk) : T(0);
+            yv[a] = (y && !yinit) ? __builtin_nontemporal_load(y + kk) : base[a];
+        }
+    };
+
+    const int nk = (z1 - z0) + 2;
+    fetch(wrap(z0 - 1, nz));
+    park(0);
+    fetch(z0);
+    park(1);
+    if (nk > 2) fetch(z0 + 1 == nz ? 0 : z0 + 1);
+    park(2);
+    fetch_point(z0);
+    __syncthreads();
+    for (int k = 2; k < nk; ++k) {
+        const int z = z0 + k - 2;
+        const bool more = k + 1 < nk;
+        if (more) {
+            const int zn = z0 - 1 + k + 1;
+            fetch(zn >= nz ? zn - nz : zn);
+        }
+        T cb[3], cyv[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            cb[a] = base[a];
+            cyv[a] = yv[a];
+        }
+        if (more) fetch_point(z + 1);
+        if (valid) {
+            const int c0 = z * plane + cyg * nx + cxg;
+            WallLds<T, TX, TY> U{&ring[(k - 2) & 3][0][0], &ring[(k - 1) & 3][0][0], &ring[k & 3][0][0], centre};
+            T F[3];
+            rhs_cell_wall<T, 3>(g, U, Nb{}, cyg, F);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int64_t kk = boff + int64_t(a) * nc + c0;
+                const bool zero = a == 1 && wallrow;
+                if (y) __builtin_nontemporal_store(zero ? T(0) : cyv[a] + cy * F[a], y + kk);
+                if (wout) __builtin_nontemporal_store(zero ? T(0) : cb[a] + cw * F[a], wout + kk);
+            }
+        }
+        if (more) park(k + 1);
+        __syncthreads();
+    }
+}
+
 // u_out = w - G p (ADJ: w - Omega_u G p, the transposed projection's
 // correction); float64 arithmetic; 0 on the wall face; u_out may alias w.
 template <typename T, int DIM, bool ADJ>
@@ -447,6 +607,172 @@ __global__ __launch_bounds__(kBlock) void k_wall_stage_vjp(Grid g, const T* __re
         if (mode >= 2) acc += out[a];
         if (u0bar) u0bar[k] = acc;
         if (ubar_out) ubar_out[k] = out[a];
+    }
+}
+
+// 3D reverse stage as a z-march (same contract and arithmetic as
+// k_wall_stage_vjp): two 3-slot LDS rings hold, per plane, the stage velocity
+// (WallVel's values) and the right-hand-side cotangent (WallFbar's values) on
+// a 32 x 8 tile plus halo; plane z's pullback stencil reads planes z-1, z, z+1.
+constexpr int kWvTX = 32, kWvTY = 8;
+
+template <typename T, bool PROJ_U, bool HAS_W>
+__global__ __launch_bounds__(kBlock) void k_wall_stage_vjp_zm(Grid g, const T* __restrict__ w,
+                                                                const double* __restrict__ p,
+                                                                const T* __restrict__ ybar, const T* __restrict__ un,
+                                                                const double* __restrict__ q, T cb, T cw,
+                                                                T* __restrict__ u0bar, int mode,
+                                                                T* __restrict__ ubar_out, int zc) {
+    constexpr int TX = kWvTX, TY = kWvTY, HX = TX + 2, HP = HX * (TY + 2);
+    constexpr int NS = (HP + kBlock - 1) / kBlock;
+    __shared__ T ru[3][3][HP];
+    __shared__ T rf[3][3][HP];
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY, nzc = (nz + zc - 1) / zc;
+    int L = xcd_logical(blockIdx.x, gridDim.x);
+    const int tx = L % ntx;
+    L /= ntx;
+    const int ty = L % nty;
+    L /= nty;
+    const int zci = L % nzc;
+    const int b = L / nzc;
+    const int x0 = tx * TX, y0 = ty * TY, z0 = zci * zc;
+    const int z1 = min(z0 + zc, nz);
+    const int64_t boff = int64_t(b) * 3 * g.ncell;
+    const int64_t soff = int64_t(b) * g.ncell;
+    const T* wb = w + boff;
+    const double* pb = PROJ_U ? p + soff : nullptr;
+    const T* yb = ybar + boff;
+    const T* ub = HAS_W ? un + boff : nullptr;
+    const double* qb = HAS_W ? q + soff : nullptr;
+    const int nc = int(g.ncell);
+    const int plane = nx * ny;
+    const YMetric M(g);
+
+    int hq[NS], hrow[NS], hx[NS], hxp[NS];
+    bool hghost[NS], hunk[NS];
+    double hid[NS], hw[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int qi = threadIdx.x + s * kBlock;
+        hq[s] = qi;
+        const int qq = qi < HP ? qi : 0;
+        const int gx = ((x0 - 1 + qq % HX) % nx + nx) % nx;
+        const int r = y0 - 1 + qq / HX;
+        const int m = r < 0 ? 0 : (r > ny - 1 ? ny - 1 : r);
+        hrow[s] = m * nx;
+        hx[s] = gx;
+        hxp[s] = gx + 1 == nx ? 0 : gx + 1;
+        hghost[s] = r < 0 || r > ny - 1;
+        hunk[s] = r >= 0 && r <= ny - 2;
+        hid[s] = hunk[s] ? M.id(r) : 0.0;
+        hw[s] = M.w(m);
+    }
+    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+    const int cxg = x0 + lx, cyg = y0 + ly;
+    const bool valid = cxg < nx && cyg < ny;
+    const bool wallrow = cyg == ny - 1;
+    const int centre = (ly + 1) * HX + (lx + 1);
+
+    T pu[NS][3], pf[NS][3];
+    auto fetch = [&](int zz) {
+        const int zoff = zz * plane;
+        const int zpo = (zz + 1 == nz ? 0 : zz + 1) * plane;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            if (hq[s] < HP) {
+                const int j = zoff + hrow[s] + hx[s];
+                const int jp[3] = {zoff + hrow[s] + hxp[s], j + nx, zpo + hrow[s] + hx[s]};
+                double pc = 0.0, qc = 0.0;
+                if constexpr (PROJ_U) pc = pb[j];
+                if constexpr (HAS_W) qc = qb[j];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    if (c == 1 && !hunk[s]) {
+                        pu[s][c] = T(0);
+                        pf[s][c] = T(0);
+                        continue;
+                    }
+                    const double gs = c == 1 ? hid[s] : g.ih[c];
+                    T uv;
+                    if constexpr (PROJ_U)
+                        uv = T(double(wb[c * nc + j]) - (pb[jp[c]] - pc) * gs);
+                    else
+                        uv = wb[c * nc + j];
+                    T fv = cb * yb[c * nc + j];
+                    if constexpr (HAS_W) {
+                        const double og = c == 1 ? (qb[jp[c]] - qc) : hw[s] * (qb[jp[c]] - qc) * g.ih[c];
+                        fv += cw * T(double(ub[c * nc + j]) - og);
+                    }
+                    const bool neg = c != 1 && hghost[s];
+                    pu[s][c] = neg ? -uv : uv;
+                    pf[s][c] = neg ? -fv : fv;
+                }
+            }
+        }
+    };
+    auto park = [&](int k) {
+        T* su = &ru[k % 3][0][0];
+        T* sf = &rf[k % 3][0][0];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            if (hq[s] < HP) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    su[c * HP + hq[s]] = pu[s][c];
+                    sf[c * HP + hq[s]] = pf[s][c];
+                }
+            }
+        }
+    };
+
+    const int nk = (z1 - z0) + 2;
+    fetch(z0 == 0 ? nz - 1 : z0 - 1);
+    park(0);
+    fetch(z0);
+    park(1);
+    fetch(z0 + 1 == nz ? 0 : z0 + 1);
+    park(2);
+    __syncthreads();
+    for (int k = 2; k < nk; ++k) {
+        const int z = z0 + k - 2;
+        const bool more = k + 1 < nk;
+        if (more) {
+            const int zn = z0 - 1 + k + 1;
+            fetch(zn >= nz ? zn - nz : zn);
+        }
+        if (valid) {
+            const int cyx = cyg * nx + cxg;
+            const int c0 = z * plane + cyx;
+            const int jpc[3] = {z * plane + cyg * nx + (cxg + 1 == nx ? 0 : cxg + 1), c0 + nx,
+                                (z + 1 == nz ? 0 : z + 1) * plane + cyx};
+            WallLds<T, TX, TY> U{&ru[(k - 2) % 3][0][0], &ru[(k - 1) % 3][0][0], &ru[k % 3][0][0], centre};
+            WallLds<T, TX, TY> F{&rf[(k - 2) % 3][0][0], &rf[(k - 1) % 3][0][0], &rf[k % 3][0][0], centre};
+            T out[3];
+            rhs_vjp_cell_wall<T, 3>(g, U, F, Nb{}, cyg, out);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int64_t kk = boff + int64_t(a) * nc + c0;
+                if (a == 1 && wallrow) {
+                    if (u0bar) u0bar[kk] = T(0);
+                    if (ubar_out) ubar_out[kk] = T(0);
+                    continue;
+                }
+                T acc = (mode == 0 || mode == 3) ? yb[int64_t(a) * nc + c0] : __builtin_nontemporal_load(u0bar + kk);
+                if constexpr (HAS_W) {
+                    const double dq = qb[jpc[a]] - qb[c0];
+                    const double og = a == 1 ? dq : M.w(cyg) * dq * g.ih[a];
+                    acc += T(double(ub[int64_t(a) * nc + c0]) - og);
+                }
+                if (mode >= 2) acc += out[a];
+                if (u0bar) __builtin_nontemporal_store(acc, u0bar + kk);
+                if (ubar_out) __builtin_nontemporal_store(out[a], ubar_out + kk);
+            }
+        }
+        // slot (k+1) % 3 is the one just read as plane z-1: wait for every reader
+        __syncthreads();
+        if (more) park(k + 1);
+        __syncthreads();
     }
 }
 
@@ -1148,9 +1474,18 @@ static void wall_stage_dim(const Grid& g, const T* w, const double* p, bool proj
 template <typename T>
 hipError_t launch_wall_stage(const Grid& g, const T* w, const double* p, bool proj, const T* u0, T* y, bool yinit,
                              double cy, T* wout, double cw, hipStream_t s) {
-    if (g.dim == 3)
-        wall_stage_dim<T, 3>(g, w, p, proj, u0, y, yinit ? 1 : 0, T(cy), wout, T(cw), s);
-    else
+    if (g.dim == 3) {
+        constexpr int TX = 64, TY = 8;
+        const int zc = zm_chunk(g, TX, TY);
+        const int nblk = ((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY) * ((g.nz + zc - 1) / zc) * g.batch;
+        const int yi = yinit ? 1 : 0;
+        if (proj)
+            hipLaunchKernelGGL((k_wall_stage_zm<T, true, TX, TY>), dim3(nblk), dim3(TX * TY), 0, s, g, w, p, u0, y, yi,
+                               T(cy), wout, T(cw), zc);
+        else
+            hipLaunchKernelGGL((k_wall_stage_zm<T, false, TX, TY>), dim3(nblk), dim3(TX * TY), 0, s, g, w, p, u0, y,
+                               yi, T(cy), wout, T(cw), zc);
+    } else
         wall_stage_dim<T, 2>(g, w, p, proj, u0, y, yinit ? 1 : 0, T(cy), wout, T(cw), s);
     return hipGetLastError();
 }
@@ -1177,9 +1512,24 @@ template <typename T>
 hipError_t launch_wall_stage_vjp(const Grid& g, const T* w, const double* p, bool proj_u, const T* ybar, const T* un,
                                  const double* q, bool has_w, double cb, double cw, T* u0bar, int mode, T* ubar_out,
                                  hipStream_t s) {
-    if (g.dim == 3)
-        wall_stage_vjp_dim<T, 3>(g, w, p, proj_u, ybar, un, q, has_w, T(cb), T(cw), u0bar, mode, ubar_out, s);
-    else
+    if (g.dim == 3) {
+        const int zc = zm_chunk(g, kWvTX, kWvTY);
+        const int nblk =
+            ((g.nx + kWvTX - 1) / kWvTX) * ((g.ny + kWvTY - 1) / kWvTY) * ((g.nz + zc - 1) / zc) * g.batch;
+        const T tb = T(cb), tw = T(cw);
+#define INS_WVJP_ZM(PU, HW)                                                                                       \
+    hipLaunchKernelGGL((k_wall_stage_vjp_zm<T, PU, HW>), dim3(nblk), dim3(kBlock), 0, s, g, w, p, ybar, un, q, tb, \
+                       tw, u0bar, mode, ubar_out, zc)
+        if (proj_u && has_w)
+            INS_WVJP_ZM(true, true);
+        else if (proj_u)
+            INS_WVJP_ZM(true, false);
+        else if (has_w)
+            INS_WVJP_ZM(false, true);
+        else
+            INS_WVJP_ZM(false, false);
+#undef INS_WVJP_ZM
+    } else
         wall_stage_vjp_dim<T, 2>(g, w, p, proj_u, ybar, un, q, has_w, T(cb), T(cw), u0bar, mode, ubar_out, s);
     return hipGetLastError();
 }
