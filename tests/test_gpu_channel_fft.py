@@ -6,8 +6,9 @@ Both sides solve the same discrete system exactly, so the bar is rounding:
 1e-11 element-wise (max |gpu - ref| / max |ref|) for solves, projections,
 steps and pullbacks; the (0, 0) mode's Neumann operator has a condition number
 growing as n_y^2 (about 5e5 at n_y = 1100), so kappa * eps stays below 1e-10
-and well-conditioned modes are at 1e-16. FP32 mode: 1e-5 relative L2 after one step. Grids cover
-one to 64 segments per line (n_y = 9 .. 1100), ragged k_x chunks (n_x = 70),
+and well-conditioned modes are at 1e-16. FP32 mode: 1e-5 relative L2 after one
+step. Grids cover one to 64 segments per line (n_y = 9 .. 1100), ragged k_x
+chunks (n_x = 70),
 2D and 3D, and a batch of two. At the 256^3 size the benchmark runs, the
 checks are properties the exact solve has at any size: D P u = 0 to
 rounding, P P u = P u, and D G p = r - mean_w(r).
