@@ -140,12 +140,27 @@ struct WallFbar {
     }
 };
 
-// F^a at the current cell (row y): diffusion (eq. diff-kernel) and convection
-// (eq. conv-kernel with the weights described above) on the channel grid.
+// y metrics of the rows y-1, y, y+1 that the stencils of a cell of row y read
+// (clamped as YMetric), loaded once per thread.
+struct RowM {
+    double iw[3], id[3], th, thm;
+    __device__ __forceinline__ RowM(const Grid& g, int y) {
+        const YMetric M(g);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            iw[k] = M.iw(y + k - 1);
+            id[k] = M.id(y + k - 1);
+        }
+        th = M.th(y);
+        thm = M.th(y - 1);
+    }
+};
+
+// F^a at the current cell (row y, metrics R): diffusion (eq. diff-kernel) and
+// convection (eq. conv-kernel with the weights described above) on the channel grid.
 template <typename T, int DIM, class Src>
-__device__ __forceinline__ void rhs_cell_wall(const Grid& g, const Src& U, const Nb& nb, int y, T F[DIM]) {
-    const YMetric M(g);
-    const T iwj = T(M.iw(y)), iwp = T(M.iw(y + 1)), idj = T(M.id(y)), idm = T(M.id(y - 1)), th = T(M.th(y));
+__device__ __forceinline__ void rhs_cell_wall(const Grid& g, const Src& U, const Nb& nb, const RowM& R, T F[DIM]) {
+    const T iwj = T(R.iw[1]), iwp = T(R.iw[2]), idj = T(R.id[1]), idm = T(R.id[0]), th = T(R.th);
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
         const int ax = a == 0, ay = a == 1, az = a == 2;
@@ -179,10 +194,10 @@ __device__ __forceinline__ void rhs_cell_wall(const Grid& g, const Src& U, const
     }
 }
 
-// 1 / |Delta^b| of the a-velocity volume whose point lies on row r.
+// 1 / |Delta^b| of the a-velocity volume whose point lies on row y + dr (dr in -1..1).
 template <typename T>
-__device__ __forceinline__ T conv_s(const Grid& g, const YMetric& M, int a, int b, int r) {
-    return b != 1 ? T(g.ih[b]) : T(a == 1 ? M.id(r) : M.iw(r));
+__device__ __forceinline__ T conv_s(const Grid& g, const RowM& R, int a, int b, int dr) {
+    return b != 1 ? T(g.ih[b]) : T(a == 1 ? R.id[dr + 1] : R.iw[dr + 1]);
 }
 
 // Pullback of the right-hand side at one cell (row y), gather form: the
@@ -191,10 +206,9 @@ __device__ __forceinline__ T conv_s(const Grid& g, const YMetric& M, int a, int 
 // Fbar^{ab}[K] = -fbar^a[K] s(K) + fbar^a[K + e_b] s(K + e_b), with the
 // interpolation weight of u^g[J] in its own factor.
 template <typename T, int DIM, class USrc, class FSrc>
-__device__ __forceinline__ void rhs_vjp_cell_wall(const Grid& g, const USrc& U, const FSrc& Fb, const Nb& nb, int y,
-                                                  T out[DIM]) {
-    const YMetric M(g);
-    const T thy = T(M.th(y)), thm = T(M.th(y - 1));
+__device__ __forceinline__ void rhs_vjp_cell_wall(const Grid& g, const USrc& U, const FSrc& Fb, const Nb& nb,
+                                                  const RowM& R, T out[DIM]) {
+    const T thy = T(R.th), thm = T(R.thm);
 #pragma unroll
     for (int gm = 0; gm < DIM; ++gm) {
         const int gx = gm == 0, gy = gm == 1, gz = gm == 2;
@@ -208,16 +222,14 @@ __device__ __forceinline__ void rhs_vjp_cell_wall(const Grid& g, const USrc& U, 
             if (b != 1) {
                 diff += (fp - T(2) * fc + fm) * T(g.ih2[b]);
             } else if (gm != 1) {
-                diff += fm * T(M.iw(y - 1) * M.id(y - 1)) - fc * T(M.iw(y) * (M.id(y) + M.id(y - 1))) +
-                        fp * T(M.iw(y + 1) * M.id(y));
+                diff += fm * T(R.iw[0] * R.id[0]) - fc * T(R.iw[1] * (R.id[1] + R.id[0])) + fp * T(R.iw[2] * R.id[1]);
             } else {
-                diff += fm * T(M.id(y - 1) * M.iw(y)) - fc * T(M.id(y) * (M.iw(y + 1) + M.iw(y))) +
-                        fp * T(M.id(y + 1) * M.iw(y + 1));
+                diff += fm * T(R.id[0] * R.iw[1]) - fc * T(R.id[1] * (R.iw[2] + R.iw[1])) + fp * T(R.id[2] * R.iw[2]);
             }
             // u^gm transported in F^{gm b} at K = J and K = J - e_b (weights 1/2)
-            const T s0 = conv_s<T>(g, M, gm, b, y);
-            const T F0 = -fc * s0 + fp * conv_s<T>(g, M, gm, b, y + by);
-            const T F1 = -fm * conv_s<T>(g, M, gm, b, y - by) + fc * s0;
+            const T s0 = conv_s<T>(g, R, gm, b, 0);
+            const T F0 = -fc * s0 + fp * conv_s<T>(g, R, gm, b, by);
+            const T F1 = -fm * conv_s<T>(g, R, gm, b, -by) + fc * s0;
             T B0, B1;
             if (gm == 1 && b != 1) {
                 B0 = thy * U(b, nb, 0, 0, 0) + (T(1) - thy) * U(b, nb, 0, 1, 0);
@@ -232,11 +244,11 @@ __device__ __forceinline__ void rhs_vjp_cell_wall(const Grid& g, const USrc& U, 
         for (int a = 0; a < DIM; ++a) {
             const int ax = a == 0, ay = a == 1, az = a == 2;
             // u^gm transporting in F^{a gm} at K = J and K = J - e_a
-            const T F0 = -Fb(a, nb, 0, 0, 0) * conv_s<T>(g, M, a, gm, y) +
-                         Fb(a, nb, gx, gy, gz) * conv_s<T>(g, M, a, gm, y + gy);
+            const T F0 = -Fb(a, nb, 0, 0, 0) * conv_s<T>(g, R, a, gm, 0) +
+                         Fb(a, nb, gx, gy, gz) * conv_s<T>(g, R, a, gm, gy);
             const T A0 = T(0.5) * (U(a, nb, 0, 0, 0) + U(a, nb, gx, gy, gz));
-            const T F1 = -Fb(a, nb, -ax, -ay, -az) * conv_s<T>(g, M, a, gm, y - ay) +
-                         Fb(a, nb, gx - ax, gy - ay, gz - az) * conv_s<T>(g, M, a, gm, y - ay + gy);
+            const T F1 = -Fb(a, nb, -ax, -ay, -az) * conv_s<T>(g, R, a, gm, -ay) +
+                         Fb(a, nb, gx - ax, gy - ay, gz - az) * conv_s<T>(g, R, a, gm, gy - ay);
             const T A1 = T(0.5) * (U(a, nb, -ax, -ay, -az) + U(a, nb, gx - ax, gy - ay, gz - az));
             T w0 = T(0.5), w1 = T(0.5);
             if (a == 1 && gm != 1) {
@@ -262,7 +274,7 @@ __global__ __launch_bounds__(kBlock) void k_wall_rhs(Grid g, const T* __restrict
     const int64_t boff = int64_t(t.b) * DIM * g.ncell;
     WallVel<T, false> U{u + boff, nullptr, int(g.ncell), g.ih[0], g.ih[2], rows, YMetric(g), t.y};
     T F[DIM];
-    rhs_cell_wall<T, DIM>(g, U, nb, t.y, F);
+    rhs_cell_wall<T, DIM>(g, U, nb, RowM(g, t.y), F);
     const int c0 = nb.at(0, 0, 0);
     const bool wall = t.y == g.ny - 1;
 #pragma unroll
@@ -283,7 +295,7 @@ __global__ __launch_bounds__(kBlock) void k_wall_stage(Grid g, const T* __restri
     WallVel<T, PROJ> U{w + boff, PROJ ? p + int64_t(t.b) * g.ncell : nullptr, int(g.ncell), g.ih[0], g.ih[2],
                        rows, YMetric(g), t.y};
     T F[DIM];
-    rhs_cell_wall<T, DIM>(g, U, nb, t.y, F);
+    rhs_cell_wall<T, DIM>(g, U, nb, RowM(g, t.y), F);
     const int c0 = nb.at(0, 0, 0);
     const bool wall = t.y == g.ny - 1;
 #pragma unroll
@@ -370,6 +382,7 @@ __global__ __launch_bounds__(TX * TY) void k_wall_stage_zm(Grid g, const T* __re
     const bool valid = cxg < nx && cyg < ny;
     const bool wallrow = cyg == ny - 1;
     const int centre = (ly + 1) * HX + (lx + 1);
+    const RowM rowm(g, valid ? cyg : 0);
 
     T pre[NS][3];
     auto fetch = [&](int zz) {
@@ -446,7 +459,7 @@ __global__ __launch_bounds__(TX * TY) void k_wall_stage_zm(Grid g, const T* __re
             const int c0 = z * plane + cyg * nx + cxg;
             WallLds<T, TX, TY> U{&ring[(k - 2) & 3][0][0], &ring[(k - 1) & 3][0][0], &ring[k & 3][0][0], centre};
             T F[3];
-            rhs_cell_wall<T, 3>(g, U, Nb{}, cyg, F);
+            rhs_cell_wall<T, 3>(g, U, Nb{}, rowm, F);
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const int64_t kk = boff + int64_t(a) * nc + c0;
@@ -561,7 +574,7 @@ __global__ __launch_bounds__(kBlock) void k_wall_rhs_vjp(Grid g, const T* __rest
     WallVel<T, false> U{u + boff, nullptr, nc, g.ih[0], g.ih[2], rows, M, t.y};
     WallFbar<T, false> F{fbar + boff, nullptr, nullptr, T(1), T(0), nc, g.ih[0], g.ih[2], rows, M, t.y};
     T out[DIM];
-    rhs_vjp_cell_wall<T, DIM>(g, U, F, nb, t.y, out);
+    rhs_vjp_cell_wall<T, DIM>(g, U, F, nb, RowM(g, t.y), out);
     const int c0 = nb.at(0, 0, 0);
     const bool wall = t.y == g.ny - 1;
 #pragma unroll
@@ -587,7 +600,7 @@ __global__ __launch_bounds__(kBlock) void k_wall_stage_vjp(Grid g, const T* __re
     WallFbar<T, HAS_W> F{ybar + boff, HAS_W ? un + boff : nullptr, HAS_W ? q + soff : nullptr, cb, cw, nc,
                          g.ih[0], g.ih[2], rows, M, t.y};
     T out[DIM];
-    rhs_vjp_cell_wall<T, DIM>(g, U, F, nb, t.y, out);
+    rhs_vjp_cell_wall<T, DIM>(g, U, F, nb, RowM(g, t.y), out);
     const int c0 = nb.at(0, 0, 0);
     const bool wall = t.y == g.ny - 1;
 #pragma unroll
@@ -673,6 +686,8 @@ __global__ __launch_bounds__(kBlock) void k_wall_stage_vjp_zm(Grid g, const T* _
     const bool valid = cxg < nx && cyg < ny;
     const bool wallrow = cyg == ny - 1;
     const int centre = (ly + 1) * HX + (lx + 1);
+    const RowM rowm(g, valid ? cyg : 0);
+    const double wrow = M.w(valid ? cyg : 0);
 
     T pu[NS][3], pf[NS][3];
     auto fetch = [&](int zz) {
@@ -749,7 +764,7 @@ __global__ __launch_bounds__(kBlock) void k_wall_stage_vjp_zm(Grid g, const T* _
             WallLds<T, TX, TY> U{&ru[(k - 2) % 3][0][0], &ru[(k - 1) % 3][0][0], &ru[k % 3][0][0], centre};
             WallLds<T, TX, TY> F{&rf[(k - 2) % 3][0][0], &rf[(k - 1) % 3][0][0], &rf[k % 3][0][0], centre};
             T out[3];
-            rhs_vjp_cell_wall<T, 3>(g, U, F, Nb{}, cyg, out);
+            rhs_vjp_cell_wall<T, 3>(g, U, F, Nb{}, rowm, out);
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const int64_t kk = boff + int64_t(a) * nc + c0;
@@ -761,7 +776,7 @@ __global__ __launch_bounds__(kBlock) void k_wall_stage_vjp_zm(Grid g, const T* _
                 T acc = (mode == 0 || mode == 3) ? yb[int64_t(a) * nc + c0] : __builtin_nontemporal_load(u0bar + kk);
                 if constexpr (HAS_W) {
                     const double dq = qb[jpc[a]] - qb[c0];
-                    const double og = a == 1 ? dq : M.w(cyg) * dq * g.ih[a];
+                    const double og = a == 1 ? dq : wrow * dq * g.ih[a];
                     acc += T(double(ub[int64_t(a) * nc + c0]) - og);
                 }
                 if (mode >= 2) acc += out[a];
