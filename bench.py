@@ -242,7 +242,8 @@ def channel_timing(steps, warmup, modes=None):
     b = kernel_bytes(dom, n, 8)
     achieved = b / (kp[dom]["avg_ms"] * 1e-3) / 1e9
     out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                       "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": _traffic_record(dom),
+                       "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                       "traffic": _traffic_record("channel:" + dom),
                        "alg_bytes_per_launch": b, "avg_ms": kp[dom]["avg_ms"]}
     return out
 

@@ -5,6 +5,7 @@
       (adds per-variant averages from the run_kernel_trace.csv beside it; for a
       run of the float64 forward step only, whose dispatch order is fixed)
   python profile_summary.py traffic <fetch counter_collection.csv> <write counter_collection.csv> <out.md> <command...>
+  (after the mode, --workload=periodic|channel|channel_cg picks the kernel-variant table)
 
 `traffic` also updates profiles/traffic.json, the measured HBM bytes per
 launch that bench.py reports as roofline.traffic. Counters are calibrated with
@@ -27,20 +28,39 @@ from collections import defaultdict
 ROOT = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(ROOT, "paper_2604_18536_amd", "csrc")
 
-# template instance (prefix of the demangled name) -> (variant names in dispatch order, source files)
-VARIANT_ORDER = {
-    "void ins::k_stage_zm<double, true,": (["stage", "stage", "stage_last"], ["k_stage3d.hip", "k_common.hpp"]),
-    "void ins::k_stage_zm<double, false,": (["stage_first"], ["k_stage3d.hip", "k_common.hpp"]),
-    "void ins::k_fft_x_fwd<double, 3, 0,": (["fft_x_fwd_div"], ["k_fft.hip", "k_common.hpp"]),
-    "void ins::k_fft_strided<0,": (["fft_y_fwd"], ["k_fft.hip", "k_common.hpp"]),
-    "void ins::k_fft_strided<2,": (["fft_z_solve"], ["k_fft.hip", "k_common.hpp"]),
-    "void ins::k_fft_strided<1,": (["fft_y_inv"], ["k_fft.hip", "k_common.hpp"]),
-    "void ins::k_fft_x_inv<": (["fft_x_inv"], ["k_fft.hip", "k_common.hpp"]),
-    "void ins::k_apply_projection<double, 3>": (["apply_projection"], ["k_stencil.hip", "k_common.hpp"]),
-    # channel grid (walls in y): the two kernels of a CG iteration
-    "ins::k_cg_apply3": (["cg_apply"], ["k_walls.hip", "k_common.hpp", "ins_internal.hpp"]),
-    "void ins::k_cg_update<3>": (["cg_update"], ["k_walls.hip", "k_common.hpp", "ins_internal.hpp"]),
+# template instance (prefix of the demangled name) -> (variant names in dispatch order, source files),
+# per workload: the same kernel serves different steps on the periodic grid and on the channel
+# (the strided FFT pass is y there, z here), so channel records carry a "channel:" prefix.
+_WALL = ["k_walls.hip", "k_common.hpp", "ins_internal.hpp"]
+VARIANT_ORDERS = {
+    "periodic": {
+        "void ins::k_stage_zm<double, true,": (["stage", "stage", "stage_last"], ["k_stage3d.hip", "k_common.hpp"]),
+        "void ins::k_stage_zm<double, false,": (["stage_first"], ["k_stage3d.hip", "k_common.hpp"]),
+        "void ins::k_fft_x_fwd<double, 3, 0,": (["fft_x_fwd_div"], ["k_fft.hip", "k_common.hpp"]),
+        "void ins::k_fft_strided<0,": (["fft_y_fwd"], ["k_fft.hip", "k_common.hpp"]),
+        "void ins::k_fft_strided<2,": (["fft_z_solve"], ["k_fft.hip", "k_common.hpp"]),
+        "void ins::k_fft_strided<1,": (["fft_y_inv"], ["k_fft.hip", "k_common.hpp"]),
+        "void ins::k_fft_x_inv<": (["fft_x_inv"], ["k_fft.hip", "k_common.hpp"]),
+        "void ins::k_apply_projection<double, 3>": (["apply_projection"], ["k_stencil.hip", "k_common.hpp"]),
+    },
+    # channel, direct pressure solve (FFTs along x and z, tridiagonal solves along y)
+    "channel": {
+        "void ins::k_wall_stage_zm<double, true,": (["channel:stage", "channel:stage", "channel:stage_last"], _WALL),
+        "void ins::k_wall_stage_zm<double, false,": (["channel:stage_first"], _WALL),
+        "void ins::k_fft_x_fwd<double, 3, 3,": (["channel:fft_x_fwd_div"], ["k_fft.hip", "k_common.hpp"]),
+        "void ins::k_fft_strided<0,": (["channel:fft_z_fwd"], ["k_fft.hip", "k_common.hpp"]),
+        "void ins::k_channel_ysolve<": (["channel:channel_ysolve"], ["k_chsolve.hip", "k_common.hpp"]),
+        "void ins::k_fft_strided<1,": (["channel:fft_z_inv"], ["k_fft.hip", "k_common.hpp"]),
+        "void ins::k_fft_x_inv<": (["channel:fft_x_inv"], ["k_fft.hip", "k_common.hpp"]),
+        "void ins::k_wall_project<double, 3, false>": (["channel:wall_projection"], _WALL),
+    },
+    # channel, conjugate-gradient pressure solve: the two kernels of an iteration
+    "channel_cg": {
+        "ins::k_cg_apply3": (["channel:cg_apply"], _WALL),
+        "void ins::k_cg_update<512, 3>": (["channel:cg_update"], _WALL),
+    },
 }
+VARIANT_ORDER = VARIANT_ORDERS["periodic"]
 COPY = "ins::k_stream_copy"
 
 
@@ -52,7 +72,8 @@ def source_hash(files):
     return h.hexdigest()[:16]
 
 
-def trace(stats_csv, out_md, command, variants=False):
+def trace(stats_csv, out_md, command, variants=False, order=None):
+    order = order or VARIANT_ORDER
     rows = list(csv.DictReader(open(stats_csv)))
     lines = ["# rocprofv3 kernel trace summary", "", "Command:", "", "```", command, "```", "",
              "| kernel | calls | avg us | min us | max us | % time |", "|---|---|---|---|---|---|"]
@@ -68,7 +89,7 @@ def trace(stats_csv, out_md, command, variants=False):
         for r in csv.DictReader(open(tpath)):
             disp[r["Kernel_Name"].split("(")[0]].append(
                 (int(r["Dispatch_Id"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
-        for inst, (vnames, _) in VARIANT_ORDER.items():
+        for inst, (vnames, _) in order.items():
             names = [k for k in disp if k == inst or (inst.endswith((",", "<")) and k.startswith(inst))]
             durs = [d for _, d in sorted(x for k in names for x in disp[k])]
             for i, d in enumerate(durs):
@@ -91,7 +112,8 @@ def _per_dispatch(path, counter):
     return d
 
 
-def traffic(fetch_csv, write_csv, out_md, command, copy_bytes=None):
+def traffic(fetch_csv, write_csv, out_md, command, copy_bytes=None, order=None):
+    order = order or VARIANT_ORDER
     f = _per_dispatch(fetch_csv, "FETCH_SIZE")
     w = _per_dispatch(write_csv, "WRITE_SIZE")
     # copy calibration: the copy kernel reads and writes copy_bytes each
@@ -110,7 +132,7 @@ def traffic(fetch_csv, write_csv, out_md, command, copy_bytes=None):
     jpath = os.path.join(ROOT, "profiles", "traffic.json")
     if os.path.exists(jpath):
         rec = json.load(open(jpath))
-    for inst, (variants, srcs) in VARIANT_ORDER.items():
+    for inst, (variants, srcs) in order.items():
         # a key is the demangled name or, for kernels templated on the FFT plan, its prefix
         names = [k for k in f if k == inst or (inst.endswith((",", "<")) and k.startswith(inst))]
         if not names:
@@ -133,10 +155,14 @@ def traffic(fetch_csv, write_csv, out_md, command, copy_bytes=None):
 
 
 if __name__ == "__main__":
-    mode = sys.argv[1]
+    args = sys.argv[1:]
+    order = VARIANT_ORDERS["periodic"]
+    if len(args) > 1 and args[1].startswith("--workload="):
+        order = VARIANT_ORDERS[args.pop(1).split("=", 1)[1]]
+    mode = args[0]
     if mode in ("trace", "trace-variants"):
-        trace(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]), variants=mode == "trace-variants")
+        trace(args[1], args[2], " ".join(args[3:]), variants=mode == "trace-variants", order=order)
     elif mode == "traffic":
-        traffic(sys.argv[2], sys.argv[3], sys.argv[4], " ".join(sys.argv[5:]))
+        traffic(args[1], args[2], args[3], " ".join(args[4:]), order=order)
     else:
         raise SystemExit(__doc__)
