@@ -383,11 +383,19 @@ def cpu_baseline(n, nu, dt, u0_np, budget_s=30.0):
         u = O.step_rk4(u, h, nu, dt)
         steps = 2
     t = time.perf_counter() - t0
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), None)
+    except OSError:
+        pass
     return {
         "value": round(ncell * steps / t / 1e6, 4),
         "unit": "Mcell/s",
         "cores": 1,
         "kind": "oracle",
+        "host_cpu": model,
+        "host_nproc": os.cpu_count(),
         "sample": f"{steps} float64 RK4 step(s) of the {n[0]}x{n[1]}x{n[2]} field (numpy, single-threaded "
                   f"elementwise and FFT), {t:.1f} s",
     }
