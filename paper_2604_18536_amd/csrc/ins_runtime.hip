@@ -33,7 +33,7 @@ void hip_check(hipError_t e, const char* what) {
 
 constexpr int kMaxLen = 4096;
 constexpr int kBlockHost = 256; // must match kBlock
-constexpr size_t kMaxLds = 65536;
+constexpr size_t kMaxLds = 98304;  // LDS budget of one FFT workgroup (gfx950: 160 KB per CU)
 
 bool factor(int n, std::vector<int>& rad) {
     rad.clear();
@@ -853,7 +853,10 @@ bool setup_fft(ins_ctx c, const std::vector<int>& rx, const std::vector<int>& ry
     if (d == 3) build_twiddles(g.nz, rz, tw, c->pz);
     c->lnl_x = choose_lines(c->px, 16, 8, 1024);
     c->lnl_y = channel ? 0 : choose_lines(c->py, 16, 8, 512);
-    c->lnl_z = d == 3 ? choose_lines(c->pz, 16, 8, 512) : 0;
+    // the channel's z passes are plain forward / inverse transforms: 16-line batches
+    // (256-byte runs) measured 13% faster there; the periodic fused z solve and the y
+    // passes are faster with 8 lines of 256 threads
+    c->lnl_z = d == 3 ? choose_lines(c->pz, 16, channel ? 16 : 8, 512) : 0;
     if (!channel) {
         ins::FftPlan& last = d == 3 ? c->pz : c->py;
         ins::FftPlan& rev = d == 3 ? c->pz_rev : c->py_rev;
