@@ -497,6 +497,7 @@ def main():
         "traffic": _traffic_record(dom),
         "alg_bytes_per_launch": dom_bytes,
         "avg_ms": kprof[dom]["avg_ms"],
+        "frac_of_copy": round(achieved / copy_gbs, 4),  # against the measured streaming-copy rate
     }
     cpu = None if args.no_cpu else cpu_baseline(n, nu, dt, u0)
     les = None if args.no_les or args.config != "turb256" else les_closure_timing(args.steps, args.warmup)
@@ -548,6 +549,7 @@ def channel_main(args):
     torch.cuda.set_device(0)
     copy_gbs = stream_copy_gbs()
     ch = channel_timing(args.steps, args.warmup, args.modes)
+    ch["roofline"]["frac_of_copy"] = round(ch["roofline"]["achieved"] / copy_gbs, 4)
     main_mode = "fp64" if "fp64" in ch["modes"] else next(iter(ch["modes"]))
     line = {
         "metric": METRIC,

@@ -134,6 +134,23 @@ def test_kept_stages_and_agreement_with_cg():
     assert max_rel(host(s.step(u0, dt)), host(ucg)) < 1e-10
 
 
+@pytest.mark.parametrize("n", [(4, 2), (4, 3), (4, 2, 2), (6, 3, 4), (4, 2048)])
+def test_smallest_and_largest_channels(n):
+    """n_y = 2, 3 (one segment of two or three rows per line, n_x = 4: two complex
+    points per x row) and n_y = 2048, the largest the direct solve takes (64 segments
+    of 32 rows). The (0, 0) mode's uniform Neumann operator has condition number
+    1 / sin^2(pi / (2 n_y)); the bar is 20 eps kappa, at least 1e-11."""
+    s = _solver(n, gamma=0.0)
+    h = _h(n, 0.0)
+    kappa = 1.0 / np.sin(np.pi / (2 * n[1])) ** 2
+    tol = max(1e-11, 20 * np.finfo(float).eps * kappa)
+    r = S.random_scalar(n, 21)
+    assert max_rel(host(s.poisson_solve(dev(r))), W.poisson_solve(r, h)) < tol
+    assert max_rel(host(s.poisson_solve_vjp(dev(r))), W.poisson_solve_vjp(r, h)) < tol
+    u = S.channel_random(n, 22)
+    assert max_rel(host(s.project(dev(u))), W.project(u, h)[0]) < tol
+
+
 def test_solver_choice():
     from paper_2604_18536_amd import Solver
 
@@ -144,6 +161,9 @@ def test_solver_choice():
         s.set_pressure("fft")
     lo, hi = S.channel_box((22, 8, 8))
     s = Solver((22, 8, 8), 0.01, lo=lo, hi=hi, bc="walls")  # n_x / 2 = 11
+    assert s.pressure == "cg"
+    lo, hi = S.channel_box((4, 2049))
+    s = Solver((4, 2049), 0.01, lo=lo, hi=hi, bc="walls")  # n_y above the direct solve's 2048
     assert s.pressure == "cg"
     lo, hi = S.channel_box((16, 8, 8))
     s = Solver((16, 8, 8), 0.01, lo=lo, hi=hi, bc="walls")
