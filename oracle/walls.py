@@ -341,8 +341,16 @@ def convection(u, h):
     return out * dof_mask(tuple(reversed(u.shape[1:])))
 
 
-def rhs(u, h, nu):
-    return convection(u, h) + diffusion(u, h, nu)
+def rhs(u, h, nu, force=None):
+    """F(u) = C(u) + nu D(u) + f (App. A momentum equation, the forcing collected in F):
+    f a constant vector (the channel's driving body force, Sec. 5), added on the
+    velocity unknowns only."""
+    out = convection(u, h) + diffusion(u, h, nu)
+    if force is not None:
+        mask = dof_mask(tuple(reversed(u.shape[1:])))
+        for a in range(u.shape[0]):
+            out[a] += float(force[a]) * mask[a]
+    return out
 
 
 def laplacian(p, h):
@@ -559,23 +567,25 @@ def project_vjp(ubar_out, h):
 # right-hand side and projection.
 # ----------------------------------------------------------------------------
 
-def _fns(h, nu):
-    return dict(rhs_fn=lambda v: rhs(v, h, nu), project_fn=lambda v: project(v, h)[0])
+def _fns(h, nu, force=None):
+    return dict(rhs_fn=lambda v: rhs(v, h, nu, force), project_fn=lambda v: project(v, h)[0])
 
 
-def step_rk4(u0, h, nu, dt):
-    return ins.step_rk4(u0, h, nu, dt, **_fns(h, nu))
+def step_rk4(u0, h, nu, dt, force=None):
+    return ins.step_rk4(u0, h, nu, dt, **_fns(h, nu, force))
 
 
-def step_wray3(u0, h, nu, dt):
-    return ins.step_wray3(u0, h, nu, dt, **_fns(h, nu))
+def step_wray3(u0, h, nu, dt, force=None):
+    return ins.step_wray3(u0, h, nu, dt, **_fns(h, nu, force))
 
 
-def step_rk4_vjp(u0, u1bar, h, nu, dt):
+# A constant force has no Jacobian: it enters the pullbacks only through the
+# forward stages they linearise about.
+def step_rk4_vjp(u0, u1bar, h, nu, dt, force=None):
     return ins.step_rk4_vjp(u0, u1bar, h, nu, dt, rhs_vjp_fn=lambda v, fb: rhs_vjp(v, fb, h, nu),
-                            project_vjp_fn=lambda v: project_vjp(v, h), **_fns(h, nu))
+                            project_vjp_fn=lambda v: project_vjp(v, h), **_fns(h, nu, force))
 
 
-def step_wray3_vjp(u0, u1bar, h, nu, dt):
+def step_wray3_vjp(u0, u1bar, h, nu, dt, force=None):
     return ins.step_wray3_vjp(u0, u1bar, h, nu, dt, rhs_vjp_fn=lambda v, fb: rhs_vjp(v, fb, h, nu),
-                              project_vjp_fn=lambda v: project_vjp(v, h), **_fns(h, nu))
+                              project_vjp_fn=lambda v: project_vjp(v, h), **_fns(h, nu, force))
