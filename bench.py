@@ -149,6 +149,8 @@ def run_mode(n, nu, dt, precision, steps, warmup, u0_np, adjoint, scheme="rk4", 
                    pressure=channel["pressure"])
         if channel.get("faces") is not None:
             s.set_y_faces(channel["faces"])
+        if channel.get("force") is not None:
+            s.set_body_force(channel["force"])
         s.cg_set(rtol=channel["rtol"], maxiter=20000, check_every=channel["check"])
     u0 = torch.as_tensor(u0_np).to(device="cuda", dtype=s.dtype).contiguous()
     s.project(u0, out=u0)
@@ -181,9 +183,14 @@ def run_mode(n, nu, dt, precision, steps, warmup, u0_np, adjoint, scheme="rk4", 
 
 CHANNEL = {"n": (256, 256, 256), "nu": 1.0 / 1000.0, "dt": 1e-3, "seed": 5, "rtol": 1e-8, "check": 16,
            "gamma": 1.5, "modes": "fp64,fp64_adj,fp64_adj_kept,fp32,fp64_tanh,fp64_tanh_adj,fp64_cg,fp64_tanh_cg"}
+# the paper's turbulent channel (Sec. 5): Re_tau = 180, box 4pi x 2 x 4pi/3, nu = 1/180, driven by
+# f = (1, 0, 0), its uniform DNS grid 512 x 1024 x 256; dt from the CFL of the initial field
+CHANNEL_DNS = {"n": (512, 1024, 256), "nu": 1.0 / 180.0, "dt": 2e-4, "seed": 7, "rtol": 1e-8, "check": 16,
+               "gamma": 1.5, "box": ((0.0, 0.0, 0.0), (4 * math.pi, 2.0, 4 * math.pi / 3)),
+               "force": (1.0, 0.0, 0.0), "bulk": 15.6, "noise": 0.1, "modes": "fp64,fp32,fp64_adj_kept"}
 
 
-def channel_timing(steps, warmup, modes=None):
+def channel_timing(steps, warmup, modes=None, cfg=None):
     """Channel flow (no-slip walls at both y ends, x and z periodic) on a 256^3
     grid over [0, 2pi] x [0, 2] x [0, pi]: laminar profile of bulk velocity 1
     plus a 20% solenoidal perturbation, nu = 1/1000, dt = 1e-3. Pressure by the
@@ -193,19 +200,24 @@ def channel_timing(steps, warmup, modes=None):
     (gamma = 1.5, cells 3x finer at the walls than in the centre)."""
     import synth as S
 
-    cfg = dict(CHANNEL)
+    cfg = dict(CHANNEL if cfg is None else cfg)
     n = cfg["n"]
-    lo, hi = S.channel_box(n)
-    u0 = S.channel_ic(n, cfg["seed"])
+    lo, hi = S.channel_box(n) if "box" not in cfg else (list(cfg["box"][0]), list(cfg["box"][1]))
+    u0 = S.channel_ic(n, cfg["seed"], bulk=cfg.get("bulk", 1.0), noise=cfg.get("noise", 0.2), box=(lo, hi))
+    print(f"[bench] channel initial field ready {n}", file=sys.stderr, flush=True)
     ncell = n[0] * n[1] * n[2]
-    out = {"workload": f"channel {n[0]}x{n[1]}x{n[2]}, walls at y=0,2, nu=1/{round(1 / cfg['nu'])}, "
-                       f"dt={cfg['dt']}, direct pressure solve (CG rtol={cfg['rtol']:g} in *_cg modes)",
+    box = "x".join(f"{v:.4g}" for v in hi)
+    force = f", body force {tuple(cfg['force'])}" if cfg.get("force") else ""
+    out = {"workload": f"channel {n[0]}x{n[1]}x{n[2]}, box {box}, walls at y=0,{hi[1]:g}, "
+                       f"nu=1/{round(1 / cfg['nu'])}, dt={cfg['dt']}{force}, direct pressure solve "
+                       f"(CG rtol={cfg['rtol']:g} in *_cg modes)",
            "modes": {}, "kernels": {}}
     for mode in (modes or cfg["modes"]).split(","):
         precision = "fp64" if mode.startswith("fp64") else "fp32"
         adjoint = "_adj" in mode
         cg = mode.endswith("_cg")
-        ch = {"lo": lo, "hi": hi, "rtol": cfg["rtol"], "check": cfg["check"], "pressure": "cg" if cg else "fft"}
+        ch = {"lo": lo, "hi": hi, "rtol": cfg["rtol"], "check": cfg["check"], "pressure": "cg" if cg else "fft",
+              "force": cfg.get("force")}
         if "_tanh" in mode:
             ch["faces"] = S.tanh_faces(n[1], lo[1], hi[1], cfg["gamma"])
         k_steps, k_warm = (min(steps, 2), min(warmup, 1)) if cg else (steps, warmup)
@@ -406,14 +418,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="turb256", choices=sorted(CONFIGS) + ["channel256"])
+    ap.add_argument("--config", default="turb256", choices=sorted(CONFIGS) + ["channel256", "channel_dns"])
     ap.add_argument("--n", type=int, default=None, help="override the grid size of the config")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-les", action="store_true", help="skip the closure-LES and small-grid timings")
     ap.add_argument("--no-channel", action="store_true", help="skip the channel (wall-bounded) timing")
     ap.add_argument("--modes", default=None)
     args = ap.parse_args()
-    if args.config == "channel256":
+    if args.config in ("channel256", "channel_dns"):
         return channel_main(args)
     cfg = dict(CONFIGS[args.config])
     if args.n is not None:
@@ -548,7 +560,7 @@ def channel_main(args):
         sys.exit(1)
     torch.cuda.set_device(0)
     copy_gbs = stream_copy_gbs()
-    ch = channel_timing(args.steps, args.warmup, args.modes)
+    ch = channel_timing(args.steps, args.warmup, args.modes, CHANNEL_DNS if args.config == "channel_dns" else None)
     ch["roofline"]["frac_of_copy"] = round(ch["roofline"]["achieved"] / copy_gbs, 4)
     main_mode = "fp64" if "fp64" in ch["modes"] else next(iter(ch["modes"]))
     line = {

@@ -191,6 +191,15 @@ const char* ins_last_error(void);
  * or non-finite coordinates. */
 ins_status ins_set_y_faces(ins_ctx ctx, const double* faces);
 
+/* Constant body force (the forcing term that F(u) collects, App. A momentum
+ * equation; the channel of Sec. 5 is driven by f = (1, 0, 0)): force is a host
+ * array of dim values, added to F on the velocity unknowns by ins_rhs and every
+ * step from the next call on (default 0). A constant has no Jacobian, so the
+ * pullbacks change only through the forward stages they linearise about. A
+ * wall-normal component is balanced by the pressure. INS_ERR_UNSUPPORTED on a
+ * periodic context; INS_ERR_INVALID for a null or non-finite force. */
+ins_status ins_set_body_force(ins_ctx ctx, const double* force);
+
 /* Defaults: rtol 1e-10, maxiter 20000, check_every 16. INS_ERR_UNSUPPORTED
  * on a periodic context; INS_ERR_INVALID for rtol < 0, maxiter < 1 or
  * check_every < 0. */
@@ -215,7 +224,8 @@ ins_status ins_get_pressure_solver(ins_ctx ctx, int* solver);
  * Forward operators (App. B kernels; Sec. 2.5)
  * ------------------------------------------------------------------------- */
 
-/* f = C(u) + nu * Lap(u) (+ m_theta(u) when a closure is set): the
+/* f = C(u) + nu * Lap(u) (+ m_theta(u) when a closure is set; + the body
+ * force on a channel, see ins_set_body_force): the
  * convection of eq. conv-kernel (uniform weights 1/2, skew-symmetric form)
  * and the diffusion of eq. diff-kernel. u, f: velocity fields. */
 ins_status ins_rhs(ins_ctx ctx, const void* u, void* f);

@@ -72,6 +72,7 @@ _SIGS = {
     "ins_set_y_faces": ([_P, C.POINTER(C.c_double)]),
     "ins_cg_info": ([_P, C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     "ins_set_pressure_solver": ([_P, C.c_int]),
+    "ins_set_body_force": ([_P, C.POINTER(C.c_double)]),
     "ins_get_pressure_solver": ([_P, C.POINTER(C.c_int)]),
     "ins_step_vjp_saved": ([_P, C.c_int, _P, _P, _P, _P, _P, _D]),
     "ins_scheme_stage_count": ([C.c_int]),

@@ -29,6 +29,8 @@ struct Grid {
     // row j, d_j the distance of the centres around y-face j (mirrored ghosts:
     // d_{-1} = w_0, d_{n_y-1} = w_{n_y-1}), theta_j = w_j / (w_j + w_{j+1}).
     const double* ym;
+    // channel grid only: constant body force per component (the forcing term of F), 0 by default
+    double force[3];
 };
 
 // One 1D FFT length: Stockham stages with their radices and twiddle tables.

@@ -1335,6 +1335,17 @@ ins_status ins_set_y_faces(ins_ctx ctx, const double* faces) {
     });
 }
 
+ins_status ins_set_body_force(ins_ctx ctx, const double* force) {
+    return guarded([&] {
+        checked(ctx);
+        need(force, "force");
+        if (!ctx->walls) raise(INS_ERR_UNSUPPORTED, "the body force is a channel (INS_BC_WALLS_Y) feature");
+        for (int a = 0; a < ctx->g.dim; ++a)
+            if (!std::isfinite(force[a])) raise(INS_ERR_INVALID, "force components must be finite");
+        for (int a = 0; a < 3; ++a) ctx->g.force[a] = a < ctx->g.dim ? force[a] : 0.0;
+    });
+}
+
 ins_status ins_cg_info(ins_ctx ctx, int* iterations, double* relres) {
     return guarded([&] {
         checked(ctx);

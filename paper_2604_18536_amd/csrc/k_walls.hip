@@ -156,8 +156,10 @@ struct RowM {
     }
 };
 
-// F^a at the current cell (row y, metrics R): diffusion (eq. diff-kernel) and
-// convection (eq. conv-kernel with the weights described above) on the channel grid.
+// F^a at the current cell (row y, metrics R): diffusion (eq. diff-kernel),
+// convection (eq. conv-kernel with the weights described above) and the constant
+// body force on the channel grid. The pullback below has no force term: a
+// constant has no Jacobian.
 template <typename T, int DIM, class Src>
 __device__ __forceinline__ void rhs_cell_wall(const Grid& g, const Src& U, const Nb& nb, const RowM& R, T F[DIM]) {
     const T iwj = T(R.iw[1]), iwp = T(R.iw[2]), idj = T(R.id[1]), idm = T(R.id[0]), th = T(R.th);
@@ -190,7 +192,7 @@ __device__ __forceinline__ void rhs_cell_wall(const Grid& g, const Src& U, const
             const T s = b != 1 ? T(g.ih[b]) : (a == 1 ? idj : iwj);
             conv -= (fr - fl) * s;
         }
-        F[a] = conv + T(g.nu) * diff;
+        F[a] = conv + T(g.nu) * diff + T(g.force[a]);
     }
 }
 

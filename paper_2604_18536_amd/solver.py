@@ -139,6 +139,14 @@ class Solver:
         L.call("ins_get_pressure_solver", self._ctx, C.byref(v))
         return "cg" if v.value == L.INS_PRESSURE_CG else "fft"
 
+    def set_body_force(self, force):
+        """Constant body force (dim values) added to F on the channel, e.g. (1, 0, 0)."""
+        if len(force) != self.dim:
+            raise ValueError(f"force must have {self.dim} components")
+        f = (C.c_double * self.dim)(*[float(v) for v in force])
+        L.call("ins_set_body_force", self._ctx, f)
+        self.body_force = tuple(float(v) for v in force)
+
     def cg_set(self, rtol=1e-10, maxiter=20000, check_every=16):
         """Stopping rule of the channel's conjugate-gradient pressure solves."""
         L.call("ins_cg_set", self._ctx, float(rtol), int(maxiter), int(check_every))

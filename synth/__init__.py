@@ -297,17 +297,18 @@ def _wall_potential(n, rng, modes, lo, hi, yoff):
     return psi
 
 
-def channel_ic(n, seed, bulk=1.0, noise=0.2, modes=12):
+def channel_ic(n, seed, bulk=1.0, noise=0.2, modes=12, box=None):
     """Laminar profile u^x = 1.5 bulk (1 - eta^2), eta = 2 (y - lo_y) / L_y - 1, plus a
     perturbation that is the discrete curl of a random potential vanishing on both walls.
 
     The curl is taken on the staggered positions (potential on cell edges, j the
     y-face index, the row below the grid being the lower wall where it is 0), so the
     field has zero discrete divergence and zero normal velocity on the walls.
-    ``noise`` is the RMS of the perturbation relative to the bulk velocity.
+    ``noise`` is the RMS of the perturbation relative to the bulk velocity; ``box`` =
+    (lo, hi) replaces the default box of ``channel_box``.
     """
     d = len(n)
-    lo, hi = channel_box(n)
+    lo, hi = channel_box(n) if box is None else box
     h = spacing(n, lo, hi)
     rng = np.random.default_rng(seed)
     shape = tuple(reversed(n))

@@ -32,7 +32,8 @@ def test_header_declares_the_boundary():
                  "ins_step_rk4", "ins_rhs_vjp", "ins_divergence_vjp", "ins_poisson_solve_vjp", "ins_project_vjp",
                  "ins_step_rk4_vjp", "ins_step_wray3", "ins_step_wray3_vjp", "ins_eddy_set", "ins_eddy_forward",
                  "ins_eddy_backward", "ins_step_save", "ins_step_vjp_saved", "ins_scheme_stage_count", "ins_cg_set",
-                 "ins_cg_info", "ins_set_y_faces", "ins_set_pressure_solver", "ins_get_pressure_solver"]:
+                 "ins_cg_info", "ins_set_y_faces", "ins_set_pressure_solver", "ins_get_pressure_solver",
+                 "ins_set_body_force"]:
         assert must in names
 
 
@@ -97,6 +98,7 @@ def test_null_context_is_rejected(lib):
     assert lib.ins_cg_info(p, C.byref(it), C.byref(rel)) == -1
     assert lib.ins_set_y_faces(p, C.cast(p, C.POINTER(C.c_double))) == -1
     assert lib.ins_set_pressure_solver(p, 1) == -1
+    assert lib.ins_set_body_force(p, C.cast(p, C.POINTER(C.c_double))) == -1
     assert lib.ins_get_pressure_solver(p, C.byref(it)) == -1
     assert b"null" in lib.ins_last_error()
     assert lib.ins_destroy(p) == 0
