@@ -39,8 +39,6 @@ namespace ins {
 
 namespace {
 
-constexpr int kYsNth = 256;
-
 // Sum over the P segments of line l of per-thread values, in a fixed order so
 // that every thread of the line gets the same bits. Called by all threads.
 template <int P, int L>
@@ -48,7 +46,7 @@ __device__ __forceinline__ cd line_sum(cd v, cd* red, int s, int l) {
     red[s * L + l] = v;
     __syncthreads();
     cd t = {0.0, 0.0};
-#pragma unroll
+#pragma unroll 4
     for (int q = 0; q < P; ++q) t = cadd(t, red[q * L + l]);
     __syncthreads();
     return t;
@@ -56,15 +54,13 @@ __device__ __forceinline__ cd line_sum(cd v, cd* red, int s, int l) {
 
 }  // namespace
 
-// One workgroup: L = 256 / P lines (adjacent k_x at one k_z of one field), P
-// threads per line (thread = s L + l: segment s of line l), at most MR rows
-// per segment. ADJ: the transpose of the solve (see launch_channel_ysolve).
-template <int MR, int P, bool ADJ>
-__global__ __launch_bounds__(kYsNth) void k_channel_ysolve(Grid g, cd* __restrict__ spec,
-                                                           const double* __restrict__ lamx,
-                                                           const double* __restrict__ lamz, double wysum,
-                                                           double scale) {
-    constexpr int L = kYsNth / P;
+// One workgroup of NT threads: L = NT / P lines (adjacent k_x at one k_z of one
+// field), P threads per line (thread = s L + l: segment s of line l), at most MR
+// rows per segment. ADJ: the transpose of the solve (see launch_channel_ysolve).
+template <int MR, int P, int NT, bool ADJ>
+__global__ __launch_bounds__(NT) void k_channel_ysolve(Grid g, cd* __restrict__ spec, const double* __restrict__ lamx,
+                                                       const double* __restrict__ lamz, double wysum, double scale) {
+    constexpr int L = NT / P;
     __shared__ double ra[2 * P * L], rc[2 * P * L];
     __shared__ cd rd[2 * P * L];
     __shared__ cd red[P * L];
@@ -297,30 +293,34 @@ hipError_t launch_channel_ysolve(const Grid& g, cd* spec, const double* lamx, co
                                  double scale, bool adj, hipStream_t s) {
     int mr = 0;
     const int p = channel_ysolve_segments(g.ny, mr);
-    const int lpw = kYsNth / p;
+    // 512 threads when a line takes 32 or 64 segments of at most 16 rows, so a
+    // workgroup still holds 16 or 8 adjacent k_x (row accesses of 256 or 128
+    // contiguous bytes); 32-row segments keep 256 threads (register budget)
+    const int nt = (p >= 32 && mr == 16) ? 512 : 256;
+    const int lpw = nt / p;
     const int nxh = g.nx / 2 + 1;
     const int nblk = ((nxh + lpw - 1) / lpw) * g.nz * g.batch;
-#define INS_YS(MR, P)                                                                                            \
+#define INS_YS(MR, P, NT)                                                                                        \
     do {                                                                                                         \
         if (adj)                                                                                                 \
-            hipLaunchKernelGGL((k_channel_ysolve<MR, P, true>), dim3(nblk), dim3(kYsNth), 0, s, g, spec, lamx,  \
+            hipLaunchKernelGGL((k_channel_ysolve<MR, P, NT, true>), dim3(nblk), dim3(NT), 0, s, g, spec, lamx,  \
                                lamz, wysum, scale);                                                              \
         else                                                                                                     \
-            hipLaunchKernelGGL((k_channel_ysolve<MR, P, false>), dim3(nblk), dim3(kYsNth), 0, s, g, spec, lamx, \
+            hipLaunchKernelGGL((k_channel_ysolve<MR, P, NT, false>), dim3(nblk), dim3(NT), 0, s, g, spec, lamx, \
                                lamz, wysum, scale);                                                              \
     } while (0)
     if (mr == 16) {
         switch (p) {
-            case 1: INS_YS(16, 1); break;
-            case 2: INS_YS(16, 2); break;
-            case 4: INS_YS(16, 4); break;
-            case 8: INS_YS(16, 8); break;
-            case 16: INS_YS(16, 16); break;
-            case 32: INS_YS(16, 32); break;
-            default: INS_YS(16, 64); break;
+            case 1: INS_YS(16, 1, 256); break;
+            case 2: INS_YS(16, 2, 256); break;
+            case 4: INS_YS(16, 4, 256); break;
+            case 8: INS_YS(16, 8, 256); break;
+            case 16: INS_YS(16, 16, 256); break;
+            case 32: INS_YS(16, 32, 512); break;
+            default: INS_YS(16, 64, 512); break;
         }
     } else {
-        INS_YS(32, 64);
+        INS_YS(32, 64, 256);
     }
 #undef INS_YS
     return hipGetLastError();
