@@ -188,6 +188,9 @@ CHANNEL = {"n": (256, 256, 256), "nu": 1.0 / 1000.0, "dt": 1e-3, "seed": 5, "rto
 CHANNEL_DNS = {"n": (512, 1024, 256), "nu": 1.0 / 180.0, "dt": 2e-4, "seed": 7, "rtol": 1e-8, "check": 16,
                "gamma": 1.5, "box": ((0.0, 0.0, 0.0), (4 * math.pi, 2.0, 4 * math.pi / 3)),
                "force": (1.0, 0.0, 0.0), "bulk": 15.6, "noise": 0.1, "modes": "fp64,fp32,fp64_adj_kept"}
+# the same channel at the reference DNS resolution 512 x 256 x 256 with tanh stretching in y, first
+# cell Delta y+ = 0.49 (Sec. 5): the run the paper's sparse LDL^T factorisation had no memory for
+CHANNEL_VK = dict(CHANNEL_DNS, n=(512, 256, 256), seed=8, first_width_plus=0.49)
 
 
 def channel_timing(steps, warmup, modes=None, cfg=None):
@@ -220,6 +223,10 @@ def channel_timing(steps, warmup, modes=None, cfg=None):
               "force": cfg.get("force")}
         if "_tanh" in mode:
             ch["faces"] = S.tanh_faces(n[1], lo[1], hi[1], cfg["gamma"])
+        if cfg.get("first_width_plus"):  # stretched in every mode, first cell in wall units (u_tau = 1)
+            gam = S.tanh_gamma(n[1], hi[1] - lo[1], cfg["first_width_plus"] * cfg["nu"])
+            ch["faces"] = S.tanh_faces(n[1], lo[1], hi[1], gam)
+            out["tanh_gamma"] = round(gam, 6)
         k_steps, k_warm = (min(steps, 2), min(warmup, 1)) if cg else (steps, warmup)
         print(f"[bench] channel {mode} starts", file=sys.stderr, flush=True)
         ms, ms_p, prof, ok, ws = run_mode(n, cfg["nu"], cfg["dt"], precision, k_steps, k_warm, u0, adjoint, "rk4",
@@ -418,14 +425,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="turb256", choices=sorted(CONFIGS) + ["channel256", "channel_dns"])
+    ap.add_argument("--config", default="turb256",
+                    choices=sorted(CONFIGS) + ["channel256", "channel_dns", "channel_vk"])
     ap.add_argument("--n", type=int, default=None, help="override the grid size of the config")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-les", action="store_true", help="skip the closure-LES and small-grid timings")
     ap.add_argument("--no-channel", action="store_true", help="skip the channel (wall-bounded) timing")
     ap.add_argument("--modes", default=None)
     args = ap.parse_args()
-    if args.config in ("channel256", "channel_dns"):
+    if args.config in ("channel256", "channel_dns", "channel_vk"):
         return channel_main(args)
     cfg = dict(CONFIGS[args.config])
     if args.n is not None:
@@ -560,7 +568,8 @@ def channel_main(args):
         sys.exit(1)
     torch.cuda.set_device(0)
     copy_gbs = stream_copy_gbs()
-    ch = channel_timing(args.steps, args.warmup, args.modes, CHANNEL_DNS if args.config == "channel_dns" else None)
+    presets = {"channel256": None, "channel_dns": CHANNEL_DNS, "channel_vk": CHANNEL_VK}
+    ch = channel_timing(args.steps, args.warmup, args.modes, presets[args.config])
     ch["roofline"]["frac_of_copy"] = round(ch["roofline"]["achieved"] / copy_gbs, 4)
     main_mode = "fp64" if "fp64" in ch["modes"] else next(iter(ch["modes"]))
     line = {

@@ -349,6 +349,25 @@ def channel_random(n, seed):
     return u
 
 
+def tanh_gamma(ny, length, first_width):
+    """Stretching parameter of ``tanh_faces`` whose first (and last) cell has the given
+    width, by bisection (the width decreases monotonically as gamma grows)."""
+    def w0(g):
+        return 0.5 * length * (1.0 + np.tanh(g * (2.0 / ny - 1.0)) / np.tanh(g))
+    if not first_width < length / ny:
+        raise ValueError("first_width must be below the uniform width")
+    a, b = 1e-6, 1.0
+    while w0(b) > first_width:
+        b *= 2.0
+    for _ in range(200):
+        m = 0.5 * (a + b)
+        if w0(m) > first_width:
+            a = m
+        else:
+            b = m
+    return 0.5 * (a + b)
+
+
 def tanh_faces(ny, lo, hi, gamma):
     """y-face coordinates of the hyperbolic-tangent grid (Sec. 2.1 non-uniform grids,
     eq. tanh-grid): clustered at both ends, stretching set by gamma > 0."""

@@ -91,3 +91,20 @@ def test_force_setting():
     p = Solver(n, 0.01)
     with pytest.raises(RuntimeError, match="INS_ERR_UNSUPPORTED"):
         p.set_body_force((1.0, 0.0, 0.0))
+
+
+def test_fp32_mode_with_force():
+    from paper_2604_18536_amd import Solver
+
+    n = (24, 13, 6)
+    nu, dt = 0.02, 5e-3
+    h, faces = _box(n, 1.4)
+    f = (1.0, 0.0, -0.5)
+    lo, hi = S.channel_box(n)
+    s = Solver(n, nu=nu, precision="fp32", lo=lo, hi=hi, bc="walls")
+    s.set_y_faces(faces)
+    s.set_body_force(f)
+    u0 = np.asarray(W.project(S.channel_ic(n, 6), h)[0], dtype=np.float32).astype(np.float64)
+    u1 = host(s.step(dev(u0, torch.float32), dt))
+    ref = W.step_rk4(u0, h, nu, dt, force=f)
+    assert np.linalg.norm(u1 - ref) / np.linalg.norm(ref) < 1e-5

@@ -335,3 +335,13 @@ def test_step_pullbacks_by_finite_differences(scheme):
         eps = 1e-5
         fd = _dot(ubar, (step(u0 + eps * v, h, nu, dt) - step(u0 - eps * v, h, nu, dt)) / (2 * eps))
         assert abs(fd - _dot(g, v)) < 1e-8 * np.abs(g * v).sum()
+
+
+def test_tanh_gamma_gives_the_requested_first_cell():
+    for ny, length, w0 in [(256, 2.0, 0.49 / 180), (64, 2.0, 0.01), (9, 1.0, 0.05)]:
+        g = S.tanh_gamma(ny, length, w0)
+        w = np.diff(S.tanh_faces(ny, 0.0, length, g))
+        assert abs(w[0] - w0) < 1e-12 * length and abs(w[-1] - w0) < 1e-12 * length
+        assert np.isclose(w.min(), w0, rtol=1e-12, atol=0) and np.isclose(w.sum(), length)
+    with pytest.raises(ValueError):
+        S.tanh_gamma(16, 2.0, 0.2)
