@@ -31,6 +31,10 @@ struct Grid {
     const double* ym;
     // channel grid only: constant body force per component (the forcing term of F), 0 by default
     double force[3];
+    // row stride of the half spectrum [batch][nz][ny][sx]: n_x/2 + 1 rounded up to a
+    // multiple of 8, so every row, and every 8-column chunk of the strided passes,
+    // starts on a 128-byte boundary (columns beyond n_x/2 are never touched)
+    int sx;
 };
 
 // One 1D FFT length: Stockham stages with their radices and twiddle tables.

@@ -908,8 +908,7 @@ bool setup_fft(ins_ctx c, const std::vector<int>& rx, const std::vector<int>& ry
     c->pz_rev.tw = c->d_tw;
     for (int a = 0; a < 3; ++a) c->st.lam[a] = c->d_lam + off[a];
     c->st.inv_ncell = 1.0 / double(g.ncell);
-    const size_t nxh = size_t(g.nx / 2 + 1);
-    c->spec = static_cast<cd*>(c->alloc(size_t(g.batch) * g.nz * g.ny * nxh * sizeof(cd)));
+    c->spec = static_cast<cd*>(c->alloc(size_t(g.batch) * g.nz * g.ny * g.sx * sizeof(cd)));
     return true;
 }
 
@@ -958,6 +957,7 @@ ins_status ins_create(const ins_grid* grid, ins_bc bc, double nu, ins_dtype dtyp
             g.ih2[a] = a < d ? 1.0 / (h * h) : 0.0;
         }
         g.nu = nu;
+        g.sx = ((g.nx / 2 + 1) + 7) / 8 * 8;
 
         if (walls) {
             // channel grid: CG workspace instead of FFT plans and spectrum

@@ -133,8 +133,8 @@ hipError_t launch_face_filter(const Grid& fine, int f, const T* u, T* uc, hipStr
 template hipError_t launch_face_filter<double>(const Grid&, int, const double*, double*, hipStream_t);
 template hipError_t launch_face_filter<float>(const Grid&, int, const float*, float*, hipStream_t);
 
-// Shell binning of one half spectrum [batch][nz][ny][nx/2+1]: every stored kx in
-// (0, nx/2) stands for the pair kx, -kx and counts twice.
+// Shell binning of one half spectrum [batch][nz][ny][sx] (columns 0 .. nx/2 in
+// use): every stored kx in (0, nx/2) stands for the pair kx, -kx and counts twice.
 __global__ __launch_bounds__(kBlock) void k_spectrum_bins(Grid g, const cd* __restrict__ spec, double* __restrict__ bins,
                                                             int nbins) {
     const int nxh = g.nx / 2 + 1;
@@ -151,7 +151,7 @@ __global__ __launch_bounds__(kBlock) void k_spectrum_bins(Grid g, const cd* __re
     const double kk = sqrt(double(kx) * kx + double(ky) * ky + double(kz) * kz);
     const int shell = int(floor(kk + 0.5));
     if (shell >= nbins) return;
-    const cd v = spec[t];
+    const cd v = spec[(int64_t(b) * g.nz * g.ny + int64_t(kz0) * g.ny + ky0) * g.sx + kx];
     const double w = (kx == 0 || 2 * kx == g.nx) ? 1.0 : 2.0;
     const double n = double(g.ncell);
     atomicAdd(&bins[int64_t(b) * nbins + shell], 0.5 * w * (v.x * v.x + v.y * v.y) / (n * n));

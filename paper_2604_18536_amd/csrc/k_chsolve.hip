@@ -80,12 +80,12 @@ __global__ __launch_bounds__(NT) void k_channel_ysolve(Grid g, cd* __restrict__ 
     const int j0 = s * ny / P;
     const int m = (s + 1) * ny / P - j0;  // >= 2
     const double lam = valid ? lamx[kx] + lamz[kz] : 1.0;
-    cd* line = spec + int64_t(outer) * ny * nxh + (valid ? kx : 0);
+    cd* line = spec + int64_t(outer) * ny * g.sx + (valid ? kx : 0);
 
     cd D[MR];
     double A[MR], C[MR];
 #pragma unroll
-    for (int i = 0; i < MR; ++i) D[i] = (valid && i < m) ? line[int64_t(j0 + i) * nxh] : cd{0.0, 0.0};
+    for (int i = 0; i < MR; ++i) D[i] = (valid && i < m) ? line[int64_t(j0 + i) * g.sx] : cd{0.0, 0.0};
 
     // right-hand side in the symmetric form, w_j r_j
     if (ADJ && wg_zero) {
@@ -275,7 +275,7 @@ __global__ __launch_bounds__(NT) void k_channel_ysolve(Grid g, cd* __restrict__ 
     if (valid) {
 #pragma unroll
         for (int i = 0; i < MR; ++i)
-            if (i < m) line[int64_t(j0 + i) * nxh] = cscale(X[i], scale);
+            if (i < m) line[int64_t(j0 + i) * g.sx] = cscale(X[i], scale);
     }
 }
 

@@ -456,7 +456,7 @@ __global__ __launch_bounds__(NTH) void k_fft_x_fwd(Grid g, const T* __restrict__
         const cd e = cscale(cadd(zk, zc), 0.5);
         const cd dd = csub(zk, zc);
         const cd o = {0.5 * dd.y, -0.5 * dd.x};
-        spec[int64_t(row) * M1 + k] = cadd(e, cmul(post[k], o));
+        spec[int64_t(row) * g.sx + k] = cadd(e, cmul(post[k], o));
     }
 }
 
@@ -470,13 +470,13 @@ __global__ __launch_bounds__(NTH) void k_fft_x_inv(Grid g, const cd* __restrict_
     extern __shared__ cd lds[];
     const int nl = 1 << lnl;
     const int ls = nl + P.pad;
-    const int M = P.n, M1 = M + 1;
+    const int M = P.n;
     const int nrows = g.batch * g.nz * g.ny;
     const int row0 = xcd_logical(blockIdx.x, gridDim.x) * nl;
     auto load = [&](int l, int k) INS_INLINE -> cd {
         const int row = row0 + l;
         if (row >= nrows) return cd{0.0, 0.0};
-        const cd* sr = spec + int64_t(row) * M1;
+        const cd* sr = spec + int64_t(row) * g.sx;
         const cd xk = sr[k];
         const cd xc = cconj(sr[M - k]);
         const cd e = cadd(xk, xc);
@@ -493,7 +493,7 @@ __global__ __launch_bounds__(NTH) void k_fft_x_inv(Grid g, const cd* __restrict_
 }
 
 // Strided complex pass along y (axis 1) or z (axis 2) of the half spectrum
-// [batch][n_z][n_y][n_x/2+1]. MODE 0 forward, 1 inverse, 2 forward + divide +
+// [batch][n_z][n_y][sx] (columns 0 .. n_x/2 in use). MODE 0 forward, 1 inverse, 2 forward + divide +
 // inverse. Columns kx < n_x/2 go in chunks of nl adjacent kx per workgroup (each
 // access a contiguous run of nl values); the Nyquist column kx = n_x/2 is taken
 // by extra workgroups, nl lines of it (adjacent values of the other non-x
@@ -515,9 +515,9 @@ __global__ __launch_bounds__(NTH) void k_fft_strided(Grid g, cd* __restrict__ sp
     const int nfix = axis == 1 ? g.nz : g.ny;  // the other non-x index
     const int nouter = g.batch * nfix;
     const int wg = xcd_logical(blockIdx.x, gridDim.x);
-    const int64_t plane = int64_t(g.nz) * g.ny * nxh;                         // one batch entry
-    const int64_t stride = axis == 1 ? int64_t(nxh) : int64_t(nxh) * g.ny;   // along the line
-    const int64_t fstride = axis == 1 ? int64_t(nxh) * g.ny : int64_t(nxh);  // along the other index
+    const int64_t plane = int64_t(g.nz) * g.ny * g.sx;                          // one batch entry
+    const int64_t stride = axis == 1 ? int64_t(g.sx) : int64_t(g.sx) * g.ny;   // along the line
+    const int64_t fstride = axis == 1 ? int64_t(g.sx) * g.ny : int64_t(g.sx);  // along the other index
     int64_t lb0, lstep;
     int kx0, kxstep, fk0, fkstep, nvalid;
     if (wg < nchunk * nouter) {
