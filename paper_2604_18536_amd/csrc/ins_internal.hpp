@@ -89,8 +89,11 @@ template <typename T>
 hipError_t launch_stage(const Grid& g, const T* w, const double* p, bool proj, const T* u0, T* y, bool yinit, double cy,
                         T* wout, double cw, hipStream_t s, const T* mc = nullptr);
 
-// z planes per workgroup of a z-marching 3D stencil on TX x TY tiles.
-int zm_chunk(const Grid& g, int tx, int ty);
+// z planes per workgroup of a z-marching 3D stencil on tx x ty tiles: at most
+// zmax, halved while the launch would have fewer than `want` workgroups.
+int zm_chunk(const Grid& g, int tx, int ty, int want, int zmax);
+// the same for the forward stage kernels (64 x 8 tiles), by field precision
+int zm_chunk_stage(const Grid& g, bool fp64);
 // 3D variant of launch_stage: 2.5D z-march with an LDS ring of projected planes.
 template <typename T>
 hipError_t launch_stage_zm(const Grid& g, const T* w, const double* p, bool proj, const T* u0, T* y, bool yinit,

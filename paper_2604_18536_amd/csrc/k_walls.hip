@@ -1493,7 +1493,7 @@ hipError_t launch_wall_stage(const Grid& g, const T* w, const double* p, bool pr
                              double cy, T* wout, double cw, hipStream_t s) {
     if (g.dim == 3) {
         constexpr int TX = 64, TY = 8;
-        const int zc = zm_chunk(g, TX, TY);
+        const int zc = zm_chunk_stage(g, sizeof(T) == 8);
         const int nblk = ((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY) * ((g.nz + zc - 1) / zc) * g.batch;
         const int yi = yinit ? 1 : 0;
         if (proj)
@@ -1530,7 +1530,7 @@ hipError_t launch_wall_stage_vjp(const Grid& g, const T* w, const double* p, boo
                                  const double* q, bool has_w, double cb, double cw, T* u0bar, int mode, T* ubar_out,
                                  hipStream_t s) {
     if (g.dim == 3) {
-        const int zc = zm_chunk(g, kWvTX, kWvTY);
+        const int zc = zm_chunk(g, kWvTX, kWvTY, 2048, 32);
         const int nblk =
             ((g.nx + kWvTX - 1) / kWvTX) * ((g.ny + kWvTY - 1) / kWvTY) * ((g.nz + zc - 1) / zc) * g.batch;
         const T tb = T(cb), tw = T(cw);
