@@ -100,8 +100,9 @@ def _source_hash(names):
     return h.hexdigest()[:16]
 
 
-def _traffic_record(kernel):
-    """HBM bytes per launch measured with rocprofv3 counters, if still valid for the current source."""
+def _traffic_record(kernel, cells):
+    """HBM bytes per launch measured with rocprofv3 counters, if still valid for the current source
+    and measured on a field of the same number of cells."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -110,6 +111,8 @@ def _traffic_record(kernel):
     if not rec:
         return None
     if rec.get("source_hash") != _source_hash(rec.get("sources", [])):
+        return None
+    if rec.get("cells") != cells:
         return None
     return rec.get("bytes_per_launch")
 
@@ -262,7 +265,7 @@ def channel_timing(steps, warmup, modes=None, cfg=None):
     achieved = b / (kp[dom]["avg_ms"] * 1e-3) / 1e9
     out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                       "traffic": _traffic_record("channel:" + dom),
+                       "traffic": _traffic_record("channel:" + dom, ncell),
                        "alg_bytes_per_launch": b, "avg_ms": kp[dom]["avg_ms"]}
     return out
 
@@ -514,7 +517,7 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": _traffic_record(dom),
+        "traffic": _traffic_record(dom, ncell),
         "alg_bytes_per_launch": dom_bytes,
         "avg_ms": kprof[dom]["avg_ms"],
         "frac_of_copy": round(achieved / copy_gbs, 4),  # against the measured streaming-copy rate

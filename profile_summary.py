@@ -5,7 +5,8 @@
       (adds per-variant averages from the run_kernel_trace.csv beside it; for a
       run of the float64 forward step only, whose dispatch order is fixed)
   python profile_summary.py traffic <fetch counter_collection.csv> <write counter_collection.csv> <out.md> <command...>
-  (after the mode, --workload=periodic|channel|channel_cg picks the kernel-variant table)
+  (after the mode, --workload=periodic|channel|channel_cg picks the kernel-variant table and
+  --cells=N records the cell count of the profiled field; bench.py uses a record only for that size)
 
 `traffic` also updates profiles/traffic.json, the measured HBM bytes per
 launch that bench.py reports as roofline.traffic. Counters are calibrated with
@@ -112,7 +113,7 @@ def _per_dispatch(path, counter):
     return d
 
 
-def traffic(fetch_csv, write_csv, out_md, command, copy_bytes=None, order=None):
+def traffic(fetch_csv, write_csv, out_md, command, copy_bytes=None, order=None, cells=None):
     order = order or VARIANT_ORDER
     f = _per_dispatch(fetch_csv, "FETCH_SIZE")
     w = _per_dispatch(write_csv, "WRITE_SIZE")
@@ -149,7 +150,7 @@ def traffic(fetch_csv, write_csv, out_md, command, copy_bytes=None, order=None):
             lines.append(f"| `{names[0].replace('void ', '')}` as {name} | {n} | {a / n / 2**20:.1f} | {b / n / 2**20:.1f} | "
                          f"{(a + b) / n / 2**20:.1f} |")
             rec[name] = {"bytes_per_launch": round((a + b) / n), "fetch": round(a / n), "write": round(b / n),
-                         "sources": srcs, "source_hash": source_hash(srcs)}
+                         "sources": srcs, "source_hash": source_hash(srcs), "cells": cells}
     open(out_md, "w").write("\n".join(lines) + "\n")
     json.dump(rec, open(jpath, "w"), indent=1, sort_keys=True)
 
@@ -157,12 +158,17 @@ def traffic(fetch_csv, write_csv, out_md, command, copy_bytes=None, order=None):
 if __name__ == "__main__":
     args = sys.argv[1:]
     order = VARIANT_ORDERS["periodic"]
-    if len(args) > 1 and args[1].startswith("--workload="):
-        order = VARIANT_ORDERS[args.pop(1).split("=", 1)[1]]
+    cells = None
+    while len(args) > 1 and args[1].startswith("--"):
+        key, val = args.pop(1)[2:].split("=", 1)
+        if key == "workload":
+            order = VARIANT_ORDERS[val]
+        elif key == "cells":
+            cells = int(val)
     mode = args[0]
     if mode in ("trace", "trace-variants"):
         trace(args[1], args[2], " ".join(args[3:]), variants=mode == "trace-variants", order=order)
     elif mode == "traffic":
-        traffic(args[1], args[2], args[3], " ".join(args[4:]), order=order)
+        traffic(args[1], args[2], args[3], " ".join(args[4:]), order=order, cells=cells)
     else:
         raise SystemExit(__doc__)
