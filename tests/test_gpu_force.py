@@ -108,3 +108,21 @@ def test_fp32_mode_with_force():
     u1 = host(s.step(dev(u0, torch.float32), dt))
     ref = W.step_rk4(u0, h, nu, dt, force=f)
     assert np.linalg.norm(u1 - ref) / np.linalg.norm(ref) < 1e-5
+
+
+@pytest.mark.parametrize("pressure", ["fft", "cg"])
+def test_forced_trajectory_on_a_tanh_grid(pressure):
+    """20 RK4 steps of the forced channel (f = (1, 0, 0), tanh y) against the oracle's
+    trajectory, compared every 5 steps: float64 rounding stays at the solve's level."""
+    n = (16, 12, 8)
+    nu, dt = 0.02, 5e-3
+    h, faces = _box(n, 1.4)
+    f = (1.0, 0.0, 0.0)
+    s = _solver(n, nu, faces, pressure, f)
+    u = W.project(S.channel_ic(n, 30, bulk=2.0, noise=0.3), h)[0]
+    t = dev(u)
+    for k in range(1, 21):
+        u = W.step_rk4(u, h, nu, dt, force=f)
+        s.step(t, dt, out=t)
+        if k % 5 == 0:
+            assert max_rel(host(t), u) < 1e-10, k
