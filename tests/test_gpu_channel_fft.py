@@ -207,3 +207,44 @@ def test_full_size_properties(gamma):
     mean_w = float((r * wr).sum() / (wr.expand_as(r)).sum())
     assert float((res - (r - mean_w)).abs().max()) < 1e-10 * float(r.abs().max())
     assert abs(float(p.mean())) < 1e-12 * float(p.abs().max())
+
+
+def test_random_shapes_sweep():
+    """Seeded random channels (n_x from the FFT's sizes, any n_y in 2..70, 2D or 3D,
+    uniform or tanh y, batch 1 or 2): solve, its transpose and the projection against
+    the oracle. Bar: 20 eps kappa with kappa = the (0, 0) mode's condition number,
+    bounded by (max width / min width) / sin^2(pi / (2 n_y)), and at least 1e-11."""
+    from paper_2604_18536_amd import Solver
+
+    rng = np.random.default_rng(2026)
+    for _ in range(10):
+        nx = int(rng.choice([4, 6, 10, 14, 16, 20, 28, 30, 42, 56]))
+        ny = int(rng.integers(2, 71))
+        three = bool(rng.integers(0, 2))
+        n = (nx, ny, int(rng.choice([2, 3, 5, 7, 8, 12]))) if three else (nx, ny)
+        gamma = float(rng.choice([0.0, rng.uniform(0.5, 2.0)]))
+        batch = int(rng.integers(1, 3))
+        lo, hi = S.channel_box(n)
+        s = Solver(n, nu=0.0, batch=batch, lo=lo, hi=hi, bc="walls", pressure="fft")
+        h = list(S.spacing(n, lo, hi))
+        if gamma:
+            f = S.tanh_faces(ny, lo[1], hi[1], gamma)
+            s.set_y_faces(f)
+            h[1] = f
+            ratio = np.diff(f).max() / np.diff(f).min()
+        else:
+            ratio = 1.0
+        h = tuple(h)
+        kappa = ratio / np.sin(np.pi / (2 * ny)) ** 2
+        tol = max(1e-11, 20 * np.finfo(float).eps * kappa)
+        r = np.stack([S.random_scalar(n, 100 + b) for b in range(batch)])
+        u = np.stack([S.channel_random(n, 200 + b) for b in range(batch)])
+        p = host(s.poisson_solve(dev(r)))
+        q = host(s.poisson_solve_vjp(dev(r)))
+        Pu = host(s.project(dev(u)))
+        for b in range(batch):
+            case = (n, gamma, batch, b)
+            assert max_rel(p[b], W.poisson_solve(r[b], h)) < tol, case
+            assert max_rel(q[b], W.poisson_solve_vjp(r[b], h)) < tol, case
+            assert max_rel(Pu[b], W.project(u[b], h)[0]) < tol, case
+        s.close()
