@@ -134,12 +134,14 @@ def test_kept_stages_and_agreement_with_cg():
     assert max_rel(host(s.step(u0, dt)), host(ucg)) < 1e-10
 
 
-@pytest.mark.parametrize("n", [(4, 2), (4, 3), (4, 2, 2), (6, 3, 4), (4, 2048)])
+@pytest.mark.parametrize("n", [(4, 2), (4, 3), (4, 2, 2), (6, 3, 4), (4, 1000), (6, 700, 4), (4, 2048)])
 def test_smallest_and_largest_channels(n):
     """n_y = 2, 3 (one segment of two or three rows per line, n_x = 4: two complex
-    points per x row) and n_y = 2048, the largest the direct solve takes (64 segments
-    of 32 rows). The (0, 0) mode's uniform Neumann operator has condition number
-    1 / sin^2(pi / (2 n_y)); the bar is 20 eps kappa, at least 1e-11."""
+    points per x row); n_y = 700 and 1000 (64 segments of up to 16 rows, 512-thread
+    workgroups, the shape of the paper's 1024-row channel); n_y = 2048, the largest
+    the direct solve takes (64 segments of 32 rows). The (0, 0) mode's uniform
+    Neumann operator has condition number 1 / sin^2(pi / (2 n_y)); the bar is
+    20 eps kappa, at least 1e-11."""
     s = _solver(n, gamma=0.0)
     h = _h(n, 0.0)
     kappa = 1.0 / np.sin(np.pi / (2 * n[1])) ** 2
