@@ -114,6 +114,11 @@ def test_batch_equals_single_and_fp32():
     u1 = host(s32.step(dev(us, torch.float32), dt))
     for b in range(2):
         assert l2_rel(u1[b], W.step_rk4(us[b], h, nu, dt)) < 1e-5
+    # FP32 pullback: float32 stencils, float64 transposed solves (scaled divergence in the x pass)
+    ubar = np.stack([f32(S.channel_random(n, 40 + b)) for b in range(2)])
+    g = host(s32.step_vjp(dev(us, torch.float32), dev(ubar, torch.float32), dt))
+    for b in range(2):
+        assert l2_rel(g[b], W.step_rk4_vjp(us[b], ubar[b], h, nu, dt)) < 1e-5
 
 
 def test_kept_stages_and_agreement_with_cg():
@@ -134,7 +139,8 @@ def test_kept_stages_and_agreement_with_cg():
     assert max_rel(host(s.step(u0, dt)), host(ucg)) < 1e-10
 
 
-@pytest.mark.parametrize("n", [(4, 2), (4, 3), (4, 2, 2), (6, 3, 4), (4, 1000), (6, 700, 4), (4, 2048)])
+@pytest.mark.parametrize("n", [(4, 2), (4, 3), (4, 2, 2), (6, 3, 4), (8, 160), (6, 200, 4), (4, 1000), (6, 700, 4),
+                               (4, 2048)])
 def test_smallest_and_largest_channels(n):
     """n_y = 2, 3 (one segment of two or three rows per line, n_x = 4: two complex
     points per x row); n_y = 700 and 1000 (64 segments of up to 16 rows, 512-thread
