@@ -196,8 +196,10 @@ ins_status ins_set_y_faces(ins_ctx ctx, const double* faces);
  * array of dim values, added to F on the velocity unknowns by ins_rhs and every
  * step from the next call on (default 0). A constant has no Jacobian, so the
  * pullbacks change only through the forward stages they linearise about. A
- * wall-normal component is balanced by the pressure. INS_ERR_UNSUPPORTED on a
- * periodic context; INS_ERR_INVALID for a null or non-finite force. */
+ * wall-normal component is balanced by the pressure. The value is captured by
+ * the kernels launched after the call (no synchronisation; work already queued
+ * keeps the old force). INS_ERR_UNSUPPORTED on a periodic context;
+ * INS_ERR_INVALID for a null or non-finite force. */
 ins_status ins_set_body_force(ins_ctx ctx, const double* force);
 
 /* Defaults: rtol 1e-10, maxiter 20000, check_every 16. INS_ERR_UNSUPPORTED
@@ -215,7 +217,9 @@ typedef enum { INS_PRESSURE_AUTO = 0, INS_PRESSURE_FFT = 1, INS_PRESSURE_CG = 2 
  * INS_PRESSURE_AUTO: FFT where it applies, else CG (the default). Periodic
  * grid: only FFT (INS_PRESSURE_CG gives INS_ERR_UNSUPPORTED). Channel:
  * INS_PRESSURE_FFT gives INS_ERR_UNSUPPORTED when the sizes above rule it out.
- * INS_ERR_INVALID for any other value. */
+ * INS_ERR_INVALID for any other value. Host-side only: no synchronisation, and
+ * both solvers' workspace is allocated at ins_create, so switching allocates
+ * nothing. */
 ins_status ins_set_pressure_solver(ins_ctx ctx, int solver);
 /* The solver in use: INS_PRESSURE_FFT or INS_PRESSURE_CG. */
 ins_status ins_get_pressure_solver(ins_ctx ctx, int* solver);
