@@ -186,6 +186,13 @@ def test_solver_choice():
         p.set_pressure("cg")
     with pytest.raises(ValueError):
         p.set_pressure("lu")
+    # the C entry points themselves: an unknown solver value, a null output
+    from paper_2604_18536_amd import _lib
+
+    lib = _lib.load()
+    assert lib.ins_set_pressure_solver(s._ctx, 7) == _lib.INS_ERR_INVALID
+    assert lib.ins_get_pressure_solver(s._ctx, None) == _lib.INS_ERR_INVALID
+    assert s.pressure == "fft"  # unchanged by the rejected calls
 
 
 @pytest.mark.parametrize("gamma", [0.0, 1.5])
