@@ -5,6 +5,8 @@
       (adds per-variant averages from the run_kernel_trace.csv beside it; for a
       run of the float64 forward step only, whose dispatch order is fixed)
   python profile_summary.py traffic <fetch counter_collection.csv> <write counter_collection.csv> <out.md> <command...>
+  python profile_summary.py counters <csv,csv,...> <out.md> <kernel prefix,...> <command...>
+      (per-dispatch averages of SQ counters from --pmc runs)
   (after the mode, --workload=periodic|channel|channel_cg picks the kernel-variant table and
   --cells=N records the cell count of the profiled field; bench.py uses a record only for that size)
 
@@ -155,6 +157,30 @@ def traffic(fetch_csv, write_csv, out_md, command, copy_bytes=None, order=None, 
     json.dump(rec, open(jpath, "w"), indent=1, sort_keys=True)
 
 
+def counters(csv_paths, out_md, command, prefixes):
+    """Per-dispatch averages of every counter in one or more counter_collection.csv files,
+    for the kernels whose demangled names start with one of `prefixes`."""
+    acc = defaultdict(lambda: defaultdict(float))
+    disp = defaultdict(set)
+    for path in csv_paths:
+        for r in csv.DictReader(open(path)):
+            name = r["Kernel_Name"].split("(")[0]
+            if not any(name.startswith(px) for px in prefixes):
+                continue
+            acc[name][r["Counter_Name"]] += float(r["Counter_Value"])
+            disp[(name, r["Counter_Name"])].add(int(r["Dispatch_Id"]))
+    names = sorted({c for k in acc for c in acc[k]})
+    lines = ["# rocprofv3 SQ counters per dispatch", "", "Commands (one counter set per run):", "", "```", command,
+             "```", "", "| kernel | " + " | ".join(names) + " |", "|---" * (len(names) + 1) + "|"]
+    for k in sorted(acc):
+        row = []
+        for c in names:
+            n = len(disp[(k, c)])
+            row.append(f"{acc[k][c] / n:.4g}" if n else "-")
+        lines.append(f"| `{k.replace('void ', '')}` | " + " | ".join(row) + " |")
+    open(out_md, "w").write("\n".join(lines) + "\n")
+
+
 if __name__ == "__main__":
     args = sys.argv[1:]
     order = VARIANT_ORDERS["periodic"]
@@ -170,5 +196,8 @@ if __name__ == "__main__":
         trace(args[1], args[2], " ".join(args[3:]), variants=mode == "trace-variants", order=order)
     elif mode == "traffic":
         traffic(args[1], args[2], args[3], " ".join(args[4:]), order=order, cells=cells)
+    elif mode == "counters":
+        # counters <csv,csv,...> <out.md> <kernel prefix,prefix,...> <command...>
+        counters(args[1].split(","), args[2], " ".join(args[4:]), args[3].split(","))
     else:
         raise SystemExit(__doc__)
