@@ -186,13 +186,13 @@ def run_mode(n, nu, dt, precision, steps, warmup, u0_np, adjoint, scheme="rk4", 
 
 CHANNEL = {"n": (256, 256, 256), "nu": 1.0 / 1000.0, "dt": 1e-3, "seed": 5, "rtol": 1e-8, "check": 16,
            "gamma": 1.5, "modes": "fp64,fp64_adj,fp64_adj_kept,fp32,fp64_tanh,fp64_tanh_adj,fp64_cg,fp64_tanh_cg"}
-# the paper's turbulent channel (Sec. 5): Re_tau = 180, box 4pi x 2 x 4pi/3, nu = 1/180, driven by
+# the paper's turbulent channel (Sec. 6): Re_tau = 180, box 4pi x 2 x 4pi/3, nu = 1/180, driven by
 # f = (1, 0, 0), its uniform DNS grid 512 x 1024 x 256; dt from the CFL of the initial field
 CHANNEL_DNS = {"n": (512, 1024, 256), "nu": 1.0 / 180.0, "dt": 2e-4, "seed": 7, "rtol": 1e-8, "check": 16,
                "gamma": 1.5, "box": ((0.0, 0.0, 0.0), (4 * math.pi, 2.0, 4 * math.pi / 3)),
                "force": (1.0, 0.0, 0.0), "bulk": 15.6, "noise": 0.1, "modes": "fp64,fp32,fp64_adj_kept"}
 # the same channel at the reference DNS resolution 512 x 256 x 256 with tanh stretching in y, first
-# cell Delta y+ = 0.49 (Sec. 5): the run the paper's sparse LDL^T factorisation had no memory for
+# cell Delta y+ = 0.49 (Sec. 6): the run the paper's sparse LDL^T factorisation had no memory for
 CHANNEL_VK = dict(CHANNEL_DNS, n=(512, 256, 256), seed=8, first_width_plus=0.49)
 
 

@@ -9,9 +9,9 @@
  * accelerated simulation of turbulent flows" (arXiv 2604.18536):
  *   Sec. 2.1   staggered Harlow-Welch grid, code-index convention (Sec. 3.1)
  *   Sec. 2.2   discrete operators; App. B explicit kernels and pullbacks
- *   Sec. 2.1   boundary conditions (no-slip walls through ghost volumes)
- *   Sec. 2.5.1 pressure Poisson equation, spectral (DFT) and iterative (CG) solvers
- *   Sec. 2.5.2 explicit Runge-Kutta with a projection at every stage
+ *   Sec. 2.4   boundary conditions (no-slip walls through ghost volumes)
+ *   Sec. 2.6.1 pressure Poisson equation, spectral (DFT) and iterative (CG) solvers
+ *   Sec. 2.6.2 explicit Runge-Kutta with a projection at every stage
  *   Sec. 3.3   memory: array reuse, low-storage stepping, lazy fluxes
  *   Sec. 3.4   pullback rule and hand-written adjoint kernels
  *   Sec. 4     neural closure inside the solver, a-posteriori training
@@ -39,7 +39,7 @@
  *             stage arithmetic run in float32; the divergence, the Poisson
  *             solve and the projection u - G p are computed in float64 and
  *             pressure-point fields (r, p) are float64. (The paper supports a
- *             choice of format but no mixed strategy, Sec. 6.2; this mode is
+ *             choice of format but no mixed strategy, Sec. 8.2; this mode is
  *             the mixed strategy its outlook proposes.)
  *
  * Ownership. The caller owns every field buffer; buffers must be 256-byte
@@ -94,10 +94,10 @@ typedef enum {
 typedef enum { INS_FP64 = 0, INS_FP32 = 1 } ins_dtype;
 
 /* INS_BC_PERIODIC: periodic in every direction; pressure by FFT.
- * INS_BC_WALLS_Y:  channel: no-slip walls at both y ends (Sec. 2.1 Dirichlet
+ * INS_BC_WALLS_Y:  channel: no-slip walls at both y ends (Sec. 2.4 Dirichlet
  *   condition u = 0 imposed through ghost volumes), x and z periodic;
  *   pressure by a direct solve (FFTs along x and z, a tridiagonal solve along
- *   y per mode) or by matrix-free conjugate gradients (Sec. 2.5.1 iterative
+ *   y per mode) or by matrix-free conjugate gradients (Sec. 2.6.1 iterative
  *   solver); see ins_set_pressure_solver.
  *   The layout is unchanged: u^y[..][n_y - 1][..] is the upper-wall face, a
  *   boundary value, not an unknown. Every operator reads it (and the lower-wall
@@ -124,7 +124,7 @@ typedef struct {
  * Requirements (else INS_ERR_UNSUPPORTED): every n in [2, 4096]; for
  * INS_BC_PERIODIC also n_x even and >= 4 and n_x/2, n_y, n_z products of the
  * primes 2, 3, 5, 7 (the real-to-complex FFT along x works on n_x/2 complex
- * points; the spectral solver of Sec. 2.5.1 needs a uniform periodic grid).
+ * points; the spectral solver of Sec. 2.6.1 needs a uniform periodic grid).
  * nu >= 0 is the kinematic viscosity of the diffusion term. Allocates the
  * forward workspace: stage registers (3 velocity fields), pressure, the half
  * spectrum (periodic grid, and the channel when its direct solver applies) and
@@ -142,22 +142,22 @@ const char* ins_last_error(void);
  *
  * Both solvers return the same discrete solution, the zero-mean p with
  * D G p = r - mean_w(r) (the augmented system of the direct solver of
- * Sec. 2.5.1), up to rounding (direct) or up to the CG stopping rule.
+ * Sec. 2.6.1), up to rounding (direct) or up to the CG stopping rule.
  *
  * INS_PRESSURE_FFT (the default when it applies: n_x even, n_x/2 and n_z
  * products of 2, 3, 5, 7, n_y <= 2048): FFTs along the periodic x and z leave
  * one tridiagonal system along y per wavenumber pair (the Neumann second
  * difference across the y widths, shifted by the periodic eigenvalue
- * 4 sin^2(pi k / n) / h^2 of Sec. 2.5.1), solved exactly; the (0, 0) mode is
+ * 4 sin^2(pi k / n) / h^2 of Sec. 2.6.1), solved exactly; the (0, 0) mode is
  * the singular Neumann problem, solved with its weighted mean removed and its
  * solution centred. On a uniform y this is the paper's channel solver (FFTs
- * and a type-II cosine transform, Sec. 5, which diagonalises the same
+ * and a type-II cosine transform, Sec. 6, which diagonalises the same
  * operator); it also holds on a stretched y. No host synchronisation; the
  * spectrum is the only workspace.
  *
  * INS_PRESSURE_CG: every pressure solve (ins_poisson_solve, ins_project, the
  * steps and their pullbacks) runs CG on A = -D G, the Laplace operator applied as the
- * divergence of the gradient without assembling it (Sec. 2.5.1 iterative
+ * divergence of the gradient without assembling it (Sec. 2.6.1 iterative
  * solver), from p = 0, for A p = mean(r) - r, independently per batch field.
  * A field stops once ||res|| <= rtol ||res_0|| (res the recursively updated
  * residual) or after maxiter iterations. Iterations run back to back on the
@@ -173,7 +173,7 @@ const char* ins_last_error(void);
  * the periodic grid (INS_ERR_UNSUPPORTED).
  * ------------------------------------------------------------------------- */
 
-/* Stretched y (Sec. 2.1 non-uniform grids, e.g. the tanh grid of eq. tanh-grid):
+/* Stretched y (Sec. 2.5 non-uniform grids, e.g. the tanh grid of eq. tanh-grid):
  * faces is a host array of the n_y + 1 y-face coordinates, strictly increasing
  * (the walls are faces[0] and faces[n_y]); x and z stay uniform. Replaces the
  * uniform spacing of the box for every later call. The operators follow App. B
@@ -192,7 +192,7 @@ const char* ins_last_error(void);
 ins_status ins_set_y_faces(ins_ctx ctx, const double* faces);
 
 /* Constant body force (the forcing term that F(u) collects, App. A momentum
- * equation; the channel of Sec. 5 is driven by f = (1, 0, 0)): force is a host
+ * equation; the channel of Sec. 6 is driven by f = (1, 0, 0)): force is a host
  * array of dim values, added to F on the velocity unknowns by ins_rhs and every
  * step from the next call on (default 0). A constant has no Jacobian, so the
  * pullbacks change only through the forward stages they linearise about. A
@@ -225,7 +225,7 @@ ins_status ins_set_pressure_solver(ins_ctx ctx, int solver);
 ins_status ins_get_pressure_solver(ins_ctx ctx, int* solver);
 
 /* ---------------------------------------------------------------------------
- * Forward operators (App. B kernels; Sec. 2.5)
+ * Forward operators (Sec. 2.2 discrete operators; App. B kernels)
  * ------------------------------------------------------------------------- */
 
 /* f = C(u) + nu * Lap(u) (+ m_theta(u) when a closure is set; + the body
@@ -242,19 +242,19 @@ ins_status ins_divergence(ins_ctx ctx, const void* u, double* r);
  * p float64 pressure-point field; g velocity field in the context dtype. */
 ins_status ins_gradient(ins_ctx ctx, const double* p, void* g);
 
-/* Solve D G p = r by the spectral solver of Sec. 2.5.1: p = DFT^-1 L^-1 DFT r
+/* Solve D G p = r by the spectral solver of Sec. 2.6.1: p = DFT^-1 L^-1 DFT r
  * with the exact discrete transfer function
  * L(k) = -sum_a 4 sin^2(pi k_a / n_a) / h_a^2 and L(0) := 1 (so the mean of
  * p equals the mean of r). r, p: float64 pressure-point fields; r may equal p. */
 ins_status ins_poisson_solve(ins_ctx ctx, const double* r, double* p);
 
 /* u_out = P u = u - G p with p = (D G)^-1 D u (the projection applied at every
- * RK stage, Sec. 2.5.2). The divergence, Poisson solve and u - G p run in
+ * RK stage, Sec. 2.6.2). The divergence, Poisson solve and u - G p run in
  * float64. p_out (float64, may be NULL) receives p. u == u_out is allowed. */
 ins_status ins_project(ins_ctx ctx, const void* u, void* u_out, double* p_out);
 
 /* One classical RK4 step with the velocity projected after every stage
- * (Sec. 2.5.2): u_{i+1} = P(u0 + dt a_{i+1} F(u_i)), a = (1/2, 1/2, 1);
+ * (Sec. 2.6.2): u_{i+1} = P(u0 + dt a_{i+1} F(u_i)), a = (1/2, 1/2, 1);
  * u1 = P(u0 + dt (F1 + 2F2 + 2F3 + F4) / 6), F = ins_rhs. u0 is used as
  * given (callers pass a solenoidal field). Low-storage schedule: stage
  * register, accumulator and one pressure solve per stage, with the
@@ -280,7 +280,7 @@ ins_status ins_divergence_vjp(ins_ctx ctx, const double* rbar, void* ubar);
 /* pbar = G^T gbar = -D gbar. gbar velocity field, pbar float64. */
 ins_status ins_gradient_vjp(ins_ctx ctx, const void* gbar, double* pbar);
 
-/* rbar = L^-T pbar = L^-1 pbar: the Poisson solve is self-adjoint (Sec. 2.5.1). */
+/* rbar = L^-T pbar = L^-1 pbar: the Poisson solve is self-adjoint (Sec. 2.6.1). */
 ins_status ins_poisson_solve_vjp(ins_ctx ctx, const double* pbar, double* rbar);
 
 /* ubar = P^T ubar_out = P ubar_out (P is symmetric on the uniform periodic
@@ -294,7 +294,7 @@ ins_status ins_project_vjp(ins_ctx ctx, const void* ubar_out, void* ubar);
 ins_status ins_step_rk4_vjp(ins_ctx ctx, const void* u0, const void* u1bar, void* u0bar, double dt);
 
 /* One step of Wray's low-storage three-stage, third-order Runge-Kutta
- * scheme (Sec. 2.5.2 lists it among the explicit integrators; Sec. 3.3 cites
+ * scheme (Sec. 2.6.2 lists it among the explicit integrators; Sec. 3.3 cites
  * it as the low-storage method), velocity projected after every stage like
  * ins_step_rk4. The paper gives no coefficients; these are Wray's:
  *   u_1 = P(u0 + dt g1 F(u0)),  u_2 = P(u_1 + dt (g2 F(u_1) + z1 F(u0))),
@@ -376,6 +376,19 @@ ins_status ins_cnn_forward(ins_ctx ctx, const void* u, void* m);
  * (d m_theta / d theta)^T mbar (overwritten; the accumulator of
  * ins_closure_grad is left at zero). */
 ins_status ins_cnn_backward(ins_ctx ctx, const void* u, const void* mbar, void* ubar, float* params_bar);
+
+/* Diagnostic copy of one of the closure's internal tensors as the last
+ * ins_cnn_backward left them (for layer-by-layer parity checks); out is a
+ * device buffer of the stated size, cells of the batch in velocity-field order
+ * and channels fastest (channels-last):
+ *   0: bfloat16 input x0 [cells][8] (channels 3..7 zero)
+ *   1: float32 pre-activation z1 [cells][32]      2: bfloat16 GELU(z1) [cells][32]
+ *   3: float32 pre-activation z2 [cells][32]      4: bfloat16 GELU(z2) [cells][32]
+ *   5: bfloat16 cotangent of m [cells][8]
+ *   6: bfloat16 cotangent of z2 [cells][32]       7: bfloat16 cotangent of z1 [cells][32]
+ *   8: m itself (velocity layout, context dtype).
+ * INS_ERR_INVALID for another `which` or when no learned closure is set. */
+ins_status ins_cnn_saved(ins_ctx ctx, int which, void* out);
 
 /* ---------------------------------------------------------------------------
  * Smagorinsky eddy-viscosity closure (appendix on eddy-viscosity models:

@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
 The paper does not define the filter or the spectrum binning (it refers to
-spectra only in passing, Sec. 5); the readings used here are:
+spectra only in passing, Sec. 5.7); the readings used here are:
 * face filter: the coarse a-velocity is the mean of the ``f**(d-1)`` fine
   a-velocities lying on the coarse a-face (coarse cell I covers fine cells
   f*I .. f*I+f-1; its right a-face is the right face of fine cell f*I+f-1);

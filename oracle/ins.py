@@ -113,14 +113,14 @@ def rhs(u, h, nu):
 
 
 # ----------------------------------------------------------------------------
-# Pressure Poisson solve and projection (Sec. 2.5.1, spectral solver)
+# Pressure Poisson solve and projection (Sec. 2.6.1, spectral solver)
 # ----------------------------------------------------------------------------
 
 def laplace_eigenvalues(n, h):
     """Transfer function of L = D G on the DFT modes: -sum_a 4 sin^2(pi k_a / N_a) / h_a^2.
 
     Array of the full complex-DFT shape (N_z, N_y, N_x). The zero mode is set to
-    one, as the spectral solver of Sec. 2.5.1 prescribes.
+    one, as the spectral solver of Sec. 2.6.1 prescribes.
     """
     d = len(n)
     lam = np.zeros(tuple(reversed(n)), dtype=np.float64)
@@ -135,7 +135,7 @@ def laplace_eigenvalues(n, h):
 
 
 def poisson_solve(r, h):
-    """p = DFT^{-1} Lhat^{-1} DFT r with Lhat(0) := 1 (Sec. 2.5.1, spectral solver).
+    """p = DFT^{-1} Lhat^{-1} DFT r with Lhat(0) := 1 (Sec. 2.6.1, spectral solver).
 
     Solves D G p = r (the sign makes p the physical pressure); the zero mode of
     p equals that of r.
@@ -146,13 +146,13 @@ def poisson_solve(r, h):
 
 
 def project(u, h):
-    """P u = u - G L^{-1} D u: the pressure projection applied at every RK stage (Sec. 2.5.2)."""
+    """P u = u - G L^{-1} D u: the pressure projection applied at every RK stage (Sec. 2.6.2)."""
     p = poisson_solve(divergence(u, h), h)
     return u - gradient(p, h), p
 
 
 # ----------------------------------------------------------------------------
-# Classical RK4 with projection after every stage (Sec. 2.5.2)
+# Classical RK4 with projection after every stage (Sec. 2.6.2)
 # ----------------------------------------------------------------------------
 
 RK4_A = (0.5, 0.5, 1.0)
@@ -193,7 +193,7 @@ def step_rk4(u0, h, nu, dt, rhs_fn=None, project_fn=None):
 
 # ----------------------------------------------------------------------------
 # Wray's low-storage three-stage Runge-Kutta scheme (one of the explicit
-# integrators named in Sec. 2.5.2 and the low-storage method of Sec. 3.3),
+# integrators named in Sec. 2.6.2 and the low-storage method of Sec. 3.3),
 # velocity projected after every stage as for RK4. The paper cites the scheme
 # without its coefficients; they are Wray's two-register ones:
 #   u_1 = P(u_0 + dt g1 F(u_0))
@@ -282,7 +282,7 @@ def rhs_vjp(u, fbar, h, nu):
 
 
 def poisson_solve_vjp(pbar, h):
-    """The Poisson solve is self-adjoint, so its pullback is a Poisson solve (Sec. 2.5.1)."""
+    """The Poisson solve is self-adjoint, so its pullback is a Poisson solve (Sec. 2.6.1)."""
     return poisson_solve(pbar, h)
 
 

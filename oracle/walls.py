@@ -6,14 +6,14 @@ TEST INFRASTRUCTURE ONLY (see the package docstring). Not used by the product pa
 
 Grid. ``h = (h_x, h_y[, h_z])``; ``h_y`` is either a spacing (uniform) or the
 array of the N_y + 1 y-face coordinates y_0 < ... < y_{N_y} (the walls are
-y_0 and y_{N_y}; Sec. 2.1 volumes Delta^y_i and App. B widths |Delta^y_i|).
+y_0 and y_{N_y}; Sec. 2.5 volumes Delta^y_i and App. B widths |Delta^y_i|).
 In code indices: w_j = y_{j+1} - y_j is the width of cell row j (a pressure
 volume, half-integer paper index j + 1/2), c_j its centre, and
 d_j = c_{j+1} - c_j the width of the velocity volume around y-face j (the face
 on top of row j, integer paper index j + 1). Beyond a wall a ghost row mirrors
 the first/last row, so d_{-1} = w_0 and d_{N_y - 1} = w_{N_y - 1}.
 
-Boundary treatment (Sec. 2.1, boundary conditions: Dirichlet velocity imposed
+Boundary treatment (Sec. 2.4, boundary conditions: Dirichlet velocity imposed
 through ghost volumes adjacent to the domain; the paper gives no ghost
 formula, the reading taken here is stated in full):
 
@@ -57,7 +57,7 @@ Arrays keep the periodic layout: velocity (d, [N_z,] N_y, N_x), pressure
 (padded row k holds index I_y = k - 1) by ``_pad``; pullbacks fold the padded
 cotangent back with ``_fold``, the transpose of ``_pad``.
 
-Pressure solves (Sec. 2.5.1): ``poisson_solve`` is the direct solver, the
+Pressure solves (Sec. 2.6.1): ``poisson_solve`` is the direct solver, the
 augmented system [L e; e^T 0] [p; lam] = [r; 0] solved with a sparse LU
 factorisation (p has zero mean and L p = r - lam, lam the volume-weighted mean
 of r); ``cg_solve`` is the iterative solver: conjugate gradients on the
@@ -343,7 +343,7 @@ def convection(u, h):
 
 def rhs(u, h, nu, force=None):
     """F(u) = C(u) + nu D(u) + f (App. A momentum equation, the forcing collected in F):
-    f a constant vector (the channel's driving body force, Sec. 5), added on the
+    f a constant vector (the channel's driving body force, Sec. 6), added on the
     velocity unknowns only."""
     out = convection(u, h) + diffusion(u, h, nu)
     if force is not None:
@@ -359,7 +359,7 @@ def laplacian(p, h):
 
 
 # ----------------------------------------------------------------------------
-# Pressure solves (Sec. 2.5.1)
+# Pressure solves (Sec. 2.6.1)
 # ----------------------------------------------------------------------------
 
 def laplace_matrix(n, h):
@@ -404,7 +404,7 @@ def _augmented(n, h):
 
 
 def poisson_solve(r, h):
-    """Direct solver of Sec. 2.5.1: [L e; e^T 0][p; lam] = [r; 0] (sparse LU)."""
+    """Direct solver of Sec. 2.6.1: [L e; e^T 0][p; lam] = [r; 0] (sparse LU)."""
     import scipy.sparse.linalg as spla
 
     A, m = _augmented(tuple(reversed(r.shape)), h)
@@ -413,7 +413,7 @@ def poisson_solve(r, h):
 
 
 def cg_solve(r, h, rtol=1e-12, maxiter=10000):
-    """Iterative solver of Sec. 2.5.1: conjugate gradients on the symmetric positive
+    """Iterative solver of Sec. 2.6.1: conjugate gradients on the symmetric positive
     semi-definite A = -Omega_p D G for A p = -Omega_p (r - rbar), rbar the volume-weighted
     mean of r, from p = 0, with A applied matrix-free (scaling, divergence, gradient).
 
@@ -452,7 +452,7 @@ def cg_solve(r, h, rtol=1e-12, maxiter=10000):
 
 
 def project(u, h, solve=None):
-    """P u = u - G L^{-1} D u on the unknowns (the projection of Sec. 2.5.2)."""
+    """P u = u - G L^{-1} D u on the unknowns (the projection of Sec. 2.6.2)."""
     solve = solve or poisson_solve
     p = solve(divergence(u, h), h)
     return (u - gradient(p, h)) * dof_mask(tuple(reversed(u.shape[1:]))), p

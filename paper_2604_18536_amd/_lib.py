@@ -83,6 +83,7 @@ _SIGS = {
     "ins_closure_grad": ([_P, _P]),
     "ins_cnn_forward": ([_P, _P, _P]),
     "ins_cnn_backward": ([_P, _P, _P, _P, _P]),
+    "ins_cnn_saved": ([_P, C.c_int, _P]),
     "ins_face_filter": ([_P, _P, C.c_int, _P]),
     "ins_energy_spectrum": ([_P, _P, _P, C.c_int]),
     "ins_stats": ([_P, _P, C.POINTER(_D)]),

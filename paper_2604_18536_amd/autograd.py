@@ -5,7 +5,7 @@ library's hand-written RK4-step pullback (``ins_step_rk4_vjp``); torch only
 chains the steps. ``rollout_loss`` unrolls many steps and keeps only every
 ``checkpoint_every``-th state: the backward recomputes each segment from its
 first state, so memory grows with (steps / k + k) fields instead of with the
-number of steps (the paper's outlook, Sec. 6.2, names checkpointing as the
+number of steps (the paper's outlook, Sec. 8.2, names checkpointing as the
 remedy for storing every state).
 """
 from __future__ import annotations

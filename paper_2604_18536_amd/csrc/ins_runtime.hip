@@ -385,7 +385,7 @@ bool cg_all_done(ins_ctx c) {
 }
 
 // Channel grid: x = (D G)^+ of the divergence of vel or of r, by conjugate
-// gradients on -D G (Sec. 2.5.1, iterative solver) from x = 0; the mean of
+// gradients on -D G (Sec. 2.6.1, iterative solver) from x = 0; the mean of
 // the right-hand side is removed first (the zero-mean solution of the
 // consistent part). Iterations are launched back to back; every cg_check
 // iterations the host reads the stop flags once and stops launching when
@@ -672,7 +672,7 @@ Stages<T> own_stages(ins_ctx c) {
     return {{static_cast<T*>(c->w2), static_cast<T*>(c->w3), static_cast<T*>(c->w4)}, {c->p2, c->p3, c->p4}};
 }
 
-// Classical RK4, projection after every stage (Sec. 2.5.2), low-storage
+// Classical RK4, projection after every stage (Sec. 2.6.2), low-storage
 // schedule: accumulator y, stage registers wa/wb, one pressure per stage.
 // With `keep` the stage registers and pressures are the given buffers (the
 // same work, their contents left for the pullback).
@@ -767,7 +767,7 @@ void step_rk4_vjp(ins_ctx c, const T* u0, const T* u1bar, T* u0bar, double dt) {
     step_rk4_reverse<T>(c, u0, S, u1bar, u0bar, dt);
 }
 
-// Wray's low-storage three-stage scheme (Sec. 2.5.2 names it among the
+// Wray's low-storage three-stage scheme (Sec. 2.6.2 names it among the
 // integrators, Sec. 3.3 as the low-storage one), projection after every
 // stage. In Butcher form its stages are u_2 = P(u0 + dt 8/15 F_1),
 // u_3 = P(u0 + dt (1/4 F_1 + 5/12 F_2)), u_new = P(u0 + dt (1/4 F_1 + 3/4 F_3));
@@ -878,7 +878,7 @@ bool setup_fft(ins_ctx c, const std::vector<int>& rx, const std::vector<int>& ry
         const long double ang = -two_pi * k / static_cast<long double>(g.nx);
         post[k] = cd{double(cosl(ang)), double(sinl(ang))};
     }
-    // 4 sin^2(pi k / n) / h^2 per direction (Sec. 2.5.1 transfer function);
+    // 4 sin^2(pi k / n) / h^2 per direction (Sec. 2.6.1 transfer function);
     // the channel's y entries are unused.
     std::vector<double> lam;
     size_t off[3] = {0, 0, 0};
@@ -1575,6 +1575,30 @@ ins_status ins_cnn_backward(ins_ctx ctx, const void* u, const void* mbar, void* 
                                  ctx->stream),
                   "copy closure gradient");
         ctx->launch("fill_zero", [&] { return ins::launch_fill_zero_f(ctx->theta_bar, kClosParams, ctx->stream); });
+    });
+}
+
+ins_status ins_cnn_saved(ins_ctx ctx, int which, void* out) {
+    return guarded([&] {
+        checked(ctx);
+        need(out, "out");
+        if (ctx->clos_kind != 1 || !ctx->clos_alloc) raise(INS_ERR_INVALID, "no learned closure has been set");
+        const size_t n = size_t(ctx->g.ncell) * ctx->g.batch;
+        const void* src = nullptr;
+        size_t bytes = 0;
+        switch (which) {
+            case 0: src = ctx->x0, bytes = n * 8 * 2; break;
+            case 1: src = ctx->z1, bytes = n * 32 * 4; break;
+            case 2: src = ctx->a1, bytes = n * 32 * 2; break;
+            case 3: src = ctx->z2, bytes = n * 32 * 4; break;
+            case 4: src = ctx->a2, bytes = n * 32 * 2; break;
+            case 5: src = ctx->gm, bytes = n * 8 * 2; break;
+            case 6: src = ctx->gz2, bytes = n * 32 * 2; break;
+            case 7: src = ctx->gz1, bytes = n * 32 * 2; break;
+            case 8: src = ctx->mclos, bytes = ctx->vel_bytes(); break;
+            default: raise(INS_ERR_INVALID, "ins_cnn_saved: which must be 0..8");
+        }
+        hip_check(hipMemcpyAsync(out, src, bytes, hipMemcpyDeviceToDevice, ctx->stream), "copy closure tensor");
     });
 }
 

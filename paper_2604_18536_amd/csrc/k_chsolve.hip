@@ -1,13 +1,13 @@
 // Direct pressure solve of the channel grid (x and z periodic and uniform, y
 // bounded by walls, uniform or stretched).
 //
-// Fourier modes in x and z diagonalise the periodic parts of D G (Sec. 2.5.1
+// Fourier modes in x and z diagonalise the periodic parts of D G (Sec. 2.6.1
 // transfer function, 4 sin^2(pi k / n) / h^2 per direction), so after forward
 // FFTs along x and z every wavenumber pair (k_x, k_z) leaves one tridiagonal
 // system along y: the Neumann second difference across the stretched widths,
 // shifted by the periodic eigenvalue. The paper solves its uniform channel with
 // FFTs in the periodic directions and a type-II cosine transform along y
-// (Sec. 5, DNS on a uniform grid); that transform diagonalises exactly this
+// (Sec. 6, DNS on a uniform grid); that transform diagonalises exactly this
 // uniform Neumann operator, so the tridiagonal solve yields the same discrete
 // pressure there and, unchanged, on a stretched y, where the paper falls back
 // to its sparse direct or iterative solver.

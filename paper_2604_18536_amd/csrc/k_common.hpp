@@ -73,7 +73,7 @@ __device__ __forceinline__ TileIdx tile_of(const Grid& g) {
 
 // Velocity value at a neighbour of the current cell. With PROJ the stored
 // field is the unprojected stage value w and the velocity is w - G p, formed
-// in float64 (the projection of the previous RK stage, Sec. 2.5.2, fused into
+// in float64 (the projection of the previous RK stage, Sec. 2.6.2, fused into
 // this stencil so the projected field is never written out).
 template <typename T, bool PROJ>
 struct VelSrc {

@@ -1,4 +1,4 @@
-// Spectral pressure solve of Sec. 2.5.1 on gfx950: p = DFT^-1 L^-1 DFT r with
+// Spectral pressure solve of Sec. 2.6.1 on gfx950: p = DFT^-1 L^-1 DFT r with
 // the exact discrete transfer function, as a real-to-complex FFT along x
 // followed by complex FFTs along y (and z), all hand-written.
 //

@@ -3,7 +3,7 @@
 //
 // A workgroup owns a 64 x 8 tile of an x-y plane (the reverse stage: 32 x 8)
 // and a chunk of consecutive z planes. For every plane it forms the stage
-// velocity u = w - G p (float64 projection, Sec. 2.5.2) on the tile plus a
+// velocity u = w - G p (float64 projection, Sec. 2.6.2) on the tile plus a
 // one-cell halo exactly once and
 // keeps it in a 4-plane LDS ring; the right-hand side of plane z then reads
 // planes z-1, z, z+1 from LDS only. Each plane of w and p is therefore fetched

@@ -1,8 +1,8 @@
 // Kernels of the channel grid: no-slip walls at both ends of y, x and z
-// periodic and uniform, y uniform or stretched (Sec. 2.1 boundary conditions
+// periodic and uniform, y uniform or stretched (Sec. 2.4 boundary conditions
 // through ghost volumes and non-uniform grids; App. B kernels with
 // non-uniform widths), and the matrix-free conjugate-gradient pressure solve
-// (Sec. 2.5.1, iterative solver).
+// (Sec. 2.6.1, iterative solver).
 //
 // Wall rules, applied where a stencil reads a neighbour:
 //  * u^y on the face on top of the last cell row (row N_y - 1) is the upper

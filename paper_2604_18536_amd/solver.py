@@ -331,6 +331,23 @@ class Solver:
                self._check(ubar, "vel", "ubar"), self._params(pbar, "params_bar"))
         return ubar, pbar
 
+    _CNN_SAVED = {0: (8, torch.int16), 1: (32, torch.float32), 2: (32, torch.int16), 3: (32, torch.float32),
+                  4: (32, torch.int16), 5: (8, torch.int16), 6: (32, torch.int16), 7: (32, torch.int16)}
+
+    def cnn_saved(self, which):
+        """Copy of one of the closure's internal tensors after cnn_backward
+        (see ins_cnn_saved): channels-last [cells][C]; bfloat16 tensors are
+        returned as torch.bfloat16, which = 8 gives m in the field layout."""
+        if which == 8:
+            out = self._out(None, None, "vel")
+        else:
+            ch, dt = self._CNN_SAVED[which]
+            ncell = self.batch * math.prod(self.n)
+            out = torch.empty((ncell, ch), dtype=dt, device=self.device)
+        self._sync_stream()
+        L.call("ins_cnn_saved", self._ctx, int(which), C.c_void_p(out.data_ptr()))
+        return out.view(torch.bfloat16) if out.dtype == torch.int16 else out
+
     # ------------------------------------------------ Smagorinsky closure
     def set_eddy(self, cs=0.17, delta=None):
         """Attach the Smagorinsky eddy-viscosity closure (cs = 0 detaches it);

@@ -369,7 +369,7 @@ def tanh_gamma(ny, length, first_width):
 
 
 def tanh_faces(ny, lo, hi, gamma):
-    """y-face coordinates of the hyperbolic-tangent grid (Sec. 2.1 non-uniform grids,
+    """y-face coordinates of the hyperbolic-tangent grid (Sec. 2.5 non-uniform grids,
     eq. tanh-grid): clustered at both ends, stretching set by gamma > 0."""
     t = np.arange(ny + 1) / ny
     return lo + 0.5 * (hi - lo) * (1.0 + np.tanh(gamma * (2.0 * t - 1.0)) / np.tanh(gamma))

@@ -1,6 +1,6 @@
 """Direct (FFT in x and z, tridiagonal along y) pressure solve of the channel
 on the GPU against the channel oracle's sparse-LU solve of the augmented
-system (Sec. 2.5.1 direct solver), uniform and stretched y.
+system (Sec. 2.6.1 direct solver), uniform and stretched y.
 
 Both sides solve the same discrete system exactly, so the bar is rounding:
 1e-11 element-wise (max |gpu - ref| / max |ref|) for solves, projections,

@@ -1,4 +1,4 @@
-"""Channel body force on the GPU (the forcing term of F; the channel of Sec. 5 is
+"""Channel body force on the GPU (the forcing term of F; the channel of Sec. 6 is
 driven by f = (1, 0, 0)) against the channel oracle with the same force.
 
 Bars as for the channel without force: the right-hand side 1e-12 element-wise,

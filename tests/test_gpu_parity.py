@@ -277,3 +277,16 @@ def test_full_size_256_step_vjp_adjoint_identity():
     rhs = float((g * v).sum())
     s.close()
     assert abs(lhs - rhs) < 1e-9 * float((ubar.abs() * jv.abs()).sum())
+
+
+def test_full_size_256_step_vjp_fp64():
+    """The reverse z-march kernels in the benchmark's launch shape: the 256^3
+    float64 step pullback against the oracle's, element by element."""
+    n = (256, 256, 256)
+    nu, dt = 1.0 / 1600.0, 1e-3
+    u0 = S.turbulence_ic(n, seed=0, k0=4.0)
+    ubar = S.random_field(n, 2)
+    s = _solver(n, nu)
+    g = host(s.step_vjp(dev(u0), dev(ubar), dt))
+    s.close()
+    assert max_rel(g, O.step_rk4_vjp(u0, ubar, S.spacing(n), nu, dt)) < TOL64

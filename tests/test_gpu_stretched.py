@@ -1,4 +1,4 @@
-"""Channel on a stretched y grid (tanh faces, Sec. 2.1 non-uniform grids) on the
+"""Channel on a stretched y grid (tanh faces, Sec. 2.5 non-uniform grids) on the
 GPU against the channel oracle with the same face coordinates.
 
 Bars as for the uniform channel: stencils and their pullbacks 1e-12

@@ -1,5 +1,5 @@
 """Pins of the channel oracle's body force (the forcing term collected in F, App. A
-momentum equation; the constant driving force of the channel, Sec. 5), by
+momentum equation; the constant driving force of the channel, Sec. 6), by
 routes other than its own array code:
 
 * exact solution: with nu = 0 a uniform streamwise/spanwise flow has no

@@ -2,7 +2,7 @@
 
 Each test checks the oracle against something other than its own formula:
 closed forms of the discrete operators on sampled trigonometric fields,
-invariants stated in the paper (D and G negative transposes, Sec. 5 test
+invariants stated in the paper (D and G negative transposes, Sec. 5.8 test
 suite; skew-symmetric convection conserves energy, App. A), a textbook
 Laplacian matrix, and brute-force loops of the printed convection kernel.
 """
@@ -59,7 +59,7 @@ def test_divergence_of_turbulence_ic_vanishes(n):
 
 @pytest.mark.parametrize("n", GRIDS)
 def test_gradient_is_negative_transpose_of_divergence(n):
-    """<D u, p> = -<u, G p> (Sec. 2.3 duality; Sec. 5 physical verification test)."""
+    """<D u, p> = -<u, G p> (Sec. 2.3 duality; Sec. 5.8 physical verification test)."""
     h = _h(n, [1.0, 2.5, 0.7][: len(n)])
     u = S.random_field(n, 11)
     p = S.random_scalar(n, 12)
@@ -233,7 +233,7 @@ def _textbook_laplacian(n, h):
 
 @pytest.mark.parametrize("n", [(8, 8), (6, 4), (4, 6, 5)])
 def test_poisson_matches_dense_augmented_solve(n):
-    """Sec. 2.5.1 direct solver: [L e; e^T 0][p; lambda] = [r; 0] vs the spectral solve."""
+    """Sec. 2.6.1 direct solver: [L e; e^T 0][p; lambda] = [r; 0] vs the spectral solve."""
     d = len(n)
     h = _h(n, [1.0, 2.0, 1.5][:d])
     L = _textbook_laplacian(n, h)

@@ -1,5 +1,5 @@
 """Pins of the channel oracle (no-slip walls at both y ends; Sec. 2.1 boundary
-conditions through ghost volumes, Sec. 2.5.1 direct and iterative pressure
+conditions through ghost volumes, Sec. 2.6.1 direct and iterative pressure
 solvers), by routes other than its own array code:
 
 * brute force: every operator re-evaluated cell by cell with pure-Python loops

@@ -1,5 +1,5 @@
 """Pins of the oracle's Wray3 step (the low-storage three-stage Runge-Kutta
-scheme named in Sec. 2.5.2 and Sec. 3.3) and of its pullback.
+scheme named in Sec. 2.6.2 and Sec. 3.3) and of its pullback.
 
 The oracle uses Wray's two-register recurrence; the pins use other routes:
 * the coefficients satisfy the textbook order conditions of a third-order
