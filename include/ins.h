@@ -454,6 +454,20 @@ ins_status ins_energy_spectrum(ins_ctx ctx, const void* u, double* e, int nbins)
  * is finite else 0. Synchronises the stream. */
 ins_status ins_stats(ins_ctx ctx, const void* u, double out[4]);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the statistics of
+ * ins_stats, written to out, a DEVICE array of 4 doubles (same order and
+ * meaning; the kinetic-energy sum is reduced in another order, so it may
+ * differ from ins_stats in the last bits), with no host synchronisation.
+ * Allocates nothing and creates no events: its partial sums live in a fixed
+ * 64 KiB device scratch array that the library holds on every device it runs
+ * on until the process ends (at most 2048 workgroups of 4 doubles; larger
+ * fields are walked by the same workgroups). Every call on a device shares
+ * that device's scratch and leaves its partials there: calls that overlap on
+ * one device (different streams or threads, any contexts) race and must be
+ * serialised by the caller. INS_ERR_INVALID for a null u or out. */
+ins_status ins_stats_noalloc(ins_ctx ctx, const void* u, double* out);
+
 /* Plain device copy of nbytes (multiple of 16) from src to dst with the
  * library's streaming-copy kernel; used to calibrate bandwidth counters. */
 ins_status ins_stream_copy(ins_ctx ctx, const void* src, void* dst, size_t nbytes);

@@ -87,6 +87,7 @@ _SIGS = {
     "ins_face_filter": ([_P, _P, C.c_int, _P]),
     "ins_energy_spectrum": ([_P, _P, _P, C.c_int]),
     "ins_stats": ([_P, _P, C.POINTER(_D)]),
+    "ins_stats_noalloc": ([_P, _P, _P]),
     "ins_stream_copy": ([_P, _P, _P, C.c_size_t]),
     "ins_profile_enable": ([_P, C.c_int]),
     "ins_profile_reset": ([_P]),

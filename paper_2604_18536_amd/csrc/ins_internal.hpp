@@ -253,5 +253,12 @@ hipError_t launch_stream_copy(const void* src, void* dst, size_t nbytes, hipStre
 
 // Number of workgroups used by launch_stats (partials buffer holds 4 per block).
 int stats_blocks(const Grid& g);
+// Statistics from at most kStatsCapBlocks workgroups into a caller-provided
+// partials buffer of 4 * stats_capped_blocks(g) doubles, then reduced on the
+// device into out[4] (kinetic energy, max |u|, max |D u|, all-finite flag).
+constexpr int kStatsCapBlocks = 2048;
+int stats_capped_blocks(const Grid& g);
+template <typename T>
+hipError_t launch_stats_capped(const Grid& g, const T* u, double* partial, double* out, hipStream_t s);
 
 }  // namespace ins

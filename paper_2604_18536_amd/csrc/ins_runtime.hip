@@ -8,6 +8,7 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -137,6 +138,32 @@ struct Pending {
     hipEvent_t a, b;
 };
 
+// Fixed device scratch of the allocation-free entry point ins_stats_noalloc:
+// the per-workgroup partials of the capped statistics kernel (4 doubles per
+// workgroup, 64 KiB). Each device holds its own copy for the life of the
+// process. Host code never names the array in a kernel argument or copy: it
+// uses the device address looked up once per device (scratch_on).
+constexpr size_t kScratchDoubles = 4 * size_t(ins::kStatsCapBlocks);
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device `dev`, looked up with
+// hipGetSymbolAddress on the first call for that device (ins_create).
+double* scratch_on(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) raise(INS_ERR_UNSUPPORTED, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* ptr = nullptr;
+        hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        if (!ptr) raise(INS_ERR_HIP, "hipGetSymbolAddress(scratch) returned a null address");
+        g_scratch_dev[dev] = static_cast<double*>(ptr);
+    }
+    return g_scratch_dev[dev];
+}
+
 }  // namespace
 
 struct ins_ctx_s {
@@ -179,6 +206,7 @@ struct ins_ctx_s {
     void* wb = nullptr;
     double* partials = nullptr;
     int nstat = 0;
+    double* scratch = nullptr;  // this device's address of the fixed scratch (ins_stats_noalloc)
 
     // reverse-pass stage storage (allocated on first use)
     void* w2 = nullptr;
@@ -943,6 +971,7 @@ ins_status ins_create(const ins_grid* grid, ins_bc bc, double nu, ins_dtype dtyp
         c = new ins_ctx_s();
         c->walls = walls;
         hip_check(hipGetDevice(&c->device), "hipGetDevice");
+        c->scratch = scratch_on(c->device);
         c->dtype = dtype;
         ins::Grid& g = c->g;
         g.dim = d;
@@ -1628,6 +1657,23 @@ ins_status ins_stats(ins_ctx ctx, const void* u, double out[4]) {
         out[1] = mu;
         out[2] = md;
         out[3] = nf == 0.0 ? 1.0 : 0.0;
+    });
+}
+
+ins_status ins_stats_noalloc(ins_ctx ctx, const void* u, double* out) {
+    return guarded([&] {
+        checked(ctx);
+        need(u, "u");
+        need(out, "out");
+        if (size_t(4) * size_t(ins::stats_capped_blocks(ctx->g)) > kScratchDoubles)
+            raise(INS_ERR_UNSUPPORTED, "ins_stats_noalloc: partials exceed the fixed scratch");
+        // launched directly (no profiling events): this call creates nothing
+        hipError_t e;
+        if (ctx->dtype == INS_FP64)
+            e = ins::launch_stats_capped<double>(ctx->g, static_cast<const double*>(u), ctx->scratch, out, ctx->stream);
+        else
+            e = ins::launch_stats_capped<float>(ctx->g, static_cast<const float*>(u), ctx->scratch, out, ctx->stream);
+        if (e != hipSuccess) raise(INS_ERR_HIP, std::string("stats_capped: ") + hipGetErrorString(e));
     });
 }
 

@@ -6,29 +6,31 @@ namespace ins {
 
 int stats_blocks(const Grid& g) { return stencil_blocks(g); }
 
-// Per-workgroup partials: [4*blk + 0] = sum u^2, +1 = max|u|, +2 = max|Du|,
-// +3 = count of non-finite entries. Reduced on the host.
+// Statistics of one cell of tile t accumulated into s2 (sum u^2), mu
+// (max |u|), md (max |D u|) and nf (count of non-finite entries).
 template <typename T, int DIM>
-__global__ __launch_bounds__(kBlock) void k_stats(Grid g, const T* __restrict__ u, double* __restrict__ part) {
-    __shared__ double sh[4][kBlock];
-    const TileIdx t = tile_of(g);
-    double s2 = 0.0, mu = 0.0, md = 0.0, nf = 0.0;
-    if (t.valid) {
-        const Nb nb = make_nb<DIM>(g, t.x, t.y, t.z);
-        const T* ub = u + int64_t(t.b) * DIM * g.ncell;
-        const int c0 = nb.at(0, 0, 0);
-        double dv = 0.0;
+__device__ __forceinline__ void stats_cell(const Grid& g, const T* __restrict__ u, const TileIdx& t, double& s2,
+                                           double& mu, double& md, double& nf) {
+    const Nb nb = make_nb<DIM>(g, t.x, t.y, t.z);
+    const T* ub = u + int64_t(t.b) * DIM * g.ncell;
+    const int c0 = nb.at(0, 0, 0);
+    double dv = 0.0;
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            const double v = ub[a * g.ncell + c0];
-            const double vm = ub[a * g.ncell + nb.at(-(a == 0), -(a == 1), -(a == 2))];
-            s2 += v * v;
-            mu = fmax(mu, fabs(v));
-            nf += isfinite(v) ? 0.0 : 1.0;
-            dv += (v - vm) * ((a == 1 && g.ym) ? g.ym[t.y] : g.ih[a]);  // channel: 1 / w_j along y
-        }
-        md = fabs(dv);
+    for (int a = 0; a < DIM; ++a) {
+        const double v = ub[a * g.ncell + c0];
+        const double vm = ub[a * g.ncell + nb.at(-(a == 0), -(a == 1), -(a == 2))];
+        s2 += v * v;
+        mu = fmax(mu, fabs(v));
+        nf += isfinite(v) ? 0.0 : 1.0;
+        dv += (v - vm) * ((a == 1 && g.ym) ? g.ym[t.y] : g.ih[a]);  // channel: 1 / w_j along y
     }
+    md = fmax(md, fabs(dv));
+}
+
+// Workgroup reduction of the four statistics (sums and maxima, fixed order);
+// thread i < 4 writes statistic i to out[i].
+__device__ __forceinline__ void stats_block_store(double s2, double mu, double md, double nf, double* out) {
+    __shared__ double sh[4][kBlock];
     const int i = threadIdx.x;
     sh[0][i] = s2;
     sh[1][i] = mu;
@@ -44,7 +46,52 @@ __global__ __launch_bounds__(kBlock) void k_stats(Grid g, const T* __restrict__ 
         }
         __syncthreads();
     }
-    if (i < 4) part[4 * blockIdx.x + i] = sh[i][0];
+    if (i < 4) out[i] = sh[i][0];
+}
+
+// Per-workgroup partials: [4*blk + 0] = sum u^2, +1 = max|u|, +2 = max|Du|,
+// +3 = count of non-finite entries. Reduced on the host.
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_stats(Grid g, const T* __restrict__ u, double* __restrict__ part) {
+    const TileIdx t = tile_of(g);
+    double s2 = 0.0, mu = 0.0, md = 0.0, nf = 0.0;
+    if (t.valid) stats_cell<T, DIM>(g, u, t, s2, mu, md, nf);
+    stats_block_store(s2, mu, md, nf, part + 4 * int64_t(blockIdx.x));
+}
+
+// The same partials from a capped number of workgroups (the allocation-free
+// entry point's fixed scratch): workgroup k walks tiles k, k + gridDim.x, ...
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_stats_capped(Grid g, const T* __restrict__ u, double* __restrict__ part,
+                                                          int ntiles) {
+    double s2 = 0.0, mu = 0.0, md = 0.0, nf = 0.0;
+    for (int k = blockIdx.x; k < ntiles; k += gridDim.x) {
+        const TileIdx t = tile_at(g, k);
+        if (t.valid) stats_cell<T, DIM>(g, u, t, s2, mu, md, nf);
+    }
+    stats_block_store(s2, mu, md, nf, part + 4 * int64_t(blockIdx.x));
+}
+
+// One workgroup: the nblk partials reduced in a fixed order into out[0..3]
+// (kinetic energy = s2 * ke_scale, max |u|, max |D u|, 1 if all finite).
+__global__ __launch_bounds__(kBlock) void k_stats_final(const double* __restrict__ part, int nblk, double ke_scale,
+                                                         double* __restrict__ out) {
+    double s2 = 0.0, mu = 0.0, md = 0.0, nf = 0.0;
+    for (int k = threadIdx.x; k < nblk; k += kBlock) {
+        s2 += part[4 * k];
+        mu = fmax(mu, part[4 * k + 1]);
+        md = fmax(md, part[4 * k + 2]);
+        nf += part[4 * k + 3];
+    }
+    __shared__ double res[4];
+    stats_block_store(s2, mu, md, nf, res);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        out[0] = ke_scale * res[0];
+        out[1] = res[1];
+        out[2] = res[2];
+        out[3] = res[3] == 0.0 ? 1.0 : 0.0;
+    }
 }
 
 template <typename T>
@@ -58,6 +105,29 @@ hipError_t launch_stats(const Grid& g, const T* u, double* partial, int nblocks,
 
 template hipError_t launch_stats<double>(const Grid&, const double*, double*, int, hipStream_t);
 template hipError_t launch_stats<float>(const Grid&, const float*, double*, int, hipStream_t);
+
+int stats_capped_blocks(const Grid& g) {
+    const int n = stencil_blocks(g);
+    return n < kStatsCapBlocks ? n : kStatsCapBlocks;
+}
+
+template <typename T>
+hipError_t launch_stats_capped(const Grid& g, const T* u, double* partial, double* out, hipStream_t s) {
+    const int ntiles = stencil_blocks(g);
+    const int nblk = stats_capped_blocks(g);
+    if (g.dim == 3)
+        hipLaunchKernelGGL((k_stats_capped<T, 3>), dim3(nblk), dim3(kBlock), 0, s, g, u, partial, ntiles);
+    else
+        hipLaunchKernelGGL((k_stats_capped<T, 2>), dim3(nblk), dim3(kBlock), 0, s, g, u, partial, ntiles);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const double ke_scale = 0.5 / (double(g.ncell) * g.batch);
+    hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(kBlock), 0, s, partial, nblk, ke_scale, out);
+    return hipGetLastError();
+}
+
+template hipError_t launch_stats_capped<double>(const Grid&, const double*, double*, double*, hipStream_t);
+template hipError_t launch_stats_capped<float>(const Grid&, const float*, double*, double*, hipStream_t);
 
 typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 

@@ -54,6 +54,23 @@ struct TileIdx {
     bool valid;
 };
 
+// Tile number t (no XCD reordering) of a stencil launch.
+__device__ __forceinline__ TileIdx tile_at(const Grid& g, int t) {
+    const int ntx = (g.nx + kTileX - 1) / kTileX;
+    const int nty = (g.ny + kTileY - 1) / kTileY;
+    TileIdx r;
+    const int tx = t % ntx;
+    t /= ntx;
+    const int ty = t % nty;
+    t /= nty;
+    r.z = t % g.nz;
+    r.b = t / g.nz;
+    r.x = tx * kTileX + (threadIdx.x & (kTileX - 1));
+    r.y = ty * kTileY + (threadIdx.x / kTileX);
+    r.valid = r.x < g.nx && r.y < g.ny;
+    return r;
+}
+
 __device__ __forceinline__ TileIdx tile_of(const Grid& g) {
     const int ntx = (g.nx + kTileX - 1) / kTileX;
     const int nty = (g.ny + kTileY - 1) / kTileY;

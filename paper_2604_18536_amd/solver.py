@@ -400,6 +400,17 @@ class Solver:
         L.call("ins_stats", self._ctx, self._check(u, "vel", "u"), out)
         return float(out[0]), float(out[1]), float(out[2]), bool(out[3] != 0.0)
 
+    def stats_noalloc(self, u, out):
+        """The statistics of ``stats`` written to ``out`` (a float64 device tensor of
+        4 values: kinetic energy, max|u|, max|Du|, 1.0 if all finite) without
+        allocating or synchronising; calls on one device must not overlap."""
+        if not isinstance(out, torch.Tensor) or out.dtype != torch.float64 or out.device != self.device \
+                or out.numel() != 4 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float64 tensor of 4 values on the solver's device")
+        self._sync_stream()
+        L.call("ins_stats_noalloc", self._ctx, self._check(u, "vel", "u"), C.c_void_p(out.data_ptr()))
+        return out
+
     def stream_copy(self, src, dst):
         if src.numel() * src.element_size() != dst.numel() * dst.element_size():
             raise ValueError("size mismatch")
