@@ -36,24 +36,25 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 CONFIGS = {
     # the benchmark workload: 3D decaying turbulence at 256^3
     "turb256": {"n": 256, "nu": 1.0 / 1600.0, "dt": 1e-3, "k0": 4.0, "seed": 0,
-                "modes": "fp64,fp64_adj,fp32,fp32_adj,fp64_adj_kept,fp32_adj_kept,fp64_wray3,fp32_wray3"},
+                "modes": "fp64,fp64_adj,fp32,fp32_adj,fp64_adj_kept,fp32_adj_kept,fp64_wray3,fp32_wray3,fp32_all"},
     # the largest single-GPU DNS: 840^3 = 2^3*3*5*7 (mixed-radix FFT), FP64 and FP32 mode
     "dns840": {"n": 840, "nu": 1.0 / 5000.0, "dt": 1e-3, "k0": 8.0, "seed": 3, "modes": "fp64,fp32"},
 }
 METRIC = "Mcell-updates/s per RK4 step (fwd, fwd+adjoint), FP32 vs FP64, % HBM peak"
 
 
-def kernel_bytes(name, n, elem, batch=1):
+def kernel_bytes(name, n, elem, batch=1, scal=8):
     """Algorithmic HBM bytes of one launch: each input read once, each output written once.
 
     n = (nx, ny, nz); elem = bytes of a velocity value (8 or 4). Pressure-point
     fields are float64 (8 B); the half spectrum holds (nx/2+1) ny nz complex
-    float64 values (16 B).
+    float64 values (16 B). With scal = 4 (the all-float32 mode) pressure-point
+    values take 4 B and complex values 8 B.
     """
     nx, ny, nz = n
     N = nx * ny * nz * batch
     Ns = (nx // 2 + 1) * ny * nz * batch
-    E, S, C = elem, 8, 16
+    E, S, C = elem, scal, 2 * scal
     v = 3 * E  # one velocity field per cell
     table = {
         "stage_first": 3 * v * N,                 # read u0; write y, w
@@ -107,14 +108,13 @@ def _traffic_record(kernel, cells):
     if not os.path.exists(path):
         return None
     with open(path) as fh:
-        rec = json.load(fh).get(kernel)
-    if not rec:
+        recs = json.load(fh).get(kernel)
+    if not recs:
         return None
-    if rec.get("source_hash") != _source_hash(rec.get("sources", [])):
-        return None
-    if rec.get("cells") != cells:
-        return None
-    return rec.get("bytes_per_launch")
+    for rec in recs if isinstance(recs, list) else [recs]:  # one record per profiled field size
+        if rec.get("cells") == cells and rec.get("source_hash") == _source_hash(rec.get("sources", [])):
+            return rec.get("bytes_per_launch")
+    return None
 
 
 def time_steps(fn, steps, warmup, solver=None):
@@ -390,6 +390,96 @@ def small_grid_timing(steps):
     return out
 
 
+def kernel_table(prof, n, elem, steps, scal=8):
+    """Per-kernel launches per step, average duration, algorithmic GB/s and its fraction of the HBM peak."""
+    out = {}
+    for k, (c, t) in prof.items():
+        b = kernel_bytes(k, n, elem, scal=scal)
+        gbs = b / (t / c * 1e-3) / 1e9 if b else None
+        out[k] = {"launches_per_step": c / steps, "avg_ms": round(t / c, 5),
+                  "gbs": None if gbs is None else round(gbs, 1),
+                  "frac": None if gbs is None else round(gbs / HBM_PEAK_GBS, 4)}
+    return out
+
+
+def size_sweep(sizes, steps, warmup):
+    """The RK4 step of 3D decaying turbulence at larger grids, FP64 and FP32 mode, with
+    per-kernel algorithmic GB/s against the 8 TB/s HBM peak: 512^3 (nu = 1/2000, k0 = 4,
+    the DNS of the closure's training data) and 840^3 (nu = 1/5000, k0 = 8, the paper's
+    largest single-GPU DNS size). Initial fields are built on the GPU."""
+    import torch
+
+    import synth as S
+
+    out = {}
+    for n1 in sizes:
+        cfg = CONFIGS["dns840"] if n1 == 840 else {"nu": 1.0 / 2000.0, "dt": 1e-3, "k0": 4.0, "seed": 10}
+        n = (n1,) * 3
+        ncell = n1 ** 3
+        u0 = S.turbulence_ic_torch(n, seed=cfg["seed"], k0=cfg["k0"], device="cuda")
+        print(f"[bench] size {n1}^3 initial field ready", file=sys.stderr, flush=True)
+        rec = {"nu": cfg["nu"], "dt": cfg["dt"], "k0": cfg["k0"], "modes": {}}
+        for precision in ("fp64", "fp32"):
+            ms, ms_p, prof, ok, ws = run_mode(n, cfg["nu"], cfg["dt"], precision, steps, warmup, u0, False)
+            elem = 8 if precision == "fp64" else 4
+            kt = kernel_table(prof, n, elem, steps)
+            alg = sum(kernel_bytes(k, n, elem) * c for k, (c, t) in prof.items() if kernel_bytes(k, n, elem))
+            dom = max(kt, key=lambda k: kt[k]["avg_ms"] * kt[k]["launches_per_step"])
+            rec["modes"][precision] = {
+                "mcell_per_s": round(ncell / (ms * 1e-3) / 1e6, 2),
+                "ms_per_step": round(ms, 3),
+                "alg_bytes_per_cell": round(alg / steps / ncell, 1),
+                "hbm_frac": round(alg / steps / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+                "finite": bool(ok),
+                "workspace_gb": round(ws / 1e9, 3),
+                "dominant": {"kernel": dom, "frac": kt[dom]["frac"],
+                             "traffic": _traffic_record(dom, ncell) if precision == "fp64" else None},
+                "kernels": kt,
+            }
+            print(f"[bench] size {n1}^3 {precision}: {rec['modes'][precision]['mcell_per_s']} Mcell/s",
+                  file=sys.stderr, flush=True)
+        out[f"{n1}^3"] = rec
+        del u0
+        torch.cuda.empty_cache()
+    return out
+
+
+def precision_study(steps=200):
+    """FP32 mode and the all-float32 comparison mode against FP64 on the benchmark
+    trajectory (256^3 decaying turbulence, nu = 1/1600, dt = 1e-3, from the same
+    float32-rounded field): relative L2 velocity error, kinetic-energy error and the
+    largest discrete divergence (in float64) of each stored field."""
+    import torch
+
+    import synth as S
+    from paper_2604_18536_amd import Solver
+
+    n, nu, dt = (256, 256, 256), 1.0 / 1600.0, 1e-3
+    u0 = S.turbulence_ic(n, seed=0, k0=4.0).astype("float32")
+    s64, s32, s32a = Solver(n, nu=nu), Solver(n, nu=nu, precision="fp32"), Solver(n, nu=nu, precision="fp32_all")
+    a = torch.as_tensor(u0).cuda().double()
+    b = torch.as_tensor(u0).cuda()
+    c = b.clone()
+    rows = {}
+    for k in range(1, steps + 1):
+        s64.step(a, dt, out=a)
+        s32.step(b, dt, out=b)
+        s32a.step(c, dt, out=c)
+        if k in (1, 10, 50, 100, 200):
+            ke64 = 0.5 * float((a * a).sum(0).mean())
+            row = {"fp64_max_div": float(s64.divergence(a).abs().max())}
+            for name, v in (("fp32", b), ("fp32_all", c)):
+                vd = v.double()
+                row[name] = {"rel_l2": float((vd - a).norm() / a.norm()),
+                             "ke_rel": abs(0.5 * float((vd * vd).sum(0).mean()) - ke64) / ke64,
+                             "max_div": float(s64.divergence(vd).abs().max())}
+            rows[str(k)] = row
+    for s_ in (s64, s32, s32a):
+        s_.close()
+    return {"workload": "256^3 decaying turbulence, nu=1/1600, dt=1e-3, 200 RK4 steps from the same float32 field",
+            "max_u0": float(abs(u0).max()), "steps": rows}
+
+
 def cpu_baseline(n, nu, dt, u0_np, budget_s=30.0):
     """The float64 numpy oracle, as written, on the host: RK4 steps of the same field."""
     import oracle as O
@@ -435,6 +525,8 @@ def main():
     ap.add_argument("--no-les", action="store_true", help="skip the closure-LES and small-grid timings")
     ap.add_argument("--no-channel", action="store_true", help="skip the channel (wall-bounded) timing")
     ap.add_argument("--modes", default=None)
+    ap.add_argument("--sizes", default="512,840", help="larger grids for the per-kernel table ('' to skip)")
+    ap.add_argument("--no-precision", action="store_true", help="skip the 256^3 precision study")
     args = ap.parse_args()
     if args.config in ("channel256", "channel_dns", "channel_vk"):
         return channel_main(args)
@@ -472,7 +564,8 @@ def main():
     modes = {}
     kernels = {}
     for mode in args.modes.split(","):
-        precision = "fp64" if mode.startswith("fp64") else "fp32"
+        precision = "fp64" if mode.startswith("fp64") else ("fp32_all" if mode.startswith("fp32_all") else "fp32")
+        scal = 4 if precision == "fp32_all" else 8
         adjoint = mode.endswith("_adj") or mode.endswith("_adj_kept")
         keep = mode.endswith("_adj_kept")
         scheme = "wray3" if "_wray3" in mode else "rk4"
@@ -480,7 +573,7 @@ def main():
         elem = 8 if precision == "fp64" else 4
         alg = 0
         for name, (cnt, tot) in prof.items():
-            b = kernel_bytes(name, n, elem)
+            b = kernel_bytes(name, n, elem, scal=scal)
             if b is not None:
                 alg += b * cnt
         alg_per_step = alg / args.steps
@@ -497,8 +590,8 @@ def main():
             name: {
                 "launches_per_step": cnt / args.steps,
                 "avg_ms": round(tot / cnt, 5),
-                "gbs": (round(kernel_bytes(name, n, elem) / (tot / cnt * 1e-3) / 1e9, 1)
-                        if kernel_bytes(name, n, elem) else None),
+                "gbs": (round(kernel_bytes(name, n, elem, scal=scal) / (tot / cnt * 1e-3) / 1e9, 1)
+                        if kernel_bytes(name, n, elem, scal=scal) else None),
             }
             for name, (cnt, tot) in prof.items()
         }
@@ -526,6 +619,10 @@ def main():
     les = None if args.no_les or args.config != "turb256" else les_closure_timing(args.steps, args.warmup)
     small = None if args.no_les or args.config != "turb256" else small_grid_timing(50)
     channel = None if args.no_channel or args.config != "turb256" else channel_timing(args.steps, args.warmup)
+    precision = None if args.no_precision or args.config != "turb256" else precision_study()
+    sizes = None
+    if args.sizes and args.config == "turb256":
+        sizes = size_sweep([int(v) for v in args.sizes.split(",")], min(args.steps, 10), min(args.warmup, 2))
     ms = modes[main_mode]["ms_per_step"]
     line = {
         "metric": METRIC,
@@ -552,6 +649,8 @@ def main():
         "les_closure": les,
         "small_grids": small,
         "channel": channel,
+        "precision_256": precision,
+        "sizes": sizes,
         "cpu_baseline": cpu,
         "modes": modes,
         "kernels": kernels,

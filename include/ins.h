@@ -20,11 +20,12 @@
  * ----------------------------------------------------------------------------
  * Conventions shared by every entry point
  * ----------------------------------------------------------------------------
- * Grid. Uniform, dim 2 or 3, cell counts n[0] (x), n[1] (y), n[2] (z;
- * ignored in 2D), box [lo, hi] per direction, and `batch` independent fields
- * processed by every call. Periodic in every direction (INS_BC_PERIODIC), or
- * a channel (INS_BC_WALLS_Y): no-slip walls at y = lo[1] and y = hi[1], x and
- * z periodic; see the channel section below.
+ * Grid. Dim 2 or 3, cell counts n[0] (x), n[1] (y), n[2] (z; ignored in
+ * 2D), box [lo, hi] per direction, and `batch` independent fields processed
+ * by every call. Periodic in every direction (INS_BC_PERIODIC), or a channel
+ * (INS_BC_WALLS_Y): no-slip walls at y = lo[1] and y = hi[1], x and z
+ * periodic; see the channel section below. Uniform unless faces are given
+ * (ins_set_y_faces, ins_set_faces).
  *
  * Layout. All field arguments are device pointers to dense arrays, x fastest:
  *   velocity-point field (u, f, ubar, ...):  [batch][dim][n_z][n_y][n_x]
@@ -41,6 +42,14 @@
  *             pressure-point fields (r, p) are float64. (The paper supports a
  *             choice of format but no mixed strategy, Sec. 8.2; this mode is
  *             the mixed strategy its outlook proposes.)
+ *   INS_FP32_ALL: for comparison only: every field (pressure-point fields
+ *             too) and all arithmetic in float32, the FFT solve included
+ *             (float32 spectrum, twiddles and eigenvalues), so the mixed mode
+ *             can be measured against a path that keeps nothing in float64.
+ *             Periodic grid, forward calls only: ins_rhs, ins_divergence,
+ *             ins_gradient, ins_poisson_solve (and its pullback, the same
+ *             solve), ins_project (and its pullback), the steps, ins_stats,
+ *             ins_face_filter; every other call returns INS_ERR_UNSUPPORTED.
  *
  * Ownership. The caller owns every field buffer; buffers must be 256-byte
  * aligned (torch allocations are) and lie on the context's device. The
@@ -62,8 +71,8 @@
  * Errors. Every entry point returns an ins_status and never throws or
  * aborts. INS_ERR_INVALID: null pointer, bad size or parameter.
  * INS_ERR_UNSUPPORTED: a grid the context cannot take (see ins_create), or a
- * feature the boundary condition lacks (closures and LES helpers on the
- * channel, CG settings and stretching on the periodic grid).
+ * feature the grid lacks (closures and LES helpers on the channel and on
+ * stretched grids, CG settings on the uniform periodic grid).
  * INS_ERR_OOM: device allocation failed. INS_ERR_HIP: a HIP call or kernel
  * launch failed. ins_last_error() returns a thread-local message for the
  * last non-OK status of the calling thread. Faults inside a kernel surface
@@ -91,7 +100,7 @@ typedef enum {
     INS_ERR_HIP = -4
 } ins_status;
 
-typedef enum { INS_FP64 = 0, INS_FP32 = 1 } ins_dtype;
+typedef enum { INS_FP64 = 0, INS_FP32 = 1, INS_FP32_ALL = 2 } ins_dtype;
 
 /* INS_BC_PERIODIC: periodic in every direction; pressure by FFT.
  * INS_BC_WALLS_Y:  channel: no-slip walls at both y ends (Sec. 2.4 Dirichlet
@@ -191,6 +200,35 @@ const char* ins_last_error(void);
  * or non-finite coordinates. */
 ins_status ins_set_y_faces(ins_ctx ctx, const double* faces);
 
+/* Stretched grid in any direction (Sec. 2.5 non-uniform grids: the cosine,
+ * tanh (eq. tanh-grid) and geometric stretchings, or any increasing faces):
+ * faces is a host array of the n_axis + 1 face coordinates of direction axis
+ * (0 = x, 1 = y, 2 = z), strictly increasing; cell i spans [faces[i],
+ * faces[i + 1]]. Along a periodic direction the faces close the period (cell
+ * n - 1 neighbours cell 0; the period is faces[n] - faces[0]), so the
+ * convergence study of Sec. 7 (Taylor-Green on a tanh grid) runs on the
+ * periodic context. On a channel, axis 1 is ins_set_y_faces; axes 0 and 2
+ * stretch the periodic directions. Directions not given keep the box's
+ * uniform spacing. Operators (App. B with the widths of each direction): cell
+ * widths w_i in the divergence, centre distances d_i = (w_i + w_{i+1}) / 2 in
+ * the gradient, eq. diff-kernel with outer and inner widths, and in the
+ * convection F^{ab} = A^{ab} B^{ab} the transported component averaged with
+ * weights 1/2 and the transporting one interpolated as the mass-flux average
+ * w_i / (w_i + w_{i+1}) of direction a (eq. interp-weights read so that
+ * convection conserves energy on a grid stretched in every direction).
+ * Volumes Omega_p = prod_a w^a, Omega_u^a = d^a prod_{b != a} w^b.
+ * The first call that stretches a periodic direction switches the context to
+ * the stretched-grid kernels for good (one thread per cell) and to the CG
+ * pressure solve (ins_cg_set applies; allocates its workspace on a periodic
+ * context): the solve returns the zero-mean p with D G p = r - mean_w(r) by CG
+ * on the symmetric -Omega_p D G, the pullbacks use the transposed projection
+ * Omega_u P Omega_u^{-1} and the transposed solve, exactly as on a stretched
+ * channel. Closures, the face filter and the energy spectrum need the uniform
+ * periodic grid (INS_ERR_UNSUPPORTED, also when a closure is set at this
+ * call). Synchronises the stream. INS_ERR_INVALID for a bad axis, a null
+ * pointer, or non-increasing or non-finite coordinates. */
+ins_status ins_set_faces(ins_ctx ctx, int axis, const double* faces);
+
 /* Constant body force (the forcing term that F(u) collects, App. A momentum
  * equation; the channel of Sec. 6 is driven by f = (1, 0, 0)): force is a host
  * array of dim values, added to F on the velocity unknowns by ins_rhs and every
@@ -202,13 +240,14 @@ ins_status ins_set_y_faces(ins_ctx ctx, const double* faces);
  * INS_ERR_INVALID for a null or non-finite force. */
 ins_status ins_set_body_force(ins_ctx ctx, const double* force);
 
-/* Defaults: rtol 1e-10, maxiter 20000, check_every 16. INS_ERR_UNSUPPORTED
- * on a periodic context; INS_ERR_INVALID for rtol < 0, maxiter < 1 or
+/* Defaults: rtol 1e-10, maxiter 20000, check_every 16 (the channel, and any
+ * grid stretched by ins_set_faces). INS_ERR_UNSUPPORTED on a uniform periodic
+ * context (solved by FFT); INS_ERR_INVALID for rtol < 0, maxiter < 1 or
  * check_every < 0. */
 ins_status ins_cg_set(ins_ctx ctx, double rtol, int maxiter, int check_every);
 /* Iterations and final relative residual ||res|| / ||res_0|| of the last
  * CG solve (maxima over the batch; 0 and 0 before the first). Synchronises
- * the context's stream. */
+ * the context's stream. INS_ERR_UNSUPPORTED on a uniform periodic context. */
 ins_status ins_cg_info(ins_ctx ctx, int* iterations, double* relres);
 
 typedef enum { INS_PRESSURE_AUTO = 0, INS_PRESSURE_FFT = 1, INS_PRESSURE_CG = 2 } ins_pressure;
@@ -235,23 +274,25 @@ ins_status ins_get_pressure_solver(ins_ctx ctx, int* solver);
 ins_status ins_rhs(ins_ctx ctx, const void* u, void* f);
 
 /* r = D u, eq. div-kernel: r[I] = sum_a (u_a[I] - u_a[I - e_a]) / h_a.
- * r is a pressure-point field, float64 in both precision modes. */
-ins_status ins_divergence(ins_ctx ctx, const void* u, double* r);
+ * r is a pressure-point field: float64 (float32 in INS_FP32_ALL, the type of
+ * every pressure-point argument declared void* below). */
+ins_status ins_divergence(ins_ctx ctx, const void* u, void* r);
 
 /* g = G p, eq. presgrad-kernel: g_a[I] = (p[I + e_a] - p[I]) / h_a.
- * p float64 pressure-point field; g velocity field in the context dtype. */
-ins_status ins_gradient(ins_ctx ctx, const double* p, void* g);
+ * p pressure-point field; g velocity field in the context dtype. */
+ins_status ins_gradient(ins_ctx ctx, const void* p, void* g);
 
 /* Solve D G p = r by the spectral solver of Sec. 2.6.1: p = DFT^-1 L^-1 DFT r
  * with the exact discrete transfer function
  * L(k) = -sum_a 4 sin^2(pi k_a / n_a) / h_a^2 and L(0) := 1 (so the mean of
- * p equals the mean of r). r, p: float64 pressure-point fields; r may equal p. */
-ins_status ins_poisson_solve(ins_ctx ctx, const double* r, double* p);
+ * p equals the mean of r). r, p: pressure-point fields; r may equal p. */
+ins_status ins_poisson_solve(ins_ctx ctx, const void* r, void* p);
 
 /* u_out = P u = u - G p with p = (D G)^-1 D u (the projection applied at every
  * RK stage, Sec. 2.6.2). The divergence, Poisson solve and u - G p run in
- * float64. p_out (float64, may be NULL) receives p. u == u_out is allowed. */
-ins_status ins_project(ins_ctx ctx, const void* u, void* u_out, double* p_out);
+ * float64 (float32 in INS_FP32_ALL). p_out (a pressure-point field, may be
+ * NULL) receives p. u == u_out is allowed. */
+ins_status ins_project(ins_ctx ctx, const void* u, void* u_out, void* p_out);
 
 /* One classical RK4 step with the velocity projected after every stage
  * (Sec. 2.6.2): u_{i+1} = P(u0 + dt a_{i+1} F(u_i)), a = (1/2, 1/2, 1);
@@ -280,8 +321,9 @@ ins_status ins_divergence_vjp(ins_ctx ctx, const double* rbar, void* ubar);
 /* pbar = G^T gbar = -D gbar. gbar velocity field, pbar float64. */
 ins_status ins_gradient_vjp(ins_ctx ctx, const void* gbar, double* pbar);
 
-/* rbar = L^-T pbar = L^-1 pbar: the Poisson solve is self-adjoint (Sec. 2.6.1). */
-ins_status ins_poisson_solve_vjp(ins_ctx ctx, const double* pbar, double* rbar);
+/* rbar = L^-T pbar = L^-1 pbar: the Poisson solve is self-adjoint (Sec. 2.6.1).
+ * pbar, rbar: pressure-point fields. */
+ins_status ins_poisson_solve_vjp(ins_ctx ctx, const void* pbar, void* rbar);
 
 /* ubar = P^T ubar_out = P ubar_out (P is symmetric on the uniform periodic
  * grid). ubar == ubar_out is allowed. */

@@ -14,6 +14,7 @@ INS_ERR_OOM = -3
 INS_ERR_HIP = -4
 INS_FP64 = 0
 INS_FP32 = 1
+INS_FP32_ALL = 2
 INS_BC_PERIODIC = 0
 INS_BC_WALLS_Y = 1
 INS_RK4 = 0
@@ -70,6 +71,7 @@ _SIGS = {
     "ins_step_save": ([_P, C.c_int, _P, _P, _D, _P, _P]),
     "ins_cg_set": ([_P, _D, C.c_int, C.c_int]),
     "ins_set_y_faces": ([_P, C.POINTER(C.c_double)]),
+    "ins_set_faces": ([_P, C.c_int, C.POINTER(C.c_double)]),
     "ins_cg_info": ([_P, C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     "ins_set_pressure_solver": ([_P, C.c_int]),
     "ins_set_body_force": ([_P, C.POINTER(C.c_double)]),

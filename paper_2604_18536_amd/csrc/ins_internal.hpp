@@ -13,6 +13,22 @@ namespace ins {
 struct cd {
     double x, y;
 };
+// Complex float32 value (the all-float32 comparison mode's spectrum).
+struct cf {
+    float x, y;
+};
+template <class C>
+struct RealOf;
+template <>
+struct RealOf<cd> {
+    using type = double;
+};
+template <>
+struct RealOf<cf> {
+    using type = float;
+};
+template <class C>
+using real_of = typename RealOf<C>::type;
 
 // Grid description handed to every kernel by value.
 struct Grid {
@@ -31,6 +47,12 @@ struct Grid {
     const double* ym;
     // channel grid only: constant body force per component (the forcing term of F), 0 by default
     double force[3];
+    // stretched grid (null unless a direction other than the channel's y is
+    // stretched): per direction a, 5 arrays of stride n_a + 2 indexed by i + 1
+    // for i = -1 .. n_a: 1 / w_i, 1 / d_i, theta_i, w_i, d_i, periodic
+    // images (or the mirrored rows beyond a wall) already applied; see k_gen.hip
+    const double* gm[3];
+    int ywalls;  // stretched grid: 1 when y is bounded by no-slip walls, 0 when periodic
     // row stride of the half spectrum [batch][nz][ny][sx]: n_x/2 + 1 rounded up to a
     // multiple of 8, so every row, and every 8-column chunk of the strided passes,
     // starts on a 128-byte boundary (columns beyond n_x/2 are never touched)
@@ -48,6 +70,7 @@ struct FftPlan {
     int vm;                  // complex values a thread holds per stage (8 or 16)
     int pad;                 // LDS line-stride padding (0 or 1)
     int nth;                 // threads per workgroup: 256; with vm 8 also 1024 (x pass) or 512 (strided)
+    const cf* twf;           // the twiddle table rounded to float32 (all-float32 mode; null otherwise)
 };
 
 // Which FFT pass shape a launch uses.
@@ -59,6 +82,8 @@ struct FftPassCfg {
 struct SolveTab {
     const double* lam[3];
     double inv_ncell;
+    const float* lamf[3];  // float32 copies (all-float32 mode; null otherwise)
+    float inv_ncellf;
 };
 
 // Field-type tags for the stencil kernels.
@@ -114,6 +139,28 @@ hipError_t launch_fft_x_inv(const Grid& g, const cd* spec, double* p, const FftP
 // axis 1 = y, 2 = z.
 hipError_t launch_fft_strided(const Grid& g, cd* spec, const FftPlan& pl, const FftPlan& rev, int axis, int mode,
                               int lines, const SolveTab& st, hipStream_t s);
+
+// All-float32 comparison mode (float32 velocity and pressure-point fields,
+// every operation in float32): divergence, gradient, projection and RK stage
+// (no closure term; 3D stages as the z-march).
+hipError_t launch_divergence_f32(const Grid& g, const float* u, float* r, hipStream_t s);
+hipError_t launch_gradient_f32(const Grid& g, const float* p, float* out, hipStream_t s);
+hipError_t launch_apply_projection_f32(const Grid& g, const float* w, const float* p, float* u_out, hipStream_t s);
+hipError_t launch_stage_f32(const Grid& g, const float* w, const float* p, bool proj, const float* u0, float* y,
+                            bool yinit, double cy, float* wout, double cw, hipStream_t s);
+hipError_t launch_stage_zm_f32(const Grid& g, const float* w, const float* p, bool proj, const float* u0, float* y,
+                               bool yinit, double cy, float* wout, double cw, hipStream_t s);
+
+// All-float32 comparison mode: the same passes on a float32 half spectrum
+// [batch][n_z][n_y][sx] of cf, float32 twiddles (FftPlan::twf), eigenvalues
+// (SolveTab::lamf) and pressure-point fields. The forward x pass takes the
+// divergence of vel (vel != null) or the rows of r.
+hipError_t launch_fft_x_fwd_f32(const Grid& g, const float* vel, const float* r, cf* spec, const FftPlan& px,
+                                const cf* post, int lnl, hipStream_t s);
+hipError_t launch_fft_x_inv_f32(const Grid& g, const cf* spec, float* p, const FftPlan& px, const cf* post, int lnl,
+                                hipStream_t s);
+hipError_t launch_fft_strided_f32(const Grid& g, cf* spec, const FftPlan& pl, const FftPlan& rev, int axis, int mode,
+                                  int lnl, const SolveTab& st, hipStream_t s);
 
 // Channel grid, direct pressure solve (x, z FFTs + one tridiagonal system
 // along y per wavenumber pair). Forward x pass whose rows are the channel
@@ -244,6 +291,43 @@ hipError_t launch_cg_update(const Grid& g, double* r, const double* p, const dou
 hipError_t launch_cg_finish(const Grid& g, const double* rb, CgScal* st, hipStream_t s);
 // t = w_j (t - mean_w(t)) in place (msum: partial-sum scratch).
 hipError_t launch_cg_weighted_center(const Grid& g, double* t, double* msum, double wsum, hipStream_t s);
+
+// Stretched grid (Grid::gm set; k_gen.hip): the same contracts as the channel's
+// launchers above, every width taken from the per-direction metrics, y
+// periodic or walled (Grid::ywalls). The launch_cg_* launchers above hand
+// over to the launch_gen_cg_* ones when Grid::gm is set.
+template <typename T>
+hipError_t launch_gen_rhs(const Grid& g, const T* u, T* f, hipStream_t s);
+template <typename T>
+hipError_t launch_gen_divergence(const Grid& g, const T* u, double* r, hipStream_t s);
+template <typename T>
+hipError_t launch_gen_gradient(const Grid& g, const double* p, T* out, hipStream_t s);
+template <typename T>
+hipError_t launch_gen_rhs_vjp(const Grid& g, const T* u, const T* fbar, T* ubar, hipStream_t s);
+template <typename T>
+hipError_t launch_gen_div_vjp(const Grid& g, const double* rbar, T* ubar, hipStream_t s);
+template <typename T>
+hipError_t launch_gen_grad_vjp(const Grid& g, const T* gbar, double* pbar, hipStream_t s);
+template <typename T>
+hipError_t launch_gen_project(const Grid& g, const T* w, const double* p, T* u_out, bool adj, hipStream_t s);
+template <typename T>
+hipError_t launch_gen_stage(const Grid& g, const T* w, const double* p, bool proj, const T* u0, T* y, bool yinit,
+                            double cy, T* wout, double cw, hipStream_t s);
+template <typename T>
+hipError_t launch_gen_stage_vjp(const Grid& g, const T* w, const double* p, bool proj_u, const T* ybar, const T* un,
+                                const double* q, bool has_w, double cb, double cw, T* u0bar, int mode, T* out,
+                                hipStream_t s);
+template <typename T>
+hipError_t launch_gen_cg_div(const Grid& g, const T* vel, const double* rin, double* r, double* msum, int mode,
+                             hipStream_t s);
+hipError_t launch_gen_cg_init(const Grid& g, double* r, double* x, const double* msum, double* rb0, CgScal* st,
+                              int mode, double wsum, hipStream_t s);
+hipError_t launch_gen_cg_apply(const Grid& g, const double* r, const double* pin, double* pout, double* x,
+                               const double* rbk, const double* rbm, const double* pqm, double* pqs, CgScal* st, int k,
+                               double rtol2, int maxiter, hipStream_t s);
+hipError_t launch_gen_cg_update(const Grid& g, double* r, const double* p, const double* rbk, const double* pqs,
+                                double* rbn, CgScal* st, int k, double rtol2, int maxiter, hipStream_t s);
+hipError_t launch_gen_cg_weighted_center(const Grid& g, double* t, double* msum, double wsum, hipStream_t s);
 
 
 // Utilities.

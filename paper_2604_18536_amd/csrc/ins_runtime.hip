@@ -189,6 +189,11 @@ struct ins_ctx_s {
     ins::CgScal* cg_st = nullptr;
     ins::CgScal* cg_host = nullptr;  // pinned host copy of cg_st
     double* d_ym = nullptr;          // y metrics of the channel grid (Grid::ym)
+    // stretched grid (a periodic direction, or the channel's x or z, given faces):
+    // every operator from the per-direction metrics Grid::gm, pressure by CG
+    bool gen = false;
+    double* d_gm = nullptr;
+    std::vector<double> faces[3];    // host copy of the faces given per direction (empty: uniform)
     double wsum = 0.0;               // sum of the cell volumes' y widths over one field (n_x n_z sum_j w_j)
 
     ins::FftPlan px{}, py{}, pz{};
@@ -197,6 +202,10 @@ struct ins_ctx_s {
     cd* d_tw = nullptr;
     cd* d_post = nullptr;
     double* d_lam = nullptr;
+    // all-float32 comparison mode: float32 tables; spec then holds cf values
+    ins::cf* d_twf = nullptr;
+    ins::cf* d_postf = nullptr;
+    float* d_lamf = nullptr;
     ins::SolveTab st{};
 
     cd* spec = nullptr;
@@ -247,7 +256,9 @@ struct ins_ctx_s {
     size_t vel_bytes() const {
         return static_cast<size_t>(g.batch) * g.dim * g.ncell * (dtype == INS_FP64 ? 8 : 4);
     }
-    size_t scal_bytes() const { return static_cast<size_t>(g.batch) * g.ncell * 8; }
+    // pressure-point fields: float64, float32 in the all-float32 comparison mode
+    size_t scal_bytes() const { return static_cast<size_t>(g.batch) * g.ncell * (dtype == INS_FP32_ALL ? 4 : 8); }
+    bool f32all() const { return dtype == INS_FP32_ALL; }
 
     void* alloc(size_t n) {
         void* ptr = nullptr;
@@ -341,8 +352,17 @@ void need(const void* ptr, const char* what) {
     if (!ptr) raise(INS_ERR_INVALID, std::string(what) + " is null");
 }
 
+// Entry points that need float64 pressure-point fields (pullbacks through a
+// solve, kept stages, closures, stretched grids, the energy spectrum): the
+// all-float32 comparison mode covers the forward operators and steps only.
+void no_f32all(ins_ctx c, const char* what) {
+    if (c->dtype == INS_FP32_ALL)
+        raise(INS_ERR_UNSUPPORTED, std::string(what) + " is not available in the all-float32 comparison mode");
+}
+
 void periodic_only(ins_ctx c, const char* what) {
     if (c->walls) raise(INS_ERR_UNSUPPORTED, std::string(what) + " needs the periodic grid");
+    if (c->gen) raise(INS_ERR_UNSUPPORTED, std::string(what) + " needs the uniform periodic grid");
 }
 
 ins_ctx checked(ins_ctx c) {
@@ -401,6 +421,84 @@ void upload_y_metrics(ins_ctx c, const double* faces) {
     c->wsum = sw * double(g.nx) * double(g.nz);
     c->wy = sw;
     g.ym = c->d_ym;
+}
+
+// Stretched grid: per-direction metrics for i = -1 .. n (layout in Grid::gm):
+// the faces given for that direction or the uniform spacing of the box;
+// periodic images wrap, beyond the channel's walls the first / last row is
+// mirrored (d_{-1} = w_0, d_{n-1} = w_{n-1}, theta = 1/2). wsum becomes the
+// total volume (the CG's weighted means use the full cell volumes here).
+void upload_gen_metrics(ins_ctx c) {
+    ins::Grid& g = c->g;
+    const int d = g.dim;
+    const int n[3] = {g.nx, g.ny, g.nz};
+    size_t total = 0;
+    for (int a = 0; a < d; ++a) total += 5 * size_t(n[a] + 2);
+    if (!c->d_gm) c->d_gm = static_cast<double*>(c->alloc(total * sizeof(double)));
+    std::vector<double> m(total, 0.0);
+    double vol = 1.0;
+    size_t off = 0;
+    for (int a = 0; a < d; ++a) {
+        const int N = n[a], S = N + 2;
+        std::vector<double> w(N);
+        if (c->faces[a].empty()) {
+            std::fill(w.begin(), w.end(), 1.0 / g.ih[a]);
+        } else {
+            for (int i = 0; i < N; ++i) w[i] = c->faces[a][i + 1] - c->faces[a][i];
+        }
+        const bool per = !(a == 1 && c->walls);
+        auto W = [&](int i) { return per ? w[((i % N) + N) % N] : w[std::min(std::max(i, 0), N - 1)]; };
+        double len = 0.0;
+        for (int i = 0; i < N; ++i) len += w[i];
+        for (int i = -1; i <= N; ++i) {
+            const double wi = W(i);
+            double di, thi;
+            if (per || (i >= 0 && i <= N - 2)) {
+                di = 0.5 * (W(i) + W(i + 1));
+                thi = W(i) / (W(i) + W(i + 1));
+            } else {
+                di = W(i);
+                thi = 0.5;
+            }
+            m[off + i + 1] = 1.0 / wi;
+            m[off + S + i + 1] = 1.0 / di;
+            m[off + 2 * S + i + 1] = thi;
+            m[off + 3 * S + i + 1] = wi;
+            m[off + 4 * S + i + 1] = di;
+        }
+        vol *= len;
+        off += 5 * size_t(S);
+    }
+    hip_check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    hip_check(hipMemcpy(c->d_gm, m.data(), m.size() * sizeof(double), hipMemcpyHostToDevice), "upload grid metrics");
+    off = 0;
+    for (int a = 0; a < d; ++a) {
+        g.gm[a] = c->d_gm + off;
+        off += 5 * size_t(n[a] + 2);
+    }
+    g.ywalls = c->walls ? 1 : 0;
+    c->wsum = vol;
+}
+
+// Switch a context to the stretched-grid operators (irreversible): the CG
+// workspace of the pressure solve is allocated here for a periodic context.
+void enter_gen(ins_ctx c) {
+    if (c->clos_on) raise(INS_ERR_UNSUPPORTED, "closures need the uniform periodic grid: clear the closure first");
+    if (!c->cg_r) {
+        const ins::Grid& g = c->g;
+        const size_t sb = c->scal_bytes();
+        c->cg_r = static_cast<double*>(c->alloc(sb));
+        c->cg_p[0] = static_cast<double*>(c->alloc(sb));
+        c->cg_p[1] = static_cast<double*>(c->alloc(sb));
+        c->cg_part = static_cast<double*>(c->alloc(5 * size_t(ins::cg_blocks(g)) * g.batch * sizeof(double)));
+        c->cg_st = static_cast<ins::CgScal*>(c->alloc(size_t(g.batch) * sizeof(ins::CgScal)));
+        hip_check(hipMemset(c->cg_st, 0, size_t(g.batch) * sizeof(ins::CgScal)), "hipMemset");
+        hip_check(hipHostMalloc(reinterpret_cast<void**>(&c->cg_host), size_t(g.batch) * sizeof(ins::CgScal)),
+                  "hipHostMalloc");
+    }
+    c->use_direct = false;
+    c->direct_ok = false;
+    c->gen = true;
 }
 
 bool cg_all_done(ins_ctx c) {
@@ -498,9 +596,33 @@ void direct_solve(ins_ctx c, const void* vel, const double* r, double* x, int mo
 
 // p = (D G)^-1 of the divergence of vel (vel != null) or of r. adj (channel):
 // the solve inside the transposed projection, of D Omega_u^{-1} vel.
+// All-float32 comparison mode: the spectral solve of poisson() on a float32
+// spectrum; r and p hold float32 values.
+void poisson_f32(ins_ctx c, const void* vel, const float* r, float* p) {
+    const ins::Grid& g = c->g;
+    ins::cf* spec = reinterpret_cast<ins::cf*>(c->spec);
+    c->launch(vel ? "fft_x_fwd_div" : "fft_x_fwd", [&] {
+        return ins::launch_fft_x_fwd_f32(g, static_cast<const float*>(vel), r, spec, c->px, c->d_postf, c->lnl_x,
+                                         c->stream);
+    });
+    if (g.dim == 3) {
+        c->launch("fft_y_fwd", [&] { return ins::launch_fft_strided_f32(g, spec, c->py, c->py, 1, 0, c->lnl_y, c->st, c->stream); });
+        c->launch("fft_z_solve", [&] { return ins::launch_fft_strided_f32(g, spec, c->pz, c->pz_rev, 2, 2, c->lnl_z, c->st, c->stream); });
+        c->launch("fft_y_inv", [&] { return ins::launch_fft_strided_f32(g, spec, c->py, c->py, 1, 1, c->lnl_y, c->st, c->stream); });
+    } else {
+        c->launch("fft_y_solve", [&] { return ins::launch_fft_strided_f32(g, spec, c->py, c->py_rev, 1, 2, c->lnl_y, c->st, c->stream); });
+    }
+    c->launch("fft_x_inv", [&] { return ins::launch_fft_x_inv_f32(g, spec, p, c->px, c->d_postf, c->lnl_x, c->stream); });
+}
+
 void poisson(ins_ctx c, const void* vel, const double* r, double* p, bool adj = false) {
     const ins::Grid& g = c->g;
-    if (c->walls) {
+    if (c->f32all()) {
+        // pressure-point buffers hold float32 values in this mode
+        poisson_f32(c, vel, reinterpret_cast<const float*>(r), reinterpret_cast<float*>(p));
+        return;
+    }
+    if (c->walls || c->gen) {
         if (c->use_direct)
             direct_solve(c, vel, r, p, vel ? (adj ? 1 : 0) : 2);
         else
@@ -535,6 +657,18 @@ void poisson(ins_ctx c, const void* vel, const double* r, double* p, bool adj = 
 // projection Omega_u P Omega_u^{-1} (on the periodic grid P^T = P).
 template <typename T>
 void apply_projection(ins_ctx c, const T* w, const double* p, T* out, bool adj = false) {
+    if (c->f32all()) {
+        c->launch("apply_projection", [&] {
+            return ins::launch_apply_projection_f32(c->g, reinterpret_cast<const float*>(w),
+                                                    reinterpret_cast<const float*>(p), reinterpret_cast<float*>(out),
+                                                    c->stream);
+        });
+        return;
+    }
+    if (c->gen) {
+        c->launch("gen_projection", [&] { return ins::launch_gen_project<T>(c->g, w, p, out, adj, c->stream); });
+        return;
+    }
     if (c->walls) {
         c->launch("wall_projection", [&] { return ins::launch_wall_project<T>(c->g, w, p, out, adj, c->stream); });
         return;
@@ -675,6 +809,18 @@ void stage(ins_ctx c, const T* w, const double* p, bool proj, const T* u0, T* y,
     const char* name = label ? label
                              : !proj ? (y ? "stage_first" : "stage_first_rec")
                                      : (y ? (wout ? "stage" : "stage_last") : "stage_rec");
+    if (c->f32all()) {
+        c->launch(name, [&] {
+            return ins::launch_stage_f32(c->g, reinterpret_cast<const float*>(w), reinterpret_cast<const float*>(p),
+                                         proj, reinterpret_cast<const float*>(u0), reinterpret_cast<float*>(y), yinit,
+                                         cy, reinterpret_cast<float*>(wout), cw, c->stream);
+        });
+        return;
+    }
+    if (c->gen) {
+        c->launch(name, [&] { return ins::launch_gen_stage<T>(c->g, w, p, proj, u0, y, yinit, cy, wout, cw, c->stream); });
+        return;
+    }
     if (c->walls) {
         c->launch(name, [&] { return ins::launch_wall_stage<T>(c->g, w, p, proj, u0, y, yinit, cy, wout, cw, c->stream); });
         return;
@@ -741,6 +887,13 @@ template <typename T>
 void stage_vjp(ins_ctx c, const T* w, const double* p, bool proj_u, const T* ybar, const T* un, const double* q,
                bool has_w, double cb, double cw, T* u0bar, int mode, T* out) {
     const char* name = mode == 0 ? "stage_vjp_first" : (mode >= 2 ? "stage_vjp_last" : "stage_vjp");
+    if (c->gen) {
+        c->launch(name, [&] {
+            return ins::launch_gen_stage_vjp<T>(c->g, w, p, proj_u, ybar, un, q, has_w, cb, cw, u0bar, mode, out,
+                                                c->stream);
+        });
+        return;
+    }
     if (c->walls) {
         c->launch(name, [&] {
             return ins::launch_wall_stage_vjp<T>(c->g, w, p, proj_u, ybar, un, q, has_w, cb, cw, u0bar, mode, out,
@@ -936,6 +1089,27 @@ bool setup_fft(ins_ctx c, const std::vector<int>& rx, const std::vector<int>& ry
     c->pz_rev.tw = c->d_tw;
     for (int a = 0; a < 3; ++a) c->st.lam[a] = c->d_lam + off[a];
     c->st.inv_ncell = 1.0 / double(g.ncell);
+    if (c->dtype == INS_FP32_ALL) {
+        // the all-float32 comparison mode: the same tables rounded to float32, a float32 spectrum
+        std::vector<ins::cf> twf(std::max<size_t>(tw.size(), 1)), postf(post.size());
+        std::vector<float> lamf(lam.size());
+        for (size_t i = 0; i < tw.size(); ++i) twf[i] = ins::cf{float(tw[i].x), float(tw[i].y)};
+        for (size_t i = 0; i < post.size(); ++i) postf[i] = ins::cf{float(post[i].x), float(post[i].y)};
+        for (size_t i = 0; i < lam.size(); ++i) lamf[i] = float(lam[i]);
+        c->d_twf = static_cast<ins::cf*>(c->alloc(twf.size() * sizeof(ins::cf)));
+        c->d_postf = static_cast<ins::cf*>(c->alloc(postf.size() * sizeof(ins::cf)));
+        c->d_lamf = static_cast<float*>(c->alloc(lamf.size() * sizeof(float)));
+        hip_check(hipMemcpy(c->d_twf, twf.data(), twf.size() * sizeof(ins::cf), hipMemcpyHostToDevice), "upload twiddles");
+        hip_check(hipMemcpy(c->d_postf, postf.data(), postf.size() * sizeof(ins::cf), hipMemcpyHostToDevice),
+                  "upload twiddles");
+        hip_check(hipMemcpy(c->d_lamf, lamf.data(), lamf.size() * sizeof(float), hipMemcpyHostToDevice),
+                  "upload eigenvalues");
+        for (ins::FftPlan* pl : {&c->px, &c->py, &c->pz, &c->py_rev, &c->pz_rev}) pl->twf = c->d_twf;
+        for (int a = 0; a < 3; ++a) c->st.lamf[a] = c->d_lamf + off[a];
+        c->st.inv_ncellf = float(1.0 / double(g.ncell));
+        c->spec = static_cast<cd*>(c->alloc(size_t(g.batch) * g.nz * g.ny * g.sx * sizeof(ins::cf)));
+        return true;
+    }
     c->spec = static_cast<cd*>(c->alloc(size_t(g.batch) * g.nz * g.ny * g.sx * sizeof(cd)));
     return true;
 }
@@ -948,7 +1122,9 @@ ins_status ins_create(const ins_grid* grid, ins_bc bc, double nu, ins_dtype dtyp
         need(out, "out");
         if (bc != INS_BC_PERIODIC && bc != INS_BC_WALLS_Y) raise(INS_ERR_UNSUPPORTED, "unknown boundary condition");
         const bool walls = bc == INS_BC_WALLS_Y;
-        if (dtype != INS_FP64 && dtype != INS_FP32) raise(INS_ERR_INVALID, "unknown dtype");
+        if (dtype != INS_FP64 && dtype != INS_FP32 && dtype != INS_FP32_ALL) raise(INS_ERR_INVALID, "unknown dtype");
+        if (dtype == INS_FP32_ALL && walls)
+            raise(INS_ERR_UNSUPPORTED, "the all-float32 comparison mode runs on the periodic grid only");
         if (grid->dim != 2 && grid->dim != 3) raise(INS_ERR_UNSUPPORTED, "dim must be 2 or 3");
         if (!(nu >= 0.0) || !std::isfinite(nu)) raise(INS_ERR_INVALID, "nu must be finite and >= 0");
         if (grid->batch < 1 || grid->batch > (1 << 20)) raise(INS_ERR_INVALID, "batch must be >= 1");
@@ -1061,6 +1237,12 @@ ins_status ins_rhs(ins_ctx ctx, const void* u, void* f) {
         need(f, "f");
         with_type(ctx, [&](auto tag) {
             using T = decltype(tag);
+            if (ctx->gen) {
+                ctx->launch("gen_rhs", [&] {
+                    return ins::launch_gen_rhs<T>(ctx->g, static_cast<const T*>(u), static_cast<T*>(f), ctx->stream);
+                });
+                return;
+            }
             if (ctx->walls) {
                 ctx->launch("wall_rhs", [&] {
                     return ins::launch_wall_rhs<T>(ctx->g, static_cast<const T*>(u), static_cast<T*>(f), ctx->stream);
@@ -1075,14 +1257,25 @@ ins_status ins_rhs(ins_ctx ctx, const void* u, void* f) {
     });
 }
 
-ins_status ins_divergence(ins_ctx ctx, const void* u, double* r) {
+ins_status ins_divergence(ins_ctx ctx, const void* u, void* rv) {
     return guarded([&] {
         checked(ctx);
         need(u, "u");
-        need(r, "r");
+        need(rv, "r");
+        if (ctx->f32all()) {
+            ctx->launch("divergence", [&] {
+                return ins::launch_divergence_f32(ctx->g, static_cast<const float*>(u), static_cast<float*>(rv), ctx->stream);
+            });
+            return;
+        }
+        double* r = static_cast<double*>(rv);
         with_type(ctx, [&](auto tag) {
             using T = decltype(tag);
-            if (ctx->walls)
+            if (ctx->gen)
+                ctx->launch("gen_divergence", [&] {
+                    return ins::launch_gen_divergence<T>(ctx->g, static_cast<const T*>(u), r, ctx->stream);
+                });
+            else if (ctx->walls)
                 ctx->launch("wall_divergence", [&] {
                     return ins::launch_wall_divergence<T>(ctx->g, static_cast<const T*>(u), r, ctx->stream);
                 });
@@ -1092,14 +1285,23 @@ ins_status ins_divergence(ins_ctx ctx, const void* u, double* r) {
     });
 }
 
-ins_status ins_gradient(ins_ctx ctx, const double* p, void* gout) {
+ins_status ins_gradient(ins_ctx ctx, const void* pv, void* gout) {
     return guarded([&] {
         checked(ctx);
-        need(p, "p");
+        need(pv, "p");
         need(gout, "g");
+        if (ctx->f32all()) {
+            ctx->launch("gradient", [&] {
+                return ins::launch_gradient_f32(ctx->g, static_cast<const float*>(pv), static_cast<float*>(gout), ctx->stream);
+            });
+            return;
+        }
+        const double* p = static_cast<const double*>(pv);
         with_type(ctx, [&](auto tag) {
             using T = decltype(tag);
-            if (ctx->walls)
+            if (ctx->gen)
+                ctx->launch("gen_gradient", [&] { return ins::launch_gen_gradient<T>(ctx->g, p, static_cast<T*>(gout), ctx->stream); });
+            else if (ctx->walls)
                 ctx->launch("wall_gradient", [&] { return ins::launch_wall_gradient<T>(ctx->g, p, static_cast<T*>(gout), ctx->stream); });
             else
                 ctx->launch("gradient", [&] { return ins::launch_gradient<T>(ctx->g, p, static_cast<T*>(gout), ctx->stream); });
@@ -1107,21 +1309,23 @@ ins_status ins_gradient(ins_ctx ctx, const double* p, void* gout) {
     });
 }
 
-ins_status ins_poisson_solve(ins_ctx ctx, const double* r, double* p) {
+// Pressure-point arguments are void*: float64 values, float32 in the
+// all-float32 comparison mode (poisson() reinterprets them there).
+ins_status ins_poisson_solve(ins_ctx ctx, const void* r, void* p) {
     return guarded([&] {
         checked(ctx);
         need(r, "r");
         need(p, "p");
-        poisson(ctx, nullptr, r, p);
+        poisson(ctx, nullptr, static_cast<const double*>(r), static_cast<double*>(p));
     });
 }
 
-ins_status ins_project(ins_ctx ctx, const void* u, void* u_out, double* p_out) {
+ins_status ins_project(ins_ctx ctx, const void* u, void* u_out, void* p_out) {
     return guarded([&] {
         checked(ctx);
         need(u, "u");
         need(u_out, "u_out");
-        double* pp = p_out ? p_out : ctx->p;
+        double* pp = p_out ? static_cast<double*>(p_out) : ctx->p;
         poisson(ctx, u, nullptr, pp);
         with_type(ctx, [&](auto tag) {
             using T = decltype(tag);
@@ -1151,6 +1355,13 @@ ins_status ins_rhs_vjp(ins_ctx ctx, const void* u, const void* fbar, void* ubar)
         need(ubar, "ubar");
         with_type(ctx, [&](auto tag) {
             using T = decltype(tag);
+            if (ctx->gen) {
+                ctx->launch("gen_rhs_vjp", [&] {
+                    return ins::launch_gen_rhs_vjp<T>(ctx->g, static_cast<const T*>(u), static_cast<const T*>(fbar),
+                                                      static_cast<T*>(ubar), ctx->stream);
+                });
+                return;
+            }
             if (ctx->walls) {
                 ctx->launch("wall_rhs_vjp", [&] {
                     return ins::launch_wall_rhs_vjp<T>(ctx->g, static_cast<const T*>(u), static_cast<const T*>(fbar),
@@ -1173,11 +1384,14 @@ ins_status ins_rhs_vjp(ins_ctx ctx, const void* u, const void* fbar, void* ubar)
 ins_status ins_divergence_vjp(ins_ctx ctx, const double* rbar, void* ubar) {
     return guarded([&] {
         checked(ctx);
+        no_f32all(ctx, "ins_divergence_vjp");
         need(rbar, "rbar");
         need(ubar, "ubar");
         with_type(ctx, [&](auto tag) {
             using T = decltype(tag);
-            if (ctx->walls)
+            if (ctx->gen)
+                ctx->launch("gen_divergence_vjp", [&] { return ins::launch_gen_div_vjp<T>(ctx->g, rbar, static_cast<T*>(ubar), ctx->stream); });
+            else if (ctx->walls)
                 ctx->launch("wall_divergence_vjp", [&] { return ins::launch_wall_div_vjp<T>(ctx->g, rbar, static_cast<T*>(ubar), ctx->stream); });
             else
                 ctx->launch("divergence_vjp", [&] { return ins::launch_div_vjp<T>(ctx->g, rbar, static_cast<T*>(ubar), ctx->stream); });
@@ -1188,11 +1402,14 @@ ins_status ins_divergence_vjp(ins_ctx ctx, const double* rbar, void* ubar) {
 ins_status ins_gradient_vjp(ins_ctx ctx, const void* gbar, double* pbar) {
     return guarded([&] {
         checked(ctx);
+        no_f32all(ctx, "ins_gradient_vjp");
         need(gbar, "gbar");
         need(pbar, "pbar");
         with_type(ctx, [&](auto tag) {
             using T = decltype(tag);
-            if (ctx->walls)
+            if (ctx->gen)
+                ctx->launch("gen_gradient_vjp", [&] { return ins::launch_gen_grad_vjp<T>(ctx->g, static_cast<const T*>(gbar), pbar, ctx->stream); });
+            else if (ctx->walls)
                 ctx->launch("wall_gradient_vjp", [&] { return ins::launch_wall_grad_vjp<T>(ctx->g, static_cast<const T*>(gbar), pbar, ctx->stream); });
             else
                 ctx->launch("gradient_vjp", [&] { return ins::launch_grad_vjp<T>(ctx->g, static_cast<const T*>(gbar), pbar, ctx->stream); });
@@ -1200,8 +1417,10 @@ ins_status ins_gradient_vjp(ins_ctx ctx, const void* gbar, double* pbar) {
     });
 }
 
-ins_status ins_poisson_solve_vjp(ins_ctx ctx, const double* pbar, double* rbar) {
-    if (!ctx || !ctx->walls) return ins_poisson_solve(ctx, pbar, rbar);
+ins_status ins_poisson_solve_vjp(ins_ctx ctx, const void* pbarv, void* rbarv) {
+    if (!ctx || !(ctx->walls || ctx->gen)) return ins_poisson_solve(ctx, pbarv, rbarv);
+    const double* pbar = static_cast<const double*>(pbarv);
+    double* rbar = static_cast<double*>(rbarv);
     return guarded([&] {
         checked(ctx);
         need(pbar, "pbar");
@@ -1221,7 +1440,7 @@ ins_status ins_poisson_solve_vjp(ins_ctx ctx, const double* pbar, double* rbar) 
 }
 
 ins_status ins_project_vjp(ins_ctx ctx, const void* ubar_out, void* ubar) {
-    if (!ctx || !ctx->walls) return ins_project(ctx, ubar_out, ubar, nullptr);
+    if (!ctx || !(ctx->walls || ctx->gen)) return ins_project(ctx, ubar_out, ubar, nullptr);
     return guarded([&] {
         checked(ctx);
         need(ubar_out, "ubar_out");
@@ -1238,6 +1457,7 @@ ins_status ins_project_vjp(ins_ctx ctx, const void* ubar_out, void* ubar) {
 ins_status ins_step_rk4_vjp(ins_ctx ctx, const void* u0, const void* u1bar, void* u0bar, double dt) {
     return guarded([&] {
         checked(ctx);
+        no_f32all(ctx, "ins_step_rk4_vjp");
         need(u0, "u0");
         need(u1bar, "u1bar");
         need(u0bar, "u0bar");
@@ -1266,6 +1486,7 @@ ins_status ins_step_wray3(ins_ctx ctx, const void* u0, void* u1, double dt) {
 ins_status ins_step_wray3_vjp(ins_ctx ctx, const void* u0, const void* u1bar, void* u0bar, double dt) {
     return guarded([&] {
         checked(ctx);
+        no_f32all(ctx, "ins_step_wray3_vjp");
         need(u0, "u0");
         need(u1bar, "u1bar");
         need(u0bar, "u0bar");
@@ -1285,6 +1506,7 @@ ins_status ins_step_save(ins_ctx ctx, int scheme, const void* u0, void* u1, doub
                          double* pstages) {
     return guarded([&] {
         checked(ctx);
+        no_f32all(ctx, "ins_step_save");
         need(u0, "u0");
         need(u1, "u1");
         need(stages, "stages");
@@ -1312,6 +1534,7 @@ ins_status ins_step_vjp_saved(ins_ctx ctx, int scheme, const void* u0, const voi
                               const void* u1bar, void* u0bar, double dt) {
     return guarded([&] {
         checked(ctx);
+        no_f32all(ctx, "ins_step_vjp_saved");
         need(u0, "u0");
         need(stages, "stages");
         need(pstages, "pstages");
@@ -1342,7 +1565,7 @@ ins_status ins_step_vjp_saved(ins_ctx ctx, int scheme, const void* u0, const voi
 ins_status ins_cg_set(ins_ctx ctx, double rtol, int maxiter, int check_every) {
     return guarded([&] {
         checked(ctx);
-        if (!ctx->walls) raise(INS_ERR_UNSUPPORTED, "the periodic grid solves by FFT, not CG");
+        if (!ctx->walls && !ctx->gen) raise(INS_ERR_UNSUPPORTED, "the uniform periodic grid solves by FFT, not CG");
         if (!(rtol >= 0.0) || !std::isfinite(rtol)) raise(INS_ERR_INVALID, "rtol must be finite and >= 0");
         if (maxiter < 1 || check_every < 0) raise(INS_ERR_INVALID, "maxiter must be >= 1 and check_every >= 0");
         ctx->cg_rtol = rtol;
@@ -1351,16 +1574,43 @@ ins_status ins_cg_set(ins_ctx ctx, double rtol, int maxiter, int check_every) {
     });
 }
 
+// Checks and stores the n_a + 1 faces of direction a (host copy).
+void store_faces(ins_ctx c, int a, const double* faces) {
+    const int n = a == 0 ? c->g.nx : (a == 1 ? c->g.ny : c->g.nz);
+    for (int j = 0; j <= n; ++j)
+        if (!std::isfinite(faces[j])) raise(INS_ERR_INVALID, "face coordinates must be finite");
+    for (int j = 0; j < n; ++j)
+        if (!(faces[j + 1] > faces[j])) raise(INS_ERR_INVALID, "face coordinates must increase strictly");
+    c->faces[a].assign(faces, faces + n + 1);
+}
+
 ins_status ins_set_y_faces(ins_ctx ctx, const double* faces) {
     return guarded([&] {
         checked(ctx);
         need(faces, "faces");
         if (!ctx->walls) raise(INS_ERR_UNSUPPORTED, "a stretched y grid needs the channel (INS_BC_WALLS_Y)");
-        for (int j = 0; j <= ctx->g.ny; ++j)
-            if (!std::isfinite(faces[j])) raise(INS_ERR_INVALID, "face coordinates must be finite");
-        for (int j = 0; j < ctx->g.ny; ++j)
-            if (!(faces[j + 1] > faces[j])) raise(INS_ERR_INVALID, "face coordinates must increase strictly");
+        store_faces(ctx, 1, faces);
         upload_y_metrics(ctx, faces);
+        if (ctx->gen) upload_gen_metrics(ctx);
+    });
+}
+
+ins_status ins_set_faces(ins_ctx ctx, int axis, const double* faces) {
+    return guarded([&] {
+        checked(ctx);
+        no_f32all(ctx, "ins_set_faces");
+        need(faces, "faces");
+        if (axis < 0 || axis >= ctx->g.dim) raise(INS_ERR_INVALID, "axis must be 0 .. dim - 1");
+        if (ctx->walls && axis == 1) {
+            store_faces(ctx, 1, faces);
+            upload_y_metrics(ctx, faces);
+            if (ctx->gen) upload_gen_metrics(ctx);
+            return;
+        }
+        if (ctx->clos_on) raise(INS_ERR_UNSUPPORTED, "closures need the uniform periodic grid: clear the closure first");
+        store_faces(ctx, axis, faces);
+        if (!ctx->gen) enter_gen(ctx);
+        upload_gen_metrics(ctx);
     });
 }
 
@@ -1380,7 +1630,7 @@ ins_status ins_cg_info(ins_ctx ctx, int* iterations, double* relres) {
         checked(ctx);
         need(iterations, "iterations");
         need(relres, "relres");
-        if (!ctx->walls) raise(INS_ERR_UNSUPPORTED, "the periodic grid solves by FFT, not CG");
+        if (!ctx->walls && !ctx->gen) raise(INS_ERR_UNSUPPORTED, "the uniform periodic grid solves by FFT, not CG");
         cg_all_done(ctx);
         int it = 0;
         double rr = 0.0;
@@ -1398,6 +1648,10 @@ ins_status ins_set_pressure_solver(ins_ctx ctx, int solver) {
         checked(ctx);
         if (solver != INS_PRESSURE_AUTO && solver != INS_PRESSURE_FFT && solver != INS_PRESSURE_CG)
             raise(INS_ERR_INVALID, "unknown pressure solver");
+        if (ctx->gen) {
+            if (solver == INS_PRESSURE_FFT) raise(INS_ERR_UNSUPPORTED, "a stretched grid solves by CG, not FFT");
+            return;
+        }
         if (!ctx->walls) {
             if (solver == INS_PRESSURE_CG) raise(INS_ERR_UNSUPPORTED, "the periodic grid solves by FFT, not CG");
             return;
@@ -1413,7 +1667,7 @@ ins_status ins_get_pressure_solver(ins_ctx ctx, int* solver) {
     return guarded([&] {
         checked(ctx);
         need(solver, "solver");
-        *solver = (ctx->walls && !ctx->use_direct) ? INS_PRESSURE_CG : INS_PRESSURE_FFT;
+        *solver = (ctx->gen || (ctx->walls && !ctx->use_direct)) ? INS_PRESSURE_CG : INS_PRESSURE_FFT;
     });
 }
 
@@ -1438,6 +1692,7 @@ ins_status ins_face_filter(ins_ctx ctx, const void* u, int factor, void* u_coars
 ins_status ins_energy_spectrum(ins_ctx ctx, const void* u, double* e, int nbins) {
     return guarded([&] {
         checked(ctx);
+        no_f32all(ctx, "ins_energy_spectrum");
         periodic_only(ctx, "ins_energy_spectrum");
         need(u, "u");
         need(e, "e");
@@ -1463,6 +1718,7 @@ ins_status ins_energy_spectrum(ins_ctx ctx, const void* u, double* e, int nbins)
 ins_status ins_closure_set(ins_ctx ctx, const float* params) {
     return guarded([&] {
         checked(ctx);
+        no_f32all(ctx, "ins_closure_set");
         periodic_only(ctx, "ins_closure_set");
         if (!params) {
             if (ctx->clos_kind == 1) {
@@ -1494,6 +1750,7 @@ ins_status ins_closure_set(ins_ctx ctx, const float* params) {
 ins_status ins_eddy_set(ins_ctx ctx, double cs, double delta) {
     return guarded([&] {
         checked(ctx);
+        no_f32all(ctx, "ins_eddy_set");
         periodic_only(ctx, "ins_eddy_set");
         if (!(cs >= 0.0) || !std::isfinite(cs)) raise(INS_ERR_INVALID, "cs must be finite and >= 0");
         if (!std::isfinite(delta)) raise(INS_ERR_INVALID, "delta must be finite");
@@ -1521,6 +1778,7 @@ ins_status ins_eddy_set(ins_ctx ctx, double cs, double delta) {
 ins_status ins_eddy_forward(ins_ctx ctx, const void* u, void* m) {
     return guarded([&] {
         checked(ctx);
+        no_f32all(ctx, "ins_eddy_forward");
         periodic_only(ctx, "ins_eddy_forward");
         need(u, "u");
         need(m, "m");
@@ -1535,6 +1793,7 @@ ins_status ins_eddy_forward(ins_ctx ctx, const void* u, void* m) {
 ins_status ins_eddy_backward(ins_ctx ctx, const void* u, const void* mbar, void* ubar) {
     return guarded([&] {
         checked(ctx);
+        no_f32all(ctx, "ins_eddy_backward");
         periodic_only(ctx, "ins_eddy_backward");
         need(u, "u");
         need(mbar, "mbar");
@@ -1569,6 +1828,7 @@ ins_status ins_closure_grad(ins_ctx ctx, float* params_bar) {
 ins_status ins_cnn_forward(ins_ctx ctx, const void* u, void* m) {
     return guarded([&] {
         checked(ctx);
+        no_f32all(ctx, "ins_cnn_forward");
         periodic_only(ctx, "ins_cnn_forward");
         need(u, "u");
         need(m, "m");
@@ -1583,6 +1843,7 @@ ins_status ins_cnn_forward(ins_ctx ctx, const void* u, void* m) {
 ins_status ins_cnn_backward(ins_ctx ctx, const void* u, const void* mbar, void* ubar, float* params_bar) {
     return guarded([&] {
         checked(ctx);
+        no_f32all(ctx, "ins_cnn_backward");
         periodic_only(ctx, "ins_cnn_backward");
         need(u, "u");
         need(mbar, "mbar");

@@ -22,7 +22,9 @@ __device__ __forceinline__ void stats_cell(const Grid& g, const T* __restrict__ 
         s2 += v * v;
         mu = fmax(mu, fabs(v));
         nf += isfinite(v) ? 0.0 : 1.0;
-        dv += (v - vm) * ((a == 1 && g.ym) ? g.ym[t.y] : g.ih[a]);  // channel: 1 / w_j along y
+        const int ca = a == 0 ? t.x : (a == 1 ? t.y : t.z);
+        // stretched grid: 1 / w of this cell per direction; channel: 1 / w_j along y
+        dv += (v - vm) * (g.gm[a] ? g.gm[a][ca + 1] : ((a == 1 && g.ym) ? g.ym[t.y] : g.ih[a]));
     }
     md = fmax(md, fabs(dv));
 }

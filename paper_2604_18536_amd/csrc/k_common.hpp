@@ -47,6 +47,12 @@ __device__ __forceinline__ cd cmul(cd a, cd b) { return {a.x * b.x - a.y * b.y, 
 __device__ __forceinline__ cd cmulc(cd a, cd b) { return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y}; }  // a*conj(b)
 __device__ __forceinline__ cd cscale(cd a, double s) { return {a.x * s, a.y * s}; }
 __device__ __forceinline__ cd cconj(cd a) { return {a.x, -a.y}; }
+__device__ __forceinline__ cf cadd(cf a, cf b) { return {a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ cf csub(cf a, cf b) { return {a.x - b.x, a.y - b.y}; }
+__device__ __forceinline__ cf cmul(cf a, cf b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+__device__ __forceinline__ cf cmulc(cf a, cf b) { return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y}; }  // a*conj(b)
+__device__ __forceinline__ cf cscale(cf a, float s) { return {a.x * s, a.y * s}; }
+__device__ __forceinline__ cf cconj(cf a) { return {a.x, -a.y}; }
 
 // Tile decomposition of a stencil launch: (x-tile, y-tile, z, batch).
 struct TileIdx {
@@ -92,10 +98,12 @@ __device__ __forceinline__ TileIdx tile_of(const Grid& g) {
 // field is the unprojected stage value w and the velocity is w - G p, formed
 // in float64 (the projection of the previous RK stage, Sec. 2.6.2, fused into
 // this stencil so the projected field is never written out).
-template <typename T, bool PROJ>
+// P: the pressure type and the precision of w - G p (float64 except in the
+// all-float32 comparison mode).
+template <typename T, bool PROJ, typename P = double>
 struct VelSrc {
     const T* __restrict__ w;
-    const double* __restrict__ p;
+    const P* __restrict__ p;
     int ncell;
     double ih0, ih1, ih2;
     __device__ __forceinline__ T operator()(int c, const Nb& nb, int dx, int dy, int dz) const {
@@ -104,8 +112,8 @@ struct VelSrc {
             return w[c * ncell + j];
         } else {
             const int jp = nb.at(dx + (c == 0), dy + (c == 1), dz + (c == 2));
-            const double ih = c == 0 ? ih0 : (c == 1 ? ih1 : ih2);
-            return T(double(w[c * ncell + j]) - (p[jp] - p[j]) * ih);
+            const P ih = P(c == 0 ? ih0 : (c == 1 ? ih1 : ih2));
+            return T(P(w[c * ncell + j]) - (p[jp] - p[j]) * ih);
         }
     }
 };

@@ -13,7 +13,9 @@
 //              so each global access is a contiguous run of `lines` values.
 //   last axis: forward FFT, multiply by 1/(L(k) #cells), inverse FFT in the
 //              same launch (the spectrum of that axis never leaves LDS).
-// All spectral arithmetic is float64.
+// The spectral arithmetic runs in the precision of the complex type C: cd
+// (float64, every mode but one) or cf (float32, the all-float32 comparison
+// mode), with twiddles and eigenvalues tabulated in that precision.
 #include "k_common.hpp"
 
 namespace ins {
@@ -42,40 +44,41 @@ __device__ __forceinline__ constexpr double ksin(int R, int j) {
 }
 
 // i * z * sgn
-template <int SIGN>
-__device__ __forceinline__ cd rot(cd z) {
-    return SIGN < 0 ? cd{z.y, -z.x} : cd{-z.y, z.x};
+template <int SIGN, class C>
+__device__ __forceinline__ C rot(C z) {
+    return SIGN < 0 ? C{z.y, -z.x} : C{-z.y, z.x};
 }
 
 // Small DFTs X[m] = sum_q x[q] exp(SIGN 2 pi i q m / R), in place.
-template <int SIGN>
-__device__ __forceinline__ void dft2(cd* v) {
-    const cd a = v[0], b = v[1];
+template <int SIGN, class C>
+__device__ __forceinline__ void dft2(C* v) {
+    const C a = v[0], b = v[1];
     v[0] = cadd(a, b);
     v[1] = csub(a, b);
 }
 
-template <int SIGN>
-__device__ __forceinline__ void dft4(cd& x0, cd& x1, cd& x2, cd& x3) {
-    const cd s02 = cadd(x0, x2), d02 = csub(x0, x2);
-    const cd s13 = cadd(x1, x3), d13 = rot<SIGN>(csub(x1, x3));
+template <int SIGN, class C>
+__device__ __forceinline__ void dft4(C& x0, C& x1, C& x2, C& x3) {
+    const C s02 = cadd(x0, x2), d02 = csub(x0, x2);
+    const C s13 = cadd(x1, x3), d13 = rot<SIGN>(csub(x1, x3));
     x0 = cadd(s02, s13);
     x2 = csub(s02, s13);
     x1 = cadd(d02, d13);
     x3 = csub(d02, d13);
 }
 
-template <int SIGN>
-__device__ __forceinline__ void dft8(cd* v) {
-    cd e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
-    cd o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+template <int SIGN, class C>
+__device__ __forceinline__ void dft8(C* v) {
+    using F = real_of<C>;
+    C e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    C o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
     dft4<SIGN>(e0, e1, e2, e3);
     dft4<SIGN>(o0, o1, o2, o3);
-    constexpr double r = 0.7071067811865476;
+    constexpr F r = F(0.7071067811865476);
     // w^1 = (1 + SIGN i)/sqrt2, w^2 = SIGN i, w^3 = (-1 + SIGN i)/sqrt2
-    const cd t1 = {r * (o1.x - SIGN * o1.y), r * (o1.y + SIGN * o1.x)};
-    const cd t2 = rot<SIGN>(o2);
-    const cd t3 = {r * (-o3.x - SIGN * o3.y), r * (-o3.y + SIGN * o3.x)};
+    const C t1 = {r * (o1.x - SIGN * o1.y), r * (o1.y + SIGN * o1.x)};
+    const C t2 = rot<SIGN>(o2);
+    const C t3 = {r * (-o3.x - SIGN * o3.y), r * (-o3.y + SIGN * o3.x)};
     v[0] = cadd(e0, o0);
     v[4] = csub(e0, o0);
     v[1] = cadd(e1, t1);
@@ -88,39 +91,40 @@ __device__ __forceinline__ void dft8(cd* v) {
 
 // Odd R: pair x[q] with x[R-q]; X[m] = A_m + SIGN i B_m, X[R-m] = A_m - SIGN i B_m with
 // A_m = x0 + sum_q (x_q + x_{R-q}) cos(2 pi q m / R), B_m = sum_q (x_q - x_{R-q}) sin(2 pi q m / R).
-template <int R, int SIGN>
-__device__ __forceinline__ void dft_odd(cd* v) {
+template <int R, int SIGN, class C>
+__device__ __forceinline__ void dft_odd(C* v) {
+    using F = real_of<C>;
     constexpr int H = (R - 1) / 2;
-    cd s[H], d[H];
+    C s[H], d[H];
 #pragma unroll
     for (int q = 1; q <= H; ++q) {
         s[q - 1] = cadd(v[q], v[R - q]);
         d[q - 1] = csub(v[q], v[R - q]);
     }
-    const cd x0 = v[0];
-    cd sum = x0;
+    const C x0 = v[0];
+    C sum = x0;
 #pragma unroll
     for (int q = 0; q < H; ++q) sum = cadd(sum, s[q]);
     v[0] = sum;
 #pragma unroll
     for (int m = 1; m <= H; ++m) {
-        cd A = x0, B = {0.0, 0.0};
+        C A = x0, B = {F(0), F(0)};
 #pragma unroll
         for (int q = 1; q <= H; ++q) {
             const int j = (q * m) % R;
-            A.x += s[q - 1].x * kcos(R, j);
-            A.y += s[q - 1].y * kcos(R, j);
-            B.x += d[q - 1].x * ksin(R, j);
-            B.y += d[q - 1].y * ksin(R, j);
+            A.x += s[q - 1].x * F(kcos(R, j));
+            A.y += s[q - 1].y * F(kcos(R, j));
+            B.x += d[q - 1].x * F(ksin(R, j));
+            B.y += d[q - 1].y * F(ksin(R, j));
         }
-        const cd iB = rot<SIGN>(B);
+        const C iB = rot<SIGN>(B);
         v[m] = cadd(A, iB);
         v[R - m] = csub(A, iB);
     }
 }
 
-template <int R, int SIGN>
-__device__ __forceinline__ void dft(cd* v) {
+template <int R, int SIGN, class C>
+__device__ __forceinline__ void dft(C* v) {
     if constexpr (R == 2) dft2<SIGN>(v);
     else if constexpr (R == 4) dft4<SIGN>(v[0], v[1], v[2], v[3]);
     else if constexpr (R == 8) dft8<SIGN>(v);
@@ -174,15 +178,15 @@ __device__ __forceinline__ void slot_of(int t, int lnl, int S, float rS, int& l,
 //          applied at once; its outputs i R + q go to LDS when the inverse has
 //          more stages (`more`), else to sink.
 // The LDS reads of an IN 1 stage that writes LDS are followed by a barrier.
-template <int R, int SIGN, int VM, int NTH, int IN, int OUT, int MAP, class Load, class Sink, class Div>
-__device__ __forceinline__ void fft_stage(cd* __restrict__ lds, int lnl, int ls, int N, int p, const cd* __restrict__ tw,
+template <int R, int SIGN, int VM, int NTH, int IN, int OUT, int MAP, class C, class Load, class Sink, class Div>
+__device__ __forceinline__ void fft_stage(C* __restrict__ lds, int lnl, int ls, int N, int p, const C* __restrict__ tw,
                                           const Load& load, const Sink& sink, const Div& divf, bool more) {
     constexpr int BMAX = VM / R > 0 ? VM / R : 1;
     const int S = N / R;
     const int nb = S << lnl;
     const float rS = __builtin_amdgcn_rcpf(static_cast<float>(S));
     const float rp = __builtin_amdgcn_rcpf(static_cast<float>(p));
-    cd w[BMAX * R];
+    C w[BMAX * R];
 #pragma unroll
     for (int b = 0; b < BMAX; ++b) {
         const int t = threadIdx.x + b * NTH;
@@ -205,9 +209,9 @@ __device__ __forceinline__ void fft_stage(cd* __restrict__ lds, int lnl, int ls,
             slot_of<MAP>(t, lnl, S, rS, l, i);
             int k;
             fdivmod(i, p, rp, k);
-            cd* x = w + b * R;
+            C* x = w + b * R;
             if (k != 0) {
-                const cd* twk = tw + k * (R - 1) - 1;
+                const C* twk = tw + k * (R - 1) - 1;
 #pragma unroll
                 for (int q = 1; q < R; ++q) x[q] = SIGN < 0 ? cmul(x[q], twk[q]) : cmulc(x[q], twk[q]);
             }
@@ -238,8 +242,8 @@ __device__ __forceinline__ void fft_stage(cd* __restrict__ lds, int lnl, int ls,
     }
 }
 
-template <int SIGN, int VM, int NTH, int IN, int OUT, int MAP, class Load, class Sink, class Div>
-__device__ __forceinline__ void fft_stage_r(int R, cd* lds, int lnl, int ls, int N, int p, const cd* tw,
+template <int SIGN, int VM, int NTH, int IN, int OUT, int MAP, class C, class Load, class Sink, class Div>
+__device__ __forceinline__ void fft_stage_r(int R, C* lds, int lnl, int ls, int N, int p, const C* tw,
                                             const Load& load, const Sink& sink, const Div& divf, bool more) {
     switch (R) {
         case 8: fft_stage<8, SIGN, VM, NTH, IN, OUT, MAP>(lds, lnl, ls, N, p, tw, load, sink, divf, more); break;
@@ -252,8 +256,19 @@ __device__ __forceinline__ void fft_stage_r(int R, cd* lds, int lnl, int ls, int
 }
 
 struct NoOp {
-    __device__ cd operator()(int, int, cd z) const { return z; }
+    template <class C>
+    __device__ C operator()(int, int, C z) const { return z; }
 };
+
+// The plan's twiddle table in the precision of C.
+__device__ __forceinline__ const cd* plan_tw(const FftPlan& P, cd) { return P.tw; }
+__device__ __forceinline__ const cf* plan_tw(const FftPlan& P, cf) { return P.twf; }
+
+// The solve's eigenvalue tables and 1 / #cells in the precision of C.
+__device__ __forceinline__ const double* const* solve_lam(const SolveTab& st, cd) { return st.lam; }
+__device__ __forceinline__ const float* const* solve_lam(const SolveTab& st, cf) { return st.lamf; }
+__device__ __forceinline__ double solve_inv_ncell(const SolveTab& st, cd) { return st.inv_ncell; }
+__device__ __forceinline__ float solve_inv_ncell(const SolveTab& st, cf) { return st.inv_ncellf; }
 
 // Every stage of plan P on nl = 2^lnl lines (LDS line stride ls); LDS must be
 // free on entry. The first stage reads through `load` with mapping MAP0 (IN0 0)
@@ -263,41 +278,43 @@ struct NoOp {
 // pivot of a solve whose inverse plan is Q (then call fft_inverse_rest).
 // The first and last stages are peeled off the loop so that the address
 // arithmetic of the memory-facing stages is not kept live across the others.
-template <int SIGN, int VM, int NTH, int IN0, int OUTL, int MAP0, int MAPL, class Load, class Sink, class Div>
-__device__ __forceinline__ void fft_run(cd* lds, int lnl, int ls, const FftPlan& P, const Load& load, const Sink& sink,
+template <int SIGN, int VM, int NTH, int IN0, int OUTL, int MAP0, int MAPL, class C, class Load, class Sink, class Div>
+__device__ __forceinline__ void fft_run(C* lds, int lnl, int ls, const FftPlan& P, const Load& load, const Sink& sink,
                                         const Div& divf, const FftPlan* Q) {
+    const C* tw = plan_tw(P, C{});
     const int ns = P.nst;
     const bool more = OUTL == 2 && Q->nst > 1;
     if (ns == 1) {
-        fft_stage_r<SIGN, VM, NTH, IN0, OUTL, MAP0>(P.rad[0], lds, lnl, ls, P.n, 1, P.tw + P.tw_off[0], load, sink, divf,
+        fft_stage_r<SIGN, VM, NTH, IN0, OUTL, MAP0>(P.rad[0], lds, lnl, ls, P.n, 1, tw + P.tw_off[0], load, sink, divf,
                                                 more);
         return;
     }
-    fft_stage_r<SIGN, VM, NTH, IN0, 0, MAP0>(P.rad[0], lds, lnl, ls, P.n, 1, P.tw + P.tw_off[0], load, sink, divf, false);
+    fft_stage_r<SIGN, VM, NTH, IN0, 0, MAP0>(P.rad[0], lds, lnl, ls, P.n, 1, tw + P.tw_off[0], load, sink, divf, false);
     int p = P.rad[0];
     for (int st = 1; st < ns - 1; ++st) {
-        fft_stage_r<SIGN, VM, NTH, 1, 0, kLineFast>(P.rad[st], lds, lnl, ls, P.n, p, P.tw + P.tw_off[st], load, sink, divf,
+        fft_stage_r<SIGN, VM, NTH, 1, 0, kLineFast>(P.rad[st], lds, lnl, ls, P.n, p, tw + P.tw_off[st], load, sink, divf,
                                                false);
         p *= P.rad[st];
     }
-    fft_stage_r<SIGN, VM, NTH, 1, OUTL, MAPL>(P.rad[ns - 1], lds, lnl, ls, P.n, p, P.tw + P.tw_off[ns - 1], load, sink,
+    fft_stage_r<SIGN, VM, NTH, 1, OUTL, MAPL>(P.rad[ns - 1], lds, lnl, ls, P.n, p, tw + P.tw_off[ns - 1], load, sink,
                                          divf, more);
 }
 
 // The stages of inverse plan Q after a pivot consumed its first one (nothing
 // when Q has a single stage): LDS to LDS, the last one to sink (mapping MAPL).
-template <int SIGN, int VM, int NTH, int MAPL, class Sink>
-__device__ __forceinline__ void fft_inverse_rest(cd* lds, int lnl, int ls, const FftPlan& Q, const Sink& sink) {
+template <int SIGN, int VM, int NTH, int MAPL, class C, class Sink>
+__device__ __forceinline__ void fft_inverse_rest(C* lds, int lnl, int ls, const FftPlan& Q, const Sink& sink) {
+    const C* tw = plan_tw(Q, C{});
     const int ns = Q.nst;
     if (ns == 1) return;
     const NoOp nop;
     int p = Q.rad[0];
     for (int st = 1; st < ns - 1; ++st) {
-        fft_stage_r<SIGN, VM, NTH, 1, 0, kLineFast>(Q.rad[st], lds, lnl, ls, Q.n, p, Q.tw + Q.tw_off[st], nop, sink, nop,
+        fft_stage_r<SIGN, VM, NTH, 1, 0, kLineFast>(Q.rad[st], lds, lnl, ls, Q.n, p, tw + Q.tw_off[st], nop, sink, nop,
                                                false);
         p *= Q.rad[st];
     }
-    fft_stage_r<SIGN, VM, NTH, 1, 1, MAPL>(Q.rad[ns - 1], lds, lnl, ls, Q.n, p, Q.tw + Q.tw_off[ns - 1], nop, sink, nop,
+    fft_stage_r<SIGN, VM, NTH, 1, 1, MAPL>(Q.rad[ns - 1], lds, lnl, ls, Q.n, p, tw + Q.tw_off[ns - 1], nop, sink, nop,
                                       false);
 }
 
@@ -306,8 +323,8 @@ __device__ __forceinline__ void fft_inverse_rest(cd* lds, int lnl, int ls, const
 // stride ls) are conflict-free; then synchronise. (Along x a first stage that
 // read memory directly would write its butterfly outputs i R + q from
 // neighbouring threads R elements apart: bank conflicts.)
-template <int NTH, class Load>
-__device__ __forceinline__ void stage_rows(cd* __restrict__ lds, int lnl, int ls, int N, const Load& load) {
+template <int NTH, class C, class Load>
+__device__ __forceinline__ void stage_rows(C* __restrict__ lds, int lnl, int ls, int N, const Load& load) {
     const int nl = 1 << lnl;
     const float rN = __builtin_amdgcn_rcpf(static_cast<float>(N));
     for (int t = threadIdx.x; t < nl * N; t += NTH) {
@@ -319,12 +336,14 @@ __device__ __forceinline__ void stage_rows(cd* __restrict__ lds, int lnl, int ls
 }
 
 // Two consecutive values of a row (x even), as one load.
-__device__ __forceinline__ void ld_pair(const double* p, double& a, double& b) {
+template <class F>
+__device__ __forceinline__ void ld_pair(const double* p, F& a, F& b) {
     const double2 t = *reinterpret_cast<const double2*>(p);
-    a = t.x;
-    b = t.y;
+    a = F(t.x);
+    b = F(t.y);
 }
-__device__ __forceinline__ void ld_pair(const float* p, double& a, double& b) {
+template <class F>
+__device__ __forceinline__ void ld_pair(const float* p, F& a, F& b) {
     const float2 t = *reinterpret_cast<const float2*>(p);
     a = t.x;
     b = t.y;
@@ -343,11 +362,13 @@ __device__ __forceinline__ void ld_pair(const float* p, double& a, double& b) {
 // projection.
 // The rows are staged in LDS first (see stage_rows); the untangling needs Z[k]
 // and Z[M-k] together, so the last stage writes to LDS as well.
-template <typename T, int DIM, int SRC, int VM, int NTH>
-__global__ __launch_bounds__(NTH) void k_fft_x_fwd(Grid g, const T* __restrict__ vel, const double* __restrict__ r,
-                                                        cd* __restrict__ spec, FftPlan P, const cd* __restrict__ post,
-                                                        int lnl, int comp) {
-    extern __shared__ cd lds[];
+template <typename T, int DIM, int SRC, int VM, int NTH, class C = cd>
+__global__ __launch_bounds__(NTH) void k_fft_x_fwd(Grid g, const T* __restrict__ vel,
+                                                        const real_of<C>* __restrict__ r, C* __restrict__ spec,
+                                                        FftPlan P, const C* __restrict__ post, int lnl, int comp) {
+    using F = real_of<C>;
+    extern __shared__ __align__(16) unsigned char fft_smem[];
+    C* lds = reinterpret_cast<C*>(fft_smem);
     const int nl = 1 << lnl;
     const int ls = nl + P.pad;
     const int M = P.n;
@@ -355,11 +376,11 @@ __global__ __launch_bounds__(NTH) void k_fft_x_fwd(Grid g, const T* __restrict__
     const int row0 = xcd_logical(blockIdx.x, gridDim.x) * nl;
     // (y, z, batch) of the first row; row0 + l follows by carrying (l < nl <= 16)
     const int yy0 = row0 % g.ny, zb0 = row0 / g.ny, zz0 = zb0 % g.nz, b0 = zb0 / g.nz;
-    auto load = [&](int l, int m) INS_INLINE -> cd {
+    auto load = [&](int l, int m) INS_INLINE -> C {
         const int row = row0 + l;
-        if (row >= nrows) return cd{0.0, 0.0};
+        if (row >= nrows) return C{F(0), F(0)};
         if constexpr (SRC == 1) {
-            return reinterpret_cast<const cd*>(r + int64_t(row) * g.nx)[m];
+            return reinterpret_cast<const C*>(r + int64_t(row) * g.nx)[m];
         } else {
             int yy = yy0 + l, zz = zz0, b = b0;
             while (yy >= g.ny) {
@@ -372,9 +393,9 @@ __global__ __launch_bounds__(NTH) void k_fft_x_fwd(Grid g, const T* __restrict__
             const int rowoff = (zz * g.ny + yy) * g.nx;
             const int x0 = 2 * m;
             if constexpr (SRC == 2) {
-                double a0, a1;
+                F a0, a1;
                 ld_pair(vel + (int64_t(b) * DIM + comp) * g.ncell + rowoff + x0, a0, a1);
-                return cd{a0, a1};
+                return C{a0, a1};
             } else if constexpr (SRC >= 3) {
                 const T* wb = vel + int64_t(b) * DIM * g.ncell;
                 const int S = g.ny + 2;
@@ -412,32 +433,32 @@ __global__ __launch_bounds__(NTH) void k_fft_x_fwd(Grid g, const T* __restrict__
                 const double iw = g.ym[yy];
                 r0 += (uy0 - vy0) * iw;
                 r1 += (uy1 - vy1) * iw;
-                return cd{r0, r1};
+                return C{F(r0), F(r1)};
             } else {
                 const T* wb = vel + int64_t(b) * DIM * g.ncell;
                 const int xm = x0 == 0 ? g.nx - 1 : x0 - 1;
-                double ux0, ux1;
+                F ux0, ux1;
                 ld_pair(wb + rowoff + x0, ux0, ux1);
-                const double uxm = wb[rowoff + xm];
-                double r0 = (ux0 - uxm) * g.ih[0];
-                double r1 = (ux1 - ux0) * g.ih[0];
+                const F uxm = wb[rowoff + xm];
+                F r0 = (ux0 - uxm) * F(g.ih[0]);
+                F r1 = (ux1 - ux0) * F(g.ih[0]);
                 const int ym = yy == 0 ? g.ny - 1 : yy - 1;
                 const T* wy = wb + g.ncell;
-                double uy0, uy1, vy0, vy1;
+                F uy0, uy1, vy0, vy1;
                 ld_pair(wy + rowoff + x0, uy0, uy1);
                 ld_pair(wy + (zz * g.ny + ym) * g.nx + x0, vy0, vy1);
-                r0 += (uy0 - vy0) * g.ih[1];
-                r1 += (uy1 - vy1) * g.ih[1];
+                r0 += (uy0 - vy0) * F(g.ih[1]);
+                r1 += (uy1 - vy1) * F(g.ih[1]);
                 if constexpr (DIM == 3) {
                     const int zm = zz == 0 ? g.nz - 1 : zz - 1;
                     const T* wz = wb + 2 * g.ncell;
-                    double uz0, uz1, vz0, vz1;
+                    F uz0, uz1, vz0, vz1;
                     ld_pair(wz + rowoff + x0, uz0, uz1);
                     ld_pair(wz + (zm * g.ny + yy) * g.nx + x0, vz0, vz1);
-                    r0 += (uz0 - vz0) * g.ih[2];
-                    r1 += (uz1 - vz1) * g.ih[2];
+                    r0 += (uz0 - vz0) * F(g.ih[2]);
+                    r1 += (uz1 - vz1) * F(g.ih[2]);
                 }
-                return cd{r0, r1};
+                return C{r0, r1};
             }
         }
     };
@@ -451,11 +472,11 @@ __global__ __launch_bounds__(NTH) void k_fft_x_fwd(Grid g, const T* __restrict__
         const int l = fdivmod(t, M1, rM1, k);
         const int row = row0 + l;
         if (row >= nrows) continue;
-        const cd zk = lds[(k == M ? 0 : k) * ls + l];
-        const cd zc = cconj(lds[(k == 0 ? 0 : M - k) * ls + l]);
-        const cd e = cscale(cadd(zk, zc), 0.5);
-        const cd dd = csub(zk, zc);
-        const cd o = {0.5 * dd.y, -0.5 * dd.x};
+        const C zk = lds[(k == M ? 0 : k) * ls + l];
+        const C zc = cconj(lds[(k == 0 ? 0 : M - k) * ls + l]);
+        const C e = cscale(cadd(zk, zc), F(0.5));
+        const C dd = csub(zk, zc);
+        const C o = {F(0.5) * dd.y, F(-0.5) * dd.x};
         spec[int64_t(row) * g.sx + k] = cadd(e, cmul(post[k], o));
     }
 }
@@ -464,28 +485,30 @@ __global__ __launch_bounds__(NTH) void k_fft_x_fwd(Grid g, const T* __restrict__
 // Z[k] = (X[k] + conj X[M-k]) + i (X[k] - conj X[M-k]) conj(W^k), z = IFFT_M(Z),
 // x[2m] = Re z[m], x[2m+1] = Im z[m]. The tangled rows are staged in LDS; the
 // last stage writes the real rows directly (element-fast).
-template <int VM, int NTH>
-__global__ __launch_bounds__(NTH) void k_fft_x_inv(Grid g, const cd* __restrict__ spec, double* __restrict__ p,
-                                                        FftPlan P, const cd* __restrict__ post, int lnl) {
-    extern __shared__ cd lds[];
+template <int VM, int NTH, class C = cd>
+__global__ __launch_bounds__(NTH) void k_fft_x_inv(Grid g, const C* __restrict__ spec, real_of<C>* __restrict__ p,
+                                                        FftPlan P, const C* __restrict__ post, int lnl) {
+    using F = real_of<C>;
+    extern __shared__ __align__(16) unsigned char fft_smem[];
+    C* lds = reinterpret_cast<C*>(fft_smem);
     const int nl = 1 << lnl;
     const int ls = nl + P.pad;
     const int M = P.n;
     const int nrows = g.batch * g.nz * g.ny;
     const int row0 = xcd_logical(blockIdx.x, gridDim.x) * nl;
-    auto load = [&](int l, int k) INS_INLINE -> cd {
+    auto load = [&](int l, int k) INS_INLINE -> C {
         const int row = row0 + l;
-        if (row >= nrows) return cd{0.0, 0.0};
-        const cd* sr = spec + int64_t(row) * g.sx;
-        const cd xk = sr[k];
-        const cd xc = cconj(sr[M - k]);
-        const cd e = cadd(xk, xc);
-        const cd o = cmulc(csub(xk, xc), post[k]);
-        return cd{e.x - o.y, e.y + o.x};
+        if (row >= nrows) return C{F(0), F(0)};
+        const C* sr = spec + int64_t(row) * g.sx;
+        const C xk = sr[k];
+        const C xc = cconj(sr[M - k]);
+        const C e = cadd(xk, xc);
+        const C o = cmulc(csub(xk, xc), post[k]);
+        return C{e.x - o.y, e.y + o.x};
     };
-    auto sink = [&](int l, int m, cd z) INS_INLINE {
+    auto sink = [&](int l, int m, C z) INS_INLINE {
         const int row = row0 + l;
-        if (row < nrows) reinterpret_cast<cd*>(p + int64_t(row) * g.nx)[m] = z;
+        if (row < nrows) reinterpret_cast<C*>(p + int64_t(row) * g.nx)[m] = z;
     };
     const NoOp nop;
     stage_rows<NTH>(lds, lnl, ls, M, load);
@@ -504,10 +527,12 @@ __global__ __launch_bounds__(NTH) void k_fft_x_inv(Grid g, const cd* __restrict_
 // its outputs in registers, they are divided there, and the inverse runs the
 // stages in reverse radix order (plan Q, whose first radix is P's last) from
 // those same registers.
-template <int MODE, int VM, int NTH>
-__global__ __launch_bounds__(NTH) void k_fft_strided(Grid g, cd* __restrict__ spec, FftPlan P, FftPlan Q, int axis,
+template <int MODE, int VM, int NTH, class C = cd>
+__global__ __launch_bounds__(NTH) void k_fft_strided(Grid g, C* __restrict__ spec, FftPlan P, FftPlan Q, int axis,
                                                           int lnl, SolveTab st) {
-    extern __shared__ cd lds[];
+    using F = real_of<C>;
+    extern __shared__ __align__(16) unsigned char fft_smem[];
+    C* lds = reinterpret_cast<C*>(fft_smem);
     const int nl = 1 << lnl;
     const int M = g.nx / 2;
     const int nxh = M + 1;
@@ -544,10 +569,10 @@ __global__ __launch_bounds__(NTH) void k_fft_strided(Grid g, cd* __restrict__ sp
         nvalid = nfix - f0;
     }
     const int ls = nl + P.pad;
-    auto load = [&](int l, int e) INS_INLINE -> cd {
-        return l < nvalid ? spec[lb0 + l * lstep + e * stride] : cd{0.0, 0.0};
+    auto load = [&](int l, int e) INS_INLINE -> C {
+        return l < nvalid ? spec[lb0 + l * lstep + e * stride] : C{F(0), F(0)};
     };
-    auto store = [&](int l, int e, cd z) INS_INLINE {
+    auto store = [&](int l, int e, C z) INS_INLINE {
         if (l < nvalid) spec[lb0 + l * lstep + e * stride] = z;
     };
     const NoOp nop;
@@ -557,20 +582,22 @@ __global__ __launch_bounds__(NTH) void k_fft_strided(Grid g, cd* __restrict__ sp
         fft_run<-1, VM, NTH, 0, 1, kLineFast, kLineFast>(lds, lnl, ls, P, load, store, nop, nullptr);
     } else {
         // divide by L(k) * #cells; L(0) := 1.
-        auto divide = [&](int l, int e, cd z) INS_INLINE -> cd {
+        const F* const* lt = solve_lam(st, C{});
+        const F inv_ncell = solve_inv_ncell(st, C{});
+        auto divide = [&](int l, int e, C z) INS_INLINE -> C {
             if (l >= nvalid) return z;
             const int kx = kx0 + l * kxstep;
             const int fk = fk0 + l * fkstep;
-            double lam;
+            F lam;
             bool kzero;
             if (axis == 2) {
-                lam = st.lam[0][kx] + st.lam[1][fk] + st.lam[2][e];
+                lam = lt[0][kx] + lt[1][fk] + lt[2][e];
                 kzero = (kx == 0 && fk == 0 && e == 0);
             } else {
-                lam = st.lam[0][kx] + st.lam[1][e];
+                lam = lt[0][kx] + lt[1][e];
                 kzero = (kx == 0 && e == 0);
             }
-            const double sc = kzero ? st.inv_ncell : -st.inv_ncell / lam;
+            const F sc = kzero ? inv_ncell : -inv_ncell / lam;
             return cscale(z, sc);
         };
         fft_run<-1, VM, NTH, 0, 2, kLineFast, kLineFast>(lds, lnl, ls, P, load, store, divide, &Q);
@@ -581,16 +608,18 @@ __global__ __launch_bounds__(NTH) void k_fft_strided(Grid g, cd* __restrict__ sp
 // ----------------------------------------------------------------------------
 // Launchers
 // ----------------------------------------------------------------------------
-template <typename T>
-hipError_t launch_fft_x_fwd(const Grid& g, const T* vel, const double* r, cd* spec, const FftPlan& px, const cd* post,
-                            int lnl, hipStream_t s, int comp) {
+namespace {
+
+template <typename T, class C>
+hipError_t fft_x_fwd(const Grid& g, const T* vel, const real_of<C>* r, C* spec, const FftPlan& px, const C* post,
+                     int lnl, hipStream_t s, int comp) {
     const int nl = 1 << lnl;
     const int nrows = g.batch * g.nz * g.ny;
     const int nblk = (nrows + nl - 1) / nl;
-    const size_t shm = size_t(nl + px.pad) * px.n * sizeof(cd);
+    const size_t shm = size_t(nl + px.pad) * px.n * sizeof(C);
 #define INS_XF(D, SRC, VM, NTH)                                                                                \
-    hipLaunchKernelGGL((k_fft_x_fwd<T, D, SRC, VM, NTH>), dim3(nblk), dim3(NTH), shm, s, g, vel, r, spec, px, post, lnl, \
-                       comp)
+    hipLaunchKernelGGL((k_fft_x_fwd<T, D, SRC, VM, NTH, C>), dim3(nblk), dim3(NTH), shm, s, g, vel, r, spec, px, post, \
+                       lnl, comp)
 #define INS_XF_VM(D, SRC)                                    \
     do {                                                     \
         if (px.nth == 1024) INS_XF(D, SRC, 8, 1024);         \
@@ -609,31 +638,33 @@ hipError_t launch_fft_x_fwd(const Grid& g, const T* vel, const double* r, cd* sp
     return hipGetLastError();
 }
 
-hipError_t launch_fft_x_inv(const Grid& g, const cd* spec, double* p, const FftPlan& px, const cd* post, int lnl,
-                            hipStream_t s) {
+template <class C>
+hipError_t fft_x_inv(const Grid& g, const C* spec, real_of<C>* p, const FftPlan& px, const C* post, int lnl,
+                     hipStream_t s) {
     const int nl = 1 << lnl;
     const int nrows = g.batch * g.nz * g.ny;
     const int nblk = (nrows + nl - 1) / nl;
-    const size_t shm = size_t(nl + px.pad) * px.n * sizeof(cd);
+    const size_t shm = size_t(nl + px.pad) * px.n * sizeof(C);
     if (px.nth == 1024)
-        hipLaunchKernelGGL((k_fft_x_inv<8, 1024>), dim3(nblk), dim3(1024), shm, s, g, spec, p, px, post, lnl);
+        hipLaunchKernelGGL((k_fft_x_inv<8, 1024, C>), dim3(nblk), dim3(1024), shm, s, g, spec, p, px, post, lnl);
     else if (px.vm == 8)
-        hipLaunchKernelGGL((k_fft_x_inv<8, 256>), dim3(nblk), dim3(256), shm, s, g, spec, p, px, post, lnl);
+        hipLaunchKernelGGL((k_fft_x_inv<8, 256, C>), dim3(nblk), dim3(256), shm, s, g, spec, p, px, post, lnl);
     else
-        hipLaunchKernelGGL((k_fft_x_inv<16, 256>), dim3(nblk), dim3(256), shm, s, g, spec, p, px, post, lnl);
+        hipLaunchKernelGGL((k_fft_x_inv<16, 256, C>), dim3(nblk), dim3(256), shm, s, g, spec, p, px, post, lnl);
     return hipGetLastError();
 }
 
-hipError_t launch_fft_strided(const Grid& g, cd* spec, const FftPlan& pl, const FftPlan& rev, int axis, int mode,
-                              int lnl, const SolveTab& st, hipStream_t s) {
+template <class C>
+hipError_t fft_strided(const Grid& g, C* spec, const FftPlan& pl, const FftPlan& rev, int axis, int mode, int lnl,
+                       const SolveTab& st, hipStream_t s) {
     const int nl = 1 << lnl;
     const int nchunk = (g.nx / 2 + nl - 1) / nl;
     const int nouter = axis == 1 ? g.batch * g.nz : g.batch * g.ny;
     const int nfix = axis == 1 ? g.nz : g.ny;
     const int nblk = nchunk * nouter + g.batch * ((nfix + nl - 1) / nl);  // + the Nyquist-column workgroups
-    const size_t shm = size_t(nl + pl.pad) * pl.n * sizeof(cd);
+    const size_t shm = size_t(nl + pl.pad) * pl.n * sizeof(C);
 #define INS_ST(MODE, VM, NTH) \
-    hipLaunchKernelGGL((k_fft_strided<MODE, VM, NTH>), dim3(nblk), dim3(NTH), shm, s, g, spec, pl, rev, axis, lnl, st)
+    hipLaunchKernelGGL((k_fft_strided<MODE, VM, NTH, C>), dim3(nblk), dim3(NTH), shm, s, g, spec, pl, rev, axis, lnl, st)
 #define INS_ST_VM(MODE)                                  \
     do {                                                 \
         if (pl.nth == 512) INS_ST(MODE, 8, 512);         \
@@ -649,6 +680,39 @@ hipError_t launch_fft_strided(const Grid& g, cd* spec, const FftPlan& pl, const 
 #undef INS_ST_VM
 #undef INS_ST
     return hipGetLastError();
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_fft_x_fwd(const Grid& g, const T* vel, const double* r, cd* spec, const FftPlan& px, const cd* post,
+                            int lnl, hipStream_t s, int comp) {
+    return fft_x_fwd<T, cd>(g, vel, r, spec, px, post, lnl, s, comp);
+}
+
+hipError_t launch_fft_x_inv(const Grid& g, const cd* spec, double* p, const FftPlan& px, const cd* post, int lnl,
+                            hipStream_t s) {
+    return fft_x_inv<cd>(g, spec, p, px, post, lnl, s);
+}
+
+hipError_t launch_fft_strided(const Grid& g, cd* spec, const FftPlan& pl, const FftPlan& rev, int axis, int mode,
+                              int lnl, const SolveTab& st, hipStream_t s) {
+    return fft_strided<cd>(g, spec, pl, rev, axis, mode, lnl, st, s);
+}
+
+hipError_t launch_fft_x_fwd_f32(const Grid& g, const float* vel, const float* r, cf* spec, const FftPlan& px,
+                                const cf* post, int lnl, hipStream_t s) {
+    return fft_x_fwd<float, cf>(g, vel, r, spec, px, post, lnl, s, -1);
+}
+
+hipError_t launch_fft_x_inv_f32(const Grid& g, const cf* spec, float* p, const FftPlan& px, const cf* post, int lnl,
+                                hipStream_t s) {
+    return fft_x_inv<cf>(g, spec, p, px, post, lnl, s);
+}
+
+hipError_t launch_fft_strided_f32(const Grid& g, cf* spec, const FftPlan& pl, const FftPlan& rev, int axis, int mode,
+                                  int lnl, const SolveTab& st, hipStream_t s) {
+    return fft_strided<cf>(g, spec, pl, rev, axis, mode, lnl, st, s);
 }
 
 template <typename T>

@@ -45,8 +45,10 @@ __device__ __forceinline__ void st_stream(T v, T* p) {
     __builtin_nontemporal_store(v, p);
 }
 
-template <typename T, bool PROJ, int TX, int TY>
-__global__ __launch_bounds__(TX * TY) void k_stage_zm(Grid g, const T* __restrict__ w, const double* __restrict__ p,
+// P: type of the pressure and of the projection arithmetic w - G p (float64;
+// float32 only in the all-float32 comparison mode).
+template <typename T, bool PROJ, int TX, int TY, typename P = double>
+__global__ __launch_bounds__(TX * TY) void k_stage_zm(Grid g, const T* __restrict__ w, const P* __restrict__ p,
                                                         const T* __restrict__ u0, T* __restrict__ y, int yinit, T cy,
                                                         T* __restrict__ wout, T cw, int zc, const T* __restrict__ mc) {
     constexpr int NT = TX * TY, HX = TX + 2, HP = HX * (TY + 2);
@@ -65,7 +67,7 @@ __global__ __launch_bounds__(TX * TY) void k_stage_zm(Grid g, const T* __restric
     const int z1 = min(z0 + zc, nz);
     const int64_t boff = int64_t(b) * 3 * g.ncell;
     const T* wb = w + boff;
-    const double* pb = PROJ ? p + int64_t(b) * g.ncell : nullptr;
+    const P* pb = PROJ ? p + int64_t(b) * g.ncell : nullptr;
     const int nc = int(g.ncell);
     const int plane = nx * ny;
 
@@ -97,10 +99,10 @@ __global__ __launch_bounds__(TX * TY) void k_stage_zm(Grid g, const T* __restric
             if (hq[s] < HP) {
                 const int j = zoff + hxy[s];
                 if constexpr (PROJ) {
-                    const double pc = pb[j];
-                    pre[s][0] = T(double(wb[j]) - (pb[zoff + hxp[s]] - pc) * g.ih[0]);
-                    pre[s][1] = T(double(wb[nc + j]) - (pb[zoff + hyp[s]] - pc) * g.ih[1]);
-                    pre[s][2] = T(double(wb[2 * nc + j]) - (pb[zpo + hxy[s]] - pc) * g.ih[2]);
+                    const P pc = pb[j];
+                    pre[s][0] = T(P(wb[j]) - (pb[zoff + hxp[s]] - pc) * P(g.ih[0]));
+                    pre[s][1] = T(P(wb[nc + j]) - (pb[zoff + hyp[s]] - pc) * P(g.ih[1]));
+                    pre[s][2] = T(P(wb[2 * nc + j]) - (pb[zpo + hxy[s]] - pc) * P(g.ih[2]));
                 } else {
                     pre[s][0] = wb[j];
                     pre[s][1] = wb[nc + j];
@@ -195,18 +197,18 @@ int zm_chunk(const Grid& g) { return zm_chunk(g, kZmTX, kZmTY, 2048, 32); }
 // faster than 64.
 int zm_chunk_stage(const Grid& g, bool fp64) { return zm_chunk(g, 64, 8, fp64 ? 512 : 1024, 64); }
 
-template <typename T, int TX, int TY>
-void launch_stage_zm_tile(const Grid& g, const T* w, const double* p, bool proj, const T* u0, T* y, bool yinit,
+template <typename T, int TX, int TY, typename P = double>
+void launch_stage_zm_tile(const Grid& g, const T* w, const P* p, bool proj, const T* u0, T* y, bool yinit,
                           double cy, T* wout, double cw, hipStream_t s, const T* mc) {
     const int zc = zm_chunk_stage(g, sizeof(T) == 8);
     const int nblk = ((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY) * ((g.nz + zc - 1) / zc) * g.batch;
     const int yi = yinit ? 1 : 0;
     if (proj)
-        hipLaunchKernelGGL((k_stage_zm<T, true, TX, TY>), dim3(nblk), dim3(TX * TY), 0, s, g, w, p, u0, y, yi, T(cy),
-                           wout, T(cw), zc, mc);
+        hipLaunchKernelGGL((k_stage_zm<T, true, TX, TY, P>), dim3(nblk), dim3(TX * TY), 0, s, g, w, p, u0, y, yi,
+                           T(cy), wout, T(cw), zc, mc);
     else
-        hipLaunchKernelGGL((k_stage_zm<T, false, TX, TY>), dim3(nblk), dim3(TX * TY), 0, s, g, w, p, u0, y, yi, T(cy),
-                           wout, T(cw), zc, mc);
+        hipLaunchKernelGGL((k_stage_zm<T, false, TX, TY, P>), dim3(nblk), dim3(TX * TY), 0, s, g, w, p, u0, y, yi,
+                           T(cy), wout, T(cw), zc, mc);
 }
 
 // The forward stage runs 64 x 8 tiles of 512 threads: the 512-byte row runs
@@ -224,6 +226,13 @@ template hipError_t launch_stage_zm<double>(const Grid&, const double*, const do
                                             double, double*, double, hipStream_t, const double*);
 template hipError_t launch_stage_zm<float>(const Grid&, const float*, const double*, bool, const float*, float*, bool,
                                            double, float*, double, hipStream_t, const float*);
+
+// All-float32 comparison mode: float32 pressure and projection arithmetic.
+hipError_t launch_stage_zm_f32(const Grid& g, const float* w, const float* p, bool proj, const float* u0, float* y,
+                               bool yinit, double cy, float* wout, double cw, hipStream_t s) {
+    launch_stage_zm_tile<float, 64, 8, float>(g, w, p, proj, u0, y, yinit, cy, wout, cw, s, nullptr);
+    return hipGetLastError();
+}
 
 }  // namespace ins
 

@@ -28,15 +28,15 @@ __global__ __launch_bounds__(kBlock) void k_rhs(Grid g, const T* __restrict__ u,
 // RK4 stage on 2D grids (3D grids use the z-march of k_stage3d.hip):
 // u_i = (PROJ ? w - G p : w), F = F(u_i) (+ mc, the closure term at u_i, if given),
 // (if y) y = (yinit ? u0 : y) + cy F, and (if wout) wout = u0 + cw F.
-template <typename T, int DIM, bool PROJ>
-__global__ __launch_bounds__(kBlock) void k_stage(Grid g, const T* __restrict__ w, const double* __restrict__ p,
+template <typename T, int DIM, bool PROJ, typename P = double>
+__global__ __launch_bounds__(kBlock) void k_stage(Grid g, const T* __restrict__ w, const P* __restrict__ p,
                                                    const T* __restrict__ u0, T* __restrict__ y, int yinit, T cy,
                                                    T* __restrict__ wout, T cw, const T* __restrict__ mc) {
     const TileIdx t = tile_of(g);
     if (!t.valid) return;
     const Nb nb = make_nb<DIM>(g, t.x, t.y, t.z);
     const int64_t boff = int64_t(t.b) * DIM * g.ncell;
-    VelSrc<T, PROJ> U{w + boff, PROJ ? p + int64_t(t.b) * g.ncell : nullptr, int(g.ncell), g.ih[0], g.ih[1], g.ih[2]};
+    VelSrc<T, PROJ, P> U{w + boff, PROJ ? p + int64_t(t.b) * g.ncell : nullptr, int(g.ncell), g.ih[0], g.ih[1], g.ih[2]};
     T F[DIM];
     rhs_cell<T, DIM>(g, U, nb, F);
     const int c0 = nb.at(0, 0, 0);
@@ -50,55 +50,56 @@ __global__ __launch_bounds__(kBlock) void k_stage(Grid g, const T* __restrict__ 
     }
 }
 
-// r = D u (float64), eq. div-kernel.
-template <typename T, int DIM>
-__global__ __launch_bounds__(kBlock) void k_divergence(Grid g, const T* __restrict__ u, double* __restrict__ r) {
+// r = D u (in P: float64, float32 only in the all-float32 mode), eq. div-kernel.
+template <typename T, int DIM, typename P = double>
+__global__ __launch_bounds__(kBlock) void k_divergence(Grid g, const T* __restrict__ u, P* __restrict__ r) {
     const TileIdx t = tile_of(g);
     if (!t.valid) return;
     const Nb nb = make_nb<DIM>(g, t.x, t.y, t.z);
     const T* ub = u + int64_t(t.b) * DIM * g.ncell;
     const int c0 = nb.at(0, 0, 0);
-    double acc = 0.0;
+    P acc = P(0);
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
         const int cm = nb.at(-(a == 0), -(a == 1), -(a == 2));
-        acc += (double(ub[a * g.ncell + c0]) - double(ub[a * g.ncell + cm])) * g.ih[a];
+        acc += (P(ub[a * g.ncell + c0]) - P(ub[a * g.ncell + cm])) * P(g.ih[a]);
     }
     r[int64_t(t.b) * g.ncell + c0] = acc;
 }
 
 // g = G p, eq. presgrad-kernel.
-template <typename T, int DIM>
-__global__ __launch_bounds__(kBlock) void k_gradient(Grid g, const double* __restrict__ p, T* __restrict__ out) {
+template <typename T, int DIM, typename P = double>
+__global__ __launch_bounds__(kBlock) void k_gradient(Grid g, const P* __restrict__ p, T* __restrict__ out) {
     const TileIdx t = tile_of(g);
     if (!t.valid) return;
     const Nb nb = make_nb<DIM>(g, t.x, t.y, t.z);
-    const double* pb = p + int64_t(t.b) * g.ncell;
+    const P* pb = p + int64_t(t.b) * g.ncell;
     T* ob = out + int64_t(t.b) * DIM * g.ncell;
     const int c0 = nb.at(0, 0, 0);
-    const double pc = pb[c0];
+    const P pc = pb[c0];
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
         const int cp = nb.at(a == 0, a == 1, a == 2);
-        ob[a * g.ncell + c0] = T((pb[cp] - pc) * g.ih[a]);
+        ob[a * g.ncell + c0] = T((pb[cp] - pc) * P(g.ih[a]));
     }
 }
 
-// u_out = w - G p, in float64; u_out may alias w (pointwise in w).
-template <typename T, int DIM>
-__global__ __launch_bounds__(kBlock) void k_apply_projection(Grid g, const T* w, const double* __restrict__ p, T* u_out) {
+// u_out = w - G p, in P (float64 except in the all-float32 mode); u_out may
+// alias w (pointwise in w).
+template <typename T, int DIM, typename P = double>
+__global__ __launch_bounds__(kBlock) void k_apply_projection(Grid g, const T* w, const P* __restrict__ p, T* u_out) {
     const TileIdx t = tile_of(g);
     if (!t.valid) return;
     const Nb nb = make_nb<DIM>(g, t.x, t.y, t.z);
-    const double* pb = p + int64_t(t.b) * g.ncell;
+    const P* pb = p + int64_t(t.b) * g.ncell;
     const int64_t boff = int64_t(t.b) * DIM * g.ncell;
     const int c0 = nb.at(0, 0, 0);
-    const double pc = pb[c0];
+    const P pc = pb[c0];
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
         const int cp = nb.at(a == 0, a == 1, a == 2);
         const int64_t k = boff + a * g.ncell + c0;
-        u_out[k] = T(double(w[k]) - (pb[cp] - pc) * g.ih[a]);
+        u_out[k] = T(P(w[k]) - (pb[cp] - pc) * P(g.ih[a]));
     }
 }
 
@@ -196,6 +197,49 @@ hipError_t launch_stage(const Grid& g, const T* w, const double* p, bool proj, c
     else
         hipLaunchKernelGGL((k_stage<T, 2, false>), dim3(nblk), dim3(kBlock), 0, s, g, w, p, u0, y, yi, T(cy), wout, T(cw),
                            mc);
+    return hipGetLastError();
+}
+
+// All-float32 comparison mode: float32 pressure-point fields and arithmetic.
+hipError_t launch_divergence_f32(const Grid& g, const float* u, float* r, hipStream_t s) {
+    const int nblk = stencil_blocks(g);
+    if (g.dim == 3)
+        hipLaunchKernelGGL((k_divergence<float, 3, float>), dim3(nblk), dim3(kBlock), 0, s, g, u, r);
+    else
+        hipLaunchKernelGGL((k_divergence<float, 2, float>), dim3(nblk), dim3(kBlock), 0, s, g, u, r);
+    return hipGetLastError();
+}
+
+hipError_t launch_gradient_f32(const Grid& g, const float* p, float* out, hipStream_t s) {
+    const int nblk = stencil_blocks(g);
+    if (g.dim == 3)
+        hipLaunchKernelGGL((k_gradient<float, 3, float>), dim3(nblk), dim3(kBlock), 0, s, g, p, out);
+    else
+        hipLaunchKernelGGL((k_gradient<float, 2, float>), dim3(nblk), dim3(kBlock), 0, s, g, p, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_apply_projection_f32(const Grid& g, const float* w, const float* p, float* u_out, hipStream_t s) {
+    const int nblk = stencil_blocks(g);
+    if (g.dim == 3)
+        hipLaunchKernelGGL((k_apply_projection<float, 3, float>), dim3(nblk), dim3(kBlock), 0, s, g, w, p, u_out);
+    else
+        hipLaunchKernelGGL((k_apply_projection<float, 2, float>), dim3(nblk), dim3(kBlock), 0, s, g, w, p, u_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_stage_f32(const Grid& g, const float* w, const float* p, bool proj, const float* u0, float* y,
+                            bool yinit, double cy, float* wout, double cw, hipStream_t s) {
+    if (g.dim == 3) return launch_stage_zm_f32(g, w, p, proj, u0, y, yinit, cy, wout, cw, s);
+    const int nblk = stencil_blocks(g);
+    const int yi = yinit ? 1 : 0;
+    const float* mc = nullptr;
+    if (proj)
+        hipLaunchKernelGGL((k_stage<float, 2, true, float>), dim3(nblk), dim3(kBlock), 0, s, g, w, p, u0, y, yi,
+                           float(cy), wout, float(cw), mc);
+    else
+        hipLaunchKernelGGL((k_stage<float, 2, false, float>), dim3(nblk), dim3(kBlock), 0, s, g, w, p, u0, y, yi,
+                           float(cy), wout, float(cw), mc);
     return hipGetLastError();
 }
 

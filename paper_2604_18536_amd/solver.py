@@ -13,7 +13,8 @@ import torch
 
 from . import _lib as L
 
-_DTYPES = {"fp64": (L.INS_FP64, torch.float64), "fp32": (L.INS_FP32, torch.float32)}
+_DTYPES = {"fp64": (L.INS_FP64, torch.float64), "fp32": (L.INS_FP32, torch.float32),
+           "fp32_all": (L.INS_FP32_ALL, torch.float32)}
 _BCS = {"periodic": L.INS_BC_PERIODIC, "walls": L.INS_BC_WALLS_Y}
 _PRESSURE = {"auto": L.INS_PRESSURE_AUTO, "fft": L.INS_PRESSURE_FFT, "cg": L.INS_PRESSURE_CG}
 
@@ -24,9 +25,11 @@ class Solver:
     Args:
         n: cells per direction, (n_x, n_y) or (n_x, n_y, n_z).
         nu: kinematic viscosity.
-        precision: "fp64" (everything float64) or "fp32" (float32 velocity
+        precision: "fp64" (everything float64), "fp32" (float32 velocity
             fields, stencils and RK stages; float64 divergence, Poisson solve
-            and projection).
+            and projection) or "fp32_all" (for comparison: everything float32,
+            pressure-point fields and the FFT solve included; periodic grid,
+            forward operators and steps only).
         batch: number of independent fields per call.
         lo, hi: box corners (default [0, 2 pi] per direction).
         bc: "periodic" (every direction; FFT pressure solve) or "walls"
@@ -54,6 +57,8 @@ class Solver:
         self.batch = int(batch)
         self.precision = precision
         self._code, self.dtype = _DTYPES[precision]
+        # pressure-point fields: float64, float32 in the all-float32 comparison mode
+        self.pdtype = torch.float32 if precision == "fp32_all" else torch.float64
         self.lo = tuple(float(v) for v in (lo if lo is not None else [0.0] * self.dim))
         self.hi = tuple(float(v) for v in (hi if hi is not None else [2 * math.pi] * self.dim))
         self.h = tuple((self.hi[a] - self.lo[a]) / self.n[a] for a in range(self.dim))
@@ -93,7 +98,7 @@ class Solver:
 
     def _check(self, t, kind, name):
         shape = self.vel_shape if kind == "vel" else self.scal_shape
-        dtype = self.dtype if kind == "vel" else torch.float64
+        dtype = self.dtype if kind == "vel" else self.pdtype
         if not isinstance(t, torch.Tensor):
             raise TypeError(f"{name} must be a torch tensor")
         if t.device != self.device:
@@ -115,7 +120,7 @@ class Solver:
             shape = self.vel_shape if kind == "vel" else self.scal_shape
             if self._unbatched(like):
                 shape = shape[1:]
-            dtype = self.dtype if kind == "vel" else torch.float64
+            dtype = self.dtype if kind == "vel" else self.pdtype
             return torch.empty(shape, dtype=dtype, device=self.device)
         return out
 
@@ -124,7 +129,7 @@ class Solver:
         return t.zero_() if fill is None else t.fill_(fill)
 
     def new_scalar(self):
-        return torch.zeros(self.scal_shape, dtype=torch.float64, device=self.device)
+        return torch.zeros(self.scal_shape, dtype=self.pdtype, device=self.device)
 
     def set_pressure(self, solver):
         """Pressure solver for later calls: "auto", "fft" or "cg"."""
@@ -161,6 +166,24 @@ class Solver:
         self._sync_stream()
         L.call("ins_set_y_faces", self._ctx, f.ctypes.data_as(C.POINTER(C.c_double)))
         self.y_faces = f.copy()
+
+    def set_faces(self, axis, faces):
+        """Stretch direction ``axis`` (0 = x, 1 = y, 2 = z): its n + 1 face coordinates
+        (host values, increasing). A periodic direction wraps with the period
+        faces[-1] - faces[0]. Stretching a periodic direction switches the solver to
+        the stretched-grid kernels and the CG pressure solve for good."""
+        import numpy as _np
+
+        axis = int(axis)
+        if not 0 <= axis < self.dim:
+            raise ValueError("axis must be 0 .. dim - 1")
+        f = _np.ascontiguousarray(_np.asarray(faces, dtype=_np.float64))
+        if f.shape != (self.n[axis] + 1,):
+            raise ValueError(f"faces must hold n + 1 = {self.n[axis] + 1} coordinates")
+        self._sync_stream()
+        L.call("ins_set_faces", self._ctx, axis, f.ctypes.data_as(C.POINTER(C.c_double)))
+        if axis == 1:
+            self.y_faces = f.copy()
 
     def cg_info(self):
         """(iterations, relative residual) of the last pressure solve (maxima over the batch)."""
