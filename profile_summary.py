@@ -11,7 +11,8 @@
   --cells=N records the cell count of the profiled field; bench.py uses a record only for that size)
 
 `traffic` also updates profiles/traffic.json, the measured HBM bytes per
-launch that bench.py reports as roofline.traffic. Counters are calibrated with
+launch that bench.py reports as roofline.traffic (a list of records per
+kernel variant, one per profiled field size). Counters are calibrated with
 the library's plain copy kernel (k_stream_copy, bytes known): the measured
 FETCH_SIZE and WRITE_SIZE of every kernel are scaled by
 (bytes the copy moved) / (what the counter read for it). A record carries a
@@ -44,7 +45,7 @@ VARIANT_ORDERS = {
         "void ins::k_fft_strided<2,": (["fft_z_solve"], ["k_fft.hip", "k_common.hpp"]),
         "void ins::k_fft_strided<1,": (["fft_y_inv"], ["k_fft.hip", "k_common.hpp"]),
         "void ins::k_fft_x_inv<": (["fft_x_inv"], ["k_fft.hip", "k_common.hpp"]),
-        "void ins::k_apply_projection<double, 3>": (["apply_projection"], ["k_stencil.hip", "k_common.hpp"]),
+        "void ins::k_apply_projection<double, 3,": (["apply_projection"], ["k_stencil.hip", "k_common.hpp"]),
     },
     # channel, direct pressure solve (FFTs along x and z, tridiagonal solves along y)
     "channel": {
@@ -151,8 +152,12 @@ def traffic(fetch_csv, write_csv, out_md, command, copy_bytes=None, order=None, 
         for name, (a, b, n) in per.items():
             lines.append(f"| `{names[0].replace('void ', '')}` as {name} | {n} | {a / n / 2**20:.1f} | {b / n / 2**20:.1f} | "
                          f"{(a + b) / n / 2**20:.1f} |")
-            rec[name] = {"bytes_per_launch": round((a + b) / n), "fetch": round(a / n), "write": round(b / n),
-                         "sources": srcs, "source_hash": source_hash(srcs), "cells": cells}
+            new = {"bytes_per_launch": round((a + b) / n), "fetch": round(a / n), "write": round(b / n),
+                   "sources": srcs, "source_hash": source_hash(srcs), "cells": cells}
+            # one record per profiled field size: replace the one of the same size
+            old = rec.get(name, [])
+            old = old if isinstance(old, list) else [old]
+            rec[name] = [r for r in old if r.get("cells") != cells] + [new]
     open(out_md, "w").write("\n".join(lines) + "\n")
     json.dump(rec, open(jpath, "w"), indent=1, sort_keys=True)
 
