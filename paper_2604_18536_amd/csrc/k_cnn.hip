@@ -72,7 +72,13 @@ enum { EPI_HIDDEN = 0, EPI_OUT = 1, EPI_DGRAD_HIDDEN = 2, EPI_DGRAD_INPUT = 3 };
 // operands from LDS instead of re-fetching them from memory. Wave w computes
 // the output rows (y, z) = (r % 4, r / 4), r = 2w, 2w + 1: four 16-cell M tiles.
 // B operands (packed weights) come from global memory (every wave of every
-// workgroup reads the same few KB per tap; they stay cache-resident). Hidden
+// workgroup reads the same few KB per tap; they stay cache-resident).
+// Wave w computes the output row y = w of both z planes (M tiles mt: plane
+// mt / 2, x half mt % 2). With 32 input channels the K loop runs over the
+// nine (ty, tx) tap columns and, inside, over the four halo planes: each A
+// operand fetched from LDS serves both output planes (taps tz = hz - z), so
+// a wave reads 8 A operands per tap column instead of 12 (the kernel is bound
+// by LDS operand reads, not by the matrix cores). Hidden
 // layer outputs are staged through LDS so that every global store is a full
 // 16-byte chunk of one cell. In LDS the input block is split by 8-channel
 // chunk, xs[chunk][cell][8]: the 16 lanes of an operand fetch read 16
@@ -80,10 +86,15 @@ enum { EPI_HIDDEN = 0, EPI_OUT = 1, EPI_DGRAD_HIDDEN = 2, EPI_DGRAD_INPUT = 3 };
 constexpr int kCbX = 32, kCbY = 4, kCbZ = 2, kCbCells = kCbX * kCbY * kCbZ;
 constexpr int kChX = kCbX + 2, kChY = kCbY + 2, kChZ = kCbZ + 2, kChCells = kChX * kChY * kChZ;
 
+// Block row (y + 4 z, 0 .. 7) of M tile mt of wave w: row y = w of plane mt / 2.
+__device__ __forceinline__ int conv_row(int wave, int mt) { return (mt >> 1) * kCbY + wave; }
+
+// keep_z false: a forward-only hidden layer stages only its bfloat16 output
+// (the smaller footprint lets more workgroups share a CU).
 template <int CIN>
-constexpr size_t conv_t_lds_bytes() {
-    constexpr size_t halo = size_t(kChCells) * CIN * 2;
-    constexpr size_t epi = size_t(kCbCells) * 32 * (4 + 2);  // float32 z (or zin) + bfloat16 out
+constexpr size_t conv_t_lds_bytes(bool keep_z = true) {
+    const size_t halo = size_t(kChCells) * CIN * 2;
+    const size_t epi = size_t(kCbCells) * 32 * (keep_z ? 4 + 2 : 2);  // float32 z (or zin) + bfloat16 out
     return halo > epi ? halo : epi;
 }
 
@@ -132,10 +143,42 @@ __global__ __launch_bounds__(kBlock) void k_conv_t(Grid g, const u16* __restrict
     int hbase[MT];  // halo cell of (tap offset 0, 0, 0) for this lane's row of each M tile
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
-        const int r = 2 * wave + (mt >> 1);
+        const int r = conv_row(wave, mt);
         const int yy = r % kCbY, zz = r / kCbY;
         hbase[mt] = (zz * kChY + yy) * kChX + (mt & 1) * 16 + lm;
     }
+    if constexpr (CIN == 32) {
+        const u16* xq = xs + (gq * kChCells) * 8;  // this lane's 8-channel chunk
+#pragma unroll
+        for (int tyx = 0; tyx < 9; ++tyx) {
+            const int ty = tyx / 3, tx = tyx % 3;
+            bf16x8 bv[3][NT];
+#pragma unroll
+            for (int tz = 0; tz < 3; ++tz)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+                    bv[tz][nt] = *reinterpret_cast<const bf16x8*>(
+                        wpk + (((tz * 9 + tyx) * NT * 16 + nt * 16 + lm) * 32 + 8 * gq));
+#pragma unroll
+            for (int hz = 0; hz < 4; ++hz) {
+#pragma unroll
+                for (int xh = 0; xh < 2; ++xh) {
+                    // halo cell of source plane hz for output row (y = wave) and x half xh
+                    const int cell = (hz * kChY + wave + ty) * kChX + xh * 16 + lm + tx;
+                    const bf16x8 av = *reinterpret_cast<const bf16x8*>(xq + cell * 8);
+#pragma unroll
+                    for (int zz = 0; zz < 2; ++zz) {
+                        const int tz = hz - zz;
+                        if (tz < 0 || tz > 2) continue;
+#pragma unroll
+                        for (int nt = 0; nt < NT; ++nt)
+                            acc[zz * 2 + xh][nt] =
+                                __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[tz][nt], acc[zz * 2 + xh][nt], 0, 0, 0);
+                    }
+                }
+            }
+        }
+    } else {
 #pragma unroll 3
     for (int kt = 0; kt < NKT; ++kt) {
         int tap, c0;
@@ -161,8 +204,9 @@ __global__ __launch_bounds__(kBlock) void k_conv_t(Grid g, const u16* __restrict
                 acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[nt], acc[mt][nt], 0, 0, 0);
         }
     }
+    }
     // 3. epilogue: lane holds D[m = 4 gq + i][n = nt*16 + lm] of M tile mt, i.e. block
-    // cell q = r * 32 + (mt & 1) * 16 + 4 gq + i with r = 2 wave + (mt >> 1)
+    // cell q = r * 32 + (mt & 1) * 16 + 4 gq + i with r = conv_row(wave, mt)
     auto block_cell = [&](int q, int64_t& c) -> bool {
         const int r = q >> 5, xx = q & 31;
         const int yy = y0 + r % kCbY, zz = z0 + r / kCbY;
@@ -170,8 +214,10 @@ __global__ __launch_bounds__(kBlock) void k_conv_t(Grid g, const u16* __restrict
         return yy < ny && zz < nz;
     };
     if constexpr (EPI == EPI_HIDDEN || EPI == EPI_DGRAD_HIDDEN) {
-        float* zt = reinterpret_cast<float*>(xs);                 // [256][32] float32
-        u16* at = reinterpret_cast<u16*>(xs + kCbCells * 32 * 2);  // [256][32] bfloat16
+        // [256][32] float32 z (not kept by a forward-only EPI_HIDDEN call: zout null), then [256][32] bfloat16
+        const bool keep_z = EPI == EPI_DGRAD_HIDDEN || zout != nullptr;
+        float* zt = reinterpret_cast<float*>(xs);
+        u16* at = keep_z ? reinterpret_cast<u16*>(xs + kCbCells * 32 * 2) : xs;
         __syncthreads();  // every wave is done reading the input block
         if constexpr (EPI == EPI_DGRAD_HIDDEN) {
             for (int e = tid; e < kCbCells * 8; e += kBlock) {  // zin block, 16-byte chunks
@@ -185,7 +231,7 @@ __global__ __launch_bounds__(kBlock) void k_conv_t(Grid g, const u16* __restrict
         }
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
-            const int qb = (2 * wave + (mt >> 1)) * 32 + (mt & 1) * 16 + 4 * gq;
+            const int qb = conv_row(wave, mt) * 32 + (mt & 1) * 16 + 4 * gq;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int q = qb + i;
@@ -195,7 +241,7 @@ __global__ __launch_bounds__(kBlock) void k_conv_t(Grid g, const u16* __restrict
                     const float v = acc[mt][nt][i];
                     if constexpr (EPI == EPI_HIDDEN) {
                         const float z = v + bias[n];
-                        zt[q * 32 + n] = z;
+                        if (keep_z) zt[q * 32 + n] = z;
                         at[q * 32 + n] = bf16_bits(gelu_f(z));
                     } else {
                         at[q * 32 + n] = bf16_bits(v * gelu_grad_f(zt[q * 32 + n]));
@@ -222,7 +268,7 @@ __global__ __launch_bounds__(kBlock) void k_conv_t(Grid g, const u16* __restrict
         const int64_t vol = int64_t(nx) * ny * nz;
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
-            const int qb = (2 * wave + (mt >> 1)) * 32 + (mt & 1) * 16 + 4 * gq;
+            const int qb = conv_row(wave, mt) * 32 + (mt & 1) * 16 + 4 * gq;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 int64_t c;
@@ -511,8 +557,9 @@ hipError_t launch_closure_conv(const Grid& g, int which, const u16* in, const u1
                                const float* zin, float* zout, u16* aout, T* fout, hipStream_t s) {
     const int grid = (g.nx / kCbX) * ((g.ny + kCbY - 1) / kCbY) * ((g.nz + kCbZ - 1) / kCbZ) * g.batch;
 #define INS_CONV(CIN, NT, EPI, NOUT)                                                                              \
-    hipLaunchKernelGGL((k_conv_t<T, CIN, NT, EPI>), dim3(grid), dim3(kBlock), conv_t_lds_bytes<CIN>(), s, g, in, wpk, \
-                       bias, zin, zout, aout, fout, NOUT)
+    hipLaunchKernelGGL((k_conv_t<T, CIN, NT, EPI>), dim3(grid), dim3(kBlock),                                     \
+                       conv_t_lds_bytes<CIN>(EPI != EPI_HIDDEN || zout != nullptr), s, g, in, wpk, bias, zin, zout, aout, \
+                       fout, NOUT)
     switch (which) {
         case 0: INS_CONV(8, 2, EPI_HIDDEN, 32); break;
         case 1: INS_CONV(32, 2, EPI_HIDDEN, 32); break;
