@@ -65,12 +65,13 @@ struct FftPlan {
     int n;                   // transform length
     int nst;                 // number of stages
     int rad[kMaxStages];     // radix of stage s (applied in order)
-    int tw_off[kMaxStages];  // offset of stage s twiddles: p*(R-1) entries
-    const cd* tw;            // device twiddle table (float64, forward sign)
+    int tw_off[kMaxStages];  // offset in tw of stage s's twiddles: p*(R-1) entries
+    int rt_off;              // offset in tw of the roots W_n^j = exp(-2 pi i j / n), j < n
+    const cd* tw;            // device twiddle and root tables (float64, forward sign)
     int vm;                  // complex values a thread holds per stage (8 or 16)
     int pad;                 // LDS line-stride padding (0 or 1)
     int nth;                 // threads per workgroup: 256; with vm 8 also 1024 (x pass) or 512 (strided)
-    const cf* twf;           // the twiddle table rounded to float32 (all-float32 mode; null otherwise)
+    const cf* twf;           // the same tables rounded to float32 (all-float32 mode; null otherwise)
 };
 
 // Which FFT pass shape a launch uses.

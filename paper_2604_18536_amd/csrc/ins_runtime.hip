@@ -34,7 +34,8 @@ void hip_check(hipError_t e, const char* what) {
 
 constexpr int kMaxLen = 4096;
 constexpr int kBlockHost = 256; // must match kBlock
-constexpr size_t kMaxLds = 98304;  // LDS budget of one FFT workgroup (gfx950: 160 KB per CU)
+constexpr size_t kMaxLds = 98304;  // LDS budget of one FFT workgroup
+constexpr size_t kCuLds = 163840;  // LDS of one gfx950 compute unit
 
 bool factor(int n, std::vector<int>& rad) {
     rad.clear();
@@ -60,8 +61,10 @@ bool factor(int n, std::vector<int>& rad) {
     return static_cast<int>(rad.size()) <= ins::kMaxStages;
 }
 
-// Twiddles exp(-2 pi i q k / (p R)), k < p, 1 <= q < R, for every stage; the
-// angle is reduced exactly in integers and evaluated in long double.
+// Twiddles exp(-2 pi i q k / (p R)), k < p, 1 <= q < R, for every stage
+// (the x passes read these), then the roots W_n^j = exp(-2 pi i j / n), j < n
+// (every stage twiddle is the root j = q k n / (p R); the strided passes read
+// these). Angles are reduced exactly in integers and evaluated in long double.
 void build_twiddles(int n, const std::vector<int>& rad, std::vector<cd>& tw, ins::FftPlan& pl) {
     const long double two_pi = 6.283185307179586476925286766559005768L;
     pl.n = n;
@@ -81,14 +84,24 @@ void build_twiddles(int n, const std::vector<int>& rad, std::vector<cd>& tw, ins
         }
         p *= R;
     }
+    pl.rt_off = static_cast<int>(tw.size());
+    for (int j = 0; j < n; ++j) {
+        const long double ang = -two_pi * static_cast<long double>(j) / static_cast<long double>(n);
+        tw.push_back(cd{static_cast<double>(cosl(ang)), static_cast<double>(sinl(ang))});
+    }
+}
+
+// LDS of one FFT workgroup: nl lines of stride nl + pad, plus `extra` bytes
+// (the roots and eigenvalues a pass keeps next to them).
+size_t fft_lds(const ins::FftPlan& pl, int nl, int pad, size_t extra) {
+    return static_cast<size_t>(nl + pad) * pl.n * sizeof(cd) + extra;
 }
 
 // Largest power-of-two line batch (<= maxl) whose every stage fits the
-// per-thread register budget vm with nth threads and whose lines (stride
-// nl + pad) fit the LDS budget.
-int lines_for(const ins::FftPlan& pl, int maxl, int vm, int pad, int nth) {
+// per-thread register budget vm with nth threads and whose LDS fits the budget.
+int lines_for(const ins::FftPlan& pl, int maxl, int vm, int pad, int nth, size_t extra) {
     for (int nl = maxl; nl >= 1; nl >>= 1) {
-        if (static_cast<size_t>(nl + pad) * pl.n * sizeof(cd) > kMaxLds) continue;
+        if (fft_lds(pl, nl, pad, extra) > kMaxLds) continue;
         bool ok = true;
         for (int s = 0; s < pl.nst; ++s) {
             const int R = pl.rad[s];
@@ -109,24 +122,29 @@ int lines_for(const ins::FftPlan& pl, int maxl, int vm, int pad, int nth) {
 // occupancy high and are preferred; when that gives batches of fewer than
 // `want` lines, a wider workgroup with 8 values per thread (`wide` threads),
 // and only then 16 values per thread with 256 threads. The LDS stride is
-// padded when that does not narrow the batch. Measured choices: the x pass
-// may use 1024 threads (10-15% faster at n_x/2 = 420); the strided passes at
-// most 512 (1024 slowed them at 840; 16-line batches of 512 threads were 7%
+// padded when that does not narrow the batch and, with `occ`, does not cost a
+// workgroup per CU either (the strided passes; the x passes' 1024-thread
+// workgroups are held to one per CU by their registers anyway). `extra`: LDS
+// bytes the pass keeps beside the lines. Measured choices: the x
+// pass may use 1024 threads (10-15% faster at n_x/2 = 420); the strided passes
+// at most 512 (1024 slowed them at 840; 16-line batches of 512 threads were 7%
 // slower than 8 lines of 256 at 256^3).
-int choose_lines(ins::FftPlan& pl, int maxl, int want, int wide) {
+int choose_lines(ins::FftPlan& pl, int maxl, int want, int wide, size_t extra, bool occ) {
     struct Shape {
         int vm, nth;
     };
     const Shape shapes[3] = {{8, kBlockHost}, {8, wide}, {16, kBlockHost}};
     int best = -1;
     for (const Shape& sh : shapes) {
-        const int lp = lines_for(pl, maxl, sh.vm, 1, sh.nth);
-        const int l0 = lines_for(pl, maxl, sh.vm, 0, sh.nth);
+        const int lp = lines_for(pl, maxl, sh.vm, 1, sh.nth, extra);
+        const int l0 = lines_for(pl, maxl, sh.vm, 0, sh.nth, extra);
         const int l = std::max(lp, l0);
         if (l <= best) continue;
         pl.vm = sh.vm;
         pl.nth = sh.nth;
-        pl.pad = lp >= l0 ? 1 : 0;
+        pl.pad = lp >= l0 && (!occ || kCuLds / fft_lds(pl, 1 << l, 1, extra) >= kCuLds / fft_lds(pl, 1 << l, 0, extra))
+                     ? 1
+                     : 0;
         best = l;
         if ((1 << l) >= want) break;
     }
@@ -1032,12 +1050,17 @@ bool setup_fft(ins_ctx c, const std::vector<int>& rx, const std::vector<int>& ry
     build_twiddles(g.nx / 2, rx, tw, c->px);
     if (!channel) build_twiddles(g.ny, ry, tw, c->py);
     if (d == 3) build_twiddles(g.nz, rz, tw, c->pz);
-    c->lnl_x = choose_lines(c->px, 16, 8, 1024);
-    c->lnl_y = channel ? 0 : choose_lines(c->py, 16, 8, 512);
+    // LDS beside the lines: the strided passes keep the roots (n/2 for even n, else n)
+    // and, in the pass that divides by the eigenvalues, those of its axis
+    auto strided_extra = [](int n, bool solve) {
+        return static_cast<size_t>((n & 1) ? n : n / 2) * sizeof(cd) + (solve ? n * sizeof(double) : 0);
+    };
+    c->lnl_x = choose_lines(c->px, 16, 8, 1024, 0, false);
+    c->lnl_y = channel ? 0 : choose_lines(c->py, 16, 8, 512, strided_extra(g.ny, d == 2), true);
     // the channel's z passes are plain forward / inverse transforms: 16-line batches
     // (256-byte runs) measured 13% faster there; the periodic fused z solve and the y
     // passes are faster with 8 lines of 256 threads
-    c->lnl_z = d == 3 ? choose_lines(c->pz, 16, channel ? 16 : 8, 512) : 0;
+    c->lnl_z = d == 3 ? choose_lines(c->pz, 16, channel ? 16 : 8, 512, strided_extra(g.nz, !channel), true) : 0;
     if (!channel) {
         ins::FftPlan& last = d == 3 ? c->pz : c->py;
         ins::FftPlan& rev = d == 3 ? c->pz_rev : c->py_rev;

@@ -148,6 +148,52 @@ __device__ __forceinline__ int fdivmod(int n, int d, float rd, int& r) {
     return q;
 }
 
+// The twiddles of every stage are powers of W_N = exp(-2 pi i / N): stage
+// (p, R) multiplies element q of butterfly k by W_N^(q k N / (p R)). Each
+// strided-pass workgroup copies the roots W_N^j into LDS once (j < N/2 for
+// even N, using W_N^(j + N/2) = -W_N^j; all N for odd N), so no stage issues
+// a global load for them. The host tabulates the roots in the precision of C from an exact
+// integer angle reduction.
+template <class C>
+struct Roots {
+    const C* t;  // LDS (or the global table, with half = N)
+    int half;    // number of stored roots
+    __device__ __forceinline__ C operator()(int j) const {
+        const C w = t[j < half ? j : j - half];
+        return j < half ? w : C{-w.x, -w.y};
+    }
+    // the twiddles W_N^(q k sN), q = 1 .. R-1, of butterfly k
+    struct Cursor {
+        const C* t;
+        int half, j, ks;
+        __device__ __forceinline__ C next() {
+            j += ks;
+            const C w = t[j < half ? j : j - half];
+            return j < half ? w : C{-w.x, -w.y};
+        }
+    };
+    __device__ __forceinline__ Cursor at(int, int k, int, int sN) const { return Cursor{t, half, 0, k * sN}; }
+};
+
+// Per-stage twiddle tables in global memory (the x passes, whose element-fast
+// stages would read LDS roots with bank conflicts): stage s keeps
+// exp(-2 pi i q k / (p R)) at tw[off[s] + k (R - 1) + q - 1].
+template <class C>
+struct TabTw {
+    const C* tw;
+    const int* off;
+    struct Cursor {
+        const C* p;
+        __device__ __forceinline__ C next() { return *++p; }
+    };
+    __device__ __forceinline__ Cursor at(int s, int k, int R, int) const {
+        return Cursor{tw + off[s] + k * (R - 1) - 1};
+    }
+};
+
+// Number of roots a plan of length n keeps in LDS.
+__host__ __device__ __forceinline__ int roots_count(int n) { return (n & 1) ? n : n / 2; }
+
 // How the butterflies t = 0 .. S*nl-1 of a stage map to (line l, index i):
 // line-fast keeps neighbouring threads on neighbouring lines (contiguous in LDS
 // and, for a strided axis, in memory); element-fast keeps them on neighbouring
@@ -178,11 +224,13 @@ __device__ __forceinline__ void slot_of(int t, int lnl, int S, float rS, int& l,
 //          applied at once; its outputs i R + q go to LDS when the inverse has
 //          more stages (`more`), else to sink.
 // The LDS reads of an IN 1 stage that writes LDS are followed by a barrier.
-template <int R, int SIGN, int VM, int NTH, int IN, int OUT, int MAP, class C, class Load, class Sink, class Div>
-__device__ __forceinline__ void fft_stage(C* __restrict__ lds, int lnl, int ls, int N, int p, const C* __restrict__ tw,
+template <int R, int SIGN, int VM, int NTH, int IN, int OUT, int MAP, class C, class TW, class Load, class Sink,
+          class Div>
+__device__ __forceinline__ void fft_stage(C* __restrict__ lds, int lnl, int ls, int N, int p, int s, const TW& tw,
                                           const Load& load, const Sink& sink, const Div& divf, bool more) {
     constexpr int BMAX = VM / R > 0 ? VM / R : 1;
     const int S = N / R;
+    const int sN = S / p;  // exp(2 pi i q k / (p R)) = W_N^(q k sN)
     const int nb = S << lnl;
     const float rS = __builtin_amdgcn_rcpf(static_cast<float>(S));
     const float rp = __builtin_amdgcn_rcpf(static_cast<float>(p));
@@ -211,9 +259,12 @@ __device__ __forceinline__ void fft_stage(C* __restrict__ lds, int lnl, int ls, 
             fdivmod(i, p, rp, k);
             C* x = w + b * R;
             if (k != 0) {
-                const C* twk = tw + k * (R - 1) - 1;
+                auto cur = tw.at(s, k, R, sN);
 #pragma unroll
-                for (int q = 1; q < R; ++q) x[q] = SIGN < 0 ? cmul(x[q], twk[q]) : cmulc(x[q], twk[q]);
+                for (int q = 1; q < R; ++q) {
+                    const C w = cur.next();
+                    x[q] = SIGN < 0 ? cmul(x[q], w) : cmulc(x[q], w);
+                }
             }
             dft<R, SIGN>(x);
             if constexpr (OUT == 0) {
@@ -242,16 +293,16 @@ __device__ __forceinline__ void fft_stage(C* __restrict__ lds, int lnl, int ls, 
     }
 }
 
-template <int SIGN, int VM, int NTH, int IN, int OUT, int MAP, class C, class Load, class Sink, class Div>
-__device__ __forceinline__ void fft_stage_r(int R, C* lds, int lnl, int ls, int N, int p, const C* tw,
+template <int SIGN, int VM, int NTH, int IN, int OUT, int MAP, class C, class TW, class Load, class Sink, class Div>
+__device__ __forceinline__ void fft_stage_r(int R, C* lds, int lnl, int ls, int N, int p, int s, const TW& tw,
                                             const Load& load, const Sink& sink, const Div& divf, bool more) {
     switch (R) {
-        case 8: fft_stage<8, SIGN, VM, NTH, IN, OUT, MAP>(lds, lnl, ls, N, p, tw, load, sink, divf, more); break;
-        case 7: fft_stage<7, SIGN, VM, NTH, IN, OUT, MAP>(lds, lnl, ls, N, p, tw, load, sink, divf, more); break;
-        case 5: fft_stage<5, SIGN, VM, NTH, IN, OUT, MAP>(lds, lnl, ls, N, p, tw, load, sink, divf, more); break;
-        case 4: fft_stage<4, SIGN, VM, NTH, IN, OUT, MAP>(lds, lnl, ls, N, p, tw, load, sink, divf, more); break;
-        case 3: fft_stage<3, SIGN, VM, NTH, IN, OUT, MAP>(lds, lnl, ls, N, p, tw, load, sink, divf, more); break;
-        default: fft_stage<2, SIGN, VM, NTH, IN, OUT, MAP>(lds, lnl, ls, N, p, tw, load, sink, divf, more); break;
+        case 8: fft_stage<8, SIGN, VM, NTH, IN, OUT, MAP>(lds, lnl, ls, N, p, s, tw, load, sink, divf, more); break;
+        case 7: fft_stage<7, SIGN, VM, NTH, IN, OUT, MAP>(lds, lnl, ls, N, p, s, tw, load, sink, divf, more); break;
+        case 5: fft_stage<5, SIGN, VM, NTH, IN, OUT, MAP>(lds, lnl, ls, N, p, s, tw, load, sink, divf, more); break;
+        case 4: fft_stage<4, SIGN, VM, NTH, IN, OUT, MAP>(lds, lnl, ls, N, p, s, tw, load, sink, divf, more); break;
+        case 3: fft_stage<3, SIGN, VM, NTH, IN, OUT, MAP>(lds, lnl, ls, N, p, s, tw, load, sink, divf, more); break;
+        default: fft_stage<2, SIGN, VM, NTH, IN, OUT, MAP>(lds, lnl, ls, N, p, s, tw, load, sink, divf, more); break;
     }
 }
 
@@ -278,44 +329,54 @@ __device__ __forceinline__ float solve_inv_ncell(const SolveTab& st, cf) { retur
 // pivot of a solve whose inverse plan is Q (then call fft_inverse_rest).
 // The first and last stages are peeled off the loop so that the address
 // arithmetic of the memory-facing stages is not kept live across the others.
-template <int SIGN, int VM, int NTH, int IN0, int OUTL, int MAP0, int MAPL, class C, class Load, class Sink, class Div>
-__device__ __forceinline__ void fft_run(C* lds, int lnl, int ls, const FftPlan& P, const Load& load, const Sink& sink,
-                                        const Div& divf, const FftPlan* Q) {
-    const C* tw = plan_tw(P, C{});
+template <int SIGN, int VM, int NTH, int IN0, int OUTL, int MAP0, int MAPL, class C, class TW, class Load, class Sink,
+          class Div>
+__device__ __forceinline__ void fft_run(C* lds, int lnl, int ls, const FftPlan& P, const TW& tw, const Load& load,
+                                        const Sink& sink, const Div& divf, const FftPlan* Q) {
     const int ns = P.nst;
     const bool more = OUTL == 2 && Q->nst > 1;
     if (ns == 1) {
-        fft_stage_r<SIGN, VM, NTH, IN0, OUTL, MAP0>(P.rad[0], lds, lnl, ls, P.n, 1, tw + P.tw_off[0], load, sink, divf,
-                                                more);
+        fft_stage_r<SIGN, VM, NTH, IN0, OUTL, MAP0>(P.rad[0], lds, lnl, ls, P.n, 1, 0, tw, load, sink, divf, more);
         return;
     }
-    fft_stage_r<SIGN, VM, NTH, IN0, 0, MAP0>(P.rad[0], lds, lnl, ls, P.n, 1, tw + P.tw_off[0], load, sink, divf, false);
+    fft_stage_r<SIGN, VM, NTH, IN0, 0, MAP0>(P.rad[0], lds, lnl, ls, P.n, 1, 0, tw, load, sink, divf, false);
     int p = P.rad[0];
     for (int st = 1; st < ns - 1; ++st) {
-        fft_stage_r<SIGN, VM, NTH, 1, 0, kLineFast>(P.rad[st], lds, lnl, ls, P.n, p, tw + P.tw_off[st], load, sink, divf,
-                                               false);
+        fft_stage_r<SIGN, VM, NTH, 1, 0, kLineFast>(P.rad[st], lds, lnl, ls, P.n, p, st, tw, load, sink, divf, false);
         p *= P.rad[st];
     }
-    fft_stage_r<SIGN, VM, NTH, 1, OUTL, MAPL>(P.rad[ns - 1], lds, lnl, ls, P.n, p, tw + P.tw_off[ns - 1], load, sink,
-                                         divf, more);
+    fft_stage_r<SIGN, VM, NTH, 1, OUTL, MAPL>(P.rad[ns - 1], lds, lnl, ls, P.n, p, ns - 1, tw, load, sink, divf, more);
 }
 
 // The stages of inverse plan Q after a pivot consumed its first one (nothing
 // when Q has a single stage): LDS to LDS, the last one to sink (mapping MAPL).
-template <int SIGN, int VM, int NTH, int MAPL, class C, class Sink>
-__device__ __forceinline__ void fft_inverse_rest(C* lds, int lnl, int ls, const FftPlan& Q, const Sink& sink) {
-    const C* tw = plan_tw(Q, C{});
+template <int SIGN, int VM, int NTH, int MAPL, class C, class TW, class Sink>
+__device__ __forceinline__ void fft_inverse_rest(C* lds, int lnl, int ls, const FftPlan& Q, const TW& tw,
+                                                 const Sink& sink) {
     const int ns = Q.nst;
     if (ns == 1) return;
     const NoOp nop;
     int p = Q.rad[0];
     for (int st = 1; st < ns - 1; ++st) {
-        fft_stage_r<SIGN, VM, NTH, 1, 0, kLineFast>(Q.rad[st], lds, lnl, ls, Q.n, p, tw + Q.tw_off[st], nop, sink, nop,
-                                               false);
+        fft_stage_r<SIGN, VM, NTH, 1, 0, kLineFast>(Q.rad[st], lds, lnl, ls, Q.n, p, st, tw, nop, sink, nop, false);
         p *= Q.rad[st];
     }
-    fft_stage_r<SIGN, VM, NTH, 1, 1, MAPL>(Q.rad[ns - 1], lds, lnl, ls, Q.n, p, tw + Q.tw_off[ns - 1], nop, sink, nop,
-                                      false);
+    fft_stage_r<SIGN, VM, NTH, 1, 1, MAPL>(Q.rad[ns - 1], lds, lnl, ls, Q.n, p, ns - 1, tw, nop, sink, nop, false);
+}
+
+// Plan P's per-stage twiddle tables in global memory.
+template <class C>
+__device__ __forceinline__ TabTw<C> plan_tab(const FftPlan& P) {
+    return TabTw<C>{plan_tw(P, C{}), P.tw_off};
+}
+
+// Copy plan P's roots into LDS at `dst` (synchronised by the caller's next barrier).
+template <int NTH, class C>
+__device__ __forceinline__ Roots<C> load_roots(C* dst, const FftPlan& P) {
+    const C* src = plan_tw(P, C{}) + P.rt_off;
+    const int ne = roots_count(P.n);
+    for (int j = threadIdx.x; j < ne; j += NTH) dst[j] = src[j];
+    return Roots<C>{dst, ne};
 }
 
 // Copy the nl lines into LDS element-major (lds[e ls + l]) with element-fast
@@ -463,8 +524,9 @@ __global__ __launch_bounds__(NTH) void k_fft_x_fwd(Grid g, const T* __restrict__
         }
     };
     const NoOp nop;
+    const TabTw<C> rt = plan_tab<C>(P);
     stage_rows<NTH>(lds, lnl, ls, M, load);
-    fft_run<-1, VM, NTH, 1, 0, kLineFast, kLineFast>(lds, lnl, ls, P, load, nop, nop, nullptr);
+    fft_run<-1, VM, NTH, 1, 0, kLineFast, kLineFast>(lds, lnl, ls, P, rt, load, nop, nop, nullptr);
     const int M1 = M + 1;
     const float rM1 = __builtin_amdgcn_rcpf(static_cast<float>(M1));
     for (int t = threadIdx.x; t < nl * M1; t += NTH) {
@@ -511,98 +573,150 @@ __global__ __launch_bounds__(NTH) void k_fft_x_inv(Grid g, const C* __restrict__
         if (row < nrows) reinterpret_cast<C*>(p + int64_t(row) * g.nx)[m] = z;
     };
     const NoOp nop;
+    const TabTw<C> rt = plan_tab<C>(P);
     stage_rows<NTH>(lds, lnl, ls, M, load);
-    fft_run<1, VM, NTH, 1, 1, kLineFast, kElemFast>(lds, lnl, ls, P, load, sink, nop, nullptr);
+    fft_run<1, VM, NTH, 1, 1, kLineFast, kElemFast>(lds, lnl, ls, P, rt, load, sink, nop, nullptr);
 }
 
 // Strided complex pass along y (axis 1) or z (axis 2) of the half spectrum
 // [batch][n_z][n_y][sx] (columns 0 .. n_x/2 in use). MODE 0 forward, 1 inverse, 2 forward + divide +
-// inverse. Columns kx < n_x/2 go in chunks of nl adjacent kx per workgroup (each
+// inverse. Columns kx < n_x/2 go in chunks of nl adjacent kx per batch (each
 // access a contiguous run of nl values); the Nyquist column kx = n_x/2 is taken
-// by extra workgroups, nl lines of it (adjacent values of the other non-x
-// index) each, so no workgroup transforms a chunk that is mostly padding. Either
-// way line l of a workgroup starts at lb0 + l*lstep, has wavenumbers
-// (kx0 + l*kxstep, fk0 + l*fkstep) and exists for l < nvalid.
+// by extra batches, nl lines of it (adjacent values of the other non-x index)
+// each, so no batch transforms a chunk that is mostly padding. Either way line
+// l of a batch starts at lb0 + l*lstep, has wavenumbers (kx0 + l*kxstep,
+// fk0 + l*fkstep) and exists for l < nvalid.
+struct LineBatch {
+    int64_t lb0, lstep;
+    int kx0, kxstep, fk0, fkstep, nvalid;
+};
+
+__device__ __forceinline__ LineBatch line_batch(const Grid& g, int axis, int lnl, int w) {
+    const int M = g.nx / 2;
+    const int nchunk = (M + (1 << lnl) - 1) >> lnl;
+    const int nfix = axis == 1 ? g.nz : g.ny;  // the other non-x index
+    const int nouter = g.batch * nfix;
+    const int64_t plane = int64_t(g.nz) * g.ny * g.sx;                          // one batch entry
+    const int64_t fstride = axis == 1 ? int64_t(g.sx) * g.ny : int64_t(g.sx);  // along the other index
+    LineBatch B;
+    if (w < nchunk * nouter) {
+        const int outer = w / nchunk;
+        const int b = outer / nfix, f = outer - b * nfix;
+        B.kx0 = (w - outer * nchunk) << lnl;
+        B.kxstep = 1;
+        B.fk0 = f;
+        B.fkstep = 0;
+        B.lb0 = b * plane + f * fstride + B.kx0;
+        B.lstep = 1;
+        B.nvalid = M - B.kx0;
+    } else {
+        const int nfc = (nfix + (1 << lnl) - 1) >> lnl;
+        const int j = w - nchunk * nouter;
+        const int b = j / nfc;
+        const int f0 = (j - b * nfc) << lnl;
+        B.kx0 = M;
+        B.kxstep = 0;
+        B.fk0 = f0;
+        B.fkstep = 1;
+        B.lb0 = b * plane + f0 * fstride + M;
+        B.lstep = fstride;
+        B.nvalid = nfix - f0;
+    }
+    return B;
+}
+
+// Number of batches of a strided pass.
+__host__ __device__ __forceinline__ int strided_batches(const Grid& g, int axis, int lnl) {
+    const int nchunk = (g.nx / 2 + (1 << lnl) - 1) >> lnl;
+    const int nfix = axis == 1 ? g.nz : g.ny;
+    return nchunk * g.batch * nfix + g.batch * ((nfix + (1 << lnl) - 1) >> lnl);
+}
+
+// 1 / a to working precision: the hardware estimate refined by Newton's
+// iteration r <- r + r (1 - a r) (each step squares the relative error).
+__device__ __forceinline__ double recip(double a) {
+    double r = __builtin_amdgcn_rcp(a);
+    r = fma(r, fma(-a, r, 1.0), r);
+    r = fma(r, fma(-a, r, 1.0), r);
+    return fma(r, fma(-a, r, 1.0), r);
+}
+__device__ __forceinline__ float recip(float a) {
+    const float r = __builtin_amdgcn_rcpf(a);
+    return fmaf(r, fmaf(-a, r, 1.0f), r);
+}
+
+// The eigenvalue sum of the directions other than the line's, for this
+// thread's line of batch B (line-fast mapping: a thread's butterflies all lie
+// on line threadIdx.x mod nl), and whether those wavenumbers are all zero.
+template <class F>
+struct LineLam {
+    F other;
+    bool zero;
+};
+template <class C>
+__device__ __forceinline__ LineLam<real_of<C>> line_lam(const SolveTab& st, const LineBatch& B, int axis, int lnl) {
+    const auto* const* lt = solve_lam(st, C{});
+    const int l = min(static_cast<int>(threadIdx.x) & ((1 << lnl) - 1), B.nvalid - 1);
+    const int kx = B.kx0 + l * B.kxstep, fk = B.fk0 + l * B.fkstep;
+    if (axis == 2) return {lt[0][kx] + lt[1][fk], kx == 0 && fk == 0};
+    return {lt[0][kx], kx == 0};
+}
+
+// One batch of a strided pass per workgroup.
+template <int MODE, int VM, int NTH, class C>
+__device__ __forceinline__ void strided_batch(const Grid& g, C* __restrict__ spec, const FftPlan& P, const FftPlan& Q,
+                                              int axis, int lnl, const SolveTab& st, int w, C* lds,
+                                              const Roots<C>& rt, const real_of<C>* lam_line) {
+    using F = real_of<C>;
+    const int ls = (1 << lnl) + P.pad;
+    const int64_t stride = axis == 1 ? int64_t(g.sx) : int64_t(g.sx) * g.ny;  // along the line
+    const LineBatch B = line_batch(g, axis, lnl, w);
+    auto load = [&](int l, int e) INS_INLINE -> C {
+        return l < B.nvalid ? spec[B.lb0 + l * B.lstep + e * stride] : C{F(0), F(0)};
+    };
+    auto store = [&](int l, int e, C z) INS_INLINE {
+        if (l < B.nvalid) spec[B.lb0 + l * B.lstep + e * stride] = z;
+    };
+    const NoOp nop;
+    if constexpr (MODE == 1) {
+        fft_run<1, VM, NTH, 0, 1, kLineFast, kLineFast>(lds, lnl, ls, P, rt, load, store, nop, nullptr);
+    } else if constexpr (MODE == 0) {
+        fft_run<-1, VM, NTH, 0, 1, kLineFast, kLineFast>(lds, lnl, ls, P, rt, load, store, nop, nullptr);
+    } else {
+        // divide by L(k) * #cells; L(0) := 1.
+        const LineLam<F> lam = line_lam<C>(st, B, axis, lnl);
+        const F inv_ncell = solve_inv_ncell(st, C{});
+        auto divide = [&](int l, int e, C z) INS_INLINE -> C {
+            if (l >= B.nvalid) return z;
+            const F sc = (lam.zero && e == 0) ? inv_ncell : -inv_ncell * recip(lam.other + lam_line[e]);
+            return cscale(z, sc);
+        };
+        fft_run<-1, VM, NTH, 0, 2, kLineFast, kLineFast>(lds, lnl, ls, P, rt, load, store, divide, &Q);
+        fft_inverse_rest<1, VM, NTH, kLineFast>(lds, lnl, ls, Q, rt, store);
+    }
+}
+
 // First and last stages touch memory directly; in MODE 2 the forward run leaves
 // its outputs in registers, they are divided there, and the inverse runs the
 // stages in reverse radix order (plan Q, whose first radix is P's last) from
-// those same registers.
+// those same registers. LDS: the line batch, then the roots, then (MODE 2) the
+// eigenvalues of the line axis.
 template <int MODE, int VM, int NTH, class C = cd>
 __global__ __launch_bounds__(NTH) void k_fft_strided(Grid g, C* __restrict__ spec, FftPlan P, FftPlan Q, int axis,
                                                           int lnl, SolveTab st) {
     using F = real_of<C>;
     extern __shared__ __align__(16) unsigned char fft_smem[];
     C* lds = reinterpret_cast<C*>(fft_smem);
-    const int nl = 1 << lnl;
-    const int M = g.nx / 2;
-    const int nxh = M + 1;
-    const int nchunk = (M + nl - 1) >> lnl;
-    const int nfix = axis == 1 ? g.nz : g.ny;  // the other non-x index
-    const int nouter = g.batch * nfix;
-    const int wg = xcd_logical(blockIdx.x, gridDim.x);
-    const int64_t plane = int64_t(g.nz) * g.ny * g.sx;                          // one batch entry
-    const int64_t stride = axis == 1 ? int64_t(g.sx) : int64_t(g.sx) * g.ny;   // along the line
-    const int64_t fstride = axis == 1 ? int64_t(g.sx) * g.ny : int64_t(g.sx);  // along the other index
-    int64_t lb0, lstep;
-    int kx0, kxstep, fk0, fkstep, nvalid;
-    if (wg < nchunk * nouter) {
-        const int outer = wg / nchunk;
-        const int b = outer / nfix, f = outer - b * nfix;
-        kx0 = (wg - outer * nchunk) << lnl;
-        kxstep = 1;
-        fk0 = f;
-        fkstep = 0;
-        lb0 = b * plane + f * fstride + kx0;
-        lstep = 1;
-        nvalid = M - kx0;
-    } else {
-        const int nfc = (nfix + nl - 1) >> lnl;
-        const int j = wg - nchunk * nouter;
-        const int b = j / nfc;
-        const int f0 = (j - b * nfc) << lnl;
-        kx0 = M;
-        kxstep = 0;
-        fk0 = f0;
-        fkstep = 1;
-        lb0 = b * plane + f0 * fstride + M;
-        lstep = fstride;
-        nvalid = nfix - f0;
+    const int ls = (1 << lnl) + P.pad;
+    const Roots<C> rt = load_roots<NTH>(lds + ls * P.n, P);
+    F* lam_line = nullptr;
+    if constexpr (MODE == 2) {
+        lam_line = reinterpret_cast<F*>(lds + ls * P.n + roots_count(P.n));
+        const F* src = solve_lam(st, C{})[axis];
+        for (int j = threadIdx.x; j < P.n; j += NTH) lam_line[j] = src[j];
     }
-    const int ls = nl + P.pad;
-    auto load = [&](int l, int e) INS_INLINE -> C {
-        return l < nvalid ? spec[lb0 + l * lstep + e * stride] : C{F(0), F(0)};
-    };
-    auto store = [&](int l, int e, C z) INS_INLINE {
-        if (l < nvalid) spec[lb0 + l * lstep + e * stride] = z;
-    };
-    const NoOp nop;
-    if constexpr (MODE == 1) {
-        fft_run<1, VM, NTH, 0, 1, kLineFast, kLineFast>(lds, lnl, ls, P, load, store, nop, nullptr);
-    } else if constexpr (MODE == 0) {
-        fft_run<-1, VM, NTH, 0, 1, kLineFast, kLineFast>(lds, lnl, ls, P, load, store, nop, nullptr);
-    } else {
-        // divide by L(k) * #cells; L(0) := 1.
-        const F* const* lt = solve_lam(st, C{});
-        const F inv_ncell = solve_inv_ncell(st, C{});
-        auto divide = [&](int l, int e, C z) INS_INLINE -> C {
-            if (l >= nvalid) return z;
-            const int kx = kx0 + l * kxstep;
-            const int fk = fk0 + l * fkstep;
-            F lam;
-            bool kzero;
-            if (axis == 2) {
-                lam = lt[0][kx] + lt[1][fk] + lt[2][e];
-                kzero = (kx == 0 && fk == 0 && e == 0);
-            } else {
-                lam = lt[0][kx] + lt[1][e];
-                kzero = (kx == 0 && e == 0);
-            }
-            const F sc = kzero ? inv_ncell : -inv_ncell / lam;
-            return cscale(z, sc);
-        };
-        fft_run<-1, VM, NTH, 0, 2, kLineFast, kLineFast>(lds, lnl, ls, P, load, store, divide, &Q);
-        fft_inverse_rest<1, VM, NTH, kLineFast>(lds, lnl, ls, Q, store);
-    }
+    __syncthreads();  // roots and eigenvalues in LDS before any stage
+    strided_batch<MODE, VM, NTH>(g, spec, P, Q, axis, lnl, st, xcd_logical(blockIdx.x, gridDim.x), lds, rt, lam_line);
 }
 
 // ----------------------------------------------------------------------------
@@ -658,13 +772,12 @@ template <class C>
 hipError_t fft_strided(const Grid& g, C* spec, const FftPlan& pl, const FftPlan& rev, int axis, int mode, int lnl,
                        const SolveTab& st, hipStream_t s) {
     const int nl = 1 << lnl;
-    const int nchunk = (g.nx / 2 + nl - 1) / nl;
-    const int nouter = axis == 1 ? g.batch * g.nz : g.batch * g.ny;
-    const int nfix = axis == 1 ? g.nz : g.ny;
-    const int nblk = nchunk * nouter + g.batch * ((nfix + nl - 1) / nl);  // + the Nyquist-column workgroups
-    const size_t shm = size_t(nl + pl.pad) * pl.n * sizeof(C);
-#define INS_ST(MODE, VM, NTH) \
-    hipLaunchKernelGGL((k_fft_strided<MODE, VM, NTH, C>), dim3(nblk), dim3(NTH), shm, s, g, spec, pl, rev, axis, lnl, st)
+    const int nwork = strided_batches(g, axis, lnl);
+    const size_t shm = (size_t(nl + pl.pad) * pl.n + roots_count(pl.n)) * sizeof(C) +
+                       (mode == 2 ? size_t(pl.n) * sizeof(real_of<C>) : 0);
+#define INS_ST(MODE, VM, NTH)                                                                                    \
+    hipLaunchKernelGGL((k_fft_strided<MODE, VM, NTH, C>), dim3(nwork), dim3(NTH), shm, s, g, spec, pl, rev, axis, lnl, \
+                       st)
 #define INS_ST_VM(MODE)                                  \
     do {                                                 \
         if (pl.nth == 512) INS_ST(MODE, 8, 512);         \
