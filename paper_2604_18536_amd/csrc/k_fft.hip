@@ -625,6 +625,43 @@ __global__ __launch_bounds__(NTH) void k_fft_x_fwd(Grid g, const T* __restrict__
     }
 }
 
+// Row staging of the inverse x pass, batched like stage_div_rows: the three
+// loads of kXBatch values (X[k], X[M-k], W^k) go out back to back, then the
+// tangled values Z[k] are formed and written to lds[k ls + l] (rows past
+// nrows: 0); synchronises. Same arithmetic as the per-value load.
+template <int NTH, class C>
+__device__ __forceinline__ void stage_tangled_rows(const Grid& g, const C* __restrict__ spec, const C* __restrict__ post,
+                                                   C* __restrict__ lds, int lnl, int ls, int M, int row0, int nrows) {
+    const int total = (1 << lnl) * M;
+    const float rM = __builtin_amdgcn_rcpf(static_cast<float>(M));
+    for (int t0 = 0; t0 < total; t0 += kXBatch * NTH) {
+        C xk[kXBatch], xm[kXBatch], wk[kXBatch];
+#pragma unroll
+        for (int j = 0; j < kXBatch; ++j) {
+            const int t = min(t0 + j * NTH + static_cast<int>(threadIdx.x), total - 1);
+            int k;
+            const int l = fdivmod(t, M, rM, k);
+            const C* sr = spec + int64_t(min(row0 + l, nrows - 1)) * g.sx;
+            xk[j] = sr[k];
+            xm[j] = sr[M - k];
+            wk[j] = post[k];
+        }
+#pragma unroll
+        for (int j = 0; j < kXBatch; ++j) {
+            const int t = t0 + j * NTH + static_cast<int>(threadIdx.x);
+            if (t < total) {
+                int k;
+                const int l = fdivmod(t, M, rM, k);
+                const C xc = cconj(xm[j]);
+                const C e = cadd(xk[j], xc);
+                const C o = cmulc(csub(xk[j], xc), wk[j]);
+                lds[k * ls + l] = row0 + l < nrows ? C{e.x - o.y, e.y + o.x} : C{real_of<C>(0), real_of<C>(0)};
+            }
+        }
+    }
+    __syncthreads();
+}
+
 // x pass, inverse: half spectrum -> real rows, scaled by n_x (unnormalised).
 // Z[k] = (X[k] + conj X[M-k]) + i (X[k] - conj X[M-k]) conj(W^k), z = IFFT_M(Z),
 // x[2m] = Re z[m], x[2m+1] = Im z[m]. The tangled rows are staged in LDS; the
@@ -656,7 +693,10 @@ __global__ __launch_bounds__(NTH) void k_fft_x_inv(Grid g, const C* __restrict__
     };
     const NoOp nop;
     const TabTw<C> rt = plan_tab<C>(P);
-    stage_rows<NTH>(lds, lnl, ls, M, load);
+    if constexpr (NTH <= 256)
+        stage_tangled_rows<NTH>(g, spec, post, lds, lnl, ls, M, row0, nrows);
+    else
+        stage_rows<NTH>(lds, lnl, ls, M, load);
     fft_run<1, VM, NTH, 1, 1, kLineFast, kElemFast>(lds, lnl, ls, P, rt, load, sink, nop, nullptr);
 }
 
