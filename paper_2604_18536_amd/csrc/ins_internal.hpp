@@ -70,7 +70,7 @@ struct FftPlan {
     const cd* tw;            // device twiddle and root tables (float64, forward sign)
     int vm;                  // complex values a thread holds per stage (8 or 16)
     int pad;                 // LDS line-stride padding (0 or 1)
-    int nth;                 // threads per workgroup: 256; with vm 8 also 1024 (x pass) or 512 (strided)
+    int nth;                 // threads per workgroup: 256; with vm 8 also 512 (strided passes)
     const cf* twf;           // the same tables rounded to float32 (all-float32 mode; null otherwise)
 };
 

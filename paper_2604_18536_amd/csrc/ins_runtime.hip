@@ -123,10 +123,10 @@ int lines_for(const ins::FftPlan& pl, int maxl, int vm, int pad, int nth, size_t
 // `want` lines, a wider workgroup with 8 values per thread (`wide` threads),
 // and only then 16 values per thread with 256 threads. The LDS stride is
 // padded when that does not narrow the batch and, with `occ`, does not cost a
-// workgroup per CU either (the strided passes; the x passes' 1024-thread
-// workgroups are held to one per CU by their registers anyway). `extra`: LDS
-// bytes the pass keeps beside the lines. Measured choices: the x
-// pass may use 1024 threads (10-15% faster at n_x/2 = 420); the strided passes
+// workgroup per CU either (the strided passes). `extra`: LDS bytes the pass
+// keeps beside the lines. Measured choices: the x passes stay at 256 threads
+// (with their batched row staging, 16 values per thread at n_x/2 = 420 beat
+// 1024-thread workgroups by 10% forward, 4% inverse); the strided passes use
 // at most 512 (1024 slowed them at 840; 16-line batches of 512 threads were 7%
 // slower than 8 lines of 256 at 256^3).
 int choose_lines(ins::FftPlan& pl, int maxl, int want, int wide, size_t extra, bool occ) {
@@ -1055,7 +1055,7 @@ bool setup_fft(ins_ctx c, const std::vector<int>& rx, const std::vector<int>& ry
     auto strided_extra = [](int n, bool solve) {
         return static_cast<size_t>((n & 1) ? n : n / 2) * sizeof(cd) + (solve ? n * sizeof(double) : 0);
     };
-    c->lnl_x = choose_lines(c->px, 16, 8, 1024, 0, false);
+    c->lnl_x = choose_lines(c->px, 16, 8, kBlockHost, 0, false);
     c->lnl_y = channel ? 0 : choose_lines(c->py, 16, 8, 512, strided_extra(g.ny, d == 2), true);
     // the channel's z passes are plain forward / inverse transforms: 16-line batches
     // (256-byte runs) measured 13% faster there; the periodic fused z solve and the y

@@ -415,7 +415,8 @@ __device__ __forceinline__ void ld_pair(const float* p, F& a, F& b) {
 // formed once per row in LDS, then each thread issues the loads of kXBatch
 // values back to back (clamped, branch-free addresses) before it uses any, so
 // it waits for memory once per kXBatch values instead of twice per value
-// (x forward pass at 256^3: 0.143 -> 0.125 ms). Writes r[2m] + i r[2m+1] of
+// (x forward pass: 0.143 -> 0.125 ms at 256^3, 5.5 -> 4.9 ms at 840^3 with 256
+// instead of 1024 threads per workgroup). Writes r[2m] + i r[2m+1] of
 // row l to lds[m ls + l] (rows past nrows: 0) and synchronises; at most 16
 // rows (the plan's batch limit). Same arithmetic as the per-value load.
 constexpr int kXBatch = 4;
@@ -602,9 +603,7 @@ __global__ __launch_bounds__(NTH) void k_fft_x_fwd(Grid g, const T* __restrict__
     };
     const NoOp nop;
     const TabTw<C> rt = plan_tab<C>(P);
-    // (the 1024-thread workgroups of long rows stage about 3 values per thread:
-    // there the batched staging's set-up costs more than it saves, 5-7% at 840)
-    if constexpr (SRC == 0 && NTH <= 256)
+    if constexpr (SRC == 0)
         stage_div_rows<T, DIM, NTH>(g, vel, lds, lnl, ls, M, row0, nrows);
     else
         stage_rows<NTH>(lds, lnl, ls, M, load);
@@ -669,7 +668,6 @@ __device__ __forceinline__ void stage_tangled_rows(const Grid& g, const C* __res
 template <int VM, int NTH, class C = cd>
 __global__ __launch_bounds__(NTH) void k_fft_x_inv(Grid g, const C* __restrict__ spec, real_of<C>* __restrict__ p,
                                                         FftPlan P, const C* __restrict__ post, int lnl) {
-    using F = real_of<C>;
     extern __shared__ __align__(16) unsigned char fft_smem[];
     C* lds = reinterpret_cast<C*>(fft_smem);
     const int nl = 1 << lnl;
@@ -677,27 +675,14 @@ __global__ __launch_bounds__(NTH) void k_fft_x_inv(Grid g, const C* __restrict__
     const int M = P.n;
     const int nrows = g.batch * g.nz * g.ny;
     const int row0 = xcd_logical(blockIdx.x, gridDim.x) * nl;
-    auto load = [&](int l, int k) INS_INLINE -> C {
-        const int row = row0 + l;
-        if (row >= nrows) return C{F(0), F(0)};
-        const C* sr = spec + int64_t(row) * g.sx;
-        const C xk = sr[k];
-        const C xc = cconj(sr[M - k]);
-        const C e = cadd(xk, xc);
-        const C o = cmulc(csub(xk, xc), post[k]);
-        return C{e.x - o.y, e.y + o.x};
-    };
     auto sink = [&](int l, int m, C z) INS_INLINE {
         const int row = row0 + l;
         if (row < nrows) reinterpret_cast<C*>(p + int64_t(row) * g.nx)[m] = z;
     };
     const NoOp nop;
     const TabTw<C> rt = plan_tab<C>(P);
-    if constexpr (NTH <= 256)
-        stage_tangled_rows<NTH>(g, spec, post, lds, lnl, ls, M, row0, nrows);
-    else
-        stage_rows<NTH>(lds, lnl, ls, M, load);
-    fft_run<1, VM, NTH, 1, 1, kLineFast, kElemFast>(lds, lnl, ls, P, rt, load, sink, nop, nullptr);
+    stage_tangled_rows<NTH>(g, spec, post, lds, lnl, ls, M, row0, nrows);
+    fft_run<1, VM, NTH, 1, 1, kLineFast, kElemFast>(lds, lnl, ls, P, rt, nop, sink, nop, nullptr);
 }
 
 // Strided complex pass along y (axis 1) or z (axis 2) of the half spectrum
@@ -858,8 +843,7 @@ hipError_t fft_x_fwd(const Grid& g, const T* vel, const real_of<C>* r, C* spec, 
                        lnl, comp)
 #define INS_XF_VM(D, SRC)                                    \
     do {                                                     \
-        if (px.nth == 1024) INS_XF(D, SRC, 8, 1024);         \
-        else if (px.vm == 8) INS_XF(D, SRC, 8, 256);         \
+        if (px.vm == 8) INS_XF(D, SRC, 8, 256);              \
         else INS_XF(D, SRC, 16, 256);                        \
     } while (0)
     if (vel && comp < 0) {
@@ -881,9 +865,7 @@ hipError_t fft_x_inv(const Grid& g, const C* spec, real_of<C>* p, const FftPlan&
     const int nrows = g.batch * g.nz * g.ny;
     const int nblk = (nrows + nl - 1) / nl;
     const size_t shm = size_t(nl + px.pad) * px.n * sizeof(C);
-    if (px.nth == 1024)
-        hipLaunchKernelGGL((k_fft_x_inv<8, 1024, C>), dim3(nblk), dim3(1024), shm, s, g, spec, p, px, post, lnl);
-    else if (px.vm == 8)
+    if (px.vm == 8)
         hipLaunchKernelGGL((k_fft_x_inv<8, 256, C>), dim3(nblk), dim3(256), shm, s, g, spec, p, px, post, lnl);
     else
         hipLaunchKernelGGL((k_fft_x_inv<16, 256, C>), dim3(nblk), dim3(256), shm, s, g, spec, p, px, post, lnl);
@@ -962,8 +944,7 @@ hipError_t launch_fft_x_fwd_wall(const Grid& g, const T* vel, bool scaled, cd* s
                        post, lnl, 0)
 #define INS_XF_VM(D, SRC)                                    \
     do {                                                     \
-        if (px.nth == 1024) INS_XF(D, SRC, 8, 1024);         \
-        else if (px.vm == 8) INS_XF(D, SRC, 8, 256);         \
+        if (px.vm == 8) INS_XF(D, SRC, 8, 256);              \
         else INS_XF(D, SRC, 16, 256);                        \
     } while (0)
     if (g.dim == 3) {
