@@ -329,6 +329,31 @@ __global__ __launch_bounds__(kBlock) void k_stage_vjp_zm(Grid g, const T* __rest
         }
     };
 
+    // pointwise inputs of the plane computed next, loaded one plane ahead and
+    // combined only when used (so the loads stay in flight through a plane):
+    // the accumulated cotangent (ybar or u0bar) and, with HAS_W, un and q at the
+    // cell and q at its +x, +y, +z neighbours
+    T nacc[3] = {T(0), T(0), T(0)}, nun[3] = {T(0), T(0), T(0)};
+    double nq[3] = {0.0, 0.0, 0.0}, nqc = 0.0;
+    auto fetch_point = [&](int z) {
+        if (!valid) return;
+        const int cyx = cyg * nx + cxg;
+        const int c0 = z * plane + cyx;
+        const int jpc[3] = {z * plane + cyg * nx + (cxg + 1 == nx ? 0 : cxg + 1),
+                            z * plane + (cyg + 1 == ny ? 0 : cyg + 1) * nx + cxg,
+                            (z + 1 == nz ? 0 : z + 1) * plane + cyx};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int64_t kk = boff + int64_t(a) * nc + c0;
+            nacc[a] = (mode == 0 || mode == 3) ? yb[int64_t(a) * nc + c0] : ld_stream(u0bar + kk);
+            if constexpr (HAS_W) {
+                nun[a] = ub[int64_t(a) * nc + c0];
+                nq[a] = qb[jpc[a]];
+            }
+        }
+        if constexpr (HAS_W) nqc = qb[c0];
+    };
+
     const int nk = (z1 - z0) + 2;
     fetch(pmod(z0 - 1, nz));
     park(0);
@@ -336,26 +361,21 @@ __global__ __launch_bounds__(kBlock) void k_stage_vjp_zm(Grid g, const T* __rest
     park(1);
     fetch(pmod(z0 + 1, nz));
     park(2);
+    fetch_point(z0);
     __syncthreads();
     for (int k = 2; k < nk; ++k) {
         const int z = z0 + k - 2;
         const bool more = k + 1 < nk;
         if (more) fetch(pmod(z0 - 1 + k + 1, nz));
-        if (valid) {
-            const int cyx = cyg * nx + cxg;
-            const int c0 = z * plane + cyx;
-            const int zpc = (z + 1 == nz ? 0 : z + 1) * plane + cyx;
-            const int xpc = z * plane + cyg * nx + (cxg + 1 == nx ? 0 : cxg + 1);
-            const int ypc = z * plane + (cyg + 1 == ny ? 0 : cyg + 1) * nx + cxg;
-            const int jpc[3] = {xpc, ypc, zpc};
-            T acc[3];
+        T acc[3];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const int64_t kk = boff + int64_t(a) * nc + c0;
-                acc[a] = (mode == 0 || mode == 3) ? yb[int64_t(a) * nc + c0] : ld_stream(u0bar + kk);
-                if constexpr (HAS_W)
-                    acc[a] += T(double(ub[int64_t(a) * nc + c0]) - (qb[jpc[a]] - qb[c0]) * g.ih[a]);
-            }
+        for (int a = 0; a < 3; ++a) {
+            acc[a] = nacc[a];
+            if constexpr (HAS_W) acc[a] += T(double(nun[a]) - (nq[a] - nqc) * g.ih[a]);
+        }
+        if (more) fetch_point(z + 1);
+        if (valid) {
+            const int c0 = z * plane + cyg * nx + cxg;
             LdsSrc<T> U{&ru[(k - 2) % 3][0][0], &ru[(k - 1) % 3][0][0], &ru[k % 3][0][0], centre};
             LdsSrc<T> F{&rf[(k - 2) % 3][0][0], &rf[(k - 1) % 3][0][0], &rf[k % 3][0][0], centre};
             T out[3];
