@@ -67,18 +67,16 @@ enum { EPI_HIDDEN = 0, EPI_OUT = 1, EPI_DGRAD_HIDDEN = 2, EPI_DGRAD_INPUT = 3 };
 //   EPI_DGRAD_HIDDEN: zbar = acc * gelu'(zin[cell][n]) -> aout [cells][32] bf16
 //   EPI_DGRAD_INPUT : ubar[b][n][cell] += acc (n < nout), field type T
 // The input block is staged in LDS. A workgroup owns a
-// 32 x 4 x 2 block of output cells (x, y, z); it copies the 34 x 6 x 4 input
-// block (periodic halo included) into LDS once, so the 27 taps read their A
-// operands from LDS instead of re-fetching them from memory. Wave w computes
-// the output rows (y, z) = (r % 4, r / 4), r = 2w, 2w + 1: four 16-cell M tiles.
-// B operands (packed weights) come from global memory (every wave of every
-// workgroup reads the same few KB per tap; they stay cache-resident).
-// Wave w computes the output row y = w of both z planes (M tiles mt: plane
-// mt / 2, x half mt % 2). With 32 input channels the K loop runs over the
-// nine (ty, tx) tap columns and, inside, over the four halo planes: each A
-// operand fetched from LDS serves both output planes (taps tz = hz - z), so
-// a wave reads 8 A operands per tap column instead of 12 (the kernel is bound
-// by LDS operand reads, not by the matrix cores). Hidden
+// 32 x 4 x BZ block of output cells (x, y, z); it copies the 34 x 6 x (BZ + 2)
+// input block (periodic halo included) into LDS once, so the 27 taps read their
+// A operands from LDS instead of re-fetching them from memory. B operands
+// (packed weights) come from global memory (every wave of every workgroup reads
+// the same few KB per tap; they stay cache-resident). Wave w computes the
+// output row y = w of every z plane of the block (M tiles mt: plane mt / 2,
+// x half mt % 2). With 32 input channels the K loop runs over the nine (ty, tx)
+// tap columns and, inside, over the BZ + 2 halo planes: each A operand fetched
+// from LDS serves every output plane it is a tap of (tz = hz - z), and each
+// weight operand fetched for a tap column serves 2 BZ M tiles. Hidden
 // layer outputs are staged through LDS so that every global store is a full
 // 16-byte chunk of one cell. In LDS the input block is split by 8-channel
 // chunk, xs[chunk][cell][8]: the 16 lanes of an operand fetch read 16
@@ -86,29 +84,37 @@ enum { EPI_HIDDEN = 0, EPI_OUT = 1, EPI_DGRAD_HIDDEN = 2, EPI_DGRAD_INPUT = 3 };
 constexpr int kCbX = 32, kCbY = 4, kCbZ = 2, kCbCells = kCbX * kCbY * kCbZ;
 constexpr int kChX = kCbX + 2, kChY = kCbY + 2, kChZ = kCbZ + 2, kChCells = kChX * kChY * kChZ;
 
-// Block row (y + 4 z, 0 .. 7) of M tile mt of wave w: row y = w of plane mt / 2.
+// Block row (y + 4 z) of M tile mt of wave w: row y = w of plane mt / 2.
 __device__ __forceinline__ int conv_row(int wave, int mt) { return (mt >> 1) * kCbY + wave; }
+
+// The convolution kernel's output block is 32 x 4 x BZ cells: BZ = 4 for the
+// 32-channel inputs (every weight operand a wave fetches then feeds 8 MFMAs
+// instead of 4), BZ = 2 for the 8-channel ones. Its epilogue stages 256 cells
+// (two planes) at a time.
+template <int BZ>
+constexpr int conv_halo_cells() { return kChX * kChY * (BZ + 2); }
 
 // keep_z false: a forward-only hidden layer stages only its bfloat16 output
 // (the smaller footprint lets more workgroups share a CU).
-template <int CIN>
+template <int CIN, int BZ>
 constexpr size_t conv_t_lds_bytes(bool keep_z = true) {
-    const size_t halo = size_t(kChCells) * CIN * 2;
+    const size_t halo = size_t(conv_halo_cells<BZ>()) * CIN * 2;
     const size_t epi = size_t(kCbCells) * 32 * (keep_z ? 4 + 2 : 2);  // float32 z (or zin) + bfloat16 out
     return halo > epi ? halo : epi;
 }
 
-template <typename T, int CIN, int NT, int EPI>
+template <typename T, int CIN, int NT, int EPI, int BZ>
 __global__ __launch_bounds__(kBlock) void k_conv_t(Grid g, const u16* __restrict__ in, const u16* __restrict__ wpk,
                                                      const float* __restrict__ bias, const float* __restrict__ zin,
                                                      float* __restrict__ zout, u16* __restrict__ aout,
                                                      T* __restrict__ fout, int nout) {
     constexpr int NKT = (kTaps * CIN + 31) / 32;
-    constexpr int MT = 4;
+    constexpr int MT = 2 * BZ;  // M tiles per wave: BZ planes x 2 halves of x
+    constexpr int HZ = BZ + 2, HCELLS = conv_halo_cells<BZ>();
     constexpr int CH = CIN / 8;  // 16-byte chunks per cell
     extern __shared__ __attribute__((aligned(16))) u16 xs[];
     const int nx = g.nx, ny = g.ny, nz = g.nz;
-    const int nbx = nx / kCbX, nby = (ny + kCbY - 1) / kCbY, nbz = (nz + kCbZ - 1) / kCbZ;
+    const int nbx = nx / kCbX, nby = (ny + kCbY - 1) / kCbY, nbz = (nz + BZ - 1) / BZ;
     int L = xcd_logical(blockIdx.x, gridDim.x);
     const int bx = L % nbx;
     L /= nbx;
@@ -116,11 +122,11 @@ __global__ __launch_bounds__(kBlock) void k_conv_t(Grid g, const u16* __restrict
     L /= nby;
     const int bz = L % nbz;
     const int b = L / nbz;
-    const int x0 = bx * kCbX, y0 = by * kCbY, z0 = bz * kCbZ;
+    const int x0 = bx * kCbX, y0 = by * kCbY, z0 = bz * BZ;
     const int tid = threadIdx.x;
     const int64_t bcell = int64_t(b) * nz * ny * nx;
     // 1. input block with periodic halo -> LDS
-    for (int cell = tid; cell < kChCells; cell += kBlock) {
+    for (int cell = tid; cell < HCELLS; cell += kBlock) {
         const int hx = cell % kChX, hy = (cell / kChX) % kChY, hz = cell / (kChX * kChY);
         const int gx = wrapi(x0 - 1 + hx, nx);
         const int gy = pmod_i(y0 - 1 + hy, ny), gz = pmod_i(z0 - 1 + hz, nz);
@@ -129,7 +135,7 @@ __global__ __launch_bounds__(kBlock) void k_conv_t(Grid g, const u16* __restrict
 #pragma unroll
         for (int ch = 0; ch < CH; ++ch) v[ch] = *reinterpret_cast<const uint4*>(in + gc * CIN + ch * 8);
 #pragma unroll
-        for (int ch = 0; ch < CH; ++ch) *reinterpret_cast<uint4*>(xs + (ch * kChCells + cell) * 8) = v[ch];
+        for (int ch = 0; ch < CH; ++ch) *reinterpret_cast<uint4*>(xs + (ch * HCELLS + cell) * 8) = v[ch];
     }
     __syncthreads();
     // 2. implicit GEMM from LDS
@@ -148,7 +154,18 @@ __global__ __launch_bounds__(kBlock) void k_conv_t(Grid g, const u16* __restrict
         hbase[mt] = (zz * kChY + yy) * kChX + (mt & 1) * 16 + lm;
     }
     if constexpr (CIN == 32) {
-        const u16* xq = xs + (gq * kChCells) * 8;  // this lane's 8-channel chunk
+        const u16* xq = xs + (gq * HCELLS) * 8;  // this lane's 8-channel chunk
+        // the weight operands of tap column tyx (tz = 0, 1, 2), fetched one column ahead
+        bf16x8 bn[3][NT];
+        auto fetch_w = [&](int tyx) {
+#pragma unroll
+            for (int tz = 0; tz < 3; ++tz)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+                    bn[tz][nt] = *reinterpret_cast<const bf16x8*>(
+                        wpk + (((tz * 9 + tyx) * NT * 16 + nt * 16 + lm) * 32 + 8 * gq));
+        };
+        fetch_w(0);
 #pragma unroll
         for (int tyx = 0; tyx < 9; ++tyx) {
             const int ty = tyx / 3, tx = tyx % 3;
@@ -156,18 +173,18 @@ __global__ __launch_bounds__(kBlock) void k_conv_t(Grid g, const u16* __restrict
 #pragma unroll
             for (int tz = 0; tz < 3; ++tz)
 #pragma unroll
-                for (int nt = 0; nt < NT; ++nt)
-                    bv[tz][nt] = *reinterpret_cast<const bf16x8*>(
-                        wpk + (((tz * 9 + tyx) * NT * 16 + nt * 16 + lm) * 32 + 8 * gq));
+                for (int nt = 0; nt < NT; ++nt) bv[tz][nt] = bn[tz][nt];
+            if (tyx < 8) fetch_w(tyx + 1);
+            __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of this column's work
 #pragma unroll
-            for (int hz = 0; hz < 4; ++hz) {
+            for (int hz = 0; hz < HZ; ++hz) {
 #pragma unroll
                 for (int xh = 0; xh < 2; ++xh) {
                     // halo cell of source plane hz for output row (y = wave) and x half xh
                     const int cell = (hz * kChY + wave + ty) * kChX + xh * 16 + lm + tx;
                     const bf16x8 av = *reinterpret_cast<const bf16x8*>(xq + cell * 8);
 #pragma unroll
-                    for (int zz = 0; zz < 2; ++zz) {
+                    for (int zz = 0; zz < BZ; ++zz) {
                         const int tz = hz - zz;
                         if (tz < 0 || tz > 2) continue;
 #pragma unroll
@@ -194,7 +211,7 @@ __global__ __launch_bounds__(kBlock) void k_conv_t(Grid g, const u16* __restrict
         for (int mt = 0; mt < MT; ++mt) {
             bf16x8 av;
             if (tap_ok) {
-                av = *reinterpret_cast<const bf16x8*>(xs + ((c0 >> 3) * kChCells + hbase[mt] + toff) * 8);
+                av = *reinterpret_cast<const bf16x8*>(xs + ((c0 >> 3) * HCELLS + hbase[mt] + toff) * 8);
             } else {
 #pragma unroll
                 for (int j = 0; j < 8; ++j) av[j] = __bf16(0.0f);
@@ -214,54 +231,62 @@ __global__ __launch_bounds__(kBlock) void k_conv_t(Grid g, const u16* __restrict
         return yy < ny && zz < nz;
     };
     if constexpr (EPI == EPI_HIDDEN || EPI == EPI_DGRAD_HIDDEN) {
-        // [256][32] float32 z (not kept by a forward-only EPI_HIDDEN call: zout null), then [256][32] bfloat16
+        // per half of the block (planes 2h, 2h + 1: 256 cells, q = 256 h + local cell):
+        // [256][32] float32 z (not kept by a forward-only EPI_HIDDEN call: zout null),
+        // then [256][32] bfloat16
         const bool keep_z = EPI == EPI_DGRAD_HIDDEN || zout != nullptr;
         float* zt = reinterpret_cast<float*>(xs);
         u16* at = keep_z ? reinterpret_cast<u16*>(xs + kCbCells * 32 * 2) : xs;
-        __syncthreads();  // every wave is done reading the input block
-        if constexpr (EPI == EPI_DGRAD_HIDDEN) {
-            for (int e = tid; e < kCbCells * 8; e += kBlock) {  // zin block, 16-byte chunks
-                const int q = e >> 3, ch = e & 7;
-                int64_t c;
-                float4 v = {0.f, 0.f, 0.f, 0.f};
-                if (block_cell(q, c)) v = *reinterpret_cast<const float4*>(zin + c * 32 + ch * 4);
-                *reinterpret_cast<float4*>(zt + q * 32 + ch * 4) = v;
+#pragma unroll
+        for (int h = 0; h < BZ / 2; ++h) {
+            const int qh = h * kCbCells;
+            __syncthreads();  // every wave is done reading the input block / the previous half
+            if constexpr (EPI == EPI_DGRAD_HIDDEN) {
+                for (int e = tid; e < kCbCells * 8; e += kBlock) {  // zin block, 16-byte chunks
+                    const int q = e >> 3, ch = e & 7;
+                    int64_t c;
+                    float4 v = {0.f, 0.f, 0.f, 0.f};
+                    if (block_cell(qh + q, c)) v = *reinterpret_cast<const float4*>(zin + c * 32 + ch * 4);
+                    *reinterpret_cast<float4*>(zt + q * 32 + ch * 4) = v;
+                }
+                __syncthreads();
             }
-            __syncthreads();
-        }
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-            const int qb = conv_row(wave, mt) * 32 + (mt & 1) * 16 + 4 * gq;
+            for (int mt = 4 * h; mt < 4 * h + 4; ++mt) {
+                const int qb = conv_row(wave, mt) * 32 + (mt & 1) * 16 + 4 * gq - qh;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int q = qb + i;
+                for (int i = 0; i < 4; ++i) {
+                    const int q = qb + i;
 #pragma unroll
-                for (int nt = 0; nt < NT; ++nt) {
-                    const int n = nt * 16 + lm;
-                    const float v = acc[mt][nt][i];
-                    if constexpr (EPI == EPI_HIDDEN) {
-                        const float z = v + bias[n];
-                        if (keep_z) zt[q * 32 + n] = z;
-                        at[q * 32 + n] = bf16_bits(gelu_f(z));
-                    } else {
-                        at[q * 32 + n] = bf16_bits(v * gelu_grad_f(zt[q * 32 + n]));
+                    for (int nt = 0; nt < NT; ++nt) {
+                        const int n = nt * 16 + lm;
+                        const float v = acc[mt][nt][i];
+                        if constexpr (EPI == EPI_HIDDEN) {
+                            const float z = v + bias[n];
+                            if (keep_z) zt[q * 32 + n] = z;
+                            at[q * 32 + n] = bf16_bits(gelu_f(z));
+                        } else {
+                            at[q * 32 + n] = bf16_bits(v * gelu_grad_f(zt[q * 32 + n]));
+                        }
                     }
                 }
             }
-        }
-        __syncthreads();
-        for (int e = tid; e < kCbCells * 4; e += kBlock) {  // bfloat16 out: 4 chunks per cell
-            const int q = e >> 2, ch = e & 3;
-            int64_t c;
-            if (block_cell(q, c))
-                *reinterpret_cast<uint4*>(aout + c * 32 + ch * 8) = *reinterpret_cast<const uint4*>(at + q * 32 + ch * 8);
-        }
-        if (EPI == EPI_HIDDEN && zout) {
-            for (int e = tid; e < kCbCells * 8; e += kBlock) {  // float32 z: 8 chunks per cell
-                const int q = e >> 3, ch = e & 7;
+            __syncthreads();
+            for (int e = tid; e < kCbCells * 4; e += kBlock) {  // bfloat16 out: 4 chunks per cell
+                const int q = e >> 2, ch = e & 3;
                 int64_t c;
-                if (block_cell(q, c))
-                    *reinterpret_cast<float4*>(zout + c * 32 + ch * 4) = *reinterpret_cast<const float4*>(zt + q * 32 + ch * 4);
+                if (block_cell(qh + q, c))
+                    *reinterpret_cast<uint4*>(aout + c * 32 + ch * 8) =
+                        *reinterpret_cast<const uint4*>(at + q * 32 + ch * 8);
+            }
+            if (EPI == EPI_HIDDEN && zout) {
+                for (int e = tid; e < kCbCells * 8; e += kBlock) {  // float32 z: 8 chunks per cell
+                    const int q = e >> 3, ch = e & 7;
+                    int64_t c;
+                    if (block_cell(qh + q, c))
+                        *reinterpret_cast<float4*>(zout + c * 32 + ch * 4) =
+                            *reinterpret_cast<const float4*>(zt + q * 32 + ch * 4);
+                }
             }
         }
     } else {
@@ -555,11 +580,14 @@ hipError_t launch_closure_pack_weights(const float* w, int cin, int cout, int ci
 template <typename T>
 hipError_t launch_closure_conv(const Grid& g, int which, const u16* in, const u16* wpk, const float* bias,
                                const float* zin, float* zout, u16* aout, T* fout, hipStream_t s) {
-    const int grid = (g.nx / kCbX) * ((g.ny + kCbY - 1) / kCbY) * ((g.nz + kCbZ - 1) / kCbZ) * g.batch;
-#define INS_CONV(CIN, NT, EPI, NOUT)                                                                              \
-    hipLaunchKernelGGL((k_conv_t<T, CIN, NT, EPI>), dim3(grid), dim3(kBlock),                                     \
-                       conv_t_lds_bytes<CIN>(EPI != EPI_HIDDEN || zout != nullptr), s, g, in, wpk, bias, zin, zout, aout, \
-                       fout, NOUT)
+#define INS_CONV(CIN, NT, EPI, NOUT)                                                                                \
+    do {                                                                                                            \
+        constexpr int BZ = CIN == 32 && EPI == EPI_HIDDEN ? 4 : 2;                                                  \
+        const int grid = (g.nx / kCbX) * ((g.ny + kCbY - 1) / kCbY) * ((g.nz + BZ - 1) / BZ) * g.batch;            \
+        const size_t shm = conv_t_lds_bytes<CIN, BZ>(EPI != EPI_HIDDEN || zout != nullptr);                         \
+        hipLaunchKernelGGL((k_conv_t<T, CIN, NT, EPI, BZ>), dim3(grid), dim3(kBlock), shm, s, g, in, wpk, bias, zin, \
+                           zout, aout, fout, NOUT);                                                                 \
+    } while (0)
     switch (which) {
         case 0: INS_CONV(8, 2, EPI_HIDDEN, 32); break;
         case 1: INS_CONV(32, 2, EPI_HIDDEN, 32); break;
