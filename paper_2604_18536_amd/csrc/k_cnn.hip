@@ -196,7 +196,15 @@ __global__ __launch_bounds__(kBlock) void k_conv_t(Grid g, const u16* __restrict
             }
         }
     } else {
-#pragma unroll 3
+    // the weight operands of K tile kt, fetched one tile ahead
+    bf16x8 bn[NT];
+    auto fetch_w = [&](int kt) {
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+            bn[nt] = *reinterpret_cast<const bf16x8*>(wpk + ((kt * NT * 16 + nt * 16 + lm) * 32 + 8 * gq));
+    };
+    fetch_w(0);
+#pragma unroll
     for (int kt = 0; kt < NKT; ++kt) {
         int tap, c0;
         ktile_tap<CIN>(kt, gq, tap, c0);
@@ -205,8 +213,9 @@ __global__ __launch_bounds__(kBlock) void k_conv_t(Grid g, const u16* __restrict
         const int toff = ((t / 9) * kChY + (t / 3) % 3) * kChX + t % 3;
         bf16x8 bv[NT];
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt)
-            bv[nt] = *reinterpret_cast<const bf16x8*>(wpk + ((kt * NT * 16 + nt * 16 + lm) * 32 + 8 * gq));
+        for (int nt = 0; nt < NT; ++nt) bv[nt] = bn[nt];
+        if (kt + 1 < NKT) fetch_w(kt + 1);
+        __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of this tile's work
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
             bf16x8 av;
@@ -386,8 +395,9 @@ __global__ void k_pack_weights(const float* __restrict__ w, int cin, int cout, i
 // reuses them for all its taps. A tap's B operand starts dx cells into the
 // halo row, i.e. 0, 2 or 4 bytes past a 16-byte boundary: two aligned reads
 // and a byte-align select it. Cells outside the grid (partial blocks in y or
-// z) stage g = 0. Workgroups loop over blocks and write per-workgroup partial
-// sums (reduced in order by k_wgrad_reduce).
+// z) stage g = 0. Workgroups loop over a contiguous range of blocks and write
+// per-workgroup partial sums (reduced in order by k_wgrad_reduce).
+constexpr int kStage = 4;                 // staging items whose loads a thread issues together
 constexpr int kGtStride = kCbCells + 8;  // gT row: 256 cells + pad (conflict-free A reads)
 constexpr int kXtRow = 40;               // xT halo row: 34 cells padded to 40
 constexpr int kXtStride = kChZ * kChY * kXtRow + 8;
@@ -420,61 +430,96 @@ __global__ __launch_bounds__(kBlock) void k_wgrad_t(Grid g, const u16* __restric
     float bacc = 0.f;
     const int nbx = nx / kCbX, nby = (ny + kCbY - 1) / kCbY, nbz = (nz + kCbZ - 1) / kCbZ;
     const int nblocks = nbx * nby * nbz * g.batch;
-    for (int blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
+    // each workgroup takes a contiguous range of blocks, z fastest: consecutive
+    // blocks share two of their four halo planes, which are still in cache
+    const int per = (nblocks + gridDim.x - 1) / gridDim.x;
+    const int blk0 = blockIdx.x * per, blk1 = min(nblocks, blk0 + per);
+    for (int blk = blk0; blk < blk1; ++blk) {
         int L = blk;
+        const int bz = L % nbz;
+        L /= nbz;
         const int bx = L % nbx;
         L /= nbx;
         const int by = L % nby;
-        L /= nby;
-        const int bz = L % nbz;
-        const int b = L / nbz;
+        const int b = L / nby;
         const int x0 = bx * kCbX, y0 = by * kCbY, z0 = bz * kCbZ;
         const int64_t bcell = int64_t(b) * nz * ny * nx;
         __syncthreads();  // the previous block's operands are no longer read
-        // g of the block, cell pairs along x: gT[n][q], q = row * 32 + x
+        // g of the block, cell pairs along x: gT[n][q], q = row * 32 + x; the loads of
+        // kStage items are issued before any is unpacked into LDS
         constexpr int G8 = COUTP / 8;
-        for (int e = tid; e < (kCbCells / 2) * G8; e += kBlock) {
-            const int ch = e % G8, pr = e / G8;
-            const int q = 2 * pr, r = q >> 5, xx = q & 31;
-            const int yy = y0 + r % kCbY, zz = z0 + r / kCbY;
-            uint4 v0 = {0u, 0u, 0u, 0u}, v1 = {0u, 0u, 0u, 0u};
-            if (yy < ny && zz < nz) {
-                const int64_t c = bcell + (int64_t(zz) * ny + yy) * nx + x0 + xx;
-                v0 = *reinterpret_cast<const uint4*>(gin + c * COUTP + ch * 8);
-                v1 = *reinterpret_cast<const uint4*>(gin + (c + 1) * COUTP + ch * 8);
-            }
-            const unsigned a[4] = {v0.x, v0.y, v0.z, v0.w}, bb[4] = {v1.x, v1.y, v1.z, v1.w};
+        constexpr int NG = (kCbCells / 2) * G8;
+        for (int e0 = 0; e0 < NG; e0 += kStage * kBlock) {
+            uint4 v0[kStage], v1[kStage];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const unsigned lo = (a[i >> 1] >> ((i & 1) * 16)) & 0xffffu;
-                const unsigned hi = (bb[i >> 1] >> ((i & 1) * 16)) & 0xffffu;
-                *reinterpret_cast<unsigned*>(gT + (ch * 8 + i) * kGtStride + q) = lo | (hi << 16);
+            for (int k = 0; k < kStage; ++k) {
+                const int e = e0 + k * kBlock + tid;
+                const int ch = e % G8, pr = e / G8;
+                const int q = 2 * pr, r = q >> 5, xx = q & 31;
+                const int yy = y0 + r % kCbY, zz = z0 + r / kCbY;
+                v0[k] = uint4{0u, 0u, 0u, 0u};
+                v1[k] = uint4{0u, 0u, 0u, 0u};
+                if (e < NG && yy < ny && zz < nz) {
+                    const int64_t c = bcell + (int64_t(zz) * ny + yy) * nx + x0 + xx;
+                    v0[k] = *reinterpret_cast<const uint4*>(gin + c * COUTP + ch * 8);
+                    v1[k] = *reinterpret_cast<const uint4*>(gin + (c + 1) * COUTP + ch * 8);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < kStage; ++k) {
+                const int e = e0 + k * kBlock + tid;
+                if (e >= NG) continue;
+                const int ch = e % G8, q = 2 * (e / G8);
+                const unsigned a[4] = {v0[k].x, v0[k].y, v0[k].z, v0[k].w};
+                const unsigned bb[4] = {v1[k].x, v1[k].y, v1[k].z, v1[k].w};
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const unsigned lo = (a[i >> 1] >> ((i & 1) * 16)) & 0xffffu;
+                    const unsigned hi = (bb[i >> 1] >> ((i & 1) * 16)) & 0xffffu;
+                    *reinterpret_cast<unsigned*>(gT + (ch * 8 + i) * kGtStride + q) = lo | (hi << 16);
+                }
             }
         }
         // x of the halo block, cell pairs along x: xT[c][(hz * 6 + hy) * 40 + hx]
         constexpr int C8 = CIN / 8;
         constexpr int NPAIR = kChZ * kChY * (kChX / 2);
-        for (int e = tid; e < NPAIR * C8; e += kBlock) {
-            const int ch = e % C8, pr = e / C8;
-            const int hx = 2 * (pr % (kChX / 2)), hrow = pr / (kChX / 2);
-            const int hy = hrow % kChY, hz = hrow / kChY;
-            const int gy = pmod_i(y0 - 1 + hy, ny), gz = pmod_i(z0 - 1 + hz, nz);
-            const int64_t rowc = bcell + (int64_t(gz) * ny + gy) * nx;
-            const int gx0 = wrapi(x0 - 1 + hx, nx), gx1 = wrapi(x0 + hx, nx);
-            const uint4 v0 = *reinterpret_cast<const uint4*>(xin + (rowc + gx0) * CIN + ch * 8);
-            const uint4 v1 = *reinterpret_cast<const uint4*>(xin + (rowc + gx1) * CIN + ch * 8);
-            const unsigned a[4] = {v0.x, v0.y, v0.z, v0.w}, bb[4] = {v1.x, v1.y, v1.z, v1.w};
+        constexpr int NX = NPAIR * C8;
+        for (int e0 = 0; e0 < NX; e0 += kStage * kBlock) {
+            uint4 v0[kStage], v1[kStage];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const unsigned lo = (a[i >> 1] >> ((i & 1) * 16)) & 0xffffu;
-                const unsigned hi = (bb[i >> 1] >> ((i & 1) * 16)) & 0xffffu;
-                *reinterpret_cast<unsigned*>(xT + (ch * 8 + i) * kXtStride + hrow * kXtRow + hx) = lo | (hi << 16);
+            for (int k = 0; k < kStage; ++k) {
+                const int e = min(e0 + k * kBlock + tid, NX - 1);
+                const int ch = e % C8, pr = e / C8;
+                const int hx = 2 * (pr % (kChX / 2)), hrow = pr / (kChX / 2);
+                const int hy = hrow % kChY, hz = hrow / kChY;
+                const int gy = pmod_i(y0 - 1 + hy, ny), gz = pmod_i(z0 - 1 + hz, nz);
+                const int64_t rowc = bcell + (int64_t(gz) * ny + gy) * nx;
+                const int gx0 = wrapi(x0 - 1 + hx, nx), gx1 = wrapi(x0 + hx, nx);
+                v0[k] = *reinterpret_cast<const uint4*>(xin + (rowc + gx0) * CIN + ch * 8);
+                v1[k] = *reinterpret_cast<const uint4*>(xin + (rowc + gx1) * CIN + ch * 8);
+            }
+#pragma unroll
+            for (int k = 0; k < kStage; ++k) {
+                const int e = e0 + k * kBlock + tid;
+                if (e >= NX) continue;
+                const int ch = e % C8, pr = e / C8;
+                const int hx = 2 * (pr % (kChX / 2)), hrow = pr / (kChX / 2);
+                const unsigned a[4] = {v0[k].x, v0[k].y, v0[k].z, v0[k].w};
+                const unsigned bb[4] = {v1[k].x, v1[k].y, v1[k].z, v1[k].w};
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const unsigned lo = (a[i >> 1] >> ((i & 1) * 16)) & 0xffffu;
+                    const unsigned hi = (bb[i >> 1] >> ((i & 1) * 16)) & 0xffffu;
+                    *reinterpret_cast<unsigned*>(xT + (ch * 8 + i) * kXtStride + hrow * kXtRow + hx) = lo | (hi << 16);
+                }
             }
         }
         __syncthreads();
-        if (tid < COUTP) {
-            const u16* row = gT + tid * kGtStride;
-            for (int q = 0; q < kCbCells; q += 8) {
+        // bias: thread (n = tid mod 32, part = tid / 32) sums cells part*32 .. +31 of channel n
+        if ((tid & 31) < COUTP) {
+            const u16* row = gT + (tid & 31) * kGtStride + (tid >> 5) * 32;
+#pragma unroll
+            for (int q = 0; q < 32; q += 8) {
                 const uint4 v = *reinterpret_cast<const uint4*>(row + q);
                 const unsigned w4[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
@@ -530,7 +575,17 @@ __global__ __launch_bounds__(kBlock) void k_wgrad_t(Grid g, const u16* __restric
                     if (n < COUTP && c < CIN) out[(n * kTaps + tap) * CIN + c] = acc[j][mt][nt][i];
                 }
     }
-    if (tid < COUTP) out[COUTP * kTaps * CIN + tid] = bacc;
+    // the eight partial bias sums of each channel, added in part order
+    __syncthreads();
+    float* red = reinterpret_cast<float*>(ws);
+    red[tid] = bacc;
+    __syncthreads();
+    if (tid < COUTP) {
+        float sum = 0.f;
+#pragma unroll
+        for (int part = 0; part < kBlock / 32; ++part) sum += red[part * 32 + tid];
+        out[COUTP * kTaps * CIN + tid] = sum;
+    }
 }
 
 template <int CIN, int COUTP>
