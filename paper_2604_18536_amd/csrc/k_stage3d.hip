@@ -47,10 +47,16 @@ __device__ __forceinline__ void st_stream(T v, T* p) {
 
 // P: type of the pressure and of the projection arithmetic w - G p (float64;
 // float32 only in the all-float32 comparison mode).
-template <typename T, bool PROJ, int TX, int TY, typename P = double>
+// yinit: 0 reads the accumulator y; 1 starts it at u0. YW: instead, form it
+// from the unprojected stage input as y = u0 + ry (w - u0) (the first stage's
+// u0 + b1 dt F1 with W2 = u0 + a1 dt F1 and ry = b1 / a1, so the first stage
+// need not store y nor this stage read it); a separate instance, so the
+// others compile as before.
+template <typename T, bool PROJ, int TX, int TY, typename P = double, bool YW = false>
 __global__ __launch_bounds__(TX * TY) void k_stage_zm(Grid g, const T* __restrict__ w, const P* __restrict__ p,
                                                         const T* __restrict__ u0, T* __restrict__ y, int yinit, T cy,
-                                                        T* __restrict__ wout, T cw, int zc, const T* __restrict__ mc) {
+                                                        T* __restrict__ wout, T cw, int zc, const T* __restrict__ mc,
+                                                        T ry) {
     constexpr int NT = TX * TY, HX = TX + 2, HP = HX * (TY + 2);
     constexpr int NS = (HP + NT - 1) / NT;  // halo-plane cells per thread
     __shared__ T ring[4][3][HP];
@@ -134,8 +140,11 @@ __global__ __launch_bounds__(TX * TY) void k_stage_zm(Grid g, const T* __restric
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const int64_t kk = boff + int64_t(a) * nc + c0;
-            base[a] = (wout || yinit) ? ld_stream(u0 + kk) : T(0);
-            yv[a] = (y && !yinit) ? ld_stream(y + kk) : base[a];
+            base[a] = (wout || yinit || YW) ? ld_stream(u0 + kk) : T(0);
+            if constexpr (YW)
+                yv[a] = base[a] + ry * (wb[int64_t(a) * nc + c0] - base[a]);
+            else
+                yv[a] = (y && !yinit) ? ld_stream(y + kk) : base[a];
         }
     };
 
@@ -198,17 +207,20 @@ int zm_chunk(const Grid& g) { return zm_chunk(g, kZmTX, kZmTY, 2048, 32); }
 int zm_chunk_stage(const Grid& g, bool fp64) { return zm_chunk(g, 64, 8, fp64 ? 512 : 1024, 64); }
 
 template <typename T, int TX, int TY, typename P = double>
-void launch_stage_zm_tile(const Grid& g, const T* w, const P* p, bool proj, const T* u0, T* y, bool yinit,
-                          double cy, T* wout, double cw, hipStream_t s, const T* mc) {
+void launch_stage_zm_tile(const Grid& g, const T* w, const P* p, bool proj, const T* u0, T* y, int yinit,
+                          double cy, T* wout, double cw, hipStream_t s, const T* mc, double ry = 0.0,
+                          bool yw = false) {
     const int zc = zm_chunk_stage(g, sizeof(T) == 8);
     const int nblk = ((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY) * ((g.nz + zc - 1) / zc) * g.batch;
-    const int yi = yinit ? 1 : 0;
-    if (proj)
-        hipLaunchKernelGGL((k_stage_zm<T, true, TX, TY, P>), dim3(nblk), dim3(TX * TY), 0, s, g, w, p, u0, y, yi,
-                           T(cy), wout, T(cw), zc, mc);
+    if (yw)
+        hipLaunchKernelGGL((k_stage_zm<T, true, TX, TY, P, true>), dim3(nblk), dim3(TX * TY), 0, s, g, w, p, u0, y,
+                           0, T(cy), wout, T(cw), zc, mc, T(ry));
+    else if (proj)
+        hipLaunchKernelGGL((k_stage_zm<T, true, TX, TY, P>), dim3(nblk), dim3(TX * TY), 0, s, g, w, p, u0, y, yinit,
+                           T(cy), wout, T(cw), zc, mc, T(ry));
     else
-        hipLaunchKernelGGL((k_stage_zm<T, false, TX, TY, P>), dim3(nblk), dim3(TX * TY), 0, s, g, w, p, u0, y, yi,
-                           T(cy), wout, T(cw), zc, mc);
+        hipLaunchKernelGGL((k_stage_zm<T, false, TX, TY, P>), dim3(nblk), dim3(TX * TY), 0, s, g, w, p, u0, y, yinit,
+                           T(cy), wout, T(cw), zc, mc, T(ry));
 }
 
 // The forward stage runs 64 x 8 tiles of 512 threads: the 512-byte row runs
@@ -218,9 +230,22 @@ void launch_stage_zm_tile(const Grid& g, const T* w, const P* p, bool proj, cons
 template <typename T>
 hipError_t launch_stage_zm(const Grid& g, const T* w, const double* p, bool proj, const T* u0, T* y, bool yinit,
                            double cy, T* wout, double cw, hipStream_t s, const T* mc) {
-    launch_stage_zm_tile<T, 64, 8>(g, w, p, proj, u0, y, yinit, cy, wout, cw, s, mc);
+    launch_stage_zm_tile<T, 64, 8>(g, w, p, proj, u0, y, yinit ? 1 : 0, cy, wout, cw, s, mc);
     return hipGetLastError();
 }
+
+// The projected stage whose accumulator is formed from its input:
+// y = u0 + ry (w - u0) + cy F, wout = u0 + cw F (F at u = w - G p).
+template <typename T>
+hipError_t launch_stage_zm_yw(const Grid& g, const T* w, const double* p, const T* u0, T* y, double cy, T* wout,
+                              double cw, double ry, hipStream_t s, const T* mc) {
+    launch_stage_zm_tile<T, 64, 8>(g, w, p, true, u0, y, 0, cy, wout, cw, s, mc, ry, true);
+    return hipGetLastError();
+}
+template hipError_t launch_stage_zm_yw<double>(const Grid&, const double*, const double*, const double*, double*, double,
+                                               double*, double, double, hipStream_t, const double*);
+template hipError_t launch_stage_zm_yw<float>(const Grid&, const float*, const double*, const float*, float*, double,
+                                              float*, double, double, hipStream_t, const float*);
 
 template hipError_t launch_stage_zm<double>(const Grid&, const double*, const double*, bool, const double*, double*, bool,
                                             double, double*, double, hipStream_t, const double*);
@@ -230,7 +255,7 @@ template hipError_t launch_stage_zm<float>(const Grid&, const float*, const doub
 // All-float32 comparison mode: float32 pressure and projection arithmetic.
 hipError_t launch_stage_zm_f32(const Grid& g, const float* w, const float* p, bool proj, const float* u0, float* y,
                                bool yinit, double cy, float* wout, double cw, hipStream_t s) {
-    launch_stage_zm_tile<float, 64, 8, float>(g, w, p, proj, u0, y, yinit, cy, wout, cw, s, nullptr);
+    launch_stage_zm_tile<float, 64, 8, float>(g, w, p, proj, u0, y, yinit ? 1 : 0, cy, wout, cw, s, nullptr);
     return hipGetLastError();
 }
 
