@@ -60,7 +60,7 @@ def kernel_bytes(name, n, elem, batch=1, scal=8):
         "stage_first": 3 * v * N,                 # read u0; write y, w
         "stage_first_rec": 2 * v * N,             # read u0; write w
         "stage": (5 * v + S) * N,                 # read w, p, u0, y; write y, w
-        "stage_yw": (4 * v + S) * N,              # read w, p, u0 (y formed from w and u0); write y, w
+        "stage_yw": (5 * v + S) * N,              # read w, p, u0, W2 (y formed from them); write y, w
         "stage_last": (3 * v + S) * N,            # read w, p, y; write y
         "stage_rec": (3 * v + S) * N,             # read w, p, u0; write w
         "wray_stage1": 3 * v * N,                 # read u0; write yacc, w

@@ -124,11 +124,12 @@ int zm_chunk_stage(const Grid& g, bool fp64);
 template <typename T>
 hipError_t launch_stage_zm(const Grid& g, const T* w, const double* p, bool proj, const T* u0, T* y, bool yinit,
                            double cy, T* wout, double cw, hipStream_t s, const T* mc);
-// The projected 3D stage with its accumulator formed as y = u0 + ry (w - u0)
-// (instead of read): y = u0 + ry (w - u0) + cy F, wout = u0 + cw F.
+// The projected 3D stage with its accumulator formed from stage inputs instead
+// of read: y = u0 + ry (wprev - u0) + rw (w - u0) + cy F, wout = u0 + cw F;
+// wprev may be wout's buffer.
 template <typename T>
-hipError_t launch_stage_zm_yw(const Grid& g, const T* w, const double* p, const T* u0, T* y, double cy, T* wout,
-                              double cw, double ry, hipStream_t s, const T* mc);
+hipError_t launch_stage_zm_yw(const Grid& g, const T* w, const double* p, const T* u0, const T* wprev, double ry,
+                              double rw, T* y, double cy, T* wout, double cw, hipStream_t s, const T* mc);
 
 // Spectral Poisson solve pieces.
 // Forward x pass: real rows -> half spectrum. vel != nullptr and comp < 0:

@@ -48,15 +48,17 @@ __device__ __forceinline__ void st_stream(T v, T* p) {
 // P: type of the pressure and of the projection arithmetic w - G p (float64;
 // float32 only in the all-float32 comparison mode).
 // yinit: 0 reads the accumulator y; 1 starts it at u0. YW: instead, form it
-// from the unprojected stage input as y = u0 + ry (w - u0) (the first stage's
-// u0 + b1 dt F1 with W2 = u0 + a1 dt F1 and ry = b1 / a1, so the first stage
-// need not store y nor this stage read it); a separate instance, so the
-// others compile as before.
+// from unprojected stage inputs as y = u0 + ry (wprev - u0) + rw (w - u0):
+// RK4's third stage forms u0 + dt/6 F1 + dt/3 F2 from W2 = u0 + dt/2 F1 (wprev)
+// and W3 = u0 + dt/2 F2 (w), so the first two stages need not store y nor
+// this stage read it. wprev may be the buffer wout writes: each cell's wprev
+// is read one plane before that cell's output is written (hence no restrict).
+// A separate instance, so the others compile as before.
 template <typename T, bool PROJ, int TX, int TY, typename P = double, bool YW = false>
 __global__ __launch_bounds__(TX * TY) void k_stage_zm(Grid g, const T* __restrict__ w, const P* __restrict__ p,
                                                         const T* __restrict__ u0, T* __restrict__ y, int yinit, T cy,
-                                                        T* __restrict__ wout, T cw, int zc, const T* __restrict__ mc,
-                                                        T ry) {
+                                                        T* wout, T cw, int zc, const T* __restrict__ mc,
+                                                        const T* wprev, T ry, T rw) {
     constexpr int NT = TX * TY, HX = TX + 2, HP = HX * (TY + 2);
     constexpr int NS = (HP + NT - 1) / NT;  // halo-plane cells per thread
     __shared__ T ring[4][3][HP];
@@ -142,7 +144,7 @@ __global__ __launch_bounds__(TX * TY) void k_stage_zm(Grid g, const T* __restric
             const int64_t kk = boff + int64_t(a) * nc + c0;
             base[a] = (wout || yinit || YW) ? ld_stream(u0 + kk) : T(0);
             if constexpr (YW)
-                yv[a] = base[a] + ry * (wb[int64_t(a) * nc + c0] - base[a]);
+                yv[a] = base[a] + ry * (ld_stream(wprev + kk) - base[a]) + rw * (wb[int64_t(a) * nc + c0] - base[a]);
             else
                 yv[a] = (y && !yinit) ? ld_stream(y + kk) : base[a];
         }
@@ -208,19 +210,19 @@ int zm_chunk_stage(const Grid& g, bool fp64) { return zm_chunk(g, 64, 8, fp64 ? 
 
 template <typename T, int TX, int TY, typename P = double>
 void launch_stage_zm_tile(const Grid& g, const T* w, const P* p, bool proj, const T* u0, T* y, int yinit,
-                          double cy, T* wout, double cw, hipStream_t s, const T* mc, double ry = 0.0,
-                          bool yw = false) {
+                          double cy, T* wout, double cw, hipStream_t s, const T* mc, const T* wprev = nullptr,
+                          double ry = 0.0, double rw = 0.0) {
     const int zc = zm_chunk_stage(g, sizeof(T) == 8);
     const int nblk = ((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY) * ((g.nz + zc - 1) / zc) * g.batch;
-    if (yw)
+    if (wprev)
         hipLaunchKernelGGL((k_stage_zm<T, true, TX, TY, P, true>), dim3(nblk), dim3(TX * TY), 0, s, g, w, p, u0, y,
-                           0, T(cy), wout, T(cw), zc, mc, T(ry));
+                           0, T(cy), wout, T(cw), zc, mc, wprev, T(ry), T(rw));
     else if (proj)
         hipLaunchKernelGGL((k_stage_zm<T, true, TX, TY, P>), dim3(nblk), dim3(TX * TY), 0, s, g, w, p, u0, y, yinit,
-                           T(cy), wout, T(cw), zc, mc, T(ry));
+                           T(cy), wout, T(cw), zc, mc, wprev, T(0), T(0));
     else
         hipLaunchKernelGGL((k_stage_zm<T, false, TX, TY, P>), dim3(nblk), dim3(TX * TY), 0, s, g, w, p, u0, y, yinit,
-                           T(cy), wout, T(cw), zc, mc, T(ry));
+                           T(cy), wout, T(cw), zc, mc, wprev, T(0), T(0));
 }
 
 // The forward stage runs 64 x 8 tiles of 512 threads: the 512-byte row runs
@@ -234,18 +236,21 @@ hipError_t launch_stage_zm(const Grid& g, const T* w, const double* p, bool proj
     return hipGetLastError();
 }
 
-// The projected stage whose accumulator is formed from its input:
-// y = u0 + ry (w - u0) + cy F, wout = u0 + cw F (F at u = w - G p).
+// The projected stage whose accumulator is formed from stage inputs:
+// y = u0 + ry (wprev - u0) + rw (w - u0) + cy F, wout = u0 + cw F (F at
+// u = w - G p); wprev may be wout's buffer.
 template <typename T>
-hipError_t launch_stage_zm_yw(const Grid& g, const T* w, const double* p, const T* u0, T* y, double cy, T* wout,
-                              double cw, double ry, hipStream_t s, const T* mc) {
-    launch_stage_zm_tile<T, 64, 8>(g, w, p, true, u0, y, 0, cy, wout, cw, s, mc, ry, true);
+hipError_t launch_stage_zm_yw(const Grid& g, const T* w, const double* p, const T* u0, const T* wprev, double ry,
+                              double rw, T* y, double cy, T* wout, double cw, hipStream_t s, const T* mc) {
+    launch_stage_zm_tile<T, 64, 8>(g, w, p, true, u0, y, 0, cy, wout, cw, s, mc, wprev, ry, rw);
     return hipGetLastError();
 }
-template hipError_t launch_stage_zm_yw<double>(const Grid&, const double*, const double*, const double*, double*, double,
-                                               double*, double, double, hipStream_t, const double*);
-template hipError_t launch_stage_zm_yw<float>(const Grid&, const float*, const double*, const float*, float*, double,
-                                              float*, double, double, hipStream_t, const float*);
+template hipError_t launch_stage_zm_yw<double>(const Grid&, const double*, const double*, const double*, const double*,
+                                               double, double, double*, double, double*, double, hipStream_t,
+                                               const double*);
+template hipError_t launch_stage_zm_yw<float>(const Grid&, const float*, const double*, const float*, const float*,
+                                              double, double, float*, double, float*, double, hipStream_t,
+                                              const float*);
 
 template hipError_t launch_stage_zm<double>(const Grid&, const double*, const double*, bool, const double*, double*, bool,
                                             double, double*, double, hipStream_t, const double*);
