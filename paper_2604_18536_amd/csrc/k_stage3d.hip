@@ -99,9 +99,22 @@ __global__ __launch_bounds__(TX * TY) void k_stage_zm(Grid g, const T* __restric
 
     // projected velocity of the halo plane zz at this thread's positions
     T pre[NS][3];
+    // YW in float64: the unprojected w at this thread's own cell of the two
+    // latest fetched planes (loaded with the plane's halo, whose requests cover
+    // the same lines; a later re-read of them went back to memory). In float32
+    // the six registers would cost a wave per SIMD, so that instance re-reads.
+    constexpr bool WREG = YW && sizeof(T) == 8;
+    T wc_prev[3] = {T(0), T(0), T(0)}, wc_last[3] = {T(0), T(0), T(0)};
     auto fetch = [&](int zz) {
         const int zoff = zz * plane;
         const int zpo = (zz + 1 == nz ? 0 : zz + 1) * plane;
+        if constexpr (WREG) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                wc_prev[a] = wc_last[a];
+                if (valid) wc_last[a] = wb[int64_t(a) * nc + zoff + cyg * nx + cxg];
+            }
+        }
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             if (hq[s] < HP) {
@@ -143,7 +156,9 @@ __global__ __launch_bounds__(TX * TY) void k_stage_zm(Grid g, const T* __restric
         for (int a = 0; a < 3; ++a) {
             const int64_t kk = boff + int64_t(a) * nc + c0;
             base[a] = (wout || yinit || YW) ? ld_stream(u0 + kk) : T(0);
-            if constexpr (YW)
+            if constexpr (WREG)  // fetch_point(z) follows fetch(z + 1): the plane before the latest
+                yv[a] = base[a] + ry * (ld_stream(wprev + kk) - base[a]) + rw * (wc_prev[a] - base[a]);
+            else if constexpr (YW)
                 yv[a] = base[a] + ry * (ld_stream(wprev + kk) - base[a]) + rw * (wb[int64_t(a) * nc + c0] - base[a]);
             else
                 yv[a] = (y && !yinit) ? ld_stream(y + kk) : base[a];
