@@ -410,6 +410,23 @@ __device__ __forceinline__ void ld_pair(const float* p, F& a, F& b) {
     b = t.y;
 }
 
+// Two consecutive values of a row as one non-temporal load (the divergence's
+// velocity rows are read once per pass; keeping them out of the caches'
+// normal retention leaves the spectrum the pass writes in the MALL for the
+// next pass: x forward and y forward each 3-5% faster at 256^3).
+template <class F>
+__device__ __forceinline__ void ld_pair_stream(const double* p, F& a, F& b) {
+    const double2 t = __builtin_nontemporal_load(reinterpret_cast<const double2*>(p));
+    a = F(t.x);
+    b = F(t.y);
+}
+template <class F>
+__device__ __forceinline__ void ld_pair_stream(const float* p, F& a, F& b) {
+    const float2 t = __builtin_nontemporal_load(reinterpret_cast<const float2*>(p));
+    a = t.x;
+    b = t.y;
+}
+
 // Row staging of the periodic divergence (the x pass's SRC 0): the offsets of
 // the rows a batch row reads (u_x; u_y at y and y-1; u_z at z and z-1) are
 // formed once per row in LDS, then each thread issues the loads of kXBatch
@@ -458,13 +475,13 @@ __device__ __forceinline__ void stage_div_rows(const Grid& g, const T* __restric
             const int l = fdivmod(t, M, rM, m);
             const DivRows d = rows[l];
             const int x0 = 2 * m, xm = x0 == 0 ? g.nx - 1 : x0 - 1;
-            ld_pair(vel + d.ux + x0, ux0[j], ux1[j]);
-            uxm[j] = vel[d.ux + xm];
-            ld_pair(vel + d.uy + x0, uy0[j], uy1[j]);
-            ld_pair(vel + d.vy + x0, vy0[j], vy1[j]);
+            ld_pair_stream(vel + d.ux + x0, ux0[j], ux1[j]);
+            uxm[j] = __builtin_nontemporal_load(vel + d.ux + xm);
+            ld_pair_stream(vel + d.uy + x0, uy0[j], uy1[j]);
+            ld_pair_stream(vel + d.vy + x0, vy0[j], vy1[j]);
             if constexpr (DIM == 3) {
-                ld_pair(vel + d.uz + x0, uz0[j], uz1[j]);
-                ld_pair(vel + d.vz + x0, vz0[j], vz1[j]);
+                ld_pair_stream(vel + d.uz + x0, uz0[j], uz1[j]);
+                ld_pair_stream(vel + d.vz + x0, vz0[j], vz1[j]);
             }
         }
 #pragma unroll
