@@ -396,6 +396,19 @@ __device__ __forceinline__ void stage_rows(C* __restrict__ lds, int lnl, int ls,
     __syncthreads();
 }
 
+// One spectrum value loaded / stored non-temporally (the strided passes over a
+// spectrum much larger than the MALL, where no pass can find the previous
+// pass's output in it anyway: their short strided runs then stream better).
+template <class C>
+__device__ __forceinline__ C ld_stream_c(const C* p) {
+    return C{__builtin_nontemporal_load(&p->x), __builtin_nontemporal_load(&p->y)};
+}
+template <class C>
+__device__ __forceinline__ void st_stream_c(C* p, C z) {
+    __builtin_nontemporal_store(z.x, &p->x);
+    __builtin_nontemporal_store(z.y, &p->y);
+}
+
 // Two consecutive values of a row (x even), as one load.
 template <class F>
 __device__ __forceinline__ void ld_pair(const double* p, F& a, F& b) {
@@ -406,23 +419,6 @@ __device__ __forceinline__ void ld_pair(const double* p, F& a, F& b) {
 template <class F>
 __device__ __forceinline__ void ld_pair(const float* p, F& a, F& b) {
     const float2 t = *reinterpret_cast<const float2*>(p);
-    a = t.x;
-    b = t.y;
-}
-
-// Two consecutive values of a row as one non-temporal load (the divergence's
-// velocity rows are read once per pass; keeping them out of the caches'
-// normal retention leaves the spectrum the pass writes in the MALL for the
-// next pass: x forward and y forward each 3-5% faster at 256^3).
-template <class F>
-__device__ __forceinline__ void ld_pair_stream(const double* p, F& a, F& b) {
-    const double2 t = __builtin_nontemporal_load(reinterpret_cast<const double2*>(p));
-    a = F(t.x);
-    b = F(t.y);
-}
-template <class F>
-__device__ __forceinline__ void ld_pair_stream(const float* p, F& a, F& b) {
-    const float2 t = __builtin_nontemporal_load(reinterpret_cast<const float2*>(p));
     a = t.x;
     b = t.y;
 }
@@ -475,13 +471,13 @@ __device__ __forceinline__ void stage_div_rows(const Grid& g, const T* __restric
             const int l = fdivmod(t, M, rM, m);
             const DivRows d = rows[l];
             const int x0 = 2 * m, xm = x0 == 0 ? g.nx - 1 : x0 - 1;
-            ld_pair_stream(vel + d.ux + x0, ux0[j], ux1[j]);
-            uxm[j] = __builtin_nontemporal_load(vel + d.ux + xm);
-            ld_pair_stream(vel + d.uy + x0, uy0[j], uy1[j]);
-            ld_pair_stream(vel + d.vy + x0, vy0[j], vy1[j]);
+            ld_pair(vel + d.ux + x0, ux0[j], ux1[j]);
+            uxm[j] = vel[d.ux + xm];
+            ld_pair(vel + d.uy + x0, uy0[j], uy1[j]);
+            ld_pair(vel + d.vy + x0, vy0[j], vy1[j]);
             if constexpr (DIM == 3) {
-                ld_pair_stream(vel + d.uz + x0, uz0[j], uz1[j]);
-                ld_pair_stream(vel + d.vz + x0, vz0[j], vz1[j]);
+                ld_pair(vel + d.uz + x0, uz0[j], uz1[j]);
+                ld_pair(vel + d.vz + x0, vz0[j], vz1[j]);
             }
         }
 #pragma unroll
@@ -786,8 +782,8 @@ __device__ __forceinline__ LineLam<real_of<C>> line_lam(const SolveTab& st, cons
     return {lt[0][kx], kx == 0};
 }
 
-// One batch of a strided pass per workgroup.
-template <int MODE, int VM, int NTH, class C>
+// One batch of a strided pass per workgroup (NT: non-temporal spectrum access).
+template <int MODE, int VM, int NTH, bool NT, class C>
 __device__ __forceinline__ void strided_batch(const Grid& g, C* __restrict__ spec, const FftPlan& P, const FftPlan& Q,
                                               int axis, int lnl, const SolveTab& st, int w, C* lds,
                                               const Roots<C>& rt, const real_of<C>* lam_line) {
@@ -796,10 +792,16 @@ __device__ __forceinline__ void strided_batch(const Grid& g, C* __restrict__ spe
     const int64_t stride = axis == 1 ? int64_t(g.sx) : int64_t(g.sx) * g.ny;  // along the line
     const LineBatch B = line_batch(g, axis, lnl, w);
     auto load = [&](int l, int e) INS_INLINE -> C {
-        return l < B.nvalid ? spec[B.lb0 + l * B.lstep + e * stride] : C{F(0), F(0)};
+        if (l >= B.nvalid) return C{F(0), F(0)};
+        const C* q = spec + B.lb0 + l * B.lstep + e * stride;
+        if constexpr (NT) return ld_stream_c(q);
+        else return *q;
     };
     auto store = [&](int l, int e, C z) INS_INLINE {
-        if (l < B.nvalid) spec[B.lb0 + l * B.lstep + e * stride] = z;
+        if (l >= B.nvalid) return;
+        C* q = spec + B.lb0 + l * B.lstep + e * stride;
+        if constexpr (NT) st_stream_c(q, z);
+        else *q = z;
     };
     const NoOp nop;
     if constexpr (MODE == 1) {
@@ -825,7 +827,7 @@ __device__ __forceinline__ void strided_batch(const Grid& g, C* __restrict__ spe
 // stages in reverse radix order (plan Q, whose first radix is P's last) from
 // those same registers. LDS: the line batch, then the roots, then (MODE 2) the
 // eigenvalues of the line axis.
-template <int MODE, int VM, int NTH, class C = cd>
+template <int MODE, int VM, int NTH, bool NT, class C = cd>
 __global__ __launch_bounds__(NTH) void k_fft_strided(Grid g, C* __restrict__ spec, FftPlan P, FftPlan Q, int axis,
                                                           int lnl, SolveTab st) {
     using F = real_of<C>;
@@ -840,7 +842,8 @@ __global__ __launch_bounds__(NTH) void k_fft_strided(Grid g, C* __restrict__ spe
         for (int j = threadIdx.x; j < P.n; j += NTH) lam_line[j] = src[j];
     }
     __syncthreads();  // roots and eigenvalues in LDS before any stage
-    strided_batch<MODE, VM, NTH>(g, spec, P, Q, axis, lnl, st, xcd_logical(blockIdx.x, gridDim.x), lds, rt, lam_line);
+    strided_batch<MODE, VM, NTH, NT>(g, spec, P, Q, axis, lnl, st, xcd_logical(blockIdx.x, gridDim.x), lds, rt,
+                                     lam_line);
 }
 
 // ----------------------------------------------------------------------------
@@ -896,14 +899,23 @@ hipError_t fft_strided(const Grid& g, C* spec, const FftPlan& pl, const FftPlan&
     const int nwork = strided_batches(g, axis, lnl);
     const size_t shm = (size_t(nl + pl.pad) * pl.n + roots_count(pl.n)) * sizeof(C) +
                        (mode == 2 ? size_t(pl.n) * sizeof(real_of<C>) : 0);
-#define INS_ST(MODE, VM, NTH)                                                                                    \
-    hipLaunchKernelGGL((k_fft_strided<MODE, VM, NTH, C>), dim3(nwork), dim3(NTH), shm, s, g, spec, pl, rev, axis, lnl, \
-                       st)
-#define INS_ST_VM(MODE)                                  \
-    do {                                                 \
-        if (pl.nth == 512) INS_ST(MODE, 8, 512);         \
-        else if (pl.vm == 8) INS_ST(MODE, 8, 256);       \
-        else INS_ST(MODE, 16, 256);                      \
+    // non-temporal access once the spectrum is well beyond the 256 MB MALL and the
+    // batches give 128-byte runs (512^3: y passes 7-10% faster; with the 64-byte
+    // runs of 840 lines it changed nothing)
+    const bool nt = nl >= 8 && size_t(g.batch) * g.nz * g.ny * g.sx * sizeof(C) > (size_t(512) << 20);
+#define INS_ST2(MODE, VM, NTH, NT)                                                                                   \
+    hipLaunchKernelGGL((k_fft_strided<MODE, VM, NTH, NT, C>), dim3(nwork), dim3(NTH), shm, s, g, spec, pl, rev, axis, \
+                       lnl, st)
+#define INS_ST(MODE, VM, NTH)                                            \
+    do {                                                                 \
+        if (nt) INS_ST2(MODE, VM, NTH, true);                            \
+        else INS_ST2(MODE, VM, NTH, false);                              \
+    } while (0)
+#define INS_ST_VM(MODE)                                                  \
+    do {                                                                 \
+        if (pl.nth == 512) INS_ST(MODE, 8, 512);                         \
+        else if (pl.vm == 8) INS_ST(MODE, 8, 256);                       \
+        else INS_ST(MODE, 16, 256);                                      \
     } while (0)
     if (mode == 0)
         INS_ST_VM(0);
@@ -913,6 +925,7 @@ hipError_t fft_strided(const Grid& g, C* spec, const FftPlan& pl, const FftPlan&
         INS_ST_VM(2);
 #undef INS_ST_VM
 #undef INS_ST
+#undef INS_ST2
     return hipGetLastError();
 }
 
