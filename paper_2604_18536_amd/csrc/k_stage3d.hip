@@ -166,6 +166,80 @@ __global__ __launch_bounds__(TX * TY) void k_stage_zm(Grid g, const T* __restric
     };
 
     const int nk = (z1 - z0) + 2;
+    if constexpr (!PROJ && sizeof(T) == 8) {
+        // The unprojected stage (its stage velocity is u0 itself, w == u0) in
+        // float64: two planes ahead. The loads of ring plane k+2 are issued in
+        // iteration k and parked at the end of iteration k+1, so each has two
+        // planes' compute to land (twice the bytes in flight of a one-plane
+        // pipeline; the LDS ring already holds the kernel to two workgroups per
+        // CU, so the extra registers cost no occupancy). The two planes in
+        // flight alternate between two register sets (static indices: the loop
+        // is unrolled by two). u0 at a thread's own cell is the centre of the
+        // ring plane it computes, so no pointwise stream is loaded
+        // (256^3: 0.243 -> 0.231 ms, 512^3: 1.98 -> 1.76 ms with the two-plane
+        // pipeline alone; the projected stages, which carry four pressure
+        // values per halo cell as well, spilled and ran slower with it).
+        T rwA[NS][3], rwB[NS][3];
+        auto fetch_raw = [&](int zz, T (&rw_)[NS][3]) {
+            const int zoff = zz * plane;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                if (hq[s] < HP) {
+                    const int j = zoff + hxy[s];
+                    rw_[s][0] = wb[j];
+                    rw_[s][1] = wb[nc + j];
+                    rw_[s][2] = wb[2 * nc + j];
+                }
+            }
+        };
+        auto park_raw = [&](int k, const T (&rw_)[NS][3]) {
+            T* slot = &ring[k & 3][0][0];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                if (hq[s] < HP) {
+                    slot[hq[s]] = rw_[s][0];
+                    slot[HP + hq[s]] = rw_[s][1];
+                    slot[2 * HP + hq[s]] = rw_[s][2];
+                }
+            }
+        };
+        // iteration k: issue ring plane k+2 into iw, compute plane z0+k-2, park
+        // ring plane k+1 from pw
+        auto iter = [&](int k, T (&iw)[NS][3], const T (&pw)[NS][3]) {
+            const int z = z0 + k - 2;
+            if (k + 2 < nk) fetch_raw(pmod(z0 - 1 + k + 2, nz), iw);
+            if (valid) {
+                const int c0 = z * plane + cyg * nx + cxg;
+                const T* zc0 = &ring[(k - 1) & 3][0][0];
+                LdsSrc<T, HX, HP> U{&ring[(k - 2) & 3][0][0], zc0, &ring[k & 3][0][0], centre};
+                T F[3];
+                rhs_cell<T, 3>(g, U, Nb{}, F);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const int64_t kk = boff + int64_t(a) * nc + c0;
+                    const T b0 = zc0[a * HP + centre];
+                    if (mc) F[a] += mc[kk];
+                    if (y) st_stream((yinit ? b0 : ld_stream(y + kk)) + cy * F[a], y + kk);
+                    if (wout) st_stream(b0 + cw * F[a], wout + kk);
+                }
+            }
+            if (k + 1 < nk) park_raw(k + 1, pw);
+            __syncthreads();
+        };
+        fetch_raw(pmod(z0 - 1, nz), rwA);
+        park_raw(0, rwA);
+        fetch_raw(pmod(z0, nz), rwA);
+        park_raw(1, rwA);
+        fetch_raw(pmod(z0 + 1, nz), rwA);
+        if (nk > 3) fetch_raw(pmod(z0 + 2, nz), rwB);
+        park_raw(2, rwA);
+        __syncthreads();
+        for (int k = 2; k < nk; k += 2) {
+            iter(k, rwA, rwB);
+            if (k + 1 < nk) iter(k + 1, rwB, rwA);
+        }
+        return;
+    }
     fetch(pmod(z0 - 1, nz));
     park(0);
     fetch(pmod(z0, nz));
@@ -247,6 +321,7 @@ void launch_stage_zm_tile(const Grid& g, const T* w, const P* p, bool proj, cons
 template <typename T>
 hipError_t launch_stage_zm(const Grid& g, const T* w, const double* p, bool proj, const T* u0, T* y, bool yinit,
                            double cy, T* wout, double cw, hipStream_t s, const T* mc) {
+    if (!proj && w != u0) return hipErrorInvalidValue;  // the unprojected stage takes its centre u0 from w
     launch_stage_zm_tile<T, 64, 8>(g, w, p, proj, u0, y, yinit ? 1 : 0, cy, wout, cw, s, mc);
     return hipGetLastError();
 }
