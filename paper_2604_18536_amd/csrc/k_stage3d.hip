@@ -47,20 +47,32 @@ __device__ __forceinline__ void st_stream(T v, T* p) {
 
 // P: type of the pressure and of the projection arithmetic w - G p (float64;
 // float32 only in the all-float32 comparison mode).
-// yinit: 0 reads the accumulator y; 1 starts it at u0. YW: instead, form it
-// from unprojected stage inputs as y = u0 + ry (wprev - u0) + rw (w - u0):
-// RK4's third stage forms u0 + dt/6 F1 + dt/3 F2 from W2 = u0 + dt/2 F1 (wprev)
-// and W3 = u0 + dt/2 F2 (w), so the first two stages need not store y nor
-// this stage read it. wprev may be the buffer wout writes: each cell's wprev
-// is read one plane before that cell's output is written (hence no restrict).
-// A separate instance, so the others compile as before.
-template <typename T, bool PROJ, int TX, int TY, typename P = double, bool YW = false>
+// PT: the pointwise streams the stage reads at its own cells, fixed per
+// instance (bit 0: base = u0, the stage register's origin and, with yinit, the
+// accumulator's; bit 1: the accumulator y, or with YW the earlier stage input
+// wprev). y and wout are written when non-null; yinit starts y at u0.
+// YW: the accumulator is formed from unprojected stage inputs as
+// y = u0 + ry (wprev - u0) + rw (w - u0): RK4's third stage forms
+// u0 + dt/6 F1 + dt/3 F2 from W2 = u0 + dt/2 F1 (wprev) and W3 = u0 + dt/2 F2
+// (w), so the first two stages need not store y nor this stage read it. wprev
+// may be the buffer wout writes: each cell's wprev is read one plane before
+// that cell's output is written (hence no restrict).
+//
+// Every global load in the plane loop is issued unconditionally (halo slots
+// past the halo load a valid position and are not parked; the last iteration
+// fetches its own last plane again, an L2 hit; the pointwise cells and planes
+// are clamped), so the compiler counts the loads in flight exactly and waits
+// only for the ones a step needs. With a load behind a condition it must
+// assume the shortest path and waits for every load in flight: the next
+// plane's halo loads were then waited for before the current plane's compute.
+template <typename T, bool PROJ, int TX, int TY, typename P = double, bool YW = false, int PT = 1>
 __global__ __launch_bounds__(TX * TY) void k_stage_zm(Grid g, const T* __restrict__ w, const P* __restrict__ p,
                                                         const T* __restrict__ u0, T* __restrict__ y, int yinit, T cy,
                                                         T* wout, T cw, int zc, const T* __restrict__ mc,
                                                         const T* wprev, T ry, T rw) {
     constexpr int NT = TX * TY, HX = TX + 2, HP = HX * (TY + 2);
     constexpr int NS = (HP + NT - 1) / NT;  // halo-plane cells per thread
+    constexpr bool LB = (PT & 1) != 0, LY = (PT & 2) != 0;
     __shared__ T ring[4][3][HP];
     const int nx = g.nx, ny = g.ny, nz = g.nz;
     const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY, nzc = (nz + zc - 1) / zc;
@@ -79,7 +91,8 @@ __global__ __launch_bounds__(TX * TY) void k_stage_zm(Grid g, const T* __restric
     const int nc = int(g.ncell);
     const int plane = nx * ny;
 
-    // halo-plane positions loaded by this thread
+    // halo-plane positions loaded by this thread (slots past the halo load the
+    // first position and are not parked)
     int hq[NS], hxy[NS], hxp[NS], hyp[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
@@ -95,101 +108,28 @@ __global__ __launch_bounds__(TX * TY) void k_stage_zm(Grid g, const T* __restric
     const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
     const int cxg = x0 + lx, cyg = y0 + ly;
     const bool valid = cxg < nx && cyg < ny;
+    const int cxy = min(cyg, ny - 1) * nx + min(cxg, nx - 1);  // own cell, clamped for the loads
     const int centre = (ly + 1) * HX + (lx + 1);
+    const int nk = (z1 - z0) + 2;  // ring planes z0-1 .. z1
 
-    // projected velocity of the halo plane zz at this thread's positions
-    T pre[NS][3];
-    // YW in float64: the unprojected w at this thread's own cell of the two
-    // latest fetched planes (loaded with the plane's halo, whose requests cover
-    // the same lines; a later re-read of them went back to memory). In float32
-    // the six registers would cost a wave per SIMD, so that instance re-reads.
-    constexpr bool WREG = YW && sizeof(T) == 8;
-    T wc_prev[3] = {T(0), T(0), T(0)}, wc_last[3] = {T(0), T(0), T(0)};
-    auto fetch = [&](int zz) {
-        const int zoff = zz * plane;
-        const int zpo = (zz + 1 == nz ? 0 : zz + 1) * plane;
-        if constexpr (WREG) {
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                wc_prev[a] = wc_last[a];
-                if (valid) wc_last[a] = wb[int64_t(a) * nc + zoff + cyg * nx + cxg];
-            }
-        }
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            if (hq[s] < HP) {
-                const int j = zoff + hxy[s];
-                if constexpr (PROJ) {
-                    const P pc = pb[j];
-                    pre[s][0] = T(P(wb[j]) - (pb[zoff + hxp[s]] - pc) * P(g.ih[0]));
-                    pre[s][1] = T(P(wb[nc + j]) - (pb[zoff + hyp[s]] - pc) * P(g.ih[1]));
-                    pre[s][2] = T(P(wb[2 * nc + j]) - (pb[zpo + hxy[s]] - pc) * P(g.ih[2]));
-                } else {
-                    pre[s][0] = wb[j];
-                    pre[s][1] = wb[nc + j];
-                    pre[s][2] = wb[2 * nc + j];
-                }
-            }
-        }
-    };
-    auto park = [&](int k) {
-        T* slot = &ring[k & 3][0][0];
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            if (hq[s] < HP) {
-                slot[hq[s]] = pre[s][0];
-                slot[HP + hq[s]] = pre[s][1];
-                slot[2 * HP + hq[s]] = pre[s][2];
-            }
-        }
-    };
-
-    // Pipeline: iteration k computes plane z0+k-2 from ring slots k-2, k-1, k
-    // while the loads of plane k+1 are in flight; they land in slot k+1, which
-    // no thread reads during iteration k.
-    // pointwise streams of the plane to be computed next, loaded one plane ahead
-    T base[3], yv[3];
-    auto fetch_point = [&](int z) {
-        if (!valid) return;
-        const int c0 = z * plane + cyg * nx + cxg;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const int64_t kk = boff + int64_t(a) * nc + c0;
-            base[a] = (wout || yinit || YW) ? ld_stream(u0 + kk) : T(0);
-            if constexpr (WREG)  // fetch_point(z) follows fetch(z + 1): the plane before the latest
-                yv[a] = base[a] + ry * (ld_stream(wprev + kk) - base[a]) + rw * (wc_prev[a] - base[a]);
-            else if constexpr (YW)
-                yv[a] = base[a] + ry * (ld_stream(wprev + kk) - base[a]) + rw * (wb[int64_t(a) * nc + c0] - base[a]);
-            else
-                yv[a] = (y && !yinit) ? ld_stream(y + kk) : base[a];
-        }
-    };
-
-    const int nk = (z1 - z0) + 2;
     if constexpr (!PROJ && sizeof(T) == 8) {
         // The unprojected stage (its stage velocity is u0 itself, w == u0) in
         // float64: two planes ahead. The loads of ring plane k+2 are issued in
         // iteration k and parked at the end of iteration k+1, so each has two
-        // planes' compute to land (twice the bytes in flight of a one-plane
-        // pipeline; the LDS ring already holds the kernel to two workgroups per
-        // CU, so the extra registers cost no occupancy). The two planes in
-        // flight alternate between two register sets (static indices: the loop
-        // is unrolled by two). u0 at a thread's own cell is the centre of the
-        // ring plane it computes, so no pointwise stream is loaded
-        // (256^3: 0.243 -> 0.231 ms, 512^3: 1.98 -> 1.76 ms with the two-plane
-        // pipeline alone; the projected stages, which carry four pressure
-        // values per halo cell as well, spilled and ran slower with it).
+        // planes' compute to land (the LDS ring already holds the kernel to two
+        // workgroups per CU, so the extra registers cost no occupancy). The two
+        // planes in flight alternate between two register sets (static indices:
+        // the loop is unrolled by two). u0 at a thread's own cell is the centre
+        // of the ring plane it computes, so no pointwise stream is loaded.
         T rwA[NS][3], rwB[NS][3];
         auto fetch_raw = [&](int zz, T (&rw_)[NS][3]) {
             const int zoff = zz * plane;
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
-                if (hq[s] < HP) {
-                    const int j = zoff + hxy[s];
-                    rw_[s][0] = wb[j];
-                    rw_[s][1] = wb[nc + j];
-                    rw_[s][2] = wb[2 * nc + j];
-                }
+                const int j = zoff + hxy[s];
+                rw_[s][0] = wb[j];
+                rw_[s][1] = wb[nc + j];
+                rw_[s][2] = wb[2 * nc + j];
             }
         };
         auto park_raw = [&](int k, const T (&rw_)[NS][3]) {
@@ -203,17 +143,17 @@ __global__ __launch_bounds__(TX * TY) void k_stage_zm(Grid g, const T* __restric
                 }
             }
         };
-        // iteration k: issue ring plane k+2 into iw, compute plane z0+k-2, park
-        // ring plane k+1 from pw
+        // iteration k: issue ring plane k+2 into iw (the last plane again near
+        // the end), compute plane z0+k-2, park ring plane k+1 from pw
         auto iter = [&](int k, T (&iw)[NS][3], const T (&pw)[NS][3]) {
             const int z = z0 + k - 2;
-            if (k + 2 < nk) fetch_raw(pmod(z0 - 1 + k + 2, nz), iw);
+            fetch_raw(pmod(z0 - 1 + min(k + 2, nk - 1), nz), iw);
+            const T* zc0 = &ring[(k - 1) & 3][0][0];
+            LdsSrc<T, HX, HP> U{&ring[(k - 2) & 3][0][0], zc0, &ring[k & 3][0][0], centre};
+            T F[3];
+            rhs_cell<T, 3>(g, U, Nb{}, F);
             if (valid) {
                 const int c0 = z * plane + cyg * nx + cxg;
-                const T* zc0 = &ring[(k - 1) & 3][0][0];
-                LdsSrc<T, HX, HP> U{&ring[(k - 2) & 3][0][0], zc0, &ring[k & 3][0][0], centre};
-                T F[3];
-                rhs_cell<T, 3>(g, U, Nb{}, F);
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
                     const int64_t kk = boff + int64_t(a) * nc + c0;
@@ -231,48 +171,137 @@ __global__ __launch_bounds__(TX * TY) void k_stage_zm(Grid g, const T* __restric
         fetch_raw(pmod(z0, nz), rwA);
         park_raw(1, rwA);
         fetch_raw(pmod(z0 + 1, nz), rwA);
-        if (nk > 3) fetch_raw(pmod(z0 + 2, nz), rwB);
+        fetch_raw(pmod(z0 - 1 + min(3, nk - 1), nz), rwB);
         park_raw(2, rwA);
         __syncthreads();
-        for (int k = 2; k < nk; k += 2) {
+        int k = 2;
+        for (; k + 1 < nk; k += 2) {
             iter(k, rwA, rwB);
-            if (k + 1 < nk) iter(k + 1, rwB, rwA);
+            iter(k + 1, rwB, rwA);
         }
+        if (k < nk) iter(k, rwA, rwB);
         return;
     }
+
+    // raw loads of the halo plane at this thread's positions (w, and with PROJ
+    // p at the cell and at its +x, +y, +z neighbours); the projection
+    // u = w - G p is formed when the plane is parked, so that the loads stay in
+    // flight through the plane computed meanwhile
+    T pw_[NS][3];
+    P pp_[NS][4];
+    // YW in float64: the unprojected w at this thread's own cell of the ring
+    // planes k-1 (wcA), k (wcB) and k+1 (wcN, in flight), loaded with the
+    // plane's halo (whose requests cover the same lines; a later re-read went
+    // back to memory). In float32 the registers would cost a wave per SIMD, so
+    // that instance reads it as a third pointwise stream.
+    constexpr bool WREG = YW && sizeof(T) == 8;
+    T wcA[3] = {T(0), T(0), T(0)}, wcB[3] = {T(0), T(0), T(0)}, wcN[3] = {T(0), T(0), T(0)};
+    auto fetch = [&](int zz) {
+        const int zoff = zz * plane;
+        const int zpo = (zz + 1 == nz ? 0 : zz + 1) * plane;
+        if constexpr (WREG) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) wcN[a] = wb[int64_t(a) * nc + zoff + cxy];
+        }
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int j = zoff + hxy[s];
+            pw_[s][0] = wb[j];
+            pw_[s][1] = wb[nc + j];
+            pw_[s][2] = wb[2 * nc + j];
+            if constexpr (PROJ) {
+                pp_[s][0] = pb[j];
+                pp_[s][1] = pb[zoff + hxp[s]];
+                pp_[s][2] = pb[zoff + hyp[s]];
+                pp_[s][3] = pb[zpo + hxy[s]];
+            }
+        }
+    };
+    auto park = [&](int k) {
+        T* slot = &ring[k & 3][0][0];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            if (hq[s] < HP) {
+                if constexpr (PROJ) {
+                    const P pc = pp_[s][0];
+                    slot[hq[s]] = T(P(pw_[s][0]) - (pp_[s][1] - pc) * P(g.ih[0]));
+                    slot[HP + hq[s]] = T(P(pw_[s][1]) - (pp_[s][2] - pc) * P(g.ih[1]));
+                    slot[2 * HP + hq[s]] = T(P(pw_[s][2]) - (pp_[s][3] - pc) * P(g.ih[2]));
+                } else {
+                    slot[hq[s]] = pw_[s][0];
+                    slot[HP + hq[s]] = pw_[s][1];
+                    slot[2 * HP + hq[s]] = pw_[s][2];
+                }
+            }
+        }
+    };
+    // Pointwise streams of the plane computed next: issued after the current
+    // plane's stores, used at the next plane's stores (raw values, combined
+    // only there).
+    constexpr bool WPT = YW && !WREG;
+    T pbase[3] = {T(0), T(0), T(0)}, pyv[3] = {T(0), T(0), T(0)}, pwc[3] = {T(0), T(0), T(0)};
+    const T* ysrc = YW ? wprev : y;
+    auto fetch_point = [&](int z) {
+        const int c0 = z * plane + cxy;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int64_t kk = boff + int64_t(a) * nc + c0;
+            if constexpr (LB) pbase[a] = ld_stream(u0 + kk);
+            if constexpr (LY) pyv[a] = ld_stream(ysrc + kk);
+            if constexpr (WPT) pwc[a] = wb[int64_t(a) * nc + c0];
+        }
+    };
+
+    // Pipeline: iteration k issues ring plane k+1, computes plane z0+k-2 from
+    // ring slots k-2, k-1, k, stores it, issues the next plane's pointwise
+    // streams and parks plane k+1 in slot k+1, which no thread reads in
+    // iteration k.
     fetch(pmod(z0 - 1, nz));
     park(0);
     fetch(pmod(z0, nz));
     park(1);
-    if (nk > 2) fetch(pmod(z0 + 1, nz));
+    if constexpr (WREG) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) wcA[a] = wcN[a];
+    }
+    fetch(pmod(z0 + 1, nz));
     park(2);
+    if constexpr (WREG) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) wcB[a] = wcN[a];
+    }
     fetch_point(z0);
     __syncthreads();
     for (int k = 2; k < nk; ++k) {
         const int z = z0 + k - 2;
-        const bool more = k + 1 < nk;
-        if (more) fetch(pmod(z0 - 1 + k + 1, nz));
-        T cb[3], cyv[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            cb[a] = base[a];
-            cyv[a] = yv[a];
-        }
-        if (more) fetch_point(z + 1);
+        fetch(pmod(z0 - 1 + min(k + 1, nk - 1), nz));
+        LdsSrc<T, HX, HP> U{&ring[(k - 2) & 3][0][0], &ring[(k - 1) & 3][0][0], &ring[k & 3][0][0], centre};
+        T F[3];
+        rhs_cell<T, 3>(g, U, Nb{}, F);
         if (valid) {
             const int c0 = z * plane + cyg * nx + cxg;
-            LdsSrc<T, HX, HP> U{&ring[(k - 2) & 3][0][0], &ring[(k - 1) & 3][0][0], &ring[k & 3][0][0], centre};
-            T F[3];
-            rhs_cell<T, 3>(g, U, Nb{}, F);
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const int64_t kk = boff + int64_t(a) * nc + c0;
+                const T base = LB ? pbase[a] : T(0);
+                T yv;
+                if constexpr (YW) yv = base + ry * (pyv[a] - base) + rw * ((WREG ? wcA[a] : pwc[a]) - base);
+                else if constexpr (LY) yv = pyv[a];
+                else yv = base;
                 if (mc) F[a] += mc[kk];
-                if (y) st_stream(cyv[a] + cy * F[a], y + kk);
-                if (wout) st_stream(cb[a] + cw * F[a], wout + kk);
+                if (y) st_stream(yv + cy * F[a], y + kk);
+                if (wout) st_stream(base + cw * F[a], wout + kk);
             }
         }
-        if (more) park(k + 1);
+        fetch_point(min(z + 1, z1 - 1));
+        if (k + 1 < nk) park(k + 1);
+        if constexpr (WREG) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                wcA[a] = wcB[a];
+                wcB[a] = wcN[a];
+            }
+        }
         __syncthreads();
     }
 }
@@ -303,15 +332,25 @@ void launch_stage_zm_tile(const Grid& g, const T* w, const P* p, bool proj, cons
                           double ry = 0.0, double rw = 0.0) {
     const int zc = zm_chunk_stage(g, sizeof(T) == 8);
     const int nblk = ((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY) * ((g.nz + zc - 1) / zc) * g.batch;
+    // pointwise streams: u0 when it seeds the stage register or the accumulator,
+    // y when the accumulator is read
+    const int pt = ((wout || yinit) ? 1 : 0) | ((y && !yinit) ? 2 : 0);
+#define INS_SZM(PR, YWI, PTI, YI, RY, RW)                                                                          \
+    hipLaunchKernelGGL((k_stage_zm<T, PR, TX, TY, P, YWI, PTI>), dim3(nblk), dim3(TX * TY), 0, s, g, w, p, u0, y, YI, \
+                       T(cy), wout, T(cw), zc, mc, wprev, T(RY), T(RW))
     if (wprev)
-        hipLaunchKernelGGL((k_stage_zm<T, true, TX, TY, P, true>), dim3(nblk), dim3(TX * TY), 0, s, g, w, p, u0, y,
-                           0, T(cy), wout, T(cw), zc, mc, wprev, T(ry), T(rw));
-    else if (proj)
-        hipLaunchKernelGGL((k_stage_zm<T, true, TX, TY, P>), dim3(nblk), dim3(TX * TY), 0, s, g, w, p, u0, y, yinit,
-                           T(cy), wout, T(cw), zc, mc, wprev, T(0), T(0));
+        INS_SZM(true, true, 3, 0, ry, rw);
+    else if (!proj && pt == 3)
+        INS_SZM(false, false, 3, yinit, 0.0, 0.0);
+    else if (!proj)
+        INS_SZM(false, false, 1, yinit, 0.0, 0.0);
+    else if (pt == 3)
+        INS_SZM(true, false, 3, yinit, 0.0, 0.0);
+    else if (pt == 2)
+        INS_SZM(true, false, 2, yinit, 0.0, 0.0);
     else
-        hipLaunchKernelGGL((k_stage_zm<T, false, TX, TY, P>), dim3(nblk), dim3(TX * TY), 0, s, g, w, p, u0, y, yinit,
-                           T(cy), wout, T(cw), zc, mc, wprev, T(0), T(0));
+        INS_SZM(true, false, 1, yinit, 0.0, 0.0);
+#undef INS_SZM
 }
 
 // The forward stage runs 64 x 8 tiles of 512 threads: the 512-byte row runs
