@@ -448,6 +448,96 @@ __global__ __launch_bounds__(kBlock) void k_stage_vjp_zm(Grid g, const T* __rest
     const bool valid = cxg < nx && cyg < ny;
     const int centre = (ly + 1) * kZmHX + (lx + 1);
 
+    if constexpr (!HAS_W) {
+        // Without a second cotangent (Fbar_i = cb ybar: the last RK stage's
+        // pullback, run first): raw halo loads (w and p at the cell and at its
+        // +x, +y, +z neighbours, ybar), combined into u_i and Fbar_i only when
+        // the plane is parked, and every load of the plane loop issued
+        // unconditionally (slots past the halo load a valid position; the last
+        // iteration fetches its own last plane again; pointwise cells and
+        // planes clamped), so the compiler's wait counts are exact and a
+        // plane's compute does not wait for the next plane's loads
+        // (256^3: 0.604 -> 0.498 ms). The stages with a second cotangent keep
+        // the schedule below: the same change made them 1-5% slower (their
+        // raw loads need 186 registers, 2 waves per SIMD instead of 3).
+        const int cxy = min(cyg, ny - 1) * nx + min(cxg, nx - 1);
+        T hw[2][3], hy[2][3];
+        double hp[2][4];
+        auto fetch_raw = [&](int zz) {
+            const int zoff = zz * plane;
+            const int zpo = (zz + 1 == nz ? 0 : zz + 1) * plane;
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const int j = zoff + hxy[s];
+                const int jp[3] = {zoff + hxp[s], zoff + hyp[s], zpo + hxy[s]};
+                if constexpr (PROJ_U) hp[s][0] = pb[j];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    hw[s][c] = wb[c * nc + j];
+                    hy[s][c] = yb[c * nc + j];
+                    if constexpr (PROJ_U) hp[s][c + 1] = pb[jp[c]];
+                }
+            }
+        };
+        auto park_raw = [&](int k) {
+            T* su = &ru[k % 3][0][0];
+            T* sf = &rf[k % 3][0][0];
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                if (hq[s] < kZmHP) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        T uv = hw[s][c];
+                        if constexpr (PROJ_U) uv = T(double(hw[s][c]) - (hp[s][c + 1] - hp[s][0]) * g.ih[c]);
+                        su[c * kZmHP + hq[s]] = uv;
+                        sf[c * kZmHP + hq[s]] = cb * hy[s][c];
+                    }
+                }
+            }
+        };
+        // the accumulated cotangent (ybar or u0bar) of the plane computed next,
+        // issued after the current plane's stores
+        const T* accb = (mode == 0 || mode == 3) ? yb : u0bar + boff;
+        T nacc[3] = {T(0), T(0), T(0)};
+        auto fetch_acc = [&](int z) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) nacc[a] = accb[int64_t(a) * nc + z * plane + cxy];
+        };
+        const int nk = (z1 - z0) + 2;
+        fetch_raw(pmod(z0 - 1, nz));
+        park_raw(0);
+        fetch_raw(pmod(z0, nz));
+        park_raw(1);
+        fetch_raw(pmod(z0 + 1, nz));
+        park_raw(2);
+        fetch_acc(z0);
+        __syncthreads();
+        for (int k = 2; k < nk; ++k) {
+            const int z = z0 + k - 2;
+            fetch_raw(pmod(z0 - 1 + min(k + 1, nk - 1), nz));
+            LdsSrc<T> U{&ru[(k - 2) % 3][0][0], &ru[(k - 1) % 3][0][0], &ru[k % 3][0][0], centre};
+            LdsSrc<T> F{&rf[(k - 2) % 3][0][0], &rf[(k - 1) % 3][0][0], &rf[k % 3][0][0], centre};
+            T out[3];
+            rhs_vjp_cell<T, 3>(g, U, F, Nb{}, out);
+            if (valid) {
+                const int c0 = z * plane + cyg * nx + cxg;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const int64_t kk = boff + int64_t(a) * nc + c0;
+                    if (u0bar) st_stream(mode >= 2 ? nacc[a] + out[a] : nacc[a], u0bar + kk);
+                    if (ubar_out) st_stream(out[a], ubar_out + kk);
+                    if (fbar_out) fbar_out[kk] = rf[(k - 1) % 3][a][centre];
+                }
+            }
+            fetch_acc(min(z + 1, z1 - 1));
+            // slot (k+1) % 3 is the one just read as plane z-1: wait for every reader
+            __syncthreads();
+            if (k + 1 < nk) park_raw(k + 1);
+            __syncthreads();
+        }
+        return;
+    }
+
     T pu[2][3], pf[2][3];
     auto fetch = [&](int zz) {
         const int zoff = zz * plane;
