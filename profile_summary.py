@@ -38,9 +38,9 @@ CSRC = os.path.join(ROOT, "paper_2604_18536_amd", "csrc")
 _WALL = ["k_walls.hip", "k_common.hpp", "ins_internal.hpp"]
 VARIANT_ORDERS = {
     "periodic": {
-        "void ins::k_stage_zm<double, true, 64, 8, double, false>": (["stage_rec", "stage_last"],
-                                                                   ["k_stage3d.hip", "k_common.hpp"]),
-        "void ins::k_stage_zm<double, true, 64, 8, double, true>": (["stage_yw"], ["k_stage3d.hip", "k_common.hpp"]),
+        "void ins::k_stage_zm<double, true, 64, 8, double, false, 1>": (["stage_rec"], ["k_stage3d.hip", "k_common.hpp"]),
+        "void ins::k_stage_zm<double, true, 64, 8, double, false, 2>": (["stage_last"], ["k_stage3d.hip", "k_common.hpp"]),
+        "void ins::k_stage_zm<double, true, 64, 8, double, true, 3>": (["stage_yw"], ["k_stage3d.hip", "k_common.hpp"]),
         "void ins::k_stage_zm<double, false,": (["stage_first_rec"], ["k_stage3d.hip", "k_common.hpp"]),
         "void ins::k_fft_x_fwd<double, 3, 0,": (["fft_x_fwd_div"], ["k_fft.hip", "k_common.hpp"]),
         "void ins::k_fft_strided<0,": (["fft_y_fwd"], ["k_fft.hip", "k_common.hpp"]),
