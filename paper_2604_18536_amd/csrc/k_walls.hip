@@ -334,11 +334,20 @@ struct WallLds {
     }
 };
 
-// The float32 instance is held to 64 VGPRs (8 waves per SIMD, four workgroups
-// per CU) at the cost of a few spilled registers: at 256^3 its stage took 0.40
-// instead of 0.42 ms (the latency-bound float32 march gains from the occupancy).
-template <typename T, bool PROJ, int TX, int TY>
-__global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 1))) void k_wall_stage_zm(Grid g, const T* __restrict__ w,
+// Every global load of the plane loop is issued unconditionally (halo slots
+// past the halo load a valid position and are not parked; a ghost row's
+// interior-face loads read the clamped row and are zeroed when parked; the
+// last iteration fetches its own last plane again; pointwise cells and planes
+// are clamped; the pointwise streams are fixed per instance: PT bit 0 u0,
+// bit 1 y), and the halo values are combined only when a plane is parked: the
+// compiler's wait counts are then exact, so a plane's compute does not wait
+// for the next plane's loads (with a load behind a condition it waited for
+// every load in flight; 256^3 channel step 3.36 -> 3.23 ms, float32 3.00 ->
+// 2.54 ms). The float32 instance is no longer held to 64 registers (8 waves
+// per SIMD): with its loads in flight it spilled 80-96 bytes there and ran
+// at the old speed; uncapped it takes 84-88 registers (5 waves).
+template <typename T, bool PROJ, int TX, int TY, int PT>
+__global__ __launch_bounds__(TX * TY) void k_wall_stage_zm(Grid g, const T* __restrict__ w,
                                                              const double* __restrict__ p, const T* __restrict__ u0,
                                                              T* __restrict__ y, int yinit, T cy, T* __restrict__ wout,
                                                              T cw, int zc) {
@@ -390,28 +399,26 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(sizeof(
     const int centre = (ly + 1) * HX + (lx + 1);
     const RowM rowm(g, valid ? cyg : 0);
 
-    T pre[NS][3];
+    constexpr bool LB = (PT & 1) != 0, LY = (PT & 2) != 0;
+    const int cxy = min(cyg, ny - 1) * nx + min(cxg, nx - 1);  // own cell, clamped for the loads
+    // raw halo loads: w and (PROJ) p at the cell, its +x neighbour, the row
+    // above (the cell itself when the row has no interior y-face) and +z
+    T pw_[NS][3];
+    double pp_[NS][4];
     auto fetch = [&](int zz) {
         const int zoff = zz * plane;
         const int zpo = (zz + 1 == nz ? 0 : zz + 1) * plane;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            if (hq[s] < HP) {
-                const int j = zoff + hrow[s] + hx[s];
-                T v0, v1 = T(0), v2;
-                if constexpr (PROJ) {
-                    const double pc = pb[j];
-                    v0 = T(double(wb[j]) - (pb[zoff + hrow[s] + hxp[s]] - pc) * g.ih[0]);
-                    if (hunk[s]) v1 = T(double(wb[nc + j]) - (pb[j + nx] - pc) * hid[s]);
-                    v2 = T(double(wb[2 * nc + j]) - (pb[zpo + hrow[s] + hx[s]] - pc) * g.ih[2]);
-                } else {
-                    v0 = wb[j];
-                    if (hunk[s]) v1 = wb[nc + j];
-                    v2 = wb[2 * nc + j];
-                }
-                pre[s][0] = hghost[s] ? -v0 : v0;
-                pre[s][1] = v1;
-                pre[s][2] = hghost[s] ? -v2 : v2;
+            const int j = zoff + hrow[s] + hx[s];
+            pw_[s][0] = wb[j];
+            pw_[s][1] = wb[nc + j];
+            pw_[s][2] = wb[2 * nc + j];
+            if constexpr (PROJ) {
+                pp_[s][0] = pb[j];
+                pp_[s][1] = pb[zoff + hrow[s] + hxp[s]];
+                pp_[s][2] = pb[hunk[s] ? j + nx : j];
+                pp_[s][3] = pb[zpo + hrow[s] + hx[s]];
             }
         }
     };
@@ -420,21 +427,29 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(sizeof(
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             if (hq[s] < HP) {
-                slot[hq[s]] = pre[s][0];
-                slot[HP + hq[s]] = pre[s][1];
-                slot[2 * HP + hq[s]] = pre[s][2];
+                T v0 = pw_[s][0], v1 = pw_[s][1], v2 = pw_[s][2];
+                if constexpr (PROJ) {
+                    const double pc = pp_[s][0];
+                    v0 = T(double(pw_[s][0]) - (pp_[s][1] - pc) * g.ih[0]);
+                    v1 = T(double(pw_[s][1]) - (pp_[s][2] - pc) * hid[s]);
+                    v2 = T(double(pw_[s][2]) - (pp_[s][3] - pc) * g.ih[2]);
+                }
+                slot[hq[s]] = hghost[s] ? -v0 : v0;
+                slot[HP + hq[s]] = hunk[s] ? v1 : T(0);
+                slot[2 * HP + hq[s]] = hghost[s] ? -v2 : v2;
             }
         }
     };
-    T base[3], yv[3];
+    // pointwise streams of the plane computed next: issued after the current
+    // plane's stores, used at the next plane's stores
+    T pbase[3] = {T(0), T(0), T(0)}, pyv[3] = {T(0), T(0), T(0)};
     auto fetch_point = [&](int z) {
-        if (!valid) return;
-        const int c0 = z * plane + cyg * nx + cxg;
+        const int c0 = z * plane + cxy;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const int64_t kk = boff + int64_t(a) * nc + c0;
-            base[a] = (wout || yinit) ? __builtin_nontemporal_load(u0 + kk) : T(0);
-            yv[a] = (y && !yinit) ? __builtin_nontemporal_load(y + kk) : base[a];
+            if constexpr (LB) pbase[a] = __builtin_nontemporal_load(u0 + kk);
+            if constexpr (LY) pyv[a] = __builtin_nontemporal_load(y + kk);
         }
     };
 
@@ -443,38 +458,31 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(sizeof(
     park(0);
     fetch(z0);
     park(1);
-    if (nk > 2) fetch(z0 + 1 == nz ? 0 : z0 + 1);
+    fetch(z0 + 1 == nz ? 0 : z0 + 1);
     park(2);
     fetch_point(z0);
     __syncthreads();
     for (int k = 2; k < nk; ++k) {
         const int z = z0 + k - 2;
-        const bool more = k + 1 < nk;
-        if (more) {
-            const int zn = z0 - 1 + k + 1;
-            fetch(zn >= nz ? zn - nz : zn);
-        }
-        T cb[3], cyv[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            cb[a] = base[a];
-            cyv[a] = yv[a];
-        }
-        if (more) fetch_point(z + 1);
+        const int zn = z0 - 1 + min(k + 1, nk - 1);
+        fetch(zn >= nz ? zn - nz : zn);
+        WallLds<T, TX, TY> U{&ring[(k - 2) & 3][0][0], &ring[(k - 1) & 3][0][0], &ring[k & 3][0][0], centre};
+        T F[3];
+        rhs_cell_wall<T, 3>(g, U, Nb{}, rowm, F);
         if (valid) {
             const int c0 = z * plane + cyg * nx + cxg;
-            WallLds<T, TX, TY> U{&ring[(k - 2) & 3][0][0], &ring[(k - 1) & 3][0][0], &ring[k & 3][0][0], centre};
-            T F[3];
-            rhs_cell_wall<T, 3>(g, U, Nb{}, rowm, F);
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const int64_t kk = boff + int64_t(a) * nc + c0;
                 const bool zero = a == 1 && wallrow;
-                if (y) __builtin_nontemporal_store(zero ? T(0) : cyv[a] + cy * F[a], y + kk);
-                if (wout) __builtin_nontemporal_store(zero ? T(0) : cb[a] + cw * F[a], wout + kk);
+                const T base = LB ? pbase[a] : T(0);
+                const T yv = LY ? pyv[a] : base;
+                if (y) __builtin_nontemporal_store(zero ? T(0) : yv + cy * F[a], y + kk);
+                if (wout) __builtin_nontemporal_store(zero ? T(0) : base + cw * F[a], wout + kk);
             }
         }
-        if (more) park(k + 1);
+        fetch_point(min(z + 1, z1 - 1));
+        if (k + 1 < nk) park(k + 1);
         __syncthreads();
     }
 }
@@ -1375,12 +1383,23 @@ hipError_t launch_wall_stage(const Grid& g, const T* w, const double* p, bool pr
         const int zc = zm_chunk_stage(g, sizeof(T) == 8);
         const int nblk = ((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY) * ((g.nz + zc - 1) / zc) * g.batch;
         const int yi = yinit ? 1 : 0;
-        if (proj)
-            hipLaunchKernelGGL((k_wall_stage_zm<T, true, TX, TY>), dim3(nblk), dim3(TX * TY), 0, s, g, w, p, u0, y, yi,
-                               T(cy), wout, T(cw), zc);
+        // pointwise streams: u0 when it seeds the stage register or the
+        // accumulator, y when the accumulator is read
+        const int pt = ((wout || yinit) ? 1 : 0) | ((y && !yinit) ? 2 : 0);
+#define INS_WSZM(PR, PTI)                                                                                            \
+    hipLaunchKernelGGL((k_wall_stage_zm<T, PR, TX, TY, PTI>), dim3(nblk), dim3(TX * TY), 0, s, g, w, p, u0, y, yi, T(cy), \
+                       wout, T(cw), zc)
+        if (proj && pt == 3)
+            INS_WSZM(true, 3);
+        else if (proj && pt == 2)
+            INS_WSZM(true, 2);
+        else if (proj)
+            INS_WSZM(true, 1);
+        else if (pt == 3)
+            INS_WSZM(false, 3);
         else
-            hipLaunchKernelGGL((k_wall_stage_zm<T, false, TX, TY>), dim3(nblk), dim3(TX * TY), 0, s, g, w, p, u0, y,
-                               yi, T(cy), wout, T(cw), zc);
+            INS_WSZM(false, 1);
+#undef INS_WSZM
     } else
         wall_stage_dim<T, 2>(g, w, p, proj, u0, y, yinit ? 1 : 0, T(cy), wout, T(cw), s);
     return hipGetLastError();
