@@ -703,39 +703,35 @@ __global__ __launch_bounds__(kBlock) void k_wall_stage_vjp_zm(Grid g, const T* _
     const RowM rowm(g, valid ? cyg : 0);
     const double wrow = M.w(valid ? cyg : 0);
 
-    T pu[NS][3], pf[NS][3];
+    // Raw halo loads (w, ybar and, with PROJ_U / HAS_W, p and un, q at the
+    // cell and at its +x, +y (the cell itself when the row has no interior
+    // y-face) and +z neighbours), combined into WallVel's and WallFbar's values
+    // when the plane is parked. Every load of the plane loop is issued
+    // unconditionally (slots past the halo load a valid position; the last
+    // iteration fetches its own last plane again; pointwise cells, rows and
+    // planes clamped), so the compiler's wait counts are exact and a plane's
+    // compute does not wait for the next plane's loads. The instance already
+    // runs 2 waves per SIMD, which the raw registers keep.
+    const int cxy = min(cyg, ny - 1) * nx + min(cxg, nx - 1);
+    T rw[NS][3], ry[NS][3], ru_[NS][3];
+    double rp[NS][4], rq[NS][4];
     auto fetch = [&](int zz) {
         const int zoff = zz * plane;
         const int zpo = (zz + 1 == nz ? 0 : zz + 1) * plane;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            if (hq[s] < HP) {
-                const int j = zoff + hrow[s] + hx[s];
-                const int jp[3] = {zoff + hrow[s] + hxp[s], j + nx, zpo + hrow[s] + hx[s]};
-                double pc = 0.0, qc = 0.0;
-                if constexpr (PROJ_U) pc = pb[j];
-                if constexpr (HAS_W) qc = qb[j];
+            const int j = zoff + hrow[s] + hx[s];
+            const int jp[3] = {zoff + hrow[s] + hxp[s], hunk[s] ? j + nx : j, zpo + hrow[s] + hx[s]};
+            if constexpr (PROJ_U) rp[s][0] = pb[j];
+            if constexpr (HAS_W) rq[s][0] = qb[j];
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    if (c == 1 && !hunk[s]) {
-                        pu[s][c] = T(0);
-                        pf[s][c] = T(0);
-                        continue;
-                    }
-                    const double gs = c == 1 ? hid[s] : g.ih[c];
-                    T uv;
-                    if constexpr (PROJ_U)
-                        uv = T(double(wb[c * nc + j]) - (pb[jp[c]] - pc) * gs);
-                    else
-                        uv = wb[c * nc + j];
-                    T fv = cb * yb[c * nc + j];
-                    if constexpr (HAS_W) {
-                        const double og = c == 1 ? (qb[jp[c]] - qc) : hw[s] * (qb[jp[c]] - qc) * g.ih[c];
-                        fv += cw * T(double(ub[c * nc + j]) - og);
-                    }
-                    const bool neg = c != 1 && hghost[s];
-                    pu[s][c] = neg ? -uv : uv;
-                    pf[s][c] = neg ? -fv : fv;
+            for (int c = 0; c < 3; ++c) {
+                rw[s][c] = wb[c * nc + j];
+                ry[s][c] = yb[c * nc + j];
+                if constexpr (PROJ_U) rp[s][c + 1] = pb[jp[c]];
+                if constexpr (HAS_W) {
+                    ru_[s][c] = ub[c * nc + j];
+                    rq[s][c + 1] = qb[jp[c]];
                 }
             }
         }
@@ -748,11 +744,44 @@ __global__ __launch_bounds__(kBlock) void k_wall_stage_vjp_zm(Grid g, const T* _
             if (hq[s] < HP) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    su[c * HP + hq[s]] = pu[s][c];
-                    sf[c * HP + hq[s]] = pf[s][c];
+                    const double gs = c == 1 ? hid[s] : g.ih[c];
+                    T uv = rw[s][c];
+                    if constexpr (PROJ_U) uv = T(double(rw[s][c]) - (rp[s][c + 1] - rp[s][0]) * gs);
+                    T fv = cb * ry[s][c];
+                    if constexpr (HAS_W) {
+                        const double dq = rq[s][c + 1] - rq[s][0];
+                        const double og = c == 1 ? dq : hw[s] * dq * g.ih[c];
+                        fv += cw * T(double(ru_[s][c]) - og);
+                    }
+                    const bool neg = c != 1 && hghost[s];
+                    const bool zero = c == 1 && !hunk[s];
+                    su[c * HP + hq[s]] = zero ? T(0) : (neg ? -uv : uv);
+                    sf[c * HP + hq[s]] = zero ? T(0) : (neg ? -fv : fv);
                 }
             }
         }
+    };
+    // pointwise inputs of the plane computed next, issued after the current
+    // plane's stores: the accumulated cotangent (ybar or u0bar) and, with
+    // HAS_W, un and q at the cell and at its +x, +y (the cell itself on the
+    // wall row, whose u^y outputs are 0) and +z neighbours
+    const T* accb = (mode == 0 || mode == 3) ? yb : u0bar + boff;
+    T nacc[3] = {T(0), T(0), T(0)}, nun[3] = {T(0), T(0), T(0)};
+    double nq[3] = {0.0, 0.0, 0.0}, nqc = 0.0;
+    auto fetch_point = [&](int z) {
+        const int c0 = z * plane + cxy;
+        const int cx = min(cxg, nx - 1), cy = min(cyg, ny - 1);
+        const int jpc[3] = {z * plane + cy * nx + (cx + 1 == nx ? 0 : cx + 1), cy == ny - 1 ? c0 : c0 + nx,
+                            (z + 1 == nz ? 0 : z + 1) * plane + cxy};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            nacc[a] = accb[int64_t(a) * nc + c0];
+            if constexpr (HAS_W) {
+                nun[a] = ub[int64_t(a) * nc + c0];
+                nq[a] = qb[jpc[a]];
+            }
+        }
+        if constexpr (HAS_W) nqc = qb[c0];
     };
 
     const int nk = (z1 - z0) + 2;
@@ -762,23 +791,18 @@ __global__ __launch_bounds__(kBlock) void k_wall_stage_vjp_zm(Grid g, const T* _
     park(1);
     fetch(z0 + 1 == nz ? 0 : z0 + 1);
     park(2);
+    fetch_point(z0);
     __syncthreads();
     for (int k = 2; k < nk; ++k) {
         const int z = z0 + k - 2;
-        const bool more = k + 1 < nk;
-        if (more) {
-            const int zn = z0 - 1 + k + 1;
-            fetch(zn >= nz ? zn - nz : zn);
-        }
+        const int zn = z0 - 1 + min(k + 1, nk - 1);
+        fetch(zn >= nz ? zn - nz : zn);
+        WallLds<T, TX, TY> U{&ru[(k - 2) % 3][0][0], &ru[(k - 1) % 3][0][0], &ru[k % 3][0][0], centre};
+        WallLds<T, TX, TY> F{&rf[(k - 2) % 3][0][0], &rf[(k - 1) % 3][0][0], &rf[k % 3][0][0], centre};
+        T out[3];
+        rhs_vjp_cell_wall<T, 3>(g, U, F, Nb{}, rowm, out);
         if (valid) {
-            const int cyx = cyg * nx + cxg;
-            const int c0 = z * plane + cyx;
-            const int jpc[3] = {z * plane + cyg * nx + (cxg + 1 == nx ? 0 : cxg + 1), c0 + nx,
-                                (z + 1 == nz ? 0 : z + 1) * plane + cyx};
-            WallLds<T, TX, TY> U{&ru[(k - 2) % 3][0][0], &ru[(k - 1) % 3][0][0], &ru[k % 3][0][0], centre};
-            WallLds<T, TX, TY> F{&rf[(k - 2) % 3][0][0], &rf[(k - 1) % 3][0][0], &rf[k % 3][0][0], centre};
-            T out[3];
-            rhs_vjp_cell_wall<T, 3>(g, U, F, Nb{}, rowm, out);
+            const int c0 = z * plane + cyg * nx + cxg;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const int64_t kk = boff + int64_t(a) * nc + c0;
@@ -787,20 +811,21 @@ __global__ __launch_bounds__(kBlock) void k_wall_stage_vjp_zm(Grid g, const T* _
                     if (ubar_out) ubar_out[kk] = T(0);
                     continue;
                 }
-                T acc = (mode == 0 || mode == 3) ? yb[int64_t(a) * nc + c0] : __builtin_nontemporal_load(u0bar + kk);
+                T acc = nacc[a];
                 if constexpr (HAS_W) {
-                    const double dq = qb[jpc[a]] - qb[c0];
+                    const double dq = nq[a] - nqc;
                     const double og = a == 1 ? dq : wrow * dq * g.ih[a];
-                    acc += T(double(ub[int64_t(a) * nc + c0]) - og);
+                    acc += T(double(nun[a]) - og);
                 }
                 if (mode >= 2) acc += out[a];
                 if (u0bar) __builtin_nontemporal_store(acc, u0bar + kk);
                 if (ubar_out) __builtin_nontemporal_store(out[a], ubar_out + kk);
             }
         }
+        fetch_point(min(z + 1, z1 - 1));
         // slot (k+1) % 3 is the one just read as plane z-1: wait for every reader
         __syncthreads();
-        if (more) park(k + 1);
+        if (k + 1 < nk) park(k + 1);
         __syncthreads();
     }
 }
