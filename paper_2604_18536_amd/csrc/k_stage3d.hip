@@ -448,21 +448,24 @@ __global__ __launch_bounds__(kBlock) void k_stage_vjp_zm(Grid g, const T* __rest
     const bool valid = cxg < nx && cyg < ny;
     const int centre = (ly + 1) * kZmHX + (lx + 1);
 
-    if constexpr (!HAS_W) {
-        // Without a second cotangent (Fbar_i = cb ybar: the last RK stage's
-        // pullback, run first): raw halo loads (w and p at the cell and at its
-        // +x, +y, +z neighbours, ybar), combined into u_i and Fbar_i only when
-        // the plane is parked, and every load of the plane loop issued
-        // unconditionally (slots past the halo load a valid position; the last
-        // iteration fetches its own last plane again; pointwise cells and
-        // planes clamped), so the compiler's wait counts are exact and a
-        // plane's compute does not wait for the next plane's loads
-        // (256^3: 0.604 -> 0.498 ms). The stages with a second cotangent keep
-        // the schedule below: the same change made them 1-5% slower (their
-        // raw loads need 186 registers, 2 waves per SIMD instead of 3).
+    if constexpr (!(PROJ_U && HAS_W && sizeof(T) == 8)) {
+        // Raw halo loads (w, ybar and, with PROJ_U / HAS_W, p and un, q at the
+        // cell and at its +x, +y, +z neighbours), combined into u_i and Fbar_i
+        // only when the plane is parked, and every load of the plane loop
+        // issued unconditionally (slots past the halo load a valid position;
+        // the last iteration fetches its own last plane again; pointwise cells
+        // and planes clamped), so the compiler's wait counts are exact and a
+        // plane's compute does not wait for the next plane's loads (256^3:
+        // the last RK stage's pullback 0.604 -> 0.499 ms, the first's 0.609 ->
+        // 0.590 ms). With HAS_W the cell's un - G q is recovered from its parked
+        // Fbar = cb ybar + cw (un - G q), so the pointwise inputs are the
+        // accumulated cotangent and ybar (6 values instead of 10). The float64
+        // instance with a projection and a second cotangent keeps the schedule
+        // below: its raw halo needs 184 registers (2 waves per SIMD instead of
+        // 3; 0.778 vs 0.771 ms, and 0.977 ms capped at 168 with a spill).
         const int cxy = min(cyg, ny - 1) * nx + min(cxg, nx - 1);
-        T hw[2][3], hy[2][3];
-        double hp[2][4];
+        T hw[2][3], hy[2][3], hu[2][3];
+        double hp[2][4], hqv[2][4];
         auto fetch_raw = [&](int zz) {
             const int zoff = zz * plane;
             const int zpo = (zz + 1 == nz ? 0 : zz + 1) * plane;
@@ -471,11 +474,16 @@ __global__ __launch_bounds__(kBlock) void k_stage_vjp_zm(Grid g, const T* __rest
                 const int j = zoff + hxy[s];
                 const int jp[3] = {zoff + hxp[s], zoff + hyp[s], zpo + hxy[s]};
                 if constexpr (PROJ_U) hp[s][0] = pb[j];
+                if constexpr (HAS_W) hqv[s][0] = qb[j];
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     hw[s][c] = wb[c * nc + j];
                     hy[s][c] = yb[c * nc + j];
                     if constexpr (PROJ_U) hp[s][c + 1] = pb[jp[c]];
+                    if constexpr (HAS_W) {
+                        hu[s][c] = ub[c * nc + j];
+                        hqv[s][c + 1] = qb[jp[c]];
+                    }
                 }
             }
         };
@@ -489,8 +497,10 @@ __global__ __launch_bounds__(kBlock) void k_stage_vjp_zm(Grid g, const T* __rest
                     for (int c = 0; c < 3; ++c) {
                         T uv = hw[s][c];
                         if constexpr (PROJ_U) uv = T(double(hw[s][c]) - (hp[s][c + 1] - hp[s][0]) * g.ih[c]);
+                        T fv = cb * hy[s][c];
+                        if constexpr (HAS_W) fv += cw * T(double(hu[s][c]) - (hqv[s][c + 1] - hqv[s][0]) * g.ih[c]);
                         su[c * kZmHP + hq[s]] = uv;
-                        sf[c * kZmHP + hq[s]] = cb * hy[s][c];
+                        sf[c * kZmHP + hq[s]] = fv;
                     }
                 }
             }
@@ -498,11 +508,16 @@ __global__ __launch_bounds__(kBlock) void k_stage_vjp_zm(Grid g, const T* __rest
         // the accumulated cotangent (ybar or u0bar) of the plane computed next,
         // issued after the current plane's stores
         const T* accb = (mode == 0 || mode == 3) ? yb : u0bar + boff;
-        T nacc[3] = {T(0), T(0), T(0)};
+        T nacc[3] = {T(0), T(0), T(0)}, nyb[3] = {T(0), T(0), T(0)};
         auto fetch_acc = [&](int z) {
 #pragma unroll
-            for (int a = 0; a < 3; ++a) nacc[a] = accb[int64_t(a) * nc + z * plane + cxy];
+            for (int a = 0; a < 3; ++a) {
+                nacc[a] = accb[int64_t(a) * nc + z * plane + cxy];
+                if constexpr (HAS_W) nyb[a] = yb[int64_t(a) * nc + z * plane + cxy];
+            }
         };
+        // un - G q at the cell, recovered from the parked Fbar = cb ybar + cw (un - G q)
+        const T rcw = HAS_W ? T(1) / cw : T(0);
         const int nk = (z1 - z0) + 2;
         fetch_raw(pmod(z0 - 1, nz));
         park_raw(0);
@@ -524,7 +539,9 @@ __global__ __launch_bounds__(kBlock) void k_stage_vjp_zm(Grid g, const T* __rest
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
                     const int64_t kk = boff + int64_t(a) * nc + c0;
-                    if (u0bar) st_stream(mode >= 2 ? nacc[a] + out[a] : nacc[a], u0bar + kk);
+                    T acc = nacc[a];
+                    if constexpr (HAS_W) acc += (rf[(k - 1) % 3][a][centre] - cb * nyb[a]) * rcw;
+                    if (u0bar) st_stream(mode >= 2 ? acc + out[a] : acc, u0bar + kk);
                     if (ubar_out) st_stream(out[a], ubar_out + kk);
                     if (fbar_out) fbar_out[kk] = rf[(k - 1) % 3][a][centre];
                 }
@@ -648,6 +665,7 @@ template <typename T>
 hipError_t launch_stage_vjp_zm(const Grid& g, const T* w, const double* p, bool proj_u, const T* ybar, const T* un,
                                const double* q, bool has_w, double cb, double cw, T* u0bar, int mode, T* ubar_out,
                                hipStream_t s, T* fbar_out) {
+    if (has_w && cw == 0.0) return hipErrorInvalidValue;  // un - G q is recovered through 1 / cw
     const int zc = zm_chunk(g);
     const int nblk = ((g.nx + kZmTX - 1) / kZmTX) * ((g.ny + kZmTY - 1) / kZmTY) * ((g.nz + zc - 1) / zc) * g.batch;
     const T tb = T(cb), tw = T(cw);
