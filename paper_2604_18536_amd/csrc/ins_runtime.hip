@@ -121,7 +121,13 @@ int lines_for(const ins::FftPlan& pl, int maxl, int vm, int pad, int nth, size_t
 // Pick the workgroup shape: 8 complex values per thread and 256 threads keep
 // occupancy high and are preferred; when that gives batches of fewer than
 // `want` lines, a wider workgroup with 8 values per thread (`wide` threads),
-// and only then 16 values per thread with 256 threads. The LDS stride is
+// then (the x passes, `wide10`) 10 values per thread with that many threads,
+// and only then 16 values per thread with 256 threads. The x passes of n_x =
+// 840 (8 rows of 420, radices 7, 5, 4, 3) take 10 values x 512 threads: 128
+// registers, 4 waves per SIMD instead of the 2 that 16 values x 256 threads
+// (211 registers) left (840^3: x forward 4.96 -> 4.34 ms, x inverse 3.08 ->
+// 2.48 ms; the strided passes gained nothing from that shape, their z solve
+// lost 8%). The LDS stride is
 // padded when that does not narrow the batch and, with `occ`, does not cost a
 // workgroup per CU either (the strided passes). `extra`: LDS bytes the pass
 // keeps beside the lines. Measured choices: the x passes stay at 256 threads
@@ -129,13 +135,14 @@ int lines_for(const ins::FftPlan& pl, int maxl, int vm, int pad, int nth, size_t
 // 1024-thread workgroups by 10% forward, 4% inverse); the strided passes use
 // at most 512 (1024 slowed them at 840; 16-line batches of 512 threads were 7%
 // slower than 8 lines of 256 at 256^3).
-int choose_lines(ins::FftPlan& pl, int maxl, int want, int wide, size_t extra, bool occ) {
+int choose_lines(ins::FftPlan& pl, int maxl, int want, int wide, size_t extra, bool occ, int wide10 = 0) {
     struct Shape {
         int vm, nth;
     };
-    const Shape shapes[3] = {{8, kBlockHost}, {8, wide}, {16, kBlockHost}};
+    const Shape shapes[4] = {{8, kBlockHost}, {8, wide}, {10, wide10}, {16, kBlockHost}};
     int best = -1;
     for (const Shape& sh : shapes) {
+        if (sh.nth == 0) continue;
         const int lp = lines_for(pl, maxl, sh.vm, 1, sh.nth, extra);
         const int l0 = lines_for(pl, maxl, sh.vm, 0, sh.nth, extra);
         const int l = std::max(lp, l0);
@@ -1075,7 +1082,7 @@ bool setup_fft(ins_ctx c, const std::vector<int>& rx, const std::vector<int>& ry
     auto strided_extra = [](int n, bool solve) {
         return static_cast<size_t>((n & 1) ? n : n / 2) * sizeof(cd) + (solve ? n * sizeof(double) : 0);
     };
-    c->lnl_x = choose_lines(c->px, 16, 8, kBlockHost, 0, false);
+    c->lnl_x = choose_lines(c->px, 16, 8, kBlockHost, 0, false, 512);
     c->lnl_y = channel ? 0 : choose_lines(c->py, 16, 8, 512, strided_extra(g.ny, d == 2), true);
     // the channel's z passes are plain forward / inverse transforms: 16-line batches
     // (256-byte runs) measured 13% faster there; the periodic fused z solve and the y

@@ -863,7 +863,8 @@ hipError_t fft_x_fwd(const Grid& g, const T* vel, const real_of<C>* r, C* spec, 
                        lnl, comp)
 #define INS_XF_VM(D, SRC)                                    \
     do {                                                     \
-        if (px.vm == 8) INS_XF(D, SRC, 8, 256);              \
+        if (px.nth == 512) INS_XF(D, SRC, 10, 512);          \
+        else if (px.vm == 8) INS_XF(D, SRC, 8, 256);         \
         else INS_XF(D, SRC, 16, 256);                        \
     } while (0)
     if (vel && comp < 0) {
@@ -885,7 +886,9 @@ hipError_t fft_x_inv(const Grid& g, const C* spec, real_of<C>* p, const FftPlan&
     const int nrows = g.batch * g.nz * g.ny;
     const int nblk = (nrows + nl - 1) / nl;
     const size_t shm = size_t(nl + px.pad) * px.n * sizeof(C);
-    if (px.vm == 8)
+    if (px.nth == 512)
+        hipLaunchKernelGGL((k_fft_x_inv<10, 512, C>), dim3(nblk), dim3(512), shm, s, g, spec, p, px, post, lnl);
+    else if (px.vm == 8)
         hipLaunchKernelGGL((k_fft_x_inv<8, 256, C>), dim3(nblk), dim3(256), shm, s, g, spec, p, px, post, lnl);
     else
         hipLaunchKernelGGL((k_fft_x_inv<16, 256, C>), dim3(nblk), dim3(256), shm, s, g, spec, p, px, post, lnl);
@@ -974,7 +977,8 @@ hipError_t launch_fft_x_fwd_wall(const Grid& g, const T* vel, bool scaled, cd* s
                        post, lnl, 0)
 #define INS_XF_VM(D, SRC)                                    \
     do {                                                     \
-        if (px.vm == 8) INS_XF(D, SRC, 8, 256);              \
+        if (px.nth == 512) INS_XF(D, SRC, 10, 512);          \
+        else if (px.vm == 8) INS_XF(D, SRC, 8, 256);         \
         else INS_XF(D, SRC, 16, 256);                        \
     } while (0)
     if (g.dim == 3) {
