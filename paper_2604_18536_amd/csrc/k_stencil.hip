@@ -95,11 +95,27 @@ __global__ __launch_bounds__(kBlock) void k_apply_projection(Grid g, const T* w,
     const int64_t boff = int64_t(t.b) * DIM * g.ncell;
     const int c0 = nb.at(0, 0, 0);
     const P pc = pb[c0];
+    if constexpr (sizeof(T) == 4) {
+        // float32 velocity: every load before the first store (u_out may alias
+        // w, so a store otherwise holds the next component's loads behind it:
+        // three dependent memory round trips per thread); 256^3 0.129 ->
+        // 0.120 ms, 512^3 0.94 -> 0.86 ms. For float64 this ordering was 3-5%
+        // slower at 256^3 (2% faster at 512^3), so it keeps the one below.
+        P wv[DIM], pn[DIM];
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-        const int cp = nb.at(a == 0, a == 1, a == 2);
-        const int64_t k = boff + a * g.ncell + c0;
-        u_out[k] = T(P(w[k]) - (pb[cp] - pc) * P(g.ih[a]));
+        for (int a = 0; a < DIM; ++a) {
+            wv[a] = P(w[boff + a * g.ncell + c0]);
+            pn[a] = pb[nb.at(a == 0, a == 1, a == 2)];
+        }
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) u_out[boff + a * g.ncell + c0] = T(wv[a] - (pn[a] - pc) * P(g.ih[a]));
+    } else {
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            const int cp = nb.at(a == 0, a == 1, a == 2);
+            const int64_t k = boff + a * g.ncell + c0;
+            u_out[k] = T(P(w[k]) - (pb[cp] - pc) * P(g.ih[a]));
+        }
     }
 }
 
